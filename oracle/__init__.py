@@ -1,0 +1,222 @@
+"""CPU oracle for the temporal 3-path sampling estimator.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  The GPU library
+never calls it, and it shares no code with the GPU library: the arithmetic
+lives in ``tc_oracle.cpp`` (plain C++17 + OpenMP, built with g++) and in the
+pure-Python enumerators of ``brute.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tc_oracle.cpp")
+_LIB = os.path.join(_HERE, "libtc_oracle.so")
+
+OR_OK, OR_RANGE, OR_OVERFLOW, OR_RNG, OR_ARG = 0, 1, 2, 4, 8
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (no HIP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["g++", "-std=c++17", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC",
+               "-shared", _SRC, "-o", tmp]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P, I64, U64, I32, U32 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64,
+                                 ctypes.c_int32, ctypes.c_uint32)
+        L.or_graph_new.restype = P
+        L.or_graph_new.argtypes = [I32, I64, P, P, P, P]
+        L.or_graph_free.argtypes = [P]
+        L.or_graph_orders.argtypes = [P, P, P, P, P, P]
+        L.or_weights.argtypes = [P, I64, P, P, P, P, P, ctypes.c_int]
+        L.or_check_motif.argtypes = [P, P, I64, I32, I32, I32, P]
+        L.or_sample.argtypes = [P, I64, P, P, P, P, P, P, ctypes.c_int, U64, U64, U32, U64,
+                                P, P, P, P, P, P, P, ctypes.c_int]
+        L.or_exhaustive.argtypes = [P, P, I64, P, P, P, P, P, P, P, ctypes.c_int]
+        L.or_brute_count.argtypes = [P, P, I64, P, ctypes.c_int]
+        L.or_list_count.argtypes = [P, P, ctypes.c_int, P]
+        L.or_philox4x32_10.argtypes = [P, P, P]
+        L.or_lemire64.argtypes = [U64, U64, P]
+        L.or_lemire32.argtypes = [U32, U32, P]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def default_threads() -> int:
+    return max(1, min(os.cpu_count() or 1, 16))
+
+
+def philox4x32_10(ctr, key):
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().or_philox4x32_10(_p(c), _p(k), _p(out))
+    return [int(x) for x in out]
+
+
+def lemire64(x: int, s: int):
+    out = np.zeros(1, dtype=np.uint64)
+    ok = lib().or_lemire64(x, s, _p(out))
+    return (int(out[0]) if ok else None)
+
+
+def lemire32(x: int, s: int):
+    out = np.zeros(1, dtype=np.uint32)
+    ok = lib().or_lemire32(x, s, _p(out))
+    return (int(out[0]) if ok else None)
+
+
+def list_count(lists):
+    vals = np.concatenate([np.asarray(l, dtype=np.int64) for l in lists]) if lists else np.zeros(0, np.int64)
+    off = np.zeros(len(lists) + 1, dtype=np.int64)
+    for i, l in enumerate(lists):
+        off[i + 1] = off[i] + len(l)
+    vals = np.ascontiguousarray(vals)
+    X = np.zeros(1, dtype=np.uint64)
+    st = lib().or_list_count(_p(vals), _p(off), len(lists), _p(X))
+    return st, int(X[0])
+
+
+@dataclass
+class Weights:
+    delta: int
+    lo_in: np.ndarray
+    a: np.ndarray
+    lo_out: np.ndarray
+    b: np.ndarray
+    S: np.ndarray
+    status: int
+
+    @property
+    def W(self) -> int:
+        return int(self.S[-1])
+
+
+@dataclass
+class Estimate:
+    cnt: list      # python ints (exact)
+    hits: np.ndarray
+    est: np.ndarray
+    status: int
+    e1: np.ndarray | None = None
+    e2: np.ndarray | None = None
+    e3: np.ndarray | None = None
+    X: np.ndarray | None = None  # [n_motifs, k]
+
+
+class OracleGraph:
+    """Temporal adjacency of one input graph, built by the oracle."""
+
+    def __init__(self, n: int, src, dst, t):
+        self.n = int(n)
+        self.src = np.ascontiguousarray(src, dtype=np.int32)
+        self.dst = np.ascontiguousarray(dst, dtype=np.int32)
+        self.t = np.ascontiguousarray(t, dtype=np.int64)
+        self.m = int(self.src.shape[0])
+        st = ctypes.c_int(0)
+        self.h = lib().or_graph_new(self.n, self.m, _p(self.src), _p(self.dst), _p(self.t),
+                                    ctypes.byref(st))
+        self.status = st.value
+        if not self.h:
+            raise ValueError(f"oracle rejected the graph (status {st.value})")
+
+    @classmethod
+    def from_graph(cls, g):
+        return cls(g.n, g.src, g.dst, g.t)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.or_graph_free(h)
+            self.h = None
+
+    def orders(self):
+        m, n = self.m, self.n
+        out = np.zeros(m, np.int32)
+        inn = np.zeros(m, np.int32)
+        pr = np.zeros(m, np.int32)
+        oo = np.zeros(n + 1, np.uint32)
+        io = np.zeros(n + 1, np.uint32)
+        lib().or_graph_orders(self.h, _p(out), _p(inn), _p(pr), _p(oo), _p(io))
+        return dict(out_eid=out, in_eid=inn, pair_eid=pr, out_off=oo, in_off=io)
+
+    def weights(self, delta: int, threads: int | None = None) -> Weights:
+        m = self.m
+        lo_in = np.zeros(m, np.uint32)
+        a = np.zeros(m, np.uint32)
+        lo_out = np.zeros(m, np.uint32)
+        b = np.zeros(m, np.uint32)
+        S = np.zeros(m + 1, np.uint64)
+        st = lib().or_weights(self.h, int(delta), _p(lo_in), _p(a), _p(lo_out), _p(b), _p(S),
+                              threads or default_threads())
+        return Weights(int(delta), lo_in, a, lo_out, b, S, st)
+
+    def check_motif(self, motif: bytes, delta: int, e1: int, e2: int, e3: int):
+        X = np.zeros(1, np.uint64)
+        mb = np.frombuffer(motif, dtype=np.uint8).copy()
+        st = lib().or_check_motif(self.h, _p(mb), int(delta), e1, e2, e3, _p(X))
+        return st, int(X[0])
+
+    def sample(self, w: Weights, motifs, k: int, seed: int, stream: int = 0, i0: int = 0,
+               per_sample: bool = False, threads: int | None = None) -> Estimate:
+        mb = np.frombuffer(b"".join(motifs), dtype=np.uint8).copy()
+        nm = len(motifs)
+        cnt = np.zeros(2 * nm, np.uint64)
+        hits = np.zeros(nm, np.uint64)
+        est = np.zeros(nm, np.float64)
+        e1 = e2 = e3 = X = None
+        null = ctypes.c_void_p(0)
+        if per_sample:
+            e1 = np.zeros(k, np.int32)
+            e2 = np.zeros(k, np.int32)
+            e3 = np.zeros(k, np.int32)
+            X = np.zeros(nm * k, np.uint64)
+        st = lib().or_sample(self.h, w.delta, _p(w.lo_in), _p(w.a), _p(w.lo_out), _p(w.b),
+                             _p(w.S), _p(mb), nm, int(k), int(seed), int(stream), int(i0),
+                             _p(e1) if per_sample else null, _p(e2) if per_sample else null,
+                             _p(e3) if per_sample else null, _p(X) if per_sample else null,
+                             _p(cnt), _p(hits), _p(est), threads or default_threads())
+        c = [int(cnt[2 * j]) | (int(cnt[2 * j + 1]) << 64) for j in range(nm)]
+        return Estimate(c, hits, est, st, e1, e2, e3, None if X is None else X.reshape(nm, k))
+
+    def exhaustive(self, w: Weights, motif: bytes, threads: int | None = None):
+        """Sum over all W delta-centred paths of CheckMotif: (sum X, sum X^2, #X>0)."""
+        mb = np.frombuffer(motif, dtype=np.uint8).copy()
+        s1 = np.zeros(2, np.uint64)
+        s2 = np.zeros(2, np.uint64)
+        nz = np.zeros(1, np.uint64)
+        st = lib().or_exhaustive(self.h, _p(mb), w.delta, _p(w.lo_in), _p(w.a), _p(w.lo_out),
+                                 _p(w.b), _p(s1), _p(s2), _p(nz), threads or default_threads())
+        return (st, int(s1[0]) | (int(s1[1]) << 64), int(s2[0]) | (int(s2[1]) << 64), int(nz[0]))
+
+    def brute_count(self, motif: bytes, delta: int, threads: int | None = None) -> int:
+        mb = np.frombuffer(motif, dtype=np.uint8).copy()
+        C = np.zeros(2, np.uint64)
+        st = lib().or_brute_count(self.h, _p(mb), int(delta), _p(C), threads or default_threads())
+        if st:
+            raise ValueError(f"brute count failed: {st}")
+        return int(C[0]) | (int(C[1]) << 64)

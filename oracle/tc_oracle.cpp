@@ -1,0 +1,583 @@
+// CPU oracle for temporal 3-path sampling (TEACUPS, Pan et al., ICDM 2024).
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+// reference that the GPU library is checked against.  Only the tests, the
+// smoke check and the CPU-baseline leg of the benchmark may load it; the
+// product path never calls it.  It shares no code with the HIP library.
+//
+// What it computes, step by step in the paper's order:
+//   * time-sorted in/out adjacency and per-pair lists (section III-A: edges
+//     sorted by time, per-vertex in/out lists sorted by time; section III-B:
+//     the lists L_{u,v}),
+//   * Preprocess: per-edge window degrees by binary search and
+//     w_e = d^-_u[t-delta, t] * d^+_v[t, t+delta] (Claim "count",
+//     Algorithm Preprocess), their running total as an exact integer CDF,
+//   * Sample: pick e with probability w_e / W by searching the CDF, then a
+//     uniform in-edge of u and a uniform out-edge of v inside the windows
+//     (Algorithm Sample),
+//   * CheckMotif + ListCount (Algorithms CheckMotif and ListCount),
+//   * Estimate: C_hat = (cnt / k) * W (Algorithm Estimate),
+//   * a definition-level backtracking count of M-matches (Definition of an
+//     M-match, section I-A) and an exhaustive sum of CheckMotif over every
+//     delta-centred 3-path (proof of Claim "est": sum_P C_P = C).
+//
+// Readings where the paper is silent or inconsistent (all listed in the
+// design notes):
+//   * windows are closed, [t-delta, t] and [t, t+delta], as in Claim "count"
+//     and its proof; the match itself needs strict t1 < t2 < t3 (the order
+//     condition of a match is an "iff", so ties are not matches); CheckMotif
+//     therefore also rejects non-increasing times,
+//   * equal timestamps inside a list are ordered by edge id (input index),
+//   * the sampling distribution p_e = w_e / W is realised exactly as an
+//     integer CDF S with a uniform integer r in [0, W),
+//   * ListCount counts strictly increasing chains (ties are not matches) and
+//     walks each pair of neighbouring lists with one forward pointer, which
+//     is what its linear-time claim needs,
+//   * the non-anchor edges of the supported motifs all come after rank 2 in
+//     pi order, so every list is the pair's times in (t3, t1 + delta].
+//
+// Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel
+// random numbers: as easy as 1, 2, 3", SC 2011) with counter
+// (i mod 2^32, i div 2^32, attempt, stream) and key (seed mod 2^32,
+// seed div 2^32).  Attempt n of sample i yields words x0..x3: x0|x1<<32 is
+// the 64-bit draw for r, x2 for j1 and x3 for j3.  Each variable takes the
+// first attempt whose word passes Lemire's rejection test ("Fast random
+// integer generation in an interval", ACM TOMACS 2019), which makes every
+// value exactly uniform.
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <numeric>
+#include <vector>
+#include <omp.h>
+
+typedef unsigned __int128 u128;
+
+namespace {
+
+const uint64_t kU64Max = ~0ull;
+const int64_t kTLimit = (int64_t)1 << 62;
+const int kMaxAttempts = 1024;
+
+enum { OR_OK = 0, OR_RANGE = 1, OR_OVERFLOW = 2, OR_RNG = 4, OR_ARG = 8 };
+
+struct Motif {
+  int nv, ne;
+  int src[16], dst[16];
+};
+
+bool parse_motif(const uint8_t* d, Motif* M) {
+  M->nv = d[0];
+  M->ne = d[1];
+  if (M->nv != 4 || M->ne < 3 || M->ne > 16) return false;
+  for (int i = 0; i < M->ne; ++i) {
+    M->src[i] = d[2 + i];
+    M->dst[i] = d[18 + i];
+    if (M->src[i] >= M->nv || M->dst[i] >= M->nv || M->src[i] == M->dst[i]) return false;
+  }
+  // the anchor is the directed 3-path formed by ranks 0, 1, 2: A->B->C->D
+  return M->src[0] == 0 && M->dst[0] == 1 && M->src[1] == 1 && M->dst[1] == 2 &&
+         M->src[2] == 2 && M->dst[2] == 3;
+}
+
+struct Graph {
+  int32_t n;
+  int64_t m;
+  std::vector<int32_t> src, dst;
+  std::vector<int64_t> t;
+  // canonical orders (vectors of edge ids)
+  std::vector<int32_t> out_ord, in_ord, pair_ord;
+  std::vector<uint32_t> out_off, in_off;  // [n+1]
+  // gathered per-order columns
+  std::vector<int64_t> out_t, in_t, pair_t;
+  std::vector<int32_t> out_dst, in_src, pair_dst;
+};
+
+// ---- Philox4x32-10 (SC'11 definition) --------------------------------------
+void philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+  uint32_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+  uint32_t k0 = key_in[0], k1 = key_in[1];
+  for (int round = 0; round < 10; ++round) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    uint32_t n1 = (uint32_t)p1;
+    uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    uint32_t n3 = (uint32_t)p0;
+    c[0] = n0; c[1] = n1; c[2] = n2; c[3] = n3;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c[0]; out[1] = c[1]; out[2] = c[2]; out[3] = c[3];
+}
+
+void draw_block(uint64_t seed, uint32_t stream, uint64_t i, uint32_t attempt, uint32_t x[4]) {
+  uint32_t ctr[4] = {(uint32_t)i, (uint32_t)(i >> 32), attempt, stream};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  philox4x32_10(ctr, key, x);
+}
+
+// Lemire: the draw x maps to floor(x * s / 2^b); it is rejected when the low
+// b bits of x * s fall below (2^b - s) mod s, which leaves exactly
+// floor(2^b / s) accepted draws per output value.
+bool lemire64(uint64_t x, uint64_t s, uint64_t* out) {
+  u128 p = (u128)x * s;
+  uint64_t lo = (uint64_t)p;
+  uint64_t thresh = (uint64_t)((((u128)1 << 64) - s) % s);
+  if (lo < thresh) return false;
+  *out = (uint64_t)(p >> 64);
+  return true;
+}
+
+bool lemire32(uint32_t x, uint32_t s, uint32_t* out) {
+  uint64_t p = (uint64_t)x * s;
+  uint32_t lo = (uint32_t)p;
+  uint32_t thresh = (uint32_t)((((uint64_t)1 << 32) - s) % s);
+  if (lo < thresh) return false;
+  *out = (uint32_t)(p >> 32);
+  return true;
+}
+
+// ---- adjacency build --------------------------------------------------------
+int build(Graph& G, int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+          const int64_t* t) {
+  G.n = n;
+  G.m = m;
+  for (int64_t e = 0; e < m; ++e) {
+    if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n) return OR_RANGE;
+    if (t[e] >= kTLimit || t[e] <= -kTLimit) return OR_RANGE;  // |t| < 2^62
+  }
+  G.src.assign(src, src + m);
+  G.dst.assign(dst, dst + m);
+  G.t.assign(t, t + m);
+  std::vector<int32_t> ids(m);
+  std::iota(ids.begin(), ids.end(), 0);
+  // out lists: by (src, t, eid)
+  G.out_ord = ids;
+  std::stable_sort(G.out_ord.begin(), G.out_ord.end(), [&](int32_t a, int32_t b) {
+    if (G.src[a] != G.src[b]) return G.src[a] < G.src[b];
+    return G.t[a] < G.t[b];
+  });
+  // in lists: by (dst, t, eid)
+  G.in_ord = ids;
+  std::stable_sort(G.in_ord.begin(), G.in_ord.end(), [&](int32_t a, int32_t b) {
+    if (G.dst[a] != G.dst[b]) return G.dst[a] < G.dst[b];
+    return G.t[a] < G.t[b];
+  });
+  // pair lists L_{u,v}: by (src, dst, t, eid)
+  G.pair_ord = ids;
+  std::stable_sort(G.pair_ord.begin(), G.pair_ord.end(), [&](int32_t a, int32_t b) {
+    if (G.src[a] != G.src[b]) return G.src[a] < G.src[b];
+    if (G.dst[a] != G.dst[b]) return G.dst[a] < G.dst[b];
+    return G.t[a] < G.t[b];
+  });
+  G.out_off.assign(n + 1, 0);
+  G.in_off.assign(n + 1, 0);
+  for (int64_t e = 0; e < m; ++e) {
+    G.out_off[src[e] + 1]++;
+    G.in_off[dst[e] + 1]++;
+  }
+  for (int32_t v = 0; v < n; ++v) {
+    G.out_off[v + 1] += G.out_off[v];
+    G.in_off[v + 1] += G.in_off[v];
+  }
+  G.out_t.resize(m); G.in_t.resize(m); G.pair_t.resize(m);
+  G.out_dst.resize(m); G.in_src.resize(m); G.pair_dst.resize(m);
+  for (int64_t p = 0; p < m; ++p) {
+    G.out_t[p] = G.t[G.out_ord[p]];
+    G.out_dst[p] = G.dst[G.out_ord[p]];
+    G.in_t[p] = G.t[G.in_ord[p]];
+    G.in_src[p] = G.src[G.in_ord[p]];
+    G.pair_t[p] = G.t[G.pair_ord[p]];
+    G.pair_dst[p] = G.dst[G.pair_ord[p]];
+  }
+  return OR_OK;
+}
+
+// Edges (a -> b) with time in the half-open interval (lo_t, hi_t]: returns
+// [first, last) positions in the pair order.
+void pair_window(const Graph& G, int32_t a, int32_t b, int64_t lo_t, int64_t hi_t,
+                 int64_t* first, int64_t* last) {
+  auto beg = G.pair_dst.begin() + G.out_off[a];
+  auto end = G.pair_dst.begin() + G.out_off[a + 1];
+  auto run = std::equal_range(beg, end, b);
+  int64_t r0 = run.first - G.pair_dst.begin();
+  int64_t r1 = run.second - G.pair_dst.begin();
+  auto tb = G.pair_t.begin();
+  *first = std::upper_bound(tb + r0, tb + r1, lo_t) - tb;
+  *last = std::upper_bound(tb + r0, tb + r1, hi_t) - tb;
+  if (*last < *first) *last = *first;
+}
+
+// ListCount: number of chains l_1 < l_2 < ... < l_l with l_r drawn from the
+// sorted list L_r.  cnt_1 is all ones; cnt_r[i] sums cnt_{r-1}[j] over the
+// entries of L_{r-1} strictly before L_r[i], found with one pointer that only
+// moves forward.  Returns false when any list's total reaches 2^64.
+bool list_count(const std::vector<std::vector<int64_t>>& L, u128* X) {
+  size_t l = L.size();
+  if (l == 0) { *X = 1; return true; }
+  std::vector<u128> prev(L[0].size(), 1), cur;
+  if ((u128)L[0].size() > kU64Max) return false;
+  for (size_t r = 1; r < l; ++r) {
+    cur.assign(L[r].size(), 0);
+    size_t j = 0;
+    u128 run = 0;
+    for (size_t i = 0; i < L[r].size(); ++i) {
+      while (j < L[r - 1].size() && L[r - 1][j] < L[r][i]) {
+        run += prev[j];
+        ++j;
+      }
+      cur[i] = run;
+    }
+    u128 total = 0;
+    for (u128 c : cur) total += c;
+    if (total > kU64Max) return false;
+    prev.swap(cur);
+  }
+  u128 s = 0;
+  for (u128 c : prev) s += c;
+  *X = s;
+  return true;
+}
+
+// CheckMotif for the path (e1, e2, e3) with e1 = (x,u,t1), e2 = (u,v,t2),
+// e3 = (v,y,t3), all given by edge id.
+int check_motif(const Graph& G, const Motif& M, int64_t delta, int32_t e1, int32_t e2,
+                int32_t e3, uint64_t* X) {
+  int32_t x = G.src[e1], u = G.dst[e1];
+  int32_t u2 = G.src[e2], v = G.dst[e2];
+  int32_t v3 = G.src[e3], y = G.dst[e3];
+  *X = 0;
+  if (u != u2 || v != v3) return OR_ARG;  // not a 3-path
+  int64_t t1 = G.t[e1], t2 = G.t[e2], t3 = G.t[e3];
+  int32_t phi[4] = {x, u, v, y};
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j)
+      if (phi[i] == phi[j]) return OR_OK;
+  if (t3 > t1 + delta) return OR_OK;
+  if (!(t1 < t2 && t2 < t3)) return OR_OK;
+  std::vector<std::vector<int64_t>> L;
+  for (int r = 3; r < M.ne; ++r) {
+    int64_t f, l;
+    pair_window(G, phi[M.src[r]], phi[M.dst[r]], t3, t1 + delta, &f, &l);
+    L.emplace_back(G.pair_t.begin() + f, G.pair_t.begin() + l);
+  }
+  u128 c;
+  if (!list_count(L, &c)) return OR_OVERFLOW;
+  *X = (uint64_t)c;
+  return OR_OK;
+}
+
+int window_weights(const Graph& G, int64_t delta, uint32_t* lo_in, uint32_t* a,
+                   uint32_t* lo_out, uint32_t* b, uint64_t* S, int nthreads) {
+  int64_t m = G.m;
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+  for (int64_t p = 0; p < m; ++p) {
+    int32_t e = G.out_ord[p];
+    int32_t u = G.src[e], v = G.dst[e];
+    int64_t t = G.t[e];
+    auto ib = G.in_t.begin();
+    // d^-_u[t - delta, t]: closed window in u's in-list
+    int64_t i0 = std::lower_bound(ib + G.in_off[u], ib + G.in_off[u + 1], t - delta) - ib;
+    int64_t i1 = std::upper_bound(ib + G.in_off[u], ib + G.in_off[u + 1], t) - ib;
+    auto ob = G.out_t.begin();
+    // d^+_v[t, t + delta]: closed window in v's out-list
+    int64_t o0 = std::lower_bound(ob + G.out_off[v], ob + G.out_off[v + 1], t) - ob;
+    int64_t o1 = std::upper_bound(ob + G.out_off[v], ob + G.out_off[v + 1], t + delta) - ob;
+    lo_in[p] = (uint32_t)i0;
+    a[p] = (uint32_t)(i1 - i0);
+    lo_out[p] = (uint32_t)o0;
+    b[p] = (uint32_t)(o1 - o0);
+  }
+  u128 run = 0;
+  int st = OR_OK;
+  for (int64_t p = 0; p < m; ++p) {
+    S[p] = (uint64_t)run;
+    run += (u128)((uint64_t)a[p] * (uint64_t)b[p]);
+  }
+  if (run > kU64Max) st = OR_OVERFLOW;
+  S[m] = (uint64_t)run;
+  return st;
+}
+
+double u128_over_k_times_w(u128 cnt, uint64_t k, uint64_t W) {
+  return ((double)cnt / (double)k) * (double)W;
+}
+
+}  // namespace
+
+extern "C" {
+
+void or_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+  philox4x32_10(ctr, key, out);
+}
+
+int or_lemire64(uint64_t x, uint64_t s, uint64_t* out) { return lemire64(x, s, out) ? 1 : 0; }
+int or_lemire32(uint32_t x, uint32_t s, uint32_t* out) { return lemire32(x, s, out) ? 1 : 0; }
+
+void* or_graph_new(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                   const int64_t* t, int* status) {
+  Graph* G = new Graph();
+  *status = build(*G, n, m, src, dst, t);
+  if (*status != OR_OK) {
+    delete G;
+    return nullptr;
+  }
+  return G;
+}
+
+void or_graph_free(void* h) { delete (Graph*)h; }
+
+void or_graph_orders(void* h, int32_t* out_ord, int32_t* in_ord, int32_t* pair_ord,
+                     uint32_t* out_off, uint32_t* in_off) {
+  Graph& G = *(Graph*)h;
+  std::copy(G.out_ord.begin(), G.out_ord.end(), out_ord);
+  std::copy(G.in_ord.begin(), G.in_ord.end(), in_ord);
+  std::copy(G.pair_ord.begin(), G.pair_ord.end(), pair_ord);
+  std::copy(G.out_off.begin(), G.out_off.end(), out_off);
+  std::copy(G.in_off.begin(), G.in_off.end(), in_off);
+}
+
+int or_weights(void* h, int64_t delta, uint32_t* lo_in, uint32_t* a, uint32_t* lo_out,
+               uint32_t* b, uint64_t* S, int nthreads) {
+  if (delta < 0 || delta > kTLimit) return OR_ARG;
+  return window_weights(*(Graph*)h, delta, lo_in, a, lo_out, b, S, nthreads);
+}
+
+// One delta-centred path given by edge ids -> CheckMotif count.
+int or_check_motif(void* h, const uint8_t* motif, int64_t delta, int32_t e1, int32_t e2,
+                   int32_t e3, uint64_t* X) {
+  Motif M;
+  if (!parse_motif(motif, &M)) return OR_ARG;
+  return check_motif(*(Graph*)h, M, delta, e1, e2, e3, X);
+}
+
+// Estimate(M, k) for a batch of motifs that share the anchor: samples
+// i0 .. i0+k-1 of (seed, stream).  Optional per-sample outputs (null = off):
+// e1/e2/e3 edge ids [k], X motif-major [n_motifs * k].  cnt holds (lo, hi)
+// per motif.
+int or_sample(void* h, int64_t delta, const uint32_t* lo_in, const uint32_t* a,
+              const uint32_t* lo_out, const uint32_t* b, const uint64_t* S,
+              const uint8_t* motifs, int n_motifs, uint64_t k, uint64_t seed, uint32_t stream,
+              uint64_t i0, int32_t* e1o, int32_t* e2o, int32_t* e3o, uint64_t* Xo,
+              uint64_t* cnt, uint64_t* hits, double* est, int nthreads) {
+  Graph& G = *(Graph*)h;
+  if (n_motifs < 1 || n_motifs > 16 || k < 1) return OR_ARG;
+  std::vector<Motif> Ms(n_motifs);
+  for (int j = 0; j < n_motifs; ++j)
+    if (!parse_motif(motifs + 34 * j, &Ms[j])) return OR_ARG;
+  const uint64_t W = S[G.m];
+  std::vector<u128> c(n_motifs, 0);
+  std::vector<uint64_t> hh(n_motifs, 0);
+  int status = OR_OK;
+  if (W == 0) {
+    for (uint64_t i = 0; i < k; ++i) {
+      if (e1o) { e1o[i] = -1; e2o[i] = -1; e3o[i] = -1; }
+      if (Xo) for (int j = 0; j < n_motifs; ++j) Xo[j * k + i] = 0;
+    }
+  } else {
+    std::vector<std::vector<u128>> pc(nthreads, std::vector<u128>(n_motifs, 0));
+    std::vector<std::vector<uint64_t>> ph(nthreads, std::vector<uint64_t>(n_motifs, 0));
+    std::vector<int> pst(nthreads, OR_OK);
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int64_t ii = 0; ii < (int64_t)k; ++ii) {
+      int tid = omp_get_thread_num();
+      uint64_t i = i0 + (uint64_t)ii;
+      uint32_t x[4];
+      // r uniform in [0, W)
+      uint64_t r = 0;
+      bool ok = false;
+      for (uint32_t n = 0; n < (uint32_t)kMaxAttempts && !ok; ++n) {
+        draw_block(seed, stream, i, n, x);
+        ok = lemire64((uint64_t)x[0] | ((uint64_t)x[1] << 32), W, &r);
+      }
+      if (!ok) { pst[tid] |= OR_RNG; continue; }
+      // pick e with probability w_e / W: S[p] <= r < S[p+1]
+      int64_t p = std::upper_bound(S, S + G.m + 1, r) - S - 1;
+      uint32_t j1 = 0, j3 = 0;
+      ok = false;
+      for (uint32_t n = 0; n < (uint32_t)kMaxAttempts && !ok; ++n) {
+        draw_block(seed, stream, i, n, x);
+        ok = lemire32(x[2], a[p], &j1);
+      }
+      if (!ok) { pst[tid] |= OR_RNG; continue; }
+      ok = false;
+      for (uint32_t n = 0; n < (uint32_t)kMaxAttempts && !ok; ++n) {
+        draw_block(seed, stream, i, n, x);
+        ok = lemire32(x[3], b[p], &j3);
+      }
+      if (!ok) { pst[tid] |= OR_RNG; continue; }
+      int32_t e2 = G.out_ord[p];
+      int32_t e1 = G.in_ord[lo_in[p] + j1];
+      int32_t e3 = G.out_ord[lo_out[p] + j3];
+      if (e1o) { e1o[ii] = e1; e2o[ii] = e2; e3o[ii] = e3; }
+      for (int j = 0; j < n_motifs; ++j) {
+        uint64_t X = 0;
+        int st = check_motif(G, Ms[j], delta, e1, e2, e3, &X);
+        pst[tid] |= st;
+        if (Xo) Xo[(uint64_t)j * k + ii] = X;
+        pc[tid][j] += X;
+        ph[tid][j] += X > 0;
+      }
+    }
+    for (int tid = 0; tid < nthreads; ++tid) {
+      status |= pst[tid];
+      for (int j = 0; j < n_motifs; ++j) {
+        c[j] += pc[tid][j];
+        hh[j] += ph[tid][j];
+      }
+    }
+  }
+  for (int j = 0; j < n_motifs; ++j) {
+    cnt[2 * j] = (uint64_t)c[j];
+    cnt[2 * j + 1] = (uint64_t)(c[j] >> 64);
+    hits[j] = hh[j];
+    est[j] = W == 0 ? 0.0 : u128_over_k_times_w(c[j], k, W);
+  }
+  return status;
+}
+
+// Sum of CheckMotif over every delta-centred <-,+,<,>> path (all W of them):
+// by the proof of Claim "est" this equals the number of M-matches.  Also
+// returns sum X^2 and the number of paths with X > 0.
+int or_exhaustive(void* h, const uint8_t* motif, int64_t delta, const uint32_t* lo_in,
+                  const uint32_t* a, const uint32_t* lo_out, const uint32_t* b,
+                  uint64_t* sum_x, uint64_t* sum_x2, uint64_t* nonzero, int nthreads) {
+  Graph& G = *(Graph*)h;
+  Motif M;
+  if (!parse_motif(motif, &M)) return OR_ARG;
+  std::vector<u128> s1(nthreads, 0), s2(nthreads, 0);
+  std::vector<uint64_t> nz(nthreads, 0);
+  std::vector<int> pst(nthreads, OR_OK);
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 64)
+  for (int64_t p = 0; p < G.m; ++p) {
+    int tid = omp_get_thread_num();
+    for (uint32_t j1 = 0; j1 < a[p]; ++j1)
+      for (uint32_t j3 = 0; j3 < b[p]; ++j3) {
+        uint64_t X;
+        pst[tid] |= check_motif(G, M, delta, G.in_ord[lo_in[p] + j1], G.out_ord[p],
+                                G.out_ord[lo_out[p] + j3], &X);
+        s1[tid] += X;
+        s2[tid] += (u128)X * X;
+        nz[tid] += X > 0;
+      }
+  }
+  u128 t1 = 0, t2 = 0;
+  uint64_t tn = 0;
+  int st = OR_OK;
+  for (int i = 0; i < nthreads; ++i) { t1 += s1[i]; t2 += s2[i]; tn += nz[i]; st |= pst[i]; }
+  sum_x[0] = (uint64_t)t1; sum_x[1] = (uint64_t)(t1 >> 64);
+  sum_x2[0] = (uint64_t)t2; sum_x2[1] = (uint64_t)(t2 >> 64);
+  *nonzero = tn;
+  return st;
+}
+
+// Definition-level count of M-matches (section I-A): every assignment of
+// distinct G-edges to the motif edges, in pi order with strictly increasing
+// times, all within delta of the first, whose endpoints define a 1-1 map
+// from V(H) into V(G).  Backtracking in pi order; candidates for rank r are
+// read from the adjacency lists of already mapped endpoints.
+namespace {
+struct Brute {
+  const Graph& G;
+  const Motif& M;
+  int64_t delta;
+  int32_t phi[16];
+  u128 count = 0;
+  Brute(const Graph& g, const Motif& m, int64_t d) : G(g), M(m), delta(d) {
+    for (int i = 0; i < 16; ++i) phi[i] = -1;
+  }
+  bool used(int32_t v) const {
+    for (int i = 0; i < M.nv; ++i)
+      if (phi[i] == v) return true;
+    return false;
+  }
+  void extend(int r, int64_t t_first, int64_t t_prev) {
+    if (r == M.ne) { count += 1; return; }
+    int ha = M.src[r], hb = M.dst[r];
+    int32_t ga = phi[ha], gb = phi[hb];
+    int64_t hi = t_first + delta;
+    if (ga >= 0 && gb >= 0) {
+      int64_t f, l;
+      pair_window(G, ga, gb, t_prev, hi, &f, &l);
+      for (int64_t q = f; q < l; ++q) extend(r + 1, t_first, G.pair_t[q]);
+    } else if (ga >= 0) {
+      auto ob = G.out_t.begin();
+      int64_t f = std::upper_bound(ob + G.out_off[ga], ob + G.out_off[ga + 1], t_prev) - ob;
+      int64_t l = std::upper_bound(ob + G.out_off[ga], ob + G.out_off[ga + 1], hi) - ob;
+      for (int64_t q = f; q < l; ++q) {
+        int32_t w = G.out_dst[q];
+        if (used(w)) continue;
+        phi[hb] = w;
+        extend(r + 1, t_first, G.out_t[q]);
+        phi[hb] = -1;
+      }
+    } else if (gb >= 0) {
+      auto ib = G.in_t.begin();
+      int64_t f = std::upper_bound(ib + G.in_off[gb], ib + G.in_off[gb + 1], t_prev) - ib;
+      int64_t l = std::upper_bound(ib + G.in_off[gb], ib + G.in_off[gb + 1], hi) - ib;
+      for (int64_t q = f; q < l; ++q) {
+        int32_t w = G.in_src[q];
+        if (used(w)) continue;
+        phi[ha] = w;
+        extend(r + 1, t_first, G.in_t[q]);
+        phi[ha] = -1;
+      }
+    } else {
+      // only possible for a motif whose prefix is disconnected; scan all edges
+      for (int64_t e = 0; e < G.m; ++e) {
+        if (!(G.t[e] > t_prev && G.t[e] <= hi)) continue;
+        int32_t s = G.src[e], d = G.dst[e];
+        if (s == d || used(s) || used(d)) continue;
+        phi[ha] = s; phi[hb] = d;
+        extend(r + 1, t_first, G.t[e]);
+        phi[ha] = -1; phi[hb] = -1;
+      }
+    }
+  }
+};
+}  // namespace
+
+int or_brute_count(void* h, const uint8_t* motif_bytes, int64_t delta, uint64_t* C,
+                   int nthreads) {
+  Graph& G = *(Graph*)h;
+  Motif M;
+  M.nv = motif_bytes[0];
+  M.ne = motif_bytes[1];
+  if (M.nv < 2 || M.nv > 16 || M.ne < 1 || M.ne > 16) return OR_ARG;
+  for (int i = 0; i < M.ne; ++i) {
+    M.src[i] = motif_bytes[2 + i];
+    M.dst[i] = motif_bytes[18 + i];
+  }
+  std::vector<u128> part(nthreads, 0);
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 16)
+  for (int64_t e = 0; e < G.m; ++e) {
+    int32_t s = G.src[e], d = G.dst[e];
+    if (s == d) continue;
+    Brute bt(G, M, delta);
+    bt.phi[M.src[0]] = s;
+    bt.phi[M.dst[0]] = d;
+    bt.extend(1, G.t[e], G.t[e]);
+    part[omp_get_thread_num()] += bt.count;
+  }
+  u128 tot = 0;
+  for (auto v : part) tot += v;
+  C[0] = (uint64_t)tot;
+  C[1] = (uint64_t)(tot >> 64);
+  return OR_OK;
+}
+
+// ListCount on caller-provided sorted lists (for pinning against product
+// enumeration): lists concatenated in `vals`, list r spans [off[r], off[r+1]).
+int or_list_count(const int64_t* vals, const int64_t* off, int l, uint64_t* X) {
+  std::vector<std::vector<int64_t>> L(l);
+  for (int r = 0; r < l; ++r) L[r].assign(vals + off[r], vals + off[r + 1]);
+  u128 c;
+  if (!list_count(L, &c)) return OR_OVERFLOW;
+  *X = (uint64_t)c;
+  return OR_OK;
+}
+
+int or_max_threads(void) { return omp_get_max_threads(); }
+
+}  // extern "C"
