@@ -1,0 +1,185 @@
+/* tc.h -- C ABI of the MI355X temporal 3-path sampling library (libtc.so).
+ *
+ * The library estimates the number of matches of a 4-vertex temporal motif
+ * M = (H, pi, delta) in a directed temporal multigraph G by sampling
+ * delta-centred <-,+,<,>> 3-paths (Pan, Bhalerao, Seshadhri, Talati,
+ * "Accurate and Fast Estimation of Temporal Motifs using Path Sampling",
+ * ICDM 2024).  Problem statement: section I-A (temporal multigraph, edges
+ * (u, v, t) with integer t, parallel edges allowed; Definitions of a
+ * temporal motif and of an M-match).  The three calls below are the three
+ * phases of Algorithm Estimate: the time-sorted adjacency it assumes,
+ * Preprocess (per-edge weights and their total W), and the loop of Sample +
+ * CheckMotif that ends in C_hat = (cnt / k) * W.
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers marked (device) are HIP device pointers owned by the caller;
+ *     (host) pointers are read during the call only.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *     Every call is stream-ordered and returns as soon as its kernels are
+ *     enqueued, except tc_build_graph, which waits once for its own
+ *     validation result (see there).
+ *   - The library allocates no memory.  The caller provides workspaces of at
+ *     least the size reported by the *_workspace_bytes queries; tc_graph and
+ *     tc_weights then hold pointers into those workspaces (borrowed: keep the
+ *     workspace alive while the struct is used).  There is no free call.
+ *   - Host-checkable argument errors are returned synchronously and nothing
+ *     is enqueued.  Data-dependent errors are recorded as bits of a device
+ *     status word (TC_F_*); results guarded by a non-zero status word are
+ *     undefined.  No C++ exception crosses this boundary.
+ *   - Results are a pure function of the inputs (graph bytes, delta, motifs,
+ *     k, seed, stream_id, i0), independent of launch configuration.
+ *   - Calls on distinct workspaces/results may run concurrently.
+ */
+#ifndef TC_H_
+#define TC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TC_OK = 0,
+  TC_E_ARG = -1,          /* null pointer, bad size, bad delta or k            */
+  TC_E_RANGE = -2,        /* vertex id outside [0, n) or |t| >= 2^62 (build)    */
+  TC_E_OVERFLOW = -3,     /* reserved for host-side reporting of TC_F_OVERFLOW  */
+  TC_E_UNSUPPORTED = -4,  /* motif not anchored on the directed 3-path 0-1-2-3   */
+  TC_E_WORKSPACE = -5,    /* workspace smaller than the query reported          */
+  TC_E_HIP = -6           /* a HIP runtime call failed                          */
+} tc_status;
+
+/* Bits of a device status word. */
+#define TC_F_RANGE 1u     /* bad vertex id or timestamp                              */
+#define TC_F_OVERFLOW 2u  /* W >= 2^64, or a ListCount partial total >= 2^64          */
+#define TC_F_RNG 4u       /* 1024 consecutive rejections in the range reduction       */
+
+/* A temporal motif: H's edges listed in pi order (edge i has time rank i),
+ * vertices 0..nv-1.  Supported: nv == 4, 3 <= ne <= 16, no self-loops, and
+ * ranks 0, 1, 2 equal to 0->1, 1->2, 2->3.  That 3-path (A->B->C->D) holds the
+ * pi-earliest edge and is the anchor S (section III-B; Algorithm Estimate
+ * chooses an anchor containing the earliest edge).  Every later edge must
+ * then fall in (t3, t1 + delta], which is how CheckMotif bounds its lists. */
+typedef struct {
+  uint8_t nv, ne;
+  uint8_t src[16], dst[16];
+} tc_motif;
+
+/* Time-sorted temporal adjacency (section III-A assumes per-vertex in- and
+ * out-lists sorted by time; section III-B uses the per-pair lists L_{u,v}).
+ * Filled by tc_build_graph; all arrays (device) live in the graph workspace.
+ *   out-CSR : edges sorted by (src, t, eid); out_off[v]..out_off[v+1]-1 are
+ *             v's out-edges.  Position p in this order is the "scan order"
+ *             used by the weights and the sampler.
+ *   in-CSR  : edges sorted by (dst, t, eid); in_off as above.
+ *   pair    : edges sorted by (src, dst, t, eid); shares out_off.
+ * eid is the edge's index in the input arrays; it breaks timestamp ties. */
+typedef struct tc_graph {
+  int32_t n;
+  int64_t m;
+  int64_t t_min, t_max;               /* host copies, valid after the build   */
+  uint32_t *out_off;                  /* [n+1] */
+  int32_t *out_src, *out_dst, *out_eid;
+  int64_t *out_t;                     /* [m] each */
+  uint32_t *in_off;                   /* [n+1] */
+  int32_t *in_src, *in_eid;
+  int64_t *in_t;                      /* [m] each */
+  int32_t *pair_dst, *pair_eid;
+  int64_t *pair_t;                    /* [m] each */
+  uint32_t *status;                   /* device status word of the build       */
+} tc_graph;
+
+/* Per-edge window metadata and the exact integer CDF of the path weights,
+ * all indexed by scan position p (out-CSR order):
+ *   lo_in[p] = first position in the in-CSR of u's in-edges with time in
+ *              [t - delta, t];  a[p] = their number  (d^-_u[t - delta, t])
+ *   lo_out[p], b[p] likewise for v's out-edges in [t, t + delta]
+ *              (d^+_v[t, t + delta])
+ *   S[p] = sum_{q < p} a[q] * b[q]  (exclusive scan), S[m] = W_delta.
+ * Claim "count" gives w_e = a * b; Algorithm Preprocess computes it with
+ * four binary searches per edge.  Windows are closed on both ends. */
+typedef struct tc_weights {
+  int64_t delta;
+  int64_t m;
+  uint32_t *lo_in, *a, *lo_out, *b;   /* [m] each (device) */
+  uint64_t *S;                        /* [m+1] (device) */
+  uint32_t *status;                   /* device word: TC_F_OVERFLOW if W >= 2^64 */
+  void *scratch;                      /* internal tile partials */
+} tc_weights;
+
+/* Outputs of tc_sample_estimate, all (device), caller-allocated.
+ *   cnt[2j], cnt[2j+1] : low and high 64 bits of cnt_j = sum_i X_ij
+ *   hits[j]            : number of samples with X_ij > 0
+ *   estimate[j]        : C_hat_j = (cnt_j / k) * W in IEEE binary64, each
+ *                        integer converted with round-to-nearest-even
+ *   status             : TC_F_* bits (OR of the weights' status and the
+ *                        sampler's own)
+ *   e1, e2, e3         : optional [k] edge ids of the sampled path (NULL=off)
+ *   X                  : optional [n_motifs * k], motif-major (NULL = off)
+ * cnt, hits, estimate and status are overwritten (not accumulated). */
+typedef struct tc_result {
+  uint64_t *cnt;
+  uint64_t *hits;
+  double *estimate;
+  uint32_t *status;
+  int32_t *e1, *e2, *e3;
+  uint64_t *X;
+} tc_result;
+
+/* Library version string (host, static storage). */
+const char *tc_version(void);
+
+/* Workspace size in bytes for tc_build_graph with n vertices and m edges.
+ * Errors: TC_E_ARG if bytes is NULL, n < 1, m < 0 or m >= 2^31. */
+tc_status tc_graph_workspace_bytes(int32_t n, int64_t m, size_t *bytes);
+
+/* Build the temporal adjacency of the multigraph given by src, dst, t
+ * (device, [m] each, eid = index).  Requires 0 <= src, dst < n and
+ * |t| < 2^62.  Enqueues the validation, three stable radix sorts and the
+ * offset computation on `stream`, and waits once for the validation word and
+ * the time range (so that a bad graph is reported here as TC_E_RANGE and the
+ * number of radix passes follows the actual time range).  On TC_OK, *g
+ * describes the graph and its arrays are ready in stream order.
+ * Errors: TC_E_ARG (null pointers, n < 1, m < 0, m >= 2^31),
+ * TC_E_WORKSPACE, TC_E_RANGE, TC_E_HIP. */
+tc_status tc_build_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                         const int64_t *t, void *ws, size_t ws_bytes, void *stream,
+                         tc_graph *g);
+
+/* Workspace size in bytes for tc_path_weights on a graph with m edges. */
+tc_status tc_weights_workspace_bytes(int64_t m, size_t *bytes);
+
+/* Preprocess(delta): window metadata and S for every edge (Algorithm
+ * Preprocess with Claim "count").  0 <= delta <= 2^62.  Enqueue only; W
+ * stays on the device as S[m]; TC_F_OVERFLOW is set in *w->status when the
+ * exact total reaches 2^64.  Errors: TC_E_ARG, TC_E_WORKSPACE, TC_E_HIP. */
+tc_status tc_path_weights(const tc_graph *g, int64_t delta, void *ws, size_t ws_bytes,
+                          void *stream, tc_weights *w);
+
+/* Estimate(M, k) for n_motifs motifs (host array, 1..16) that share the
+ * anchor: samples i0 .. i0+k-1 (k >= 1) of the counter-based stream
+ * (seed, stream_id).  For each sample i (Algorithm Sample, then CheckMotif):
+ *   Philox4x32-10 (Salmon et al., SC 2011) with counter
+ *   (i mod 2^32, i div 2^32, attempt, stream_id) and key
+ *   (seed mod 2^32, seed div 2^32) gives words x0..x3 per attempt;
+ *   r = floor((x0 + 2^32 x1) * W / 2^64), j1 = floor(x2 * a_p / 2^32),
+ *   j3 = floor(x3 * b_p / 2^32), each taken from the first attempt that
+ *   passes Lemire's rejection test (exactly uniform);
+ *   p is the edge with S[p] <= r < S[p+1]; e2 = out-CSR[p],
+ *   e1 = in-CSR[lo_in[p] + j1], e3 = out-CSR[lo_out[p] + j3];
+ *   X = 0 unless the four vertices are distinct, t1 < t2 < t3 and
+ *   t3 - t1 <= delta; otherwise X = the number of strictly increasing
+ *   chains l_3 < ... < l_{ne-1} with l_r a timestamp in (t3, t1 + delta] of
+ *   the pair (phi(src_r), phi(dst_r)), phi = (x, u, v, y)  (ListCount).
+ * W == 0 gives cnt = hits = 0, estimate 0, e* = -1, X = 0.
+ * Errors: TC_E_ARG, TC_E_UNSUPPORTED (motif shape), TC_E_HIP. */
+tc_status tc_sample_estimate(const tc_graph *g, const tc_weights *w, const tc_motif *motifs,
+                             int32_t n_motifs, uint64_t k, uint64_t seed, uint32_t stream_id,
+                             uint64_t i0, tc_result *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TC_H_ */

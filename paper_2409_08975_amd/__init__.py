@@ -1,0 +1,269 @@
+"""Python binding of libtc.so (the MI355X temporal 3-path sampling library).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+``libtc.so``.  PyTorch provides device memory and the current HIP stream.
+The names mirror the C ABI in ``include/tc.h``.  The library must be built
+(``python paper_2409_08975_amd/build.py``); importing the binding without it
+raises, and there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtc.so")
+
+TC_OK, TC_E_ARG, TC_E_RANGE, TC_E_OVERFLOW, TC_E_UNSUPPORTED, TC_E_WORKSPACE, TC_E_HIP = (
+    0, -1, -2, -3, -4, -5, -6)
+TC_F_RANGE, TC_F_OVERFLOW, TC_F_RNG = 1, 2, 4
+_STATUS_NAMES = {0: "TC_OK", -1: "TC_E_ARG", -2: "TC_E_RANGE", -3: "TC_E_OVERFLOW",
+                 -4: "TC_E_UNSUPPORTED", -5: "TC_E_WORKSPACE", -6: "TC_E_HIP"}
+
+EXPORTED = ["tc_version", "tc_graph_workspace_bytes", "tc_build_graph",
+            "tc_weights_workspace_bytes", "tc_path_weights", "tc_sample_estimate"]
+
+
+class TCError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__(f"{what}: {_STATUS_NAMES.get(code, code)}")
+
+
+class TCDeviceError(RuntimeError):
+    def __init__(self, bits, what=""):
+        self.bits = bits
+        names = [n for b, n in ((TC_F_RANGE, "RANGE"), (TC_F_OVERFLOW, "OVERFLOW"),
+                                (TC_F_RNG, "RNG")) if bits & b]
+        super().__init__(f"{what}: device status {'|'.join(names) or bits}")
+
+
+_P = ctypes.c_void_p
+
+
+class tc_motif(ctypes.Structure):
+    _fields_ = [("nv", ctypes.c_uint8), ("ne", ctypes.c_uint8),
+                ("src", ctypes.c_uint8 * 16), ("dst", ctypes.c_uint8 * 16)]
+
+
+class tc_graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("t_min", ctypes.c_int64),
+                ("t_max", ctypes.c_int64), ("out_off", _P), ("out_src", _P), ("out_dst", _P),
+                ("out_eid", _P), ("out_t", _P), ("in_off", _P), ("in_src", _P), ("in_eid", _P),
+                ("in_t", _P), ("pair_dst", _P), ("pair_eid", _P), ("pair_t", _P),
+                ("status", _P)]
+
+
+class tc_weights(ctypes.Structure):
+    _fields_ = [("delta", ctypes.c_int64), ("m", ctypes.c_int64), ("lo_in", _P), ("a", _P),
+                ("lo_out", _P), ("b", _P), ("S", _P), ("status", _P), ("scratch", _P)]
+
+
+class tc_result(ctypes.Structure):
+    _fields_ = [("cnt", _P), ("hits", _P), ("estimate", _P), ("status", _P), ("e1", _P),
+                ("e2", _P), ("e3", _P), ("X", _P)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libtc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2409_08975_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        I32, I64, U64, U32, SZ = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                                  ctypes.c_uint32, ctypes.c_size_t)
+        L.tc_version.restype = ctypes.c_char_p
+        L.tc_graph_workspace_bytes.argtypes = [I32, I64, ctypes.POINTER(SZ)]
+        L.tc_build_graph.argtypes = [I32, I64, _P, _P, _P, _P, SZ, _P, ctypes.POINTER(tc_graph)]
+        L.tc_weights_workspace_bytes.argtypes = [I64, ctypes.POINTER(SZ)]
+        L.tc_path_weights.argtypes = [ctypes.POINTER(tc_graph), I64, _P, SZ, _P,
+                                      ctypes.POINTER(tc_weights)]
+        L.tc_sample_estimate.argtypes = [ctypes.POINTER(tc_graph), ctypes.POINTER(tc_weights),
+                                         ctypes.POINTER(tc_motif), I32, U64, U64, U32, U64,
+                                         ctypes.POINTER(tc_result), _P]
+        for name in EXPORTED[1:]:
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code, what):
+    if code != TC_OK:
+        raise TCError(code, what)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_motif(edges, nv: int = 4) -> tc_motif:
+    m = tc_motif()
+    m.nv = nv
+    m.ne = len(edges)
+    for i, (a, b) in enumerate(edges):
+        m.src[i] = a
+        m.dst[i] = b
+    return m
+
+
+@dataclass
+class Graph:
+    c: tc_graph
+    ws: torch.Tensor
+    inputs: tuple = field(default=())
+
+    @property
+    def n(self):
+        return self.c.n
+
+    @property
+    def m(self):
+        return self.c.m
+
+    def view(self, name, dtype, length):
+        """Tensor view of one device array of the graph (no copy)."""
+        ptr = getattr(self.c, name)
+        base = self.ws.data_ptr()
+        elt = torch.empty((), dtype=dtype).element_size()
+        off = ptr - base
+        return self.ws[off:off + length * elt].view(dtype)
+
+    def arrays(self):
+        n, m = self.n, self.m
+        d = {}
+        for name, dt, ln in [("out_off", torch.int32, n + 1), ("in_off", torch.int32, n + 1),
+                             ("out_src", torch.int32, m), ("out_dst", torch.int32, m),
+                             ("out_eid", torch.int32, m), ("out_t", torch.int64, m),
+                             ("in_src", torch.int32, m), ("in_eid", torch.int32, m),
+                             ("in_t", torch.int64, m), ("pair_dst", torch.int32, m),
+                             ("pair_eid", torch.int32, m), ("pair_t", torch.int64, m)]:
+            d[name] = self.view(name, dt, ln)
+        return d
+
+
+@dataclass
+class Weights:
+    c: tc_weights
+    ws: torch.Tensor
+    graph: Graph
+
+    def view(self, name, dtype, length):
+        ptr = getattr(self.c, name)
+        off = ptr - self.ws.data_ptr()
+        elt = torch.empty((), dtype=dtype).element_size()
+        return self.ws[off:off + length * elt].view(dtype)
+
+    def arrays(self):
+        m = self.c.m
+        return dict(lo_in=self.view("lo_in", torch.int32, m), a=self.view("a", torch.int32, m),
+                    lo_out=self.view("lo_out", torch.int32, m), b=self.view("b", torch.int32, m),
+                    S=self.view("S", torch.int64, m + 1))
+
+    def status(self) -> int:
+        return int(self.view("status", torch.int32, 1).item()) & 0xFFFFFFFF
+
+    def total(self) -> int:
+        """W_delta as a Python int (synchronises)."""
+        return int(self.view("S", torch.int64, self.c.m + 1)[-1].item()) & (2**64 - 1)
+
+
+@dataclass
+class Result:
+    cnt: torch.Tensor       # int64 [2 * n_motifs] (lo, hi) bit patterns of u64
+    hits: torch.Tensor      # int64 [n_motifs]
+    estimate: torch.Tensor  # float64 [n_motifs]
+    status: torch.Tensor    # int32 [1]
+    e1: torch.Tensor | None = None
+    e2: torch.Tensor | None = None
+    e3: torch.Tensor | None = None
+    X: torch.Tensor | None = None  # int64 [n_motifs, k] (u64 bit patterns)
+
+    def counts(self):
+        c = self.cnt.cpu().tolist()
+        return [(c[2 * j] & (2**64 - 1)) | ((c[2 * j + 1] & (2**64 - 1)) << 64)
+                for j in range(len(c) // 2)]
+
+    def check(self, what="tc_sample_estimate"):
+        s = int(self.status.item()) & 0xFFFFFFFF
+        if s:
+            raise TCDeviceError(s, what)
+        return self
+
+
+def graph_workspace_bytes(n: int, m: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().tc_graph_workspace_bytes(n, m, ctypes.byref(b)), "tc_graph_workspace_bytes")
+    return b.value
+
+
+def weights_workspace_bytes(m: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().tc_weights_workspace_bytes(m, ctypes.byref(b)), "tc_weights_workspace_bytes")
+    return b.value
+
+
+def tc_build_graph(n: int, src: torch.Tensor, dst: torch.Tensor, t: torch.Tensor,
+                   stream=None) -> Graph:
+    """Build the temporal adjacency on the device (inputs: int32, int32, int64 CUDA tensors)."""
+    assert src.is_cuda and dst.is_cuda and t.is_cuda
+    assert src.dtype == torch.int32 and dst.dtype == torch.int32 and t.dtype == torch.int64
+    src, dst, t = src.contiguous(), dst.contiguous(), t.contiguous()
+    m = src.numel()
+    assert dst.numel() == m and t.numel() == m
+    nbytes = graph_workspace_bytes(n, m)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=src.device)
+    g = tc_graph()
+    _check(lib().tc_build_graph(n, m, _ptr(src), _ptr(dst), _ptr(t), _ptr(ws), nbytes,
+                                _stream(stream), ctypes.byref(g)), "tc_build_graph")
+    return Graph(g, ws, (src, dst, t))
+
+
+def tc_path_weights(graph: Graph, delta: int, stream=None) -> Weights:
+    nbytes = weights_workspace_bytes(graph.m)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=graph.ws.device)
+    w = tc_weights()
+    _check(lib().tc_path_weights(ctypes.byref(graph.c), int(delta), _ptr(ws), nbytes,
+                                 _stream(stream), ctypes.byref(w)), "tc_path_weights")
+    return Weights(w, ws, graph)
+
+
+def tc_sample_estimate(graph: Graph, weights: Weights, motifs, k: int, seed: int,
+                       stream_id: int = 0, i0: int = 0, per_sample: bool = False,
+                       stream=None, out: Result | None = None) -> Result:
+    """Estimate(M, k) for a list of motifs (each a list of (src, dst) edges in pi order)."""
+    nm = len(motifs)
+    arr = (tc_motif * nm)(*[make_motif(m) for m in motifs])
+    dev = graph.ws.device
+    if out is None:
+        out = Result(torch.zeros(2 * nm, dtype=torch.int64, device=dev),
+                     torch.zeros(nm, dtype=torch.int64, device=dev),
+                     torch.zeros(nm, dtype=torch.float64, device=dev),
+                     torch.zeros(1, dtype=torch.int32, device=dev))
+        if per_sample:
+            out.e1 = torch.empty(k, dtype=torch.int32, device=dev)
+            out.e2 = torch.empty(k, dtype=torch.int32, device=dev)
+            out.e3 = torch.empty(k, dtype=torch.int32, device=dev)
+            out.X = torch.empty((nm, k), dtype=torch.int64, device=dev)
+    r = tc_result(_ptr(out.cnt).value, _ptr(out.hits).value, _ptr(out.estimate).value,
+                  _ptr(out.status).value, _ptr(out.e1).value, _ptr(out.e2).value,
+                  _ptr(out.e3).value, _ptr(out.X).value)
+    _check(lib().tc_sample_estimate(ctypes.byref(graph.c), ctypes.byref(weights.c), arr, nm,
+                                    int(k), int(seed), int(stream_id), int(i0),
+                                    ctypes.byref(r), _stream(stream)), "tc_sample_estimate")
+    return out
+
+
+def version() -> str:
+    return lib().tc_version().decode()

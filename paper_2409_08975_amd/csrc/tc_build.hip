@@ -1,0 +1,521 @@
+// Temporal adjacency build: validation, stable LSD radix sorts and CSR
+// offsets.  The canonical orders are (t, eid) -> (src, t, eid) for the
+// out-lists, (dst, t, eid) for the in-lists and (src, dst, t, eid) for the
+// per-pair lists; each later sort is a stable sort of the previous order, so
+// timestamp ties keep increasing edge id (section III-A assumes time-sorted
+// per-vertex lists; the tie order is this library's convention).
+//
+// Radix sort design (gfx950, wave64): 8-bit digits, tiles of 4096 keys per
+// 256-thread block.  A pass is (1) per-tile digit histograms written
+// digit-major, (2) one exclusive scan of that [256][tiles] matrix, (3) a
+// scatter that ranks keys stably inside the tile with wavefront ballots
+// (8 ballots give the lanes sharing a digit), stages the tile in LDS in
+// digit order and writes each digit run to its global slot with coalesced
+// stores.
+#include <hip/hip_runtime.h>
+
+#include "tc_device.h"
+#include "tc_internal.h"
+
+namespace tc {
+
+constexpr int kSortBlock = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortBlock * kSortItems;  // 4096
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+// ---------------------------------------------------------------- scans ----
+// Exclusive scan of u32 in three kernels: tile sums, one-block scan of the
+// tile sums, tile scans with the tile offset added.
+__global__ __launch_bounds__(kScanBlock) void k_tile_sum_u32(const uint32_t* __restrict__ in,
+                                                           int64_t n, uint32_t* __restrict__ part) {
+  __shared__ uint32_t s_w[kScanBlock / kWave];
+  int64_t base = (int64_t)blockIdx.x * kScanTile;
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    int64_t i = base + (int64_t)j * kScanBlock + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < kScanBlock / kWave; ++w) t += s_w[w];
+    part[blockIdx.x] = t;
+  }
+}
+
+// single block of 1024 threads; any length, chunked with a running carry
+__global__ __launch_bounds__(1024) void k_scan_small_u32(uint32_t* __restrict__ a, int64_t n) {
+  __shared__ uint32_t s_w[16];
+  __shared__ uint32_t s_carry;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t base = 0; base < n; base += 1024) {
+    int64_t i = base + threadIdx.x;
+    uint32_t v = i < n ? a[i] : 0;
+    uint32_t inc = wave_inclusive_scan(v);
+    if (lane == 63) s_w[wave] = inc;
+    __syncthreads();
+    uint32_t wo = 0;
+    for (int w = 0; w < wave; ++w) wo += s_w[w];
+    uint32_t carry = s_carry;
+    if (i < n) a[i] = carry + wo + inc - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) s_carry = carry + wo + inc;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_tile_scan_u32(const uint32_t* __restrict__ in,
+                                                            uint32_t* __restrict__ out, int64_t n,
+                                                            const uint32_t* __restrict__ part) {
+  __shared__ uint32_t s_w[kScanBlock / kWave];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // blocked arrangement: thread owns kScanItems consecutive elements
+  int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    v[j] = (base + j < n) ? in[base + j] : 0;
+    s += v[j];
+  }
+  uint32_t inc = wave_inclusive_scan(s);
+  if (lane == 63) s_w[wave] = inc;
+  __syncthreads();
+  uint32_t run = part[blockIdx.x] + inc - s;
+  for (int w = 0; w < wave; ++w) run += s_w[w];
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    if (base + j < n) out[base + j] = run;
+    run += v[j];
+  }
+}
+
+size_t scan_u32_scratch_elems(int64_t n) {
+  return (size_t)((n + kScanTile - 1) / kScanTile) + 1;
+}
+
+// in-place exclusive scan of a[0..n)
+void scan_u32(uint32_t* a, int64_t n, uint32_t* part, hipStream_t st) {
+  if (n <= 0) return;
+  int64_t tiles = (n + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_tile_sum_u32, dim3((unsigned)tiles), dim3(kScanBlock), 0, st, a, n, part);
+  hipLaunchKernelGGL(k_scan_small_u32, dim3(1), dim3(1024), 0, st, part, tiles);
+  hipLaunchKernelGGL(k_tile_scan_u32, dim3((unsigned)tiles), dim3(kScanBlock), 0, st, a, a, n,
+                     (const uint32_t*)part);
+}
+
+// ------------------------------------------------------------ validation ---
+__global__ void k_init_build(uint32_t* status, uint64_t* tminmax) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *status = 0;
+    tminmax[0] = ~0ull;  // min of order-preserving keys
+    tminmax[1] = 0ull;   // max
+  }
+}
+
+// t is mapped to an order-preserving unsigned key (flip the sign bit)
+__global__ __launch_bounds__(256) void k_validate(const int32_t* __restrict__ src,
+                                                  const int32_t* __restrict__ dst,
+                                                  const int64_t* __restrict__ t, int64_t m,
+                                                  int32_t n, uint32_t* status, uint64_t* tminmax) {
+  const int64_t lim = (int64_t)1 << 62;
+  uint64_t mn = ~0ull, mx = 0;
+  uint32_t bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t s = src[i], d = dst[i];
+    int64_t tt = t[i];
+    if (s < 0 || s >= n || d < 0 || d >= n || tt >= lim || tt <= -lim) bad = 1;
+    uint64_t key = (uint64_t)tt ^ (1ull << 63);
+    mn = key < mn ? key : mn;
+    mx = key > mx ? key : mx;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    uint64_t a = __shfl_xor(mn, off, kWave);
+    uint64_t b = __shfl_xor(mx, off, kWave);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+    bad |= __shfl_xor(bad, off, kWave);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin((unsigned long long*)&tminmax[0], (unsigned long long)mn);
+    atomicMax((unsigned long long*)&tminmax[1], (unsigned long long)mx);
+    if (bad) atomicOr(status, TC_F_RANGE);
+  }
+}
+
+// ----------------------------------------------------------- key making ----
+template <typename K>
+__global__ __launch_bounds__(256) void k_time_keys(const int64_t* __restrict__ t, int64_t m,
+                                                   int64_t tmin, K* __restrict__ keys,
+                                                   int32_t* __restrict__ vals) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) {
+    keys[i] = (K)(uint64_t)(t[i] - tmin);
+    vals[i] = (int32_t)i;
+  }
+}
+
+// keys[i] = vert[order[i]], vals[i] = order[i]
+__global__ __launch_bounds__(256) void k_vertex_keys(const int32_t* __restrict__ vert,
+                                                     const int32_t* __restrict__ order, int64_t m,
+                                                     uint32_t* __restrict__ keys,
+                                                     int32_t* __restrict__ vals) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) {
+    int32_t e = order[i];
+    keys[i] = (uint32_t)vert[e];
+    vals[i] = e;
+  }
+}
+
+// ----------------------------------------------------------- radix pass ----
+template <typename K>
+__global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__ keys, int64_t m,
+                                                           int shift, uint32_t* __restrict__ hist,
+                                                           int64_t ntiles) {
+  __shared__ uint32_t s_h[256];
+  s_h[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t start = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    int64_t i = start + (int64_t)r * kSortBlock + threadIdx.x;
+    if (i < m) atomicAdd(&s_h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = s_h[threadIdx.x];
+}
+
+template <typename K>
+__global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restrict__ kin,
+                                                              const int32_t* __restrict__ vin,
+                                                              K* __restrict__ kout,
+                                                              int32_t* __restrict__ vout, int64_t m,
+                                                              int shift,
+                                                              const uint32_t* __restrict__ hist,
+                                                              int64_t ntiles) {
+  __shared__ uint32_t s_base[256];
+  __shared__ uint32_t s_run[256];
+  __shared__ uint32_t s_excl[256];
+  __shared__ uint32_t s_wcnt[kSortBlock / kWave][256];
+  __shared__ uint32_t s_wsum[kSortBlock / kWave];
+  __shared__ K s_key[kSortTile];
+  __shared__ int32_t s_val[kSortTile];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t start = (int64_t)blockIdx.x * kSortTile;
+  const int len = (int)((m - start) < kSortTile ? (m - start) : kSortTile);
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+  s_base[tid] = hist[(int64_t)tid * ntiles + blockIdx.x];
+  s_run[tid] = 0;
+#pragma unroll
+  for (int w = 0; w < kSortBlock / kWave; ++w) s_wcnt[w][tid] = 0;
+  __syncthreads();
+
+  K key[kSortItems];
+  int32_t val[kSortItems];
+  uint32_t rank[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int idx = r * kSortBlock + tid;
+    const bool valid = idx < len;
+    key[r] = valid ? kin[start + idx] : (K)0;
+    val[r] = valid ? vin[start + idx] : 0;
+    const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+    // lanes holding the same digit (and the same validity)
+    uint64_t vb = __ballot(valid);
+    uint64_t peers = valid ? vb : ~vb;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t wrank = (uint32_t)__popcll(peers & lt_mask);
+    if (valid && wrank == 0) s_wcnt[wave][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    uint32_t before = s_run[d];
+    for (int w = 0; w < wave; ++w) before += s_wcnt[w][d];
+    rank[r] = before + wrank;
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int w = 0; w < kSortBlock / kWave; ++w) {
+      add += s_wcnt[w][tid];
+      s_wcnt[w][tid] = 0;
+    }
+    s_run[tid] += add;
+    __syncthreads();
+  }
+  // tile-local exclusive offsets per digit (thread tid owns digit tid)
+  {
+    uint32_t c = s_run[tid];
+    uint32_t inc = wave_inclusive_scan(c);
+    if (lane == 63) s_wsum[wave] = inc;
+    __syncthreads();
+    uint32_t off = inc - c;
+    for (int w = 0; w < wave; ++w) off += s_wsum[w];
+    s_excl[tid] = off;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int idx = r * kSortBlock + tid;
+    if (idx < len) {
+      const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+      const uint32_t pos = s_excl[d] + rank[r];
+      s_key[pos] = key[r];
+      s_val[pos] = val[r];
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < len; i += kSortBlock) {
+    const K k = s_key[i];
+    const uint32_t d = (uint32_t)(k >> shift) & 255u;
+    const int64_t g = (int64_t)s_base[d] + (i - (int64_t)s_excl[d]);
+    kout[g] = k;
+    vout[g] = s_val[i];
+  }
+}
+
+// Sort (keys, vals) of length m by the low `bits` bits of the key, stably.
+// Ping-pongs between (k0, v0) and (k1, v1); returns 0 if the result is in
+// buffer 0, 1 if in buffer 1.
+template <typename K>
+int radix_sort(K* k0, int32_t* v0, K* k1, int32_t* v1, int64_t m, int bits, uint32_t* hist,
+               uint32_t* part, hipStream_t st) {
+  if (m <= 0) return 0;
+  const int64_t ntiles = (m + kSortTile - 1) / kSortTile;
+  int cur = 0;
+  for (int shift = 0; shift < bits; shift += 8) {
+    K* ki = cur ? k1 : k0;
+    int32_t* vi = cur ? v1 : v0;
+    K* ko = cur ? k0 : k1;
+    int32_t* vo = cur ? v0 : v1;
+    hipLaunchKernelGGL((k_radix_hist<K>), dim3((unsigned)ntiles), dim3(kSortBlock), 0, st,
+                       (const K*)ki, m, shift, hist, ntiles);
+    scan_u32(hist, 256 * ntiles, part, st);
+    hipLaunchKernelGGL((k_radix_scatter<K>), dim3((unsigned)ntiles), dim3(kSortBlock), 0, st,
+                       (const K*)ki, (const int32_t*)vi, ko, vo, m, shift, (const uint32_t*)hist,
+                       ntiles);
+    cur ^= 1;
+  }
+  return cur;
+}
+
+// -------------------------------------------------------- columns/offsets ---
+// Gather the columns of one order.  key_col receives the sort key (the
+// vertex), the optional other columns come from the input arrays.
+__global__ __launch_bounds__(256) void k_gather_order(
+    const uint32_t* __restrict__ skeys, const int32_t* __restrict__ order, int64_t m,
+    const int32_t* __restrict__ other_v, const int64_t* __restrict__ t,
+    int32_t* __restrict__ key_col, int32_t* __restrict__ other_col, int64_t* __restrict__ t_col,
+    int32_t* __restrict__ eid_col) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) {
+    int32_t e = order[i];
+    if (key_col) key_col[i] = (int32_t)skeys[i];
+    if (other_col) other_col[i] = other_v[e];
+    t_col[i] = t[e];
+    eid_col[i] = e;
+  }
+}
+
+// off[v] = first position whose sorted key is >= v, for v in [0, n]
+__global__ __launch_bounds__(256) void k_offsets(const uint32_t* __restrict__ skeys, int64_t m,
+                                                 int32_t n, uint32_t* __restrict__ off) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > m) return;
+  int64_t prev = (i == 0) ? -1 : (int64_t)skeys[i - 1];
+  int64_t cur = (i == m) ? (int64_t)n : (int64_t)skeys[i];
+  for (int64_t v = prev + 1; v <= cur; ++v) off[v] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ a, int64_t n,
+                                                  uint32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// --------------------------------------------------------------- layout ----
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct GraphLayout {
+  size_t out_off, in_off, out_src, out_dst, out_eid, out_t, in_src, in_eid, in_t, pair_dst,
+      pair_eid, pair_t, status, tminmax, keys0, keys1, vals0, vals1, hist, part, total;
+};
+
+static GraphLayout graph_layout(int32_t n, int64_t m) {
+  GraphLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(bytes ? bytes : 1);
+    return at;
+  };
+  const size_t M = (size_t)m;
+  const int64_t ntiles = (m + kSortTile - 1) / kSortTile;
+  L.out_off = take(((size_t)n + 1) * 4);
+  L.in_off = take(((size_t)n + 1) * 4);
+  L.out_src = take(M * 4);
+  L.out_dst = take(M * 4);
+  L.out_eid = take(M * 4);
+  L.out_t = take(M * 8);
+  L.in_src = take(M * 4);
+  L.in_eid = take(M * 4);
+  L.in_t = take(M * 8);
+  L.pair_dst = take(M * 4);
+  L.pair_eid = take(M * 4);
+  L.pair_t = take(M * 8);
+  L.status = take(4);
+  L.tminmax = take(16);
+  L.keys0 = take(M * 8);
+  L.keys1 = take(M * 8);
+  L.vals0 = take(M * 4);
+  L.vals1 = take(M * 4);
+  L.hist = take((size_t)256 * ntiles * 4);
+  L.part = take(scan_u32_scratch_elems(256 * ntiles + 1) * 4 + 1024);
+  L.total = o;
+  return L;
+}
+
+size_t graph_workspace_bytes(int32_t n, int64_t m) { return graph_layout(n, m).total; }
+
+static int bitlen(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
+
+static unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                      const int64_t* t, void* ws, size_t ws_bytes, hipStream_t st, tc_graph* g) {
+  GraphLayout L = graph_layout(n, m);
+  if (ws_bytes < L.total) return TC_E_WORKSPACE;
+  char* base = (char*)ws;
+  g->n = n;
+  g->m = m;
+  g->out_off = (uint32_t*)(base + L.out_off);
+  g->in_off = (uint32_t*)(base + L.in_off);
+  g->out_src = (int32_t*)(base + L.out_src);
+  g->out_dst = (int32_t*)(base + L.out_dst);
+  g->out_eid = (int32_t*)(base + L.out_eid);
+  g->out_t = (int64_t*)(base + L.out_t);
+  g->in_src = (int32_t*)(base + L.in_src);
+  g->in_eid = (int32_t*)(base + L.in_eid);
+  g->in_t = (int64_t*)(base + L.in_t);
+  g->pair_dst = (int32_t*)(base + L.pair_dst);
+  g->pair_eid = (int32_t*)(base + L.pair_eid);
+  g->pair_t = (int64_t*)(base + L.pair_t);
+  g->status = (uint32_t*)(base + L.status);
+  uint64_t* tminmax = (uint64_t*)(base + L.tminmax);
+  void* keys0 = base + L.keys0;
+  void* keys1 = base + L.keys1;
+  int32_t* vals0 = (int32_t*)(base + L.vals0);
+  int32_t* vals1 = (int32_t*)(base + L.vals1);
+  uint32_t* hist = (uint32_t*)(base + L.hist);
+  uint32_t* part = (uint32_t*)(base + L.part);
+
+  hipLaunchKernelGGL(k_init_build, dim3(1), dim3(64), 0, st, g->status, tminmax);
+  if (m > 0) {
+    unsigned vb = blocks_for(m, 256);
+    if (vb > 4096) vb = 4096;
+    hipLaunchKernelGGL(k_validate, dim3(vb), dim3(256), 0, st, src, dst, t, m, n, g->status,
+                       tminmax);
+  }
+  uint32_t h_status = 0;
+  uint64_t h_mm[2] = {0, 0};
+  if (hipMemcpyAsync(&h_status, g->status, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(h_mm, tminmax, 16, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return TC_E_HIP;
+  if (h_status != 0) return TC_E_RANGE;
+  const int64_t tmin = m > 0 ? (int64_t)(h_mm[0] ^ (1ull << 63)) : 0;
+  const int64_t tmax = m > 0 ? (int64_t)(h_mm[1] ^ (1ull << 63)) : 0;
+  g->t_min = tmin;
+  g->t_max = tmax;
+  const unsigned eb = blocks_for(m > 0 ? m : 1, 256);
+
+  // 1. time order: stable by t (initial order = eid)
+  const int tbits = bitlen((uint64_t)(tmax - tmin));
+  int32_t* torder;
+  if (m > 0) {
+    int where;
+    if (tbits <= 32) {
+      hipLaunchKernelGGL((k_time_keys<uint32_t>), dim3(eb), dim3(256), 0, st, t, m, tmin,
+                         (uint32_t*)keys0, vals0);
+      where = radix_sort<uint32_t>((uint32_t*)keys0, vals0, (uint32_t*)keys1, vals1, m, tbits,
+                                   hist, part, st);
+    } else {
+      hipLaunchKernelGGL((k_time_keys<uint64_t>), dim3(eb), dim3(256), 0, st, t, m, tmin,
+                         (uint64_t*)keys0, vals0);
+      where = radix_sort<uint64_t>((uint64_t*)keys0, vals0, (uint64_t*)keys1, vals1, m, tbits,
+                                   hist, part, st);
+    }
+    torder = where ? vals1 : vals0;
+  } else {
+    torder = vals0;
+  }
+  // the time order is kept in the eid column of the pair index until the
+  // pair sort needs it (pair_eid is rewritten at the end)
+  int32_t* torder_keep = g->pair_eid;
+  if (m > 0 &&
+      hipMemcpyAsync(torder_keep, torder, (size_t)m * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return TC_E_HIP;
+  const int vbits = bitlen((uint64_t)(n - 1));
+  uint32_t* k0 = (uint32_t*)keys0;
+  uint32_t* k1 = (uint32_t*)keys1;
+  // 2. out-CSR: stable by src
+  if (m > 0) {
+    hipLaunchKernelGGL(k_vertex_keys, dim3(eb), dim3(256), 0, st, src, torder_keep, m, k0, vals0);
+    int w = radix_sort<uint32_t>(k0, vals0, k1, vals1, m, vbits, hist, part, st);
+    uint32_t* sk = w ? k1 : k0;
+    int32_t* sv = w ? vals1 : vals0;
+    hipLaunchKernelGGL(k_gather_order, dim3(eb), dim3(256), 0, st, (const uint32_t*)sk,
+                       (const int32_t*)sv, m, dst, t, g->out_src, g->out_dst, g->out_t,
+                       g->out_eid);
+    hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
+                       (const uint32_t*)sk, m, n, g->out_off);
+  } else {
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for((int64_t)n + 1, 256)), dim3(256), 0, st,
+                       g->out_off, (int64_t)n + 1, 0u);
+  }
+  // 3. in-CSR: stable by dst
+  if (m > 0) {
+    hipLaunchKernelGGL(k_vertex_keys, dim3(eb), dim3(256), 0, st, dst, torder_keep, m, k0, vals0);
+    int w = radix_sort<uint32_t>(k0, vals0, k1, vals1, m, vbits, hist, part, st);
+    uint32_t* sk = w ? k1 : k0;
+    int32_t* sv = w ? vals1 : vals0;
+    hipLaunchKernelGGL(k_gather_order, dim3(eb), dim3(256), 0, st, (const uint32_t*)sk,
+                       (const int32_t*)sv, m, src, t, (int32_t*)nullptr, g->in_src, g->in_t,
+                       g->in_eid);
+    hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
+                       (const uint32_t*)sk, m, n, g->in_off);
+  } else {
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for((int64_t)n + 1, 256)), dim3(256), 0, st,
+                       g->in_off, (int64_t)n + 1, 0u);
+  }
+  // 4. pair index: the in-order (dst, t, eid) stably sorted by src
+  if (m > 0) {
+    hipLaunchKernelGGL(k_vertex_keys, dim3(eb), dim3(256), 0, st, src, g->in_eid, m, k0, vals0);
+    int w = radix_sort<uint32_t>(k0, vals0, k1, vals1, m, vbits, hist, part, st);
+    uint32_t* sk = w ? k1 : k0;
+    int32_t* sv = w ? vals1 : vals0;
+    hipLaunchKernelGGL(k_gather_order, dim3(eb), dim3(256), 0, st, (const uint32_t*)sk,
+                       (const int32_t*)sv, m, dst, t, (int32_t*)nullptr, g->pair_dst, g->pair_t,
+                       g->pair_eid);
+  }
+  if (hipGetLastError() != hipSuccess) return TC_E_HIP;
+  return TC_OK;
+}
+
+}  // namespace tc

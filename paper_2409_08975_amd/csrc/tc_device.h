@@ -1,0 +1,168 @@
+// Device helpers for gfx950 (wave64): counter-based RNG, exact range
+// reduction, branch-light binary searches, 128-bit accumulation and
+// wavefront reductions/scans.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tc.h"
+
+namespace tc {
+
+constexpr int kWave = 64;
+constexpr int kMaxAttempts = 1024;
+
+// ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011) -------------------
+// Ten rounds of two 32x32->64 multiplies (multipliers 0xD2511F53 and
+// 0xCD9E8D57) with the Weyl key schedule (0x9E3779B9, 0xBB67AE85).
+struct Words4 {
+  uint32_t x0, x1, x2, x3;
+};
+
+__device__ __forceinline__ Words4 philox_block(uint64_t seed, uint32_t stream, uint64_t i,
+                                               uint32_t attempt) {
+  uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32), c2 = attempt, c3 = stream;
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint32_t lo0 = 0xD2511F53u * c0;
+    uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+    uint32_t lo1 = 0xCD9E8D57u * c2;
+    uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return Words4{c0, c1, c2, c3};
+}
+
+// ---- Lemire range reduction with rejection ---------------------------------
+// floor(x * s / 2^64); the draw is rejected iff the low 64 bits of x * s are
+// below (2^64 - s) mod s.  The modulo is only needed when low < s.
+__device__ __forceinline__ bool range64(uint64_t x, uint64_t s, uint64_t* out) {
+  uint64_t lo = x * s;
+  uint64_t hi = __umul64hi(x, s);
+  if (lo < s) {
+    uint64_t thresh = (0ull - s) % s;
+    if (lo < thresh) return false;
+  }
+  *out = hi;
+  return true;
+}
+
+__device__ __forceinline__ bool range32(uint32_t x, uint32_t s, uint32_t* out) {
+  uint64_t p = (uint64_t)x * (uint64_t)s;
+  uint32_t lo = (uint32_t)p;
+  if (lo < s) {
+    uint32_t thresh = (0u - s) % s;
+    if (lo < thresh) return false;
+  }
+  *out = (uint32_t)(p >> 32);
+  return true;
+}
+
+// ---- searches over sorted device arrays ------------------------------------
+// first index in [lo, hi) with a[idx] >= key
+template <typename T>
+__device__ __forceinline__ uint32_t lower_bound(const T* __restrict__ a, uint32_t lo, uint32_t hi,
+                                                T key) {
+  uint32_t n = hi - lo;
+  while (n > 0) {
+    uint32_t half = n >> 1;
+    uint32_t mid = lo + half;
+    bool go_right = a[mid] < key;
+    lo = go_right ? mid + 1 : lo;
+    n = go_right ? n - half - 1 : half;
+  }
+  return lo;
+}
+
+// first index in [lo, hi) with a[idx] > key
+template <typename T>
+__device__ __forceinline__ uint32_t upper_bound(const T* __restrict__ a, uint32_t lo, uint32_t hi,
+                                                T key) {
+  uint32_t n = hi - lo;
+  while (n > 0) {
+    uint32_t half = n >> 1;
+    uint32_t mid = lo + half;
+    bool go_right = !(key < a[mid]);
+    lo = go_right ? mid + 1 : lo;
+    n = go_right ? n - half - 1 : half;
+  }
+  return lo;
+}
+
+// ---- 128-bit unsigned accumulation ----------------------------------------
+struct U128 {
+  uint64_t lo, hi;
+};
+
+__device__ __forceinline__ U128 add128(U128 a, U128 b) {
+  U128 r;
+  r.lo = a.lo + b.lo;
+  r.hi = a.hi + b.hi + (r.lo < a.lo ? 1ull : 0ull);
+  return r;
+}
+
+__device__ __forceinline__ U128 shfl_xor128(U128 v, int mask) {
+  U128 r;
+  r.lo = __shfl_xor(v.lo, mask, kWave);
+  r.hi = __shfl_xor(v.hi, mask, kWave);
+  return r;
+}
+
+__device__ __forceinline__ U128 wave_sum128(U128 v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = add128(v, shfl_xor128(v, off));
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// inclusive scan across the wave (lane order)
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    T o = __shfl_up(v, off, kWave);
+    if (lane >= off) v += o;
+  }
+  return v;
+}
+
+// Correctly rounded (round-to-nearest-even) conversion of a 128-bit unsigned
+// integer to binary64.  The top 64 significant bits are converted with the
+// lowest bit forced to 1 when any lower bit is set (a sticky bit below the
+// rounding position keeps the single rounding exact), then scaled exactly.
+__device__ __forceinline__ double u128_to_double(uint64_t lo, uint64_t hi) {
+  if (hi == 0) return (double)lo;
+  int lz = __clzll(hi);
+  int shift = 64 - lz;  // bits beyond 64, 1..64
+  uint64_t top, rest;
+  if (shift == 64) {
+    top = hi;
+    rest = lo;
+  } else {
+    top = (hi << (64 - shift)) | (lo >> shift);
+    rest = lo << (64 - shift);
+  }
+  if (rest != 0) top |= 1ull;
+  return ldexp((double)top, shift);
+}
+
+__device__ __forceinline__ void set_status(uint32_t* status, uint32_t bits) {
+  atomicOr(status, bits);
+}
+
+}  // namespace tc

@@ -1,0 +1,224 @@
+// Preprocess(delta): per-edge window degrees and the exact integer CDF of the
+// path weights (Algorithm Preprocess with Claim "count":
+// w_e = d^-_u[t - delta, t] * d^+_v[t, t + delta]).
+//
+// Three kernels, all streaming in scan order p (out-CSR order):
+//   k_windows     coalesced reads of (src, dst, t)[p]; four binary searches
+//                 per edge (two in u's in-list, two in v's out-list; u is
+//                 shared by consecutive p, so its list stays in cache);
+//                 writes lo_in, a, lo_out, b and the 128-bit sum of a*b per
+//                 2048-edge tile.
+//   k_scan_tiles  one block scans the tile sums in 128-bit arithmetic, so
+//                 W >= 2^64 is detected exactly, and writes S[m] = W.
+//   k_scan_apply  per tile: w = a*b, block-wide exclusive scan, plus the
+//                 tile offset -> S[p].
+#include <hip/hip_runtime.h>
+
+#include "tc_device.h"
+#include "tc_internal.h"
+
+namespace tc {
+
+constexpr int kWBlock = 256;
+constexpr int kWItems = 8;
+constexpr int kWTile = kWBlock * kWItems;  // 2048 edges per tile
+
+__global__ __launch_bounds__(kWBlock) void k_windows(
+    const int32_t* __restrict__ out_src, const int32_t* __restrict__ out_dst,
+    const int64_t* __restrict__ out_t, const uint32_t* __restrict__ in_off,
+    const int64_t* __restrict__ in_t, const uint32_t* __restrict__ out_off, int64_t m,
+    int64_t delta, uint32_t* __restrict__ lo_in, uint32_t* __restrict__ a_out,
+    uint32_t* __restrict__ lo_out, uint32_t* __restrict__ b_out, uint64_t* __restrict__ tile_sums) {
+  __shared__ U128 s_w[kWBlock / kWave];
+  const int64_t start = (int64_t)blockIdx.x * kWTile;
+  U128 acc{0, 0};
+#pragma unroll 2
+  for (int r = 0; r < kWItems; ++r) {
+    const int64_t p = start + (int64_t)r * kWBlock + threadIdx.x;
+    if (p < m) {
+      const int32_t u = out_src[p];
+      const int32_t v = out_dst[p];
+      const int64_t t = out_t[p];
+      const uint32_t il = in_off[u], ih = in_off[u + 1];
+      const uint32_t i0 = lower_bound<int64_t>(in_t, il, ih, t - delta);
+      const uint32_t i1 = upper_bound<int64_t>(in_t, i0, ih, t);
+      const uint32_t ol = out_off[v], oh = out_off[v + 1];
+      const uint32_t o0 = lower_bound<int64_t>(out_t, ol, oh, t);
+      const uint32_t o1 = upper_bound<int64_t>(out_t, o0, oh, t + delta);
+      lo_in[p] = i0;
+      a_out[p] = i1 - i0;
+      lo_out[p] = o0;
+      b_out[p] = o1 - o0;
+      const uint64_t w = (uint64_t)(i1 - i0) * (uint64_t)(o1 - o0);
+      acc = add128(acc, U128{w, 0});
+    }
+  }
+  acc = wave_sum128(acc);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    U128 t{0, 0};
+    for (int w = 0; w < kWBlock / kWave; ++w) t = add128(t, s_w[w]);
+    tile_sums[2 * blockIdx.x] = t.lo;
+    tile_sums[2 * blockIdx.x + 1] = t.hi;
+  }
+}
+
+// One block of 1024 threads: exclusive scan of the 128-bit tile sums; the
+// offsets are stored modulo 2^64 (only meaningful when W < 2^64).
+__global__ __launch_bounds__(1024) void k_scan_tiles(const uint64_t* __restrict__ tile_sums,
+                                                     int64_t ntiles, uint64_t* __restrict__ tile_off,
+                                                     uint64_t* __restrict__ S, int64_t m,
+                                                     uint32_t* __restrict__ status) {
+  __shared__ U128 s_w[16];
+  __shared__ U128 s_carry;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) s_carry = U128{0, 0};
+  __syncthreads();
+  for (int64_t base = 0; base < ntiles; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    U128 v = (i < ntiles) ? U128{tile_sums[2 * i], tile_sums[2 * i + 1]} : U128{0, 0};
+    U128 inc = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      U128 o{__shfl_up(inc.lo, off, kWave), __shfl_up(inc.hi, off, kWave)};
+      if (lane >= off) inc = add128(inc, o);
+    }
+    if (lane == 63) s_w[wave] = inc;
+    __syncthreads();
+    U128 pre = s_carry;
+    for (int w = 0; w < wave; ++w) pre = add128(pre, s_w[w]);
+    // exclusive = pre + inc - v
+    U128 excl = pre;
+    {
+      U128 d{inc.lo - v.lo, inc.hi - v.hi - (inc.lo < v.lo ? 1ull : 0ull)};
+      excl = add128(excl, d);
+    }
+    if (i < ntiles) tile_off[i] = excl.lo;
+    __syncthreads();
+    if (threadIdx.x == 1023) s_carry = add128(pre, inc);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const U128 W = s_carry;
+    S[m] = W.lo;
+    *status = (W.hi != 0) ? TC_F_OVERFLOW : 0u;
+  }
+}
+
+__global__ __launch_bounds__(kWBlock) void k_scan_apply(const uint32_t* __restrict__ a,
+                                                      const uint32_t* __restrict__ b, int64_t m,
+                                                      const uint64_t* __restrict__ tile_off,
+                                                      uint64_t* __restrict__ S) {
+  __shared__ uint64_t s_w[kWBlock / kWave];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t p0 = (int64_t)blockIdx.x * kWTile + (int64_t)threadIdx.x * kWItems;
+  uint64_t w[kWItems];
+  uint64_t s = 0;
+  if (p0 + kWItems <= m) {
+    const uint4* a4 = reinterpret_cast<const uint4*>(a + p0);
+    const uint4* b4 = reinterpret_cast<const uint4*>(b + p0);
+    uint4 aa0 = a4[0], aa1 = a4[1], bb0 = b4[0], bb1 = b4[1];
+    uint32_t av[8] = {aa0.x, aa0.y, aa0.z, aa0.w, aa1.x, aa1.y, aa1.z, aa1.w};
+    uint32_t bv[8] = {bb0.x, bb0.y, bb0.z, bb0.w, bb1.x, bb1.y, bb1.z, bb1.w};
+#pragma unroll
+    for (int j = 0; j < kWItems; ++j) {
+      w[j] = (uint64_t)av[j] * (uint64_t)bv[j];
+      s += w[j];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kWItems; ++j) {
+      const int64_t p = p0 + j;
+      w[j] = (p < m) ? (uint64_t)a[p] * (uint64_t)b[p] : 0ull;
+      s += w[j];
+    }
+  }
+  const uint64_t inc = wave_inclusive_scan(s);
+  if (lane == 63) s_w[wave] = inc;
+  __syncthreads();
+  uint64_t run = tile_off[blockIdx.x] + inc - s;
+  for (int q = 0; q < wave; ++q) run += s_w[q];
+  if (p0 + kWItems <= m) {
+    uint64_t out[kWItems];
+#pragma unroll
+    for (int j = 0; j < kWItems; ++j) {
+      out[j] = run;
+      run += w[j];
+    }
+    ulonglong2* S2 = reinterpret_cast<ulonglong2*>(S + p0);
+#pragma unroll
+    for (int j = 0; j < kWItems / 2; ++j) S2[j] = make_ulonglong2(out[2 * j], out[2 * j + 1]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < kWItems; ++j) {
+      const int64_t p = p0 + j;
+      if (p < m) S[p] = run;
+      run += w[j];
+    }
+  }
+}
+
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct WeightsLayout {
+  size_t lo_in, a, lo_out, b, S, status, tile_sums, tile_off, total;
+};
+
+static WeightsLayout weights_layout(int64_t m) {
+  WeightsLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(bytes ? bytes : 1);
+    return at;
+  };
+  const size_t M = (size_t)m;
+  const size_t ntiles = (size_t)((m + kWTile - 1) / kWTile);
+  L.lo_in = take(M * 4);
+  L.a = take(M * 4);
+  L.lo_out = take(M * 4);
+  L.b = take(M * 4);
+  L.S = take((M + 1) * 8);
+  L.status = take(4);
+  L.tile_sums = take(ntiles * 16);
+  L.tile_off = take(ntiles * 8);
+  L.total = o;
+  return L;
+}
+
+size_t weights_workspace_bytes(int64_t m) { return weights_layout(m).total; }
+
+tc_status path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_bytes,
+                       hipStream_t st, tc_weights* w) {
+  const int64_t m = g->m;
+  WeightsLayout L = weights_layout(m);
+  if (ws_bytes < L.total) return TC_E_WORKSPACE;
+  char* base = (char*)ws;
+  w->delta = delta;
+  w->m = m;
+  w->lo_in = (uint32_t*)(base + L.lo_in);
+  w->a = (uint32_t*)(base + L.a);
+  w->lo_out = (uint32_t*)(base + L.lo_out);
+  w->b = (uint32_t*)(base + L.b);
+  w->S = (uint64_t*)(base + L.S);
+  w->status = (uint32_t*)(base + L.status);
+  w->scratch = base + L.tile_sums;
+  uint64_t* tile_sums = (uint64_t*)(base + L.tile_sums);
+  uint64_t* tile_off = (uint64_t*)(base + L.tile_off);
+  const int64_t ntiles = (m + kWTile - 1) / kWTile;
+  if (ntiles > 0)
+    hipLaunchKernelGGL(k_windows, dim3((unsigned)ntiles), dim3(kWBlock), 0, st, g->out_src,
+                       g->out_dst, g->out_t, g->in_off, g->in_t, g->out_off, m, delta, w->lo_in,
+                       w->a, w->lo_out, w->b, tile_sums);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, (const uint64_t*)tile_sums, ntiles,
+                     tile_off, w->S, m, w->status);
+  if (ntiles > 0)
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
+                       (const uint32_t*)w->a, (const uint32_t*)w->b, m,
+                       (const uint64_t*)tile_off, w->S);
+  if (hipGetLastError() != hipSuccess) return TC_E_HIP;
+  return TC_OK;
+}
+
+}  // namespace tc

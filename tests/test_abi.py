@@ -1,0 +1,104 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and host-checkable errors are reported without touching a
+GPU (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tc.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tc_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def tcb():
+    import paper_2409_08975_amd as tcb
+    if not os.path.exists(tcb.LIB_PATH):
+        import paper_2409_08975_amd.build as b
+        b.build()
+    tcb.lib()
+    return tcb
+
+
+def test_header_declares_the_three_phases():
+    d = _declared()
+    for name in ["tc_build_graph", "tc_path_weights", "tc_sample_estimate",
+                 "tc_graph_workspace_bytes", "tc_weights_workspace_bytes", "tc_version"]:
+        assert name in d
+
+
+def test_library_exports_every_declared_symbol(tcb):
+    L = tcb.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert set(_declared()) == set(tcb.EXPORTED)
+
+
+def test_version_string(tcb):
+    assert "gfx950" in tcb.version()
+
+
+def test_workspace_queries(tcb):
+    b1 = tcb.graph_workspace_bytes(1000, 20000)
+    b2 = tcb.graph_workspace_bytes(1000, 40000)
+    assert b2 > b1 > 20000 * 16
+    w = tcb.weights_workspace_bytes(20000)
+    assert w >= 20000 * 16 + 20001 * 8
+    assert tcb.weights_workspace_bytes(0) > 0
+    with pytest.raises(tcb.TCError):
+        tcb.graph_workspace_bytes(0, 10)
+    with pytest.raises(tcb.TCError):
+        tcb.graph_workspace_bytes(10, -1)
+    with pytest.raises(tcb.TCError):
+        tcb.graph_workspace_bytes(10, 2**31)
+
+
+def test_host_argument_errors_return_before_any_launch(tcb):
+    L = tcb.lib()
+    g = tcb.tc_graph()
+    # n < 1, null workspace
+    assert L.tc_build_graph(0, 1, None, None, None, None, 0, None, ctypes.byref(g)) == tcb.TC_E_ARG
+    assert L.tc_build_graph(5, 1, None, None, None, ctypes.c_void_p(1), 0, None,
+                            ctypes.byref(g)) == tcb.TC_E_ARG
+    w = tcb.tc_weights()
+    g.m = 10
+    w.m = 10
+    assert L.tc_path_weights(ctypes.byref(g), -1, ctypes.c_void_p(1), 0, None,
+                             ctypes.byref(w)) == tcb.TC_E_ARG
+    assert L.tc_path_weights(ctypes.byref(g), 2**62 + 1, ctypes.c_void_p(1), 0, None,
+                             ctypes.byref(w)) == tcb.TC_E_ARG
+    fake = ctypes.c_void_p(256).value
+    r = tcb.tc_result(fake, fake, fake, fake, None, None, None, None)
+    bad = [(0, 1), (2, 1), (1, 2)]  # not anchored on 0->1->2->3
+    arr = (tcb.tc_motif * 1)(tcb.make_motif(bad))
+    assert L.tc_sample_estimate(ctypes.byref(g), ctypes.byref(w), arr, 1, 10, 1, 0, 0,
+                                ctypes.byref(r), None) == tcb.TC_E_UNSUPPORTED
+    ok = [(0, 1), (1, 2), (2, 3), (3, 0)]
+    arr = (tcb.tc_motif * 1)(tcb.make_motif(ok))
+    assert L.tc_sample_estimate(ctypes.byref(g), ctypes.byref(w), arr, 1, 0, 1, 0, 0,
+                                ctypes.byref(r), None) == tcb.TC_E_ARG  # k = 0
+    assert L.tc_sample_estimate(ctypes.byref(g), ctypes.byref(w), arr, 0, 10, 1, 0, 0,
+                                ctypes.byref(r), None) == tcb.TC_E_ARG  # no motifs
+    selfloop = [(0, 1), (1, 2), (2, 3), (3, 3)]
+    arr = (tcb.tc_motif * 1)(tcb.make_motif(selfloop))
+    assert L.tc_sample_estimate(ctypes.byref(g), ctypes.byref(w), arr, 1, 10, 1, 0, 0,
+                                ctypes.byref(r), None) == tcb.TC_E_UNSUPPORTED
+    r.e1 = fake  # only some per-sample outputs given
+    arr = (tcb.tc_motif * 1)(tcb.make_motif(ok))
+    assert L.tc_sample_estimate(ctypes.byref(g), ctypes.byref(w), arr, 1, 10, 1, 0, 0,
+                                ctypes.byref(r), None) == tcb.TC_E_ARG
+
+
+def test_binding_raises_without_library(tmp_path, monkeypatch):
+    import paper_2409_08975_amd as tcb
+    monkeypatch.setattr(tcb, "_lib", None)
+    monkeypatch.setattr(tcb, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        tcb.lib()
