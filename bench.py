@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="medium", choices=["medium", "tiny"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--motifs", default="six", choices=["six", "M4-0"],
+                    help="motif set of the step (the medium workload uses all six)")
     ap.add_argument("--cpu-sample", type=int, default=10**6,
                     help="samples the oracle draws for the CPU baseline")
     return ap.parse_args()
@@ -78,7 +80,7 @@ def main():
         g = sg.gen_tiny()
     log(f"[bench] generated {g.name}: n={g.n} m={g.m} in {time.time() - t0:.1f}s")
     delta, k, seed = P["delta"], P["k"], P["seed"]
-    names = sg.SIX_MOTIFS if args.workload == "medium" else ["M4-0"]
+    names = sg.SIX_MOTIFS if (args.workload == "medium" and args.motifs == "six") else ["M4-0"]
     motifs = [sg.MOTIFS[x] for x in names]
     src = torch.from_numpy(g.src).to(dev)
     dst = torch.from_numpy(g.dst).to(dev)

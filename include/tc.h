@@ -73,7 +73,8 @@ typedef struct {
  *             v's out-edges.  Position p in this order is the "scan order"
  *             used by the weights and the sampler.
  *   in-CSR  : edges sorted by (dst, t, eid); in_off as above.
- *   pair    : edges sorted by (src, dst, t, eid); shares out_off.
+ *   pair    : edges sorted by (src, dst, t, eid); shares out_off; each run
+ *             of equal (src, dst) is also reachable through pair_hash.
  * eid is the edge's index in the input arrays; it breaks timestamp ties. */
 typedef struct tc_graph {
   int32_t n;
@@ -88,6 +89,11 @@ typedef struct tc_graph {
   int32_t *pair_dst, *pair_eid;
   int64_t *pair_t;                    /* [m] each */
   uint32_t *status;                   /* device status word of the build       */
+  void *pair_hash;                    /* run table of the pair index: 2^pair_hash_log2
+                                         16-byte slots {u64 src<<32|dst, u32 start,
+                                         u32 end}, open addressing, linear probing,
+                                         empty key = all ones                     */
+  int32_t pair_hash_log2;
 } tc_graph;
 
 /* Per-edge window metadata and the exact integer CDF of the path weights,
@@ -103,9 +109,10 @@ typedef struct tc_weights {
   int64_t delta;
   int64_t m;
   uint32_t *lo_in, *a, *lo_out, *b;   /* [m] each (device) */
-  uint64_t *S;                        /* [m+1] (device) */
+  uint64_t *S;                        /* [m+1] (device; followed by all-ones padding
+                                         to a multiple of 16 words) */
   uint32_t *status;                   /* device word: TC_F_OVERFLOW if W >= 2^64 */
-  void *scratch;                      /* internal tile partials */
+  void *scratch;                      /* 16-ary search tree over S (internal) */
 } tc_weights;
 
 /* Outputs of tc_sample_estimate, all (device), caller-allocated.
@@ -157,6 +164,12 @@ tc_status tc_weights_workspace_bytes(int64_t m, size_t *bytes);
 tc_status tc_path_weights(const tc_graph *g, int64_t delta, void *ws, size_t ws_bytes,
                           void *stream, tc_weights *w);
 
+/* Workspace size in bytes for tc_sample_estimate with k samples and n_motifs
+ * motifs (per-sample pair windows and the closure work queue of one chunk of
+ * at most 2^22 samples).  Errors: TC_E_ARG (null, k < 1, n_motifs not in
+ * 1..16). */
+tc_status tc_sample_workspace_bytes(uint64_t k, int32_t n_motifs, size_t *bytes);
+
 /* Estimate(M, k) for n_motifs motifs (host array, 1..16) that share the
  * anchor: samples i0 .. i0+k-1 (k >= 1) of the counter-based stream
  * (seed, stream_id).  For each sample i (Algorithm Sample, then CheckMotif):
@@ -173,10 +186,14 @@ tc_status tc_path_weights(const tc_graph *g, int64_t delta, void *ws, size_t ws_
  *   chains l_3 < ... < l_{ne-1} with l_r a timestamp in (t3, t1 + delta] of
  *   the pair (phi(src_r), phi(dst_r)), phi = (x, u, v, y)  (ListCount).
  * W == 0 gives cnt = hits = 0, estimate 0, e* = -1, X = 0.
- * Errors: TC_E_ARG, TC_E_UNSUPPORTED (motif shape), TC_E_HIP. */
+ * ws (device) is scratch of at least tc_sample_workspace_bytes(k, n_motifs)
+ * bytes, reused across the call's chunks; calls that share it must be
+ * stream-ordered.  Errors: TC_E_ARG, TC_E_UNSUPPORTED (motif shape),
+ * TC_E_WORKSPACE, TC_E_HIP. */
 tc_status tc_sample_estimate(const tc_graph *g, const tc_weights *w, const tc_motif *motifs,
                              int32_t n_motifs, uint64_t k, uint64_t seed, uint32_t stream_id,
-                             uint64_t i0, tc_result *out, void *stream);
+                             uint64_t i0, void *ws, size_t ws_bytes, tc_result *out,
+                             void *stream);
 
 #ifdef __cplusplus
 }

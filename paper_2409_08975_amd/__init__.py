@@ -24,7 +24,8 @@ _STATUS_NAMES = {0: "TC_OK", -1: "TC_E_ARG", -2: "TC_E_RANGE", -3: "TC_E_OVERFLO
                  -4: "TC_E_UNSUPPORTED", -5: "TC_E_WORKSPACE", -6: "TC_E_HIP"}
 
 EXPORTED = ["tc_version", "tc_graph_workspace_bytes", "tc_build_graph",
-            "tc_weights_workspace_bytes", "tc_path_weights", "tc_sample_estimate"]
+            "tc_weights_workspace_bytes", "tc_path_weights", "tc_sample_workspace_bytes",
+            "tc_sample_estimate"]
 
 
 class TCError(RuntimeError):
@@ -54,7 +55,7 @@ class tc_graph(ctypes.Structure):
                 ("t_max", ctypes.c_int64), ("out_off", _P), ("out_src", _P), ("out_dst", _P),
                 ("out_eid", _P), ("out_t", _P), ("in_off", _P), ("in_src", _P), ("in_eid", _P),
                 ("in_t", _P), ("pair_dst", _P), ("pair_eid", _P), ("pair_t", _P),
-                ("status", _P)]
+                ("status", _P), ("pair_hash", _P), ("pair_hash_log2", ctypes.c_int32)]
 
 
 class tc_weights(ctypes.Structure):
@@ -85,9 +86,10 @@ def lib():
         L.tc_weights_workspace_bytes.argtypes = [I64, ctypes.POINTER(SZ)]
         L.tc_path_weights.argtypes = [ctypes.POINTER(tc_graph), I64, _P, SZ, _P,
                                       ctypes.POINTER(tc_weights)]
+        L.tc_sample_workspace_bytes.argtypes = [U64, I32, ctypes.POINTER(SZ)]
         L.tc_sample_estimate.argtypes = [ctypes.POINTER(tc_graph), ctypes.POINTER(tc_weights),
                                          ctypes.POINTER(tc_motif), I32, U64, U64, U32, U64,
-                                         ctypes.POINTER(tc_result), _P]
+                                         _P, SZ, ctypes.POINTER(tc_result), _P]
         for name in EXPORTED[1:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -214,6 +216,28 @@ def weights_workspace_bytes(m: int) -> int:
     return b.value
 
 
+def sample_workspace_bytes(k: int, n_motifs: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().tc_sample_workspace_bytes(int(k), int(n_motifs), ctypes.byref(b)),
+           "tc_sample_workspace_bytes")
+    return b.value
+
+
+_ws_cache: dict = {}
+
+
+def _sample_ws(k: int, nm: int, device) -> torch.Tensor:
+    """Scratch for tc_sample_estimate, kept per (device, stream) and grown on
+    demand (stream-ordered reuse)."""
+    need = sample_workspace_bytes(k, nm)
+    key = (str(device), torch.cuda.current_stream(device).cuda_stream)
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < need:
+        buf = torch.empty(need, dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
 def tc_build_graph(n: int, src: torch.Tensor, dst: torch.Tensor, t: torch.Tensor,
                    stream=None) -> Graph:
     """Build the temporal adjacency on the device (inputs: int32, int32, int64 CUDA tensors)."""
@@ -241,7 +265,8 @@ def tc_path_weights(graph: Graph, delta: int, stream=None) -> Weights:
 
 def tc_sample_estimate(graph: Graph, weights: Weights, motifs, k: int, seed: int,
                        stream_id: int = 0, i0: int = 0, per_sample: bool = False,
-                       stream=None, out: Result | None = None) -> Result:
+                       stream=None, out: Result | None = None,
+                       workspace: torch.Tensor | None = None) -> Result:
     """Estimate(M, k) for a list of motifs (each a list of (src, dst) edges in pi order)."""
     nm = len(motifs)
     arr = (tc_motif * nm)(*[make_motif(m) for m in motifs])
@@ -259,9 +284,11 @@ def tc_sample_estimate(graph: Graph, weights: Weights, motifs, k: int, seed: int
     r = tc_result(_ptr(out.cnt).value, _ptr(out.hits).value, _ptr(out.estimate).value,
                   _ptr(out.status).value, _ptr(out.e1).value, _ptr(out.e2).value,
                   _ptr(out.e3).value, _ptr(out.X).value)
+    ws = _sample_ws(k, nm, dev) if workspace is None else workspace
     _check(lib().tc_sample_estimate(ctypes.byref(graph.c), ctypes.byref(weights.c), arr, nm,
-                                    int(k), int(seed), int(stream_id), int(i0),
-                                    ctypes.byref(r), _stream(stream)), "tc_sample_estimate")
+                                    int(k), int(seed), int(stream_id), int(i0), _ptr(ws),
+                                    ws.numel(), ctypes.byref(r), _stream(stream)),
+           "tc_sample_estimate")
     return out
 
 

@@ -19,11 +19,21 @@ tc_status compile_motifs(const tc_motif* motifs, int32_t n_motifs, MotifPlan* pl
     if (!(M.src[0] == 0 && M.dst[0] == 1 && M.src[1] == 1 && M.dst[1] == 2 && M.src[2] == 2 &&
           M.dst[2] == 3))
       return TC_E_UNSUPPORTED;
-    // phi maps motif vertex 0..3 to (x, u, v, y), which are slots 0..3
+    // phi maps motif vertex 0..3 to (x, u, v, y), which are slots 0..3; each
+    // later edge is a list over the pair (phi(src), phi(dst))
     plan->n_lists[j] = M.ne - 3;
+    if (plan->n_lists[j] > plan->max_lists) plan->max_lists = plan->n_lists[j];
     for (int e = 3; e < M.ne; ++e) {
-      plan->a_slot[j][e - 3] = M.src[e];
-      plan->b_slot[j][e - 3] = M.dst[e];
+      int q = 0;
+      while (q < plan->n_pairs &&
+             !(plan->pair_a[q] == M.src[e] && plan->pair_b[q] == M.dst[e]))
+        ++q;
+      if (q == plan->n_pairs) {
+        plan->pair_a[q] = M.src[e];
+        plan->pair_b[q] = M.dst[e];
+        plan->n_pairs++;
+      }
+      plan->list_pair[j][e - 3] = (uint8_t)q;
     }
   }
   return TC_OK;
@@ -61,16 +71,25 @@ tc_status tc_path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_
   return tc::path_weights(g, delta, ws, ws_bytes, (hipStream_t)stream, w);
 }
 
+tc_status tc_sample_workspace_bytes(uint64_t k, int32_t n_motifs, size_t* bytes) {
+  if (!bytes || k < 1 || n_motifs < 1 || n_motifs > tc::kMaxMotifs) return TC_E_ARG;
+  *bytes = tc::sample_workspace_bytes(k, n_motifs);
+  return TC_OK;
+}
+
 tc_status tc_sample_estimate(const tc_graph* g, const tc_weights* w, const tc_motif* motifs,
                              int32_t n_motifs, uint64_t k, uint64_t seed, uint32_t stream_id,
-                             uint64_t i0, tc_result* out, void* stream) {
+                             uint64_t i0, void* ws, size_t ws_bytes, tc_result* out,
+                             void* stream) {
   if (!g || !w || !out || !out->cnt || !out->hits || !out->estimate || !out->status) return TC_E_ARG;
   if (k < 1 || w->m != g->m) return TC_E_ARG;
   if ((out->e1 || out->e2 || out->e3) && !(out->e1 && out->e2 && out->e3)) return TC_E_ARG;
   tc::MotifPlan plan;
   tc_status s = tc::compile_motifs(motifs, n_motifs, &plan);
   if (s != TC_OK) return s;
-  return tc::sample_estimate(g, w, plan, k, seed, stream_id, i0, out, (hipStream_t)stream);
+  if (!ws) return TC_E_ARG;
+  return tc::sample_estimate(g, w, plan, k, seed, stream_id, i0, out, ws, ws_bytes,
+                             (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -103,14 +103,17 @@ size_t scan_u32_scratch_elems(int64_t n) {
   return (size_t)((n + kScanTile - 1) / kScanTile) + 1;
 }
 
-// in-place exclusive scan of a[0..n)
-void scan_u32(uint32_t* a, int64_t n, uint32_t* part, hipStream_t st) {
-  if (n <= 0) return;
+// in-place exclusive scan of a[0..n); `part` must hold scan_u32_scratch_elems(n)
+// entries (checked: returns false and enqueues nothing otherwise)
+bool scan_u32(uint32_t* a, int64_t n, uint32_t* part, size_t part_elems, hipStream_t st) {
+  if (n <= 0) return true;
+  if (part_elems < scan_u32_scratch_elems(n)) return false;
   int64_t tiles = (n + kScanTile - 1) / kScanTile;
   hipLaunchKernelGGL(k_tile_sum_u32, dim3((unsigned)tiles), dim3(kScanBlock), 0, st, a, n, part);
   hipLaunchKernelGGL(k_scan_small_u32, dim3(1), dim3(1024), 0, st, part, tiles);
   hipLaunchKernelGGL(k_tile_scan_u32, dim3((unsigned)tiles), dim3(kScanBlock), 0, st, a, a, n,
                      (const uint32_t*)part);
+  return true;
 }
 
 // ------------------------------------------------------------ validation ---
@@ -180,11 +183,15 @@ __global__ __launch_bounds__(256) void k_vertex_keys(const int32_t* __restrict__
 }
 
 // ----------------------------------------------------------- radix pass ----
+// `dev_m` (optional) holds the element count on the device; m is then the
+// capacity the grid was sized for.
 template <typename K>
 __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__ keys, int64_t m,
                                                            int shift, uint32_t* __restrict__ hist,
-                                                           int64_t ntiles) {
+                                                           int64_t ntiles,
+                                                           const uint32_t* __restrict__ dev_m) {
   __shared__ uint32_t s_h[256];
+  if (dev_m) m = (int64_t)*dev_m < m ? (int64_t)*dev_m : m;
   s_h[threadIdx.x] = 0;
   __syncthreads();
   int64_t start = (int64_t)blockIdx.x * kSortTile;
@@ -204,7 +211,10 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
                                                               int32_t* __restrict__ vout, int64_t m,
                                                               int shift,
                                                               const uint32_t* __restrict__ hist,
-                                                              int64_t ntiles) {
+                                                              int64_t ntiles,
+                                                              const uint32_t* __restrict__ dev_m) {
+  if (dev_m) m = (int64_t)*dev_m < m ? (int64_t)*dev_m : m;
+  if ((int64_t)blockIdx.x * kSortTile >= m) return;
   __shared__ uint32_t s_base[256];
   __shared__ uint32_t s_run[256];
   __shared__ uint32_t s_excl[256];
@@ -293,11 +303,14 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
 // Sort (keys, vals) of length m by the low `bits` bits of the key, stably.
 // Ping-pongs between (k0, v0) and (k1, v1); returns 0 if the result is in
 // buffer 0, 1 if in buffer 1.
+// returns -1 if the scan scratch is too small (nothing enqueued then)
 template <typename K>
 int radix_sort(K* k0, int32_t* v0, K* k1, int32_t* v1, int64_t m, int bits, uint32_t* hist,
-               uint32_t* part, hipStream_t st) {
+               uint32_t* part, size_t part_elems, hipStream_t st,
+               const uint32_t* dev_m = nullptr) {
   if (m <= 0) return 0;
   const int64_t ntiles = (m + kSortTile - 1) / kSortTile;
+  if (part_elems < scan_u32_scratch_elems(256 * ntiles)) return -1;
   int cur = 0;
   for (int shift = 0; shift < bits; shift += 8) {
     K* ki = cur ? k1 : k0;
@@ -305,14 +318,32 @@ int radix_sort(K* k0, int32_t* v0, K* k1, int32_t* v1, int64_t m, int bits, uint
     K* ko = cur ? k0 : k1;
     int32_t* vo = cur ? v0 : v1;
     hipLaunchKernelGGL((k_radix_hist<K>), dim3((unsigned)ntiles), dim3(kSortBlock), 0, st,
-                       (const K*)ki, m, shift, hist, ntiles);
-    scan_u32(hist, 256 * ntiles, part, st);
+                       (const K*)ki, m, shift, hist, ntiles, dev_m);
+    scan_u32(hist, 256 * ntiles, part, part_elems, st);
     hipLaunchKernelGGL((k_radix_scatter<K>), dim3((unsigned)ntiles), dim3(kSortBlock), 0, st,
                        (const K*)ki, (const int32_t*)vi, ko, vo, m, shift, (const uint32_t*)hist,
-                       ntiles);
+                       ntiles, dev_m);
     cur ^= 1;
   }
   return cur;
+}
+
+size_t radix_hist_bytes(int64_t capacity) {
+  const int64_t ntiles = (capacity + kSortTile - 1) / kSortTile;
+  return (size_t)256 * (ntiles > 0 ? ntiles : 1) * 4;
+}
+size_t radix_part_bytes(int64_t capacity) {
+  const int64_t ntiles = (capacity + kSortTile - 1) / kSortTile;
+  return scan_u32_scratch_elems(256 * (ntiles > 0 ? ntiles : 1) + 1) * 4;
+}
+
+// One stable 8-bit pass over (key, val) pairs whose count lives on the
+// device (at most `capacity`); the result is left in (k1, v1).
+bool sort_u8_keys_dev(uint32_t* k0, int32_t* v0, uint32_t* k1, int32_t* v1, int64_t capacity,
+                      const uint32_t* dev_count, uint32_t* hist, uint32_t* part,
+                      size_t part_bytes, hipStream_t st) {
+  return radix_sort<uint32_t>(k0, v0, k1, v1, capacity, 8, hist, part, part_bytes / 4, st,
+                              dev_count) >= 0;
 }
 
 // -------------------------------------------------------- columns/offsets ---
@@ -349,12 +380,79 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ a, int6
   if (i < n) a[i] = v;
 }
 
+// ----------------------------------------------------- pair-run hash table ---
+// Every maximal run of equal (src, dst) in the pair index is one entry of an
+// open-addressing table (linear probing, Fibonacci hashing of the 64-bit key
+// src << 32 | dst).  A slot is 16 bytes {key, run start, run end}, so a hit
+// costs one 16-byte load.  The capacity is a power of two above 1.25 m, so
+// the load factor stays below 0.8 and a probe always reaches an empty slot.
+__global__ __launch_bounds__(256) void k_run_flags(const uint32_t* __restrict__ psrc,
+                                                   const int32_t* __restrict__ pdst, int64_t m,
+                                                   uint32_t* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m)
+    flag[i] = (i == 0 || psrc[i] != psrc[i - 1] || pdst[i] != pdst[i - 1]) ? 1u : 0u;
+  else if (i == m)
+    flag[i] = 0u;
+}
+
+// flag has been scanned in place: flag[i] = run index of a run starting at i
+__global__ __launch_bounds__(256) void k_run_starts(const uint32_t* __restrict__ psrc,
+                                                    const int32_t* __restrict__ pdst, int64_t m,
+                                                    const uint32_t* __restrict__ run_of,
+                                                    uint32_t* __restrict__ run_start) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m && (i == 0 || psrc[i] != psrc[i - 1] || pdst[i] != pdst[i - 1]))
+    run_start[run_of[i]] = (uint32_t)i;
+  if (i == m) run_start[run_of[m]] = (uint32_t)m;  // sentinel after the last run
+}
+
+__global__ __launch_bounds__(256) void k_hash_clear(PairSlot* __restrict__ tab, int64_t cap) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cap) {
+    tab[i].key = kPairEmpty;
+    tab[i].start = 0;
+    tab[i].end = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_hash_insert(const uint32_t* __restrict__ psrc,
+                                                     const int32_t* __restrict__ pdst,
+                                                     const uint32_t* __restrict__ run_start,
+                                                     const uint32_t* __restrict__ n_runs,
+                                                     PairSlot* __restrict__ tab, int log2cap) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= *n_runs) return;
+  const uint32_t s0 = run_start[r], s1 = run_start[r + 1];
+  const uint64_t key = pair_key(psrc[s0], pdst[s0]);
+  const uint64_t mask = (1ull << log2cap) - 1;
+  uint64_t h = pair_hash(key, log2cap);
+  for (uint64_t probe = 0; probe <= mask; ++probe) {
+    const unsigned long long prev =
+        atomicCAS((unsigned long long*)&tab[h].key, (unsigned long long)kPairEmpty,
+                  (unsigned long long)key);
+    if (prev == kPairEmpty) {
+      tab[h].start = s0;
+      tab[h].end = s1;
+      return;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+int pair_hash_log2(int64_t m) {
+  int lg = 4;
+  while (((int64_t)1 << lg) < m + m / 4 + 1) ++lg;
+  return lg;
+}
+
 // --------------------------------------------------------------- layout ----
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct GraphLayout {
   size_t out_off, in_off, out_src, out_dst, out_eid, out_t, in_src, in_eid, in_t, pair_dst,
-      pair_eid, pair_t, status, tminmax, keys0, keys1, vals0, vals1, hist, part, total;
+      pair_eid, pair_t, pair_hash, status, tminmax, keys0, keys1, vals0, vals1, hist, part,
+      part_elems, total;
 };
 
 static GraphLayout graph_layout(int32_t n, int64_t m) {
@@ -379,14 +477,18 @@ static GraphLayout graph_layout(int32_t n, int64_t m) {
   L.pair_dst = take(M * 4);
   L.pair_eid = take(M * 4);
   L.pair_t = take(M * 8);
+  L.pair_hash = take(sizeof(PairSlot) << pair_hash_log2(m));
   L.status = take(4);
   L.tminmax = take(16);
-  L.keys0 = take(M * 8);
-  L.keys1 = take(M * 8);
-  L.vals0 = take(M * 4);
-  L.vals1 = take(M * 4);
+  L.keys0 = take((M + 1) * 8);
+  L.keys1 = take((M + 1) * 8);
+  L.vals0 = take((M + 1) * 4);
+  L.vals1 = take((M + 1) * 4);
   L.hist = take((size_t)256 * ntiles * 4);
-  L.part = take(scan_u32_scratch_elems(256 * ntiles + 1) * 4 + 1024);
+  // scan scratch: the larger of the histogram scan and the (m + 1)-entry run scan
+  L.part_elems = scan_u32_scratch_elems(256 * ntiles + 1);
+  if (scan_u32_scratch_elems(m + 1) > L.part_elems) L.part_elems = scan_u32_scratch_elems(m + 1);
+  L.part = take(L.part_elems * 4);
   L.total = o;
   return L;
 }
@@ -417,6 +519,8 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   g->pair_eid = (int32_t*)(base + L.pair_eid);
   g->pair_t = (int64_t*)(base + L.pair_t);
   g->status = (uint32_t*)(base + L.status);
+  g->pair_hash = (void*)(base + L.pair_hash);
+  g->pair_hash_log2 = pair_hash_log2(m);
   uint64_t* tminmax = (uint64_t*)(base + L.tminmax);
   void* keys0 = base + L.keys0;
   void* keys1 = base + L.keys1;
@@ -424,6 +528,7 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   int32_t* vals1 = (int32_t*)(base + L.vals1);
   uint32_t* hist = (uint32_t*)(base + L.hist);
   uint32_t* part = (uint32_t*)(base + L.part);
+  const size_t pe = L.part_elems;
 
   hipLaunchKernelGGL(k_init_build, dim3(1), dim3(64), 0, st, g->status, tminmax);
   if (m > 0) {
@@ -454,13 +559,14 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
       hipLaunchKernelGGL((k_time_keys<uint32_t>), dim3(eb), dim3(256), 0, st, t, m, tmin,
                          (uint32_t*)keys0, vals0);
       where = radix_sort<uint32_t>((uint32_t*)keys0, vals0, (uint32_t*)keys1, vals1, m, tbits,
-                                   hist, part, st);
+                                   hist, part, pe, st);
     } else {
       hipLaunchKernelGGL((k_time_keys<uint64_t>), dim3(eb), dim3(256), 0, st, t, m, tmin,
                          (uint64_t*)keys0, vals0);
       where = radix_sort<uint64_t>((uint64_t*)keys0, vals0, (uint64_t*)keys1, vals1, m, tbits,
-                                   hist, part, st);
+                                   hist, part, pe, st);
     }
+    if (where < 0) return TC_E_WORKSPACE;
     torder = where ? vals1 : vals0;
   } else {
     torder = vals0;
@@ -477,7 +583,8 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   // 2. out-CSR: stable by src
   if (m > 0) {
     hipLaunchKernelGGL(k_vertex_keys, dim3(eb), dim3(256), 0, st, src, torder_keep, m, k0, vals0);
-    int w = radix_sort<uint32_t>(k0, vals0, k1, vals1, m, vbits, hist, part, st);
+    int w = radix_sort<uint32_t>(k0, vals0, k1, vals1, m, vbits, hist, part, pe, st);
+    if (w < 0) return TC_E_WORKSPACE;
     uint32_t* sk = w ? k1 : k0;
     int32_t* sv = w ? vals1 : vals0;
     hipLaunchKernelGGL(k_gather_order, dim3(eb), dim3(256), 0, st, (const uint32_t*)sk,
@@ -492,7 +599,8 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   // 3. in-CSR: stable by dst
   if (m > 0) {
     hipLaunchKernelGGL(k_vertex_keys, dim3(eb), dim3(256), 0, st, dst, torder_keep, m, k0, vals0);
-    int w = radix_sort<uint32_t>(k0, vals0, k1, vals1, m, vbits, hist, part, st);
+    int w = radix_sort<uint32_t>(k0, vals0, k1, vals1, m, vbits, hist, part, pe, st);
+    if (w < 0) return TC_E_WORKSPACE;
     uint32_t* sk = w ? k1 : k0;
     int32_t* sv = w ? vals1 : vals0;
     hipLaunchKernelGGL(k_gather_order, dim3(eb), dim3(256), 0, st, (const uint32_t*)sk,
@@ -505,14 +613,30 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
                        g->in_off, (int64_t)n + 1, 0u);
   }
   // 4. pair index: the in-order (dst, t, eid) stably sorted by src
+  const int64_t cap = (int64_t)1 << g->pair_hash_log2;
+  PairSlot* tab = (PairSlot*)g->pair_hash;
+  hipLaunchKernelGGL(k_hash_clear, dim3(blocks_for(cap, 256)), dim3(256), 0, st, tab, cap);
   if (m > 0) {
     hipLaunchKernelGGL(k_vertex_keys, dim3(eb), dim3(256), 0, st, src, g->in_eid, m, k0, vals0);
-    int w = radix_sort<uint32_t>(k0, vals0, k1, vals1, m, vbits, hist, part, st);
+    int w = radix_sort<uint32_t>(k0, vals0, k1, vals1, m, vbits, hist, part, pe, st);
+    if (w < 0) return TC_E_WORKSPACE;
     uint32_t* sk = w ? k1 : k0;
     int32_t* sv = w ? vals1 : vals0;
     hipLaunchKernelGGL(k_gather_order, dim3(eb), dim3(256), 0, st, (const uint32_t*)sk,
                        (const int32_t*)sv, m, dst, t, (int32_t*)nullptr, g->pair_dst, g->pair_t,
                        g->pair_eid);
+    // 5. pair-run hash table (the sorted src keys are still in sk)
+    uint32_t* run_of = w ? k0 : k1;            // the free key buffer, m + 1 entries
+    uint32_t* run_start = (uint32_t*)(w ? vals0 : vals1);  // the free value buffer (m + 1)
+    hipLaunchKernelGGL(k_run_flags, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
+                       (const uint32_t*)sk, (const int32_t*)g->pair_dst, m, run_of);
+    if (!scan_u32(run_of, m + 1, part, pe, st)) return TC_E_WORKSPACE;
+    hipLaunchKernelGGL(k_run_starts, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
+                       (const uint32_t*)sk, (const int32_t*)g->pair_dst, m,
+                       (const uint32_t*)run_of, run_start);
+    hipLaunchKernelGGL(k_hash_insert, dim3(eb), dim3(256), 0, st, (const uint32_t*)sk,
+                       (const int32_t*)g->pair_dst, (const uint32_t*)run_start,
+                       (const uint32_t*)(run_of + m), tab, g->pair_hash_log2);
   }
   if (hipGetLastError() != hipSuccess) return TC_E_HIP;
   return TC_OK;

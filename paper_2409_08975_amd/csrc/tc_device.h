@@ -161,6 +161,42 @@ __device__ __forceinline__ double u128_to_double(uint64_t lo, uint64_t hi) {
   return ldexp((double)top, shift);
 }
 
+// ---- pair-run hash table ----------------------------------------------------
+struct __align__(16) PairSlot {
+  uint64_t key;    // src << 32 | dst, or kPairEmpty
+  uint32_t start;  // first position of the run in the pair index
+  uint32_t end;    // one past the last
+};
+constexpr uint64_t kPairEmpty = ~0ull;
+
+__host__ __device__ __forceinline__ uint64_t pair_key(uint32_t a, uint32_t b) {
+  return ((uint64_t)a << 32) | (uint64_t)b;
+}
+
+__host__ __device__ __forceinline__ uint64_t pair_hash(uint64_t key, int log2cap) {
+  return (key * 0x9E3779B97F4A7C15ull) >> (64 - log2cap);
+}
+
+// [start, end) of the run of edges a -> b in the pair index (empty if none)
+__device__ __forceinline__ void pair_run(const PairSlot* __restrict__ tab, int log2cap, int32_t a,
+                                         int32_t b, uint32_t* start, uint32_t* end) {
+  const uint64_t key = pair_key((uint32_t)a, (uint32_t)b);
+  const uint64_t mask = (1ull << log2cap) - 1;
+  uint64_t h = pair_hash(key, log2cap);
+  *start = 0;
+  *end = 0;
+  for (uint64_t probe = 0; probe <= mask; ++probe) {
+    const PairSlot sl = tab[h];
+    if (sl.key == key) {
+      *start = sl.start;
+      *end = sl.end;
+      return;
+    }
+    if (sl.key == kPairEmpty) return;
+    h = (h + 1) & mask;
+  }
+}
+
 __device__ __forceinline__ void set_status(uint32_t* status, uint32_t bits) {
   atomicOr(status, bits);
 }

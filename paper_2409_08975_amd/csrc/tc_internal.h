@@ -13,6 +13,23 @@ size_t graph_workspace_bytes(int32_t n, int64_t m);
 tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
                       const int64_t* t, void* ws, size_t ws_bytes, hipStream_t st, tc_graph* g);
 
+size_t radix_hist_bytes(int64_t capacity);
+size_t radix_part_bytes(int64_t capacity);
+bool sort_u8_keys_dev(uint32_t* k0, int32_t* v0, uint32_t* k1, int32_t* v1, int64_t capacity,
+                      const uint32_t* dev_count, uint32_t* hist, uint32_t* part,
+                      size_t part_bytes, hipStream_t st);
+
+// Shape of the 16-ary search tree over S (level 0 = S padded to 16n words;
+// levels 1..levels live in tc_weights.scratch at offset[L] words).
+constexpr int kMaxTreeLevels = 16;
+struct STree {
+  int levels;
+  int64_t count[kMaxTreeLevels];
+  size_t offset[kMaxTreeLevels];
+  size_t total_words;
+};
+STree stree_layout(int64_t m);
+
 size_t weights_workspace_bytes(int64_t m);
 tc_status path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_bytes,
                        hipStream_t st, tc_weights* w);
@@ -20,19 +37,28 @@ tc_status path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_byt
 // Compiled form of a batch of motifs that share the anchor 0->1->2->3:
 // for motif j, ranks 3..ne-1 become lists over vertex slots of
 // phi = (x, u, v, y).
+// The distinct pairs used by any list of the batch are looked up once per
+// sample (at most 12 ordered pairs of 4 vertices).
 constexpr int kMaxMotifs = 16;
 constexpr int kMaxLists = 13;
+constexpr int kMaxPairs = 12;
 struct MotifPlan {
   int32_t n_motifs;
+  int32_t n_pairs;
+  int32_t max_lists;
+  uint8_t pair_a[kMaxPairs], pair_b[kMaxPairs];  // vertex slots of each pair
   int32_t n_lists[kMaxMotifs];
-  uint8_t a_slot[kMaxMotifs][kMaxLists];
-  uint8_t b_slot[kMaxMotifs][kMaxLists];
+  uint8_t list_pair[kMaxMotifs][kMaxLists];     // pair index of each list
 };
 
 tc_status compile_motifs(const tc_motif* motifs, int32_t n_motifs, MotifPlan* plan);
 
+// samples per chunk of the two-kernel sampler, for a call with k samples
+uint64_t sample_chunk(uint64_t k);
+size_t sample_workspace_bytes(uint64_t k, int32_t n_motifs);
+
 tc_status sample_estimate(const tc_graph* g, const tc_weights* w, const MotifPlan& plan,
                           uint64_t k, uint64_t seed, uint32_t stream_id, uint64_t i0,
-                          tc_result* out, hipStream_t st);
+                          tc_result* out, void* ws, size_t ws_bytes, hipStream_t st);
 
 }  // namespace tc

@@ -159,10 +159,49 @@ __global__ __launch_bounds__(kWBlock) void k_scan_apply(const uint32_t* __restri
   }
 }
 
+// ---- 16-ary search tree over S ----------------------------------------------
+// Level 0 is S itself, padded with all-ones words to a multiple of 16
+// entries; level L holds S[16^L * i] (padded likewise) and the last level has
+// at most 16 entries.  upper_bound(S, r) - 1 is then found by reading one
+// 128-byte node per level: at each level the node is the last entry <= r of
+// the level above, and counting its entries <= r gives the next index.
+__global__ __launch_bounds__(256) void k_tree_level(const uint64_t* __restrict__ S, int64_t m,
+                                                    uint64_t stride, uint64_t* __restrict__ lvl,
+                                                    int64_t n_padded) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_padded) return;
+  const uint64_t at = (uint64_t)i * stride;
+  lvl[i] = (at <= (uint64_t)m) ? S[at] : ~0ull;
+}
+
+__global__ __launch_bounds__(256) void k_pad_s(uint64_t* __restrict__ S, int64_t m,
+                                               int64_t n_padded) {
+  const int64_t i = m + 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_padded) S[i] = ~0ull;
+}
+
+STree stree_layout(int64_t m) {
+  STree T;
+  T.levels = 0;
+  int64_t n = m + 1;
+  T.count[0] = ((n + 15) / 16) * 16;
+  T.offset[0] = 0;  // level 0 lives in S
+  size_t off = 0;
+  while (n > 16) {
+    n = (n + 15) / 16;
+    ++T.levels;
+    T.count[T.levels] = ((n + 15) / 16) * 16;
+    T.offset[T.levels] = off;
+    off += (size_t)T.count[T.levels];
+  }
+  T.total_words = off;
+  return T;
+}
+
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WeightsLayout {
-  size_t lo_in, a, lo_out, b, S, status, tile_sums, tile_off, total;
+  size_t lo_in, a, lo_out, b, S, status, tile_sums, tile_off, tree, total;
 };
 
 static WeightsLayout weights_layout(int64_t m) {
@@ -179,7 +218,9 @@ static WeightsLayout weights_layout(int64_t m) {
   L.a = take(M * 4);
   L.lo_out = take(M * 4);
   L.b = take(M * 4);
-  L.S = take((M + 1) * 8);
+  const STree T = stree_layout(m);
+  L.S = take((size_t)T.count[0] * 8);
+  L.tree = take(T.total_words * 8);
   L.status = take(4);
   L.tile_sums = take(ntiles * 16);
   L.tile_off = take(ntiles * 8);
@@ -203,7 +244,7 @@ tc_status path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_byt
   w->b = (uint32_t*)(base + L.b);
   w->S = (uint64_t*)(base + L.S);
   w->status = (uint32_t*)(base + L.status);
-  w->scratch = base + L.tile_sums;
+  w->scratch = base + L.tree;  // search tree over S
   uint64_t* tile_sums = (uint64_t*)(base + L.tile_sums);
   uint64_t* tile_off = (uint64_t*)(base + L.tile_off);
   const int64_t ntiles = (m + kWTile - 1) / kWTile;
@@ -217,6 +258,19 @@ tc_status path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_byt
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
                        (const uint32_t*)w->a, (const uint32_t*)w->b, m,
                        (const uint64_t*)tile_off, w->S);
+  // search tree over S (padding first, then each level)
+  const STree T = stree_layout(m);
+  const int64_t pad = T.count[0] - (m + 1);
+  if (pad > 0)
+    hipLaunchKernelGGL(k_pad_s, dim3((unsigned)((pad + 255) / 256)), dim3(256), 0, st, w->S, m,
+                       T.count[0]);
+  uint64_t stride = 1;
+  for (int L = 1; L <= T.levels; ++L) {
+    stride *= 16;
+    hipLaunchKernelGGL(k_tree_level, dim3((unsigned)((T.count[L] + 255) / 256)), dim3(256), 0, st,
+                       (const uint64_t*)w->S, m, stride,
+                       (uint64_t*)w->scratch + T.offset[L], T.count[L]);
+  }
   if (hipGetLastError() != hipSuccess) return TC_E_HIP;
   return TC_OK;
 }

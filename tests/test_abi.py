@@ -60,6 +60,18 @@ def test_workspace_queries(tcb):
         tcb.graph_workspace_bytes(10, 2**31)
 
 
+def test_sample_workspace_query(tcb):
+    b1 = tcb.sample_workspace_bytes(1000, 1)
+    b6 = tcb.sample_workspace_bytes(1000, 6)
+    big = tcb.sample_workspace_bytes(10**9, 6)
+    assert b6 > b1 > 0
+    assert big == tcb.sample_workspace_bytes(2**22, 6)  # chunked: bounded in k
+    with pytest.raises(tcb.TCError):
+        tcb.sample_workspace_bytes(0, 1)
+    with pytest.raises(tcb.TCError):
+        tcb.sample_workspace_bytes(10, 17)
+
+
 def test_host_argument_errors_return_before_any_launch(tcb):
     L = tcb.lib()
     g = tcb.tc_graph()
@@ -79,21 +91,21 @@ def test_host_argument_errors_return_before_any_launch(tcb):
     bad = [(0, 1), (2, 1), (1, 2)]  # not anchored on 0->1->2->3
     arr = (tcb.tc_motif * 1)(tcb.make_motif(bad))
     assert L.tc_sample_estimate(ctypes.byref(g), ctypes.byref(w), arr, 1, 10, 1, 0, 0,
-                                ctypes.byref(r), None) == tcb.TC_E_UNSUPPORTED
+                                ctypes.c_void_p(fake), 1 << 40, ctypes.byref(r), None) == tcb.TC_E_UNSUPPORTED
     ok = [(0, 1), (1, 2), (2, 3), (3, 0)]
     arr = (tcb.tc_motif * 1)(tcb.make_motif(ok))
     assert L.tc_sample_estimate(ctypes.byref(g), ctypes.byref(w), arr, 1, 0, 1, 0, 0,
-                                ctypes.byref(r), None) == tcb.TC_E_ARG  # k = 0
+                                ctypes.c_void_p(fake), 1 << 40, ctypes.byref(r), None) == tcb.TC_E_ARG  # k = 0
     assert L.tc_sample_estimate(ctypes.byref(g), ctypes.byref(w), arr, 0, 10, 1, 0, 0,
-                                ctypes.byref(r), None) == tcb.TC_E_ARG  # no motifs
+                                ctypes.c_void_p(fake), 1 << 40, ctypes.byref(r), None) == tcb.TC_E_ARG  # no motifs
     selfloop = [(0, 1), (1, 2), (2, 3), (3, 3)]
     arr = (tcb.tc_motif * 1)(tcb.make_motif(selfloop))
     assert L.tc_sample_estimate(ctypes.byref(g), ctypes.byref(w), arr, 1, 10, 1, 0, 0,
-                                ctypes.byref(r), None) == tcb.TC_E_UNSUPPORTED
+                                ctypes.c_void_p(fake), 1 << 40, ctypes.byref(r), None) == tcb.TC_E_UNSUPPORTED
     r.e1 = fake  # only some per-sample outputs given
     arr = (tcb.tc_motif * 1)(tcb.make_motif(ok))
     assert L.tc_sample_estimate(ctypes.byref(g), ctypes.byref(w), arr, 1, 10, 1, 0, 0,
-                                ctypes.byref(r), None) == tcb.TC_E_ARG
+                                ctypes.c_void_p(fake), 1 << 40, ctypes.byref(r), None) == tcb.TC_E_ARG
 
 
 def test_binding_raises_without_library(tmp_path, monkeypatch):
