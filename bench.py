@@ -24,6 +24,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNELS = ["k_paths", "k_listcount_reg", "k_windows", "k_scan_apply", "k_radix_scatter"]
+# Kernel -> source file whose hash must match the stored counter readings.
+KERNEL_SRC = {"k_paths": "tc_sample.hip", "k_listcount_reg": "tc_sample.hip",
+              "k_windows": "tc_weights.hip", "k_scan_apply": "tc_weights.hip",
+              "k_radix_scatter": "tc_build.hip"}
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_medium.txt")
 
 
 def parse():
@@ -37,6 +43,8 @@ def parse():
                     help="motif set of the step (the medium workload uses all six)")
     ap.add_argument("--cpu-sample", type=int, default=10**6,
                     help="samples the oracle draws for the CPU baseline")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="copy 1 GiB device-to-device first (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -44,16 +52,48 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def sample_bytes_model(m, k, n_motifs):
-    """Algorithmic bytes of the sampling kernel per launch: per sample, the
-    ceil(log2(m+1)) probes of S (8 B each), the chosen edge's record (window
-    metadata 16 B + src, dst, eid 12 B + t 8 B), the two end edges (vertex 4 B
-    + time 8 B each) and the per-sample outputs it does not write in the
-    benchmark (none).  Closure lookups are data dependent and not counted,
-    so this is a lower bound on the useful bytes."""
-    probes = math.ceil(math.log2(m + 1))
-    per = 8 * probes + 16 + 12 + 8 + 2 * 12
-    return per * k, per
+def algorithmic_bytes(kernel, m, units):
+    """Algorithmic bytes of one launch: a per-unit figure times the units the
+    launch processes.  Data-dependent searches inside adjacency lists and
+    pair runs are not counted, so these are lower bounds.
+      k_paths          per sample: ceil(log2(m+1)) probes of S (8 B each), the
+                       chosen edge with its window metadata (32 B), the two end
+                       edges (16 B each)
+      k_windows        per edge: read src, dst, t (16 B), write lo_in, a,
+                       lo_out, b (16 B)
+      k_scan_apply     per edge: read a, b (8 B), write S (8 B)
+      k_radix_scatter  per element and pass: read and write a 4-byte key and a
+                       4-byte value (16 B)"""
+    if kernel == "k_paths":
+        per = 8 * math.ceil(math.log2(m + 1)) + 32 + 2 * 16
+    elif kernel == "k_windows":
+        per = 32
+    elif kernel == "k_scan_apply":
+        per = 16
+    elif kernel == "k_radix_scatter":
+        per = 16
+    else:
+        return None, None
+    return per * units, per
+
+
+def source_hash(name):
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2409_08975_amd", "csrc", name), "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()[:12]
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current source of the kernel (else None)."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    want = source_hash(KERNEL_SRC[kernel])
+    for line in open(PMC_FILE):
+        f = dict(kv.split("=", 1) for kv in line.split() if "=" in kv)
+        if f.get("kernel") == kernel and f.get("src_sha") == want and "hbm_bytes_per_launch" in f:
+            return float(f["hbm_bytes_per_launch"])
+    return None
 
 
 def main():
@@ -88,6 +128,12 @@ def main():
     torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream()
+    if args.calib_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     def step():
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
@@ -106,6 +152,8 @@ def main():
         R.check()
         log(f"[bench] warmup {i} done")
     torch.cuda.synchronize()
+    tcb.timing_reset()
+    tcb.timing_enable(True)
     stage = np.zeros(3)
     t_start = time.perf_counter()
     evs = []
@@ -114,6 +162,13 @@ def main():
         evs.append(ev)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
+    tcb.timing_enable(False)
+    ktime = {}
+    for kname in KERNELS:
+        ms, n = tcb.timing_read(kname)
+        if n:
+            ktime[kname] = (ms, n)
+    tcb.timing_reset()
     for ev in evs:
         for s in range(3):
             stage[s] += ev[s].elapsed_time(ev[s + 1])
@@ -126,12 +181,33 @@ def main():
     log(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step; stages ms "
         f"build={stage[0]:.3f} weights={stage[1]:.3f} sample={stage[2]:.3f}")
 
-    # roofline of the dominant stage kernel (sampling: one main kernel)
-    alg_bytes, per_sample = sample_bytes_model(g.m, k, len(motifs))
-    achieved = alg_bytes / (stage[2] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_sample", "alg_bytes_per_sample": per_sample}
+    # per-kernel rooflines; the dominant kernel is the one with the most time per step
+    units = {"k_paths": None, "k_windows": g.m, "k_scan_apply": g.m, "k_radix_scatter": g.m}
+    kernels = {}
+    for kname, (ms, n) in ktime.items():
+        per_launch_ms = ms / n
+        u = units.get(kname)
+        if kname == "k_paths":
+            u = k / (n / args.steps)  # samples per launch (chunks of the k samples)
+        alg, per = algorithmic_bytes(kname, g.m, u) if u is not None else (None, None)
+        entry = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps,
+                 "ms_per_launch": per_launch_ms}
+        if alg is not None:
+            gbs = alg / (per_launch_ms * 1e-3) / 1e9
+            entry.update({"alg_bytes_per_unit": per, "alg_bytes_per_launch": alg,
+                          "achieved_GBs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS})
+            tr = stored_traffic(kname)
+            entry["hbm_bytes_per_launch"] = tr
+        kernels[kname] = entry
+    dom = max(kernels, key=lambda x: kernels[x]["ms_per_step"])
+    d = kernels[dom]
+    roofline = {"bound": "hbm", "achieved": round(d.get("achieved_GBs", 0.0), 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(d.get("frac_of_hbm_peak", 0.0), 4),
+                "traffic": d.get("hbm_bytes_per_launch"), "kernel": dom,
+                "ms_per_launch": round(d["ms_per_launch"], 4),
+                "alg_bytes_per_unit": d.get("alg_bytes_per_unit")}
+    log(f"[bench] kernels: " + ", ".join(f"{k_}={v['ms_per_step']:.3f}ms" for k_, v in kernels.items()))
 
     out = {
         "metric": "sampled temporal 3-paths/sec and rel. error vs exact at fixed k; learned vs plain",
@@ -156,6 +232,7 @@ def main():
         "cnt": [str(c) for c in counts],
         "estimate": est,
         "roofline": roofline,
+        "kernels": kernels,
     }
 
     if not args.no_cpu_baseline:

@@ -84,8 +84,10 @@ typedef struct tc_graph {
   int32_t *out_src, *out_dst, *out_eid;
   int64_t *out_t;                     /* [m] each */
   uint32_t *in_off;                   /* [n+1] */
-  int32_t *in_src, *in_eid;
+  int32_t *in_src, *in_eid, *in_dst;
   int64_t *in_t;                      /* [m] each */
+  uint32_t *out_to_in;                /* [m]: in-CSR position of the edge at
+                                         out-CSR position p */
   int32_t *pair_dst, *pair_eid;
   int64_t *pair_t;                    /* [m] each */
   uint32_t *status;                   /* device status word of the build       */
@@ -194,6 +196,17 @@ tc_status tc_sample_estimate(const tc_graph *g, const tc_weights *w, const tc_mo
                              int32_t n_motifs, uint64_t k, uint64_t seed, uint32_t stream_id,
                              uint64_t i0, void *ws, size_t ws_bytes, tc_result *out,
                              void *stream);
+
+/* Profiling aid (not part of the method).  After tc_timing_enable(1) the
+ * library records a pair of HIP events on the launch stream around each
+ * launch of its main kernels ("k_windows", "k_scan_apply", "k_paths",
+ * "k_listcount_reg", "k_radix_scatter").  tc_timing_read waits for the
+ * recorded events of one kernel and returns the summed elapsed milliseconds
+ * and the number of launches; tc_timing_reset drops all records.  Events are
+ * created only while timing is enabled.  Errors: TC_E_ARG, TC_E_HIP. */
+tc_status tc_timing_enable(int32_t on);
+tc_status tc_timing_reset(void);
+tc_status tc_timing_read(const char *kernel, double *total_ms, int64_t *launches);
 
 #ifdef __cplusplus
 }

@@ -25,7 +25,7 @@ _STATUS_NAMES = {0: "TC_OK", -1: "TC_E_ARG", -2: "TC_E_RANGE", -3: "TC_E_OVERFLO
 
 EXPORTED = ["tc_version", "tc_graph_workspace_bytes", "tc_build_graph",
             "tc_weights_workspace_bytes", "tc_path_weights", "tc_sample_workspace_bytes",
-            "tc_sample_estimate"]
+            "tc_sample_estimate", "tc_timing_enable", "tc_timing_reset", "tc_timing_read"]
 
 
 class TCError(RuntimeError):
@@ -54,7 +54,8 @@ class tc_graph(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("t_min", ctypes.c_int64),
                 ("t_max", ctypes.c_int64), ("out_off", _P), ("out_src", _P), ("out_dst", _P),
                 ("out_eid", _P), ("out_t", _P), ("in_off", _P), ("in_src", _P), ("in_eid", _P),
-                ("in_t", _P), ("pair_dst", _P), ("pair_eid", _P), ("pair_t", _P),
+                ("in_dst", _P), ("in_t", _P), ("out_to_in", _P), ("pair_dst", _P),
+                ("pair_eid", _P), ("pair_t", _P),
                 ("status", _P), ("pair_hash", _P), ("pair_hash_log2", ctypes.c_int32)]
 
 
@@ -90,6 +91,10 @@ def lib():
         L.tc_sample_estimate.argtypes = [ctypes.POINTER(tc_graph), ctypes.POINTER(tc_weights),
                                          ctypes.POINTER(tc_motif), I32, U64, U64, U32, U64,
                                          _P, SZ, ctypes.POINTER(tc_result), _P]
+        L.tc_timing_enable.argtypes = [I32]
+        L.tc_timing_reset.argtypes = []
+        L.tc_timing_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(I64)]
         for name in EXPORTED[1:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -149,7 +154,8 @@ class Graph:
                              ("out_src", torch.int32, m), ("out_dst", torch.int32, m),
                              ("out_eid", torch.int32, m), ("out_t", torch.int64, m),
                              ("in_src", torch.int32, m), ("in_eid", torch.int32, m),
-                             ("in_t", torch.int64, m), ("pair_dst", torch.int32, m),
+                             ("in_dst", torch.int32, m), ("in_t", torch.int64, m),
+                             ("out_to_in", torch.int32, m), ("pair_dst", torch.int32, m),
                              ("pair_eid", torch.int32, m), ("pair_t", torch.int64, m)]:
             d[name] = self.view(name, dt, ln)
         return d
@@ -290,6 +296,23 @@ def tc_sample_estimate(graph: Graph, weights: Weights, motifs, k: int, seed: int
                                     ws.numel(), ctypes.byref(r), _stream(stream)),
            "tc_sample_estimate")
     return out
+
+
+def timing_enable(on: bool = True) -> None:
+    _check(lib().tc_timing_enable(1 if on else 0), "tc_timing_enable")
+
+
+def timing_reset() -> None:
+    _check(lib().tc_timing_reset(), "tc_timing_reset")
+
+
+def timing_read(kernel: str):
+    """(total milliseconds, launches) recorded for one kernel."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(lib().tc_timing_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)),
+           "tc_timing_read")
+    return ms.value, n.value
 
 
 def version() -> str:

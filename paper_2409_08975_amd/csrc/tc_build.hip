@@ -21,7 +21,8 @@ namespace tc {
 
 constexpr int kSortBlock = 256;
 constexpr int kSortItems = 16;
-constexpr int kSortTile = kSortBlock * kSortItems;  // 4096
+constexpr int kRecItems = 8;  // record-carrying sorts: 2048-entry tiles (LDS holds 16 B/entry)
+constexpr int kRecTile = kSortBlock * kRecItems;
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanBlock * kScanItems;
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(256) void k_vertex_keys(const int32_t* __restrict__
 // ----------------------------------------------------------- radix pass ----
 // `dev_m` (optional) holds the element count on the device; m is then the
 // capacity the grid was sized for.
-template <typename K>
+template <typename K, int ITEMS>
 __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__ keys, int64_t m,
                                                            int shift, uint32_t* __restrict__ hist,
                                                            int64_t ntiles,
@@ -194,9 +195,9 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__
   if (dev_m) m = (int64_t)*dev_m < m ? (int64_t)*dev_m : m;
   s_h[threadIdx.x] = 0;
   __syncthreads();
-  int64_t start = (int64_t)blockIdx.x * kSortTile;
+  int64_t start = (int64_t)blockIdx.x * (kSortBlock * ITEMS);
 #pragma unroll
-  for (int r = 0; r < kSortItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     int64_t i = start + (int64_t)r * kSortBlock + threadIdx.x;
     if (i < m) atomicAdd(&s_h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
   }
@@ -204,47 +205,51 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__
   hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = s_h[threadIdx.x];
 }
 
-template <typename K>
+template <typename K, typename V, int ITEMS>
 __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restrict__ kin,
-                                                              const int32_t* __restrict__ vin,
+                                                              const V* __restrict__ vin,
                                                               K* __restrict__ kout,
-                                                              int32_t* __restrict__ vout, int64_t m,
+                                                              V* __restrict__ vout, int64_t m,
                                                               int shift,
                                                               const uint32_t* __restrict__ hist,
                                                               int64_t ntiles,
                                                               const uint32_t* __restrict__ dev_m) {
+  // Each wavefront owns a contiguous quarter of the tile and ranks its keys
+  // in order with ballots (no block barrier inside); one block-wide pass then
+  // offsets every wavefront's digit counts by those of the wavefronts before
+  // it, which keeps the pass stable.
+  constexpr int kTile = kSortBlock * ITEMS;
+  constexpr int kWaves = kSortBlock / kWave;
+  constexpr int kSub = kWave * ITEMS;  // entries per wavefront
   if (dev_m) m = (int64_t)*dev_m < m ? (int64_t)*dev_m : m;
-  if ((int64_t)blockIdx.x * kSortTile >= m) return;
+  if ((int64_t)blockIdx.x * kTile >= m) return;
   __shared__ uint32_t s_base[256];
-  __shared__ uint32_t s_run[256];
   __shared__ uint32_t s_excl[256];
-  __shared__ uint32_t s_wcnt[kSortBlock / kWave][256];
-  __shared__ uint32_t s_wsum[kSortBlock / kWave];
-  __shared__ K s_key[kSortTile];
-  __shared__ int32_t s_val[kSortTile];
+  __shared__ uint32_t s_wcnt[kWaves][256];  // per-wavefront running digit counts
+  __shared__ uint32_t s_wsum[kWaves];
+  __shared__ K s_key[kTile];
+  __shared__ V s_val[kTile];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t start = (int64_t)blockIdx.x * kSortTile;
-  const int len = (int)((m - start) < kSortTile ? (m - start) : kSortTile);
+  const int64_t start = (int64_t)blockIdx.x * kTile;
+  const int len = (int)((m - start) < kTile ? (m - start) : kTile);
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
   s_base[tid] = hist[(int64_t)tid * ntiles + blockIdx.x];
-  s_run[tid] = 0;
 #pragma unroll
-  for (int w = 0; w < kSortBlock / kWave; ++w) s_wcnt[w][tid] = 0;
+  for (int w = 0; w < kWaves; ++w) s_wcnt[w][tid] = 0;
   __syncthreads();
 
-  K key[kSortItems];
-  int32_t val[kSortItems];
-  uint32_t rank[kSortItems];
+  K key[ITEMS];
+  V val[ITEMS];
+  uint32_t rank[ITEMS];  // rank among the wavefront's keys of the same digit
 #pragma unroll
-  for (int r = 0; r < kSortItems; ++r) {
-    const int idx = r * kSortBlock + tid;
+  for (int r = 0; r < ITEMS; ++r) {
+    const int idx = wave * kSub + r * kWave + lane;
     const bool valid = idx < len;
     key[r] = valid ? kin[start + idx] : (K)0;
-    val[r] = valid ? vin[start + idx] : 0;
+    if (valid) val[r] = vin[start + idx];
     const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
-    // lanes holding the same digit (and the same validity)
     uint64_t vb = __ballot(valid);
     uint64_t peers = valid ? vb : ~vb;
 #pragma unroll
@@ -253,39 +258,38 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
       const uint64_t bb = __ballot(bit);
       peers &= bit ? bb : ~bb;
     }
-    const uint32_t wrank = (uint32_t)__popcll(peers & lt_mask);
-    if (valid && wrank == 0) s_wcnt[wave][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    uint32_t before = s_run[d];
-    for (int w = 0; w < wave; ++w) before += s_wcnt[w][d];
-    rank[r] = before + wrank;
-    __syncthreads();
-    uint32_t add = 0;
-#pragma unroll
-    for (int w = 0; w < kSortBlock / kWave; ++w) {
-      add += s_wcnt[w][tid];
-      s_wcnt[w][tid] = 0;
-    }
-    s_run[tid] += add;
-    __syncthreads();
+    const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
+    // read the running count before the leader of each digit group adds to it
+    const uint32_t run = valid ? s_wcnt[wave][d] : 0u;
+    rank[r] = run + below;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && below == 0) s_wcnt[wave][d] = run + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
   }
-  // tile-local exclusive offsets per digit (thread tid owns digit tid)
+  __syncthreads();
+  // thread tid owns digit tid: offsets of each wavefront's run of that digit
   {
-    uint32_t c = s_run[tid];
-    uint32_t inc = wave_inclusive_scan(c);
+    uint32_t tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      const uint32_t c = s_wcnt[w][tid];
+      s_wcnt[w][tid] = tot;  // exclusive prefix over wavefronts
+      tot += c;
+    }
+    const uint32_t inc = wave_inclusive_scan(tot);
     if (lane == 63) s_wsum[wave] = inc;
     __syncthreads();
-    uint32_t off = inc - c;
+    uint32_t off = inc - tot;
     for (int w = 0; w < wave; ++w) off += s_wsum[w];
     s_excl[tid] = off;
-    __syncthreads();
   }
+  __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kSortItems; ++r) {
-    const int idx = r * kSortBlock + tid;
+  for (int r = 0; r < ITEMS; ++r) {
+    const int idx = wave * kSub + r * kWave + lane;
     if (idx < len) {
       const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
-      const uint32_t pos = s_excl[d] + rank[r];
+      const uint32_t pos = s_excl[d] + s_wcnt[wave][d] + rank[r];
       s_key[pos] = key[r];
       s_val[pos] = val[r];
     }
@@ -294,9 +298,9 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
   for (int i = tid; i < len; i += kSortBlock) {
     const K k = s_key[i];
     const uint32_t d = (uint32_t)(k >> shift) & 255u;
-    const int64_t g = (int64_t)s_base[d] + (i - (int64_t)s_excl[d]);
-    kout[g] = k;
-    vout[g] = s_val[i];
+    const int64_t gpos = (int64_t)s_base[d] + (i - (int64_t)s_excl[d]);
+    kout[gpos] = k;
+    vout[gpos] = s_val[i];
   }
 }
 
@@ -304,46 +308,32 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
 // Ping-pongs between (k0, v0) and (k1, v1); returns 0 if the result is in
 // buffer 0, 1 if in buffer 1.
 // returns -1 if the scan scratch is too small (nothing enqueued then)
-template <typename K>
-int radix_sort(K* k0, int32_t* v0, K* k1, int32_t* v1, int64_t m, int bits, uint32_t* hist,
+template <typename K, typename V = int32_t, int ITEMS = kSortItems>
+int radix_sort(K* k0, V* v0, K* k1, V* v1, int64_t m, int bits, uint32_t* hist,
                uint32_t* part, size_t part_elems, hipStream_t st,
                const uint32_t* dev_m = nullptr) {
   if (m <= 0) return 0;
-  const int64_t ntiles = (m + kSortTile - 1) / kSortTile;
+  constexpr int kTile = kSortBlock * ITEMS;
+  const int64_t ntiles = (m + kTile - 1) / kTile;
   if (part_elems < scan_u32_scratch_elems(256 * ntiles)) return -1;
   int cur = 0;
   for (int shift = 0; shift < bits; shift += 8) {
     K* ki = cur ? k1 : k0;
-    int32_t* vi = cur ? v1 : v0;
+    V* vi = cur ? v1 : v0;
     K* ko = cur ? k0 : k1;
-    int32_t* vo = cur ? v0 : v1;
-    hipLaunchKernelGGL((k_radix_hist<K>), dim3((unsigned)ntiles), dim3(kSortBlock), 0, st,
+    V* vo = cur ? v0 : v1;
+    hipLaunchKernelGGL((k_radix_hist<K, ITEMS>), dim3((unsigned)ntiles), dim3(kSortBlock), 0, st,
                        (const K*)ki, m, shift, hist, ntiles, dev_m);
     scan_u32(hist, 256 * ntiles, part, part_elems, st);
-    hipLaunchKernelGGL((k_radix_scatter<K>), dim3((unsigned)ntiles), dim3(kSortBlock), 0, st,
-                       (const K*)ki, (const int32_t*)vi, ko, vo, m, shift, (const uint32_t*)hist,
-                       ntiles, dev_m);
+    {
+      TimedLaunch tl("k_radix_scatter", st);
+      hipLaunchKernelGGL((k_radix_scatter<K, V, ITEMS>), dim3((unsigned)ntiles), dim3(kSortBlock),
+                         0, st, (const K*)ki, (const V*)vi, ko, vo, m, shift,
+                         (const uint32_t*)hist, ntiles, dev_m);
+    }
     cur ^= 1;
   }
   return cur;
-}
-
-size_t radix_hist_bytes(int64_t capacity) {
-  const int64_t ntiles = (capacity + kSortTile - 1) / kSortTile;
-  return (size_t)256 * (ntiles > 0 ? ntiles : 1) * 4;
-}
-size_t radix_part_bytes(int64_t capacity) {
-  const int64_t ntiles = (capacity + kSortTile - 1) / kSortTile;
-  return scan_u32_scratch_elems(256 * (ntiles > 0 ? ntiles : 1) + 1) * 4;
-}
-
-// One stable 8-bit pass over (key, val) pairs whose count lives on the
-// device (at most `capacity`); the result is left in (k1, v1).
-bool sort_u8_keys_dev(uint32_t* k0, int32_t* v0, uint32_t* k1, int32_t* v1, int64_t capacity,
-                      const uint32_t* dev_count, uint32_t* hist, uint32_t* part,
-                      size_t part_bytes, hipStream_t st) {
-  return radix_sort<uint32_t>(k0, v0, k1, v1, capacity, 8, hist, part, part_bytes / 4, st,
-                              dev_count) >= 0;
 }
 
 // -------------------------------------------------------- columns/offsets ---
@@ -372,6 +362,21 @@ __global__ __launch_bounds__(256) void k_offsets(const uint32_t* __restrict__ sk
   int64_t prev = (i == 0) ? -1 : (int64_t)skeys[i - 1];
   int64_t cur = (i == m) ? (int64_t)n : (int64_t)skeys[i];
   for (int64_t v = prev + 1; v <= cur; ++v) off[v] = (uint32_t)i;
+}
+
+// pos_of[order[i]] = i
+__global__ __launch_bounds__(256) void k_scatter_pos(const int32_t* __restrict__ order, int64_t m,
+                                                     uint32_t* __restrict__ pos_of) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) pos_of[order[i]] = (uint32_t)i;
+}
+
+// out[i] = pos_of[order[i]]
+__global__ __launch_bounds__(256) void k_gather_pos(const int32_t* __restrict__ order, int64_t m,
+                                                    const uint32_t* __restrict__ pos_of,
+                                                    uint32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) out[i] = pos_of[order[i]];
 }
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ a, int64_t n,
@@ -446,13 +451,72 @@ int pair_hash_log2(int64_t m) {
   return lg;
 }
 
+// ---------------------------------------------- sorts carrying their payload ---
+// When the time range fits 32 bits every sort moves its whole record:
+// key (u32) + payload {eid, other vertex, t - t_min}, so each column of the
+// three orders comes out of the last pass in order, with no random gathers.
+__global__ __launch_bounds__(256) void k_rec_init(const int32_t* __restrict__ src,
+                                                  const int32_t* __restrict__ dst,
+                                                  const int64_t* __restrict__ t, int64_t m,
+                                                  int64_t tmin, uint32_t* __restrict__ k,
+                                                  uint3* __restrict__ v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) {
+    k[i] = (uint32_t)(t[i] - tmin);
+    v[i] = make_uint3((uint32_t)i, (uint32_t)src[i], (uint32_t)dst[i]);
+  }
+}
+
+// MODE 0: (t, {eid, src, dst}) -> (src, {eid, dst, t})   out-CSR input
+// MODE 1: (t, {eid, src, dst}) -> (dst, {eid, src, t})   in-CSR input
+// MODE 2: (dst, {eid, src, t}) -> (src, {eid, dst, t})   pair-index input
+template <int MODE>
+__global__ __launch_bounds__(256) void k_rekey(const uint32_t* __restrict__ kin,
+                                               const uint3* __restrict__ vin, int64_t m,
+                                               uint32_t* __restrict__ kout,
+                                               uint3* __restrict__ vout) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) {
+    const uint32_t k = kin[i];
+    const uint3 v = vin[i];
+    if (MODE == 0) {
+      kout[i] = v.y;
+      vout[i] = make_uint3(v.x, v.z, k);
+    } else if (MODE == 1) {
+      kout[i] = v.z;
+      vout[i] = make_uint3(v.x, v.y, k);
+    } else {
+      kout[i] = v.y;
+      vout[i] = make_uint3(v.x, k, v.z);
+    }
+  }
+}
+
+// sorted (key, {eid, other, t - t_min}) -> columns of one order
+__global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ k,
+                                              const uint3* __restrict__ v, int64_t m,
+                                              int64_t tmin, int32_t* __restrict__ key_col,
+                                              int32_t* __restrict__ other_col,
+                                              int64_t* __restrict__ t_col,
+                                              int32_t* __restrict__ eid_col) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) {
+    const uint3 r = v[i];
+    if (key_col) key_col[i] = (int32_t)k[i];
+    other_col[i] = (int32_t)r.y;
+    t_col[i] = tmin + (int64_t)r.z;
+    eid_col[i] = (int32_t)r.x;
+  }
+}
+
 // --------------------------------------------------------------- layout ----
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct GraphLayout {
-  size_t out_off, in_off, out_src, out_dst, out_eid, out_t, in_src, in_eid, in_t, pair_dst,
+  size_t out_off, in_off, out_src, out_dst, out_eid, out_t, in_src, in_eid, in_dst, in_t,
+      out_to_in, pair_dst,
       pair_eid, pair_t, pair_hash, status, tminmax, keys0, keys1, vals0, vals1, hist, part,
-      part_elems, total;
+      part_elems, rk[3], rv[3], total;
 };
 
 static GraphLayout graph_layout(int32_t n, int64_t m) {
@@ -464,7 +528,8 @@ static GraphLayout graph_layout(int32_t n, int64_t m) {
     return at;
   };
   const size_t M = (size_t)m;
-  const int64_t ntiles = (m + kSortTile - 1) / kSortTile;
+  // histograms sized for the smaller (2048-entry) tiles of the record sorts
+  const int64_t ntiles = (m + kRecTile - 1) / kRecTile;
   L.out_off = take(((size_t)n + 1) * 4);
   L.in_off = take(((size_t)n + 1) * 4);
   L.out_src = take(M * 4);
@@ -473,6 +538,8 @@ static GraphLayout graph_layout(int32_t n, int64_t m) {
   L.out_t = take(M * 8);
   L.in_src = take(M * 4);
   L.in_eid = take(M * 4);
+  L.in_dst = take(M * 4);
+  L.out_to_in = take(M * 4);
   L.in_t = take(M * 8);
   L.pair_dst = take(M * 4);
   L.pair_eid = take(M * 4);
@@ -480,10 +547,19 @@ static GraphLayout graph_layout(int32_t n, int64_t m) {
   L.pair_hash = take(sizeof(PairSlot) << pair_hash_log2(m));
   L.status = take(4);
   L.tminmax = take(16);
+  // sort scratch: three (u32 key, 12-byte payload) buffers for the
+  // record-carrying sorts, aliased by the 64-bit-key buffers of the wide-time
+  // path (the two paths never run in the same build)
+  const size_t region = o;
+  for (int b = 0; b < 3; ++b) L.rk[b] = take((M + 1) * 4);
+  for (int b = 0; b < 3; ++b) L.rv[b] = take((M + 1) * 12);
+  const size_t rec_end = o;
+  o = region;
   L.keys0 = take((M + 1) * 8);
   L.keys1 = take((M + 1) * 8);
   L.vals0 = take((M + 1) * 4);
   L.vals1 = take((M + 1) * 4);
+  if (o < rec_end) o = rec_end;
   L.hist = take((size_t)256 * ntiles * 4);
   // scan scratch: the larger of the histogram scan and the (m + 1)-entry run scan
   L.part_elems = scan_u32_scratch_elems(256 * ntiles + 1);
@@ -498,6 +574,22 @@ size_t graph_workspace_bytes(int32_t n, int64_t m) { return graph_layout(n, m).t
 static int bitlen(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
 
 static unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// Runs of equal (src, dst) in the pair index -> hash table.  psrc holds the
+// sorted src keys; run_of and run_start are free buffers of m + 1 entries.
+static bool build_pair_hash(const uint32_t* psrc, const tc_graph* g, int64_t m, uint32_t* run_of,
+                            uint32_t* run_start, uint32_t* part, size_t pe, PairSlot* tab,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_run_flags, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st, psrc,
+                     (const int32_t*)g->pair_dst, m, run_of);
+  if (!scan_u32(run_of, m + 1, part, pe, st)) return false;
+  hipLaunchKernelGGL(k_run_starts, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st, psrc,
+                     (const int32_t*)g->pair_dst, m, (const uint32_t*)run_of, run_start);
+  hipLaunchKernelGGL(k_hash_insert, dim3(blocks_for(m, 256)), dim3(256), 0, st, psrc,
+                     (const int32_t*)g->pair_dst, (const uint32_t*)run_start,
+                     (const uint32_t*)(run_of + m), tab, g->pair_hash_log2);
+  return true;
+}
 
 tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
                       const int64_t* t, void* ws, size_t ws_bytes, hipStream_t st, tc_graph* g) {
@@ -514,6 +606,8 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   g->out_t = (int64_t*)(base + L.out_t);
   g->in_src = (int32_t*)(base + L.in_src);
   g->in_eid = (int32_t*)(base + L.in_eid);
+  g->in_dst = (int32_t*)(base + L.in_dst);
+  g->out_to_in = (uint32_t*)(base + L.out_to_in);
   g->in_t = (int64_t*)(base + L.in_t);
   g->pair_dst = (int32_t*)(base + L.pair_dst);
   g->pair_eid = (int32_t*)(base + L.pair_eid);
@@ -550,8 +644,76 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   g->t_max = tmax;
   const unsigned eb = blocks_for(m > 0 ? m : 1, 256);
 
-  // 1. time order: stable by t (initial order = eid)
   const int tbits = bitlen((uint64_t)(tmax - tmin));
+  const int vbits = bitlen((uint64_t)(n - 1));
+  const int64_t cap = (int64_t)1 << g->pair_hash_log2;
+  PairSlot* tab = (PairSlot*)g->pair_hash;
+  hipLaunchKernelGGL(k_hash_clear, dim3(blocks_for(cap, 256)), dim3(256), 0, st, tab, cap);
+  if (m == 0) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for((int64_t)n + 1, 256)), dim3(256), 0, st,
+                       g->out_off, (int64_t)n + 1, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for((int64_t)n + 1, 256)), dim3(256), 0, st,
+                       g->in_off, (int64_t)n + 1, 0u);
+    if (hipGetLastError() != hipSuccess) return TC_E_HIP;
+    return TC_OK;
+  }
+  if (tbits <= 32) {
+    // record-carrying sorts
+    uint32_t* rk[3];
+    uint3* rv[3];
+    for (int b = 0; b < 3; ++b) {
+      rk[b] = (uint32_t*)(base + L.rk[b]);
+      rv[b] = (uint3*)(base + L.rv[b]);
+    }
+    auto sort_rec = [&](int from, int tmp, int bits) -> int {
+      const int w = radix_sort<uint32_t, uint3, kRecItems>(rk[from], rv[from], rk[tmp], rv[tmp],
+                                                            m, bits, hist, part, pe, st);
+      return w < 0 ? -1 : (w ? tmp : from);
+    };
+    hipLaunchKernelGGL(k_rec_init, dim3(eb), dim3(256), 0, st, src, dst, t, m, tmin, rk[0], rv[0]);
+    const int T = sort_rec(0, 1, tbits);  // time order
+    if (T < 0) return TC_E_WORKSPACE;
+    const int X = (T + 1) % 3, Y = (T + 2) % 3;
+    // out-CSR: stable by src
+    hipLaunchKernelGGL(k_rekey<0>, dim3(eb), dim3(256), 0, st, (const uint32_t*)rk[T],
+                       (const uint3*)rv[T], m, rk[X], rv[X]);
+    int R = sort_rec(X, Y, vbits);
+    if (R < 0) return TC_E_WORKSPACE;
+    hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint32_t*)rk[R],
+                       (const uint3*)rv[R], m, tmin, g->out_src, g->out_dst, g->out_t,
+                       g->out_eid);
+    hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
+                       (const uint32_t*)rk[R], m, n, g->out_off);
+    // in-CSR: stable by dst
+    hipLaunchKernelGGL(k_rekey<1>, dim3(eb), dim3(256), 0, st, (const uint32_t*)rk[T],
+                       (const uint3*)rv[T], m, rk[X], rv[X]);
+    const int I = sort_rec(X, Y, vbits);
+    if (I < 0) return TC_E_WORKSPACE;
+    hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint32_t*)rk[I],
+                       (const uint3*)rv[I], m, tmin, g->in_dst, g->in_src, g->in_t, g->in_eid);
+    hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
+                       (const uint32_t*)rk[I], m, n, g->in_off);
+    // out_to_in[p] = in-CSR position of out_eid[p] (through the free key buffer of T)
+    hipLaunchKernelGGL(k_scatter_pos, dim3(eb), dim3(256), 0, st, (const int32_t*)g->in_eid, m,
+                       rk[T]);
+    hipLaunchKernelGGL(k_gather_pos, dim3(eb), dim3(256), 0, st, (const int32_t*)g->out_eid, m,
+                       (const uint32_t*)rk[T], g->out_to_in);
+    // pair index: the in-order (dst, t, eid) stably by src
+    const int P0 = (I + 1) % 3, P1 = (I + 2) % 3;
+    hipLaunchKernelGGL(k_rekey<2>, dim3(eb), dim3(256), 0, st, (const uint32_t*)rk[I],
+                       (const uint3*)rv[I], m, rk[P0], rv[P0]);
+    const int Pr = sort_rec(P0, P1, vbits);
+    if (Pr < 0) return TC_E_WORKSPACE;
+    hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint32_t*)rk[Pr],
+                       (const uint3*)rv[Pr], m, tmin, (int32_t*)nullptr, g->pair_dst,
+                       g->pair_t, g->pair_eid);
+    const int F0 = (Pr + 1) % 3, F1 = (Pr + 2) % 3;  // two free key buffers
+    if (!build_pair_hash(rk[Pr], g, m, rk[F0], rk[F1], part, pe, tab, st)) return TC_E_WORKSPACE;
+    if (hipGetLastError() != hipSuccess) return TC_E_HIP;
+    return TC_OK;
+  }
+  // wide time range: 64-bit time keys, columns gathered after each sort
+  // 1. time order: stable by t (initial order = eid)
   int32_t* torder;
   if (m > 0) {
     int where;
@@ -577,7 +739,6 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   if (m > 0 &&
       hipMemcpyAsync(torder_keep, torder, (size_t)m * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
     return TC_E_HIP;
-  const int vbits = bitlen((uint64_t)(n - 1));
   uint32_t* k0 = (uint32_t*)keys0;
   uint32_t* k1 = (uint32_t*)keys1;
   // 2. out-CSR: stable by src
@@ -604,7 +765,7 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     uint32_t* sk = w ? k1 : k0;
     int32_t* sv = w ? vals1 : vals0;
     hipLaunchKernelGGL(k_gather_order, dim3(eb), dim3(256), 0, st, (const uint32_t*)sk,
-                       (const int32_t*)sv, m, src, t, (int32_t*)nullptr, g->in_src, g->in_t,
+                       (const int32_t*)sv, m, src, t, g->in_dst, g->in_src, g->in_t,
                        g->in_eid);
     hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
                        (const uint32_t*)sk, m, n, g->in_off);
@@ -612,10 +773,14 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for((int64_t)n + 1, 256)), dim3(256), 0, st,
                        g->in_off, (int64_t)n + 1, 0u);
   }
+  // 3b. out_to_in[p] = in-CSR position of out_eid[p]
+  if (m > 0) {
+    hipLaunchKernelGGL(k_scatter_pos, dim3(eb), dim3(256), 0, st, (const int32_t*)g->in_eid, m,
+                       (uint32_t*)vals0);
+    hipLaunchKernelGGL(k_gather_pos, dim3(eb), dim3(256), 0, st, (const int32_t*)g->out_eid, m,
+                       (const uint32_t*)vals0, g->out_to_in);
+  }
   // 4. pair index: the in-order (dst, t, eid) stably sorted by src
-  const int64_t cap = (int64_t)1 << g->pair_hash_log2;
-  PairSlot* tab = (PairSlot*)g->pair_hash;
-  hipLaunchKernelGGL(k_hash_clear, dim3(blocks_for(cap, 256)), dim3(256), 0, st, tab, cap);
   if (m > 0) {
     hipLaunchKernelGGL(k_vertex_keys, dim3(eb), dim3(256), 0, st, src, g->in_eid, m, k0, vals0);
     int w = radix_sort<uint32_t>(k0, vals0, k1, vals1, m, vbits, hist, part, pe, st);
@@ -626,17 +791,9 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
                        (const int32_t*)sv, m, dst, t, (int32_t*)nullptr, g->pair_dst, g->pair_t,
                        g->pair_eid);
     // 5. pair-run hash table (the sorted src keys are still in sk)
-    uint32_t* run_of = w ? k0 : k1;            // the free key buffer, m + 1 entries
+    uint32_t* run_of = w ? k0 : k1;                        // the free key buffer (m + 1)
     uint32_t* run_start = (uint32_t*)(w ? vals0 : vals1);  // the free value buffer (m + 1)
-    hipLaunchKernelGGL(k_run_flags, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
-                       (const uint32_t*)sk, (const int32_t*)g->pair_dst, m, run_of);
-    if (!scan_u32(run_of, m + 1, part, pe, st)) return TC_E_WORKSPACE;
-    hipLaunchKernelGGL(k_run_starts, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
-                       (const uint32_t*)sk, (const int32_t*)g->pair_dst, m,
-                       (const uint32_t*)run_of, run_start);
-    hipLaunchKernelGGL(k_hash_insert, dim3(eb), dim3(256), 0, st, (const uint32_t*)sk,
-                       (const int32_t*)g->pair_dst, (const uint32_t*)run_start,
-                       (const uint32_t*)(run_of + m), tab, g->pair_hash_log2);
+    if (!build_pair_hash(sk, g, m, run_of, run_start, part, pe, tab, st)) return TC_E_WORKSPACE;
   }
   if (hipGetLastError() != hipSuccess) return TC_E_HIP;
   return TC_OK;

@@ -13,12 +13,6 @@ size_t graph_workspace_bytes(int32_t n, int64_t m);
 tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
                       const int64_t* t, void* ws, size_t ws_bytes, hipStream_t st, tc_graph* g);
 
-size_t radix_hist_bytes(int64_t capacity);
-size_t radix_part_bytes(int64_t capacity);
-bool sort_u8_keys_dev(uint32_t* k0, int32_t* v0, uint32_t* k1, int32_t* v1, int64_t capacity,
-                      const uint32_t* dev_count, uint32_t* hist, uint32_t* part,
-                      size_t part_bytes, hipStream_t st);
-
 // Shape of the 16-ary search tree over S (level 0 = S padded to 16n words;
 // levels 1..levels live in tc_weights.scratch at offset[L] words).
 constexpr int kMaxTreeLevels = 16;
@@ -60,5 +54,17 @@ size_t sample_workspace_bytes(uint64_t k, int32_t n_motifs);
 tc_status sample_estimate(const tc_graph* g, const tc_weights* w, const MotifPlan& plan,
                           uint64_t k, uint64_t seed, uint32_t stream_id, uint64_t i0,
                           tc_result* out, void* ws, size_t ws_bytes, hipStream_t st);
+
+// RAII timing of one launch site (active only after tc_timing_enable(1))
+class TimedLaunch {
+ public:
+  TimedLaunch(const char* name, hipStream_t st);
+  ~TimedLaunch();
+
+ private:
+  const char* name_;
+  hipStream_t st_;
+  hipEvent_t a_ = nullptr, b_ = nullptr;
+};
 
 }  // namespace tc

@@ -782,11 +782,17 @@ template <int NM>
 static void launch_chunk(const SampleArgs& A, hipStream_t st) {
   const unsigned blocks = (unsigned)((A.clen + kSBlock - 1) / kSBlock);
   hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, A.item_count);
-  hipLaunchKernelGGL(k_paths<NM>, dim3(blocks), dim3(kSBlock), 0, st, A);
+  {
+    TimedLaunch tl("k_paths", st);
+    hipLaunchKernelGGL(k_paths<NM>, dim3(blocks), dim3(kSBlock), 0, st, A);
+  }
   // enough wavefronts to fill the chip; each pulls items until the queue is empty
-  hipLaunchKernelGGL((k_listcount_reg<NM, 4>), dim3(kFastWaves), dim3(kWave), 0, st, A,
-                     (const uint32_t*)A.item_code, (const uint32_t*)A.item_count, A.mid_code,
-                     A.mid_count);
+  {
+    TimedLaunch tl("k_listcount_reg", st);
+    hipLaunchKernelGGL((k_listcount_reg<NM, 4>), dim3(kFastWaves), dim3(kWave), 0, st, A,
+                       (const uint32_t*)A.item_code, (const uint32_t*)A.item_count, A.mid_code,
+                       A.mid_count);
+  }
   hipLaunchKernelGGL((k_listcount_wave<NM, true>), dim3(kFastWaves), dim3(kWave), 0, st, A,
                      (const uint32_t*)A.mid_code, (const uint32_t*)A.mid_count, A.item_next,
                      A.wide_code, A.wide_count, A.fast_p, (uint32_t)kKeyCap);

@@ -2,12 +2,19 @@
 // path weights (Algorithm Preprocess with Claim "count":
 // w_e = d^-_u[t - delta, t] * d^+_v[t, t + delta]).
 //
-// Three kernels, all streaming in scan order p (out-CSR order):
-//   k_windows     coalesced reads of (src, dst, t)[p]; four binary searches
-//                 per edge (two in u's in-list, two in v's out-list; u is
-//                 shared by consecutive p, so its list stays in cache);
-//                 writes lo_in, a, lo_out, b and the 128-bit sum of a*b per
-//                 2048-edge tile.
+// The window bounds are ranks of sorted query sequences in sorted adjacency
+// arrays on the composite key (vertex, time): the out-CSR order p is sorted
+// by (u, t), so lo_in[p] = #{in-CSR entries < (u, t - delta)} and
+// lo_in[p] + a[p] = #{in-CSR entries <= (u, t)}; the in-CSR order q is sorted
+// by (v, t), so v's out-window bounds are ranks of (v, t) and (v, t + delta)
+// in the out-CSR.  Each rank sequence is one merge-path pass:
+//   k_mp_split    splits the merged sequence (queries + data) into tiles of
+//                 kMPTile entries by a binary search on each tile diagonal,
+//   k_mp_rank     stages the tile's data keys in LDS and ranks each of the
+//                 tile's queries there,
+// so every array is read once, coalesced.  Then:
+//   k_combine     per p: gathers v's window through the p -> q map, writes
+//                 lo_out, b and the 128-bit sum of a*b per 2048-edge tile.
 //   k_scan_tiles  one block scans the tile sums in 128-bit arithmetic, so
 //                 W >= 2^64 is detected exactly, and writes S[m] = W.
 //   k_scan_apply  per tile: w = a*b, block-wide exclusive scan, plus the
@@ -23,34 +30,105 @@ constexpr int kWBlock = 256;
 constexpr int kWItems = 8;
 constexpr int kWTile = kWBlock * kWItems;  // 2048 edges per tile
 
-__global__ __launch_bounds__(kWBlock) void k_windows(
-    const int32_t* __restrict__ out_src, const int32_t* __restrict__ out_dst,
-    const int64_t* __restrict__ out_t, const uint32_t* __restrict__ in_off,
-    const int64_t* __restrict__ in_t, const uint32_t* __restrict__ out_off, int64_t m,
-    int64_t delta, uint32_t* __restrict__ lo_in, uint32_t* __restrict__ a_out,
-    uint32_t* __restrict__ lo_out, uint32_t* __restrict__ b_out, uint64_t* __restrict__ tile_sums) {
+// ---- merge-path sorted search on (vertex, time) keys -------------------------
+constexpr int kMPTile = 2048;   // merged entries (queries + data) per block
+constexpr int kMPBlock = 256;
+
+struct KeyCols {
+  const int32_t* v;  // vertex column
+  const int64_t* t;  // time column
+  int64_t shift;     // added to every time of this side
+};
+
+// data entry (dv, dt) is ranked before query (qv, qt)
+template <bool UPPER>
+__device__ __forceinline__ bool before(int32_t dv, int64_t dt, int32_t qv, int64_t qt) {
+  return dv < qv || (dv == qv && (UPPER ? dt <= qt : dt < qt));
+}
+
+// split[b] = number of queries among the first min(b * kMPTile, nq + nd)
+// entries of the merge (a query is taken first unless a data entry is ranked
+// before it)
+template <bool UPPER>
+__global__ __launch_bounds__(256) void k_mp_split(KeyCols Q, int64_t nq, KeyCols D, int64_t nd,
+                                                  int64_t nsplit, uint32_t* __restrict__ split) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nsplit) return;
+  const int64_t d = b * kMPTile < nq + nd ? b * kMPTile : nq + nd;
+  int64_t lo = d - nd > 0 ? d - nd : 0;
+  int64_t hi = d < nq ? d : nq;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    const int64_t j = d - mid - 1;
+    if (!before<UPPER>(D.v[j], D.t[j] + D.shift, Q.v[mid], Q.t[mid] + Q.shift))
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  split[b] = (uint32_t)lo;
+}
+
+// rank of every query of the tile: out[i] = rank, or with `sub`
+// pair_out[i] = {sub[i], rank - sub[i]} (a window's start and length)
+template <bool UPPER>
+__global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, KeyCols D, int64_t nd,
+                                                      const uint32_t* __restrict__ split,
+                                                      const uint32_t* __restrict__ sub,
+                                                      uint32_t* __restrict__ out,
+                                                      uint2* __restrict__ pair_out) {
+  __shared__ int32_t s_v[kMPTile];
+  __shared__ int64_t s_t[kMPTile];
+  const int64_t b = blockIdx.x;
+  const int64_t d0 = b * kMPTile;
+  const int64_t d1 = d0 + kMPTile < nq + nd ? d0 + kMPTile : nq + nd;
+  const int64_t q0 = split[b], q1 = split[b + 1];
+  const int64_t i0 = d0 - q0, i1 = d1 - q1;
+  const int nd_t = (int)(i1 - i0);
+  for (int k = threadIdx.x; k < nd_t; k += kMPBlock) {
+    s_v[k] = D.v[i0 + k];
+    s_t[k] = D.t[i0 + k] + D.shift;
+  }
+  __syncthreads();
+  for (int64_t i = q0 + threadIdx.x; i < q1; i += kMPBlock) {
+    const int32_t qv = Q.v[i];
+    const int64_t qt = Q.t[i] + Q.shift;
+    int lo = 0, n = nd_t;
+    while (n > 0) {
+      const int half = n >> 1;
+      const int mid = lo + half;
+      const bool go = before<UPPER>(s_v[mid], s_t[mid], qv, qt);
+      lo = go ? mid + 1 : lo;
+      n = go ? n - half - 1 : half;
+    }
+    const uint32_t rank = (uint32_t)(i0 + lo);
+    if (pair_out) {
+      const uint32_t s0 = sub[i];
+      pair_out[i] = make_uint2(s0, rank - s0);
+    } else {
+      out[i] = sub ? rank - sub[i] : rank;
+    }
+  }
+}
+
+// per p: v's window from its in-CSR position, and the tile sums of a * b
+__global__ __launch_bounds__(kWBlock) void k_combine(const uint32_t* __restrict__ out_to_in,
+                                                     const uint2* __restrict__ win_q,
+                                                     const uint32_t* __restrict__ a, int64_t m,
+                                                     uint32_t* __restrict__ lo_out,
+                                                     uint32_t* __restrict__ b_out,
+                                                     uint64_t* __restrict__ tile_sums) {
   __shared__ U128 s_w[kWBlock / kWave];
   const int64_t start = (int64_t)blockIdx.x * kWTile;
   U128 acc{0, 0};
-#pragma unroll 2
+#pragma unroll 4
   for (int r = 0; r < kWItems; ++r) {
     const int64_t p = start + (int64_t)r * kWBlock + threadIdx.x;
     if (p < m) {
-      const int32_t u = out_src[p];
-      const int32_t v = out_dst[p];
-      const int64_t t = out_t[p];
-      const uint32_t il = in_off[u], ih = in_off[u + 1];
-      const uint32_t i0 = lower_bound<int64_t>(in_t, il, ih, t - delta);
-      const uint32_t i1 = upper_bound<int64_t>(in_t, i0, ih, t);
-      const uint32_t ol = out_off[v], oh = out_off[v + 1];
-      const uint32_t o0 = lower_bound<int64_t>(out_t, ol, oh, t);
-      const uint32_t o1 = upper_bound<int64_t>(out_t, o0, oh, t + delta);
-      lo_in[p] = i0;
-      a_out[p] = i1 - i0;
-      lo_out[p] = o0;
-      b_out[p] = o1 - o0;
-      const uint64_t w = (uint64_t)(i1 - i0) * (uint64_t)(o1 - o0);
-      acc = add128(acc, U128{w, 0});
+      const uint2 wq = win_q[out_to_in[p]];
+      const uint32_t bb = wq.y;
+      lo_out[p] = wq.x;
+      b_out[p] = bb;
+      acc = add128(acc, U128{(uint64_t)a[p] * (uint64_t)bb, 0});
     }
   }
   acc = wave_sum128(acc);
@@ -201,7 +279,7 @@ STree stree_layout(int64_t m) {
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WeightsLayout {
-  size_t lo_in, a, lo_out, b, S, status, tile_sums, tile_off, tree, total;
+  size_t lo_in, a, lo_out, b, S, status, tile_sums, tile_off, tree, lo_out_q, win_q, split, total;
 };
 
 static WeightsLayout weights_layout(int64_t m) {
@@ -224,6 +302,9 @@ static WeightsLayout weights_layout(int64_t m) {
   L.status = take(4);
   L.tile_sums = take(ntiles * 16);
   L.tile_off = take(ntiles * 8);
+  L.lo_out_q = take(M * 4);
+  L.win_q = take(M * 8);
+  L.split = take((size_t)((2 * M + kMPTile - 1) / kMPTile + 2) * 4);
   L.total = o;
   return L;
 }
@@ -248,16 +329,45 @@ tc_status path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_byt
   uint64_t* tile_sums = (uint64_t*)(base + L.tile_sums);
   uint64_t* tile_off = (uint64_t*)(base + L.tile_off);
   const int64_t ntiles = (m + kWTile - 1) / kWTile;
-  if (ntiles > 0)
-    hipLaunchKernelGGL(k_windows, dim3((unsigned)ntiles), dim3(kWBlock), 0, st, g->out_src,
-                       g->out_dst, g->out_t, g->in_off, g->in_t, g->out_off, m, delta, w->lo_in,
-                       w->a, w->lo_out, w->b, tile_sums);
+  uint32_t* lo_out_q = (uint32_t*)(base + L.lo_out_q);
+  uint2* win_q = (uint2*)(base + L.win_q);
+  uint32_t* split = (uint32_t*)(base + L.split);
+  if (m > 0) {
+    TimedLaunch tl("k_windows", st);
+    const int64_t nsplit = (2 * m + kMPTile - 1) / kMPTile + 1;
+    const unsigned sb = (unsigned)((nsplit + 255) / 256);
+    const unsigned rb = (unsigned)(nsplit - 1);
+    const KeyCols outk{g->out_src, g->out_t, 0};
+    const KeyCols ink{g->in_dst, g->in_t, 0};
+    // u's in-window [t - delta, t] for every out-CSR position p
+    const KeyCols q_lo{g->out_src, g->out_t, -delta};
+    hipLaunchKernelGGL(k_mp_split<false>, dim3(sb), dim3(256), 0, st, q_lo, m, ink, m, nsplit, split);
+    hipLaunchKernelGGL(k_mp_rank<false>, dim3(rb), dim3(kMPBlock), 0, st, q_lo, m, ink, m,
+                       (const uint32_t*)split, (const uint32_t*)nullptr, w->lo_in, (uint2*)nullptr);
+    hipLaunchKernelGGL(k_mp_split<true>, dim3(sb), dim3(256), 0, st, outk, m, ink, m, nsplit, split);
+    hipLaunchKernelGGL(k_mp_rank<true>, dim3(rb), dim3(kMPBlock), 0, st, outk, m, ink, m,
+                       (const uint32_t*)split, (const uint32_t*)w->lo_in, w->a, (uint2*)nullptr);
+    // v's out-window [t, t + delta] for every in-CSR position q
+    hipLaunchKernelGGL(k_mp_split<false>, dim3(sb), dim3(256), 0, st, ink, m, outk, m, nsplit, split);
+    hipLaunchKernelGGL(k_mp_rank<false>, dim3(rb), dim3(kMPBlock), 0, st, ink, m, outk, m,
+                       (const uint32_t*)split, (const uint32_t*)nullptr, lo_out_q, (uint2*)nullptr);
+    const KeyCols q_hi{g->in_dst, g->in_t, delta};
+    hipLaunchKernelGGL(k_mp_split<true>, dim3(sb), dim3(256), 0, st, q_hi, m, outk, m, nsplit, split);
+    hipLaunchKernelGGL(k_mp_rank<true>, dim3(rb), dim3(kMPBlock), 0, st, q_hi, m, outk, m,
+                       (const uint32_t*)split, (const uint32_t*)lo_out_q, (uint32_t*)nullptr,
+                       win_q);
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
+                       (const uint32_t*)g->out_to_in, (const uint2*)win_q,
+                       (const uint32_t*)w->a, m, w->lo_out, w->b, tile_sums);
+  }
   hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, (const uint64_t*)tile_sums, ntiles,
                      tile_off, w->S, m, w->status);
-  if (ntiles > 0)
+  if (ntiles > 0) {
+    TimedLaunch tl("k_scan_apply", st);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
                        (const uint32_t*)w->a, (const uint32_t*)w->b, m,
                        (const uint64_t*)tile_off, w->S);
+  }
   // search tree over S (padding first, then each level)
   const STree T = stree_layout(m);
   const int64_t pad = T.count[0] - (m + 1);
