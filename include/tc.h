@@ -136,6 +136,20 @@ typedef struct tc_result {
   uint64_t *X;
 } tc_result;
 
+/* Launch-shape choices of the sampler.  They change speed only, never a
+ * result (every output is a pure function of the inputs).
+ *   chunk_log2  log2 of the samples processed per chunk over all deltas
+ *               (10..22; the queue and window scratch scale with it)
+ *   path_blocks persistent blocks of the path kernel (0 = one per tile)
+ *   reg_waves   wavefronts of the register ListCount pass
+ *   fast_waves  wavefronts of the LDS-key ListCount pass (64..8192) */
+typedef struct {
+  int32_t chunk_log2;
+  int32_t path_blocks;
+  int32_t reg_waves;
+  int32_t fast_waves;
+} tc_tuning;
+
 /* Library version string (host, static storage). */
 const char *tc_version(void);
 
@@ -196,6 +210,32 @@ tc_status tc_sample_estimate(const tc_graph *g, const tc_weights *w, const tc_mo
                              int32_t n_motifs, uint64_t k, uint64_t seed, uint32_t stream_id,
                              uint64_t i0, void *ws, size_t ws_bytes, tc_result *out,
                              void *stream);
+
+/* Batched Estimate: n_deltas (1..8) weight sets of the same graph (one per
+ * delta, from tc_path_weights) and n_motifs motifs sharing the anchor, in one
+ * launch sequence: the path kernel is persistent over (delta, sample tile)
+ * work and every ListCount pass serves all deltas.  Sample i of every delta
+ * uses the counter of sample i of a single tc_sample_estimate call with the
+ * same (seed, stream_id), so out[d] equals that call's result bit for bit.
+ * out is a host array of n_deltas tc_result pointers; tuning may be NULL
+ * (defaults).  Enqueue only, no host synchronisation, no allocation, no
+ * memset: the sequence can be captured into a HIP graph and replayed.
+ * Errors: as tc_sample_estimate. */
+tc_status tc_batch_workspace_bytes(uint64_t k, int32_t n_deltas, int32_t n_motifs, size_t *bytes);
+tc_status tc_batch_estimate(const tc_graph *g, const tc_weights *const *w, int32_t n_deltas,
+                            const tc_motif *motifs, int32_t n_motifs, uint64_t k, uint64_t seed,
+                            uint32_t stream_id, uint64_t i0, const tc_tuning *tuning, void *ws,
+                            size_t ws_bytes, tc_result *const *out, void *stream);
+
+/* Autotuner: times tc_batch_estimate with k_probe samples for candidate
+ * tunings (coordinate descent over chunk_log2, path_blocks, reg_waves,
+ * fast_waves) with HIP events on `stream`, and returns the fastest in *best
+ * and its time in *best_ms.  Synchronises the stream; `out` receives the
+ * probe results.  ws must hold tc_batch_workspace_bytes(k_probe, ...). */
+tc_status tc_autotune(const tc_graph *g, const tc_weights *const *w, int32_t n_deltas,
+                      const tc_motif *motifs, int32_t n_motifs, uint64_t k_probe, uint64_t seed,
+                      void *ws, size_t ws_bytes, tc_result *const *out, void *stream,
+                      tc_tuning *best, double *best_ms);
 
 /* Profiling aid (not part of the method).  After tc_timing_enable(1) the
  * library records a pair of HIP events on the launch stream around each

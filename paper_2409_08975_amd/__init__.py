@@ -25,7 +25,8 @@ _STATUS_NAMES = {0: "TC_OK", -1: "TC_E_ARG", -2: "TC_E_RANGE", -3: "TC_E_OVERFLO
 
 EXPORTED = ["tc_version", "tc_graph_workspace_bytes", "tc_build_graph",
             "tc_weights_workspace_bytes", "tc_path_weights", "tc_sample_workspace_bytes",
-            "tc_sample_estimate", "tc_timing_enable", "tc_timing_reset", "tc_timing_read"]
+            "tc_sample_estimate", "tc_batch_workspace_bytes", "tc_batch_estimate",
+            "tc_autotune", "tc_timing_enable", "tc_timing_reset", "tc_timing_read"]
 
 
 class TCError(RuntimeError):
@@ -69,6 +70,18 @@ class tc_result(ctypes.Structure):
                 ("e2", _P), ("e3", _P), ("X", _P)]
 
 
+class tc_tuning(ctypes.Structure):
+    _fields_ = [("chunk_log2", ctypes.c_int32), ("path_blocks", ctypes.c_int32),
+                ("reg_waves", ctypes.c_int32), ("fast_waves", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def make_tuning(chunk_log2=22, path_blocks=0, reg_waves=5120, fast_waves=5120) -> tc_tuning:
+    return tc_tuning(chunk_log2, path_blocks, reg_waves, fast_waves)
+
+
 _lib = None
 
 
@@ -91,6 +104,13 @@ def lib():
         L.tc_sample_estimate.argtypes = [ctypes.POINTER(tc_graph), ctypes.POINTER(tc_weights),
                                          ctypes.POINTER(tc_motif), I32, U64, U64, U32, U64,
                                          _P, SZ, ctypes.POINTER(tc_result), _P]
+        L.tc_batch_workspace_bytes.argtypes = [U64, I32, I32, ctypes.POINTER(SZ)]
+        L.tc_batch_estimate.argtypes = [ctypes.POINTER(tc_graph), _P, I32,
+                                        ctypes.POINTER(tc_motif), I32, U64, U64, U32, U64,
+                                        ctypes.POINTER(tc_tuning), _P, SZ, _P, _P]
+        L.tc_autotune.argtypes = [ctypes.POINTER(tc_graph), _P, I32, ctypes.POINTER(tc_motif),
+                                  I32, U64, U64, _P, SZ, _P, _P, ctypes.POINTER(tc_tuning),
+                                  ctypes.POINTER(ctypes.c_double)]
         L.tc_timing_enable.argtypes = [I32]
         L.tc_timing_reset.argtypes = []
         L.tc_timing_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -229,14 +249,22 @@ def sample_workspace_bytes(k: int, n_motifs: int) -> int:
     return b.value
 
 
+def batch_workspace_bytes(k: int, n_deltas: int, n_motifs: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().tc_batch_workspace_bytes(int(k), int(n_deltas), int(n_motifs), ctypes.byref(b)),
+           "tc_batch_workspace_bytes")
+    return b.value
+
+
 _ws_cache: dict = {}
 
 
-def _sample_ws(k: int, nm: int, device) -> torch.Tensor:
-    """Scratch for tc_sample_estimate, kept per (device, stream) and grown on
-    demand (stream-ordered reuse)."""
-    need = sample_workspace_bytes(k, nm)
-    key = (str(device), torch.cuda.current_stream(device).cuda_stream)
+def _sample_ws(k: int, nm: int, device, nd: int = 1, stream=None) -> torch.Tensor:
+    """Scratch for the sampler, kept per (device, stream) and grown on demand
+    (stream-ordered reuse)."""
+    need = batch_workspace_bytes(k, nd, nm)
+    st = stream if stream is not None else torch.cuda.current_stream(device)
+    key = (str(device), st.cuda_stream)
     buf = _ws_cache.get(key)
     if buf is None or buf.numel() < need:
         buf = torch.empty(need, dtype=torch.uint8, device=device)
@@ -269,33 +297,99 @@ def tc_path_weights(graph: Graph, delta: int, stream=None) -> Weights:
     return Weights(w, ws, graph)
 
 
+def new_result(n_motifs: int, k: int, device, per_sample: bool = False) -> Result:
+    """Output buffers of one delta (per-sample arrays only with per_sample)."""
+    nm = n_motifs
+    out = Result(torch.zeros(2 * nm, dtype=torch.int64, device=device),
+                 torch.zeros(nm, dtype=torch.int64, device=device),
+                 torch.zeros(nm, dtype=torch.float64, device=device),
+                 torch.zeros(1, dtype=torch.int32, device=device))
+    if per_sample:
+        out.e1 = torch.empty(k, dtype=torch.int32, device=device)
+        out.e2 = torch.empty(k, dtype=torch.int32, device=device)
+        out.e3 = torch.empty(k, dtype=torch.int32, device=device)
+        out.X = torch.empty((nm, k), dtype=torch.int64, device=device)
+    return out
+
+
+def _c_result(out: Result) -> tc_result:
+    return tc_result(_ptr(out.cnt).value, _ptr(out.hits).value, _ptr(out.estimate).value,
+                     _ptr(out.status).value, _ptr(out.e1).value, _ptr(out.e2).value,
+                     _ptr(out.e3).value, _ptr(out.X).value)
+
+
+def _motif_array(motifs):
+    nm = len(motifs)
+    return nm, (tc_motif * nm)(*[make_motif(m) for m in motifs])
+
+
 def tc_sample_estimate(graph: Graph, weights: Weights, motifs, k: int, seed: int,
                        stream_id: int = 0, i0: int = 0, per_sample: bool = False,
                        stream=None, out: Result | None = None,
                        workspace: torch.Tensor | None = None) -> Result:
     """Estimate(M, k) for a list of motifs (each a list of (src, dst) edges in pi order)."""
-    nm = len(motifs)
-    arr = (tc_motif * nm)(*[make_motif(m) for m in motifs])
+    nm, arr = _motif_array(motifs)
     dev = graph.ws.device
     if out is None:
-        out = Result(torch.zeros(2 * nm, dtype=torch.int64, device=dev),
-                     torch.zeros(nm, dtype=torch.int64, device=dev),
-                     torch.zeros(nm, dtype=torch.float64, device=dev),
-                     torch.zeros(1, dtype=torch.int32, device=dev))
-        if per_sample:
-            out.e1 = torch.empty(k, dtype=torch.int32, device=dev)
-            out.e2 = torch.empty(k, dtype=torch.int32, device=dev)
-            out.e3 = torch.empty(k, dtype=torch.int32, device=dev)
-            out.X = torch.empty((nm, k), dtype=torch.int64, device=dev)
-    r = tc_result(_ptr(out.cnt).value, _ptr(out.hits).value, _ptr(out.estimate).value,
-                  _ptr(out.status).value, _ptr(out.e1).value, _ptr(out.e2).value,
-                  _ptr(out.e3).value, _ptr(out.X).value)
-    ws = _sample_ws(k, nm, dev) if workspace is None else workspace
+        out = new_result(nm, k, dev, per_sample)
+    r = _c_result(out)
+    ws = _sample_ws(k, nm, dev, 1, stream) if workspace is None else workspace
     _check(lib().tc_sample_estimate(ctypes.byref(graph.c), ctypes.byref(weights.c), arr, nm,
                                     int(k), int(seed), int(stream_id), int(i0), _ptr(ws),
                                     ws.numel(), ctypes.byref(r), _stream(stream)),
            "tc_sample_estimate")
     return out
+
+
+class _BatchArgs:
+    """ctypes arrays of one batched call, kept alive together."""
+
+    def __init__(self, weights, outs):
+        nd = len(weights)
+        self.wc = [w.c for w in weights]
+        self.wp = (ctypes.POINTER(tc_weights) * nd)(*[ctypes.pointer(c) for c in self.wc])
+        self.rc = [_c_result(o) for o in outs]
+        self.rp = (ctypes.POINTER(tc_result) * nd)(*[ctypes.pointer(c) for c in self.rc])
+
+
+def tc_batch_estimate(graph: Graph, weights, motifs, k: int, seed: int, stream_id: int = 0,
+                      i0: int = 0, per_sample: bool = False, tuning: tc_tuning | None = None,
+                      stream=None, outs=None, workspace: torch.Tensor | None = None):
+    """Estimate(M, k) for every motif and every delta of `weights` (a list of
+    Weights of this graph) in one launch sequence; returns one Result per delta."""
+    nd = len(weights)
+    nm, arr = _motif_array(motifs)
+    dev = graph.ws.device
+    if outs is None:
+        outs = [new_result(nm, k, dev, per_sample) for _ in range(nd)]
+    args = _BatchArgs(weights, outs)
+    ws = _sample_ws(k, nm, dev, nd, stream) if workspace is None else workspace
+    _check(lib().tc_batch_estimate(ctypes.byref(graph.c), ctypes.cast(args.wp, _P), nd, arr, nm,
+                                   int(k), int(seed), int(stream_id), int(i0),
+                                   ctypes.byref(tuning) if tuning is not None else None,
+                                   _ptr(ws), ws.numel(), ctypes.cast(args.rp, _P),
+                                   _stream(stream)),
+           "tc_batch_estimate")
+    return outs
+
+
+def tc_autotune(graph: Graph, weights, motifs, k_probe: int, seed: int = 1, stream=None):
+    """Fastest tuning for this (graph, deltas, motifs) by timed probes of
+    k_probe samples; returns (tc_tuning, milliseconds of the best probe)."""
+    nd = len(weights)
+    nm, arr = _motif_array(motifs)
+    dev = graph.ws.device
+    outs = [new_result(nm, k_probe, dev) for _ in range(nd)]
+    args = _BatchArgs(weights, outs)
+    ws = _sample_ws(k_probe, nm, dev, nd, stream)
+    best = tc_tuning()
+    ms = ctypes.c_double(0.0)
+    _check(lib().tc_autotune(ctypes.byref(graph.c), ctypes.cast(args.wp, _P), nd, arr, nm,
+                             int(k_probe), int(seed), _ptr(ws), ws.numel(),
+                             ctypes.cast(args.rp, _P), _stream(stream), ctypes.byref(best),
+                             ctypes.byref(ms)),
+           "tc_autotune")
+    return best, ms.value
 
 
 def timing_enable(on: bool = True) -> None:

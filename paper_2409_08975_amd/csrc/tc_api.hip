@@ -73,23 +73,113 @@ tc_status tc_path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_
 
 tc_status tc_sample_workspace_bytes(uint64_t k, int32_t n_motifs, size_t* bytes) {
   if (!bytes || k < 1 || n_motifs < 1 || n_motifs > tc::kMaxMotifs) return TC_E_ARG;
-  *bytes = tc::sample_workspace_bytes(k, n_motifs);
+  *bytes = tc::sample_workspace_bytes(k, 1, n_motifs, nullptr);
   return TC_OK;
+}
+
+tc_status tc_batch_workspace_bytes(uint64_t k, int32_t n_deltas, int32_t n_motifs, size_t* bytes) {
+  if (!bytes || k < 1 || n_motifs < 1 || n_motifs > tc::kMaxMotifs || n_deltas < 1 ||
+      n_deltas > tc::kMaxDeltas)
+    return TC_E_ARG;
+  *bytes = tc::sample_workspace_bytes(k, n_deltas, n_motifs, nullptr);
+  return TC_OK;
+}
+
+static tc_status check_result(const tc_result* out) {
+  if (!out || !out->cnt || !out->hits || !out->estimate || !out->status) return TC_E_ARG;
+  if ((out->e1 || out->e2 || out->e3) && !(out->e1 && out->e2 && out->e3)) return TC_E_ARG;
+  return TC_OK;
+}
+
+tc_status tc_batch_estimate(const tc_graph* g, const tc_weights* const* w, int32_t n_deltas,
+                            const tc_motif* motifs, int32_t n_motifs, uint64_t k, uint64_t seed,
+                            uint32_t stream_id, uint64_t i0, const tc_tuning* tuning, void* ws,
+                            size_t ws_bytes, tc_result* const* out, void* stream) {
+  if (!g || !w || !out || k < 1 || n_deltas < 1 || n_deltas > tc::kMaxDeltas) return TC_E_ARG;
+  for (int d = 0; d < n_deltas; ++d) {
+    if (!w[d] || w[d]->m != g->m) return TC_E_ARG;
+    if (check_result(out[d]) != TC_OK) return TC_E_ARG;
+  }
+  tc::MotifPlan plan;
+  tc_status s = tc::compile_motifs(motifs, n_motifs, &plan);
+  if (s != TC_OK) return s;
+  if (!ws) return TC_E_ARG;
+  const tc::SampleTuning t = tuning ? *tuning : tc::default_tuning();
+  return tc::sample_batch(g, w, n_deltas, plan, k, seed, stream_id, i0, out, t, ws, ws_bytes,
+                          (hipStream_t)stream);
 }
 
 tc_status tc_sample_estimate(const tc_graph* g, const tc_weights* w, const tc_motif* motifs,
                              int32_t n_motifs, uint64_t k, uint64_t seed, uint32_t stream_id,
                              uint64_t i0, void* ws, size_t ws_bytes, tc_result* out,
                              void* stream) {
-  if (!g || !w || !out || !out->cnt || !out->hits || !out->estimate || !out->status) return TC_E_ARG;
+  if (!g || !w || check_result(out) != TC_OK) return TC_E_ARG;
   if (k < 1 || w->m != g->m) return TC_E_ARG;
-  if ((out->e1 || out->e2 || out->e3) && !(out->e1 && out->e2 && out->e3)) return TC_E_ARG;
   tc::MotifPlan plan;
   tc_status s = tc::compile_motifs(motifs, n_motifs, &plan);
   if (s != TC_OK) return s;
   if (!ws) return TC_E_ARG;
-  return tc::sample_estimate(g, w, plan, k, seed, stream_id, i0, out, ws, ws_bytes,
-                             (hipStream_t)stream);
+  const tc_weights* wl[1] = {w};
+  tc_result* ol[1] = {out};
+  return tc::sample_batch(g, wl, 1, plan, k, seed, stream_id, i0, ol, tc::default_tuning(), ws,
+                          ws_bytes, (hipStream_t)stream);
+}
+
+tc_status tc_autotune(const tc_graph* g, const tc_weights* const* w, int32_t n_deltas,
+                      const tc_motif* motifs, int32_t n_motifs, uint64_t k_probe, uint64_t seed,
+                      void* ws, size_t ws_bytes, tc_result* const* out, void* stream,
+                      tc_tuning* best, double* best_ms) {
+  if (!best || !best_ms) return TC_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return TC_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return TC_E_HIP;
+  }
+  auto run = [&](const tc_tuning& t, double* ms) -> tc_status {
+    tc_status s = tc_batch_estimate(g, w, n_deltas, motifs, n_motifs, k_probe, seed, 0, 0, &t,
+                                    ws, ws_bytes, out, stream);
+    if (s != TC_OK) return s;  // warm
+    if (hipEventRecord(e0, st) != hipSuccess) return TC_E_HIP;
+    s = tc_batch_estimate(g, w, n_deltas, motifs, n_motifs, k_probe, seed, 0, 0, &t, ws,
+                          ws_bytes, out, stream);
+    if (s != TC_OK) return s;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+      return TC_E_HIP;
+    float f = 0.f;
+    if (hipEventElapsedTime(&f, e0, e1) != hipSuccess) return TC_E_HIP;
+    *ms = f;
+    return TC_OK;
+  };
+  tc_tuning cur = tc::default_tuning();
+  double cur_ms = 0;
+  tc_status s = run(cur, &cur_ms);
+  const int32_t chunks[] = {20, 21, 22};
+  const int32_t pblocks[] = {0, 1024, 4096};
+  const int32_t rwaves[] = {2560, 5120, 10240};
+  const int32_t fwaves[] = {2560, 5120, 8192};
+  for (int dim = 0; dim < 4 && s == TC_OK; ++dim) {
+    for (int c = 0; c < 3 && s == TC_OK; ++c) {
+      tc_tuning t = cur;
+      if (dim == 0) t.chunk_log2 = chunks[c];
+      if (dim == 1) t.path_blocks = pblocks[c];
+      if (dim == 2) t.reg_waves = rwaves[c];
+      if (dim == 3) t.fast_waves = fwaves[c];
+      double ms = 0;
+      s = run(t, &ms);
+      if (s == TC_OK && ms < cur_ms) {
+        cur = t;
+        cur_ms = ms;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != TC_OK) return s;
+  *best = cur;
+  *best_ms = cur_ms;
+  return TC_OK;
 }
 
 }  // extern "C"

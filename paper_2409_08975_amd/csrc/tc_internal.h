@@ -47,13 +47,16 @@ struct MotifPlan {
 
 tc_status compile_motifs(const tc_motif* motifs, int32_t n_motifs, MotifPlan* plan);
 
-// samples per chunk of the two-kernel sampler, for a call with k samples
-uint64_t sample_chunk(uint64_t k);
-size_t sample_workspace_bytes(uint64_t k, int32_t n_motifs);
-
-tc_status sample_estimate(const tc_graph* g, const tc_weights* w, const MotifPlan& plan,
-                          uint64_t k, uint64_t seed, uint32_t stream_id, uint64_t i0,
-                          tc_result* out, void* ws, size_t ws_bytes, hipStream_t st);
+// Several deltas share one sampling launch sequence.
+constexpr int kMaxDeltas = 8;
+typedef tc_tuning SampleTuning;
+SampleTuning default_tuning();
+// Workspace of sample_batch; with t == NULL, room for any tuning.
+size_t sample_workspace_bytes(uint64_t k, int nd, int32_t n_motifs, const SampleTuning* t);
+tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
+                       const MotifPlan& plan, uint64_t k, uint64_t seed, uint32_t stream_id,
+                       uint64_t i0, tc_result* const* out, const SampleTuning& tune, void* ws,
+                       size_t ws_bytes, hipStream_t st);
 
 // RAII timing of one launch site (active only after tc_timing_enable(1))
 class TimedLaunch {

@@ -1,40 +1,40 @@
 // Sample + CheckMotif + ListCount + reduction (Algorithms Sample,
-// CheckMotif, ListCount and the last line of Estimate).
+// CheckMotif, ListCount and the last line of Estimate), for one or several
+// values of delta at once (each delta with its own weights, all motifs
+// sharing the anchor, sample i of every delta drawn from the same counter).
 //
-// The k samples are processed in chunks.  Per chunk:
-//   k_paths          one thread per sample: a Philox4x32-10 block keyed by
+// The samples are processed in chunks of `chunk` samples per delta.  Per chunk:
+//   k_paths          persistent: each block takes (delta, 256-sample tile)
+//                    work units.  Per sample: a Philox4x32-10 block keyed by
 //                    (seed, stream) at counter (i, attempt); r uniform in
 //                    [0, W) by Lemire reduction of a 64-bit draw; p with
-//                    S[p] <= r < S[p+1] by binary search of the exact CDF;
+//                    S[p] <= r < S[p+1] through the 16-ary search tree over S;
 //                    j1, j3 uniform inside the two windows; gathers give
 //                    e1 = (x, u, t1), e2 = (u, v, t2), e3 = (v, y, t3).
 //                    CheckMotif rejects unless x, u, v, y are distinct,
-//                    t1 < t2 < t3 and t3 - t1 <= delta.  For an accepted path
-//                    the window (t3, t1 + delta] of every distinct pair used
-//                    by the batch's lists is found once (a hash lookup of the
-//                    pair's run, then two binary searches on time) and stored
-//                    per sample.  A motif with no list counts 1, with one list
-//                    counts its length, with an empty list counts 0; every
-//                    other (sample, motif) is appended to a work queue.
-//   k_listcount_wave one wavefront per queued item, items handed out by an
-//                    atomic counter.  ListCount level by level:
+//                    t1 < t2 < t3 and t3 - t1 <= delta.  The accepted paths of
+//                    the tile are compacted in LDS and the window
+//                    (t3, t1 + delta] of every distinct pair used by the
+//                    motifs is found once per path (hash lookup of the pair's
+//                    run, two binary searches on time), spread over the block.
+//                    A motif with no list counts 1, with one list its length,
+//                    with an empty list 0; every other (sample, motif) is
+//                    queued.
+//   k_listcount_reg  one wavefront per queued item, lists up to 256 entries.
+//                    ListCount level by level:
 //                      c_1[i] = #{j : L_0[j] < L_1[i]},
 //                      c_r[i] = P_{r-1}[#{j : L_{r-1}[j] < L_r[i]}],
-//                    where P_r is the exclusive prefix sum of c_r (so that
-//                    P_r[q] counts the chains ending among the first q entries
-//                    of L_r), and X = sum_i c_{l-1}[i].  The 64 lanes take 64
-//                    entries of L_r at a time: a binary search in L_{r-1}, a
-//                    lookup of P_{r-1} in LDS and a wavefront prefix scan
-//                    that writes P_r back to LDS.  Each level's total is also
-//                    summed in 128 bits, which flags a total >= 2^64.
-//                    A first pass stages the keys in LDS (lists up to 1,024
-//                    entries); a second, narrow pass searches the pair index
-//                    in memory (lists up to 65,536 entries).
-//   k_listcount_big  items with a longer list: one thread per item runs the
-//                    same count as a merged sweep over the lists in time
-//                    order.
-// Per-thread sums are 64-bit with carries sent straight to the high word, so
-// cnt is an exact 128-bit integer whatever the launch shape or item order.
+//                    with P_r the prefix sums of c_r and X = sum_i c_{l-1}[i];
+//                    keys staged in LDS, prefix sums held in registers across
+//                    the lanes, gathered with ds_bpermute.
+//   k_listcount_wave the same level recursion for longer lists, prefix sums
+//                    in per-wavefront scratch (LDS keys up to 1,024 entries,
+//                    then in-memory searches up to 65,536 entries).
+//   k_listcount_big  longer still: one thread per item, merged time sweep.
+// Each level total is summed in 128 bits (a total >= 2^64 sets the overflow
+// bit).  Block sums are 128-bit and reach the outputs with one set of
+// atomics per block, so cnt is exact whatever the launch shape, the item
+// order or the tuning.
 #include <hip/hip_runtime.h>
 
 #include "tc_device.h"
@@ -43,47 +43,22 @@
 namespace tc {
 
 constexpr int kSBlock = 256;
-constexpr uint64_t kMaxChunk = 1ull << 22;
-constexpr int kKeyCap = 1024;      // longest list of the LDS-staged wavefront ListCount
-constexpr int kFastWaves = 5120;   // its wavefronts (one prefix-sum scratch slice each)
-constexpr int kWideCap = 65536;    // longest list of the global-memory wavefront ListCount
-constexpr int kWideWaves = 64;     // its wavefronts
+constexpr int kSWaves = kSBlock / kWave;
+constexpr int kLiBits = 22;  // local sample index bits of an item code
+constexpr int kKeyCap = 1024;
+constexpr int kWideCap = 65536;
+constexpr int kWideWaves = 64;
+constexpr int kMaxFastWaves = 8192;
 
-struct SampleArgs {
-  // graph
-  const uint32_t* out_off;
-  const int32_t* out_src;
-  const int32_t* out_dst;
-  const int32_t* out_eid;
-  const int64_t* out_t;
-  const int32_t* in_src;
-  const int32_t* in_eid;
-  const int64_t* in_t;
-  const int32_t* pair_dst;
-  const int64_t* pair_t;
-  const PairSlot* pair_hash;
-  int32_t pair_hash_log2;
-  // weights
+struct DeltaArgs {
   const uint32_t* lo_in;
   const uint32_t* a;
   const uint32_t* lo_out;
   const uint32_t* b;
   const uint64_t* S;
   const uint64_t* tree;  // levels 1.. of the search tree over S
-  uint64_t tree_off[kMaxTreeLevels];
-  int32_t tree_levels;
   const uint32_t* wstatus;
-  int64_t m;
   int64_t delta;
-  // sampling
-  uint64_t k;
-  uint64_t seed;
-  uint64_t i0;
-  uint32_t stream_id;
-  uint64_t c0;     // first sample (0-based, relative to i0) of this chunk
-  uint32_t clen;   // samples in this chunk
-  uint32_t chunk;  // stride of the per-sample window arrays
-  // outputs
   uint64_t* cnt;
   uint64_t* hits;
   uint32_t* status;
@@ -91,24 +66,62 @@ struct SampleArgs {
   int32_t* e2;
   int32_t* e3;
   uint64_t* X;
+};
+
+struct SampleArgs {
+  // graph
+  const int32_t* out_src;
+  const int32_t* out_dst;
+  const int32_t* out_eid;
+  const int64_t* out_t;
+  const int32_t* in_src;
+  const int32_t* in_eid;
+  const int64_t* in_t;
+  const int64_t* pair_t;
+  const PairSlot* pair_hash;
+  int32_t pair_hash_log2;
+  int64_t m;
+  uint64_t tree_off[kMaxTreeLevels];
+  int32_t tree_levels;
+  // deltas
+  int32_t nd;
+  DeltaArgs D[kMaxDeltas];
+  // sampling
+  uint64_t k;
+  uint64_t seed;
+  uint64_t i0;
+  uint32_t stream_id;
+  uint64_t c0;     // first sample (0-based, relative to i0) of this chunk
+  uint32_t clen;   // samples per delta in this chunk
+  uint32_t chunk;  // stride of the per-sample window arrays
+  uint32_t tiles_per_delta;
   // per-chunk scratch
-  uint32_t* win_lo;   // [n_pairs][chunk]
-  uint32_t* win_len;  // [n_pairs][chunk]
-  uint32_t* item_code;  // (local sample index) | (motif << 24)
+  uint32_t* win_lo;   // [nd][kMaxPairs][chunk]
+  uint32_t* win_len;  // [nd][kMaxPairs][chunk]
+  uint32_t* item_code;  // local sample | motif << 22 | delta << 26
   uint32_t* item_count;
-  uint32_t* item_next;  // work counter of the fast wavefront ListCount
-  uint32_t* mid_code;   // items with a list longer than the register ListCount holds
+  uint32_t* item_next;
+  uint32_t* mid_code;
   uint32_t* mid_count;
-  uint32_t* wide_code;  // items with a list longer than kKeyCap
+  uint32_t* wide_code;
   uint32_t* wide_count;
   uint32_t* wide_next;
-  uint32_t* big_code;   // items with a list longer than kWideCap
+  uint32_t* big_code;
   uint32_t* big_count;
-  uint64_t* fast_p;     // [kFastWaves][2][kKeyCap + 1]
-  uint64_t* wide_p;     // [kWideWaves][2][kWideCap + 1]
-  uint32_t item_cap;
+  uint64_t* fast_p;  // [fast waves][2][kKeyCap + 1]
+  uint64_t* wide_p;  // [kWideWaves][2][kWideCap + 1]
   MotifPlan plan;
 };
+
+__device__ __forceinline__ uint64_t win_index(const SampleArgs& A, int d, int q, uint32_t li) {
+  return ((uint64_t)d * kMaxPairs + q) * A.chunk + li;
+}
+
+__device__ __forceinline__ void decode(uint32_t code, uint32_t* li, int* j, int* d) {
+  *li = code & ((1u << kLiBits) - 1);
+  *j = (int)((code >> kLiBits) & 15u);
+  *d = (int)(code >> (kLiBits + 4));
+}
 
 // [lo, hi) positions in the pair index of edges va -> vb with time in (t_lo, t_hi]
 __device__ __forceinline__ void pair_window(const SampleArgs& A, int32_t va, int32_t vb,
@@ -126,55 +139,12 @@ __device__ __forceinline__ int32_t slot_vertex(int s, int32_t x, int32_t u, int3
   return s == 0 ? x : (s == 1 ? u : (s == 2 ? v : y));
 }
 
-__device__ __forceinline__ void accumulate(uint64_t* s_acc, uint32_t* s_hit, const SampleArgs& A,
-                                           int j, int tid, uint64_t X) {
-  const uint64_t old = s_acc[j * kSBlock + tid];
-  const uint64_t nv = old + X;
-  if (nv < old) atomicAdd((unsigned long long*)&A.cnt[2 * j + 1], 1ull);
-  s_acc[j * kSBlock + tid] = nv;
-  s_hit[j * kSBlock + tid] += (X != 0);
-}
-
-// block reduction of the per-thread sums, then one set of atomics per block
-__device__ void flush_block(const uint64_t* s_acc, const uint32_t* s_hit, uint64_t* s_red,
-                            const SampleArgs& A, int nm, uint32_t st_bits) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int nw = kSBlock / kWave;
-  for (int j = 0; j < nm; ++j) {
-    const U128 s = wave_sum128(U128{s_acc[j * kSBlock + tid], 0});
-    const uint64_t h = wave_sum64((uint64_t)s_hit[j * kSBlock + tid]);
-    if (lane == 0) {
-      s_red[(j * nw + wave) * 3 + 0] = s.lo;
-      s_red[(j * nw + wave) * 3 + 1] = s.hi;
-      s_red[(j * nw + wave) * 3 + 2] = h;
-    }
-  }
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) st_bits |= __shfl_xor(st_bits, off, kWave);
-  if (lane == 0 && st_bits) atomicOr(A.status, st_bits);
-  __syncthreads();
-  if (tid < nm) {
-    const int j = tid;
-    U128 s{0, 0};
-    uint64_t h = 0;
-    for (int w = 0; w < nw; ++w) {
-      s = add128(s, U128{s_red[(j * nw + w) * 3 + 0], s_red[(j * nw + w) * 3 + 1]});
-      h += s_red[(j * nw + w) * 3 + 2];
-    }
-    if (s.lo | s.hi) {
-      const uint64_t old = atomicAdd((unsigned long long*)&A.cnt[2 * j], (unsigned long long)s.lo);
-      const uint64_t carry = (old + s.lo < old) ? 1ull : 0ull;
-      if (s.hi + carry) atomicAdd((unsigned long long*)&A.cnt[2 * j + 1], s.hi + carry);
-    }
-    if (h) atomicAdd((unsigned long long*)&A.hits[j], (unsigned long long)h);
-  }
-}
-
 // upper_bound(S, r) - 1 through the 16-ary tree: one 128-byte node per level
-__device__ __forceinline__ uint32_t tree_search(const SampleArgs& A, uint64_t r) {
+__device__ __forceinline__ uint32_t tree_search(const SampleArgs& A, const DeltaArgs& D,
+                                                uint64_t r) {
   uint64_t i = 0;
   for (int L = A.tree_levels; L >= 0; --L) {
-    const uint64_t* lvl = (L == 0) ? A.S : A.tree + A.tree_off[L];
+    const uint64_t* lvl = (L == 0) ? D.S : D.tree + A.tree_off[L];
     const uint64_t node = (L == A.tree_levels) ? 0 : i;
     const ulonglong2* nd = reinterpret_cast<const ulonglong2*>(lvl + 16 * node);
     uint32_t cnt = 0;
@@ -188,116 +158,173 @@ __device__ __forceinline__ uint32_t tree_search(const SampleArgs& A, uint64_t r)
   return (uint32_t)i;
 }
 
+// ---- per-block sums of (delta, motif) and their flush -------------------------
+// Dynamic LDS: slot (w, d, j) at w * nd * nm + d * nm + j for NW wavefronts.
+struct BlockSums {
+  uint64_t lo, hi, hits;
+};
+extern __shared__ BlockSums s_dyn_sums[];
+
+__host__ __device__ inline size_t sums_bytes(int nw, int nd, int nm) {
+  return (size_t)nw * nd * nm * sizeof(BlockSums);
+}
+
+__device__ __forceinline__ BlockSums* sums_slot(const SampleArgs& A, int w, int d, int j) {
+  const int nm = A.plan.n_motifs;
+  return &s_dyn_sums[(w * A.nd + d) * nm + j];
+}
+
+template <int NW>
+__device__ __forceinline__ void sums_clear(const SampleArgs& A) {
+  for (int i = threadIdx.x; i < NW * A.nd * A.plan.n_motifs; i += blockDim.x)
+    s_dyn_sums[i] = BlockSums{0, 0, 0};
+}
+
+__device__ __forceinline__ void sums_add(BlockSums* p, U128 v, uint64_t h) {
+  const U128 r = add128(U128{p->lo, p->hi}, v);
+  p->lo = r.lo;
+  p->hi = r.hi;
+  p->hits += h;
+}
+
+// after a barrier: thread (d, j) adds the slots of all wavefronts to the outputs
+template <int NW>
+__device__ void sums_flush(const SampleArgs& A) {
+  const int nm = A.plan.n_motifs;
+  for (int i = threadIdx.x; i < A.nd * nm; i += blockDim.x) {
+    const int d = i / nm, j = i - d * nm;
+    U128 sum{0, 0};
+    uint64_t h = 0;
+    for (int w = 0; w < NW; ++w) {
+      const BlockSums* p = sums_slot(A, w, d, j);
+      sum = add128(sum, U128{p->lo, p->hi});
+      h += p->hits;
+    }
+    uint64_t* cnt = A.D[d].cnt;
+    if (sum.lo | sum.hi) {
+      const uint64_t old = atomicAdd((unsigned long long*)&cnt[2 * j], (unsigned long long)sum.lo);
+      const uint64_t carry = (old + sum.lo < old) ? 1ull : 0ull;
+      if (sum.hi + carry) atomicAdd((unsigned long long*)&cnt[2 * j + 1], sum.hi + carry);
+    }
+    if (h) atomicAdd((unsigned long long*)&A.D[d].hits[j], (unsigned long long)h);
+  }
+}
+
+__device__ __forceinline__ void flag_status(const SampleArgs& A, int d, uint32_t bits) {
+  if (bits) atomicOr(A.D[d].status, bits);
+}
+
+// ---- paths ------------------------------------------------------------------
 struct PathRec {
   int32_t x, u, v, y;
   int64_t t1, t3;
   uint32_t li;
 };
 
-template <int NM>
 __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
-  constexpr int nw = kSBlock / kWave;
-  __shared__ uint64_t s_red[NM * nw * 3];
   __shared__ PathRec s_path[kSBlock];
   __shared__ uint32_t s_nvalid;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int nm = A.plan.n_motifs;
   const int np = A.plan.n_pairs;
-  const uint64_t W = A.S[A.m];
-  const int wave = tid >> 6;
-  if (tid == 0) s_nvalid = 0;
-  __syncthreads();
-  uint32_t st_bits = 0;
-  const uint32_t li = blockIdx.x * kSBlock + tid;  // sample index inside the chunk
-  const bool active = li < A.clen && *A.wstatus == 0;
-  const uint64_t ii = A.c0 + li;                    // output index
-  bool valid = false;
-  int32_t x = 0, u = 0, v = 0, y = 0;
-  int64_t t1 = 0, t3 = 0;
-  if (active) {
-    if (W == 0) {
-      if (A.e1) {
-        A.e1[ii] = -1;
-        A.e2[ii] = -1;
-        A.e3[ii] = -1;
+  sums_clear<kSWaves>(A);
+  const uint32_t n_units = A.tiles_per_delta * (uint32_t)A.nd;
+  for (uint32_t unit = blockIdx.x; unit < n_units; unit += gridDim.x) {
+    const int d = (int)(unit / A.tiles_per_delta);
+    const uint32_t tile = unit - (uint32_t)d * A.tiles_per_delta;
+    const DeltaArgs& D = A.D[d];
+    const uint64_t W = D.S[A.m];
+    __syncthreads();  // the previous unit's LDS use is over
+    if (tid == 0) s_nvalid = 0;
+    __syncthreads();
+    uint32_t st_bits = 0;
+    const uint32_t li = tile * kSBlock + tid;  // sample index inside the chunk
+    const bool active = li < A.clen && *D.wstatus == 0;
+    const uint64_t ii = A.c0 + li;  // output index
+    bool valid = false;
+    int32_t x = 0, u = 0, v = 0, y = 0;
+    int64_t t1 = 0, t3 = 0;
+    if (active) {
+      if (W == 0) {
+        if (D.e1) {
+          D.e1[ii] = -1;
+          D.e2[ii] = -1;
+          D.e3[ii] = -1;
+        }
+        if (D.X)
+          for (int j = 0; j < nm; ++j) D.X[(uint64_t)j * A.k + ii] = 0;
+      } else {
+        const uint64_t i = A.i0 + ii;  // counter of the random stream
+        const Words4 blk0 = philox_block(A.seed, A.stream_id, i, 0);
+        uint64_t r;
+        bool ok = range64((uint64_t)blk0.x0 | ((uint64_t)blk0.x1 << 32), W, &r);
+        for (uint32_t att = 1; !ok && att < kMaxAttempts; ++att) {
+          const Words4 bk = philox_block(A.seed, A.stream_id, i, att);
+          ok = range64((uint64_t)bk.x0 | ((uint64_t)bk.x1 << 32), W, &r);
+        }
+        if (!ok) {
+          st_bits |= TC_F_RNG;
+          r = 0;
+        }
+        const uint32_t p = tree_search(A, D, r);  // S[p] <= r < S[p+1]
+        const uint32_t ap = D.a[p], bp = D.b[p];
+        uint32_t j1, j3;
+        ok = range32(blk0.x2, ap, &j1);
+        for (uint32_t att = 1; !ok && att < kMaxAttempts; ++att)
+          ok = range32(philox_block(A.seed, A.stream_id, i, att).x2, ap, &j1);
+        if (!ok) {
+          st_bits |= TC_F_RNG;
+          j1 = 0;
+        }
+        ok = range32(blk0.x3, bp, &j3);
+        for (uint32_t att = 1; !ok && att < kMaxAttempts; ++att)
+          ok = range32(philox_block(A.seed, A.stream_id, i, att).x3, bp, &j3);
+        if (!ok) {
+          st_bits |= TC_F_RNG;
+          j3 = 0;
+        }
+        u = A.out_src[p];
+        v = A.out_dst[p];
+        const int64_t t2 = A.out_t[p];
+        const uint32_t q1 = D.lo_in[p] + j1;
+        const uint32_t q3 = D.lo_out[p] + j3;
+        x = A.in_src[q1];
+        t1 = A.in_t[q1];
+        y = A.out_dst[q3];
+        t3 = A.out_t[q3];
+        if (D.e1) {
+          D.e1[ii] = A.in_eid[q1];
+          D.e2[ii] = A.out_eid[p];
+          D.e3[ii] = A.out_eid[q3];
+        }
+        valid = x != u && x != v && x != y && u != v && u != y && v != y && t1 < t2 &&
+                t2 < t3 && (t3 - t1) <= D.delta;
       }
-      if (A.X)
-        for (int j = 0; j < nm; ++j) A.X[(uint64_t)j * A.k + ii] = 0;
-    } else {
-      const uint64_t i = A.i0 + ii;  // counter of the random stream
-      const Words4 blk0 = philox_block(A.seed, A.stream_id, i, 0);
-      uint64_t r;
-      bool ok = range64((uint64_t)blk0.x0 | ((uint64_t)blk0.x1 << 32), W, &r);
-      for (uint32_t att = 1; !ok && att < kMaxAttempts; ++att) {
-        const Words4 bk = philox_block(A.seed, A.stream_id, i, att);
-        ok = range64((uint64_t)bk.x0 | ((uint64_t)bk.x1 << 32), W, &r);
-      }
-      if (!ok) {
-        st_bits |= TC_F_RNG;
-        r = 0;
-      }
-      // p with S[p] <= r < S[p+1]
-      const uint32_t p = tree_search(A, r);
-      const uint32_t ap = A.a[p], bp = A.b[p];
-      uint32_t j1, j3;
-      ok = range32(blk0.x2, ap, &j1);
-      for (uint32_t att = 1; !ok && att < kMaxAttempts; ++att)
-        ok = range32(philox_block(A.seed, A.stream_id, i, att).x2, ap, &j1);
-      if (!ok) {
-        st_bits |= TC_F_RNG;
-        j1 = 0;
-      }
-      ok = range32(blk0.x3, bp, &j3);
-      for (uint32_t att = 1; !ok && att < kMaxAttempts; ++att)
-        ok = range32(philox_block(A.seed, A.stream_id, i, att).x3, bp, &j3);
-      if (!ok) {
-        st_bits |= TC_F_RNG;
-        j3 = 0;
-      }
-      u = A.out_src[p];
-      v = A.out_dst[p];
-      const int64_t t2 = A.out_t[p];
-      const uint32_t q1 = A.lo_in[p] + j1;
-      const uint32_t q3 = A.lo_out[p] + j3;
-      x = A.in_src[q1];
-      t1 = A.in_t[q1];
-      y = A.out_dst[q3];
-      t3 = A.out_t[q3];
-      if (A.e1) {
-        A.e1[ii] = A.in_eid[q1];
-        A.e2[ii] = A.out_eid[p];
-        A.e3[ii] = A.out_eid[q3];
-      }
-      valid = x != u && x != v && x != y && u != v && u != y && v != y && t1 < t2 && t2 < t3 &&
-              (t3 - t1) <= A.delta;
     }
-  }
-  // compact the accepted paths of the block into LDS
-  {
-    const uint64_t mask = __ballot(valid);
-    uint32_t base = 0;
-    if (lane == 0 && mask) base = atomicAdd(&s_nvalid, (uint32_t)__popcll(mask));
-    base = __shfl(base, 0, kWave);
-    if (valid) s_path[base + __popcll(mask & lt_mask)] = PathRec{x, u, v, y, t1, t3, li};
-  }
-  __syncthreads();
-  // one (path, pair) window per task, spread over the block
-  const uint32_t nvalid = s_nvalid;
-  for (uint32_t task = tid; task < nvalid * (uint32_t)np; task += kSBlock) {
-    const uint32_t q = task / nvalid, sidx = task - q * nvalid;
-    const PathRec P = s_path[sidx];
-    uint32_t lo, hi;
-    pair_window(A, slot_vertex(A.plan.pair_a[q], P.x, P.u, P.v, P.y),
-                slot_vertex(A.plan.pair_b[q], P.x, P.u, P.v, P.y), P.t3, P.t1 + A.delta, &lo,
-                &hi);
-    A.win_lo[(uint64_t)q * A.chunk + P.li] = lo;
-    A.win_len[(uint64_t)q * A.chunk + P.li] = hi - lo;
-  }
-  __threadfence_block();
-  __syncthreads();
-  {
+    // compact the accepted paths of the tile into LDS
+    {
+      const uint64_t mask = __ballot(valid);
+      uint32_t base = 0;
+      if (lane == 0 && mask) base = atomicAdd(&s_nvalid, (uint32_t)__popcll(mask));
+      base = __shfl(base, 0, kWave);
+      if (valid) s_path[base + __popcll(mask & lt_mask)] = PathRec{x, u, v, y, t1, t3, li};
+    }
+    __syncthreads();
+    // one (path, pair) window per task, spread over the block
+    const uint32_t nvalid = s_nvalid;
+    for (uint32_t task = tid; task < nvalid * (uint32_t)np; task += kSBlock) {
+      const uint32_t q = task / nvalid, sidx = task - q * nvalid;
+      const PathRec P = s_path[sidx];
+      uint32_t lo, hi;
+      pair_window(A, slot_vertex(A.plan.pair_a[q], P.x, P.u, P.v, P.y),
+                  slot_vertex(A.plan.pair_b[q], P.x, P.u, P.v, P.y), P.t3, P.t1 + D.delta,
+                  &lo, &hi);
+      A.win_lo[win_index(A, d, q, P.li)] = lo;
+      A.win_len[win_index(A, d, q, P.li)] = hi - lo;
+    }
+    __threadfence_block();
+    __syncthreads();
     for (int j = 0; j < nm; ++j) {
       const int l = A.plan.n_lists[j];
       uint64_t X = 0;
@@ -306,71 +333,53 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
         if (l == 0) {
           X = 1;
         } else if (l == 1) {
-          X = A.win_len[(uint64_t)A.plan.list_pair[j][0] * A.chunk + li];
+          X = A.win_len[win_index(A, d, A.plan.list_pair[j][0], li)];
         } else {
           // an empty list gives 0 unless the lists before it could already
           // hold 2^64 chains (then the count must run to flag it)
           uint64_t prod = 1;
           bool empty = false, big = false;
           for (int r = 0; r < l; ++r) {
-            const uint32_t len = A.win_len[(uint64_t)A.plan.list_pair[j][r] * A.chunk + li];
+            const uint32_t len = A.win_len[win_index(A, d, A.plan.list_pair[j][r], li)];
             if (len == 0) empty = true;
             if (!empty && __builtin_mul_overflow(prod, (uint64_t)len, &prod)) big = true;
           }
           if (!empty || big) defer = true;
         }
       }
-      // one queue reservation per wave
+      // one queue reservation per wavefront
       const uint64_t mask = __ballot(defer);
       if (mask) {
         const int leader = __ffsll((long long)mask) - 1;
         uint32_t base = 0;
         if (lane == leader) base = atomicAdd(A.item_count, (uint32_t)__popcll(mask));
         base = __shfl(base, leader, kWave);
-        if (defer) {
-          const uint32_t slot = base + (uint32_t)__popcll(mask & lt_mask);
-          A.item_code[slot] = li | ((uint32_t)j << 24);
-        }
+        if (defer)
+          A.item_code[base + (uint32_t)__popcll(mask & lt_mask)] =
+              li | ((uint32_t)j << kLiBits) | ((uint32_t)d << (kLiBits + 4));
       }
-      if (active && W != 0 && !defer && A.X) A.X[(uint64_t)j * A.k + ii] = X;
-      // this sample's resolved count goes straight into the block sums
+      if (active && W != 0 && !defer && D.X) D.X[(uint64_t)j * A.k + ii] = X;
       const U128 sx = wave_sum128(U128{defer ? 0ull : X, 0});
       const uint64_t h = wave_sum64((!defer && X != 0) ? 1ull : 0ull);
-      if (lane == 0) {
-        s_red[(j * nw + wave) * 3 + 0] = sx.lo;
-        s_red[(j * nw + wave) * 3 + 1] = sx.hi;
-        s_red[(j * nw + wave) * 3 + 2] = h;
-      }
+      if (lane == 0) sums_add(sums_slot(A, wave, d, j), sx, h);
     }
-  }
 #pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) st_bits |= __shfl_xor(st_bits, off, kWave);
-  if (lane == 0 && st_bits) atomicOr(A.status, st_bits);
-  __syncthreads();
-  if (tid < nm) {
-    const int j = tid;
-    U128 sum{0, 0};
-    uint64_t hh = 0;
-    for (int w = 0; w < nw; ++w) {
-      sum = add128(sum, U128{s_red[(j * nw + w) * 3 + 0], s_red[(j * nw + w) * 3 + 1]});
-      hh += s_red[(j * nw + w) * 3 + 2];
-    }
-    if (sum.lo | sum.hi) {
-      const uint64_t old = atomicAdd((unsigned long long*)&A.cnt[2 * j], (unsigned long long)sum.lo);
-      const uint64_t carry = (old + sum.lo < old) ? 1ull : 0ull;
-      if (sum.hi + carry) atomicAdd((unsigned long long*)&A.cnt[2 * j + 1], sum.hi + carry);
-    }
-    if (hh) atomicAdd((unsigned long long*)&A.hits[j], (unsigned long long)hh);
+    for (int off = 1; off < kWave; off <<= 1) st_bits |= __shfl_xor(st_bits, off, kWave);
+    if (lane == 0) flag_status(A, d, st_bits);
   }
+  __syncthreads();
+  sums_flush<kSWaves>(A);
 }
 
+// ---- ListCount ----------------------------------------------------------------
 // Number of strictly increasing chains through lists 0..l-1 (pair-index
-// ranges [ptr, end)), by the merged sweep described at the top.
+// ranges [ptr, end)) by a merged sweep in time order: f[r] counts chains
+// ending in list r at times seen so far; a group of c equal times at the head
+// of list r adds c * f[r-1] (f[-1] = 1), lists taken last to first so equal
+// times never chain.
 template <int ML, bool CHECKED>
 __device__ uint64_t sweep(const int64_t* __restrict__ pair_t, uint32_t (&ptr)[ML],
                           const uint32_t (&end)[ML], int l, bool* overflow) {
-  // head[r] is the first unconsumed time of list r and nxt[r] the one after
-  // it, loaded one step ahead so the sweep rarely waits on memory.
   const int64_t kNone = INT64_MAX;
   int64_t head[ML], nxt[ML];
   uint64_t f[ML];
@@ -413,43 +422,41 @@ __device__ uint64_t sweep(const int64_t* __restrict__ pair_t, uint32_t (&ptr)[ML
   return X;
 }
 
-// Register-resident ListCount, one wavefront per item (64-thread blocks),
-// for items whose lists all have at most 64 * CH entries and whose window is
-// shorter than 2^32.  All keys are staged once in LDS as 32-bit offsets from
-// the smallest head; lane q of chunk h holds entry 64 h + q of the current
-// level.  Per level: the LDS binary search gives pos = #{L_{r-1} < key}, the
-// value P_{r-1}[pos] is fetched from the lane that holds prefix entry pos - 1
-// (ds_bpermute), and a wavefront scan with a carry across chunks gives P_r.
-// Items are taken in a fixed stride; others go to the next queue.
-constexpr int kRegKeys = 2048;  // keys staged per item by the register ListCount
-template <int NM, int CH>
-__global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A,
-                                                         const uint32_t* __restrict__ in_code,
-                                                         const uint32_t* __restrict__ in_count,
-                                                         uint32_t* fwd_code, uint32_t* fwd_count) {
+// record one item's count (lane 0 of a one-wavefront block)
+__device__ __forceinline__ void item_done(const SampleArgs& A, int d, int j, uint32_t li,
+                                          uint64_t X) {
+  if (A.D[d].X) A.D[d].X[(uint64_t)j * A.k + A.c0 + li] = X;
+  sums_add(sums_slot(A, 0, d, j), U128{X, 0}, X != 0 ? 1ull : 0ull);
+}
+
+// Register-resident wavefront ListCount (64-thread blocks) for items whose
+// lists all have at most 64 * CH entries and whose window is shorter than
+// 2^32.  Keys are staged once in LDS as 32-bit offsets from the smallest
+// head; lane q of chunk h holds entry 64 h + q of the current level.  Per
+// level: an LDS binary search gives pos = #{L_{r-1} < key}, P_{r-1}[pos] comes
+// from the lane holding prefix entry pos - 1, and a wavefront scan with a
+// carry across chunks gives P_r.
+constexpr int kRegKeys = 2048;
+template <int CH>
+__global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A) {
   __shared__ uint32_t s_key[kRegKeys];
-  __shared__ uint64_t s_acc[NM];
-  __shared__ uint64_t s_hits[NM];
   const int lane = threadIdx.x;
-  const int nm = A.plan.n_motifs;
-  if (lane < NM) {
-    s_acc[lane] = 0;
-    s_hits[lane] = 0;
-  }
-  uint32_t st_bits = 0;
-  const uint32_t n_items = *in_count;
-  const bool narrow_window = A.delta < ((int64_t)1 << 32);
+  sums_clear<1>(A);
+  uint32_t st_bits = 0;  // bit d of st_dmask: delta d overflowed
+  uint32_t st_dmask = 0;
+  const uint32_t n_items = *A.item_count;
   for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
-    const uint32_t code = in_code[it];
-    const uint32_t li = code & 0xFFFFFFu;
-    const int j = (int)(code >> 24);
+    const uint32_t code = A.item_code[it];
+    uint32_t li;
+    int j, d;
+    decode(code, &li, &j, &d);
     const int l = A.plan.n_lists[j];
     uint32_t my_lo = 0, my_len = 0;
     int64_t my_first = INT64_MAX;
     if (lane < l) {
-      const uint64_t q = A.plan.list_pair[j][lane];
-      my_lo = A.win_lo[q * A.chunk + li];
-      my_len = A.win_len[q * A.chunk + li];
+      const uint64_t wi = win_index(A, d, A.plan.list_pair[j][lane], li);
+      my_lo = A.win_lo[wi];
+      my_len = A.win_len[wi];
       if (my_len) my_first = A.pair_t[my_lo];
     }
     uint32_t maxlen = my_len;
@@ -465,8 +472,9 @@ __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A,
     const uint32_t incl = wave_inclusive_scan(my_len);
     const uint32_t my_off = incl - my_len;
     const uint32_t total_keys = __shfl(incl, kWave - 1, kWave);
-    if (maxlen > (uint32_t)(kWave * CH) || total_keys > (uint32_t)kRegKeys || !narrow_window) {
-      if (lane == 0) fwd_code[atomicAdd(fwd_count, 1u)] = code;
+    if (maxlen > (uint32_t)(kWave * CH) || total_keys > (uint32_t)kRegKeys ||
+        A.D[d].delta >= ((int64_t)1 << 32)) {
+      if (lane == 0) A.mid_code[atomicAdd(A.mid_count, 1u)] = code;
       continue;
     }
     for (int r = 0; r < l; ++r) {
@@ -479,7 +487,7 @@ __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A,
       }
     }
     __threadfence_block();
-    uint64_t P[CH];  // P[h] on lane q: inclusive prefix through entry 64 h + q
+    uint64_t P[CH];  // P[h] on lane q: prefix through entry 64 h + q
 #pragma unroll
     for (int h = 0; h < CH; ++h) P[h] = (uint64_t)(h * kWave + lane + 1);  // level 0: all ones
     U128 total{0, 0};
@@ -497,8 +505,7 @@ __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A,
         const bool act = i < len;
         uint32_t pos = 0;
         if (act) pos = lower_bound<uint32_t>(kprev, 0u, prev_len, kcur[i]);
-        // P_{r-1}[pos] lives on lane (pos - 1) & 63 of chunk (pos - 1) >> 6
-        const uint32_t q = pos - 1;
+        const uint32_t q = pos - 1;  // prefix entry pos - 1: lane q & 63 of chunk q >> 6
         const int src = (int)(q & 63u);
         const uint32_t hsrc = q >> 6;
         uint64_t c = 0;
@@ -514,38 +521,28 @@ __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A,
         total = add128(total, wave_sum128(U128{c, 0}));
         carry += __shfl(inc, kWave - 1, kWave);
       }
-      if (total.hi != 0) st_bits |= TC_F_OVERFLOW;
+      if (total.hi != 0) {
+        st_bits = TC_F_OVERFLOW;
+        st_dmask |= 1u << d;
+      }
 #pragma unroll
       for (int h = 0; h < CH; ++h) P[h] = Pn[h];
     }
-    const uint64_t X = total.lo;
-    if (lane == 0) {
-      if (A.X) A.X[(uint64_t)j * A.k + A.c0 + li] = X;
-      const uint64_t old = s_acc[j];
-      const uint64_t nv = old + X;
-      if (nv < old) atomicAdd((unsigned long long*)&A.cnt[2 * j + 1], 1ull);
-      s_acc[j] = nv;
-      s_hits[j] += (X != 0);
-    }
+    if (lane == 0) item_done(A, d, j, li, total.lo);
     __threadfence_block();
   }
-  if (lane == 0) {
-    for (int j = 0; j < nm; ++j) {
-      if (s_acc[j]) atomicAdd((unsigned long long*)&A.cnt[2 * j], (unsigned long long)s_acc[j]);
-      if (s_hits[j]) atomicAdd((unsigned long long*)&A.hits[j], (unsigned long long)s_hits[j]);
-    }
-  }
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) st_bits |= __shfl_xor(st_bits, off, kWave);
-  if (lane == 0 && st_bits) atomicOr(A.status, st_bits);
+  __syncthreads();
+  sums_flush<1>(A);
+  if (lane == 0)
+    for (int d = 0; d < A.nd; ++d)
+      if (st_dmask & (1u << d)) flag_status(A, d, st_bits);
 }
 
-// One wavefront per item (64-thread blocks).  FAST keeps the keys of the
-// previous and the current list in LDS as 32-bit offsets from the smallest
-// head, so the searches are LDS probes (lists up to kKeyCap entries, window
-// length below 2^32); otherwise the searches read the pair index directly
-// (lists up to kWideCap).  Items over the limit go to the next queue.
-template <int NM, bool FAST>
+// The level recursion with prefix sums in per-wavefront scratch (64-thread
+// blocks).  FAST keeps the keys of the previous and the current list in LDS
+// (lists up to kKeyCap, window below 2^32); otherwise the searches read the
+// pair index (lists up to kWideCap).  Items over the limit go to `fwd`.
+template <bool FAST>
 __global__ __launch_bounds__(kWave) void k_listcount_wave(SampleArgs A,
                                                           const uint32_t* __restrict__ in_code,
                                                           const uint32_t* __restrict__ in_count,
@@ -553,37 +550,28 @@ __global__ __launch_bounds__(kWave) void k_listcount_wave(SampleArgs A,
                                                           uint32_t* fwd_count, uint64_t* pscratch,
                                                           uint32_t cap) {
   __shared__ uint32_t s_key[2][FAST ? kKeyCap : 1];
-  __shared__ uint64_t s_acc[NM];
-  __shared__ uint64_t s_hits[NM];
-  // this wavefront's two prefix-sum buffers (L2-resident; written then read
-  // by the same wavefront, ordered by a workgroup fence between levels)
   uint64_t* s_p[2] = {pscratch + (uint64_t)blockIdx.x * 2 * (cap + 1),
                       pscratch + ((uint64_t)blockIdx.x * 2 + 1) * (cap + 1)};
   const int lane = threadIdx.x;
-  const int nm = A.plan.n_motifs;
-  if (lane < NM) {
-    s_acc[lane] = 0;
-    s_hits[lane] = 0;
-  }
-  uint32_t st_bits = 0;
+  sums_clear<1>(A);
+  uint32_t st_dmask = 0;
   const uint32_t n_items = *in_count;
-  const bool narrow_window = A.delta < ((int64_t)1 << 32);
   while (true) {
     uint32_t it = 0;
     if (lane == 0) it = atomicAdd(in_next, 1u);
     it = __shfl(it, 0, kWave);
     if (it >= n_items) break;
     const uint32_t code = in_code[it];
-    const uint32_t li = code & 0xFFFFFFu;
-    const int j = (int)(code >> 24);
+    uint32_t li;
+    int j, d;
+    decode(code, &li, &j, &d);
     const int l = A.plan.n_lists[j];
-    // lane r < l holds list r's window and its first time
     uint32_t my_lo = 0, my_len = 0;
     int64_t my_first = INT64_MAX;
     if (lane < l) {
-      const uint64_t q = A.plan.list_pair[j][lane];
-      my_lo = A.win_lo[q * A.chunk + li];
-      my_len = A.win_len[q * A.chunk + li];
+      const uint64_t wi = win_index(A, d, A.plan.list_pair[j][lane], li);
+      my_lo = A.win_lo[wi];
+      my_len = A.win_len[wi];
       if (FAST && my_len) my_first = A.pair_t[my_lo];
     }
     uint32_t maxlen = my_len;
@@ -595,12 +583,11 @@ __global__ __launch_bounds__(kWave) void k_listcount_wave(SampleArgs A,
       const int64_t b = __shfl_xor(base, off, kWave);
       base = b < base ? b : base;
     }
-    if (maxlen > cap || (FAST && !narrow_window)) {
+    if (maxlen > cap || (FAST && A.D[d].delta >= ((int64_t)1 << 32))) {
       if (lane == 0) fwd_code[atomicAdd(fwd_count, 1u)] = code;
       continue;
     }
     if (FAST) {
-      // keys of list 0
       const uint32_t lo0 = __shfl(my_lo, 0, kWave), len0 = __shfl(my_len, 0, kWave);
       for (uint32_t i = lane; i < len0; i += kWave)
         s_key[0][i] = (uint32_t)(A.pair_t[lo0 + i] - base);
@@ -641,49 +628,29 @@ __global__ __launch_bounds__(kWave) void k_listcount_wave(SampleArgs A,
         total = add128(total, wave_sum128(U128{c, 0}));
         carry += __shfl(inc, kWave - 1, kWave);
       }
-      if (total.hi != 0) st_bits |= TC_F_OVERFLOW;
+      if (total.hi != 0) st_dmask |= 1u << d;
       pb ^= 1;
       __threadfence_block();
     }
-    const uint64_t X = total.lo;
-    if (lane == 0) {
-      if (A.X) A.X[(uint64_t)j * A.k + A.c0 + li] = X;
-      const uint64_t old = s_acc[j];
-      const uint64_t nv = old + X;
-      if (nv < old) atomicAdd((unsigned long long*)&A.cnt[2 * j + 1], 1ull);
-      s_acc[j] = nv;
-      s_hits[j] += (X != 0);
-    }
+    if (lane == 0) item_done(A, d, j, li, total.lo);
   }
-  if (lane == 0) {
-    for (int j = 0; j < nm; ++j) {
-      if (s_acc[j]) atomicAdd((unsigned long long*)&A.cnt[2 * j], (unsigned long long)s_acc[j]);
-      if (s_hits[j]) atomicAdd((unsigned long long*)&A.hits[j], (unsigned long long)s_hits[j]);
-    }
-  }
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) st_bits |= __shfl_xor(st_bits, off, kWave);
-  if (lane == 0 && st_bits) atomicOr(A.status, st_bits);
+  __syncthreads();
+  sums_flush<1>(A);
+  if (lane == 0)
+    for (int d = 0; d < A.nd; ++d)
+      if (st_dmask & (1u << d)) flag_status(A, d, TC_F_OVERFLOW);
 }
 
 // Items with a list longer than kWideCap: one thread per item.
-template <int NM>
 __global__ __launch_bounds__(kSBlock) void k_listcount_big(SampleArgs A) {
-  __shared__ uint64_t s_acc[NM * kSBlock];
-  __shared__ uint32_t s_hit[NM * kSBlock];
-  __shared__ uint64_t s_red[NM * (kSBlock / kWave) * 3];
-  const int tid = threadIdx.x;
-  const int nm = A.plan.n_motifs;
-  for (int j = 0; j < NM; ++j) {
-    s_acc[j * kSBlock + tid] = 0;
-    s_hit[j * kSBlock + tid] = 0;
-  }
-  uint32_t st_bits = 0;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  sums_clear<kSWaves>(A);
+  __syncthreads();
   const uint32_t n_items = *A.big_count;
   for (uint32_t it = blockIdx.x * kSBlock + tid; it < n_items; it += gridDim.x * kSBlock) {
-    const uint32_t code = A.big_code[it];
-    const uint32_t li = code & 0xFFFFFFu;
-    const int j = (int)(code >> 24);
+    uint32_t li;
+    int j, d;
+    decode(A.big_code[it], &li, &j, &d);
     const int l = A.plan.n_lists[j];
     uint32_t ptr[kMaxLists], end[kMaxLists];
     uint64_t prod = 1;
@@ -693,9 +660,9 @@ __global__ __launch_bounds__(kSBlock) void k_listcount_big(SampleArgs A) {
       ptr[r] = 0;
       end[r] = 0;
       if (r < l) {
-        const uint64_t q = A.plan.list_pair[j][r];
-        ptr[r] = A.win_lo[q * A.chunk + li];
-        const uint32_t len = A.win_len[q * A.chunk + li];
+        const uint64_t wi = win_index(A, d, A.plan.list_pair[j][r], li);
+        ptr[r] = A.win_lo[wi];
+        const uint32_t len = A.win_len[wi];
         end[r] = ptr[r] + len;
         if (__builtin_mul_overflow(prod, (uint64_t)len, &prod)) big = true;
       }
@@ -703,21 +670,36 @@ __global__ __launch_bounds__(kSBlock) void k_listcount_big(SampleArgs A) {
     bool ovf = false;
     const uint64_t X = big ? sweep<kMaxLists, true>(A.pair_t, ptr, end, l, &ovf)
                            : sweep<kMaxLists, false>(A.pair_t, ptr, end, l, &ovf);
-    if (ovf) st_bits |= TC_F_OVERFLOW;
-    if (A.X) A.X[(uint64_t)j * A.k + A.c0 + li] = X;
-    accumulate(s_acc, s_hit, A, j, tid, X);
+    if (ovf) flag_status(A, d, TC_F_OVERFLOW);
+    if (A.D[d].X) A.D[d].X[(uint64_t)j * A.k + A.c0 + li] = X;
+    // few items: this wavefront's slot, updated with LDS atomics
+    BlockSums* slot = sums_slot(A, wave, d, j);
+    atomicAdd((unsigned long long*)&slot->hits, X != 0 ? 1ull : 0ull);
+    const uint64_t old = atomicAdd((unsigned long long*)&slot->lo, (unsigned long long)X);
+    if (old + X < old) atomicAdd((unsigned long long*)&slot->hi, 1ull);
   }
-  flush_block(s_acc, s_hit, s_red, A, nm, st_bits);
+  __syncthreads();
+  sums_flush<kSWaves>(A);
 }
 
-__global__ void k_zero_result(uint64_t* cnt, uint64_t* hits, uint32_t* status, int nm) {
-  const int j = threadIdx.x;
-  if (j < nm) {
-    cnt[2 * j] = 0;
-    cnt[2 * j + 1] = 0;
-    hits[j] = 0;
+__global__ void k_zero_result(SampleArgs A) {
+  const int nm = A.plan.n_motifs;
+  for (int i = threadIdx.x; i < A.nd * nm; i += blockDim.x) {
+    const int d = i / nm, j = i - d * nm;
+    A.D[d].cnt[2 * j] = 0;
+    A.D[d].cnt[2 * j + 1] = 0;
+    A.D[d].hits[j] = 0;
   }
-  if (j == 0) *status = 0;
+  if ((int)threadIdx.x < A.nd) *A.D[threadIdx.x].status = 0;
+}
+
+// estimate output pointers of the deltas, passed by value
+struct EstPtrs {
+  double* p[kMaxDeltas];
+};
+
+__global__ void k_store_ptrs(EstPtrs ep, double** dst) {
+  if (threadIdx.x < kMaxDeltas) dst[threadIdx.x] = ep.p[threadIdx.x];
 }
 
 __global__ void k_zero_counters(uint32_t* p) {
@@ -725,91 +707,92 @@ __global__ void k_zero_counters(uint32_t* p) {
   if (threadIdx.x < 6) p[threadIdx.x] = 0;
 }
 
-// C_hat_j = (cnt_j / k) * W, each integer rounded to nearest-even binary64
-__global__ void k_finalize(const uint64_t* cnt, const uint64_t* S, int64_t m,
-                           const uint32_t* wstatus, uint64_t k, double* est, uint32_t* status,
-                           int nm) {
-  const int j = threadIdx.x;
-  const uint64_t W = S[m];
-  if (j < nm) {
-    const double c = u128_to_double(cnt[2 * j], cnt[2 * j + 1]);
-    est[j] = (W == 0) ? 0.0 : (c / (double)k) * (double)W;
+// C_hat = (cnt / k) * W, each integer rounded to nearest-even binary64
+__global__ void k_finalize(SampleArgs A, double* const* est) {
+  const int nm = A.plan.n_motifs;
+  for (int i = threadIdx.x; i < A.nd * nm; i += blockDim.x) {
+    const int d = i / nm, j = i - d * nm;
+    const uint64_t W = A.D[d].S[A.m];
+    const double c = u128_to_double(A.D[d].cnt[2 * j], A.D[d].cnt[2 * j + 1]);
+    est[d][j] = (W == 0) ? 0.0 : (c / (double)A.k) * (double)W;
   }
-  if (j == 0 && *wstatus) atomicOr(status, *wstatus);
+  __syncthreads();
+  if ((int)threadIdx.x < A.nd && *A.D[threadIdx.x].wstatus)
+    atomicOr(A.D[threadIdx.x].status, *A.D[threadIdx.x].wstatus);
 }
 
 // ------------------------------------------------------------ workspace ----
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-uint64_t sample_chunk(uint64_t k) {
-  uint64_t c = k < kMaxChunk ? k : kMaxChunk;
+SampleTuning default_tuning() {
+  SampleTuning t;
+  t.chunk_log2 = kLiBits;
+  t.path_blocks = 0;
+  t.reg_waves = 5120;
+  t.fast_waves = 5120;
+  return t;
+}
+
+static uint64_t chunk_for(uint64_t k, int nd, const SampleTuning& t) {
+  const int lg = t.chunk_log2 < 10 ? 10 : (t.chunk_log2 > kLiBits ? kLiBits : t.chunk_log2);
+  uint64_t c = (1ull << lg) / (uint64_t)nd;  // all deltas of a chunk within 2^22 samples
+  if (c > k) c = k;
   return c < 1 ? 1 : c;
 }
 
+static int fast_waves_for(const SampleTuning& t) {
+  return t.fast_waves < 64 ? 64 : (t.fast_waves > kMaxFastWaves ? kMaxFastWaves : t.fast_waves);
+}
+
 struct SampleLayout {
-  size_t win_lo, win_len, code, mid, wide, big, counters, fast_p, wide_p, total;
+  size_t win_lo, win_len, code, mid, wide, big, counters, fast_p, wide_p, est_ptrs, total;
   uint64_t chunk, cap;
+  int fast_waves;
 };
 
-static SampleLayout sample_layout(uint64_t k, int32_t n_motifs) {
+static SampleLayout sample_layout(uint64_t k, int nd, int32_t n_motifs, const SampleTuning& t) {
   SampleLayout L;
-  L.chunk = sample_chunk(k);
-  L.cap = L.chunk * (uint64_t)n_motifs;
+  L.chunk = chunk_for(k, nd, t);
+  L.cap = L.chunk * (uint64_t)nd * (uint64_t)n_motifs;
+  L.fast_waves = fast_waves_for(t);
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
     o += align256(bytes ? bytes : 1);
     return at;
   };
-  L.win_lo = take((size_t)kMaxPairs * L.chunk * 4);
-  L.win_len = take((size_t)kMaxPairs * L.chunk * 4);
+  L.win_lo = take((size_t)nd * kMaxPairs * L.chunk * 4);
+  L.win_len = take((size_t)nd * kMaxPairs * L.chunk * 4);
   L.code = take(L.cap * 4);
   L.mid = take(L.cap * 4);
   L.wide = take(L.cap * 4);
   L.big = take(L.cap * 4);
   L.counters = take(32);
-  L.fast_p = take((size_t)kFastWaves * 2 * (kKeyCap + 1) * 8);
+  L.fast_p = take((size_t)L.fast_waves * 2 * (kKeyCap + 1) * 8);
   L.wide_p = take((size_t)kWideWaves * 2 * (kWideCap + 1) * 8);
+  L.est_ptrs = take(kMaxDeltas * sizeof(double*));
   L.total = o;
   return L;
 }
 
-size_t sample_workspace_bytes(uint64_t k, int32_t n_motifs) {
-  return sample_layout(k, n_motifs).total;
+size_t sample_workspace_bytes(uint64_t k, int nd, int32_t n_motifs, const SampleTuning* t) {
+  SampleTuning tt = t ? *t : default_tuning();
+  if (!t) {  // room for any tuning
+    tt.chunk_log2 = kLiBits;
+    tt.fast_waves = kMaxFastWaves;
+  }
+  return sample_layout(k, nd, n_motifs, tt).total;
 }
 
-template <int NM>
-static void launch_chunk(const SampleArgs& A, hipStream_t st) {
-  const unsigned blocks = (unsigned)((A.clen + kSBlock - 1) / kSBlock);
-  hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, A.item_count);
-  {
-    TimedLaunch tl("k_paths", st);
-    hipLaunchKernelGGL(k_paths<NM>, dim3(blocks), dim3(kSBlock), 0, st, A);
-  }
-  // enough wavefronts to fill the chip; each pulls items until the queue is empty
-  {
-    TimedLaunch tl("k_listcount_reg", st);
-    hipLaunchKernelGGL((k_listcount_reg<NM, 4>), dim3(kFastWaves), dim3(kWave), 0, st, A,
-                       (const uint32_t*)A.item_code, (const uint32_t*)A.item_count, A.mid_code,
-                       A.mid_count);
-  }
-  hipLaunchKernelGGL((k_listcount_wave<NM, true>), dim3(kFastWaves), dim3(kWave), 0, st, A,
-                     (const uint32_t*)A.mid_code, (const uint32_t*)A.mid_count, A.item_next,
-                     A.wide_code, A.wide_count, A.fast_p, (uint32_t)kKeyCap);
-  hipLaunchKernelGGL((k_listcount_wave<NM, false>), dim3(kWideWaves), dim3(kWave), 0, st, A,
-                     (const uint32_t*)A.wide_code, (const uint32_t*)A.wide_count, A.wide_next,
-                     A.big_code, A.big_count, A.wide_p, (uint32_t)kWideCap);
-  hipLaunchKernelGGL(k_listcount_big<NM>, dim3(64), dim3(kSBlock), 0, st, A);
-}
-
-tc_status sample_estimate(const tc_graph* g, const tc_weights* w, const MotifPlan& plan,
-                          uint64_t k, uint64_t seed, uint32_t stream_id, uint64_t i0,
-                          tc_result* out, void* ws, size_t ws_bytes, hipStream_t st) {
-  const SampleLayout L = sample_layout(k, plan.n_motifs);
+tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
+                       const MotifPlan& plan, uint64_t k, uint64_t seed, uint32_t stream_id,
+                       uint64_t i0, tc_result* const* out, const SampleTuning& tune, void* ws,
+                       size_t ws_bytes, hipStream_t st) {
+  if (nd < 1 || nd > kMaxDeltas) return TC_E_ARG;
+  const SampleLayout L = sample_layout(k, nd, plan.n_motifs, tune);
   if (!ws || ws_bytes < L.total) return TC_E_WORKSPACE;
   char* base = (char*)ws;
   SampleArgs A;
-  A.out_off = g->out_off;
   A.out_src = g->out_src;
   A.out_dst = g->out_dst;
   A.out_eid = g->out_eid;
@@ -817,39 +800,48 @@ tc_status sample_estimate(const tc_graph* g, const tc_weights* w, const MotifPla
   A.in_src = g->in_src;
   A.in_eid = g->in_eid;
   A.in_t = g->in_t;
-  A.pair_dst = g->pair_dst;
   A.pair_t = g->pair_t;
   A.pair_hash = (const PairSlot*)g->pair_hash;
   A.pair_hash_log2 = g->pair_hash_log2;
-  A.lo_in = w->lo_in;
-  A.a = w->a;
-  A.lo_out = w->lo_out;
-  A.b = w->b;
-  A.S = w->S;
-  A.tree = (const uint64_t*)w->scratch;
+  A.m = g->m;
   {
     const STree T = stree_layout(g->m);
     A.tree_levels = T.levels;
-    for (int L = 0; L < kMaxTreeLevels; ++L) A.tree_off[L] = L <= T.levels ? T.offset[L] : 0;
+    for (int L2 = 0; L2 < kMaxTreeLevels; ++L2) A.tree_off[L2] = L2 <= T.levels ? T.offset[L2] : 0;
   }
-  A.wstatus = w->status;
-  A.m = g->m;
-  A.delta = w->delta;
+  A.nd = nd;
+  double* est_host[kMaxDeltas] = {};
+  for (int d = 0; d < kMaxDeltas; ++d) {
+    DeltaArgs& D = A.D[d];
+    D = DeltaArgs{};
+    if (d >= nd) continue;
+    if (w[d]->m != g->m) return TC_E_ARG;
+    D.lo_in = w[d]->lo_in;
+    D.a = w[d]->a;
+    D.lo_out = w[d]->lo_out;
+    D.b = w[d]->b;
+    D.S = w[d]->S;
+    D.tree = (const uint64_t*)w[d]->scratch;
+    D.wstatus = w[d]->status;
+    D.delta = w[d]->delta;
+    D.cnt = out[d]->cnt;
+    D.hits = out[d]->hits;
+    D.status = out[d]->status;
+    D.e1 = out[d]->e1;
+    D.e2 = out[d]->e2;
+    D.e3 = out[d]->e3;
+    D.X = out[d]->X;
+    est_host[d] = out[d]->estimate;
+  }
   A.k = k;
   A.seed = seed;
   A.i0 = i0;
   A.stream_id = stream_id;
   A.chunk = (uint32_t)L.chunk;
-  A.cnt = out->cnt;
-  A.hits = out->hits;
-  A.status = out->status;
-  A.e1 = out->e1;
-  A.e2 = out->e2;
-  A.e3 = out->e3;
-  A.X = out->X;
   A.win_lo = (uint32_t*)(base + L.win_lo);
   A.win_len = (uint32_t*)(base + L.win_len);
   A.item_code = (uint32_t*)(base + L.code);
+  A.mid_code = (uint32_t*)(base + L.mid);
   A.wide_code = (uint32_t*)(base + L.wide);
   A.big_code = (uint32_t*)(base + L.big);
   A.item_count = (uint32_t*)(base + L.counters);
@@ -857,28 +849,51 @@ tc_status sample_estimate(const tc_graph* g, const tc_weights* w, const MotifPla
   A.wide_count = A.item_count + 2;
   A.wide_next = A.item_count + 3;
   A.big_count = A.item_count + 4;
-  A.mid_code = (uint32_t*)(base + L.mid);
   A.mid_count = A.item_count + 5;
   A.fast_p = (uint64_t*)(base + L.fast_p);
   A.wide_p = (uint64_t*)(base + L.wide_p);
-  A.item_cap = (uint32_t)L.cap;
   A.plan = plan;
+  // the estimate pointers go to the device through a small kernel argument
+  // copy, so the call stays capturable (no host-to-device memcpy)
+  EstPtrs ep;
+  for (int d = 0; d < kMaxDeltas; ++d) ep.p[d] = est_host[d];
+  double** est_dev = (double**)(base + L.est_ptrs);
+  hipLaunchKernelGGL(k_store_ptrs, dim3(1), dim3(kMaxDeltas), 0, st, ep, est_dev);
+  hipLaunchKernelGGL(k_zero_result, dim3(1), dim3(128), 0, st, A);
   const int nm = plan.n_motifs;
-  hipLaunchKernelGGL(k_zero_result, dim3(1), dim3(64), 0, st, out->cnt, out->hits, out->status,
-                     nm);
+  const unsigned reg_waves = (unsigned)(tune.reg_waves < 64 ? 64 : tune.reg_waves);
   for (uint64_t c0 = 0; c0 < k; c0 += L.chunk) {
     A.c0 = c0;
     A.clen = (uint32_t)((k - c0) < L.chunk ? (k - c0) : L.chunk);
-    if (nm == 1)
-      launch_chunk<1>(A, st);
-    else if (nm <= 8)
-      launch_chunk<8>(A, st);
-    else
-      launch_chunk<16>(A, st);
+    A.tiles_per_delta = (A.clen + kSBlock - 1) / kSBlock;
+    const uint32_t units = A.tiles_per_delta * (uint32_t)nd;
+    const unsigned pblocks =
+        (unsigned)((tune.path_blocks > 0 && (uint32_t)tune.path_blocks < units) ? tune.path_blocks
+                                                                                : units);
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, A.item_count);
+    {
+      TimedLaunch tl("k_paths", st);
+      hipLaunchKernelGGL(k_paths, dim3(pblocks), dim3(kSBlock), sums_bytes(kSWaves, nd, nm), st,
+                         A);
+    }
+    if (plan.max_lists >= 2) {
+      {
+        TimedLaunch tl("k_listcount_reg", st);
+        hipLaunchKernelGGL(k_listcount_reg<4>, dim3(reg_waves), dim3(kWave), sums_bytes(1, nd, nm),
+                           st, A);
+      }
+      hipLaunchKernelGGL(k_listcount_wave<true>, dim3((unsigned)L.fast_waves), dim3(kWave),
+                         sums_bytes(1, nd, nm), st, A, (const uint32_t*)A.mid_code, (const uint32_t*)A.mid_count,
+                         A.item_next, A.wide_code, A.wide_count, A.fast_p, (uint32_t)kKeyCap);
+      hipLaunchKernelGGL(k_listcount_wave<false>, dim3(kWideWaves), dim3(kWave),
+                         sums_bytes(1, nd, nm), st, A,
+                         (const uint32_t*)A.wide_code, (const uint32_t*)A.wide_count,
+                         A.wide_next, A.big_code, A.big_count, A.wide_p, (uint32_t)kWideCap);
+      hipLaunchKernelGGL(k_listcount_big, dim3(64), dim3(kSBlock), sums_bytes(kSWaves, nd, nm), st,
+                         A);
+    }
   }
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, (const uint64_t*)out->cnt,
-                     (const uint64_t*)w->S, g->m, (const uint32_t*)w->status, k, out->estimate,
-                     out->status, nm);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(128), 0, st, A, (double* const*)est_dev);
   if (hipGetLastError() != hipSuccess) return TC_E_HIP;
   return TC_OK;
 }
