@@ -26,6 +26,30 @@ def test_philox_known_answers():
         assert oracle.philox4x32_10(v[0:4], v[4:6]) == v[6:10]
 
 
+def _philox_py(ctr, key):
+    """Philox4x32-10 from the description in Salmon et al. (SC 2011): ten
+    rounds of two 32x32->64 products whose halves are mixed with the other
+    two words and the round key; the key is bumped by the two Weyl constants
+    between rounds."""
+    M0, M1, W0, W1, MASK = 0xD2511F53, 0xCD9E8D57, 0x9E3779B9, 0xBB67AE85, 0xFFFFFFFF
+    x0, x1, x2, x3 = ctr
+    k0, k1 = key
+    for rnd in range(10):
+        if rnd:
+            k0, k1 = (k0 + W0) & MASK, (k1 + W1) & MASK
+        p0, p1 = M0 * x0, M1 * x2
+        x0, x1, x2, x3 = ((p1 >> 32) ^ x1 ^ k0, p1 & MASK, (p0 >> 32) ^ x3 ^ k1, p0 & MASK)
+    return [x0, x1, x2, x3]
+
+
+def test_philox_matches_independent_bigint_version():
+    rng = np.random.default_rng(5)
+    for _ in range(300):
+        ctr = [int(v) for v in rng.integers(0, 2**32, size=4)]
+        key = [int(v) for v in rng.integers(0, 2**32, size=2)]
+        assert oracle.philox4x32_10(ctr, key) == _philox_py(ctr, key)
+
+
 @pytest.mark.parametrize("s", [3 * 2**30, 2**32 - 5, 2**31 + 1, 1000003, 2**20 + 7, 7])
 def test_lemire32_every_output_has_equal_preimages(s):
     """Exact uniformity: each output y has exactly floor(2^32 / s) accepted
