@@ -52,6 +52,10 @@ def lib():
         L.or_check_motif.argtypes = [P, P, I64, I32, I32, I32, P]
         L.or_sample.argtypes = [P, I64, P, P, P, P, P, P, ctypes.c_int, U64, U64, U32, U64,
                                 P, P, P, P, P, P, P, ctypes.c_int]
+        L.or_sample_ex.argtypes = [P, I64, P, P, P, P, P, P, P, ctypes.c_int, U64, U64, U32,
+                                   U64, P, P, P, P, P, P, P, P, P, ctypes.c_int]
+        L.or_proposal_scan.argtypes = [P, P, P, P, P]
+        L.or_features.argtypes = [P, I64, P, P, P, P, P, ctypes.c_int]
         L.or_exhaustive.argtypes = [P, P, I64, P, P, P, P, P, P, P, ctypes.c_int]
         L.or_brute_count.argtypes = [P, P, I64, P, ctypes.c_int]
         L.or_list_count.argtypes = [P, P, ctypes.c_int, P]
@@ -111,6 +115,8 @@ class Weights:
     S: np.ndarray
     status: int
 
+    h: np.ndarray | None = None  # proposal h_int per scan position (S is then Q)
+
     @property
     def W(self) -> int:
         return int(self.S[-1])
@@ -126,6 +132,8 @@ class Estimate:
     e2: np.ndarray | None = None
     e3: np.ndarray | None = None
     X: np.ndarray | None = None  # [n_motifs, k]
+    P: np.ndarray | None = None  # [k] scan position of the centre edge
+    m2: np.ndarray | None = None  # [n_motifs] sum of (X / h)^2
 
 
 class OracleGraph:
@@ -183,25 +191,48 @@ class OracleGraph:
 
     def sample(self, w: Weights, motifs, k: int, seed: int, stream: int = 0, i0: int = 0,
                per_sample: bool = False, threads: int | None = None) -> Estimate:
+        """Estimate(M, k); with a proposal weight set (w.h set, from
+        ``proposal``) the importance-sampling estimator."""
         mb = np.frombuffer(b"".join(motifs), dtype=np.uint8).copy()
         nm = len(motifs)
         cnt = np.zeros(2 * nm, np.uint64)
         hits = np.zeros(nm, np.uint64)
         est = np.zeros(nm, np.float64)
-        e1 = e2 = e3 = X = None
+        m2 = np.zeros(nm, np.float64)
+        e1 = e2 = e3 = X = P = None
         null = ctypes.c_void_p(0)
         if per_sample:
             e1 = np.zeros(k, np.int32)
             e2 = np.zeros(k, np.int32)
             e3 = np.zeros(k, np.int32)
             X = np.zeros(nm * k, np.uint64)
-        st = lib().or_sample(self.h, w.delta, _p(w.lo_in), _p(w.a), _p(w.lo_out), _p(w.b),
-                             _p(w.S), _p(mb), nm, int(k), int(seed), int(stream), int(i0),
-                             _p(e1) if per_sample else null, _p(e2) if per_sample else null,
-                             _p(e3) if per_sample else null, _p(X) if per_sample else null,
-                             _p(cnt), _p(hits), _p(est), threads or default_threads())
+            P = np.zeros(k, np.uint32)
+        hq = _p(w.h) if w.h is not None else null
+        st = lib().or_sample_ex(self.h, w.delta, _p(w.lo_in), _p(w.a), _p(w.lo_out), _p(w.b),
+                                _p(w.S), hq, _p(mb), nm, int(k), int(seed), int(stream), int(i0),
+                                _p(e1) if per_sample else null, _p(e2) if per_sample else null,
+                                _p(e3) if per_sample else null, _p(X) if per_sample else null,
+                                _p(P) if per_sample else null, _p(cnt), _p(hits), _p(est),
+                                _p(m2), threads or default_threads())
         c = [int(cnt[2 * j]) | (int(cnt[2 * j + 1]) << 64) for j in range(nm)]
-        return Estimate(c, hits, est, st, e1, e2, e3, None if X is None else X.reshape(nm, k))
+        return Estimate(c, hits, est, st, e1, e2, e3, None if X is None else X.reshape(nm, k),
+                        P, m2)
+
+    def proposal(self, w: Weights, h_int) -> Weights:
+        """Weight set of the proposal q_p = w_p * h_p: same windows, S = the
+        exact scan of q (Q = S[m]), h attached."""
+        h = np.ascontiguousarray(h_int, dtype=np.uint32)
+        assert h.shape[0] == self.m
+        Q = np.zeros(self.m + 1, np.uint64)
+        st = lib().or_proposal_scan(self.h, _p(w.a), _p(w.b), _p(h), _p(Q))
+        return Weights(w.delta, w.lo_in, w.a, w.lo_out, w.b, Q, st, h)
+
+    def features(self, w: Weights, threads: int | None = None) -> np.ndarray:
+        """Per-edge proposal features [m, 8] in binary64 (scan order)."""
+        F = np.zeros((self.m, 8), np.float64)
+        lib().or_features(self.h, w.delta, _p(w.lo_in), _p(w.a), _p(w.lo_out), _p(w.b), _p(F),
+                          threads or default_threads())
+        return F
 
     def exhaustive(self, w: Weights, motif: bytes, threads: int | None = None):
         """Sum over all W delta-centred paths of CheckMotif: (sum X, sum X^2, #X>0)."""

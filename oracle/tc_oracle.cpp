@@ -45,6 +45,7 @@
 // integer generation in an interval", ACM TOMACS 2019), which makes every
 // value exactly uniform.
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <numeric>
@@ -354,30 +355,41 @@ int or_check_motif(void* h, const uint8_t* motif, int64_t delta, int32_t e1, int
 
 // Estimate(M, k) for a batch of motifs that share the anchor: samples
 // i0 .. i0+k-1 of (seed, stream).  Optional per-sample outputs (null = off):
-// e1/e2/e3 edge ids [k], X motif-major [n_motifs * k].  cnt holds (lo, hi)
-// per motif.
-int or_sample(void* h, int64_t delta, const uint32_t* lo_in, const uint32_t* a,
-              const uint32_t* lo_out, const uint32_t* b, const uint64_t* S,
-              const uint8_t* motifs, int n_motifs, uint64_t k, uint64_t seed, uint32_t stream,
-              uint64_t i0, int32_t* e1o, int32_t* e2o, int32_t* e3o, uint64_t* Xo,
-              uint64_t* cnt, uint64_t* hits, double* est, int nthreads) {
-  Graph& G = *(Graph*)h;
+// e1/e2/e3 edge ids [k], X motif-major [n_motifs * k], P the scan position of
+// the centre edge [k].  cnt holds (lo, hi) per motif.
+//
+// With a proposal h (null = plain sampler), S must be the scan of
+// q_p = w_p * h_p and Q = S[m]: the centre edge is drawn with probability
+// q_p / Q, so a path P centred at p has probability h_p / Q and the
+// unbiased per-sample value is Y = X * Q / h_p.  cnt then accumulates
+// floor(X * 2^64 / h_p) in 128 bits and est = (cnt * 2^-64 / k) * Q.
+// m2 (null = off) receives sum over samples of (X / h_p)^2 in binary64.
+int or_sample_ex(void* hg, int64_t delta, const uint32_t* lo_in, const uint32_t* a,
+                 const uint32_t* lo_out, const uint32_t* b, const uint64_t* S,
+                 const uint32_t* hq, const uint8_t* motifs, int n_motifs, uint64_t k,
+                 uint64_t seed, uint32_t stream, uint64_t i0, int32_t* e1o, int32_t* e2o,
+                 int32_t* e3o, uint64_t* Xo, uint32_t* Po, uint64_t* cnt, uint64_t* hits,
+                 double* est, double* m2o, int nthreads) {
+  Graph& G = *(Graph*)hg;
   if (n_motifs < 1 || n_motifs > 16 || k < 1) return OR_ARG;
   std::vector<Motif> Ms(n_motifs);
   for (int j = 0; j < n_motifs; ++j)
     if (!parse_motif(motifs + 34 * j, &Ms[j])) return OR_ARG;
-  const uint64_t W = S[G.m];
+  const uint64_t W = S[G.m];  // W, or Q with a proposal
   std::vector<u128> c(n_motifs, 0);
   std::vector<uint64_t> hh(n_motifs, 0);
+  std::vector<double> mm(n_motifs, 0.0);
   int status = OR_OK;
   if (W == 0) {
     for (uint64_t i = 0; i < k; ++i) {
       if (e1o) { e1o[i] = -1; e2o[i] = -1; e3o[i] = -1; }
+      if (Po) Po[i] = 0xFFFFFFFFu;
       if (Xo) for (int j = 0; j < n_motifs; ++j) Xo[j * k + i] = 0;
     }
   } else {
     std::vector<std::vector<u128>> pc(nthreads, std::vector<u128>(n_motifs, 0));
     std::vector<std::vector<uint64_t>> ph(nthreads, std::vector<uint64_t>(n_motifs, 0));
+    std::vector<std::vector<double>> pm(nthreads, std::vector<double>(n_motifs, 0.0));
     std::vector<int> pst(nthreads, OR_OK);
 #pragma omp parallel for num_threads(nthreads) schedule(static)
     for (int64_t ii = 0; ii < (int64_t)k; ++ii) {
@@ -392,7 +404,7 @@ int or_sample(void* h, int64_t delta, const uint32_t* lo_in, const uint32_t* a,
         ok = lemire64((uint64_t)x[0] | ((uint64_t)x[1] << 32), W, &r);
       }
       if (!ok) { pst[tid] |= OR_RNG; continue; }
-      // pick e with probability w_e / W: S[p] <= r < S[p+1]
+      // pick e with probability w_e / W (or q_e / Q): S[p] <= r < S[p+1]
       int64_t p = std::upper_bound(S, S + G.m + 1, r) - S - 1;
       uint32_t j1 = 0, j3 = 0;
       ok = false;
@@ -411,20 +423,28 @@ int or_sample(void* h, int64_t delta, const uint32_t* lo_in, const uint32_t* a,
       int32_t e1 = G.in_ord[lo_in[p] + j1];
       int32_t e3 = G.out_ord[lo_out[p] + j3];
       if (e1o) { e1o[ii] = e1; e2o[ii] = e2; e3o[ii] = e3; }
+      if (Po) Po[ii] = (uint32_t)p;
+      const uint32_t hp = hq ? hq[p] : 1u;
       for (int j = 0; j < n_motifs; ++j) {
         uint64_t X = 0;
         int st = check_motif(G, Ms[j], delta, e1, e2, e3, &X);
         pst[tid] |= st;
         if (Xo) Xo[(uint64_t)j * k + ii] = X;
-        pc[tid][j] += X;
+        u128 add = hq ? (((u128)X << 64) / hp) : (u128)X;
+        if (pc[tid][j] + add < pc[tid][j]) pst[tid] |= OR_OVERFLOW;
+        pc[tid][j] += add;
         ph[tid][j] += X > 0;
+        const double v = (double)X / (double)hp;
+        pm[tid][j] += v * v;
       }
     }
     for (int tid = 0; tid < nthreads; ++tid) {
       status |= pst[tid];
       for (int j = 0; j < n_motifs; ++j) {
+        if (c[j] + pc[tid][j] < c[j]) status |= OR_OVERFLOW;
         c[j] += pc[tid][j];
         hh[j] += ph[tid][j];
+        mm[j] += pm[tid][j];
       }
     }
   }
@@ -432,9 +452,87 @@ int or_sample(void* h, int64_t delta, const uint32_t* lo_in, const uint32_t* a,
     cnt[2 * j] = (uint64_t)c[j];
     cnt[2 * j + 1] = (uint64_t)(c[j] >> 64);
     hits[j] = hh[j];
-    est[j] = W == 0 ? 0.0 : u128_over_k_times_w(c[j], k, W);
+    if (W == 0) {
+      est[j] = 0.0;
+    } else if (hq) {
+      const double cd = std::ldexp((double)c[j], -64);
+      est[j] = (cd / (double)k) * (double)W;
+    } else {
+      est[j] = u128_over_k_times_w(c[j], k, W);
+    }
+    if (m2o) m2o[j] = mm[j];
   }
   return status;
+}
+
+int or_sample(void* h, int64_t delta, const uint32_t* lo_in, const uint32_t* a,
+              const uint32_t* lo_out, const uint32_t* b, const uint64_t* S,
+              const uint8_t* motifs, int n_motifs, uint64_t k, uint64_t seed, uint32_t stream,
+              uint64_t i0, int32_t* e1o, int32_t* e2o, int32_t* e3o, uint64_t* Xo,
+              uint64_t* cnt, uint64_t* hits, double* est, int nthreads) {
+  return or_sample_ex(h, delta, lo_in, a, lo_out, b, S, nullptr, motifs, n_motifs, k, seed,
+                      stream, i0, e1o, e2o, e3o, Xo, nullptr, cnt, hits, est, nullptr, nthreads);
+}
+
+// Scan of the proposal weights q_p = a_p * b_p * h_p (exact, 128-bit
+// running total): Q[p] = sum_{p' < p} q_p', Q[m] = Q.  Overflow if Q >= 2^64.
+int or_proposal_scan(void* hg, const uint32_t* a, const uint32_t* b, const uint32_t* hq,
+                     uint64_t* Q) {
+  Graph& G = *(Graph*)hg;
+  u128 run = 0;
+  int st = OR_OK;
+  for (int64_t p = 0; p < G.m; ++p) {
+    Q[p] = (uint64_t)run;
+    run += (u128)((uint64_t)a[p] * (uint64_t)b[p]) * hq[p];
+    if (run > kU64Max) st = OR_OVERFLOW;
+  }
+  Q[G.m] = (uint64_t)run;
+  return st;
+}
+
+// Per-edge features of the learned proposal, in binary64, for every scan
+// position p (centre edge e = (u, v, t)):
+//   0 ln(1 + a)     in-window size of u in [t - delta, t]
+//   1 ln(1 + b)     out-window size of v in [t, t + delta]
+//   2 ln(1 + a b)   the path weight w_e
+//   3 (t - t_first) / delta, t_first the earliest time in u's in-window
+//   4 (t_last - t) / delta, t_last the latest time in v's out-window
+//   5 ln(1 + #edges u -> v with time in [t - delta, t + delta])
+//   6 ln(1 + #edges v -> u with time in [t - delta, t + delta])
+//   7 ln(1 + #edges out of u with time in [t, t + delta])
+// Features 3 and 4 are 0 when their window is empty or delta = 0.
+void or_features(void* hg, int64_t delta, const uint32_t* lo_in, const uint32_t* a,
+                 const uint32_t* lo_out, const uint32_t* b, double* F, int nthreads) {
+  Graph& G = *(Graph*)hg;
+  auto pair_count = [&](int32_t x, int32_t y, int64_t lo_t, int64_t hi_t) -> int64_t {
+    auto beg = G.pair_dst.begin() + G.out_off[x];
+    auto end = G.pair_dst.begin() + G.out_off[x + 1];
+    auto run = std::equal_range(beg, end, y);
+    auto tb = G.pair_t.begin();
+    auto r0 = tb + (run.first - G.pair_dst.begin());
+    auto r1 = tb + (run.second - G.pair_dst.begin());
+    return std::upper_bound(r0, r1, hi_t) - std::lower_bound(r0, r1, lo_t);
+  };
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+  for (int64_t p = 0; p < G.m; ++p) {
+    const int32_t e = G.out_ord[p];
+    const int32_t u = G.src[e], v = G.dst[e];
+    const int64_t t = G.t[e];
+    double* f = F + 8 * p;
+    f[0] = std::log1p((double)a[p]);
+    f[1] = std::log1p((double)b[p]);
+    f[2] = std::log1p((double)a[p] * (double)b[p]);
+    f[3] = (a[p] > 0 && delta > 0) ? (double)(t - G.in_t[lo_in[p]]) / (double)delta : 0.0;
+    f[4] = (b[p] > 0 && delta > 0)
+               ? (double)(G.out_t[lo_out[p] + b[p] - 1] - t) / (double)delta
+               : 0.0;
+    f[5] = std::log1p((double)pair_count(u, v, t - delta, t + delta));
+    f[6] = std::log1p((double)pair_count(v, u, t - delta, t + delta));
+    auto ob = G.out_t.begin();
+    const int64_t d0 = std::lower_bound(ob + G.out_off[u], ob + G.out_off[u + 1], t) - ob;
+    const int64_t d1 = std::upper_bound(ob + G.out_off[u], ob + G.out_off[u + 1], t + delta) - ob;
+    f[7] = std::log1p((double)(d1 - d0));
+  }
 }
 
 // Sum of CheckMotif over every delta-centred <-,+,<,>> path (all W of them):
