@@ -43,6 +43,11 @@ def parse():
                     help="motif set of the step (the medium workload uses all six)")
     ap.add_argument("--cpu-sample", type=int, default=10**6,
                     help="samples the oracle draws for the CPU baseline")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-proposal versus method comparison")
+    ap.add_argument("--learned-seeds", type=int, default=32)
+    ap.add_argument("--k-ref", type=float, default=1e10,
+                    help="samples of the reference estimate C_ref")
     ap.add_argument("--calib-copy", action="store_true",
                     help="copy 1 GiB device-to-device first (reference for HBM counters)")
     return ap.parse_args()
@@ -94,6 +99,68 @@ def stored_traffic(kernel):
         if f.get("kernel") == kernel and f.get("src_sha") == want and "hbm_bytes_per_launch" in f:
             return float(f["hbm_bytes_per_launch"])
     return None
+
+
+def event_ms(fn, stream):
+    """Run fn() on `stream` and return (result, milliseconds between HIP events)."""
+    import torch
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    r = fn()
+    b.record(stream)
+    b.synchronize()
+    return r, a.elapsed_time(b)
+
+
+def learned_vs_method(tcb, G, Wt, motif, seeds, k_ref, stream):
+    """Relative error against C_ref (the method at k_ref samples on its own
+    stream) at k = 10^5, 10^6, 10^7 over `seeds` seeds, for the method and
+    for the learned proposal (labels on another stream), plus the time of
+    each part."""
+    from paper_2409_08975_amd import learned
+    out = {"motif": "M4-0", "delta": int(Wt.c.delta), "seeds": seeds}
+    lp = learned.LearnedProposal(G, Wt, motif, seed=11)
+    _, out["features_ms"] = event_ms(lambda: tcb.tc_edge_features(G, Wt), stream)
+    losses, out["train_ms"] = event_ms(lambda: lp.fit(n_labels=10**6, epochs=6, batch=8192,
+                                                      lr=3e-3), stream)
+    out["train"] = {"labels": 10**6, "epochs": 6, "batch": 8192,
+                    "loss_per_epoch": [round(float(x), 6) for x in losses.cpu().tolist()],
+                    "label_rate": lp.label_rate}
+    _, out["proposal_ms"] = event_ms(lp.build_proposal, stream)  # inference, h, q-scan
+    out["proposal_status"] = lp.proposal.status()
+    ref, t_ref = event_ms(lambda: tcb.tc_sample_estimate(G, Wt, [motif], int(k_ref), 1,
+                                                         stream_id=0x52454600, moments=True),
+                          stream)
+    ref.check("reference")
+    mref = learned.moments(ref, Wt, int(k_ref))
+    C = mref.estimate
+    out["C_ref"] = C
+    out["C_ref_rel_stderr"] = mref.stderr / C if C else None
+    out["k_ref"] = int(k_ref)
+    out["ref_ms"] = t_ref
+    mp, mi = lp.pilot(10**7, 0x5EED)
+    out["variance_ratio"] = mp.var / mi.var if mi.var > 0 else None
+    rows = []
+    for k in (10**5, 10**6, 10**7):
+        ep, el, tp, tl = [], [], 0.0, 0.0
+        for sd in range(1, seeds + 1):
+            r, t = event_ms(lambda: tcb.tc_sample_estimate(G, Wt, [motif], k, sd, stream_id=1),
+                            stream)
+            ep.append(float(r.estimate[0].item()))
+            tp += t
+            r, t = event_ms(lambda: tcb.tc_sample_estimate(G, lp.proposal, [motif], k, sd,
+                                                           stream_id=2), stream)
+            el.append(float(r.estimate[0].item()))
+            tl += t
+        ep, el = np.array(ep), np.array(el)
+        rows.append({"k": k,
+                     "rms_rel_err_method": float(np.sqrt(np.mean((ep - C) ** 2)) / C),
+                     "rms_rel_err_learned": float(np.sqrt(np.mean((el - C) ** 2)) / C),
+                     "ms_per_estimate_method": tp / seeds,
+                     "ms_per_estimate_learned": tl / seeds})
+    out["by_k"] = rows
+    return out
 
 
 def main():
@@ -234,6 +301,23 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
     }
+
+    # relative standard error of each motif's estimate at this k (second moment run)
+    Rm = tcb.tc_sample_estimate(G, W, motifs, k, seed, moments=True)
+    Rm.check("moments")
+    from paper_2409_08975_amd import learned as _learned
+    rse = []
+    for j in range(len(motifs)):
+        mm = _learned.moments(Rm, W, k, j)
+        rse.append(mm.stderr / mm.estimate if mm.estimate else None)
+    out["rel_stderr_at_k"] = dict(zip(names, rse))
+
+    if not args.no_learned and args.workload == "medium":
+        t0 = time.time()
+        out["learned_vs_method"] = learned_vs_method(tcb, G, W, sg.MOTIFS["M4-0"],
+                                                     args.learned_seeds, args.k_ref, stream)
+        log(f"[bench] learned vs method in {time.time() - t0:.1f}s: variance ratio "
+            f"{out['learned_vs_method']['variance_ratio']}")
 
     if not args.no_cpu_baseline:
         import oracle

@@ -115,6 +115,10 @@ typedef struct tc_weights {
                                          to a multiple of 16 words) */
   uint32_t *status;                   /* device word: TC_F_OVERFLOW if W >= 2^64 */
   void *scratch;                      /* 16-ary search tree over S (internal) */
+  const uint32_t *h;                  /* NULL for the weights of the method; for a
+                                         proposal weight set (tc_proposal_weights)
+                                         the integer factor h[p] >= 1 per edge, and
+                                         S is then the scan of q = a * b * h      */
 } tc_weights;
 
 /* Outputs of tc_sample_estimate, all (device), caller-allocated.
@@ -126,7 +130,17 @@ typedef struct tc_weights {
  *                        sampler's own)
  *   e1, e2, e3         : optional [k] edge ids of the sampled path (NULL=off)
  *   X                  : optional [n_motifs * k], motif-major (NULL = off)
- * cnt, hits, estimate and status are overwritten (not accumulated). */
+ *   P                  : optional [k] scan position of the centre edge
+ *                        (all ones when W = 0; NULL = off)
+ *   m2                 : optional [n_motifs] sum over samples of
+ *                        (X_ij / h_p)^2 in binary64 (h = 1 for the method's
+ *                        weights), for variance estimates; its summation
+ *                        order is not fixed (NULL = off)
+ * With a proposal weight set (w->h != NULL) the estimator is importance
+ * sampling: a path centred at p has probability h[p] / Q, Q = S[m], and
+ * contributes Y = X * Q / h[p].  cnt_j then holds the exact 128-bit sum of
+ * floor(X_ij * 2^64 / h_p) and estimate[j] = ((cnt_j * 2^-64) / k) * Q.
+ * cnt, hits, estimate, m2 and status are overwritten (not accumulated). */
 typedef struct tc_result {
   uint64_t *cnt;
   uint64_t *hits;
@@ -134,6 +148,8 @@ typedef struct tc_result {
   uint32_t *status;
   int32_t *e1, *e2, *e3;
   uint64_t *X;
+  uint32_t *P;
+  double *m2;
 } tc_result;
 
 /* Launch-shape choices of the sampler.  They change speed only, never a
@@ -236,6 +252,82 @@ tc_status tc_autotune(const tc_graph *g, const tc_weights *const *w, int32_t n_d
                       const tc_motif *motifs, int32_t n_motifs, uint64_t k_probe, uint64_t seed,
                       void *ws, size_t ws_bytes, tc_result *const *out, void *stream,
                       tc_tuning *best, double *best_ms);
+
+/* ---- Learned importance proposal (not part of the paper) -----------------
+ * The sampler draws the centre edge with probability proportional to
+ * q_p = w_p * h_p instead of w_p and corrects each sample by Q / h_p, which
+ * keeps the estimate unbiased for any integers h_p >= 1 (see tc_result).
+ * h comes from a small network g(f_p) over per-edge window features:
+ * h = eps + (1 - eps) g, quantised to integers.  The network is
+ * 8 -> 64 -> 64 -> 1 (ReLU, ReLU, sigmoid), TC_MLP_PARAMS float32
+ * parameters in the order W1 [64][8] (row = unit), b1 [64], W2 [64][64],
+ * b2 [64], w3 [64], b3; the kernels use bfloat16 copies of the weight
+ * matrices, features and hidden activations with float32 accumulation. */
+#define TC_MLP_PARAMS 4801
+
+/* Features of every scan position p (centre edge (u, v, t)) into feat
+ * (device, [m][8] bfloat16 bit patterns, 16 bytes per edge):
+ *   0 ln(1+a)  1 ln(1+b)  2 ln(1+a b)  3 (t - earliest time of u's in-window)/delta
+ *   4 (latest time of v's out-window - t)/delta  5 ln(1 + #u->v edges with time
+ *   in [t-delta, t+delta])  6 the same for v->u  7 ln(1 + #out-edges of u in
+ *   [t, t+delta]); 3 and 4 are 0 for an empty window or delta = 0.
+ * Errors: TC_E_ARG for null pointers or a weight set of another graph. */
+tc_status tc_edge_features(const tc_graph *g, const tc_weights *w, uint16_t *feat, void *stream);
+
+/* g[i] = network output for feature row i, i < n (device arrays). */
+tc_status tc_mlp_forward(const float *params, const uint16_t *feat, int64_t n, float *g,
+                         void *stream);
+
+/* Workspace of tc_mlp_grad for n rows and of tc_mlp_train for one batch. */
+tc_status tc_mlp_workspace_bytes(int64_t n, size_t *bytes);
+
+/* Mean binary cross-entropy (*loss, device float) and its gradient
+ * (grad, device [TC_MLP_PARAMS]) over n labels: label i uses feature row
+ * rows[i] of the n_feat rows of feat (rows may be NULL: row i, then
+ * n <= n_feat) and y_i = [X[i] > 0] (X device [n], e.g. per-sample counts
+ * and centre positions of the method's sampler).  Labels whose row is
+ * >= n_feat are ignored (they add nothing; the mean still divides by n).
+ * Deterministic for a given n.  Errors: TC_E_ARG (null pointers, n < 1 or
+ * n >= 2^31), TC_E_WORKSPACE. */
+tc_status tc_mlp_grad(const float *params, const uint16_t *feat, int64_t n_feat,
+                      const uint32_t *rows, const uint64_t *X, int64_t n, float *grad,
+                      float *loss, void *ws, size_t ws_bytes, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected for the
+ * 1-based step) on params with moments opt[0..P) and opt[P..2P) (device,
+ * P = TC_MLP_PARAMS; start from zeros). */
+tc_status tc_mlp_adam(float *params, float *opt, const float *grad, int64_t step, float lr,
+                      void *stream);
+
+/* Minibatch training: `epochs` passes over the n labels in a Philox-drawn
+ * order per epoch (seed), batches of `batch` labels, one gradient and one
+ * Adam step per batch (steps numbered from step0 + 1).  loss_per_epoch
+ * (device [epochs], may be NULL) receives each epoch's mean loss.
+ * Enqueue only.  Errors as tc_mlp_grad; batch in [32, 2^20]. */
+tc_status tc_mlp_train(float *params, float *opt, const uint16_t *feat, int64_t n_feat,
+                       const uint32_t *rows, const uint64_t *X, int64_t n, int32_t batch,
+                       int32_t epochs, float lr, uint64_t seed, int64_t step0,
+                       float *loss_per_epoch, void *ws, size_t ws_bytes, void *stream);
+
+/* h[p] = max(1, floor((eps + (1 - eps) x[p]) * 2^s + 1/2)) with
+ * s = clamp(63 - bitlen(W), 1, 16), W = w->S[m], and x = g clamped to
+ * [0, 1] (NaN read as 0), every operation in float32.  With g_max non-NULL
+ * (a device float the call overwrites) the scores are first normalised:
+ * *g_max = max_p x[p] and x[p] is replaced by x[p] / *g_max when that is
+ * positive, so the factors span [eps, 1] whatever the label base rate.
+ * Then W * 2^s < 2^63 when W < 2^62, so the proposal total cannot
+ * overflow.  eps in (0, 1]. */
+tc_status tc_quantize_proposal(const tc_weights *w, const float *g, float eps, float *g_max,
+                               uint32_t *h, void *stream);
+
+/* Proposal weight set wq from w and h (device [m], h[p] >= 1): the same
+ * window arrays (borrowed from w), S = exclusive scan of q = a * b * h with
+ * Q = S[m] (128-bit exact; TC_F_OVERFLOW in *wq->status if Q >= 2^64), its
+ * search tree, and wq->h = h.  Pass wq to tc_sample_estimate or
+ * tc_batch_estimate for the importance-sampling estimate. */
+tc_status tc_proposal_workspace_bytes(int64_t m, size_t *bytes);
+tc_status tc_proposal_weights(const tc_graph *g, const tc_weights *w, const uint32_t *h,
+                              void *ws, size_t ws_bytes, tc_weights *wq, void *stream);
 
 /* Profiling aid (not part of the method).  After tc_timing_enable(1) the
  * library records a pair of HIP events on the launch stream around each

@@ -128,12 +128,15 @@ def quant_shift(W: int) -> int:
     return min(16, max(1, 63 - int(W).bit_length()))
 
 
-def quantize(g, W: int, eps: float = 0.1) -> np.ndarray:
+def quantize(g, W: int, eps: float = 0.1, normalize: bool = False) -> np.ndarray:
     """h_int per edge from g (float32), every operation in float32; g is
-    taken as 0 where it is NaN and clamped to [0, 1]."""
+    taken as 0 where it is NaN and clamped to [0, 1]; with normalize it is
+    then divided by its maximum (when that is positive)."""
     g = np.asarray(g, dtype=np.float32).copy()
     g[np.isnan(g)] = np.float32(0)
     g = np.clip(g, np.float32(0), np.float32(1))
+    if normalize and g.size and g.max() > 0:
+        g = (g / g.max()).astype(np.float32)
     e = np.float32(eps)
     one_m = np.float32(1) - e
     h = e + one_m * g                                # float32 ops

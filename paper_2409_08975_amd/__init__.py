@@ -26,7 +26,11 @@ _STATUS_NAMES = {0: "TC_OK", -1: "TC_E_ARG", -2: "TC_E_RANGE", -3: "TC_E_OVERFLO
 EXPORTED = ["tc_version", "tc_graph_workspace_bytes", "tc_build_graph",
             "tc_weights_workspace_bytes", "tc_path_weights", "tc_sample_workspace_bytes",
             "tc_sample_estimate", "tc_batch_workspace_bytes", "tc_batch_estimate",
-            "tc_autotune", "tc_timing_enable", "tc_timing_reset", "tc_timing_read"]
+            "tc_autotune", "tc_edge_features", "tc_mlp_forward", "tc_mlp_workspace_bytes",
+            "tc_mlp_grad", "tc_mlp_adam", "tc_mlp_train", "tc_quantize_proposal",
+            "tc_proposal_workspace_bytes", "tc_proposal_weights", "tc_timing_enable",
+            "tc_timing_reset", "tc_timing_read"]
+MLP_PARAMS = 4801
 
 
 class TCError(RuntimeError):
@@ -62,12 +66,13 @@ class tc_graph(ctypes.Structure):
 
 class tc_weights(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_int64), ("m", ctypes.c_int64), ("lo_in", _P), ("a", _P),
-                ("lo_out", _P), ("b", _P), ("S", _P), ("status", _P), ("scratch", _P)]
+                ("lo_out", _P), ("b", _P), ("S", _P), ("status", _P), ("scratch", _P),
+                ("h", _P)]
 
 
 class tc_result(ctypes.Structure):
     _fields_ = [("cnt", _P), ("hits", _P), ("estimate", _P), ("status", _P), ("e1", _P),
-                ("e2", _P), ("e3", _P), ("X", _P)]
+                ("e2", _P), ("e3", _P), ("X", _P), ("P", _P), ("m2", _P)]
 
 
 class tc_tuning(ctypes.Structure):
@@ -111,6 +116,18 @@ def lib():
         L.tc_autotune.argtypes = [ctypes.POINTER(tc_graph), _P, I32, ctypes.POINTER(tc_motif),
                                   I32, U64, U64, _P, SZ, _P, _P, ctypes.POINTER(tc_tuning),
                                   ctypes.POINTER(ctypes.c_double)]
+        F32 = ctypes.c_float
+        L.tc_edge_features.argtypes = [ctypes.POINTER(tc_graph), ctypes.POINTER(tc_weights), _P, _P]
+        L.tc_mlp_forward.argtypes = [_P, _P, I64, _P, _P]
+        L.tc_mlp_workspace_bytes.argtypes = [I64, ctypes.POINTER(SZ)]
+        L.tc_mlp_grad.argtypes = [_P, _P, I64, _P, _P, I64, _P, _P, _P, SZ, _P]
+        L.tc_mlp_adam.argtypes = [_P, _P, _P, I64, F32, _P]
+        L.tc_mlp_train.argtypes = [_P, _P, _P, I64, _P, _P, I64, I32, I32, F32, U64, I64, _P, _P,
+                                   SZ, _P]
+        L.tc_quantize_proposal.argtypes = [ctypes.POINTER(tc_weights), _P, F32, _P, _P, _P]
+        L.tc_proposal_workspace_bytes.argtypes = [I64, ctypes.POINTER(SZ)]
+        L.tc_proposal_weights.argtypes = [ctypes.POINTER(tc_graph), ctypes.POINTER(tc_weights),
+                                          _P, _P, SZ, ctypes.POINTER(tc_weights), _P]
         L.tc_timing_enable.argtypes = [I32]
         L.tc_timing_reset.argtypes = []
         L.tc_timing_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -186,6 +203,8 @@ class Weights:
     c: tc_weights
     ws: torch.Tensor
     graph: Graph
+    base: "Weights | None" = None     # the method's weights a proposal set borrows from
+    h: torch.Tensor | None = None     # proposal factors (int32 storage of uint32)
 
     def view(self, name, dtype, length):
         ptr = getattr(self.c, name)
@@ -195,6 +214,10 @@ class Weights:
 
     def arrays(self):
         m = self.c.m
+        if self.base is not None:
+            d = self.base.arrays()
+            d["S"] = self.view("S", torch.int64, m + 1)
+            return d
         return dict(lo_in=self.view("lo_in", torch.int32, m), a=self.view("a", torch.int32, m),
                     lo_out=self.view("lo_out", torch.int32, m), b=self.view("b", torch.int32, m),
                     S=self.view("S", torch.int64, m + 1))
@@ -217,6 +240,8 @@ class Result:
     e2: torch.Tensor | None = None
     e3: torch.Tensor | None = None
     X: torch.Tensor | None = None  # int64 [n_motifs, k] (u64 bit patterns)
+    P: torch.Tensor | None = None  # int32 [k] centre scan positions (u32 bit patterns)
+    m2: torch.Tensor | None = None  # float64 [n_motifs] sum of (X / h)^2
 
     def counts(self):
         c = self.cnt.cpu().tolist()
@@ -297,8 +322,10 @@ def tc_path_weights(graph: Graph, delta: int, stream=None) -> Weights:
     return Weights(w, ws, graph)
 
 
-def new_result(n_motifs: int, k: int, device, per_sample: bool = False) -> Result:
-    """Output buffers of one delta (per-sample arrays only with per_sample)."""
+def new_result(n_motifs: int, k: int, device, per_sample: bool = False,
+               moments: bool = False) -> Result:
+    """Output buffers of one delta (per-sample arrays only with per_sample,
+    the second moment only with moments)."""
     nm = n_motifs
     out = Result(torch.zeros(2 * nm, dtype=torch.int64, device=device),
                  torch.zeros(nm, dtype=torch.int64, device=device),
@@ -309,13 +336,17 @@ def new_result(n_motifs: int, k: int, device, per_sample: bool = False) -> Resul
         out.e2 = torch.empty(k, dtype=torch.int32, device=device)
         out.e3 = torch.empty(k, dtype=torch.int32, device=device)
         out.X = torch.empty((nm, k), dtype=torch.int64, device=device)
+        out.P = torch.empty(k, dtype=torch.int32, device=device)
+    if moments:
+        out.m2 = torch.zeros(nm, dtype=torch.float64, device=device)
     return out
 
 
 def _c_result(out: Result) -> tc_result:
     return tc_result(_ptr(out.cnt).value, _ptr(out.hits).value, _ptr(out.estimate).value,
                      _ptr(out.status).value, _ptr(out.e1).value, _ptr(out.e2).value,
-                     _ptr(out.e3).value, _ptr(out.X).value)
+                     _ptr(out.e3).value, _ptr(out.X).value, _ptr(out.P).value,
+                     _ptr(out.m2).value)
 
 
 def _motif_array(motifs):
@@ -326,12 +357,13 @@ def _motif_array(motifs):
 def tc_sample_estimate(graph: Graph, weights: Weights, motifs, k: int, seed: int,
                        stream_id: int = 0, i0: int = 0, per_sample: bool = False,
                        stream=None, out: Result | None = None,
-                       workspace: torch.Tensor | None = None) -> Result:
-    """Estimate(M, k) for a list of motifs (each a list of (src, dst) edges in pi order)."""
+                       workspace: torch.Tensor | None = None, moments: bool = False) -> Result:
+    """Estimate(M, k) for a list of motifs (each a list of (src, dst) edges in
+    pi order); importance sampling when `weights` is a proposal set."""
     nm, arr = _motif_array(motifs)
     dev = graph.ws.device
     if out is None:
-        out = new_result(nm, k, dev, per_sample)
+        out = new_result(nm, k, dev, per_sample, moments)
     r = _c_result(out)
     ws = _sample_ws(k, nm, dev, 1, stream) if workspace is None else workspace
     _check(lib().tc_sample_estimate(ctypes.byref(graph.c), ctypes.byref(weights.c), arr, nm,
@@ -390,6 +422,95 @@ def tc_autotune(graph: Graph, weights, motifs, k_probe: int, seed: int = 1, stre
                              ctypes.byref(ms)),
            "tc_autotune")
     return best, ms.value
+
+
+# ------------------------------------------------------- learned proposal ----
+def tc_edge_features(graph: Graph, weights: Weights, stream=None) -> torch.Tensor:
+    """[m, 8] bfloat16 features (int16 storage of the bit patterns)."""
+    feat = torch.empty((graph.m, 8), dtype=torch.int16, device=graph.ws.device)
+    _check(lib().tc_edge_features(ctypes.byref(graph.c), ctypes.byref(weights.c), _ptr(feat),
+                                  _stream(stream)), "tc_edge_features")
+    return feat
+
+
+def tc_mlp_forward(params: torch.Tensor, feat: torch.Tensor, n: int | None = None,
+                   stream=None, out: torch.Tensor | None = None) -> torch.Tensor:
+    n = feat.shape[0] if n is None else n
+    g = torch.empty(n, dtype=torch.float32, device=feat.device) if out is None else out
+    _check(lib().tc_mlp_forward(_ptr(params), _ptr(feat), int(n), _ptr(g), _stream(stream)),
+           "tc_mlp_forward")
+    return g
+
+
+def mlp_workspace_bytes(n: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().tc_mlp_workspace_bytes(int(n), ctypes.byref(b)), "tc_mlp_workspace_bytes")
+    return b.value
+
+
+def tc_mlp_grad(params, feat, rows, X, n: int | None = None, stream=None):
+    """(grad [4801] float32, loss [1] float32) of the mean BCE over n labels."""
+    n = X.shape[0] if n is None else n
+    dev = feat.device
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    nb = mlp_workspace_bytes(n)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    _check(lib().tc_mlp_grad(_ptr(params), _ptr(feat), int(feat.shape[0]), _ptr(rows), _ptr(X),
+                             int(n), _ptr(grad), _ptr(loss), _ptr(ws), nb, _stream(stream)),
+           "tc_mlp_grad")
+    return grad, loss
+
+
+def tc_mlp_adam(params, opt, grad, step: int, lr: float, stream=None) -> None:
+    _check(lib().tc_mlp_adam(_ptr(params), _ptr(opt), _ptr(grad), int(step), float(lr),
+                             _stream(stream)), "tc_mlp_adam")
+
+
+def tc_mlp_train(params, opt, feat, rows, X, batch: int, epochs: int, lr: float, seed: int,
+                 step0: int = 0, stream=None) -> torch.Tensor:
+    """Train in place; returns the mean loss of each epoch (device float32)."""
+    n = X.shape[0]
+    dev = feat.device
+    losses = torch.empty(epochs, dtype=torch.float32, device=dev)
+    nb = mlp_workspace_bytes(batch)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    _check(lib().tc_mlp_train(_ptr(params), _ptr(opt), _ptr(feat), int(feat.shape[0]), _ptr(rows),
+                              _ptr(X), int(n), int(batch), int(epochs), float(lr), int(seed),
+                              int(step0), _ptr(losses), _ptr(ws), ws.numel(), _stream(stream)),
+           "tc_mlp_train")
+    return losses
+
+
+def tc_quantize_proposal(weights: Weights, g: torch.Tensor, eps: float = 0.1,
+                         normalize: bool = False, stream=None) -> torch.Tensor:
+    """Integer proposal factors (int32 storage of uint32); with normalize the
+    scores are divided by their maximum first."""
+    h = torch.empty(weights.c.m, dtype=torch.int32, device=g.device)
+    gmax = torch.empty(1, dtype=torch.float32, device=g.device) if normalize else None
+    _check(lib().tc_quantize_proposal(ctypes.byref(weights.c), _ptr(g), float(eps), _ptr(gmax),
+                                      _ptr(h), _stream(stream)), "tc_quantize_proposal")
+    return h
+
+
+def proposal_workspace_bytes(m: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().tc_proposal_workspace_bytes(int(m), ctypes.byref(b)),
+           "tc_proposal_workspace_bytes")
+    return b.value
+
+
+def tc_proposal_weights(graph: Graph, weights: Weights, h: torch.Tensor,
+                        stream=None) -> Weights:
+    """Proposal weight set: windows of `weights`, S = scan of a * b * h."""
+    h = h.contiguous()
+    nb = proposal_workspace_bytes(graph.m)
+    ws = torch.empty(nb, dtype=torch.uint8, device=graph.ws.device)
+    wq = tc_weights()
+    _check(lib().tc_proposal_weights(ctypes.byref(graph.c), ctypes.byref(weights.c), _ptr(h),
+                                     _ptr(ws), nb, ctypes.byref(wq), _stream(stream)),
+           "tc_proposal_weights")
+    return Weights(wq, ws, graph, base=weights, h=h)
 
 
 def timing_enable(on: bool = True) -> None:

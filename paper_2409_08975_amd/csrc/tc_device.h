@@ -20,16 +20,16 @@ struct Words4 {
   uint32_t x0, x1, x2, x3;
 };
 
-__device__ __forceinline__ Words4 philox_block(uint64_t seed, uint32_t stream, uint64_t i,
-                                               uint32_t attempt) {
+__host__ __device__ __forceinline__ Words4 philox_block(uint64_t seed, uint32_t stream,
+                                                        uint64_t i, uint32_t attempt) {
   uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32), c2 = attempt, c3 = stream;
   uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    uint32_t lo0 = 0xD2511F53u * c0;
-    uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-    uint32_t lo1 = 0xCD9E8D57u * c2;
-    uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+    const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
     uint32_t n0 = hi1 ^ c1 ^ k0;
     uint32_t n2 = hi0 ^ c3 ^ k1;
     c0 = n0;

@@ -66,6 +66,9 @@ struct DeltaArgs {
   int32_t* e2;
   int32_t* e3;
   uint64_t* X;
+  const uint32_t* h;  // proposal factors (importance sampling) or null
+  uint32_t* P;
+  double* m2;
 };
 
 struct SampleArgs {
@@ -108,6 +111,7 @@ struct SampleArgs {
   uint32_t* wide_next;
   uint32_t* big_code;
   uint32_t* big_count;
+  uint32_t* samp_h;  // [nd][chunk] proposal factor of each accepted sample
   uint64_t* fast_p;  // [fast waves][2][kKeyCap + 1]
   uint64_t* wide_p;  // [kWideWaves][2][kWideCap + 1]
   MotifPlan plan;
@@ -162,6 +166,8 @@ __device__ __forceinline__ uint32_t tree_search(const SampleArgs& A, const Delta
 // Dynamic LDS: slot (w, d, j) at w * nd * nm + d * nm + j for NW wavefronts.
 struct BlockSums {
   uint64_t lo, hi, hits;
+  double m2;
+  uint32_t ovf;
 };
 extern __shared__ BlockSums s_dyn_sums[];
 
@@ -177,14 +183,61 @@ __device__ __forceinline__ BlockSums* sums_slot(const SampleArgs& A, int w, int 
 template <int NW>
 __device__ __forceinline__ void sums_clear(const SampleArgs& A) {
   for (int i = threadIdx.x; i < NW * A.nd * A.plan.n_motifs; i += blockDim.x)
-    s_dyn_sums[i] = BlockSums{0, 0, 0};
+    s_dyn_sums[i] = BlockSums{0, 0, 0, 0.0, 0u};
 }
 
-__device__ __forceinline__ void sums_add(BlockSums* p, U128 v, uint64_t h) {
-  const U128 r = add128(U128{p->lo, p->hi}, v);
+// 128-bit add that reports a carry out (a total >= 2^128)
+__device__ __forceinline__ U128 add128c(U128 a, U128 b, bool* ovf) {
+  const U128 r = add128(a, b);
+  if (r.hi < a.hi || (r.hi == a.hi && r.lo < a.lo)) *ovf = true;
+  return r;
+}
+
+__device__ __forceinline__ U128 wave_sum128c(U128 v, bool* ovf) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+    v = add128c(v, U128{__shfl_xor(v.lo, off, kWave), __shfl_xor(v.hi, off, kWave)}, ovf);
+  return v;
+}
+
+__device__ __forceinline__ double wave_sumf64(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ void sums_add(BlockSums* p, U128 v, uint64_t h, double sq, bool ovf) {
+  bool o = ovf;
+  const U128 r = add128c(U128{p->lo, p->hi}, v, &o);
   p->lo = r.lo;
   p->hi = r.hi;
   p->hits += h;
+  p->m2 += sq;
+  if (o) p->ovf = 1u;
+}
+
+// Contribution of one sample to cnt: X for the method's weights; with a
+// proposal factor hp, floor(X * 2^64 / hp) by long division in 32-bit limbs.
+__device__ __forceinline__ U128 contribution(uint64_t X, bool is, uint32_t hp) {
+  if (!is) return U128{X, 0};
+  if (X == 0) return U128{0, 0};
+  const uint32_t limb[4] = {(uint32_t)(X >> 32), (uint32_t)X, 0u, 0u};
+  uint32_t q[4];
+  uint64_t rem = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint64_t cur = (rem << 32) | limb[i];
+    q[i] = (uint32_t)(cur / hp);
+    rem = cur % hp;
+  }
+  return U128{((uint64_t)q[2] << 32) | q[3], ((uint64_t)q[0] << 32) | q[1]};
+}
+
+// (X / hp)^2 in binary64 (no contraction into a later sum)
+__device__ __forceinline__ double square_term(uint64_t X, uint32_t hp) {
+  if (X == 0) return 0.0;
+  const double v = __ddiv_rn((double)X, (double)hp);
+  return __dmul_rn(v, v);
 }
 
 // after a barrier: thread (d, j) adds the slots of all wavefronts to the outputs
@@ -195,18 +248,30 @@ __device__ void sums_flush(const SampleArgs& A) {
     const int d = i / nm, j = i - d * nm;
     U128 sum{0, 0};
     uint64_t h = 0;
+    double sq = 0.0;
+    bool ovf = false;
     for (int w = 0; w < NW; ++w) {
       const BlockSums* p = sums_slot(A, w, d, j);
-      sum = add128(sum, U128{p->lo, p->hi});
+      sum = add128c(sum, U128{p->lo, p->hi}, &ovf);
       h += p->hits;
+      sq += p->m2;
+      if (p->ovf) ovf = true;
     }
     uint64_t* cnt = A.D[d].cnt;
     if (sum.lo | sum.hi) {
       const uint64_t old = atomicAdd((unsigned long long*)&cnt[2 * j], (unsigned long long)sum.lo);
       const uint64_t carry = (old + sum.lo < old) ? 1ull : 0ull;
-      if (sum.hi + carry) atomicAdd((unsigned long long*)&cnt[2 * j + 1], sum.hi + carry);
+      const uint64_t add_hi = sum.hi + carry;
+      if (add_hi < sum.hi) ovf = true;
+      if (add_hi) {
+        const uint64_t old_hi =
+            atomicAdd((unsigned long long*)&cnt[2 * j + 1], (unsigned long long)add_hi);
+        if (old_hi + add_hi < old_hi) ovf = true;
+      }
     }
     if (h) atomicAdd((unsigned long long*)&A.D[d].hits[j], (unsigned long long)h);
+    if (A.D[d].m2 && sq != 0.0) atomicAdd(&A.D[d].m2[j], sq);
+    if (ovf) atomicOr(A.D[d].status, TC_F_OVERFLOW);
   }
 }
 
@@ -245,8 +310,10 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
     bool valid = false;
     int32_t x = 0, u = 0, v = 0, y = 0;
     int64_t t1 = 0, t3 = 0;
+    uint32_t hp = 1;
     if (active) {
       if (W == 0) {
+        if (D.P) D.P[ii] = 0xFFFFFFFFu;
         if (D.e1) {
           D.e1[ii] = -1;
           D.e2[ii] = -1;
@@ -298,8 +365,13 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
           D.e2[ii] = A.out_eid[p];
           D.e3[ii] = A.out_eid[q3];
         }
+        if (D.P) D.P[ii] = p;
         valid = x != u && x != v && x != y && u != v && u != y && v != y && t1 < t2 &&
                 t2 < t3 && (t3 - t1) <= D.delta;
+        if (D.h && valid) {
+          hp = D.h[p];
+          A.samp_h[(uint64_t)d * A.chunk + li] = hp;
+        }
       }
     }
     // compact the accepted paths of the tile into LDS
@@ -359,9 +431,12 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
               li | ((uint32_t)j << kLiBits) | ((uint32_t)d << (kLiBits + 4));
       }
       if (active && W != 0 && !defer && D.X) D.X[(uint64_t)j * A.k + ii] = X;
-      const U128 sx = wave_sum128(U128{defer ? 0ull : X, 0});
-      const uint64_t h = wave_sum64((!defer && X != 0) ? 1ull : 0ull);
-      if (lane == 0) sums_add(sums_slot(A, wave, d, j), sx, h);
+      const uint64_t Xc = defer ? 0ull : X;
+      bool ovf = false;
+      const U128 sx = wave_sum128c(contribution(Xc, D.h != nullptr, hp), &ovf);
+      const uint64_t h = wave_sum64(Xc != 0 ? 1ull : 0ull);
+      const double sq = D.m2 ? wave_sumf64(square_term(Xc, hp)) : 0.0;
+      if (lane == 0) sums_add(sums_slot(A, wave, d, j), sx, h, sq, ovf);
     }
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) st_bits |= __shfl_xor(st_bits, off, kWave);
@@ -425,8 +500,11 @@ __device__ uint64_t sweep(const int64_t* __restrict__ pair_t, uint32_t (&ptr)[ML
 // record one item's count (lane 0 of a one-wavefront block)
 __device__ __forceinline__ void item_done(const SampleArgs& A, int d, int j, uint32_t li,
                                           uint64_t X) {
-  if (A.D[d].X) A.D[d].X[(uint64_t)j * A.k + A.c0 + li] = X;
-  sums_add(sums_slot(A, 0, d, j), U128{X, 0}, X != 0 ? 1ull : 0ull);
+  const DeltaArgs& D = A.D[d];
+  if (D.X) D.X[(uint64_t)j * A.k + A.c0 + li] = X;
+  const uint32_t hp = D.h ? A.samp_h[(uint64_t)d * A.chunk + li] : 1u;
+  sums_add(sums_slot(A, 0, d, j), contribution(X, D.h != nullptr, hp), X != 0 ? 1ull : 0ull,
+           D.m2 ? square_term(X, hp) : 0.0, false);
 }
 
 // Register-resident wavefront ListCount (64-thread blocks) for items whose
@@ -671,12 +749,21 @@ __global__ __launch_bounds__(kSBlock) void k_listcount_big(SampleArgs A) {
     const uint64_t X = big ? sweep<kMaxLists, true>(A.pair_t, ptr, end, l, &ovf)
                            : sweep<kMaxLists, false>(A.pair_t, ptr, end, l, &ovf);
     if (ovf) flag_status(A, d, TC_F_OVERFLOW);
-    if (A.D[d].X) A.D[d].X[(uint64_t)j * A.k + A.c0 + li] = X;
+    const DeltaArgs& D = A.D[d];
+    if (D.X) D.X[(uint64_t)j * A.k + A.c0 + li] = X;
+    const uint32_t hp = D.h ? A.samp_h[(uint64_t)d * A.chunk + li] : 1u;
+    const U128 c = contribution(X, D.h != nullptr, hp);
     // few items: this wavefront's slot, updated with LDS atomics
     BlockSums* slot = sums_slot(A, wave, d, j);
     atomicAdd((unsigned long long*)&slot->hits, X != 0 ? 1ull : 0ull);
-    const uint64_t old = atomicAdd((unsigned long long*)&slot->lo, (unsigned long long)X);
-    if (old + X < old) atomicAdd((unsigned long long*)&slot->hi, 1ull);
+    if (D.m2 && X) atomicAdd(&slot->m2, square_term(X, hp));
+    const uint64_t old = atomicAdd((unsigned long long*)&slot->lo, (unsigned long long)c.lo);
+    const uint64_t add_hi = c.hi + ((old + c.lo < old) ? 1ull : 0ull);
+    if (add_hi < c.hi) atomicOr(&slot->ovf, 1u);
+    if (add_hi) {
+      const uint64_t old_hi = atomicAdd((unsigned long long*)&slot->hi, (unsigned long long)add_hi);
+      if (old_hi + add_hi < old_hi) atomicOr(&slot->ovf, 1u);
+    }
   }
   __syncthreads();
   sums_flush<kSWaves>(A);
@@ -689,6 +776,7 @@ __global__ void k_zero_result(SampleArgs A) {
     A.D[d].cnt[2 * j] = 0;
     A.D[d].cnt[2 * j + 1] = 0;
     A.D[d].hits[j] = 0;
+    if (A.D[d].m2) A.D[d].m2[j] = 0.0;
   }
   if ((int)threadIdx.x < A.nd) *A.D[threadIdx.x].status = 0;
 }
@@ -707,14 +795,16 @@ __global__ void k_zero_counters(uint32_t* p) {
   if (threadIdx.x < 6) p[threadIdx.x] = 0;
 }
 
-// C_hat = (cnt / k) * W, each integer rounded to nearest-even binary64
+// C_hat = (cnt / k) * W, each integer rounded to nearest-even binary64; with
+// a proposal, C_hat = ((cnt * 2^-64) / k) * Q
 __global__ void k_finalize(SampleArgs A, double* const* est) {
   const int nm = A.plan.n_motifs;
   for (int i = threadIdx.x; i < A.nd * nm; i += blockDim.x) {
     const int d = i / nm, j = i - d * nm;
     const uint64_t W = A.D[d].S[A.m];
-    const double c = u128_to_double(A.D[d].cnt[2 * j], A.D[d].cnt[2 * j + 1]);
-    est[d][j] = (W == 0) ? 0.0 : (c / (double)A.k) * (double)W;
+    double c = u128_to_double(A.D[d].cnt[2 * j], A.D[d].cnt[2 * j + 1]);
+    if (A.D[d].h) c = ldexp(c, -64);
+    est[d][j] = (W == 0) ? 0.0 : __dmul_rn(__ddiv_rn(c, (double)A.k), (double)W);
   }
   __syncthreads();
   if ((int)threadIdx.x < A.nd && *A.D[threadIdx.x].wstatus)
@@ -745,7 +835,7 @@ static int fast_waves_for(const SampleTuning& t) {
 }
 
 struct SampleLayout {
-  size_t win_lo, win_len, code, mid, wide, big, counters, fast_p, wide_p, est_ptrs, total;
+  size_t win_lo, win_len, code, mid, wide, big, counters, fast_p, wide_p, est_ptrs, samp_h, total;
   uint64_t chunk, cap;
   int fast_waves;
 };
@@ -771,6 +861,7 @@ static SampleLayout sample_layout(uint64_t k, int nd, int32_t n_motifs, const Sa
   L.fast_p = take((size_t)L.fast_waves * 2 * (kKeyCap + 1) * 8);
   L.wide_p = take((size_t)kWideWaves * 2 * (kWideCap + 1) * 8);
   L.est_ptrs = take(kMaxDeltas * sizeof(double*));
+  L.samp_h = take((size_t)nd * L.chunk * 4);
   L.total = o;
   return L;
 }
@@ -831,6 +922,9 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
     D.e2 = out[d]->e2;
     D.e3 = out[d]->e3;
     D.X = out[d]->X;
+    D.h = w[d]->h;
+    D.P = out[d]->P;
+    D.m2 = out[d]->m2;
     est_host[d] = out[d]->estimate;
   }
   A.k = k;
@@ -851,6 +945,7 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
   A.big_count = A.item_count + 4;
   A.mid_count = A.item_count + 5;
   A.fast_p = (uint64_t*)(base + L.fast_p);
+  A.samp_h = (uint32_t*)(base + L.samp_h);
   A.wide_p = (uint64_t*)(base + L.wide_p);
   A.plan = plan;
   // the estimate pointers go to the device through a small kernel argument

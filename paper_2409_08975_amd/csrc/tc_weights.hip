@@ -184,8 +184,39 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const uint64_t* __restrict_
   }
 }
 
+// 128-bit tile sums of q = a * b * h (the proposal weights)
+__global__ __launch_bounds__(kWBlock) void k_qtile_sums(const uint32_t* __restrict__ a,
+                                                      const uint32_t* __restrict__ b,
+                                                      const uint32_t* __restrict__ h, int64_t m,
+                                                      uint64_t* __restrict__ tile_sums) {
+  __shared__ U128 s_w[kWBlock / kWave];
+  const int64_t start = (int64_t)blockIdx.x * kWTile;
+  U128 acc{0, 0};
+#pragma unroll 4
+  for (int r = 0; r < kWItems; ++r) {
+    const int64_t p = start + (int64_t)r * kWBlock + threadIdx.x;
+    if (p < m) {
+      const uint64_t w = (uint64_t)a[p] * (uint64_t)b[p];
+      acc = add128(acc, U128{w * h[p], __umul64hi(w, (uint64_t)h[p])});
+    }
+  }
+  acc = wave_sum128(acc);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    U128 t{0, 0};
+    for (int w = 0; w < kWBlock / kWave; ++w) t = add128(t, s_w[w]);
+    tile_sums[2 * blockIdx.x] = t.lo;
+    tile_sums[2 * blockIdx.x + 1] = t.hi;
+  }
+}
+
+// per tile: w = a * b (times h for the proposal), block-wide exclusive scan,
+// plus the tile offset -> S[p]
+template <bool H>
 __global__ __launch_bounds__(kWBlock) void k_scan_apply(const uint32_t* __restrict__ a,
-                                                      const uint32_t* __restrict__ b, int64_t m,
+                                                      const uint32_t* __restrict__ b,
+                                                      const uint32_t* __restrict__ h, int64_t m,
                                                       const uint64_t* __restrict__ tile_off,
                                                       uint64_t* __restrict__ S) {
   __shared__ uint64_t s_w[kWBlock / kWave];
@@ -199,16 +230,27 @@ __global__ __launch_bounds__(kWBlock) void k_scan_apply(const uint32_t* __restri
     uint4 aa0 = a4[0], aa1 = a4[1], bb0 = b4[0], bb1 = b4[1];
     uint32_t av[8] = {aa0.x, aa0.y, aa0.z, aa0.w, aa1.x, aa1.y, aa1.z, aa1.w};
     uint32_t bv[8] = {bb0.x, bb0.y, bb0.z, bb0.w, bb1.x, bb1.y, bb1.z, bb1.w};
+    if (H) {
+      const uint4* h4 = reinterpret_cast<const uint4*>(h + p0);
+      const uint4 hh0 = h4[0], hh1 = h4[1];
+      const uint32_t hv[8] = {hh0.x, hh0.y, hh0.z, hh0.w, hh1.x, hh1.y, hh1.z, hh1.w};
 #pragma unroll
-    for (int j = 0; j < kWItems; ++j) {
-      w[j] = (uint64_t)av[j] * (uint64_t)bv[j];
-      s += w[j];
+      for (int j = 0; j < kWItems; ++j) {
+        w[j] = (uint64_t)av[j] * (uint64_t)bv[j] * (uint64_t)hv[j];
+        s += w[j];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kWItems; ++j) {
+        w[j] = (uint64_t)av[j] * (uint64_t)bv[j];
+        s += w[j];
+      }
     }
   } else {
 #pragma unroll
     for (int j = 0; j < kWItems; ++j) {
       const int64_t p = p0 + j;
-      w[j] = (p < m) ? (uint64_t)a[p] * (uint64_t)b[p] : 0ull;
+      w[j] = (p < m) ? (uint64_t)a[p] * (uint64_t)b[p] * (H ? (uint64_t)h[p] : 1ull) : 0ull;
       s += w[j];
     }
   }
@@ -278,6 +320,23 @@ STree stree_layout(int64_t m) {
 
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// search tree over w->S (padding first, then each level)
+static void build_tree(tc_weights* w, hipStream_t st) {
+  const int64_t m = w->m;
+  const STree T = stree_layout(m);
+  const int64_t pad = T.count[0] - (m + 1);
+  if (pad > 0)
+    hipLaunchKernelGGL(k_pad_s, dim3((unsigned)((pad + 255) / 256)), dim3(256), 0, st, w->S, m,
+                       T.count[0]);
+  uint64_t stride = 1;
+  for (int L = 1; L <= T.levels; ++L) {
+    stride *= 16;
+    hipLaunchKernelGGL(k_tree_level, dim3((unsigned)((T.count[L] + 255) / 256)), dim3(256), 0, st,
+                       (const uint64_t*)w->S, m, stride,
+                       (uint64_t*)w->scratch + T.offset[L], T.count[L]);
+  }
+}
+
 struct WeightsLayout {
   size_t lo_in, a, lo_out, b, S, status, tile_sums, tile_off, tree, lo_out_q, win_q, split, total;
 };
@@ -326,6 +385,7 @@ tc_status path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_byt
   w->S = (uint64_t*)(base + L.S);
   w->status = (uint32_t*)(base + L.status);
   w->scratch = base + L.tree;  // search tree over S
+  w->h = nullptr;
   uint64_t* tile_sums = (uint64_t*)(base + L.tile_sums);
   uint64_t* tile_off = (uint64_t*)(base + L.tile_off);
   const int64_t ntiles = (m + kWTile - 1) / kWTile;
@@ -364,23 +424,65 @@ tc_status path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_byt
                      tile_off, w->S, m, w->status);
   if (ntiles > 0) {
     TimedLaunch tl("k_scan_apply", st);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
-                       (const uint32_t*)w->a, (const uint32_t*)w->b, m,
+    hipLaunchKernelGGL(k_scan_apply<false>, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
+                       (const uint32_t*)w->a, (const uint32_t*)w->b, (const uint32_t*)nullptr, m,
                        (const uint64_t*)tile_off, w->S);
   }
-  // search tree over S (padding first, then each level)
+  build_tree(w, st);
+  if (hipGetLastError() != hipSuccess) return TC_E_HIP;
+  return TC_OK;
+}
+
+// Proposal weights: windows borrowed from w, S = scan of a * b * h.
+struct ProposalLayout {
+  size_t S, tree, status, tile_sums, tile_off, total;
+};
+
+static ProposalLayout proposal_layout(int64_t m) {
+  ProposalLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(bytes ? bytes : 1);
+    return at;
+  };
+  const size_t ntiles = (size_t)((m + kWTile - 1) / kWTile);
   const STree T = stree_layout(m);
-  const int64_t pad = T.count[0] - (m + 1);
-  if (pad > 0)
-    hipLaunchKernelGGL(k_pad_s, dim3((unsigned)((pad + 255) / 256)), dim3(256), 0, st, w->S, m,
-                       T.count[0]);
-  uint64_t stride = 1;
-  for (int L = 1; L <= T.levels; ++L) {
-    stride *= 16;
-    hipLaunchKernelGGL(k_tree_level, dim3((unsigned)((T.count[L] + 255) / 256)), dim3(256), 0, st,
-                       (const uint64_t*)w->S, m, stride,
-                       (uint64_t*)w->scratch + T.offset[L], T.count[L]);
-  }
+  L.S = take((size_t)T.count[0] * 8);
+  L.tree = take(T.total_words * 8);
+  L.status = take(4);
+  L.tile_sums = take(ntiles * 16);
+  L.tile_off = take(ntiles * 8);
+  L.total = o;
+  return L;
+}
+
+size_t proposal_workspace_bytes(int64_t m) { return proposal_layout(m).total; }
+
+tc_status proposal_weights(const tc_weights* w, const uint32_t* h, void* ws, size_t ws_bytes,
+                           hipStream_t st, tc_weights* wq) {
+  const int64_t m = w->m;
+  const ProposalLayout L = proposal_layout(m);
+  if (ws_bytes < L.total) return TC_E_WORKSPACE;
+  char* base = (char*)ws;
+  *wq = *w;
+  wq->S = (uint64_t*)(base + L.S);
+  wq->scratch = base + L.tree;
+  wq->status = (uint32_t*)(base + L.status);
+  wq->h = h;
+  uint64_t* tile_sums = (uint64_t*)(base + L.tile_sums);
+  uint64_t* tile_off = (uint64_t*)(base + L.tile_off);
+  const int64_t ntiles = (m + kWTile - 1) / kWTile;
+  if (ntiles > 0)
+    hipLaunchKernelGGL(k_qtile_sums, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
+                       (const uint32_t*)w->a, (const uint32_t*)w->b, h, m, tile_sums);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, (const uint64_t*)tile_sums, ntiles,
+                     tile_off, wq->S, m, wq->status);
+  if (ntiles > 0)
+    hipLaunchKernelGGL(k_scan_apply<true>, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
+                       (const uint32_t*)w->a, (const uint32_t*)w->b, h, m,
+                       (const uint64_t*)tile_off, wq->S);
+  build_tree(wq, st);
   if (hipGetLastError() != hipSuccess) return TC_E_HIP;
   return TC_OK;
 }

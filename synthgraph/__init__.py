@@ -255,3 +255,30 @@ def gen_overflow_layers(l1: int, l2: int, l3: int) -> TemporalGraph:
     dst = np.concatenate([np.full(l1, 1), np.full(l2, 2), np.full(l3, 3)]).astype(np.int32)
     t = np.zeros(l1 + l2 + l3, np.int64)
     return TemporalGraph(4, src, dst, t, name="overflow-layers")
+
+
+def random_bf16_bits(seed: int, shape, exp_lo: int = 118, exp_hi: int = 129) -> np.ndarray:
+    """bfloat16 bit patterns (uint16) with random sign, a biased exponent in
+    [exp_lo, exp_hi] and random 7-bit mantissa: magnitudes roughly
+    2^(exp_lo-127) .. 2^(exp_hi-126).  Inputs for network tests."""
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(shape))
+    sign = rng.integers(0, 2, size=n, dtype=np.uint16) << 15
+    expo = rng.integers(exp_lo, exp_hi + 1, size=n).astype(np.uint16) << 7
+    mant = rng.integers(0, 128, size=n, dtype=np.uint16)
+    return (sign | expo | mant).astype(np.uint16).reshape(shape)
+
+
+def random_params(seed: int, n: int = 4801, scale: float = 0.25) -> np.ndarray:
+    """float32 normal parameters for network tests."""
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal(n) * scale).astype(np.float32)
+
+
+def random_counts(seed: int, n: int, p_nonzero: float = 0.3) -> np.ndarray:
+    """uint64 per-sample counts: zero with probability 1 - p_nonzero, else
+    1 + Geometric-like small integers."""
+    rng = np.random.default_rng(seed)
+    x = rng.geometric(0.5, size=n).astype(np.uint64)
+    x[rng.random(n) >= p_nonzero] = 0
+    return x

@@ -119,6 +119,11 @@ def test_quantize_range_monotone_and_bound():
         # the proposal total never overflows: W * 2^s < 2^63 for bitlen(W) <= 62
         if W.bit_length() <= 62:
             assert W * int(h.max()) < 2**63
+    # normalised: the largest score maps to 2^s, order is kept
+    gs = (g * np.float32(0.02)).astype(np.float32)
+    hn = learn.quantize(gs, 2**40, 0.05, normalize=True)
+    assert hn.max() == 2**16 and np.all(np.diff(hn.astype(np.int64)) >= 0)
+    assert hn[0] == math.floor(float(np.float32(0.05) * np.float32(2.0**16)) + 0.5)
     h = learn.quantize(np.array([np.nan, -1.0, 2.0], np.float32), 1000, 0.1)
     assert list(h) == [learn.quantize(np.float32([0.0]), 1000)[0], h[0], 2**16]
 
