@@ -122,9 +122,10 @@ def learned_vs_method(tcb, G, Wt, motif, seeds, k_ref, stream):
     out = {"motif": "M4-0", "delta": int(Wt.c.delta), "seeds": seeds}
     lp = learned.LearnedProposal(G, Wt, motif, seed=11)
     _, out["features_ms"] = event_ms(lambda: tcb.tc_edge_features(G, Wt), stream)
-    losses, out["train_ms"] = event_ms(lambda: lp.fit(n_labels=10**6, epochs=6, batch=8192,
-                                                      lr=3e-3), stream)
-    out["train"] = {"labels": 10**6, "epochs": 6, "batch": 8192,
+    losses, out["train_ms"] = event_ms(lambda: lp.fit(n_labels=10**6, epochs=8, batch=8192,
+                                                      lr=3e-3, label_cap=64.0), stream)
+    out["train"] = {"labels": 10**6, "epochs": 8, "batch": 8192, "label_cap": 64.0,
+                    "eps": lp.eps, "normalized": lp.normalize,
                     "loss_per_epoch": [round(float(x), 6) for x in losses.cpu().tolist()],
                     "label_rate": lp.label_rate}
     _, out["proposal_ms"] = event_ms(lp.build_proposal, stream)  # inference, h, q-scan

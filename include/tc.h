@@ -266,13 +266,19 @@ tc_status tc_autotune(const tc_graph *g, const tc_weights *const *w, int32_t n_d
 #define TC_MLP_PARAMS 4801
 
 /* Features of every scan position p (centre edge (u, v, t)) into feat
- * (device, [m][8] bfloat16 bit patterns, 16 bytes per edge):
+ * (device, [m][8] bfloat16 bit patterns, 16 bytes per edge, 16-byte aligned):
  *   0 ln(1+a)  1 ln(1+b)  2 ln(1+a b)  3 (t - earliest time of u's in-window)/delta
  *   4 (latest time of v's out-window - t)/delta  5 ln(1 + #u->v edges with time
- *   in [t-delta, t+delta])  6 the same for v->u  7 ln(1 + #out-edges of u in
- *   [t, t+delta]); 3 and 4 are 0 for an empty window or delta = 0.
- * Errors: TC_E_ARG for null pointers or a weight set of another graph. */
-tc_status tc_edge_features(const tc_graph *g, const tc_weights *w, uint16_t *feat, void *stream);
+ *   in [t-delta, t+delta])  6 the same for v->u  7 ln(1 + M_in M_out) / 2 with
+ *   M_in the mean of min(indeg(x), 65535)^2 over u's in-window edges x -> u and
+ *   M_out the mean of min(outdeg(y), 65535)^2 over v's out-window edges v -> y
+ *   (0 for an empty window); 3 and 4 are 0 for an empty window or delta = 0.
+ * ws holds tc_features_workspace_bytes(m) bytes of scratch (prefix sums).
+ * Errors: TC_E_ARG for null pointers or a weight set of another graph,
+ * TC_E_WORKSPACE. */
+tc_status tc_features_workspace_bytes(int64_t m, size_t *bytes);
+tc_status tc_edge_features(const tc_graph *g, const tc_weights *w, uint16_t *feat, void *ws,
+                           size_t ws_bytes, void *stream);
 
 /* g[i] = network output for feature row i, i < n (device arrays). */
 tc_status tc_mlp_forward(const float *params, const uint16_t *feat, int64_t n, float *g,
@@ -284,14 +290,16 @@ tc_status tc_mlp_workspace_bytes(int64_t n, size_t *bytes);
 /* Mean binary cross-entropy (*loss, device float) and its gradient
  * (grad, device [TC_MLP_PARAMS]) over n labels: label i uses feature row
  * rows[i] of the n_feat rows of feat (rows may be NULL: row i, then
- * n <= n_feat) and y_i = [X[i] > 0] (X device [n], e.g. per-sample counts
- * and centre positions of the method's sampler).  Labels whose row is
- * >= n_feat are ignored (they add nothing; the mean still divides by n).
- * Deterministic for a given n.  Errors: TC_E_ARG (null pointers, n < 1 or
- * n >= 2^31), TC_E_WORKSPACE. */
+ * n <= n_feat) and the closure outcome X[i] (X device [n], e.g. per-sample
+ * counts and centre positions of the method's sampler): y_i = [X[i] > 0]
+ * when label_cap = 0, else the soft label min(1, X[i] / label_cap) in
+ * float32.  Labels whose row is >= n_feat are ignored (they add nothing;
+ * the mean still divides by n).  Deterministic for a given n.
+ * Errors: TC_E_ARG (null pointers, n < 1 or n >= 2^31, label_cap < 0),
+ * TC_E_WORKSPACE. */
 tc_status tc_mlp_grad(const float *params, const uint16_t *feat, int64_t n_feat,
-                      const uint32_t *rows, const uint64_t *X, int64_t n, float *grad,
-                      float *loss, void *ws, size_t ws_bytes, void *stream);
+                      const uint32_t *rows, const uint64_t *X, int64_t n, float label_cap,
+                      float *grad, float *loss, void *ws, size_t ws_bytes, void *stream);
 
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected for the
  * 1-based step) on params with moments opt[0..P) and opt[P..2P) (device,
@@ -305,8 +313,8 @@ tc_status tc_mlp_adam(float *params, float *opt, const float *grad, int64_t step
  * (device [epochs], may be NULL) receives each epoch's mean loss.
  * Enqueue only.  Errors as tc_mlp_grad; batch in [32, 2^20]. */
 tc_status tc_mlp_train(float *params, float *opt, const uint16_t *feat, int64_t n_feat,
-                       const uint32_t *rows, const uint64_t *X, int64_t n, int32_t batch,
-                       int32_t epochs, float lr, uint64_t seed, int64_t step0,
+                       const uint32_t *rows, const uint64_t *X, int64_t n, float label_cap,
+                       int32_t batch, int32_t epochs, float lr, uint64_t seed, int64_t step0,
                        float *loss_per_epoch, void *ws, size_t ws_bytes, void *stream);
 
 /* h[p] = max(1, floor((eps + (1 - eps) x[p]) * 2^s + 1/2)) with

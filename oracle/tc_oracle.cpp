@@ -499,7 +499,11 @@ int or_proposal_scan(void* hg, const uint32_t* a, const uint32_t* b, const uint3
 //   4 (t_last - t) / delta, t_last the latest time in v's out-window
 //   5 ln(1 + #edges u -> v with time in [t - delta, t + delta])
 //   6 ln(1 + #edges v -> u with time in [t - delta, t + delta])
-//   7 ln(1 + #edges out of u with time in [t, t + delta])
+//   7 ln(1 + M_in * M_out) / 2, with M_in the mean over u's in-window
+//     edges (x -> u) of min(indeg(x), 65535)^2 and M_out the mean over v's
+//     out-window edges (v -> y) of min(outdeg(y), 65535)^2 (0 if a window
+//     is empty): how heavy the closing pairs y -> x of the paths through
+//     the edge can be
 // Features 3 and 4 are 0 when their window is empty or delta = 0.
 void or_features(void* hg, int64_t delta, const uint32_t* lo_in, const uint32_t* a,
                  const uint32_t* lo_out, const uint32_t* b, double* F, int nthreads) {
@@ -528,10 +532,22 @@ void or_features(void* hg, int64_t delta, const uint32_t* lo_in, const uint32_t*
                : 0.0;
     f[5] = std::log1p((double)pair_count(u, v, t - delta, t + delta));
     f[6] = std::log1p((double)pair_count(v, u, t - delta, t + delta));
-    auto ob = G.out_t.begin();
-    const int64_t d0 = std::lower_bound(ob + G.out_off[u], ob + G.out_off[u + 1], t) - ob;
-    const int64_t d1 = std::upper_bound(ob + G.out_off[u], ob + G.out_off[u + 1], t + delta) - ob;
-    f[7] = std::log1p((double)(d1 - d0));
+    auto cap2 = [](uint64_t d) -> uint64_t {
+      const uint64_t c = d < 65535u ? d : 65535u;
+      return c * c;
+    };
+    uint64_t s_in = 0, s_out = 0;
+    for (uint32_t j = 0; j < a[p]; ++j) {
+      const int32_t x = G.in_src[lo_in[p] + j];
+      s_in += cap2(G.in_off[x + 1] - G.in_off[x]);
+    }
+    for (uint32_t j = 0; j < b[p]; ++j) {
+      const int32_t y = G.out_dst[lo_out[p] + j];
+      s_out += cap2(G.out_off[y + 1] - G.out_off[y]);
+    }
+    const double m_in = a[p] ? (double)s_in / (double)a[p] : 0.0;
+    const double m_out = b[p] ? (double)s_out / (double)b[p] : 0.0;
+    f[7] = 0.5 * std::log1p(m_in * m_out);
   }
 }
 

@@ -26,7 +26,7 @@ _STATUS_NAMES = {0: "TC_OK", -1: "TC_E_ARG", -2: "TC_E_RANGE", -3: "TC_E_OVERFLO
 EXPORTED = ["tc_version", "tc_graph_workspace_bytes", "tc_build_graph",
             "tc_weights_workspace_bytes", "tc_path_weights", "tc_sample_workspace_bytes",
             "tc_sample_estimate", "tc_batch_workspace_bytes", "tc_batch_estimate",
-            "tc_autotune", "tc_edge_features", "tc_mlp_forward", "tc_mlp_workspace_bytes",
+            "tc_autotune", "tc_features_workspace_bytes", "tc_edge_features", "tc_mlp_forward", "tc_mlp_workspace_bytes",
             "tc_mlp_grad", "tc_mlp_adam", "tc_mlp_train", "tc_quantize_proposal",
             "tc_proposal_workspace_bytes", "tc_proposal_weights", "tc_timing_enable",
             "tc_timing_reset", "tc_timing_read"]
@@ -117,13 +117,15 @@ def lib():
                                   I32, U64, U64, _P, SZ, _P, _P, ctypes.POINTER(tc_tuning),
                                   ctypes.POINTER(ctypes.c_double)]
         F32 = ctypes.c_float
-        L.tc_edge_features.argtypes = [ctypes.POINTER(tc_graph), ctypes.POINTER(tc_weights), _P, _P]
+        L.tc_features_workspace_bytes.argtypes = [I64, ctypes.POINTER(SZ)]
+        L.tc_edge_features.argtypes = [ctypes.POINTER(tc_graph), ctypes.POINTER(tc_weights), _P,
+                                       _P, SZ, _P]
         L.tc_mlp_forward.argtypes = [_P, _P, I64, _P, _P]
         L.tc_mlp_workspace_bytes.argtypes = [I64, ctypes.POINTER(SZ)]
-        L.tc_mlp_grad.argtypes = [_P, _P, I64, _P, _P, I64, _P, _P, _P, SZ, _P]
+        L.tc_mlp_grad.argtypes = [_P, _P, I64, _P, _P, I64, F32, _P, _P, _P, SZ, _P]
         L.tc_mlp_adam.argtypes = [_P, _P, _P, I64, F32, _P]
-        L.tc_mlp_train.argtypes = [_P, _P, _P, I64, _P, _P, I64, I32, I32, F32, U64, I64, _P, _P,
-                                   SZ, _P]
+        L.tc_mlp_train.argtypes = [_P, _P, _P, I64, _P, _P, I64, F32, I32, I32, F32, U64, I64, _P,
+                                   _P, SZ, _P]
         L.tc_quantize_proposal.argtypes = [ctypes.POINTER(tc_weights), _P, F32, _P, _P, _P]
         L.tc_proposal_workspace_bytes.argtypes = [I64, ctypes.POINTER(SZ)]
         L.tc_proposal_weights.argtypes = [ctypes.POINTER(tc_graph), ctypes.POINTER(tc_weights),
@@ -428,8 +430,12 @@ def tc_autotune(graph: Graph, weights, motifs, k_probe: int, seed: int = 1, stre
 def tc_edge_features(graph: Graph, weights: Weights, stream=None) -> torch.Tensor:
     """[m, 8] bfloat16 features (int16 storage of the bit patterns)."""
     feat = torch.empty((graph.m, 8), dtype=torch.int16, device=graph.ws.device)
+    b = ctypes.c_size_t(0)
+    _check(lib().tc_features_workspace_bytes(graph.m, ctypes.byref(b)),
+           "tc_features_workspace_bytes")
+    ws = torch.empty(b.value, dtype=torch.uint8, device=graph.ws.device)
     _check(lib().tc_edge_features(ctypes.byref(graph.c), ctypes.byref(weights.c), _ptr(feat),
-                                  _stream(stream)), "tc_edge_features")
+                                  _ptr(ws), b.value, _stream(stream)), "tc_edge_features")
     return feat
 
 
@@ -448,7 +454,8 @@ def mlp_workspace_bytes(n: int) -> int:
     return b.value
 
 
-def tc_mlp_grad(params, feat, rows, X, n: int | None = None, stream=None):
+def tc_mlp_grad(params, feat, rows, X, n: int | None = None, label_cap: float = 0.0,
+                stream=None):
     """(grad [4801] float32, loss [1] float32) of the mean BCE over n labels."""
     n = X.shape[0] if n is None else n
     dev = feat.device
@@ -457,8 +464,8 @@ def tc_mlp_grad(params, feat, rows, X, n: int | None = None, stream=None):
     nb = mlp_workspace_bytes(n)
     ws = torch.empty(nb, dtype=torch.uint8, device=dev)
     _check(lib().tc_mlp_grad(_ptr(params), _ptr(feat), int(feat.shape[0]), _ptr(rows), _ptr(X),
-                             int(n), _ptr(grad), _ptr(loss), _ptr(ws), nb, _stream(stream)),
-           "tc_mlp_grad")
+                             int(n), float(label_cap), _ptr(grad), _ptr(loss), _ptr(ws), nb,
+                             _stream(stream)), "tc_mlp_grad")
     return grad, loss
 
 
@@ -468,7 +475,7 @@ def tc_mlp_adam(params, opt, grad, step: int, lr: float, stream=None) -> None:
 
 
 def tc_mlp_train(params, opt, feat, rows, X, batch: int, epochs: int, lr: float, seed: int,
-                 step0: int = 0, stream=None) -> torch.Tensor:
+                 step0: int = 0, label_cap: float = 0.0, stream=None) -> torch.Tensor:
     """Train in place; returns the mean loss of each epoch (device float32)."""
     n = X.shape[0]
     dev = feat.device
@@ -476,9 +483,9 @@ def tc_mlp_train(params, opt, feat, rows, X, batch: int, epochs: int, lr: float,
     nb = mlp_workspace_bytes(batch)
     ws = torch.empty(nb, dtype=torch.uint8, device=dev)
     _check(lib().tc_mlp_train(_ptr(params), _ptr(opt), _ptr(feat), int(feat.shape[0]), _ptr(rows),
-                              _ptr(X), int(n), int(batch), int(epochs), float(lr), int(seed),
-                              int(step0), _ptr(losses), _ptr(ws), ws.numel(), _stream(stream)),
-           "tc_mlp_train")
+                              _ptr(X), int(n), float(label_cap), int(batch), int(epochs),
+                              float(lr), int(seed), int(step0), _ptr(losses), _ptr(ws),
+                              ws.numel(), _stream(stream)), "tc_mlp_train")
     return losses
 
 

@@ -185,10 +185,16 @@ tc_status tc_autotune(const tc_graph* g, const tc_weights* const* w, int32_t n_d
 static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 static const int64_t kMaxLabels = (int64_t)1 << 31;
 
-tc_status tc_edge_features(const tc_graph* g, const tc_weights* w, uint16_t* feat,
-                           void* stream) {
-  if (!g || !w || !feat || w->m != g->m || !aligned16(feat)) return TC_E_ARG;
-  return tc::edge_features(g, w, feat, (hipStream_t)stream);
+tc_status tc_features_workspace_bytes(int64_t m, size_t* bytes) {
+  if (!bytes || m < 0) return TC_E_ARG;
+  *bytes = tc::features_workspace_bytes(m);
+  return TC_OK;
+}
+
+tc_status tc_edge_features(const tc_graph* g, const tc_weights* w, uint16_t* feat, void* ws,
+                           size_t ws_bytes, void* stream) {
+  if (!g || !w || !feat || !ws || w->m != g->m || !aligned16(feat)) return TC_E_ARG;
+  return tc::edge_features(g, w, feat, ws, ws_bytes, (hipStream_t)stream);
 }
 
 tc_status tc_mlp_forward(const float* params, const uint16_t* feat, int64_t n, float* g,
@@ -204,12 +210,12 @@ tc_status tc_mlp_workspace_bytes(int64_t n, size_t* bytes) {
 }
 
 tc_status tc_mlp_grad(const float* params, const uint16_t* feat, int64_t n_feat,
-                      const uint32_t* rows, const uint64_t* X, int64_t n, float* grad,
-                      float* loss, void* ws, size_t ws_bytes, void* stream) {
+                      const uint32_t* rows, const uint64_t* X, int64_t n, float label_cap,
+                      float* grad, float* loss, void* ws, size_t ws_bytes, void* stream) {
   if (!params || !feat || !X || !grad || !loss || !ws || n < 1 || n >= kMaxLabels ||
-      n_feat < 1 || (!rows && n > n_feat) || !aligned16(feat))
+      n_feat < 1 || (!rows && n > n_feat) || !aligned16(feat) || !(label_cap >= 0.0f))
     return TC_E_ARG;
-  return tc::mlp_grad(params, feat, n_feat, rows, X, n, grad, loss, ws, ws_bytes,
+  return tc::mlp_grad(params, feat, n_feat, rows, X, n, label_cap, grad, loss, ws, ws_bytes,
                       (hipStream_t)stream);
 }
 
@@ -220,15 +226,15 @@ tc_status tc_mlp_adam(float* params, float* opt, const float* grad, int64_t step
 }
 
 tc_status tc_mlp_train(float* params, float* opt, const uint16_t* feat, int64_t n_feat,
-                       const uint32_t* rows, const uint64_t* X, int64_t n, int32_t batch,
-                       int32_t epochs, float lr, uint64_t seed, int64_t step0,
+                       const uint32_t* rows, const uint64_t* X, int64_t n, float label_cap,
+                       int32_t batch, int32_t epochs, float lr, uint64_t seed, int64_t step0,
                        float* loss_per_epoch, void* ws, size_t ws_bytes, void* stream) {
   if (!params || !opt || !feat || !X || !ws || n < 1 || n >= kMaxLabels || n_feat < 1 ||
       (!rows && n > n_feat) || batch < 32 || batch > (1 << 20) || epochs < 1 || step0 < 0 ||
-      !aligned16(feat))
+      !aligned16(feat) || !(label_cap >= 0.0f))
     return TC_E_ARG;
-  return tc::mlp_train(params, opt, feat, n_feat, rows, X, n, batch, epochs, lr, seed, step0,
-                       loss_per_epoch, ws, ws_bytes, (hipStream_t)stream);
+  return tc::mlp_train(params, opt, feat, n_feat, rows, X, n, label_cap, batch, epochs, lr,
+                       seed, step0, loss_per_epoch, ws, ws_bytes, (hipStream_t)stream);
 }
 
 tc_status tc_quantize_proposal(const tc_weights* w, const float* g, float eps, float* g_max,

@@ -62,18 +62,20 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
 size_t proposal_workspace_bytes(int64_t m);
 tc_status proposal_weights(const tc_weights* w, const uint32_t* h, void* ws, size_t ws_bytes,
                            hipStream_t st, tc_weights* wq);
-tc_status edge_features(const tc_graph* g, const tc_weights* w, uint16_t* feat, hipStream_t st);
+size_t features_workspace_bytes(int64_t m);
+tc_status edge_features(const tc_graph* g, const tc_weights* w, uint16_t* feat, void* ws,
+                        size_t ws_bytes, hipStream_t st);
 tc_status mlp_forward(const float* params, const uint16_t* feat, int64_t n, float* g,
                       hipStream_t st);
 size_t mlp_workspace_bytes(int64_t batch);
 tc_status mlp_grad(const float* params, const uint16_t* feat, int64_t n_feat,
-                   const uint32_t* rows, const uint64_t* X, int64_t n, float* grad, float* loss,
-                   void* ws, size_t ws_bytes, hipStream_t st);
+                   const uint32_t* rows, const uint64_t* X, int64_t n, float label_cap,
+                   float* grad, float* loss, void* ws, size_t ws_bytes, hipStream_t st);
 tc_status mlp_adam(float* params, float* opt, const float* grad, int64_t step, float lr,
                    hipStream_t st);
 tc_status mlp_train(float* params, float* opt, const uint16_t* feat, int64_t n_feat,
-                    const uint32_t* rows, const uint64_t* X, int64_t n, int32_t batch,
-                    int32_t epochs, float lr,
+                    const uint32_t* rows, const uint64_t* X, int64_t n, float label_cap,
+                    int32_t batch, int32_t epochs, float lr,
                     uint64_t seed, int64_t step0, float* loss_per_epoch, void* ws,
                     size_t ws_bytes, hipStream_t st);
 tc_status quantize_proposal(const tc_weights* w, const float* g, float eps, float* gmax,

@@ -7,7 +7,8 @@
 //                  edge (sizes of its in- and out-windows and of the path
 //                  weight, the spans of the two windows relative to delta,
 //                  the multi-edge counts of (u, v) and (v, u) around t, and
-//                  u's out-degree in [t, t + delta]), stored as bfloat16.
+//                  the mean squared degree of the windows' far endpoints from
+//                  prefix sums, k_deg2_*), stored as bfloat16.
 //   k_mlp_forward  g = sigmoid(w3 . relu(W2 relu(W1 f + b1) + b2) + b3) for
 //                  32 edges per wavefront: both hidden layers on MFMA
 //                  (bfloat16 operands, float32 accumulation).  The
@@ -16,7 +17,8 @@
 //                  order of the contraction index is free, so the weights are
 //                  loaded in the order in which each lane holds the
 //                  activations.
-//   k_mlp_grad     mean binary cross-entropy against y = [X > 0] and its
+//   k_mlp_grad     mean binary cross-entropy against y = [X > 0] (or the
+//                  soft label min(1, X / cap)) and its
 //                  gradient, per block (fixed row-to-block assignment):
 //                  the same forward, dH1 = W2^T dZ2 on MFMA from registers,
 //                  and the weight gradients dW2 = dZ2 H1^T and
@@ -82,13 +84,98 @@ __device__ __forceinline__ bf16x8 pack8(const uint16_t (&e)[8]) {
 }
 
 // ---------------------------------------------------------------- features --
+// Squared (capped) degree of the far endpoint of each adjacency entry: the
+// source of an in-CSR entry (its in-degree) or the target of an out-CSR
+// entry (its out-degree).  Capping at 2^16 - 1 keeps a window's sum below
+// 2^63, so window sums taken from wrapping 64-bit prefix sums are exact.
+struct Deg2 {
+  const int32_t* end;   // in_src or out_dst
+  const uint32_t* off;  // in_off or out_off
+  __device__ __forceinline__ uint64_t operator()(int64_t i) const {
+    const int32_t x = end[i];
+    uint64_t d = (uint64_t)(off[x + 1] - off[x]);
+    d = d < 65535u ? d : 65535u;
+    return d * d;
+  }
+};
+
+constexpr int kPBlock = 256, kPItems = 8, kPTile = kPBlock * kPItems;
+
+// per tile: wrapping sum of the values
+__global__ __launch_bounds__(kPBlock) void k_deg2_tiles(Deg2 f, int64_t m,
+                                                       uint64_t* __restrict__ tile_sums) {
+  __shared__ uint64_t s_w[kPBlock / kWave];
+  uint64_t s = 0;
+  const int64_t p0 = (int64_t)blockIdx.x * kPTile + (int64_t)threadIdx.x * kPItems;
+#pragma unroll
+  for (int j = 0; j < kPItems; ++j)
+    if (p0 + j < m) s += f(p0 + j);
+  s = wave_sum64(s);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+    for (int w = 0; w < kPBlock / kWave; ++w) t += s_w[w];
+    tile_sums[blockIdx.x] = t;
+  }
+}
+
+// one block: exclusive wrapping scan of the tile sums (in place)
+__global__ __launch_bounds__(1024) void k_deg2_scan_tiles(uint64_t* __restrict__ tile_sums,
+                                                          int64_t ntiles) {
+  __shared__ uint64_t s_w[16];
+  __shared__ uint64_t s_carry;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < ntiles; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const uint64_t v = i < ntiles ? tile_sums[i] : 0;
+    const uint64_t inc = wave_inclusive_scan(v);
+    if (lane == 63) s_w[wave] = inc;
+    __syncthreads();
+    uint64_t pre = s_carry;
+    for (int w = 0; w < wave; ++w) pre += s_w[w];
+    if (i < ntiles) tile_sums[i] = pre + inc - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) s_carry = pre + inc;
+    __syncthreads();
+  }
+}
+
+// per tile: exclusive prefix sums ps[i] (wrapping), ps[m] = total
+__global__ __launch_bounds__(kPBlock) void k_deg2_apply(Deg2 f, int64_t m,
+                                                       const uint64_t* __restrict__ tile_off,
+                                                       uint64_t* __restrict__ ps) {
+  __shared__ uint64_t s_w[kPBlock / kWave];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t p0 = (int64_t)blockIdx.x * kPTile + (int64_t)threadIdx.x * kPItems;
+  uint64_t v[kPItems];
+  uint64_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kPItems; ++j) {
+    v[j] = p0 + j < m ? f(p0 + j) : 0;
+    s += v[j];
+  }
+  const uint64_t inc = wave_inclusive_scan(s);
+  if (lane == 63) s_w[wave] = inc;
+  __syncthreads();
+  uint64_t run = tile_off[blockIdx.x] + inc - s;
+  for (int q = 0; q < wave; ++q) run += s_w[q];
+#pragma unroll
+  for (int j = 0; j < kPItems; ++j) {
+    if (p0 + j <= m) ps[p0 + j] = run;  // p0 + j == m stores the total
+    run += v[j];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_features(
     const int32_t* __restrict__ out_src, const int32_t* __restrict__ out_dst,
-    const int64_t* __restrict__ out_t, const uint32_t* __restrict__ out_off,
-    const int64_t* __restrict__ in_t, const int64_t* __restrict__ pair_t,
-    const PairSlot* __restrict__ pair_hash, int32_t pair_hash_log2,
-    const uint32_t* __restrict__ lo_in, const uint32_t* __restrict__ a,
-    const uint32_t* __restrict__ lo_out, const uint32_t* __restrict__ b, int64_t delta,
+    const int64_t* __restrict__ out_t, const int64_t* __restrict__ in_t,
+    const int64_t* __restrict__ pair_t, const PairSlot* __restrict__ pair_hash,
+    int32_t pair_hash_log2, const uint32_t* __restrict__ lo_in, const uint32_t* __restrict__ a,
+    const uint32_t* __restrict__ lo_out, const uint32_t* __restrict__ b,
+    const uint64_t* __restrict__ ps_in, const uint64_t* __restrict__ ps_out, int64_t delta,
     int64_t m, uint4* __restrict__ feat) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= m) return;
@@ -108,9 +195,11 @@ __global__ __launch_bounds__(256) void k_features(
   pair_run(pair_hash, pair_hash_log2, v, u, &r0, &r1);
   f[6] = log1pf((float)(upper_bound<int64_t>(pair_t, r0, r1, t + delta) -
                         lower_bound<int64_t>(pair_t, r0, r1, t - delta)));
-  const uint32_t s0 = out_off[u], s1 = out_off[u + 1];
-  f[7] = log1pf((float)(upper_bound<int64_t>(out_t, s0, s1, t + delta) -
-                        lower_bound<int64_t>(out_t, s0, s1, t)));
+  // mean squared degree of the window ends (exact wrapping window sums)
+  const uint32_t li = lo_in[p], lo = lo_out[p];
+  const double m_in = ap ? (double)(ps_in[li + ap] - ps_in[li]) / (double)ap : 0.0;
+  const double m_out = bp ? (double)(ps_out[lo + bp] - ps_out[lo]) / (double)bp : 0.0;
+  f[7] = (float)(0.5 * log1p(m_in * m_out));
   uint32_t w[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -258,6 +347,7 @@ struct BatchMap {
   uint64_t mul, add, n, start;
   uint32_t count;
   uint64_t n_feat;  // feature rows; labels whose row is outside are ignored
+  float label_cap;  // 0: y = [X > 0]; else y = min(1, X / label_cap)
 };
 
 // mul < n and start + i < n with n < 2^31, so the product fits 64 bits
@@ -310,7 +400,9 @@ __global__ __launch_bounds__(kGradBlock) void k_mlp_grad(const float* __restrict
     if (in_batch) {
       const uint64_t idx = batch_index(bm, item);
       row = rows ? (int64_t)rows[idx] : (int64_t)idx;
-      y = X[idx] != 0 ? 1.0f : 0.0f;
+      const uint64_t xv = X[idx];
+      y = bm.label_cap > 0.0f ? fminf(1.0f, __fdiv_rn((float)xv, bm.label_cap))
+                              : (xv != 0 ? 1.0f : 0.0f);
       valid = (uint64_t)row < bm.n_feat;
     }
     const s16x4 fb = valid ? load_feat4(feat, row, h) : s16x4{0, 0, 0, 0};
@@ -536,15 +628,44 @@ __global__ __launch_bounds__(256) void k_quantize(const float* __restrict__ g, i
 }
 
 // ------------------------------------------------------------- host side --
-tc_status edge_features(const tc_graph* g, const tc_weights* w, uint16_t* feat, hipStream_t st) {
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t features_workspace_bytes(int64_t m) {
+  const size_t ntiles = (size_t)((m + 1 + kPTile - 1) / kPTile);
+  return 2 * align256((size_t)(m + 1) * 8) + align256(ntiles * 8);
+}
+
+tc_status edge_features(const tc_graph* g, const tc_weights* w, uint16_t* feat, void* ws,
+                        size_t ws_bytes, hipStream_t st) {
   const int64_t m = g->m;
-  if (m > 0)
+  if (ws_bytes < features_workspace_bytes(m)) return TC_E_WORKSPACE;
+  if (m == 0) return TC_OK;
+  char* base = (char*)ws;
+  uint64_t* ps_in = (uint64_t*)base;
+  uint64_t* ps_out = (uint64_t*)(base + align256((size_t)(m + 1) * 8));
+  uint64_t* tiles = (uint64_t*)(base + 2 * align256((size_t)(m + 1) * 8));
+  // tiles cover indices 0..m so that the last one also stores ps[m]
+  const int64_t ntiles = (m + 1 + kPTile - 1) / kPTile;
+  const Deg2 fin{(const int32_t*)g->in_src, (const uint32_t*)g->in_off};
+  const Deg2 fout{(const int32_t*)g->out_dst, (const uint32_t*)g->out_off};
+  for (int side = 0; side < 2; ++side) {
+    const Deg2 f = side == 0 ? fin : fout;
+    uint64_t* ps = side == 0 ? ps_in : ps_out;
+    hipLaunchKernelGGL(k_deg2_tiles, dim3((unsigned)ntiles), dim3(kPBlock), 0, st, f, m, tiles);
+    hipLaunchKernelGGL(k_deg2_scan_tiles, dim3(1), dim3(1024), 0, st, tiles, ntiles);
+    hipLaunchKernelGGL(k_deg2_apply, dim3((unsigned)ntiles), dim3(kPBlock), 0, st, f, m,
+                       (const uint64_t*)tiles, ps);
+  }
+  {
+    TimedLaunch tl("k_features", st);
     hipLaunchKernelGGL(k_features, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st,
                        (const int32_t*)g->out_src, (const int32_t*)g->out_dst,
-                       (const int64_t*)g->out_t, (const uint32_t*)g->out_off,
-                       (const int64_t*)g->in_t, (const int64_t*)g->pair_t,
-                       (const PairSlot*)g->pair_hash, g->pair_hash_log2, w->lo_in, w->a,
-                       w->lo_out, w->b, w->delta, m, (uint4*)feat);
+                       (const int64_t*)g->out_t, (const int64_t*)g->in_t,
+                       (const int64_t*)g->pair_t, (const PairSlot*)g->pair_hash,
+                       g->pair_hash_log2, w->lo_in, w->a, w->lo_out, w->b,
+                       (const uint64_t*)ps_in, (const uint64_t*)ps_out, w->delta, m,
+                       (uint4*)feat);
+  }
   return hipGetLastError() == hipSuccess ? TC_OK : TC_E_HIP;
 }
 
@@ -585,10 +706,10 @@ static tc_status launch_grad(const float* params, const uint16_t* feat, const ui
 }
 
 tc_status mlp_grad(const float* params, const uint16_t* feat, int64_t n_feat, const uint32_t* rows,
-                   const uint64_t* X, int64_t n, float* grad, float* loss, void* ws,
-                   size_t ws_bytes, hipStream_t st) {
+                   const uint64_t* X, int64_t n, float label_cap, float* grad, float* loss,
+                   void* ws, size_t ws_bytes, hipStream_t st) {
   if (ws_bytes < mlp_workspace_bytes(n)) return TC_E_WORKSPACE;
-  const BatchMap bm{1, 0, (uint64_t)n, 0, (uint32_t)n, (uint64_t)n_feat};
+  const BatchMap bm{1, 0, (uint64_t)n, 0, (uint32_t)n, (uint64_t)n_feat, label_cap};
   float* partial = (float*)ws;
   tc_status s = launch_grad(params, feat, rows, X, bm, partial, st);
   if (s != TC_OK) return s;
@@ -630,8 +751,8 @@ static uint64_t gcd64(uint64_t a, uint64_t b) {
 }
 
 tc_status mlp_train(float* params, float* opt, const uint16_t* feat, int64_t n_feat,
-                    const uint32_t* rows, const uint64_t* X, int64_t n, int32_t batch,
-                    int32_t epochs, float lr,
+                    const uint32_t* rows, const uint64_t* X, int64_t n, float label_cap,
+                    int32_t batch, int32_t epochs, float lr,
                     uint64_t seed, int64_t step0, float* loss_per_epoch, void* ws,
                     size_t ws_bytes, hipStream_t st) {
   if (ws_bytes < mlp_workspace_bytes(batch)) return TC_E_WORKSPACE;
@@ -650,7 +771,7 @@ tc_status mlp_train(float* params, float* opt, const uint16_t* feat, int64_t n_f
     for (int64_t bi = 0; bi < nbatches; ++bi) {
       const uint64_t start = (uint64_t)bi * (uint64_t)batch;
       const uint32_t count = (uint32_t)std::min<int64_t>(batch, n - (int64_t)start);
-      const BatchMap bm{mul, add, (uint64_t)n, start, count, (uint64_t)n_feat};
+      const BatchMap bm{mul, add, (uint64_t)n, start, count, (uint64_t)n_feat, label_cap};
       tc_status s = launch_grad(params, feat, rows, X, bm, partial, st);
       if (s != TC_OK) return s;
       ++step;

@@ -65,7 +65,7 @@ def moments(result, weights: Weights, k: int, j: int = 0) -> Moments:
 
 
 class LearnedProposal:
-    def __init__(self, graph: Graph, weights: Weights, motif, eps: float = 0.05, seed: int = 1,
+    def __init__(self, graph: Graph, weights: Weights, motif, eps: float = 0.01, seed: int = 1,
                  normalize: bool = True):
         self.graph, self.weights, self.motif = graph, weights, motif
         self.eps, self.seed, self.normalize = eps, seed, normalize
@@ -82,15 +82,19 @@ class LearnedProposal:
                                stream_id=LABEL_STREAM, per_sample=True)
         return r
 
-    def fit(self, n_labels: int = 10**6, epochs: int = 6, batch: int = 8192, lr: float = 3e-3):
+    def fit(self, n_labels: int = 10**6, epochs: int = 8, batch: int = 8192, lr: float = 3e-3,
+            label_cap: float = 64.0):
+        """Train on closure outcomes: y = [X > 0], or min(1, X / label_cap)."""
         lab = self.collect_labels(n_labels)
         rate = int(lab.hits[0].item()) / n_labels
+        if label_cap > 0:  # mean soft label, roughly
+            rate = min(rate, lab.counts()[0] / n_labels / label_cap)
         dev = self.feat.device
         self.params = torch.from_numpy(init_params(self.seed, max(rate, 1e-4))).to(dev)
         self.opt = torch.zeros(2 * MLP_PARAMS, dtype=torch.float32, device=dev)
         X = lab.X[0]
         self.losses = tc_mlp_train(self.params, self.opt, self.feat, lab.P, X, batch, epochs, lr,
-                                   self.seed)
+                                   self.seed, label_cap=label_cap)
         self.label_rate = rate
         return self.losses
 

@@ -86,8 +86,9 @@ def test_mlp_forward_matches_oracle(tcb, torch_mod, n):
     assert err.max() <= 4e-3 and err.mean() <= 4e-4, (err.max(), err.mean())
 
 
-@pytest.mark.parametrize("n,with_rows", [(64, False), (1000, True), (20011, True)])
-def test_mlp_grad_matches_oracle(tcb, torch_mod, n, with_rows):
+@pytest.mark.parametrize("n,with_rows,cap", [(64, False, 0.0), (1000, True, 0.0),
+                                             (20011, True, 0.0), (5000, True, 3.0)])
+def test_mlp_grad_matches_oracle(tcb, torch_mod, n, with_rows, cap):
     from oracle import learn
     torch = torch_mod
     P, Fb, Pd, Fd = _net_inputs(torch, 3000, 100 + n)
@@ -95,9 +96,11 @@ def test_mlp_grad_matches_oracle(tcb, torch_mod, n, with_rows):
     rows = rng.integers(0, 3000, size=n).astype(np.uint32) if with_rows else np.arange(n, dtype=np.uint32)
     X = sg.random_counts(200 + n, n)
     grad, loss = tcb.tc_mlp_grad(Pd, Fd, torch.from_numpy(rows.view(np.int32)).cuda() if with_rows else None,
-                                 torch.from_numpy(X.view(np.int64)).cuda())
+                                 torch.from_numpy(X.view(np.int64)).cuda(), label_cap=cap)
     grad = grad.cpu().numpy().astype(np.float64)
-    lw, gw = learn.grad(P, _bf16_to_f64(Fb)[rows], (X > 0).astype(np.float64), bf16=True)
+    y = ((X > 0).astype(np.float64) if cap == 0 else
+         np.minimum(np.float32(1), X.astype(np.float32) / np.float32(cap)).astype(np.float64))
+    lw, gw = learn.grad(P, _bf16_to_f64(Fb)[rows], y, bf16=True)
     assert abs(float(loss.item()) - lw) <= 1e-4 * abs(lw) + 1e-6
     blocks = [(learn.OFF_W1, learn.OFF_B1), (learn.OFF_B1, learn.OFF_W2),
               (learn.OFF_W2, learn.OFF_B2), (learn.OFF_B2, learn.OFF_W3),

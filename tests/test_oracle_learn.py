@@ -150,8 +150,15 @@ def test_features_by_direct_scan():
                                        and abs(int(g.t[i]) - t) <= delta)),
                         math.log1p(sum(1 for i in range(g.m) if g.src[i] == v and g.dst[i] == u
                                        and abs(int(g.t[i]) - t) <= delta)),
-                        math.log1p(sum(1 for i in range(g.m) if g.src[i] == u
-                                       and t <= g.t[i] <= t + delta))]
+                        0.5 * math.log1p(
+                            (np.mean([min(int(np.sum(g.dst == g.src[i])), 65535) ** 2
+                                      for i in range(g.m)
+                                      if g.dst[i] == u and t - delta <= g.t[i] <= t])
+                             if a else 0.0) *
+                            (np.mean([min(int(np.sum(g.src == g.dst[i])), 65535) ** 2
+                                      for i in range(g.m)
+                                      if g.src[i] == v and t <= g.t[i] <= t + delta])
+                             if b else 0.0))]
                 assert np.allclose(F[p], want, rtol=1e-15, atol=0), (seed, delta, p)
 
 
