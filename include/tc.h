@@ -96,6 +96,10 @@ typedef struct tc_graph {
                                          u32 end}, open addressing, linear probing,
                                          empty key = all ones                     */
   int32_t pair_hash_log2;
+  void *out_rec, *in_rec;             /* [m] 16-byte records of the two CSRs, one
+                                         cache-line access per sampled end edge:
+                                         {i32 other end (dst resp. src), i32 eid,
+                                         i64 t}                                  */
 } tc_graph;
 
 /* Per-edge window metadata and the exact integer CDF of the path weights,
@@ -119,6 +123,10 @@ typedef struct tc_weights {
                                          proposal weight set (tc_proposal_weights)
                                          the integer factor h[p] >= 1 per edge, and
                                          S is then the scan of q = a * b * h      */
+  void *prec;                         /* [m] 32-byte path records {u32 lo_in, a,
+                                         lo_out, b; i32 u, v; i64 t} of the scan
+                                         positions (what the sampler needs of the
+                                         centre edge, in one access)              */
 } tc_weights;
 
 /* Outputs of tc_sample_estimate, all (device), caller-allocated.

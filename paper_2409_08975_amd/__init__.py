@@ -61,13 +61,14 @@ class tc_graph(ctypes.Structure):
                 ("out_eid", _P), ("out_t", _P), ("in_off", _P), ("in_src", _P), ("in_eid", _P),
                 ("in_dst", _P), ("in_t", _P), ("out_to_in", _P), ("pair_dst", _P),
                 ("pair_eid", _P), ("pair_t", _P),
-                ("status", _P), ("pair_hash", _P), ("pair_hash_log2", ctypes.c_int32)]
+                ("status", _P), ("pair_hash", _P), ("pair_hash_log2", ctypes.c_int32),
+                ("out_rec", _P), ("in_rec", _P)]
 
 
 class tc_weights(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_int64), ("m", ctypes.c_int64), ("lo_in", _P), ("a", _P),
                 ("lo_out", _P), ("b", _P), ("S", _P), ("status", _P), ("scratch", _P),
-                ("h", _P)]
+                ("h", _P), ("prec", _P)]
 
 
 class tc_result(ctypes.Structure):

@@ -343,14 +343,17 @@ __global__ __launch_bounds__(256) void k_gather_order(
     const uint32_t* __restrict__ skeys, const int32_t* __restrict__ order, int64_t m,
     const int32_t* __restrict__ other_v, const int64_t* __restrict__ t,
     int32_t* __restrict__ key_col, int32_t* __restrict__ other_col, int64_t* __restrict__ t_col,
-    int32_t* __restrict__ eid_col) {
+    int32_t* __restrict__ eid_col, uint4* __restrict__ rec) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) {
     int32_t e = order[i];
     if (key_col) key_col[i] = (int32_t)skeys[i];
-    if (other_col) other_col[i] = other_v[e];
-    t_col[i] = t[e];
+    const int32_t o = other_v[e];
+    const int64_t te = t[e];
+    if (other_col) other_col[i] = o;
+    t_col[i] = te;
     eid_col[i] = e;
+    if (rec) rec[i] = make_uint4((uint32_t)o, (uint32_t)e, (uint32_t)te, (uint32_t)(te >> 32));
   }
 }
 
@@ -498,14 +501,17 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ k,
                                               int64_t tmin, int32_t* __restrict__ key_col,
                                               int32_t* __restrict__ other_col,
                                               int64_t* __restrict__ t_col,
-                                              int32_t* __restrict__ eid_col) {
+                                              int32_t* __restrict__ eid_col,
+                                              uint4* __restrict__ rec) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) {
     const uint3 r = v[i];
     if (key_col) key_col[i] = (int32_t)k[i];
+    const int64_t te = tmin + (int64_t)r.z;
     other_col[i] = (int32_t)r.y;
-    t_col[i] = tmin + (int64_t)r.z;
+    t_col[i] = te;
     eid_col[i] = (int32_t)r.x;
+    if (rec) rec[i] = make_uint4(r.y, r.x, (uint32_t)te, (uint32_t)(te >> 32));
   }
 }
 
@@ -514,7 +520,7 @@ static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct GraphLayout {
   size_t out_off, in_off, out_src, out_dst, out_eid, out_t, in_src, in_eid, in_dst, in_t,
-      out_to_in, pair_dst,
+      out_to_in, pair_dst, out_rec, in_rec,
       pair_eid, pair_t, pair_hash, status, tminmax, keys0, keys1, vals0, vals1, hist, part,
       part_elems, rk[3], rv[3], total;
 };
@@ -544,6 +550,8 @@ static GraphLayout graph_layout(int32_t n, int64_t m) {
   L.pair_dst = take(M * 4);
   L.pair_eid = take(M * 4);
   L.pair_t = take(M * 8);
+  L.out_rec = take(M * 16);
+  L.in_rec = take(M * 16);
   L.pair_hash = take(sizeof(PairSlot) << pair_hash_log2(m));
   L.status = take(4);
   L.tminmax = take(16);
@@ -615,6 +623,8 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   g->status = (uint32_t*)(base + L.status);
   g->pair_hash = (void*)(base + L.pair_hash);
   g->pair_hash_log2 = pair_hash_log2(m);
+  g->out_rec = (void*)(base + L.out_rec);
+  g->in_rec = (void*)(base + L.in_rec);
   uint64_t* tminmax = (uint64_t*)(base + L.tminmax);
   void* keys0 = base + L.keys0;
   void* keys1 = base + L.keys1;
@@ -681,7 +691,7 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     if (R < 0) return TC_E_WORKSPACE;
     hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint32_t*)rk[R],
                        (const uint3*)rv[R], m, tmin, g->out_src, g->out_dst, g->out_t,
-                       g->out_eid);
+                       g->out_eid, (uint4*)g->out_rec);
     hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
                        (const uint32_t*)rk[R], m, n, g->out_off);
     // in-CSR: stable by dst
@@ -690,7 +700,8 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     const int I = sort_rec(X, Y, vbits);
     if (I < 0) return TC_E_WORKSPACE;
     hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint32_t*)rk[I],
-                       (const uint3*)rv[I], m, tmin, g->in_dst, g->in_src, g->in_t, g->in_eid);
+                       (const uint3*)rv[I], m, tmin, g->in_dst, g->in_src, g->in_t, g->in_eid,
+                       (uint4*)g->in_rec);
     hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
                        (const uint32_t*)rk[I], m, n, g->in_off);
     // out_to_in[p] = in-CSR position of out_eid[p] (through the free key buffer of T)
@@ -706,7 +717,7 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     if (Pr < 0) return TC_E_WORKSPACE;
     hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint32_t*)rk[Pr],
                        (const uint3*)rv[Pr], m, tmin, (int32_t*)nullptr, g->pair_dst,
-                       g->pair_t, g->pair_eid);
+                       g->pair_t, g->pair_eid, (uint4*)nullptr);
     const int F0 = (Pr + 1) % 3, F1 = (Pr + 2) % 3;  // two free key buffers
     if (!build_pair_hash(rk[Pr], g, m, rk[F0], rk[F1], part, pe, tab, st)) return TC_E_WORKSPACE;
     if (hipGetLastError() != hipSuccess) return TC_E_HIP;
@@ -750,7 +761,7 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     int32_t* sv = w ? vals1 : vals0;
     hipLaunchKernelGGL(k_gather_order, dim3(eb), dim3(256), 0, st, (const uint32_t*)sk,
                        (const int32_t*)sv, m, dst, t, g->out_src, g->out_dst, g->out_t,
-                       g->out_eid);
+                       g->out_eid, (uint4*)g->out_rec);
     hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
                        (const uint32_t*)sk, m, n, g->out_off);
   } else {
@@ -766,7 +777,7 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     int32_t* sv = w ? vals1 : vals0;
     hipLaunchKernelGGL(k_gather_order, dim3(eb), dim3(256), 0, st, (const uint32_t*)sk,
                        (const int32_t*)sv, m, src, t, g->in_dst, g->in_src, g->in_t,
-                       g->in_eid);
+                       g->in_eid, (uint4*)g->in_rec);
     hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
                        (const uint32_t*)sk, m, n, g->in_off);
   } else {
@@ -789,7 +800,7 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     int32_t* sv = w ? vals1 : vals0;
     hipLaunchKernelGGL(k_gather_order, dim3(eb), dim3(256), 0, st, (const uint32_t*)sk,
                        (const int32_t*)sv, m, dst, t, (int32_t*)nullptr, g->pair_dst, g->pair_t,
-                       g->pair_eid);
+                       g->pair_eid, (uint4*)nullptr);
     // 5. pair-run hash table (the sorted src keys are still in sk)
     uint32_t* run_of = w ? k0 : k1;                        // the free key buffer (m + 1)
     uint32_t* run_start = (uint32_t*)(w ? vals0 : vals1);  // the free value buffer (m + 1)

@@ -36,6 +36,9 @@ tc_status path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_byt
 constexpr int kMaxMotifs = 16;
 constexpr int kMaxLists = 13;
 constexpr int kMaxPairs = 12;
+// A motif's first list gates it: when that window is empty its count is 0
+// and its other lists are never needed.  The gate pairs are therefore
+// searched for every accepted path, the others only for live motifs.
 struct MotifPlan {
   int32_t n_motifs;
   int32_t n_pairs;
@@ -43,6 +46,9 @@ struct MotifPlan {
   uint8_t pair_a[kMaxPairs], pair_b[kMaxPairs];  // vertex slots of each pair
   int32_t n_lists[kMaxMotifs];
   uint8_t list_pair[kMaxMotifs][kMaxLists];     // pair index of each list
+  int32_t n_gates;
+  uint8_t gate_pair[kMaxPairs];                 // distinct first-list pairs
+  uint16_t rest_mask[kMaxMotifs];               // other pairs of each motif (not gates)
 };
 
 tc_status compile_motifs(const tc_motif* motifs, int32_t n_motifs, MotifPlan* plan);

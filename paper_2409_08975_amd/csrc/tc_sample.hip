@@ -51,10 +51,7 @@ constexpr int kWideWaves = 64;
 constexpr int kMaxFastWaves = 8192;
 
 struct DeltaArgs {
-  const uint32_t* lo_in;
-  const uint32_t* a;
-  const uint32_t* lo_out;
-  const uint32_t* b;
+  const uint4* prec;  // [2 m]: {lo_in, a, lo_out, b}, {u, v, t lo, t hi}
   const uint64_t* S;
   const uint64_t* tree;  // levels 1.. of the search tree over S
   const uint32_t* wstatus;
@@ -73,13 +70,9 @@ struct DeltaArgs {
 
 struct SampleArgs {
   // graph
-  const int32_t* out_src;
-  const int32_t* out_dst;
+  const uint4* out_rec;  // {dst, eid, t lo, t hi} in out-CSR order
+  const uint4* in_rec;   // {src, eid, t lo, t hi} in in-CSR order
   const int32_t* out_eid;
-  const int64_t* out_t;
-  const int32_t* in_src;
-  const int32_t* in_eid;
-  const int64_t* in_t;
   const int64_t* pair_t;
   const PairSlot* pair_hash;
   int32_t pair_hash_log2;
@@ -289,6 +282,9 @@ struct PathRec {
 __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
   __shared__ PathRec s_path[kSBlock];
   __shared__ uint32_t s_nvalid;
+  __shared__ uint32_t s_mask[kSBlock];     // pairs still needed by each accepted path
+  __shared__ uint32_t s_off[kSBlock + 1];  // exclusive prefix of their counts
+  __shared__ uint32_t s_wsum[kSWaves];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int nm = A.plan.n_motifs;
@@ -335,7 +331,8 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
           r = 0;
         }
         const uint32_t p = tree_search(A, D, r);  // S[p] <= r < S[p+1]
-        const uint32_t ap = D.a[p], bp = D.b[p];
+        const uint4 pr0 = D.prec[2 * (uint64_t)p], pr1 = D.prec[2 * (uint64_t)p + 1];
+        const uint32_t ap = pr0.y, bp = pr0.w;
         uint32_t j1, j3;
         ok = range32(blk0.x2, ap, &j1);
         for (uint32_t att = 1; !ok && att < kMaxAttempts; ++att)
@@ -351,19 +348,19 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
           st_bits |= TC_F_RNG;
           j3 = 0;
         }
-        u = A.out_src[p];
-        v = A.out_dst[p];
-        const int64_t t2 = A.out_t[p];
-        const uint32_t q1 = D.lo_in[p] + j1;
-        const uint32_t q3 = D.lo_out[p] + j3;
-        x = A.in_src[q1];
-        t1 = A.in_t[q1];
-        y = A.out_dst[q3];
-        t3 = A.out_t[q3];
+        u = (int32_t)pr1.x;
+        v = (int32_t)pr1.y;
+        const int64_t t2 = (int64_t)(((uint64_t)pr1.w << 32) | pr1.z);
+        const uint4 er1 = A.in_rec[pr0.x + j1];   // e1 = (x, u, t1)
+        const uint4 er3 = A.out_rec[pr0.z + j3];  // e3 = (v, y, t3)
+        x = (int32_t)er1.x;
+        t1 = (int64_t)(((uint64_t)er1.w << 32) | er1.z);
+        y = (int32_t)er3.x;
+        t3 = (int64_t)(((uint64_t)er3.w << 32) | er3.z);
         if (D.e1) {
-          D.e1[ii] = A.in_eid[q1];
+          D.e1[ii] = (int32_t)er1.y;
           D.e2[ii] = A.out_eid[p];
-          D.e3[ii] = A.out_eid[q3];
+          D.e3[ii] = (int32_t)er3.y;
         }
         if (D.P) D.P[ii] = p;
         valid = x != u && x != v && x != y && u != v && u != y && v != y && t1 < t2 &&
@@ -383,10 +380,13 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
       if (valid) s_path[base + __popcll(mask & lt_mask)] = PathRec{x, u, v, y, t1, t3, li};
     }
     __syncthreads();
-    // one (path, pair) window per task, spread over the block
+    // phase A: the gate pairs of every accepted path, one (path, pair)
+    // window per task, spread over the block
     const uint32_t nvalid = s_nvalid;
-    for (uint32_t task = tid; task < nvalid * (uint32_t)np; task += kSBlock) {
-      const uint32_t q = task / nvalid, sidx = task - q * nvalid;
+    const uint32_t ng = (uint32_t)A.plan.n_gates;
+    for (uint32_t task = tid; task < nvalid * ng; task += kSBlock) {
+      const uint32_t gi = task / nvalid, sidx = task - gi * nvalid;
+      const uint32_t q = A.plan.gate_pair[gi];
       const PathRec P = s_path[sidx];
       uint32_t lo, hi;
       pair_window(A, slot_vertex(A.plan.pair_a[q], P.x, P.u, P.v, P.y),
@@ -397,6 +397,49 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
     }
     __threadfence_block();
     __syncthreads();
+    // phase B: the other pairs, only for motifs whose gate window is non-empty
+    if ((uint32_t)np > ng) {
+      uint32_t mask = 0;
+      if (tid < nvalid) {
+        const uint32_t pli = s_path[tid].li;
+        for (int j = 0; j < nm; ++j)
+          if (A.plan.n_lists[j] >= 2 &&
+              A.win_len[win_index(A, d, A.plan.list_pair[j][0], pli)] != 0)
+            mask |= A.plan.rest_mask[j];
+      }
+      const uint32_t cnt = (uint32_t)__popc(mask);
+      const uint32_t inc = wave_inclusive_scan(cnt);
+      if (lane == 63) s_wsum[wave] = inc;
+      __syncthreads();
+      uint32_t pre = 0;
+      for (int w2 = 0; w2 < wave; ++w2) pre += s_wsum[w2];
+      s_mask[tid] = mask;
+      s_off[tid] = pre + inc - cnt;
+      if (tid == kSBlock - 1) s_off[kSBlock] = pre + inc;
+      __syncthreads();
+      const uint32_t total = s_off[kSBlock];
+      for (uint32_t task = tid; task < total; task += kSBlock) {
+        // the accepted path of this task: last sidx with s_off[sidx] <= task
+        uint32_t lo2 = 0, hi2 = nvalid;
+        while (hi2 - lo2 > 1) {
+          const uint32_t mid = (lo2 + hi2) >> 1;
+          if (s_off[mid] <= task) lo2 = mid; else hi2 = mid;
+        }
+        const uint32_t sidx = lo2;
+        uint32_t mk = s_mask[sidx];
+        for (uint32_t skip = task - s_off[sidx]; skip > 0; --skip) mk &= mk - 1;
+        const uint32_t q = (uint32_t)__ffs(mk) - 1;
+        const PathRec P = s_path[sidx];
+        uint32_t lo, hi;
+        pair_window(A, slot_vertex(A.plan.pair_a[q], P.x, P.u, P.v, P.y),
+                    slot_vertex(A.plan.pair_b[q], P.x, P.u, P.v, P.y), P.t3, P.t1 + D.delta,
+                    &lo, &hi);
+        A.win_lo[win_index(A, d, q, P.li)] = lo;
+        A.win_len[win_index(A, d, q, P.li)] = hi - lo;
+      }
+      __threadfence_block();
+      __syncthreads();
+    }
     for (int j = 0; j < nm; ++j) {
       const int l = A.plan.n_lists[j];
       uint64_t X = 0;
@@ -411,10 +454,14 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
           // hold 2^64 chains (then the count must run to flag it)
           uint64_t prod = 1;
           bool empty = false, big = false;
+          // lists after the first empty one were not searched (gating)
           for (int r = 0; r < l; ++r) {
             const uint32_t len = A.win_len[win_index(A, d, A.plan.list_pair[j][r], li)];
-            if (len == 0) empty = true;
-            if (!empty && __builtin_mul_overflow(prod, (uint64_t)len, &prod)) big = true;
+            if (len == 0) {
+              empty = true;
+              break;
+            }
+            if (__builtin_mul_overflow(prod, (uint64_t)len, &prod)) big = true;
           }
           if (!empty || big) defer = true;
         }
@@ -884,13 +931,9 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
   if (!ws || ws_bytes < L.total) return TC_E_WORKSPACE;
   char* base = (char*)ws;
   SampleArgs A;
-  A.out_src = g->out_src;
-  A.out_dst = g->out_dst;
+  A.out_rec = (const uint4*)g->out_rec;
+  A.in_rec = (const uint4*)g->in_rec;
   A.out_eid = g->out_eid;
-  A.out_t = g->out_t;
-  A.in_src = g->in_src;
-  A.in_eid = g->in_eid;
-  A.in_t = g->in_t;
   A.pair_t = g->pair_t;
   A.pair_hash = (const PairSlot*)g->pair_hash;
   A.pair_hash_log2 = g->pair_hash_log2;
@@ -907,10 +950,7 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
     D = DeltaArgs{};
     if (d >= nd) continue;
     if (w[d]->m != g->m) return TC_E_ARG;
-    D.lo_in = w[d]->lo_in;
-    D.a = w[d]->a;
-    D.lo_out = w[d]->lo_out;
-    D.b = w[d]->b;
+    D.prec = (const uint4*)w[d]->prec;
     D.S = w[d]->S;
     D.tree = (const uint64_t*)w[d]->scratch;
     D.wstatus = w[d]->status;

@@ -110,12 +110,18 @@ __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, Key
   }
 }
 
-// per p: v's window from its in-CSR position, and the tile sums of a * b
+// per p: v's window from its in-CSR position, the path record, and the
+// tile sums of a * b
 __global__ __launch_bounds__(kWBlock) void k_combine(const uint32_t* __restrict__ out_to_in,
                                                      const uint2* __restrict__ win_q,
-                                                     const uint32_t* __restrict__ a, int64_t m,
+                                                     const uint32_t* __restrict__ lo_in,
+                                                     const uint32_t* __restrict__ a,
+                                                     const int32_t* __restrict__ out_src,
+                                                     const int32_t* __restrict__ out_dst,
+                                                     const int64_t* __restrict__ out_t, int64_t m,
                                                      uint32_t* __restrict__ lo_out,
                                                      uint32_t* __restrict__ b_out,
+                                                     uint4* __restrict__ prec,
                                                      uint64_t* __restrict__ tile_sums) {
   __shared__ U128 s_w[kWBlock / kWave];
   const int64_t start = (int64_t)blockIdx.x * kWTile;
@@ -125,10 +131,14 @@ __global__ __launch_bounds__(kWBlock) void k_combine(const uint32_t* __restrict_
     const int64_t p = start + (int64_t)r * kWBlock + threadIdx.x;
     if (p < m) {
       const uint2 wq = win_q[out_to_in[p]];
-      const uint32_t bb = wq.y;
+      const uint32_t bb = wq.y, ap = a[p];
       lo_out[p] = wq.x;
       b_out[p] = bb;
-      acc = add128(acc, U128{(uint64_t)a[p] * (uint64_t)bb, 0});
+      const int64_t t = out_t[p];
+      prec[2 * p] = make_uint4(lo_in[p], ap, wq.x, bb);
+      prec[2 * p + 1] =
+          make_uint4((uint32_t)out_src[p], (uint32_t)out_dst[p], (uint32_t)t, (uint32_t)(t >> 32));
+      acc = add128(acc, U128{(uint64_t)ap * (uint64_t)bb, 0});
     }
   }
   acc = wave_sum128(acc);
@@ -338,7 +348,8 @@ static void build_tree(tc_weights* w, hipStream_t st) {
 }
 
 struct WeightsLayout {
-  size_t lo_in, a, lo_out, b, S, status, tile_sums, tile_off, tree, lo_out_q, win_q, split, total;
+  size_t lo_in, a, lo_out, b, S, status, tile_sums, tile_off, tree, lo_out_q, win_q, split, prec,
+      total;
 };
 
 static WeightsLayout weights_layout(int64_t m) {
@@ -364,6 +375,7 @@ static WeightsLayout weights_layout(int64_t m) {
   L.lo_out_q = take(M * 4);
   L.win_q = take(M * 8);
   L.split = take((size_t)((2 * M + kMPTile - 1) / kMPTile + 2) * 4);
+  L.prec = take(M * 32);
   L.total = o;
   return L;
 }
@@ -386,6 +398,7 @@ tc_status path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_byt
   w->status = (uint32_t*)(base + L.status);
   w->scratch = base + L.tree;  // search tree over S
   w->h = nullptr;
+  w->prec = base + L.prec;
   uint64_t* tile_sums = (uint64_t*)(base + L.tile_sums);
   uint64_t* tile_off = (uint64_t*)(base + L.tile_off);
   const int64_t ntiles = (m + kWTile - 1) / kWTile;
@@ -418,7 +431,9 @@ tc_status path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_byt
                        win_q);
     hipLaunchKernelGGL(k_combine, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
                        (const uint32_t*)g->out_to_in, (const uint2*)win_q,
-                       (const uint32_t*)w->a, m, w->lo_out, w->b, tile_sums);
+                       (const uint32_t*)w->lo_in, (const uint32_t*)w->a,
+                       (const int32_t*)g->out_src, (const int32_t*)g->out_dst,
+                       (const int64_t*)g->out_t, m, w->lo_out, w->b, (uint4*)w->prec, tile_sums);
   }
   hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, (const uint64_t*)tile_sums, ntiles,
                      tile_off, w->S, m, w->status);

@@ -69,9 +69,23 @@ def check_graph(G, og, g):
     assert np.array_equal(A["in_t"].cpu().numpy(), g.t[ie])
     assert np.array_equal(A["pair_dst"].cpu().numpy(), g.dst[pe])
     assert np.array_equal(A["pair_t"].cpu().numpy(), g.t[pe])
+    # 16-byte records {other end, eid, t} of the two CSRs
+    m = g.m
+    if m:
+        orec = G.view("out_rec", torch_i32(), 4 * m).cpu().numpy().reshape(m, 4)
+        irec = G.view("in_rec", torch_i32(), 4 * m).cpu().numpy().reshape(m, 4)
+        assert np.array_equal(orec[:, 0], g.dst[oe]) and np.array_equal(orec[:, 1], oe)
+        assert np.array_equal(orec[:, 2:].copy().view(np.int64).ravel(), g.t[oe])
+        assert np.array_equal(irec[:, 0], g.src[ie]) and np.array_equal(irec[:, 1], ie)
+        assert np.array_equal(irec[:, 2:].copy().view(np.int64).ravel(), g.t[ie])
 
 
-def check_weights(Wt, ow):
+def torch_i32():
+    import torch
+    return torch.int32
+
+
+def check_weights(Wt, ow, g=None, og=None):
     A = Wt.arrays()
     assert np.array_equal(_u32(A["lo_in"]), ow.lo_in)
     assert np.array_equal(_u32(A["a"]), ow.a)
@@ -79,6 +93,18 @@ def check_weights(Wt, ow):
     assert np.array_equal(_u32(A["b"]), ow.b)
     assert np.array_equal(_u64(A["S"]), ow.S)
     assert Wt.status() == ow.status
+    m = ow.a.shape[0]
+    if m:
+        # 32-byte path records {lo_in, a, lo_out, b, u, v, t}
+        pr = Wt.view("prec", torch_i32(), 8 * m).cpu().numpy().reshape(m, 8)
+        assert np.array_equal(pr[:, 0].view(np.uint32), ow.lo_in)
+        assert np.array_equal(pr[:, 1].view(np.uint32), ow.a)
+        assert np.array_equal(pr[:, 2].view(np.uint32), ow.lo_out)
+        assert np.array_equal(pr[:, 3].view(np.uint32), ow.b)
+        if g is not None:
+            oe = og.orders()["out_eid"]
+            assert np.array_equal(pr[:, 4], g.src[oe]) and np.array_equal(pr[:, 5], g.dst[oe])
+            assert np.array_equal(pr[:, 6:].copy().view(np.int64).ravel(), g.t[oe])
 
 
 def check_sample(tcb, G, Wt, og, ow, motifs, k, seed, stream=0, i0=0, per_sample=True):
@@ -119,7 +145,7 @@ def test_tiny_graph_orders(tiny):
 def test_tiny_weights(tcb, tiny, delta):
     g, G, og = tiny
     Wt = tcb.tc_path_weights(G, delta)
-    check_weights(Wt, og.weights(delta))
+    check_weights(Wt, og.weights(delta), g, og)
 
 
 def test_tiny_m40_k1e5_seed1(tcb, tiny):
@@ -170,7 +196,7 @@ def test_planted_micro(tcb, torch_mod, seed):
     for delta in (3, 9, 40):
         Wt = tcb.tc_path_weights(G, delta)
         ow = og.weights(delta)
-        check_weights(Wt, ow)
+        check_weights(Wt, ow, g, og)
         check_sample(tcb, G, Wt, og, ow, SIX, 20000, seed=seed + 1)
 
 
@@ -182,7 +208,7 @@ def test_ragged_sizes(tcb, torch_mod, m):
     delta = max(2, m // 10)
     Wt = tcb.tc_path_weights(G, delta)
     ow = og.weights(delta)
-    check_weights(Wt, ow)
+    check_weights(Wt, ow, g, og)
     check_sample(tcb, G, Wt, og, ow, SIX, 3000, seed=m)
 
 
@@ -208,7 +234,7 @@ def test_zero_weight_graph(tcb, torch_mod):
     G, og = build_both(tcb, torch_mod, g)
     Wt = tcb.tc_path_weights(G, 100)
     ow = og.weights(100)
-    check_weights(Wt, ow)
+    check_weights(Wt, ow, g, og)
     check_sample(tcb, G, Wt, og, ow, [M40], 257, seed=1)
 
 
@@ -220,7 +246,7 @@ def test_single_vertex_and_wide_time_range(tcb, torch_mod):
     check_graph(G, og, g)
     Wt = tcb.tc_path_weights(G, 3)
     ow = og.weights(3)
-    check_weights(Wt, ow)
+    check_weights(Wt, ow, g, og)
     check_sample(tcb, G, Wt, og, ow, [M40], 1000, seed=2)
     # timestamps spanning more than 32 bits (64-bit radix keys), negatives
     rng = np.random.default_rng(5)
@@ -231,7 +257,7 @@ def test_single_vertex_and_wide_time_range(tcb, torch_mod):
     for delta in (0, 2**58, 2**62):
         Wt = tcb.tc_path_weights(G, delta)
         ow = og.weights(delta)
-        check_weights(Wt, ow)
+        check_weights(Wt, ow, g, og)
         check_sample(tcb, G, Wt, og, ow, SIX, 5000, seed=3)
 
 
@@ -265,7 +291,7 @@ def test_weight_overflow(tcb, torch_mod):
     Wt = tcb.tc_path_weights(G, 0)
     ow = og.weights(0)
     assert Wt.status() == 0 and Wt.total() == 2**64 - 2**42
-    check_weights(Wt, ow)
+    check_weights(Wt, ow, g, og)
     check_sample(tcb, G, Wt, og, ow, [M40], 20000, seed=1)
 
 
@@ -294,7 +320,7 @@ def test_listcount_overflow_flag(tcb, torch_mod):
     delta = base + 10
     Wt = tcb.tc_path_weights(G, delta)
     ow = og.weights(delta)
-    check_weights(Wt, ow)
+    check_weights(Wt, ow, g, og)
     R, E = check_sample(tcb, G, Wt, og, ow, [motif], 20000, seed=1, per_sample=False)
     assert E.status & 2
     # the same graph with the 4-cycle only: no overflow, full parity
@@ -319,6 +345,6 @@ def test_medium_full_size_parity(tcb, medium):
     delta = sg.MEDIUM["delta"]
     Wt = tcb.tc_path_weights(G, delta)
     ow = og.weights(delta)
-    check_weights(Wt, ow)
+    check_weights(Wt, ow, g, og)
     check_sample(tcb, G, Wt, og, ow, SIX, sg.MEDIUM["k"], seed=1, per_sample=False)
     check_sample(tcb, G, Wt, og, ow, SIX, 200000, seed=1, i0=4_000_000, per_sample=True)
