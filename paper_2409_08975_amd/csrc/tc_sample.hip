@@ -615,45 +615,64 @@ __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A) {
     uint64_t P[CH];  // P[h] on lane q: prefix through entry 64 h + q
 #pragma unroll
     for (int h = 0; h < CH; ++h) P[h] = (uint64_t)(h * kWave + lane + 1);  // level 0: all ones
-    U128 total{0, 0};
+    // Level totals: T_0 = |L_0| and T_r <= |L_r| T_{r-1}.  While that bound
+    // stays below 2^64 the running 64-bit carry is the exact total; only
+    // otherwise are the 128-bit level sums formed (to detect overflow).
+    uint64_t t_prev = __shfl(my_len, 0, kWave);
+    bool sat = false;  // a level total reached 2^64 (results undefined)
     for (int r = 1; r < l; ++r) {
       const uint32_t prev_len = __shfl(my_len, r - 1, kWave);
       const uint32_t len = __shfl(my_len, r, kWave);
       const uint32_t* kprev = s_key + __shfl(my_off, r - 1, kWave);
       const uint32_t* kcur = s_key + __shfl(my_off, r, kWave);
+      const uint32_t nch = (len + kWave - 1) / kWave;       // chunks of this level
+      const uint32_t pch = (prev_len + kWave - 1) / kWave;  // chunks of the previous one
+      uint64_t bound;
+      const bool exact64 = !sat && !__builtin_mul_overflow((uint64_t)len, t_prev, &bound);
       uint64_t Pn[CH];
       uint64_t carry = 0;
-      total = U128{0, 0};
+      U128 total{0, 0};
 #pragma unroll
       for (int h = 0; h < CH; ++h) {
-        const uint32_t i = h * kWave + lane;
-        const bool act = i < len;
-        uint32_t pos = 0;
-        if (act) pos = lower_bound<uint32_t>(kprev, 0u, prev_len, kcur[i]);
-        const uint32_t q = pos - 1;  // prefix entry pos - 1: lane q & 63 of chunk q >> 6
-        const int src = (int)(q & 63u);
-        const uint32_t hsrc = q >> 6;
-        uint64_t c = 0;
+        Pn[h] = 0;
+        if ((uint32_t)h < nch) {  // uniform over the wavefront
+          const uint32_t i = h * kWave + lane;
+          const bool act = i < len;
+          uint32_t pos = 0;
+          if (act) pos = lower_bound<uint32_t>(kprev, 0u, prev_len, kcur[i]);
+          const uint32_t q = pos - 1;  // prefix entry pos - 1: lane q & 63 of chunk q >> 6
+          const int src = (int)(q & 63u);
+          const uint32_t hsrc = q >> 6;
+          uint64_t c = 0;
 #pragma unroll
-        for (int g = 0; g < CH; ++g) {
-          const uint32_t lo32 = (uint32_t)__shfl((uint32_t)P[g], src, kWave);
-          const uint32_t hi32 = (uint32_t)__shfl((uint32_t)(P[g] >> 32), src, kWave);
-          if (hsrc == (uint32_t)g) c = ((uint64_t)hi32 << 32) | lo32;
+          for (int g = 0; g < CH; ++g) {
+            if ((uint32_t)g < pch) {
+              const uint32_t lo32 = (uint32_t)__shfl((uint32_t)P[g], src, kWave);
+              const uint32_t hi32 = (uint32_t)__shfl((uint32_t)(P[g] >> 32), src, kWave);
+              if (hsrc == (uint32_t)g) c = ((uint64_t)hi32 << 32) | lo32;
+            }
+          }
+          if (!act || pos == 0) c = 0;
+          const uint64_t inc = wave_inclusive_scan(c);
+          Pn[h] = carry + inc;
+          if (!exact64) total = add128(total, wave_sum128(U128{c, 0}));
+          carry += __shfl(inc, kWave - 1, kWave);
         }
-        if (!act || pos == 0) c = 0;
-        const uint64_t inc = wave_inclusive_scan(c);
-        Pn[h] = carry + inc;
-        total = add128(total, wave_sum128(U128{c, 0}));
-        carry += __shfl(inc, kWave - 1, kWave);
       }
-      if (total.hi != 0) {
-        st_bits = TC_F_OVERFLOW;
-        st_dmask |= 1u << d;
+      if (exact64) {
+        t_prev = carry;
+      } else {
+        if (total.hi != 0) sat = true;
+        t_prev = total.hi ? ~0ull : total.lo;
       }
 #pragma unroll
       for (int h = 0; h < CH; ++h) P[h] = Pn[h];
     }
-    if (lane == 0) item_done(A, d, j, li, total.lo);
+    if (sat) {
+      st_bits = TC_F_OVERFLOW;
+      st_dmask |= 1u << d;
+    }
+    if (lane == 0) item_done(A, d, j, li, t_prev);
     __threadfence_block();
   }
   __syncthreads();
