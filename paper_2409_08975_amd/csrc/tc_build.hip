@@ -151,7 +151,22 @@ __global__ __launch_bounds__(256) void k_validate(const int32_t* __restrict__ sr
     mx = b > mx ? b : mx;
     bad |= __shfl_xor(bad, off, kWave);
   }
+  // one pair of atomics per block (not per wavefront): they all hit two words
+  __shared__ uint64_t s_mn[4], s_mx[4];
+  __shared__ uint32_t s_bad[4];
+  const int wave = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
+    s_mn[wave] = mn;
+    s_mx[wave] = mx;
+    s_bad[wave] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+      mn = s_mn[w] < mn ? s_mn[w] : mn;
+      mx = s_mx[w] > mx ? s_mx[w] : mx;
+      bad |= s_bad[w];
+    }
     atomicMin((unsigned long long*)&tminmax[0], (unsigned long long)mn);
     atomicMax((unsigned long long*)&tminmax[1], (unsigned long long)mx);
     if (bad) atomicOr(status, TC_F_RANGE);
@@ -637,7 +652,7 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   hipLaunchKernelGGL(k_init_build, dim3(1), dim3(64), 0, st, g->status, tminmax);
   if (m > 0) {
     unsigned vb = blocks_for(m, 256);
-    if (vb > 4096) vb = 4096;
+    if (vb > 1024) vb = 1024;
     hipLaunchKernelGGL(k_validate, dim3(vb), dim3(256), 0, st, src, dst, t, m, n, g->status,
                        tminmax);
   }
