@@ -54,6 +54,9 @@ typedef enum {
 #define TC_F_RANGE 1u     /* bad vertex id or timestamp                              */
 #define TC_F_OVERFLOW 2u  /* W >= 2^64, or a ListCount partial total >= 2^64          */
 #define TC_F_RNG 4u       /* 1024 consecutive rejections in the range reduction       */
+/* With TC_F_OVERFLOW from the sampler, bit 8 + j names each motif j whose
+ * count reached 2^64; the counts of the other motifs of the call stay exact. */
+#define TC_F_MOTIF(j) (1u << (8 + (j)))
 
 /* A temporal motif: H's edges listed in pi order (edge i has time rank i),
  * vertices 0..nv-1.  Supported: nv == 4, 3 <= ne <= 16, no self-loops, and

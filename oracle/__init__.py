@@ -57,6 +57,7 @@ def lib():
         L.or_proposal_scan.argtypes = [P, P, P, P, P]
         L.or_features.argtypes = [P, I64, P, P, P, P, P, ctypes.c_int]
         L.or_exhaustive.argtypes = [P, P, I64, P, P, P, P, P, P, P, ctypes.c_int]
+        L.or_list_lengths.argtypes = [P, P, I64, I32, I32, I32, P]
         L.or_brute_count.argtypes = [P, P, I64, P, ctypes.c_int]
         L.or_list_count.argtypes = [P, P, ctypes.c_int, P]
         L.or_philox4x32_10.argtypes = [P, P, P]
@@ -243,6 +244,13 @@ class OracleGraph:
         st = lib().or_exhaustive(self.h, _p(mb), w.delta, _p(w.lo_in), _p(w.a), _p(w.lo_out),
                                  _p(w.b), _p(s1), _p(s2), _p(nz), threads or default_threads())
         return (st, int(s1[0]) | (int(s1[1]) << 64), int(s2[0]) | (int(s2[1]) << 64), int(nz[0]))
+
+    def list_lengths(self, motif: bytes, delta: int, e1: int, e2: int, e3: int):
+        """Window lengths of a path's lists (None if CheckMotif rejects it)."""
+        mb = np.frombuffer(motif, dtype=np.uint8).copy()
+        lens = np.zeros(16, np.int64)
+        n = lib().or_list_lengths(self.h, _p(mb), int(delta), e1, e2, e3, _p(lens))
+        return None if n < 0 else lens[:n].tolist()
 
     def brute_count(self, motif: bytes, delta: int, threads: int | None = None) -> int:
         mb = np.frombuffer(motif, dtype=np.uint8).copy()

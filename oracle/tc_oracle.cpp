@@ -428,10 +428,11 @@ int or_sample_ex(void* hg, int64_t delta, const uint32_t* lo_in, const uint32_t*
       for (int j = 0; j < n_motifs; ++j) {
         uint64_t X = 0;
         int st = check_motif(G, Ms[j], delta, e1, e2, e3, &X);
-        pst[tid] |= st;
+        // an overflow also names its motif (bit 8 + j)
+        pst[tid] |= st | ((st & OR_OVERFLOW) ? (1 << (8 + j)) : 0);
         if (Xo) Xo[(uint64_t)j * k + ii] = X;
         u128 add = hq ? (((u128)X << 64) / hp) : (u128)X;
-        if (pc[tid][j] + add < pc[tid][j]) pst[tid] |= OR_OVERFLOW;
+        if (pc[tid][j] + add < pc[tid][j]) pst[tid] |= OR_OVERFLOW | (1 << (8 + j));
         pc[tid][j] += add;
         ph[tid][j] += X > 0;
         const double v = (double)X / (double)hp;
@@ -441,7 +442,7 @@ int or_sample_ex(void* hg, int64_t delta, const uint32_t* lo_in, const uint32_t*
     for (int tid = 0; tid < nthreads; ++tid) {
       status |= pst[tid];
       for (int j = 0; j < n_motifs; ++j) {
-        if (c[j] + pc[tid][j] < c[j]) status |= OR_OVERFLOW;
+        if (c[j] + pc[tid][j] < c[j]) status |= OR_OVERFLOW | (1 << (8 + j));
         c[j] += pc[tid][j];
         hh[j] += ph[tid][j];
         mm[j] += pm[tid][j];
@@ -693,5 +694,28 @@ int or_list_count(const int64_t* vals, const int64_t* off, int l, uint64_t* X) {
 }
 
 int or_max_threads(void) { return omp_get_max_threads(); }
+
+// Window lengths of the lists of one delta-centred path (e1, e2, e3 by edge
+// id) for one motif, in rank order; returns the number of lists, or -1 if
+// the path fails CheckMotif's vertex and time tests.  Test diagnostics.
+int or_list_lengths(void* h, const uint8_t* motif, int64_t delta, int32_t e1, int32_t e2,
+                    int32_t e3, int64_t* lens) {
+  Graph& G = *(Graph*)h;
+  Motif M;
+  if (!parse_motif(motif, &M)) return -2;
+  int32_t x = G.src[e1], u = G.dst[e1], v = G.dst[e2], y = G.dst[e3];
+  int64_t t1 = G.t[e1], t2 = G.t[e2], t3 = G.t[e3];
+  int32_t phi[4] = {x, u, v, y};
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j)
+      if (phi[i] == phi[j]) return -1;
+  if (t3 > t1 + delta || !(t1 < t2 && t2 < t3)) return -1;
+  for (int r = 3; r < M.ne; ++r) {
+    int64_t f, l;
+    pair_window(G, phi[M.src[r]], phi[M.dst[r]], t3, t1 + delta, &f, &l);
+    lens[r - 3] = l - f;
+  }
+  return M.ne - 3;
+}
 
 }  // extern "C"

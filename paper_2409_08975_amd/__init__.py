@@ -20,6 +20,11 @@ LIB_PATH = os.path.join(_HERE, "libtc.so")
 TC_OK, TC_E_ARG, TC_E_RANGE, TC_E_OVERFLOW, TC_E_UNSUPPORTED, TC_E_WORKSPACE, TC_E_HIP = (
     0, -1, -2, -3, -4, -5, -6)
 TC_F_RANGE, TC_F_OVERFLOW, TC_F_RNG = 1, 2, 4
+
+
+def TC_F_MOTIF(j: int) -> int:
+    """Status bit naming motif j of a call whose count reached 2^64."""
+    return 1 << (8 + j)
 _STATUS_NAMES = {0: "TC_OK", -1: "TC_E_ARG", -2: "TC_E_RANGE", -3: "TC_E_OVERFLOW",
                  -4: "TC_E_UNSUPPORTED", -5: "TC_E_WORKSPACE", -6: "TC_E_HIP"}
 
@@ -44,6 +49,9 @@ class TCDeviceError(RuntimeError):
         self.bits = bits
         names = [n for b, n in ((TC_F_RANGE, "RANGE"), (TC_F_OVERFLOW, "OVERFLOW"),
                                 (TC_F_RNG, "RNG")) if bits & b]
+        motifs = [j for j in range(16) if bits & (1 << (8 + j))]
+        if motifs:
+            names.append("motifs " + ",".join(map(str, motifs)))
         super().__init__(f"{what}: device status {'|'.join(names) or bits}")
 
 

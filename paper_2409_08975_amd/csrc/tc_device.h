@@ -67,6 +67,19 @@ __device__ __forceinline__ bool range32(uint32_t x, uint32_t s, uint32_t* out) {
   return true;
 }
 
+// Wave-uniform values as scalars.  Wavefront-cooperative kernels
+// branch and loop on per-item values (item index, list bounds, maxima,
+// carries) that every lane holds identically after a broadcast or a
+// butterfly; reading them through v_readfirstlane makes that uniformity
+// visible to the compiler, so those branches are scalar and the wavefront is
+// never split around them (a split would let lanes run a broadcast from a
+// lane that is masked off).
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+  return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
+}
+__device__ __forceinline__ int64_t uni64s(int64_t v) { return (int64_t)uni64((uint64_t)v); }
+
 // ---- searches over sorted device arrays ------------------------------------
 // first index in [lo, hi) with a[idx] >= key
 template <typename T>

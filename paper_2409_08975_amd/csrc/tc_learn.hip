@@ -316,8 +316,10 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P
   __syncthreads();
   const int64_t tiles = (n + 31) / 32;
   const int64_t wstride = (int64_t)gridDim.x * (blockDim.x / kWave);
-  for (int64_t tile = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6);
-       tile < tiles; tile += wstride) {
+  // one tile of 32 rows per wavefront at a time; the wavefront index is
+  // uniform across its lanes, so the tile loop branches as a whole
+  const int64_t wave_id = (int64_t)blockIdx.x * (blockDim.x / kWave) + uni(threadIdx.x >> 6);
+  for (int64_t tile = wave_id; tile < tiles; tile += wstride) {
     const int64_t row = tile * 32 + (lane & 31);
     const s16x4 fb = row < n ? load_feat4(feat, row, h) : s16x4{0, 0, 0, 0};
     Fwd r;

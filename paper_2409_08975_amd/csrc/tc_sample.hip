@@ -264,7 +264,7 @@ __device__ void sums_flush(const SampleArgs& A) {
     }
     if (h) atomicAdd((unsigned long long*)&A.D[d].hits[j], (unsigned long long)h);
     if (A.D[d].m2 && sq != 0.0) atomicAdd(&A.D[d].m2[j], sq);
-    if (ovf) atomicOr(A.D[d].status, TC_F_OVERFLOW);
+    if (ovf) atomicOr(A.D[d].status, TC_F_OVERFLOW | TC_F_MOTIF(j));
   }
 }
 
@@ -567,8 +567,7 @@ __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A) {
   __shared__ uint32_t s_key[kRegKeys];
   const int lane = threadIdx.x;
   sums_clear<1>(A);
-  uint32_t st_bits = 0;  // bit d of st_dmask: delta d overflowed
-  uint32_t st_dmask = 0;
+
   const uint32_t n_items = *A.item_count;
   for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const uint32_t code = A.item_code[it];
@@ -593,18 +592,20 @@ __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A) {
       const int64_t b = __shfl_xor(base, off, kWave);
       base = b < base ? b : base;
     }
+    maxlen = uni(maxlen);
+    base = uni64s(base);
     // list r's keys start at my_off of lane r (exclusive prefix of the lengths)
     const uint32_t incl = wave_inclusive_scan(my_len);
     const uint32_t my_off = incl - my_len;
-    const uint32_t total_keys = __shfl(incl, kWave - 1, kWave);
+    const uint32_t total_keys = uni(__shfl(incl, kWave - 1, kWave));
     if (maxlen > (uint32_t)(kWave * CH) || total_keys > (uint32_t)kRegKeys ||
         A.D[d].delta >= ((int64_t)1 << 32)) {
       if (lane == 0) A.mid_code[atomicAdd(A.mid_count, 1u)] = code;
       continue;
     }
     for (int r = 0; r < l; ++r) {
-      const uint32_t lo = __shfl(my_lo, r, kWave), len = __shfl(my_len, r, kWave);
-      const uint32_t off = __shfl(my_off, r, kWave);
+      const uint32_t lo = uni(__shfl(my_lo, r, kWave)), len = uni(__shfl(my_len, r, kWave));
+      const uint32_t off = uni(__shfl(my_off, r, kWave));
 #pragma unroll
       for (int h = 0; h < CH; ++h) {
         const uint32_t i = h * kWave + lane;
@@ -618,13 +619,13 @@ __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A) {
     // Level totals: T_0 = |L_0| and T_r <= |L_r| T_{r-1}.  While that bound
     // stays below 2^64 the running 64-bit carry is the exact total; only
     // otherwise are the 128-bit level sums formed (to detect overflow).
-    uint64_t t_prev = __shfl(my_len, 0, kWave);
+    uint64_t t_prev = uni(__shfl(my_len, 0, kWave));
     bool sat = false;  // a level total reached 2^64 (results undefined)
     for (int r = 1; r < l; ++r) {
-      const uint32_t prev_len = __shfl(my_len, r - 1, kWave);
-      const uint32_t len = __shfl(my_len, r, kWave);
-      const uint32_t* kprev = s_key + __shfl(my_off, r - 1, kWave);
-      const uint32_t* kcur = s_key + __shfl(my_off, r, kWave);
+      const uint32_t prev_len = uni(__shfl(my_len, r - 1, kWave));
+      const uint32_t len = uni(__shfl(my_len, r, kWave));
+      const uint32_t* kprev = s_key + uni(__shfl(my_off, r - 1, kWave));
+      const uint32_t* kcur = s_key + uni(__shfl(my_off, r, kWave));
       const uint32_t nch = (len + kWave - 1) / kWave;       // chunks of this level
       const uint32_t pch = (prev_len + kWave - 1) / kWave;  // chunks of the previous one
       uint64_t bound;
@@ -656,30 +657,25 @@ __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A) {
           const uint64_t inc = wave_inclusive_scan(c);
           Pn[h] = carry + inc;
           if (!exact64) total = add128(total, wave_sum128(U128{c, 0}));
-          carry += __shfl(inc, kWave - 1, kWave);
+          carry += uni64(__shfl(inc, kWave - 1, kWave));
         }
       }
       if (exact64) {
         t_prev = carry;
       } else {
-        if (total.hi != 0) sat = true;
-        t_prev = total.hi ? ~0ull : total.lo;
+        const uint64_t thi = uni64(total.hi), tlo = uni64(total.lo);
+        if (thi != 0) sat = true;
+        t_prev = thi ? ~0ull : tlo;
       }
 #pragma unroll
       for (int h = 0; h < CH; ++h) P[h] = Pn[h];
     }
-    if (sat) {
-      st_bits = TC_F_OVERFLOW;
-      st_dmask |= 1u << d;
-    }
+    if (sat && lane == 0) flag_status(A, d, TC_F_OVERFLOW | TC_F_MOTIF(j));
     if (lane == 0) item_done(A, d, j, li, t_prev);
     __threadfence_block();
   }
   __syncthreads();
   sums_flush<1>(A);
-  if (lane == 0)
-    for (int d = 0; d < A.nd; ++d)
-      if (st_dmask & (1u << d)) flag_status(A, d, st_bits);
 }
 
 // The level recursion with prefix sums in per-wavefront scratch (64-thread
@@ -698,12 +694,14 @@ __global__ __launch_bounds__(kWave) void k_listcount_wave(SampleArgs A,
                       pscratch + ((uint64_t)blockIdx.x * 2 + 1) * (cap + 1)};
   const int lane = threadIdx.x;
   sums_clear<1>(A);
-  uint32_t st_dmask = 0;
   const uint32_t n_items = *in_count;
+  // Lane 0 claims items; each iteration ends in the one lane-0 block that
+  // retires the current item and claims the next, so no test of the lane
+  // index lies between that block and the broadcast at the loop head.
+  uint32_t next = 0;
+  if (lane == 0) next = atomicAdd(in_next, 1u);
   while (true) {
-    uint32_t it = 0;
-    if (lane == 0) it = atomicAdd(in_next, 1u);
-    it = __shfl(it, 0, kWave);
+    const uint32_t it = uni(__shfl(next, 0, kWave));
     if (it >= n_items) break;
     const uint32_t code = in_code[it];
     uint32_t li;
@@ -727,23 +725,23 @@ __global__ __launch_bounds__(kWave) void k_listcount_wave(SampleArgs A,
       const int64_t b = __shfl_xor(base, off, kWave);
       base = b < base ? b : base;
     }
-    if (maxlen > cap || (FAST && A.D[d].delta >= ((int64_t)1 << 32))) {
-      if (lane == 0) fwd_code[atomicAdd(fwd_count, 1u)] = code;
-      continue;
-    }
+    maxlen = uni(maxlen);
+    base = uni64s(base);
+    const bool fwd = maxlen > cap || (FAST && A.D[d].delta >= ((int64_t)1 << 32));
+    U128 total{0, 0};
+    if (!fwd) {
     if (FAST) {
-      const uint32_t lo0 = __shfl(my_lo, 0, kWave), len0 = __shfl(my_len, 0, kWave);
+      const uint32_t lo0 = uni(__shfl(my_lo, 0, kWave)), len0 = uni(__shfl(my_len, 0, kWave));
       for (uint32_t i = lane; i < len0; i += kWave)
         s_key[0][i] = (uint32_t)(A.pair_t[lo0 + i] - base);
       __threadfence_block();
     }
-    U128 total{0, 0};
     int pb = 0;
     for (int r = 1; r < l; ++r) {
-      const uint32_t prev_lo = __shfl(my_lo, r - 1, kWave);
-      const uint32_t prev_len = __shfl(my_len, r - 1, kWave);
-      const uint32_t lo = __shfl(my_lo, r, kWave);
-      const uint32_t len = __shfl(my_len, r, kWave);
+      const uint32_t prev_lo = uni(__shfl(my_lo, r - 1, kWave));
+      const uint32_t prev_len = uni(__shfl(my_len, r - 1, kWave));
+      const uint32_t lo = uni(__shfl(my_lo, r, kWave));
+      const uint32_t len = uni(__shfl(my_len, r, kWave));
       const uint32_t* kprev = s_key[(r - 1) & 1];
       uint32_t* kcur = s_key[r & 1];
       const uint64_t* Pprev = s_p[pb ^ 1];
@@ -770,19 +768,24 @@ __global__ __launch_bounds__(kWave) void k_listcount_wave(SampleArgs A,
         const uint64_t inc = wave_inclusive_scan(c);
         if (act) Pcur[i + 1] = carry + inc;
         total = add128(total, wave_sum128(U128{c, 0}));
-        carry += __shfl(inc, kWave - 1, kWave);
+        carry += uni64(__shfl(inc, kWave - 1, kWave));
       }
-      if (total.hi != 0) st_dmask |= 1u << d;
+      total = U128{uni64(total.lo), uni64(total.hi)};
+      if (total.hi != 0 && lane == 0) flag_status(A, d, TC_F_OVERFLOW | TC_F_MOTIF(j));
       pb ^= 1;
       __threadfence_block();
     }
-    if (lane == 0) item_done(A, d, j, li, total.lo);
+    }
+    if (lane == 0) {
+      if (fwd)
+        fwd_code[atomicAdd(fwd_count, 1u)] = code;
+      else
+        item_done(A, d, j, li, total.lo);
+      next = atomicAdd(in_next, 1u);
+    }
   }
   __syncthreads();
   sums_flush<1>(A);
-  if (lane == 0)
-    for (int d = 0; d < A.nd; ++d)
-      if (st_dmask & (1u << d)) flag_status(A, d, TC_F_OVERFLOW);
 }
 
 // Items with a list longer than kWideCap: one thread per item.
@@ -814,7 +817,7 @@ __global__ __launch_bounds__(kSBlock) void k_listcount_big(SampleArgs A) {
     bool ovf = false;
     const uint64_t X = big ? sweep<kMaxLists, true>(A.pair_t, ptr, end, l, &ovf)
                            : sweep<kMaxLists, false>(A.pair_t, ptr, end, l, &ovf);
-    if (ovf) flag_status(A, d, TC_F_OVERFLOW);
+    if (ovf) flag_status(A, d, TC_F_OVERFLOW | TC_F_MOTIF(j));
     const DeltaArgs& D = A.D[d];
     if (D.X) D.X[(uint64_t)j * A.k + A.c0 + li] = X;
     const uint32_t hp = D.h ? A.samp_h[(uint64_t)d * A.chunk + li] : 1u;
@@ -1036,15 +1039,25 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
         hipLaunchKernelGGL(k_listcount_reg<4>, dim3(reg_waves), dim3(kWave), sums_bytes(1, nd, nm),
                            st, A);
       }
-      hipLaunchKernelGGL(k_listcount_wave<true>, dim3((unsigned)L.fast_waves), dim3(kWave),
-                         sums_bytes(1, nd, nm), st, A, (const uint32_t*)A.mid_code, (const uint32_t*)A.mid_count,
-                         A.item_next, A.wide_code, A.wide_count, A.fast_p, (uint32_t)kKeyCap);
-      hipLaunchKernelGGL(k_listcount_wave<false>, dim3(kWideWaves), dim3(kWave),
-                         sums_bytes(1, nd, nm), st, A,
-                         (const uint32_t*)A.wide_code, (const uint32_t*)A.wide_count,
-                         A.wide_next, A.big_code, A.big_count, A.wide_p, (uint32_t)kWideCap);
-      hipLaunchKernelGGL(k_listcount_big, dim3(64), dim3(kSBlock), sums_bytes(kSWaves, nd, nm), st,
-                         A);
+      {
+        TimedLaunch tl("k_listcount_wave_lds", st);
+        hipLaunchKernelGGL(k_listcount_wave<true>, dim3((unsigned)L.fast_waves), dim3(kWave),
+                           sums_bytes(1, nd, nm), st, A, (const uint32_t*)A.mid_code,
+                           (const uint32_t*)A.mid_count, A.item_next, A.wide_code, A.wide_count,
+                           A.fast_p, (uint32_t)kKeyCap);
+      }
+      {
+        TimedLaunch tl("k_listcount_wave_mem", st);
+        hipLaunchKernelGGL(k_listcount_wave<false>, dim3(kWideWaves), dim3(kWave),
+                           sums_bytes(1, nd, nm), st, A, (const uint32_t*)A.wide_code,
+                           (const uint32_t*)A.wide_count, A.wide_next, A.big_code, A.big_count,
+                           A.wide_p, (uint32_t)kWideCap);
+      }
+      {
+        TimedLaunch tl("k_listcount_big", st);
+        hipLaunchKernelGGL(k_listcount_big, dim3(64), dim3(kSBlock), sums_bytes(kSWaves, nd, nm),
+                           st, A);
+      }
     }
   }
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(128), 0, st, A, (double* const*)est_dev);

@@ -322,7 +322,12 @@ def test_listcount_overflow_flag(tcb, torch_mod):
     ow = og.weights(delta)
     check_weights(Wt, ow, g, og)
     R, E = check_sample(tcb, G, Wt, og, ow, [motif], 20000, seed=1, per_sample=False)
-    assert E.status & 2
+    assert E.status == 2 | (1 << 8)  # overflow, naming motif 0
+    # an overflowing motif beside one that does not: the other count stays exact
+    R, E = check_sample(tcb, G, Wt, og, ow, [motif, M40], 20000, seed=1, per_sample=False)
+    assert E.status == 2 | (1 << 8)
+    assert R.counts()[1] == E.cnt[1] and int(R.hits[1].item()) == int(E.hits[1])
+    assert R.estimate[1].item() == E.est[1]
     # the same graph with the 4-cycle only: no overflow, full parity
     check_sample(tcb, G, Wt, og, ow, [M40, motif[:9]], 20000, seed=1, per_sample=True)
 
