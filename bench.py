@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bfloat16 MFMA
 KERNELS = ["k_paths", "k_listcount_reg", "k_windows", "k_scan_apply", "k_radix_scatter"]
 # Kernel -> source file whose hash must match the stored counter readings.
 KERNEL_SRC = {"k_paths": "tc_sample.hip", "k_listcount_reg": "tc_sample.hip",
@@ -37,7 +38,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="medium", choices=["medium", "tiny"])
+    ap.add_argument("--workload", default="medium", choices=["medium", "tiny", "batched"],
+                    help="medium: the headline step; batched: six motifs x four deltas on the "
+                         "Bitcoin-like graph in one captured HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--motifs", default="six", choices=["six", "M4-0"],
                     help="motif set of the step (the medium workload uses all six)")
@@ -120,6 +123,8 @@ def learned_vs_method(tcb, G, Wt, motif, seeds, k_ref, stream):
     each part."""
     from paper_2409_08975_amd import learned
     out = {"motif": "M4-0", "delta": int(Wt.c.delta), "seeds": seeds}
+    tcb.timing_reset()
+    tcb.timing_enable(True)
     lp = learned.LearnedProposal(G, Wt, motif, seed=11)
     _, out["features_ms"] = event_ms(lambda: tcb.tc_edge_features(G, Wt), stream)
     losses, out["train_ms"] = event_ms(lambda: lp.fit(n_labels=10**6, epochs=8, batch=8192,
@@ -130,6 +135,26 @@ def learned_vs_method(tcb, G, Wt, motif, seeds, k_ref, stream):
                     "label_rate": lp.label_rate}
     _, out["proposal_ms"] = event_ms(lp.build_proposal, stream)  # inference, h, q-scan
     out["proposal_status"] = lp.proposal.status()
+    tcb.timing_enable(False)
+    # network kernels: 2 (8*64 + 64*64 + 64) flops per row, both hidden layers on MFMA
+    flop_row = 2 * (8 * 64 + 64 * 64 + 64)
+    kt = {}
+    for name, rows in (("k_mlp_forward", G.m), ("k_mlp_grad", None), ("k_features", G.m)):
+        ms, n = tcb.timing_read(name)
+        if not n:
+            continue
+        e = {"ms_per_launch": ms / n, "launches": n}
+        if name == "k_mlp_forward":
+            tf = flop_row * rows / (ms / n * 1e-3) / 1e12
+            e.update({"flop_per_row": flop_row, "rows": rows, "achieved_TFLOPs": tf,
+                      "frac_of_bf16_dense_peak": tf / BF16_PEAK_TFLOPS})
+        if name == "k_mlp_grad":
+            # forward plus backward: about three times the forward flops per row
+            e["rows_per_launch"] = 8192
+            e["achieved_TFLOPs"] = 3 * flop_row * 8192 / (ms / n * 1e-3) / 1e12
+        kt[name] = e
+    tcb.timing_reset()
+    out["kernels"] = kt
     ref, t_ref = event_ms(lambda: tcb.tc_sample_estimate(G, Wt, [motif], int(k_ref), 1,
                                                          stream_id=0x52454600, moments=True),
                           stream)
@@ -164,8 +189,123 @@ def learned_vs_method(tcb, G, Wt, motif, seeds, k_ref, stream):
     return out
 
 
+def run_batched(args):
+    """Six spine-sharing motifs x delta in {600, 3600, 86400, 604800} on the
+    Bitcoin-like graph (5*10^7 vertices, 3*10^8 edges), 10^8 samples per
+    delta shared by the six motifs, the whole batched sequence captured once
+    in a HIP graph and replayed; launch shape from the autotuner.  Every
+    replay is checked bit for bit against an eager call with the default
+    launch shape."""
+    import torch
+
+    import paper_2409_08975_amd as tcb
+    import synthgraph as sg
+
+    dev = torch.device("cuda:0")
+    P = sg.BITCOIN
+    t0 = time.time()
+    g = sg.gen_bitcoin_like()
+    log(f"[bench] generated {g.name}: n={g.n} m={g.m} in {time.time() - t0:.1f}s")
+    src = torch.from_numpy(g.src).to(dev)
+    dst = torch.from_numpy(g.dst).to(dev)
+    tt = torch.from_numpy(g.t).to(dev)
+    del g
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    motifs = [sg.MOTIFS[x] for x in sg.SIX_MOTIFS]
+    deltas, k, seed = P["deltas"], P["k"], P["seed"]
+    G, t_build = event_ms(lambda: tcb.tc_build_graph(P["n"], src, dst, tt), stream)
+    Ws, t_w = [], []
+    for d in deltas:
+        W, t = event_ms(lambda: tcb.tc_path_weights(G, d), stream)
+        Ws.append(W)
+        t_w.append(t)
+    log(f"[bench] build {t_build:.1f} ms, weights {', '.join(f'{x:.1f}' for x in t_w)} ms")
+    best, probe_ms = tcb.tc_autotune(G, Ws, motifs, 2**22, seed=7)
+    log(f"[bench] autotuned {best.as_dict()} ({probe_ms:.2f} ms per 2^22-sample probe)")
+    nd, nm = len(deltas), len(motifs)
+    ws = torch.empty(tcb.batch_workspace_bytes(k, nd, nm), dtype=torch.uint8, device=dev)
+    ref = tcb.tc_batch_estimate(G, Ws, motifs, k, seed, workspace=ws)
+    torch.cuda.synchronize()
+    ref_counts = [r.counts() for r in ref]
+    # per-delta status: a motif whose count reached 2^64 is named by bit 8 + j
+    ref_status = [int(r.status.item()) & 0xFFFFFFFF for r in ref]
+    if any(st & ~(tcb.TC_F_OVERFLOW | 0xFFFF00) for st in ref_status):
+        raise tcb.TCDeviceError(max(ref_status), "batched reference")
+    outs = [tcb.new_result(nm, k, dev) for _ in deltas]
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    cg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(cg, stream=side):
+        tcb.tc_batch_estimate(G, Ws, motifs, k, seed, tuning=best, outs=outs, workspace=ws)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        cg.replay()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.steps):
+        _, t = event_ms(cg.replay, stream)
+        times.append(t)
+        for o, rc, rs in zip(outs, ref_counts, ref_status):
+            assert (int(o.status.item()) & 0xFFFFFFFF) == rs, "replay status differs"
+            assert o.counts() == rc, "replay differs from the eager result"
+    ms = float(np.mean(times))
+    log(f"[bench] replay {ms:.1f} ms ({nd * k / (ms * 1e-3):.3g} samples/s), every replay "
+        f"bit-identical to the eager call; status per delta {[hex(x) for x in ref_status]}")
+    # per-kernel times of the same work, eager, with the chosen launch shape
+    tcb.timing_reset()
+    tcb.timing_enable(True)
+    tcb.tc_batch_estimate(G, Ws, motifs, k, seed, tuning=best, outs=outs, workspace=ws)
+    torch.cuda.synchronize()
+    tcb.timing_enable(False)
+    kernels = {}
+    for kname in ("k_paths", "k_listcount_reg", "k_listcount_wave_lds", "k_listcount_wave_mem",
+                  "k_listcount_big"):
+        kms, n = tcb.timing_read(kname)
+        if n:
+            kernels[kname] = {"ms_total": kms, "launches": n, "ms_per_launch": kms / n}
+    tcb.timing_reset()
+    log("[bench] kernels (one eager pass): " +
+        ", ".join(f"{kn}={v['ms_total']:.1f}ms/{v['launches']}" for kn, v in kernels.items()))
+    kp = kernels.get("k_paths")
+    roofline = None
+    if kp:
+        samples_per_launch = nd * k / kp["launches"]
+        alg, per = algorithmic_bytes("k_paths", G.m, samples_per_launch)
+        gbs = alg / (kp["ms_per_launch"] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": "k_paths", "alg_bytes_per_unit": per}
+    out = {
+        "metric": "batched sampled temporal 3-paths/sec (six motifs x four deltas, one graph "
+                  "replay)",
+        "value": nd * k / (ms * 1e-3), "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"bitcoin-like batched: n={P['n']} m={P['m']} deltas={deltas} "
+                               f"k={k} per delta, six motifs", "n": P["n"], "m": P["m"],
+                   "deltas": deltas, "k_per_delta": k, "motifs": sg.SIX_MOTIFS, "seed": seed},
+        "tuning": best.as_dict(), "autotune_probe_ms": probe_ms,
+        "build_ms": t_build, "weights_ms": dict(zip(map(str, deltas), t_w)),
+        "edges_per_s_weights": {str(d): G.m / (t * 1e-3) for d, t in zip(deltas, t_w)},
+        "W": {str(d): W.total() for d, W in zip(deltas, Ws)},
+        "estimate": {str(d): o.estimate.cpu().tolist() for d, o in zip(deltas, outs)},
+        "overflowed_motifs": {str(d): [sg.SIX_MOTIFS[j] for j in range(nm) if st & (1 << (8 + j))]
+                              for d, st in zip(deltas, ref_status)},
+        "kernels": kernels, "roofline": roofline,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "batched":
+        if args.gpus != 1:
+            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                              "n_gpus": args.gpus}), flush=True)
+            sys.exit(2)
+        run_batched(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)

@@ -160,35 +160,50 @@ def gen_medium(seed: int = 1002, n: int = MEDIUM["n"], m: int = MEDIUM["m"],
     return TemporalGraph(n, src, dst, t, name="medium")
 
 
+def _powerlaw_ranks(rng, size: int, n: int, beta: float) -> np.ndarray:
+    """Ranks in [0, n) with density proportional to (r + 1)^-beta: inverse of
+    the continuous CDF F(x) = ((x + 1)^(1 - beta) - 1) / ((n + 1)^(1 - beta) - 1)."""
+    a = 1.0 - beta
+    top = (n + 1.0) ** a - 1.0
+    r = np.floor((1.0 + rng.random(size) * top) ** (1.0 / a) - 1.0).astype(np.int64)
+    return np.minimum(r, n - 1)
+
+
 def gen_bitcoin_like(seed: int = 1003, n: int = 5 * 10**7, m: int = 3 * 10**8,
                      alpha: float = 1.9, span: int = 7 * 365 * 86400,
                      chunk: int = 1 << 24) -> TemporalGraph:
-    """Bitcoin-like scale: Zipf(1.9) weights, each drawn (u, v) pair repeated
-    Geometric(0.5) times, timestamps uniform over seven years at 1 s."""
+    """Bitcoin-like scale: endpoint ranks drawn from a power law with degree
+    exponent alpha (rank density (r + 1)^(-1 / (alpha - 1)), one random
+    permutation mapping ranks to vertex ids for both roles, no self-loops),
+    each drawn (u, v) pair repeated Geometric(0.5) times, timestamps uniform
+    over seven years at 1 s."""
     rng = np.random.default_rng(seed)
-    p = zipf_vertex_weights(n, alpha, rng)
-    cdf = np.cumsum(p)
-    cdf[-1] = 1.0
+    beta = 1.0 / (alpha - 1.0)
+    perm = rng.permutation(n).astype(np.int32)
     src = np.empty(m, dtype=np.int32)
     dst = np.empty(m, dtype=np.int32)
     filled = 0
     while filled < m:
         q = min(chunk, m - filled)
-        s = np.minimum(np.searchsorted(cdf, rng.random(q), side="right"), n - 1).astype(np.int32)
-        d = np.minimum(np.searchsorted(cdf, rng.random(q), side="right"), n - 1).astype(np.int32)
+        s = _powerlaw_ranks(rng, q, n, beta)
+        d = _powerlaw_ranks(rng, q, n, beta)
         loops = np.nonzero(s == d)[0]
         while loops.size:
-            d[loops] = np.minimum(np.searchsorted(cdf, rng.random(loops.size), side="right"), n - 1)
+            d[loops] = _powerlaw_ranks(rng, loops.size, n, beta)
             loops = loops[s[loops] == d[loops]]
         reps = rng.geometric(0.5, size=q)
-        s = np.repeat(s, reps)
-        d = np.repeat(d, reps)
+        s = np.repeat(perm[s], reps)
+        d = np.repeat(perm[d], reps)
         take = min(s.size, m - filled)
         src[filled:filled + take] = s[:take]
         dst[filled:filled + take] = d[:take]
         filled += take
     t = rng.integers(0, span, size=m, dtype=np.int64)
     return TemporalGraph(n, src, dst, t, name="bitcoin-like")
+
+
+BITCOIN = dict(n=5 * 10**7, m=3 * 10**8, alpha=1.9, span=7 * 365 * 86400,
+               deltas=[600, 3600, 86400, 604800], k=10**8, seed=1)
 
 
 def gen_micro(seed: int, n: int = 5, m: int = 16, t_span: int = 12,
