@@ -259,7 +259,7 @@ def run_batched(args):
     torch.cuda.synchronize()
     tcb.timing_enable(False)
     kernels = {}
-    for kname in ("k_paths", "k_listcount_reg", "k_listcount_wave_lds", "k_listcount_wave_mem",
+    for kname in ("k_paths", "k_listcount_reg", "k_listcount_lds", "k_listcount_wide",
                   "k_listcount_big"):
         kms, n = tcb.timing_read(kname)
         if n:

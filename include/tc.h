@@ -169,12 +169,15 @@ typedef struct tc_result {
  *               (10..22; the queue and window scratch scale with it)
  *   path_blocks persistent blocks of the path kernel (0 = one per tile)
  *   reg_waves   wavefronts of the register ListCount pass
- *   fast_waves  wavefronts of the LDS-key ListCount pass (64..8192) */
+ *   fast_waves  wavefronts of the LDS-key ListCount pass (64..8192)
+ *   wide_blocks 256-thread blocks of the merged ListCount pass for lists
+ *               over 1024 entries (64..2048; 1 MiB of workspace each) */
 typedef struct {
   int32_t chunk_log2;
   int32_t path_blocks;
   int32_t reg_waves;
   int32_t fast_waves;
+  int32_t wide_blocks;
 } tc_tuning;
 
 /* Library version string (host, static storage). */
@@ -256,7 +259,7 @@ tc_status tc_batch_estimate(const tc_graph *g, const tc_weights *const *w, int32
 
 /* Autotuner: times tc_batch_estimate with k_probe samples for candidate
  * tunings (coordinate descent over chunk_log2, path_blocks, reg_waves,
- * fast_waves) with HIP events on `stream`, and returns the fastest in *best
+ * fast_waves, wide_blocks) with HIP events on `stream`, and returns the fastest in *best
  * and its time in *best_ms.  Synchronises the stream; `out` receives the
  * probe results.  ws must hold tc_batch_workspace_bytes(k_probe, ...). */
 tc_status tc_autotune(const tc_graph *g, const tc_weights *const *w, int32_t n_deltas,

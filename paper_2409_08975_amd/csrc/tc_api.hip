@@ -169,13 +169,15 @@ tc_status tc_autotune(const tc_graph* g, const tc_weights* const* w, int32_t n_d
   const int32_t pblocks[] = {0, 1024, 4096};
   const int32_t rwaves[] = {2560, 5120, 10240};
   const int32_t fwaves[] = {2560, 5120, 8192};
-  for (int dim = 0; dim < 4 && s == TC_OK; ++dim) {
+  const int32_t wblocks[] = {512, 1024, 2048};
+  for (int dim = 0; dim < 5 && s == TC_OK; ++dim) {
     for (int c = 0; c < 3 && s == TC_OK; ++c) {
       tc_tuning t = cur;
       if (dim == 0) t.chunk_log2 = chunks[c];
       if (dim == 1) t.path_blocks = pblocks[c];
       if (dim == 2) t.reg_waves = rwaves[c];
       if (dim == 3) t.fast_waves = fwaves[c];
+      if (dim == 4) t.wide_blocks = wblocks[c];
       double ms = 0;
       s = run(t, &ms);
       if (s == TC_OK && ms < cur_ms) {

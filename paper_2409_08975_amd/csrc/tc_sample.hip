@@ -27,9 +27,12 @@
 //                    with P_r the prefix sums of c_r and X = sum_i c_{l-1}[i];
 //                    keys staged in LDS, prefix sums held in registers across
 //                    the lanes, gathered with ds_bpermute.
-//   k_listcount_wave the same level recursion for longer lists, prefix sums
-//                    in per-wavefront scratch (LDS keys up to 1,024 entries,
-//                    then in-memory searches up to 65,536 entries).
+//   k_listcount_lds  one wavefront per item, lists up to 1,024 entries: the
+//                    same recursion with keys in LDS and prefix sums in
+//                    per-wavefront scratch.
+//   k_listcount_wide one 256-thread block per item, lists up to 65,536
+//                    entries: each level as a merge of L_{r-1} and L_r in
+//                    LDS tiles, prefix sums in per-block scratch.
 //   k_listcount_big  longer still: one thread per item, merged time sweep.
 // Each level total is summed in 128 bits (a total >= 2^64 sets the overflow
 // bit).  Block sums are 128-bit and reach the outputs with one set of
@@ -47,7 +50,6 @@ constexpr int kSWaves = kSBlock / kWave;
 constexpr int kLiBits = 22;  // local sample index bits of an item code
 constexpr int kKeyCap = 1024;
 constexpr int kWideCap = 65536;
-constexpr int kWideWaves = 64;
 constexpr int kMaxFastWaves = 8192;
 
 struct DeltaArgs {
@@ -106,7 +108,7 @@ struct SampleArgs {
   uint32_t* big_count;
   uint32_t* samp_h;  // [nd][chunk] proposal factor of each accepted sample
   uint64_t* fast_p;  // [fast waves][2][kKeyCap + 1]
-  uint64_t* wide_p;  // [kWideWaves][2][kWideCap + 1]
+  uint64_t* wide_p;  // [wide blocks][2][kWideCap + 1]
   MotifPlan plan;
 };
 
@@ -678,32 +680,27 @@ __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A) {
   sums_flush<1>(A);
 }
 
-// The level recursion with prefix sums in per-wavefront scratch (64-thread
-// blocks).  FAST keeps the keys of the previous and the current list in LDS
-// (lists up to kKeyCap, window below 2^32); otherwise the searches read the
-// pair index (lists up to kWideCap).  Items over the limit go to `fwd`.
-template <bool FAST>
-__global__ __launch_bounds__(kWave) void k_listcount_wave(SampleArgs A,
-                                                          const uint32_t* __restrict__ in_code,
-                                                          const uint32_t* __restrict__ in_count,
-                                                          uint32_t* in_next, uint32_t* fwd_code,
-                                                          uint32_t* fwd_count, uint64_t* pscratch,
-                                                          uint32_t cap) {
-  __shared__ uint32_t s_key[2][FAST ? kKeyCap : 1];
-  uint64_t* s_p[2] = {pscratch + (uint64_t)blockIdx.x * 2 * (cap + 1),
-                      pscratch + ((uint64_t)blockIdx.x * 2 + 1) * (cap + 1)};
+// Wavefront-per-item ListCount (64-thread blocks) for lists up to kKeyCap
+// entries in a window shorter than 2^32: the keys of the previous and the
+// current list sit in LDS as 32-bit offsets from the smallest head, the
+// prefix sums in per-wavefront scratch.  Longer lists or wider windows go to
+// the merged block-per-item pass.
+__global__ __launch_bounds__(kWave) void k_listcount_lds(SampleArgs A, uint64_t* pscratch) {
+  __shared__ uint32_t s_key[2][kKeyCap];
+  uint64_t* s_p[2] = {pscratch + (uint64_t)blockIdx.x * 2 * (kKeyCap + 1),
+                      pscratch + ((uint64_t)blockIdx.x * 2 + 1) * (kKeyCap + 1)};
   const int lane = threadIdx.x;
   sums_clear<1>(A);
-  const uint32_t n_items = *in_count;
+  const uint32_t n_items = *A.mid_count;
   // Lane 0 claims items; each iteration ends in the one lane-0 block that
   // retires the current item and claims the next, so no test of the lane
   // index lies between that block and the broadcast at the loop head.
   uint32_t next = 0;
-  if (lane == 0) next = atomicAdd(in_next, 1u);
+  if (lane == 0) next = atomicAdd(A.item_next, 1u);
   while (true) {
     const uint32_t it = uni(__shfl(next, 0, kWave));
     if (it >= n_items) break;
-    const uint32_t code = in_code[it];
+    const uint32_t code = A.mid_code[it];
     uint32_t li;
     int j, d;
     decode(code, &li, &j, &d);
@@ -714,7 +711,7 @@ __global__ __launch_bounds__(kWave) void k_listcount_wave(SampleArgs A,
       const uint64_t wi = win_index(A, d, A.plan.list_pair[j][lane], li);
       my_lo = A.win_lo[wi];
       my_len = A.win_len[wi];
-      if (FAST && my_len) my_first = A.pair_t[my_lo];
+      if (my_len) my_first = A.pair_t[my_lo];
     }
     uint32_t maxlen = my_len;
     int64_t base = my_first;
@@ -727,62 +724,231 @@ __global__ __launch_bounds__(kWave) void k_listcount_wave(SampleArgs A,
     }
     maxlen = uni(maxlen);
     base = uni64s(base);
-    const bool fwd = maxlen > cap || (FAST && A.D[d].delta >= ((int64_t)1 << 32));
+    const bool fwd = maxlen > (uint32_t)kKeyCap || A.D[d].delta >= ((int64_t)1 << 32);
     U128 total{0, 0};
     if (!fwd) {
-    if (FAST) {
       const uint32_t lo0 = uni(__shfl(my_lo, 0, kWave)), len0 = uni(__shfl(my_len, 0, kWave));
       for (uint32_t i = lane; i < len0; i += kWave)
         s_key[0][i] = (uint32_t)(A.pair_t[lo0 + i] - base);
       __threadfence_block();
-    }
-    int pb = 0;
-    for (int r = 1; r < l; ++r) {
-      const uint32_t prev_lo = uni(__shfl(my_lo, r - 1, kWave));
-      const uint32_t prev_len = uni(__shfl(my_len, r - 1, kWave));
-      const uint32_t lo = uni(__shfl(my_lo, r, kWave));
-      const uint32_t len = uni(__shfl(my_len, r, kWave));
-      const uint32_t* kprev = s_key[(r - 1) & 1];
-      uint32_t* kcur = s_key[r & 1];
-      const uint64_t* Pprev = s_p[pb ^ 1];
-      uint64_t* Pcur = s_p[pb];
-      total = U128{0, 0};
-      uint64_t carry = 0;
-      if (lane == 0) Pcur[0] = 0;
-      for (uint32_t c0 = 0; c0 < len; c0 += kWave) {
-        const uint32_t i = c0 + lane;
-        const bool act = i < len;
-        uint64_t c = 0;
-        if (act) {
-          const int64_t t = A.pair_t[lo + i];
-          uint32_t pos;  // entries of L_{r-1} strictly before t
-          if (FAST) {
-            const uint32_t key = (uint32_t)(t - base);
+      int pb = 0;
+      for (int r = 1; r < l; ++r) {
+        const uint32_t prev_len = uni(__shfl(my_len, r - 1, kWave));
+        const uint32_t lo = uni(__shfl(my_lo, r, kWave));
+        const uint32_t len = uni(__shfl(my_len, r, kWave));
+        const uint32_t* kprev = s_key[(r - 1) & 1];
+        uint32_t* kcur = s_key[r & 1];
+        const uint64_t* Pprev = s_p[pb ^ 1];
+        uint64_t* Pcur = s_p[pb];
+        total = U128{0, 0};
+        uint64_t carry = 0;
+        if (lane == 0) Pcur[0] = 0;
+        for (uint32_t c0 = 0; c0 < len; c0 += kWave) {
+          const uint32_t i = c0 + lane;
+          const bool act = i < len;
+          uint64_t c = 0;
+          if (act) {
+            const uint32_t key = (uint32_t)(A.pair_t[lo + i] - base);
             kcur[i] = key;
-            pos = lower_bound<uint32_t>(kprev, 0u, prev_len, key);
-          } else {
-            pos = lower_bound<int64_t>(A.pair_t, prev_lo, prev_lo + prev_len, t) - prev_lo;
+            const uint32_t pos = lower_bound<uint32_t>(kprev, 0u, prev_len, key);
+            c = (r == 1) ? (uint64_t)pos : Pprev[pos];
           }
-          c = (r == 1) ? (uint64_t)pos : Pprev[pos];
+          const uint64_t inc = wave_inclusive_scan(c);
+          if (act) Pcur[i + 1] = carry + inc;
+          total = add128(total, wave_sum128(U128{c, 0}));
+          carry += uni64(__shfl(inc, kWave - 1, kWave));
         }
-        const uint64_t inc = wave_inclusive_scan(c);
-        if (act) Pcur[i + 1] = carry + inc;
-        total = add128(total, wave_sum128(U128{c, 0}));
-        carry += uni64(__shfl(inc, kWave - 1, kWave));
+        total = U128{uni64(total.lo), uni64(total.hi)};
+        if (total.hi != 0 && lane == 0) flag_status(A, d, TC_F_OVERFLOW | TC_F_MOTIF(j));
+        pb ^= 1;
+        __threadfence_block();
       }
-      total = U128{uni64(total.lo), uni64(total.hi)};
-      if (total.hi != 0 && lane == 0) flag_status(A, d, TC_F_OVERFLOW | TC_F_MOTIF(j));
-      pb ^= 1;
-      __threadfence_block();
-    }
     }
     if (lane == 0) {
       if (fwd)
-        fwd_code[atomicAdd(fwd_count, 1u)] = code;
+        A.wide_code[atomicAdd(A.wide_count, 1u)] = code;
       else
         item_done(A, d, j, li, total.lo);
-      next = atomicAdd(in_next, 1u);
+      next = atomicAdd(A.item_next, 1u);
     }
+  }
+  __syncthreads();
+  sums_flush<1>(A);
+}
+
+// Block-per-item ListCount for lists up to kWideCap entries (256 threads).
+// Level r is a merge of the sorted times of L_{r-1} (A) and L_r (B): a step
+// stages a tile of A's times and of P_{r-1} in LDS and gives every thread four
+// consecutive entries of B; an entry is settled in this step when its time
+// is at most the tile's last time (or the tile ends A), and then
+//   pos = a0 + #{tile entries < t},  c = P_{r-1}[pos]
+// and P_r over the settled entries is a block scan with a carry across steps.
+// Settled entries are a prefix of B's tile.  If all are settled the next step
+// starts A at the last one's position; otherwise the tile is used up and A
+// restarts past it, first jumping by a 256-way probe of A to within one tile
+// of the first unsettled time.  Each step settles B's tile or moves A by a
+// full tile, so a level reads A, B and P_{r-1} once, in coalesced tiles.
+constexpr int kWBlock = 256;
+constexpr int kWWaves = kWBlock / kWave;
+constexpr int kWPer = 4;
+constexpr int kWTile = kWBlock * kWPer;  // entries of B per step, of A per tile
+constexpr int kDefaultWideBlocks = 1024;
+constexpr int kMaxWideBlocks = 2048;
+
+__global__ __launch_bounds__(kWBlock) void k_listcount_wide(SampleArgs A, uint64_t* pscratch) {
+  __shared__ int64_t sA[kWTile];
+  __shared__ uint64_t sP[kWTile + 1];
+  __shared__ uint64_t s_wsum[kWWaves];
+  __shared__ uint64_t s_wlo[kWWaves], s_whi[kWWaves];
+  __shared__ uint32_t s_wset[kWWaves];
+  __shared__ uint32_t s_lo[kMaxLists], s_len[kMaxLists];
+  __shared__ uint32_t s_item, s_last_pos;
+  __shared__ int64_t s_key0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint64_t* Pbuf[2] = {pscratch + (uint64_t)blockIdx.x * 2 * (kWideCap + 1),
+                       pscratch + ((uint64_t)blockIdx.x * 2 + 1) * (kWideCap + 1)};
+  sums_clear<1>(A);
+  const uint32_t n_items = *A.wide_count;
+  if (tid == 0) s_item = atomicAdd(A.wide_next, 1u);
+  __syncthreads();
+  uint32_t it = uni(s_item);
+  while (it < n_items) {
+    const uint32_t code = A.wide_code[it];
+    uint32_t li;
+    int j, d;
+    decode(code, &li, &j, &d);
+    const int l = A.plan.n_lists[j];
+    if (tid < l) {
+      const uint64_t wi = win_index(A, d, A.plan.list_pair[j][tid], li);
+      s_lo[tid] = A.win_lo[wi];
+      s_len[tid] = A.win_len[wi];
+    }
+    __syncthreads();
+    uint32_t maxlen = 0;
+    for (int r = 0; r < l; ++r) maxlen = s_len[r] > maxlen ? s_len[r] : maxlen;
+    maxlen = uni(maxlen);
+    U128 total{0, 0};
+    if (maxlen <= (uint32_t)kWideCap) {
+      for (int r = 1; r < l; ++r) {
+        const uint32_t loA = uni(s_lo[r - 1]), nA = uni(s_len[r - 1]);
+        const uint32_t loB = uni(s_lo[r]), nB = uni(s_len[r]);
+        const uint64_t* Pprev = Pbuf[(r - 1) & 1];
+        uint64_t* Pcur = Pbuf[r & 1];
+        const bool keep = r + 1 < l;  // P_r is read by the next level
+        if (keep && tid == 0) Pcur[0] = 0;
+        total = U128{0, 0};
+        uint64_t carry = 0;
+        uint32_t a0 = 0, b0 = 0;
+        while (b0 < nB) {
+          const uint32_t na = nA - a0 < (uint32_t)kWTile ? nA - a0 : (uint32_t)kWTile;
+          const uint32_t nb = nB - b0 < (uint32_t)kWTile ? nB - b0 : (uint32_t)kWTile;
+          for (uint32_t i = tid; i < na; i += kWBlock) sA[i] = A.pair_t[loA + a0 + i];
+          for (uint32_t i = tid; i <= na; i += kWBlock)
+            sP[i] = (r == 1) ? (uint64_t)(a0 + i) : Pprev[a0 + i];
+          int64_t key[kWPer];
+#pragma unroll
+          for (int e = 0; e < kWPer; ++e) {
+            const uint32_t bi = (uint32_t)(tid * kWPer + e);
+            key[e] = bi < nb ? A.pair_t[loB + b0 + bi] : INT64_MAX;
+          }
+          __syncthreads();
+          const bool a_ends = a0 + na == nA;
+          const int64_t a_last = na ? sA[na - 1] : INT64_MIN;
+          uint64_t c[kWPer];
+          uint32_t pl[kWPer];
+          uint32_t nset = 0;
+#pragma unroll
+          for (int e = 0; e < kWPer; ++e) {
+            const uint32_t bi = (uint32_t)(tid * kWPer + e);
+            const bool set = bi < nb && (a_ends || key[e] <= a_last);
+            pl[e] = set ? lower_bound<int64_t>(sA, 0u, na, key[e]) : 0u;
+            c[e] = set ? sP[pl[e]] : 0ull;
+            nset += set ? 1u : 0u;
+          }
+          // inclusive prefix of this thread's four counts, then across the block
+          uint64_t run[kWPer];
+          U128 tsum{0, 0};
+#pragma unroll
+          for (int e = 0; e < kWPer; ++e) {
+            run[e] = (e ? run[e - 1] : 0ull) + c[e];
+            tsum = add128(tsum, U128{c[e], 0});
+          }
+          const uint64_t incl = wave_inclusive_scan(run[kWPer - 1]);
+          const U128 wsum = wave_sum128(tsum);
+          uint32_t wset = nset;
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) wset += __shfl_xor(wset, off, kWave);
+          if (lane == kWave - 1) {
+            s_wsum[wave] = incl;
+            s_wlo[wave] = wsum.lo;
+            s_whi[wave] = wsum.hi;
+            s_wset[wave] = wset;
+          }
+          __syncthreads();
+          uint64_t before = carry + incl - run[kWPer - 1];
+          uint32_t nr = 0;
+          U128 step{0, 0};
+#pragma unroll
+          for (int w = 0; w < kWWaves; ++w) {
+            if (w < wave) before += s_wsum[w];
+            nr += s_wset[w];
+            step = add128(step, U128{s_wlo[w], s_whi[w]});
+          }
+          nr = uni(nr);
+          if (keep) {
+#pragma unroll
+            for (int e = 0; e < kWPer; ++e) {
+              const uint32_t bi = (uint32_t)(tid * kWPer + e);
+              if (bi < nr) Pcur[b0 + bi + 1] = before + run[e];
+            }
+          }
+          total = add128(total, U128{uni64(step.lo), uni64(step.hi)});
+          uint64_t blk = 0;
+#pragma unroll
+          for (int w = 0; w < kWWaves; ++w) blk += s_wsum[w];
+          carry += uni64(blk);
+          // the next step's start in A
+          if (nr == nb) {
+#pragma unroll
+            for (int e = 0; e < kWPer; ++e)
+              if ((uint32_t)(tid * kWPer + e) == nb - 1) s_last_pos = pl[e];
+          } else {
+#pragma unroll
+            for (int e = 0; e < kWPer; ++e)
+              if ((uint32_t)(tid * kWPer + e) == nr) s_key0 = key[e];
+          }
+          __syncthreads();
+          b0 += nr;
+          if (nr == nb) {
+            a0 += uni(s_last_pos);
+          } else {
+            a0 += na;
+            const uint32_t rem = nA - a0;
+            if (rem > (uint32_t)kWTile) {
+              const int64_t key0 = uni64s(s_key0);
+              const uint32_t stride = (rem + kWBlock - 1) / kWBlock;
+              const uint64_t q = (uint64_t)a0 + (uint64_t)(tid + 1) * stride - 1;
+              const bool below = q < nA && A.pair_t[loA + q] < key0;
+              const uint32_t nb_below = (uint32_t)__syncthreads_count(below);
+              a0 += uni(nb_below) * stride;
+            }
+          }
+          __syncthreads();  // the tiles are rewritten by the next step
+        }
+        if (uni64(total.hi) != 0 && tid == 0) flag_status(A, d, TC_F_OVERFLOW | TC_F_MOTIF(j));
+        __threadfence_block();
+        __syncthreads();  // P_r complete before the next level reads it
+      }
+    }
+    if (tid == 0) {
+      if (maxlen > (uint32_t)kWideCap)
+        A.big_code[atomicAdd(A.big_count, 1u)] = code;
+      else
+        item_done(A, d, j, li, total.lo);
+      s_item = atomicAdd(A.wide_next, 1u);
+    }
+    __syncthreads();
+    it = uni(s_item);
   }
   __syncthreads();
   sums_flush<1>(A);
@@ -889,6 +1055,7 @@ SampleTuning default_tuning() {
   t.path_blocks = 0;
   t.reg_waves = 5120;
   t.fast_waves = 5120;
+  t.wide_blocks = kDefaultWideBlocks;
   return t;
 }
 
@@ -903,10 +1070,15 @@ static int fast_waves_for(const SampleTuning& t) {
   return t.fast_waves < 64 ? 64 : (t.fast_waves > kMaxFastWaves ? kMaxFastWaves : t.fast_waves);
 }
 
+static int wide_blocks_for(const SampleTuning& t) {
+  return t.wide_blocks < 64 ? 64
+                            : (t.wide_blocks > kMaxWideBlocks ? kMaxWideBlocks : t.wide_blocks);
+}
+
 struct SampleLayout {
   size_t win_lo, win_len, code, mid, wide, big, counters, fast_p, wide_p, est_ptrs, samp_h, total;
   uint64_t chunk, cap;
-  int fast_waves;
+  int fast_waves, wide_blocks;
 };
 
 static SampleLayout sample_layout(uint64_t k, int nd, int32_t n_motifs, const SampleTuning& t) {
@@ -914,6 +1086,7 @@ static SampleLayout sample_layout(uint64_t k, int nd, int32_t n_motifs, const Sa
   L.chunk = chunk_for(k, nd, t);
   L.cap = L.chunk * (uint64_t)nd * (uint64_t)n_motifs;
   L.fast_waves = fast_waves_for(t);
+  L.wide_blocks = wide_blocks_for(t);
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -928,7 +1101,7 @@ static SampleLayout sample_layout(uint64_t k, int nd, int32_t n_motifs, const Sa
   L.big = take(L.cap * 4);
   L.counters = take(32);
   L.fast_p = take((size_t)L.fast_waves * 2 * (kKeyCap + 1) * 8);
-  L.wide_p = take((size_t)kWideWaves * 2 * (kWideCap + 1) * 8);
+  L.wide_p = take((size_t)L.wide_blocks * 2 * (kWideCap + 1) * 8);
   L.est_ptrs = take(kMaxDeltas * sizeof(double*));
   L.samp_h = take((size_t)nd * L.chunk * 4);
   L.total = o;
@@ -940,6 +1113,7 @@ size_t sample_workspace_bytes(uint64_t k, int nd, int32_t n_motifs, const Sample
   if (!t) {  // room for any tuning
     tt.chunk_log2 = kLiBits;
     tt.fast_waves = kMaxFastWaves;
+    tt.wide_blocks = kMaxWideBlocks;
   }
   return sample_layout(k, nd, n_motifs, tt).total;
 }
@@ -1040,18 +1214,14 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
                            st, A);
       }
       {
-        TimedLaunch tl("k_listcount_wave_lds", st);
-        hipLaunchKernelGGL(k_listcount_wave<true>, dim3((unsigned)L.fast_waves), dim3(kWave),
-                           sums_bytes(1, nd, nm), st, A, (const uint32_t*)A.mid_code,
-                           (const uint32_t*)A.mid_count, A.item_next, A.wide_code, A.wide_count,
-                           A.fast_p, (uint32_t)kKeyCap);
+        TimedLaunch tl("k_listcount_lds", st);
+        hipLaunchKernelGGL(k_listcount_lds, dim3((unsigned)L.fast_waves), dim3(kWave),
+                           sums_bytes(1, nd, nm), st, A, A.fast_p);
       }
       {
-        TimedLaunch tl("k_listcount_wave_mem", st);
-        hipLaunchKernelGGL(k_listcount_wave<false>, dim3(kWideWaves), dim3(kWave),
-                           sums_bytes(1, nd, nm), st, A, (const uint32_t*)A.wide_code,
-                           (const uint32_t*)A.wide_count, A.wide_next, A.big_code, A.big_count,
-                           A.wide_p, (uint32_t)kWideCap);
+        TimedLaunch tl("k_listcount_wide", st);
+        hipLaunchKernelGGL(k_listcount_wide, dim3((unsigned)L.wide_blocks), dim3(kWBlock),
+                           sums_bytes(1, nd, nm), st, A, A.wide_p);
       }
       {
         TimedLaunch tl("k_listcount_big", st);

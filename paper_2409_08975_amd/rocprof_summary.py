@@ -24,7 +24,8 @@ CALIB_BYTES = 1 << 30
 # kernel base name -> source file holding it
 KERNEL_SRC = {
     "k_paths": "tc_sample.hip", "k_listcount_reg": "tc_sample.hip",
-    "k_listcount_wave": "tc_sample.hip", "k_listcount_big": "tc_sample.hip",
+    "k_listcount_lds": "tc_sample.hip", "k_listcount_wide": "tc_sample.hip",
+    "k_listcount_big": "tc_sample.hip",
     "k_windows": "tc_weights.hip", "k_mp_rank": "tc_weights.hip", "k_combine": "tc_weights.hip",
     "k_scan_tiles": "tc_weights.hip", "k_scan_apply": "tc_weights.hip",
     "k_tree_level": "tc_weights.hip", "k_radix_scatter": "tc_build.hip",

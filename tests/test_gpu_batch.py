@@ -67,10 +67,10 @@ def test_batch_equals_single_delta_calls_and_oracle(tcb, tiny):
 
 
 @pytest.mark.parametrize("tuning", [
-    dict(chunk_log2=12, path_blocks=0, reg_waves=5120, fast_waves=5120),
-    dict(chunk_log2=16, path_blocks=7, reg_waves=64, fast_waves=64),
-    dict(chunk_log2=22, path_blocks=1, reg_waves=100, fast_waves=16384),
-    dict(chunk_log2=10, path_blocks=3000, reg_waves=1, fast_waves=1),
+    dict(chunk_log2=12, path_blocks=0, reg_waves=5120, fast_waves=5120, wide_blocks=1024),
+    dict(chunk_log2=16, path_blocks=7, reg_waves=64, fast_waves=64, wide_blocks=64),
+    dict(chunk_log2=22, path_blocks=1, reg_waves=100, fast_waves=16384, wide_blocks=2048),
+    dict(chunk_log2=10, path_blocks=3000, reg_waves=1, fast_waves=1, wide_blocks=1),
 ])
 def test_batch_results_independent_of_tuning(tcb, tiny, tuning):
     g, G, og, Ws = tiny

@@ -332,6 +332,50 @@ def test_listcount_overflow_flag(tcb, torch_mod):
     check_sample(tcb, G, Wt, og, ow, [M40, motif[:9]], 20000, seed=1, per_sample=True)
 
 
+LONG_CASES = {
+    # name: (A->D edges, B->D edges, time span of the lists, delta offset)
+    "wide_balanced": (3000, 2000, 4000, 0),
+    "wide_imbalanced": (60, 90000, 30000, 0),
+    "wide_ragged": (2100, 2000, 1500, 0),
+    "wide_delta_2e32": (900, 700, 1200, 2**33),
+    "big": (150000, 400, 20000, 0),
+}
+
+
+@pytest.mark.parametrize("case", list(LONG_CASES))
+def test_long_lists_tiers(tcb, torch_mod, case):
+    """Items whose lists run past the register and LDS tiers: the spine
+    A->B->C->D (30 x 1 x 30 copies, so every draw is this spine with its own
+    t1 and t3) and a motif with three lists A->D, B->D, A->D after it.  D has
+    no out-edges, so no list edge centres a path.  List times are drawn with
+    many ties over `span` seconds and delta cuts through them, so the windows
+    differ with t1; lengths reach the merged block-per-item tier (1,025 ..
+    65,536 entries, with a strongly imbalanced pair and with delta >= 2^32)
+    and the one-thread tier beyond."""
+    n_ad, n_bd, span, dplus = LONG_CASES[case]
+    A_, B_, C_, D_ = 0, 1, 2, 3
+    rng = np.random.default_rng(len(case))
+    src = [A_] * 30 + [B_] + [C_] * 30
+    dst = [B_] * 30 + [C_] + [D_] * 30
+    t = list(range(1, 31)) + [40] + list(range(41, 71))
+    t0 = 100
+    src += [A_] * n_ad + [B_] * n_bd
+    dst += [D_] * (n_ad + n_bd)
+    t += (t0 + rng.integers(0, span, size=n_ad)).tolist()
+    t += (t0 + rng.integers(0, span, size=n_bd)).tolist()
+    g = sg.TemporalGraph(4, np.array(src, np.int32), np.array(dst, np.int32),
+                         np.array(t, np.int64))
+    G, og = build_both(tcb, torch_mod, g)
+    motif = [(A_, B_), (B_, C_), (C_, D_), (A_, D_), (B_, D_), (A_, D_)]
+    delta = t0 + span // 2 + dplus
+    Wt = tcb.tc_path_weights(G, delta)
+    ow = og.weights(delta)
+    check_weights(Wt, ow, g, og)
+    assert ow.W == 900
+    R, E = check_sample(tcb, G, Wt, og, ow, [motif, motif[:5]], 3000, seed=4, per_sample=True)
+    assert E.status == 0 and int(E.hits[0]) > 0
+
+
 # --------------------------------------------------------- medium scale ----
 @pytest.fixture(scope="module")
 def medium(tcb, torch_mod):
