@@ -186,6 +186,26 @@ def learned_vs_method(tcb, G, Wt, motif, seeds, k_ref, stream):
                      "ms_per_estimate_method": tp / seeds,
                      "ms_per_estimate_learned": tl / seeds})
     out["by_k"] = rows
+    # Equal error: the learned proposal needs k / ratio samples for the error
+    # of the method at k.  Its wall time counts features, inference, h and
+    # the q-scan (training is reported apart), plus sampling at k / ratio,
+    # from the per-sample time measured at each k.
+    ratio = out["variance_ratio"]
+    if ratio:
+        fixed = out["features_ms"] + out["proposal_ms"]
+        eq = []
+        for row in rows:
+            k = row["k"]
+            t_m = row["ms_per_estimate_method"]
+            t_l = fixed + row["ms_per_estimate_learned"] / ratio
+            eq.append({"k_method": k, "k_learned": k / ratio, "wall_ms_method": t_m,
+                       "wall_ms_learned": t_l, "learned_faster": t_l < t_m})
+        big = rows[-1]
+        per_m = big["ms_per_estimate_method"] / big["k"]
+        per_l = big["ms_per_estimate_learned"] / big["k"] / ratio
+        out["equal_error"] = {
+            "samples_factor": ratio, "fixed_ms": fixed, "by_k": eq,
+            "break_even_k": fixed / (per_m - per_l) if per_m > per_l else None}
     return out
 
 

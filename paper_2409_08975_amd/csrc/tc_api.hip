@@ -39,8 +39,12 @@ tc_status compile_motifs(const tc_motif* motifs, int32_t n_motifs, MotifPlan* pl
   uint32_t gate_mask = 0;
   for (int j = 0; j < n_motifs; ++j)
     if (plan->n_lists[j] >= 1) gate_mask |= 1u << plan->list_pair[j][0];
+  for (int q = 0; q < kMaxPairs; ++q) plan->gate_index[q] = 0xFF;
   for (int q = 0; q < plan->n_pairs; ++q)
-    if (gate_mask & (1u << q)) plan->gate_pair[plan->n_gates++] = (uint8_t)q;
+    if (gate_mask & (1u << q)) {
+      plan->gate_index[q] = (uint8_t)plan->n_gates;
+      plan->gate_pair[plan->n_gates++] = (uint8_t)q;
+    }
   for (int j = 0; j < n_motifs; ++j) {
     uint32_t mk = 0;
     for (int r = 1; r < plan->n_lists[j]; ++r) mk |= 1u << plan->list_pair[j][r];

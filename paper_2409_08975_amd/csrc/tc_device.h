@@ -190,14 +190,89 @@ __host__ __device__ __forceinline__ uint64_t pair_hash(uint64_t key, int log2cap
   return (key * 0x9E3779B97F4A7C15ull) >> (64 - log2cap);
 }
 
-// [start, end) of the run of edges a -> b in the pair index (empty if none)
-__device__ __forceinline__ void pair_run(const PairSlot* __restrict__ tab, int log2cap, int32_t a,
+// First index in [lo, hi) with a[idx] > key, searched outward from lo:
+// probes lo, lo+1, lo+3, lo+7, ... until one exceeds key, then bisects the
+// last gap.  When the answer is near lo (a short time window starting at lo)
+// the probes stay in the cache lines already fetched.
+template <typename T>
+__device__ __forceinline__ uint32_t upper_bound_from(const T* __restrict__ a, uint32_t lo,
+                                                     uint32_t hi, T key) {
+  uint32_t step = 1, prev = lo;  // every index below prev holds a value <= key
+  uint32_t probe = lo;
+  while (probe < hi && a[probe] <= key) {
+    prev = probe + 1;
+    probe = lo + 2 * step - 1;
+    step *= 2;
+  }
+  return upper_bound<T>(a, prev, probe < hi ? probe : hi, key);
+}
+
+// Entries of sampled level k (pair_t[16^k i]) of a pair index of m entries.
+__host__ __device__ __forceinline__ int64_t skip_level_len(int64_t m, int k) {
+  return (m + ((int64_t)1 << (4 * k)) - 1) >> (4 * k);
+}
+
+// Number of the n (<= 16) consecutive values a[0..n) that are <= t (the
+// values are sorted, so these form a prefix).  All sixteen loads are issued
+// before any is used (indices past n reload a[0]), so the count costs one
+// memory round trip.
+__device__ __forceinline__ uint32_t count_le16(const int64_t* __restrict__ a, uint32_t n,
+                                               int64_t t) {
+  int64_t v[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = a[(uint32_t)j < n ? (uint32_t)j : 0u];
+  uint32_t c = 0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) c += ((uint32_t)j < n && v[j] <= t) ? 1u : 0u;
+  return c;
+}
+
+// First position in [lo, hi) whose time exceeds t (hi if none), where
+// [lo, hi) lies inside one run of the pair index (times sorted).  Equal to
+// upper_bound over pair_t.  From the coarsest level down, the samples of
+// level k inside the range (at most 16 once a coarser level has cut it)
+// cut the range to the gap between two neighbouring samples; the last step
+// counts at most 16 consecutive times.  A run of L entries takes about
+// log16(L) dependent round trips instead of log2(L).
+__device__ __forceinline__ uint32_t run_upper_bound(const int64_t* __restrict__ pair_t,
+                                                   const int64_t* __restrict__ skip, int64_t m,
+                                                   uint32_t lo, uint32_t hi, int64_t t) {
+  const int64_t n1 = skip_level_len(m, 1), n2 = skip_level_len(m, 2);
+  for (int k = 3; k >= 1; --k) {
+    if (hi - lo <= 16u) break;
+    const int sh = 4 * k;
+    const uint32_t i0 = (uint32_t)(((uint64_t)lo + ((uint64_t)1 << sh) - 1) >> sh);
+    const uint32_t i1 = (hi - 1) >> sh;  // samples i0..i1 lie in [lo, hi)
+    if (i1 < i0) continue;
+    const int64_t* C = skip + (k == 1 ? 0 : (k == 2 ? n1 : n1 + n2));
+    const uint32_t cnt = i1 - i0 + 1;
+    const uint32_t n_le =  // samples with time <= t (a prefix of them)
+        cnt <= 16u ? count_le16(C + i0, cnt, t) : upper_bound<int64_t>(C, i0, i1 + 1, t) - i0;
+    if (n_le > 0) lo = ((i0 + n_le - 1) << sh) + 1;
+    if (n_le < cnt) hi = (i0 + n_le) << sh;
+  }
+  return lo + count_le16(pair_t + lo, hi - lo, t);
+}
+
+// Bit of a pair in the membership filter (the top log2bits of the same
+// multiplicative hash as the run table).
+__host__ __device__ __forceinline__ uint64_t pair_filter_bit(uint64_t key, int log2bits) {
+  return pair_hash(key, log2bits);
+}
+
+// [start, end) of the run of edges a -> b in the pair index (empty if none).
+// The filter is asked first: it is small enough to stay in the last-level
+// cache, and most pairs the sampler asks for have no edge.
+__device__ __forceinline__ void pair_run(const uint64_t* __restrict__ filter, int filter_log2,
+                                         const PairSlot* __restrict__ tab, int log2cap, int32_t a,
                                          int32_t b, uint32_t* start, uint32_t* end) {
   const uint64_t key = pair_key((uint32_t)a, (uint32_t)b);
-  const uint64_t mask = (1ull << log2cap) - 1;
-  uint64_t h = pair_hash(key, log2cap);
   *start = 0;
   *end = 0;
+  const uint64_t fb = pair_filter_bit(key, filter_log2);
+  if (!((filter[fb >> 6] >> (fb & 63)) & 1ull)) return;
+  const uint64_t mask = (1ull << log2cap) - 1;
+  uint64_t h = pair_hash(key, log2cap);
   for (uint64_t probe = 0; probe <= mask; ++probe) {
     const PairSlot sl = tab[h];
     if (sl.key == key) {

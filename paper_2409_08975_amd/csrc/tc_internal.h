@@ -48,6 +48,7 @@ struct MotifPlan {
   uint8_t list_pair[kMaxMotifs][kMaxLists];     // pair index of each list
   int32_t n_gates;
   uint8_t gate_pair[kMaxPairs];                 // distinct first-list pairs
+  uint8_t gate_index[kMaxPairs];                // pair -> its gate index, or 0xFF
   uint16_t rest_mask[kMaxMotifs];               // other pairs of each motif (not gates)
 };
 

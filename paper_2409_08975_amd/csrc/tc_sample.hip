@@ -78,6 +78,9 @@ struct SampleArgs {
   const int64_t* pair_t;
   const PairSlot* pair_hash;
   int32_t pair_hash_log2;
+  const uint64_t* pair_filter;
+  int32_t pair_filter_log2;
+  const int64_t* pair_skip;
   int64_t m;
   uint64_t tree_off[kMaxTreeLevels];
   int32_t tree_levels;
@@ -127,9 +130,9 @@ __device__ __forceinline__ void pair_window(const SampleArgs& A, int32_t va, int
                                             int64_t t_lo, int64_t t_hi, uint32_t* lo,
                                             uint32_t* hi) {
   uint32_t r0, r1;
-  pair_run(A.pair_hash, A.pair_hash_log2, va, vb, &r0, &r1);
-  const uint32_t l = upper_bound<int64_t>(A.pair_t, r0, r1, t_lo);
-  const uint32_t h = upper_bound<int64_t>(A.pair_t, l, r1, t_hi);
+  pair_run(A.pair_filter, A.pair_filter_log2, A.pair_hash, A.pair_hash_log2, va, vb, &r0, &r1);
+  const uint32_t l = run_upper_bound(A.pair_t, A.pair_skip, A.m, r0, r1, t_lo);
+  const uint32_t h = run_upper_bound(A.pair_t, A.pair_skip, A.m, l, r1, t_hi);
   *lo = l;
   *hi = h;
 }
@@ -287,6 +290,7 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
   __shared__ uint32_t s_mask[kSBlock];     // pairs still needed by each accepted path
   __shared__ uint32_t s_off[kSBlock + 1];  // exclusive prefix of their counts
   __shared__ uint32_t s_wsum[kSWaves];
+  __shared__ uint32_t s_glen[kMaxPairs][kSBlock];  // gate window length per accepted path
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int nm = A.plan.n_motifs;
@@ -374,12 +378,14 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
       }
     }
     // compact the accepted paths of the tile into LDS
+    uint32_t my_sidx = 0;  // this sample's slot among them (if accepted)
     {
       const uint64_t mask = __ballot(valid);
       uint32_t base = 0;
       if (lane == 0 && mask) base = atomicAdd(&s_nvalid, (uint32_t)__popcll(mask));
       base = __shfl(base, 0, kWave);
-      if (valid) s_path[base + __popcll(mask & lt_mask)] = PathRec{x, u, v, y, t1, t3, li};
+      my_sidx = base + (uint32_t)__popcll(mask & lt_mask);
+      if (valid) s_path[my_sidx] = PathRec{x, u, v, y, t1, t3, li};
     }
     __syncthreads();
     // phase A: the gate pairs of every accepted path, one (path, pair)
@@ -396,6 +402,7 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
                   &lo, &hi);
       A.win_lo[win_index(A, d, q, P.li)] = lo;
       A.win_len[win_index(A, d, q, P.li)] = hi - lo;
+      s_glen[gi][sidx] = hi - lo;
     }
     __threadfence_block();
     __syncthreads();
@@ -403,10 +410,9 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
     if ((uint32_t)np > ng) {
       uint32_t mask = 0;
       if (tid < nvalid) {
-        const uint32_t pli = s_path[tid].li;
         for (int j = 0; j < nm; ++j)
           if (A.plan.n_lists[j] >= 2 &&
-              A.win_len[win_index(A, d, A.plan.list_pair[j][0], pli)] != 0)
+              s_glen[A.plan.gate_index[A.plan.list_pair[j][0]]][tid] != 0)
             mask |= A.plan.rest_mask[j];
       }
       const uint32_t cnt = (uint32_t)__popc(mask);
@@ -450,7 +456,7 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
         if (l == 0) {
           X = 1;
         } else if (l == 1) {
-          X = A.win_len[win_index(A, d, A.plan.list_pair[j][0], li)];
+          X = s_glen[A.plan.gate_index[A.plan.list_pair[j][0]]][my_sidx];
         } else {
           // an empty list gives 0 unless the lists before it could already
           // hold 2^64 chains (then the count must run to flag it)
@@ -458,7 +464,10 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
           bool empty = false, big = false;
           // lists after the first empty one were not searched (gating)
           for (int r = 0; r < l; ++r) {
-            const uint32_t len = A.win_len[win_index(A, d, A.plan.list_pair[j][r], li)];
+            const uint32_t q = A.plan.list_pair[j][r];
+            const uint32_t gi = A.plan.gate_index[q];
+            const uint32_t len =
+                gi != 0xFFu ? s_glen[gi][my_sidx] : A.win_len[win_index(A, d, (int)q, li)];
             if (len == 0) {
               empty = true;
               break;
@@ -481,11 +490,15 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
       }
       if (active && W != 0 && !defer && D.X) D.X[(uint64_t)j * A.k + ii] = X;
       const uint64_t Xc = defer ? 0ull : X;
-      bool ovf = false;
-      const U128 sx = wave_sum128c(contribution(Xc, D.h != nullptr, hp), &ovf);
-      const uint64_t h = wave_sum64(Xc != 0 ? 1ull : 0ull);
-      const double sq = D.m2 ? wave_sumf64(square_term(Xc, hp)) : 0.0;
-      if (lane == 0) sums_add(sums_slot(A, wave, d, j), sx, h, sq, ovf);
+      // most wavefronts close no path of a motif: their sums are all zero
+      const uint64_t nz = __ballot(Xc != 0);
+      if (nz) {
+        bool ovf = false;
+        const U128 sx = wave_sum128c(contribution(Xc, D.h != nullptr, hp), &ovf);
+        const double sq = D.m2 ? wave_sumf64(square_term(Xc, hp)) : 0.0;
+        if (lane == 0)
+          sums_add(sums_slot(A, wave, d, j), sx, (uint64_t)__popcll(nz), sq, ovf);
+      }
     }
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) st_bits |= __shfl_xor(st_bits, off, kWave);
@@ -1133,6 +1146,9 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
   A.pair_t = g->pair_t;
   A.pair_hash = (const PairSlot*)g->pair_hash;
   A.pair_hash_log2 = g->pair_hash_log2;
+  A.pair_filter = g->pair_filter;
+  A.pair_filter_log2 = g->pair_filter_log2;
+  A.pair_skip = g->pair_skip;
   A.m = g->m;
   {
     const STree T = stree_layout(g->m);
