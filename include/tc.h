@@ -103,12 +103,6 @@ typedef struct tc_graph {
                                          cache-line access per sampled end edge:
                                          {i32 other end (dst resp. src), i32 eid,
                                          i64 t}                                  */
-  uint64_t *pair_filter;              /* 2^pair_filter_log2 bits (at most 2^28,
-                                         32 MiB): the bit of hash(src<<32|dst) is
-                                         set for every pair that has an edge, so
-                                         a clear bit proves a pair absent without
-                                         touching the run table                  */
-  int32_t pair_filter_log2;
   int64_t *pair_skip;                 /* sampled pair times for searches inside a
                                          run: level k = 1, 2, 3 holds
                                          pair_t[16^k i] for i < ceil(m / 16^k),

@@ -70,8 +70,7 @@ class tc_graph(ctypes.Structure):
                 ("in_dst", _P), ("in_t", _P), ("out_to_in", _P), ("pair_dst", _P),
                 ("pair_eid", _P), ("pair_t", _P),
                 ("status", _P), ("pair_hash", _P), ("pair_hash_log2", ctypes.c_int32),
-                ("out_rec", _P), ("in_rec", _P), ("pair_filter", _P),
-                ("pair_filter_log2", ctypes.c_int32), ("pair_skip", _P)]
+                ("out_rec", _P), ("in_rec", _P), ("pair_skip", _P)]
 
 
 class tc_weights(ctypes.Structure):

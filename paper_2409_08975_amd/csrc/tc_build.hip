@@ -443,15 +443,11 @@ __global__ __launch_bounds__(256) void k_hash_insert(const uint32_t* __restrict_
                                                      const int32_t* __restrict__ pdst,
                                                      const uint32_t* __restrict__ run_start,
                                                      const uint32_t* __restrict__ n_runs,
-                                                     PairSlot* __restrict__ tab, int log2cap,
-                                                     uint64_t* __restrict__ filter,
-                                                     int filter_log2) {
+                                                     PairSlot* __restrict__ tab, int log2cap) {
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= *n_runs) return;
   const uint32_t s0 = run_start[r], s1 = run_start[r + 1];
   const uint64_t key = pair_key(psrc[s0], pdst[s0]);
-  const uint64_t fb = pair_filter_bit(key, filter_log2);
-  atomicOr((unsigned long long*)&filter[fb >> 6], 1ull << (fb & 63));
   const uint64_t mask = (1ull << log2cap) - 1;
   uint64_t h = pair_hash(key, log2cap);
   for (uint64_t probe = 0; probe <= mask; ++probe) {
@@ -483,14 +479,6 @@ __global__ __launch_bounds__(256) void k_pair_skip(const int64_t* __restrict__ p
 int pair_hash_log2(int64_t m) {
   int lg = 4;
   while (((int64_t)1 << lg) < m + m / 4 + 1) ++lg;
-  return lg;
-}
-
-// Membership filter: about 8 bits per edge, at most 2^28 bits (32 MiB), so
-// that it stays resident in the 256 MiB last-level cache.
-int pair_filter_log2(int64_t m) {
-  int lg = 12;
-  while (lg < 28 && ((int64_t)1 << lg) < 8 * m) ++lg;
   return lg;
 }
 
@@ -561,7 +549,7 @@ static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct GraphLayout {
   size_t out_off, in_off, out_src, out_dst, out_eid, out_t, in_src, in_eid, in_dst, in_t,
       out_to_in, pair_dst, out_rec, in_rec,
-      pair_eid, pair_t, pair_hash, pair_filter, pair_skip, status, tminmax, keys0, keys1, vals0, vals1, hist, part,
+      pair_eid, pair_t, pair_hash, pair_skip, status, tminmax, keys0, keys1, vals0, vals1, hist, part,
       part_elems, rk[3], rv[3], total;
 };
 
@@ -593,7 +581,6 @@ static GraphLayout graph_layout(int32_t n, int64_t m) {
   L.out_rec = take(M * 16);
   L.in_rec = take(M * 16);
   L.pair_hash = take(sizeof(PairSlot) << pair_hash_log2(m));
-  L.pair_filter = take(((size_t)1 << pair_filter_log2(m)) / 8);
   L.pair_skip =
       take((size_t)(skip_level_len(m, 1) + skip_level_len(m, 2) + skip_level_len(m, 3)) * 8);
   L.status = take(4);
@@ -643,8 +630,7 @@ static bool build_pair_hash(const uint32_t* psrc, const tc_graph* g, int64_t m, 
   }
   hipLaunchKernelGGL(k_hash_insert, dim3(blocks_for(m, 256)), dim3(256), 0, st, psrc,
                      (const int32_t*)g->pair_dst, (const uint32_t*)run_start,
-                     (const uint32_t*)(run_of + m), tab, g->pair_hash_log2, g->pair_filter,
-                     g->pair_filter_log2);
+                     (const uint32_t*)(run_of + m), tab, g->pair_hash_log2);
   return true;
 }
 
@@ -672,8 +658,6 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   g->status = (uint32_t*)(base + L.status);
   g->pair_hash = (void*)(base + L.pair_hash);
   g->pair_hash_log2 = pair_hash_log2(m);
-  g->pair_filter = (uint64_t*)(base + L.pair_filter);
-  g->pair_filter_log2 = pair_filter_log2(m);
   g->pair_skip = (int64_t*)(base + L.pair_skip);
   g->out_rec = (void*)(base + L.out_rec);
   g->in_rec = (void*)(base + L.in_rec);
@@ -711,11 +695,6 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   const int64_t cap = (int64_t)1 << g->pair_hash_log2;
   PairSlot* tab = (PairSlot*)g->pair_hash;
   hipLaunchKernelGGL(k_hash_clear, dim3(blocks_for(cap, 256)), dim3(256), 0, st, tab, cap);
-  {
-    const int64_t words32 = ((int64_t)1 << g->pair_filter_log2) / 32;
-    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(words32, 256)), dim3(256), 0, st,
-                       (uint32_t*)g->pair_filter, words32, 0u);
-  }
   if (m == 0) {
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for((int64_t)n + 1, 256)), dim3(256), 0, st,
                        g->out_off, (int64_t)n + 1, 0u);

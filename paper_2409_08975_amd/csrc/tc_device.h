@@ -254,23 +254,12 @@ __device__ __forceinline__ uint32_t run_upper_bound(const int64_t* __restrict__ 
   return lo + count_le16(pair_t + lo, hi - lo, t);
 }
 
-// Bit of a pair in the membership filter (the top log2bits of the same
-// multiplicative hash as the run table).
-__host__ __device__ __forceinline__ uint64_t pair_filter_bit(uint64_t key, int log2bits) {
-  return pair_hash(key, log2bits);
-}
-
-// [start, end) of the run of edges a -> b in the pair index (empty if none).
-// The filter is asked first: it is small enough to stay in the last-level
-// cache, and most pairs the sampler asks for have no edge.
-__device__ __forceinline__ void pair_run(const uint64_t* __restrict__ filter, int filter_log2,
-                                         const PairSlot* __restrict__ tab, int log2cap, int32_t a,
+// [start, end) of the run of edges a -> b in the pair index (empty if none)
+__device__ __forceinline__ void pair_run(const PairSlot* __restrict__ tab, int log2cap, int32_t a,
                                          int32_t b, uint32_t* start, uint32_t* end) {
   const uint64_t key = pair_key((uint32_t)a, (uint32_t)b);
   *start = 0;
   *end = 0;
-  const uint64_t fb = pair_filter_bit(key, filter_log2);
-  if (!((filter[fb >> 6] >> (fb & 63)) & 1ull)) return;
   const uint64_t mask = (1ull << log2cap) - 1;
   uint64_t h = pair_hash(key, log2cap);
   for (uint64_t probe = 0; probe <= mask; ++probe) {

@@ -173,8 +173,7 @@ __global__ __launch_bounds__(256) void k_features(
     const int32_t* __restrict__ out_src, const int32_t* __restrict__ out_dst,
     const int64_t* __restrict__ out_t, const int64_t* __restrict__ in_t,
     const int64_t* __restrict__ pair_t, const PairSlot* __restrict__ pair_hash,
-    int32_t pair_hash_log2, const uint64_t* __restrict__ pair_filter, int32_t pair_filter_log2,
-    const uint32_t* __restrict__ lo_in, const uint32_t* __restrict__ a,
+    int32_t pair_hash_log2, const uint32_t* __restrict__ lo_in, const uint32_t* __restrict__ a,
     const uint32_t* __restrict__ lo_out, const uint32_t* __restrict__ b,
     const uint64_t* __restrict__ ps_in, const uint64_t* __restrict__ ps_out, int64_t delta,
     int64_t m, uint4* __restrict__ feat) {
@@ -190,10 +189,10 @@ __global__ __launch_bounds__(256) void k_features(
   f[3] = (ap > 0 && delta > 0) ? (float)(t - in_t[lo_in[p]]) / (float)delta : 0.0f;
   f[4] = (bp > 0 && delta > 0) ? (float)(out_t[lo_out[p] + bp - 1] - t) / (float)delta : 0.0f;
   uint32_t r0, r1;
-  pair_run(pair_filter, pair_filter_log2, pair_hash, pair_hash_log2, u, v, &r0, &r1);
+  pair_run(pair_hash, pair_hash_log2, u, v, &r0, &r1);
   f[5] = log1pf((float)(upper_bound<int64_t>(pair_t, r0, r1, t + delta) -
                         lower_bound<int64_t>(pair_t, r0, r1, t - delta)));
-  pair_run(pair_filter, pair_filter_log2, pair_hash, pair_hash_log2, v, u, &r0, &r1);
+  pair_run(pair_hash, pair_hash_log2, v, u, &r0, &r1);
   f[6] = log1pf((float)(upper_bound<int64_t>(pair_t, r0, r1, t + delta) -
                         lower_bound<int64_t>(pair_t, r0, r1, t - delta)));
   // mean squared degree of the window ends (exact wrapping window sums)
@@ -665,8 +664,7 @@ tc_status edge_features(const tc_graph* g, const tc_weights* w, uint16_t* feat, 
                        (const int32_t*)g->out_src, (const int32_t*)g->out_dst,
                        (const int64_t*)g->out_t, (const int64_t*)g->in_t,
                        (const int64_t*)g->pair_t, (const PairSlot*)g->pair_hash,
-                       g->pair_hash_log2, (const uint64_t*)g->pair_filter, g->pair_filter_log2,
-                       w->lo_in, w->a, w->lo_out, w->b,
+                       g->pair_hash_log2, w->lo_in, w->a, w->lo_out, w->b,
                        (const uint64_t*)ps_in, (const uint64_t*)ps_out, w->delta, m,
                        (uint4*)feat);
   }

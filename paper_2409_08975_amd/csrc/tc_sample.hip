@@ -78,8 +78,6 @@ struct SampleArgs {
   const int64_t* pair_t;
   const PairSlot* pair_hash;
   int32_t pair_hash_log2;
-  const uint64_t* pair_filter;
-  int32_t pair_filter_log2;
   const int64_t* pair_skip;
   int64_t m;
   uint64_t tree_off[kMaxTreeLevels];
@@ -130,7 +128,7 @@ __device__ __forceinline__ void pair_window(const SampleArgs& A, int32_t va, int
                                             int64_t t_lo, int64_t t_hi, uint32_t* lo,
                                             uint32_t* hi) {
   uint32_t r0, r1;
-  pair_run(A.pair_filter, A.pair_filter_log2, A.pair_hash, A.pair_hash_log2, va, vb, &r0, &r1);
+  pair_run(A.pair_hash, A.pair_hash_log2, va, vb, &r0, &r1);
   const uint32_t l = run_upper_bound(A.pair_t, A.pair_skip, A.m, r0, r1, t_lo);
   const uint32_t h = run_upper_bound(A.pair_t, A.pair_skip, A.m, l, r1, t_hi);
   *lo = l;
@@ -1146,8 +1144,6 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
   A.pair_t = g->pair_t;
   A.pair_hash = (const PairSlot*)g->pair_hash;
   A.pair_hash_log2 = g->pair_hash_log2;
-  A.pair_filter = g->pair_filter;
-  A.pair_filter_log2 = g->pair_filter_log2;
   A.pair_skip = g->pair_skip;
   A.m = g->m;
   {

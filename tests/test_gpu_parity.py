@@ -141,22 +141,10 @@ def test_tiny_graph_orders(tiny):
     check_graph(G, og, g)
 
 
-def test_pair_lookup_structures(tcb, tiny, torch_mod):
-    """The membership filter in front of the pair-run table: the bit of every
-    (src, dst) pair that has an edge is set (a clear bit must prove absence),
-    and no other bits are set, so absent pairs are mostly rejected.  The
-    sampled levels of the pair times are pair_t[16^k i]."""
+def test_pair_skip_levels(tcb, tiny, torch_mod):
+    """The sampled levels of the pair times used by the searches inside a
+    run are pair_t[16^k i] for k = 1, 2, 3."""
     g, G, og = tiny
-    lg = G.c.pair_filter_log2
-    assert 12 <= lg <= 28
-    words = G.view("pair_filter", torch_mod.int64, (1 << lg) // 64).cpu().numpy().view(np.uint64)
-    keys = (g.src.astype(np.uint64) << np.uint64(32)) | g.dst.astype(np.uint32).astype(np.uint64)
-    # top lg bits of the 64-bit product with the golden-ratio multiplier
-    bit = (keys * np.uint64(0x9E3779B97F4A7C15)) >> np.uint64(64 - lg)
-    assert np.all((words[bit >> np.uint64(6)] >> (bit & np.uint64(63))) & np.uint64(1))
-    expect = np.zeros_like(words)
-    np.bitwise_or.at(expect, bit >> np.uint64(6), np.uint64(1) << (bit & np.uint64(63)))
-    assert np.array_equal(words, expect)
     # sampled levels of the pair times used by the searches inside a run
     pt = G.arrays()["pair_t"].cpu().numpy()
     n = [-(-g.m // 16 ** k) for k in (1, 2, 3)]
