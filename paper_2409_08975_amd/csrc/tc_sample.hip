@@ -99,7 +99,6 @@ struct SampleArgs {
   uint32_t* win_len;  // [nd][kMaxPairs][chunk]
   uint32_t* item_code;  // local sample | motif << 22 | delta << 26
   uint32_t* item_count;
-  uint32_t* item_next;
   uint32_t* mid_code;
   uint32_t* mid_count;
   uint32_t* wide_code;
@@ -289,6 +288,8 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
   __shared__ uint32_t s_off[kSBlock + 1];  // exclusive prefix of their counts
   __shared__ uint32_t s_wsum[kSWaves];
   __shared__ uint32_t s_glen[kMaxPairs][kSBlock];  // gate window length per accepted path
+  __shared__ uint32_t s_qcnt[kSWaves];
+  __shared__ uint32_t s_qbase;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int nm = A.plan.n_motifs;
@@ -446,6 +447,8 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
       __threadfence_block();
       __syncthreads();
     }
+    uint32_t dmask = 0;
+    uint32_t wdefer = 0;
     for (int j = 0; j < nm; ++j) {
       const int l = A.plan.n_lists[j];
       uint64_t X = 0;
@@ -475,17 +478,8 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
           if (!empty || big) defer = true;
         }
       }
-      // one queue reservation per wavefront
-      const uint64_t mask = __ballot(defer);
-      if (mask) {
-        const int leader = __ffsll((long long)mask) - 1;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(A.item_count, (uint32_t)__popcll(mask));
-        base = __shfl(base, leader, kWave);
-        if (defer)
-          A.item_code[base + (uint32_t)__popcll(mask & lt_mask)] =
-              li | ((uint32_t)j << kLiBits) | ((uint32_t)d << (kLiBits + 4));
-      }
+      if (defer) dmask |= 1u << j;
+      wdefer += (uint32_t)__popcll(__ballot(defer));
       if (active && W != 0 && !defer && D.X) D.X[(uint64_t)j * A.k + ii] = X;
       const uint64_t Xc = defer ? 0ull : X;
       // most wavefronts close no path of a motif: their sums are all zero
@@ -498,6 +492,29 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
           sums_add(sums_slot(A, wave, d, j), sx, (uint64_t)__popcll(nz), sq, ovf);
       }
     }
+    // queue the deferred (sample, motif) items of the unit with one
+    // reservation for the whole block
+    if (lane == 0) s_qcnt[wave] = wdefer;
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t tot = 0;
+      for (int w = 0; w < kSWaves; ++w) tot += s_qcnt[w];
+      s_qbase = tot ? atomicAdd(A.item_count, tot) : 0u;
+    }
+    __syncthreads();
+    if (uni(wdefer) != 0) {
+      uint32_t wbase = s_qbase;
+      for (int w = 0; w < wave; ++w) wbase += s_qcnt[w];
+      for (int j = 0; j < nm; ++j) {
+        const bool dj = (dmask >> j) & 1u;
+        const uint64_t mask = __ballot(dj);
+        if (dj)
+          A.item_code[wbase + (uint32_t)__popcll(mask & lt_mask)] =
+              li | ((uint32_t)j << kLiBits) | ((uint32_t)d << (kLiBits + 4));
+        wbase += (uint32_t)__popcll(mask);
+      }
+    }
+    __syncthreads();  // s_qcnt and s_qbase are reused by the next unit
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) st_bits |= __shfl_xor(st_bits, off, kWave);
     if (lane == 0) flag_status(A, d, st_bits);
@@ -703,14 +720,9 @@ __global__ __launch_bounds__(kWave) void k_listcount_lds(SampleArgs A, uint64_t*
   const int lane = threadIdx.x;
   sums_clear<1>(A);
   const uint32_t n_items = *A.mid_count;
-  // Lane 0 claims items; each iteration ends in the one lane-0 block that
-  // retires the current item and claims the next, so no test of the lane
-  // index lies between that block and the broadcast at the loop head.
-  uint32_t next = 0;
-  if (lane == 0) next = atomicAdd(A.item_next, 1u);
-  while (true) {
-    const uint32_t it = uni(__shfl(next, 0, kWave));
-    if (it >= n_items) break;
+  // items are dealt round robin (the loop index is uniform over the
+  // wavefront; no shared counter is contended)
+  for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const uint32_t code = A.mid_code[it];
     uint32_t li;
     int j, d;
@@ -780,7 +792,6 @@ __global__ __launch_bounds__(kWave) void k_listcount_lds(SampleArgs A, uint64_t*
         A.wide_code[atomicAdd(A.wide_count, 1u)] = code;
       else
         item_done(A, d, j, li, total.lo);
-      next = atomicAdd(A.item_next, 1u);
     }
   }
   __syncthreads();
@@ -1037,7 +1048,7 @@ __global__ void k_store_ptrs(EstPtrs ep, double** dst) {
 }
 
 __global__ void k_zero_counters(uint32_t* p) {
-  // item_count, item_next, wide_count, wide_next, big_count, mid_count
+  // item_count, (spare), wide_count, wide_next, big_count, mid_count
   if (threadIdx.x < 6) p[threadIdx.x] = 0;
 }
 
@@ -1064,7 +1075,7 @@ SampleTuning default_tuning() {
   SampleTuning t;
   t.chunk_log2 = kLiBits;
   t.path_blocks = 0;
-  t.reg_waves = 5120;
+  t.reg_waves = 10240;
   t.fast_waves = 5120;
   t.wide_blocks = kDefaultWideBlocks;
   return t;
@@ -1187,7 +1198,6 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
   A.wide_code = (uint32_t*)(base + L.wide);
   A.big_code = (uint32_t*)(base + L.big);
   A.item_count = (uint32_t*)(base + L.counters);
-  A.item_next = A.item_count + 1;
   A.wide_count = A.item_count + 2;
   A.wide_next = A.item_count + 3;
   A.big_count = A.item_count + 4;
