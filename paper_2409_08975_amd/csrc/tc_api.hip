@@ -171,7 +171,7 @@ tc_status tc_autotune(const tc_graph* g, const tc_weights* const* w, int32_t n_d
   tc_status s = run(cur, &cur_ms);
   const int32_t chunks[] = {20, 21, 22};
   const int32_t pblocks[] = {0, 1024, 4096};
-  const int32_t rwaves[] = {2560, 5120, 10240};
+  const int32_t rwaves[] = {5120, 10240, 20480};
   const int32_t fwaves[] = {2560, 5120, 8192};
   const int32_t wblocks[] = {512, 1024, 2048};
   for (int dim = 0; dim < 5 && s == TC_OK; ++dim) {
