@@ -154,6 +154,63 @@ __device__ __forceinline__ T wave_inclusive_scan(T v) {
   return v;
 }
 
+// ---- wavefront collectives without LDS traffic -------------------------------
+// For code where all 64 lanes are active.  A lane's value moves to another
+// lane through DPP (data-parallel primitives: an operand modifier of the
+// vector ALU) instead of ds_bpermute, which goes through the LDS crossbar.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  // bound_ctrl: a lane whose source is outside its row reads 0; lanes of
+  // rows outside ROW_MASK keep the old value 0
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, true);
+}
+
+// Inclusive prefix sum over the wavefront in lane order: shifts by 1, 2, 4
+// and 8 lanes inside each row of 16, then lane 15 of rows 0 and 2 added into
+// rows 1 and 3, then lane 31 into rows 2 and 3.
+__device__ __forceinline__ uint32_t scan_dpp(uint32_t v) {
+  v += dpp_u32<0x111, 0xF>(v);
+  v += dpp_u32<0x112, 0xF>(v);
+  v += dpp_u32<0x114, 0xF>(v);
+  v += dpp_u32<0x118, 0xF>(v);
+  v += dpp_u32<0x142, 0xA>(v);
+  v += dpp_u32<0x143, 0xC>(v);
+  return v;
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+  const uint32_t lo = dpp_u32<CTRL, ROW_MASK>((uint32_t)v);
+  const uint32_t hi = dpp_u32<CTRL, ROW_MASK>((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t scan_dpp(uint64_t v) {
+  v += dpp_u64<0x111, 0xF>(v);
+  v += dpp_u64<0x112, 0xF>(v);
+  v += dpp_u64<0x114, 0xF>(v);
+  v += dpp_u64<0x118, 0xF>(v);
+  v += dpp_u64<0x142, 0xA>(v);
+  v += dpp_u64<0x143, 0xC>(v);
+  return v;
+}
+
+// The value of a lane given by a wave-uniform index, as a scalar.
+__device__ __forceinline__ uint32_t lane_u32(uint32_t v, int lane) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int lane) {
+  return ((uint64_t)lane_u32((uint32_t)(v >> 32), lane) << 32) | lane_u32((uint32_t)v, lane);
+}
+
+// Sum of the 64 lanes' u64 values as 128 bits (exact), uniform.
+__device__ __forceinline__ U128 wave_sum128_dpp(uint64_t c) {
+  const uint64_t lo = lane_u64(scan_dpp((uint64_t)(uint32_t)c), 63);
+  const uint64_t hi = lane_u64(scan_dpp(c >> 32), 63);
+  const uint64_t r = lo + (hi << 32);
+  return U128{r, (hi >> 32) + (r < lo ? 1ull : 0ull)};
+}
+
 // Correctly rounded (round-to-nearest-even) conversion of a 128-bit unsigned
 // integer to binary64.  The top 64 significant bits are converted with the
 // lowest bit forced to 1 when any lower bit is set (a sticky bit below the

@@ -613,29 +613,27 @@ __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A) {
       my_len = A.win_len[wi];
       if (my_len) my_first = A.pair_t[my_lo];
     }
-    uint32_t maxlen = my_len;
-    int64_t base = my_first;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const uint32_t o = __shfl_xor(maxlen, off, kWave);
-      maxlen = o > maxlen ? o : maxlen;
-      const int64_t b = __shfl_xor(base, off, kWave);
-      base = b < base ? b : base;
+    // longest list and smallest head time, read lane by lane as scalars
+    uint32_t maxlen = 0;
+    int64_t base = INT64_MAX;
+    for (int r = 0; r < l; ++r) {
+      const uint32_t len_r = lane_u32(my_len, r);
+      const int64_t first_r = (int64_t)lane_u64((uint64_t)my_first, r);
+      maxlen = len_r > maxlen ? len_r : maxlen;
+      base = first_r < base ? first_r : base;
     }
-    maxlen = uni(maxlen);
-    base = uni64s(base);
     // list r's keys start at my_off of lane r (exclusive prefix of the lengths)
-    const uint32_t incl = wave_inclusive_scan(my_len);
+    const uint32_t incl = scan_dpp(my_len);
     const uint32_t my_off = incl - my_len;
-    const uint32_t total_keys = uni(__shfl(incl, kWave - 1, kWave));
+    const uint32_t total_keys = lane_u32(incl, kWave - 1);
     if (maxlen > (uint32_t)(kWave * CH) || total_keys > (uint32_t)kRegKeys ||
         A.D[d].delta >= ((int64_t)1 << 32)) {
       if (lane == 0) A.mid_code[atomicAdd(A.mid_count, 1u)] = code;
       continue;
     }
     for (int r = 0; r < l; ++r) {
-      const uint32_t lo = uni(__shfl(my_lo, r, kWave)), len = uni(__shfl(my_len, r, kWave));
-      const uint32_t off = uni(__shfl(my_off, r, kWave));
+      const uint32_t lo = lane_u32(my_lo, r), len = lane_u32(my_len, r);
+      const uint32_t off = lane_u32(my_off, r);
 #pragma unroll
       for (int h = 0; h < CH; ++h) {
         const uint32_t i = h * kWave + lane;
@@ -649,13 +647,13 @@ __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A) {
     // Level totals: T_0 = |L_0| and T_r <= |L_r| T_{r-1}.  While that bound
     // stays below 2^64 the running 64-bit carry is the exact total; only
     // otherwise are the 128-bit level sums formed (to detect overflow).
-    uint64_t t_prev = uni(__shfl(my_len, 0, kWave));
+    uint64_t t_prev = lane_u32(my_len, 0);
     bool sat = false;  // a level total reached 2^64 (results undefined)
     for (int r = 1; r < l; ++r) {
-      const uint32_t prev_len = uni(__shfl(my_len, r - 1, kWave));
-      const uint32_t len = uni(__shfl(my_len, r, kWave));
-      const uint32_t* kprev = s_key + uni(__shfl(my_off, r - 1, kWave));
-      const uint32_t* kcur = s_key + uni(__shfl(my_off, r, kWave));
+      const uint32_t prev_len = lane_u32(my_len, r - 1);
+      const uint32_t len = lane_u32(my_len, r);
+      const uint32_t* kprev = s_key + lane_u32(my_off, r - 1);
+      const uint32_t* kcur = s_key + lane_u32(my_off, r);
       const uint32_t nch = (len + kWave - 1) / kWave;       // chunks of this level
       const uint32_t pch = (prev_len + kWave - 1) / kWave;  // chunks of the previous one
       uint64_t bound;
@@ -684,10 +682,10 @@ __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A) {
             }
           }
           if (!act || pos == 0) c = 0;
-          const uint64_t inc = wave_inclusive_scan(c);
+          const uint64_t inc = scan_dpp(c);
           Pn[h] = carry + inc;
-          if (!exact64) total = add128(total, wave_sum128(U128{c, 0}));
-          carry += uni64(__shfl(inc, kWave - 1, kWave));
+          if (!exact64) total = add128(total, wave_sum128_dpp(c));
+          carry += lane_u64(inc, kWave - 1);
         }
       }
       if (exact64) {
@@ -736,29 +734,27 @@ __global__ __launch_bounds__(kWave) void k_listcount_lds(SampleArgs A, uint64_t*
       my_len = A.win_len[wi];
       if (my_len) my_first = A.pair_t[my_lo];
     }
-    uint32_t maxlen = my_len;
-    int64_t base = my_first;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const uint32_t o = __shfl_xor(maxlen, off, kWave);
-      maxlen = o > maxlen ? o : maxlen;
-      const int64_t b = __shfl_xor(base, off, kWave);
-      base = b < base ? b : base;
+    // longest list and smallest head time, read lane by lane as scalars
+    uint32_t maxlen = 0;
+    int64_t base = INT64_MAX;
+    for (int r = 0; r < l; ++r) {
+      const uint32_t len_r = lane_u32(my_len, r);
+      const int64_t first_r = (int64_t)lane_u64((uint64_t)my_first, r);
+      maxlen = len_r > maxlen ? len_r : maxlen;
+      base = first_r < base ? first_r : base;
     }
-    maxlen = uni(maxlen);
-    base = uni64s(base);
     const bool fwd = maxlen > (uint32_t)kKeyCap || A.D[d].delta >= ((int64_t)1 << 32);
     U128 total{0, 0};
     if (!fwd) {
-      const uint32_t lo0 = uni(__shfl(my_lo, 0, kWave)), len0 = uni(__shfl(my_len, 0, kWave));
+      const uint32_t lo0 = lane_u32(my_lo, 0), len0 = lane_u32(my_len, 0);
       for (uint32_t i = lane; i < len0; i += kWave)
         s_key[0][i] = (uint32_t)(A.pair_t[lo0 + i] - base);
       __threadfence_block();
       int pb = 0;
       for (int r = 1; r < l; ++r) {
-        const uint32_t prev_len = uni(__shfl(my_len, r - 1, kWave));
-        const uint32_t lo = uni(__shfl(my_lo, r, kWave));
-        const uint32_t len = uni(__shfl(my_len, r, kWave));
+        const uint32_t prev_len = lane_u32(my_len, r - 1);
+        const uint32_t lo = lane_u32(my_lo, r);
+        const uint32_t len = lane_u32(my_len, r);
         const uint32_t* kprev = s_key[(r - 1) & 1];
         uint32_t* kcur = s_key[r & 1];
         const uint64_t* Pprev = s_p[pb ^ 1];
@@ -776,10 +772,10 @@ __global__ __launch_bounds__(kWave) void k_listcount_lds(SampleArgs A, uint64_t*
             const uint32_t pos = lower_bound<uint32_t>(kprev, 0u, prev_len, key);
             c = (r == 1) ? (uint64_t)pos : Pprev[pos];
           }
-          const uint64_t inc = wave_inclusive_scan(c);
+          const uint64_t inc = scan_dpp(c);
           if (act) Pcur[i + 1] = carry + inc;
-          total = add128(total, wave_sum128(U128{c, 0}));
-          carry += uni64(__shfl(inc, kWave - 1, kWave));
+          total = add128(total, wave_sum128_dpp(c));
+          carry += lane_u64(inc, kWave - 1);
         }
         total = U128{uni64(total.lo), uni64(total.hi)};
         if (total.hi != 0 && lane == 0) flag_status(A, d, TC_F_OVERFLOW | TC_F_MOTIF(j));
@@ -895,11 +891,11 @@ __global__ __launch_bounds__(kWBlock) void k_listcount_wide(SampleArgs A, uint64
             run[e] = (e ? run[e - 1] : 0ull) + c[e];
             tsum = add128(tsum, U128{c[e], 0});
           }
-          const uint64_t incl = wave_inclusive_scan(run[kWPer - 1]);
-          const U128 wsum = wave_sum128(tsum);
-          uint32_t wset = nset;
-#pragma unroll
-          for (int off = 32; off > 0; off >>= 1) wset += __shfl_xor(wset, off, kWave);
+          const uint64_t incl = scan_dpp(run[kWPer - 1]);
+          // tsum.hi <= 3 (four values below 2^64 each)
+          U128 wsum = wave_sum128_dpp(tsum.lo);
+          wsum.hi += lane_u32(scan_dpp((uint32_t)tsum.hi), kWave - 1);
+          const uint32_t wset = lane_u32(scan_dpp(nset), kWave - 1);
           if (lane == kWave - 1) {
             s_wsum[wave] = incl;
             s_wlo[wave] = wsum.lo;
