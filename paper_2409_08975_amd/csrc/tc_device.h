@@ -269,28 +269,13 @@ __host__ __device__ __forceinline__ int64_t skip_level_len(int64_t m, int k) {
   return (m + ((int64_t)1 << (4 * k)) - 1) >> (4 * k);
 }
 
-// Number of the n (<= 16) consecutive values a[0..n) that are <= t (the
-// values are sorted, so these form a prefix).  All sixteen loads are issued
-// before any is used (indices past n reload a[0]), so the count costs one
-// memory round trip.
-__device__ __forceinline__ uint32_t count_le16(const int64_t* __restrict__ a, uint32_t n,
-                                               int64_t t) {
-  int64_t v[16];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) v[j] = a[(uint32_t)j < n ? (uint32_t)j : 0u];
-  uint32_t c = 0;
-#pragma unroll
-  for (int j = 0; j < 16; ++j) c += ((uint32_t)j < n && v[j] <= t) ? 1u : 0u;
-  return c;
-}
-
 // First position in [lo, hi) whose time exceeds t (hi if none), where
 // [lo, hi) lies inside one run of the pair index (times sorted).  Equal to
-// upper_bound over pair_t.  From the coarsest level down, the samples of
-// level k inside the range (at most 16 once a coarser level has cut it)
-// cut the range to the gap between two neighbouring samples; the last step
-// counts at most 16 consecutive times.  A run of L entries takes about
-// log16(L) dependent round trips instead of log2(L).
+// upper_bound over pair_t.  From the coarsest level down, a bisection over
+// the samples of level k inside the range cuts it to the gap between two
+// neighbouring samples; the last step bisects at most 16 consecutive times
+// (one or two cache lines).  The probes of a long run thus fall mostly on
+// the small sampled levels, which stay in cache, instead of on pair_t.
 __device__ __forceinline__ uint32_t run_upper_bound(const int64_t* __restrict__ pair_t,
                                                    const int64_t* __restrict__ skip, int64_t m,
                                                    uint32_t lo, uint32_t hi, int64_t t) {
@@ -303,12 +288,11 @@ __device__ __forceinline__ uint32_t run_upper_bound(const int64_t* __restrict__ 
     if (i1 < i0) continue;
     const int64_t* C = skip + (k == 1 ? 0 : (k == 2 ? n1 : n1 + n2));
     const uint32_t cnt = i1 - i0 + 1;
-    const uint32_t n_le =  // samples with time <= t (a prefix of them)
-        cnt <= 16u ? count_le16(C + i0, cnt, t) : upper_bound<int64_t>(C, i0, i1 + 1, t) - i0;
+    const uint32_t n_le = upper_bound<int64_t>(C, i0, i1 + 1, t) - i0;  // samples with time <= t
     if (n_le > 0) lo = ((i0 + n_le - 1) << sh) + 1;
     if (n_le < cnt) hi = (i0 + n_le) << sh;
   }
-  return lo + count_le16(pair_t + lo, hi - lo, t);
+  return upper_bound<int64_t>(pair_t, lo, hi, t);  // at most 16 times, one or two lines
 }
 
 // [start, end) of the run of edges a -> b in the pair index (empty if none)
