@@ -138,20 +138,16 @@ __device__ __forceinline__ int32_t slot_vertex(int s, int32_t x, int32_t u, int3
   return s == 0 ? x : (s == 1 ? u : (s == 2 ? v : y));
 }
 
-// upper_bound(S, r) - 1 through the 16-ary tree: one 128-byte node per level
+// upper_bound(S, r) - 1 through the 16-ary tree: one 128-byte node per
+// level, bisected (four 8-byte probes inside one cache line rather than the
+// whole node, which keeps the vector-memory traffic of a lane per level low)
 __device__ __forceinline__ uint32_t tree_search(const SampleArgs& A, const DeltaArgs& D,
                                                 uint64_t r) {
   uint64_t i = 0;
   for (int L = A.tree_levels; L >= 0; --L) {
     const uint64_t* lvl = (L == 0) ? D.S : D.tree + A.tree_off[L];
     const uint64_t node = (L == A.tree_levels) ? 0 : i;
-    const ulonglong2* nd = reinterpret_cast<const ulonglong2*>(lvl + 16 * node);
-    uint32_t cnt = 0;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const ulonglong2 v = nd[q];
-      cnt += (v.x <= r) + (v.y <= r);
-    }
+    const uint32_t cnt = upper_bound<uint64_t>(lvl + 16 * node, 0u, 16u, r);  // entries <= r
     i = 16 * node + cnt - 1;
   }
   return (uint32_t)i;
