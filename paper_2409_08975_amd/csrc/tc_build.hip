@@ -14,6 +14,8 @@
 // stores.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "tc_device.h"
 #include "tc_internal.h"
 
@@ -550,7 +552,7 @@ struct GraphLayout {
   size_t out_off, in_off, out_src, out_dst, out_eid, out_t, in_src, in_eid, in_dst, in_t,
       out_to_in, pair_dst, out_rec, in_rec,
       pair_eid, pair_t, pair_hash, pair_skip, status, tminmax, keys0, keys1, vals0, vals1, hist, part,
-      part_elems, rk[3], rv[3], total;
+      part_elems, rk[4], rv[4], hist2, part2, total;
 };
 
 static GraphLayout graph_layout(int32_t n, int64_t m) {
@@ -585,12 +587,13 @@ static GraphLayout graph_layout(int32_t n, int64_t m) {
       take((size_t)(skip_level_len(m, 1) + skip_level_len(m, 2) + skip_level_len(m, 3)) * 8);
   L.status = take(4);
   L.tminmax = take(16);
-  // sort scratch: three (u32 key, 12-byte payload) buffers for the
-  // record-carrying sorts, aliased by the 64-bit-key buffers of the wide-time
-  // path (the two paths never run in the same build)
+  // sort scratch: four (u32 key, 12-byte payload) buffers for the
+  // record-carrying sorts (two per concurrent branch), aliased by the
+  // 64-bit-key buffers of the wide-time path (the two paths never run in the
+  // same build)
   const size_t region = o;
-  for (int b = 0; b < 3; ++b) L.rk[b] = take((M + 1) * 4);
-  for (int b = 0; b < 3; ++b) L.rv[b] = take((M + 1) * 12);
+  for (int b = 0; b < 4; ++b) L.rk[b] = take((M + 1) * 4);
+  for (int b = 0; b < 4; ++b) L.rv[b] = take((M + 1) * 12);
   const size_t rec_end = o;
   o = region;
   L.keys0 = take((M + 1) * 8);
@@ -603,8 +606,40 @@ static GraphLayout graph_layout(int32_t n, int64_t m) {
   L.part_elems = scan_u32_scratch_elems(256 * ntiles + 1);
   if (scan_u32_scratch_elems(m + 1) > L.part_elems) L.part_elems = scan_u32_scratch_elems(m + 1);
   L.part = take(L.part_elems * 4);
+  // histogram and scan scratch of the side stream
+  L.hist2 = take((size_t)256 * ntiles * 4);
+  L.part2 = take(L.part_elems * 4);
   L.total = o;
   return L;
+}
+
+// Second stream of a device for the build's independent branch, created once
+// (default priority); the mutex also keeps two builds from interleaving their
+// use of it and of its events.
+struct SideStream {
+  std::mutex mu;
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, out_done = nullptr;
+  bool ok = false, tried = false;
+};
+static SideStream g_side[64];
+
+static SideStream* side_stream() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  SideStream* S = &g_side[dev];
+  return S;
+}
+
+// with S->mu held
+static bool side_ready(SideStream* S) {
+  if (!S->tried) {
+    S->tried = true;
+    S->ok = hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&S->fork, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&S->out_done, hipEventDisableTiming) == hipSuccess;
+  }
+  return S->ok;
 }
 
 size_t graph_workspace_bytes(int32_t n, int64_t m) { return graph_layout(n, m).total; }
@@ -704,58 +739,82 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     return TC_OK;
   }
   if (tbits <= 32) {
-    // record-carrying sorts
-    uint32_t* rk[3];
-    uint3* rv[3];
-    for (int b = 0; b < 3; ++b) {
+    // record-carrying sorts.  This stream sorts by time, then the in-CSR and
+    // the pair index, then builds the run table (random atomics, latency
+    // bound); the out-CSR sort and the out-to-in positions (bandwidth bound)
+    // run meanwhile on a second stream.  Buffers: T (time order), B and T
+    // (in-CSR, pair index), A and C (out-CSR).
+    uint32_t* rk[4];
+    uint3* rv[4];
+    for (int b = 0; b < 4; ++b) {
       rk[b] = (uint32_t*)(base + L.rk[b]);
       rv[b] = (uint3*)(base + L.rv[b]);
     }
-    auto sort_rec = [&](int from, int tmp, int bits) -> int {
+    uint32_t* hist2 = (uint32_t*)(base + L.hist2);
+    uint32_t* part2 = (uint32_t*)(base + L.part2);
+    auto sort_rec = [&](int from, int tmp, int bits, uint32_t* h, uint32_t* pt,
+                        hipStream_t s) -> int {
       const int w = radix_sort<uint32_t, uint3, kRecItems>(rk[from], rv[from], rk[tmp], rv[tmp],
-                                                            m, bits, hist, part, pe, st);
+                                                            m, bits, h, pt, pe, s);
       return w < 0 ? -1 : (w ? tmp : from);
     };
+    SideStream* S = side_stream();
+    std::unique_lock<std::mutex> lock;
+    if (S) lock = std::unique_lock<std::mutex>(S->mu);
+    const bool two = S && side_ready(S);
+    hipStream_t s2 = two ? S->s : st;
     hipLaunchKernelGGL(k_rec_init, dim3(eb), dim3(256), 0, st, src, dst, t, m, tmin, rk[0], rv[0]);
-    const int T = sort_rec(0, 1, tbits);  // time order
+    const int T = sort_rec(0, 1, tbits, hist, part, st);  // time order
     if (T < 0) return TC_E_WORKSPACE;
-    const int X = (T + 1) % 3, Y = (T + 2) % 3;
-    // out-CSR: stable by src
+    int others[3], no = 0;
+    for (int b = 0; b < 4; ++b)
+      if (b != T) others[no++] = b;
+    const int A = others[0], B = others[1], C = others[2];
     hipLaunchKernelGGL(k_rekey<0>, dim3(eb), dim3(256), 0, st, (const uint32_t*)rk[T],
-                       (const uint3*)rv[T], m, rk[X], rv[X]);
-    int R = sort_rec(X, Y, vbits);
-    if (R < 0) return TC_E_WORKSPACE;
-    hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint32_t*)rk[R],
-                       (const uint3*)rv[R], m, tmin, g->out_src, g->out_dst, g->out_t,
-                       g->out_eid, (uint4*)g->out_rec);
-    hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
-                       (const uint32_t*)rk[R], m, n, g->out_off);
-    // in-CSR: stable by dst
+                       (const uint3*)rv[T], m, rk[A], rv[A]);
     hipLaunchKernelGGL(k_rekey<1>, dim3(eb), dim3(256), 0, st, (const uint32_t*)rk[T],
-                       (const uint3*)rv[T], m, rk[X], rv[X]);
-    const int I = sort_rec(X, Y, vbits);
+                       (const uint3*)rv[T], m, rk[B], rv[B]);
+    // in-CSR: stable by dst
+    const int I = sort_rec(B, T, vbits, hist, part, st);
     if (I < 0) return TC_E_WORKSPACE;
+    const int Ifree = (I == B) ? T : B;
     hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint32_t*)rk[I],
                        (const uint3*)rv[I], m, tmin, g->in_dst, g->in_src, g->in_t, g->in_eid,
                        (uint4*)g->in_rec);
     hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
                        (const uint32_t*)rk[I], m, n, g->in_off);
-    // out_to_in[p] = in-CSR position of out_eid[p] (through the free key buffer of T)
-    hipLaunchKernelGGL(k_scatter_pos, dim3(eb), dim3(256), 0, st, (const int32_t*)g->in_eid, m,
-                       rk[T]);
-    hipLaunchKernelGGL(k_gather_pos, dim3(eb), dim3(256), 0, st, (const int32_t*)g->out_eid, m,
-                       (const uint32_t*)rk[T], g->out_to_in);
     // pair index: the in-order (dst, t, eid) stably by src
-    const int P0 = (I + 1) % 3, P1 = (I + 2) % 3;
     hipLaunchKernelGGL(k_rekey<2>, dim3(eb), dim3(256), 0, st, (const uint32_t*)rk[I],
-                       (const uint3*)rv[I], m, rk[P0], rv[P0]);
-    const int Pr = sort_rec(P0, P1, vbits);
+                       (const uint3*)rv[I], m, rk[Ifree], rv[Ifree]);
+    const int Pr = sort_rec(Ifree, I, vbits, hist, part, st);
     if (Pr < 0) return TC_E_WORKSPACE;
+    const int Pfree = (Pr == I) ? Ifree : I;
     hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint32_t*)rk[Pr],
                        (const uint3*)rv[Pr], m, tmin, (int32_t*)nullptr, g->pair_dst,
                        g->pair_t, g->pair_eid, (uint4*)nullptr);
-    const int F0 = (Pr + 1) % 3, F1 = (Pr + 2) % 3;  // two free key buffers
-    if (!build_pair_hash(rk[Pr], g, m, rk[F0], rk[F1], part, pe, tab, st)) return TC_E_WORKSPACE;
+    if (two) {
+      if (hipEventRecord(S->fork, st) != hipSuccess ||
+          hipStreamWaitEvent(s2, S->fork, 0) != hipSuccess)
+        return TC_E_HIP;
+    }
+    // second stream: out-CSR (stable by src), then out_to_in[p] = in-CSR
+    // position of out_eid[p] through the key buffer of the finished sort
+    const int R = sort_rec(A, C, vbits, hist2, part2, s2);
+    if (R < 0) return TC_E_WORKSPACE;
+    hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, s2, (const uint32_t*)rk[R],
+                       (const uint3*)rv[R], m, tmin, g->out_src, g->out_dst, g->out_t,
+                       g->out_eid, (uint4*)g->out_rec);
+    hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, s2,
+                       (const uint32_t*)rk[R], m, n, g->out_off);
+    hipLaunchKernelGGL(k_scatter_pos, dim3(eb), dim3(256), 0, s2, (const int32_t*)g->in_eid, m,
+                       rk[R]);
+    hipLaunchKernelGGL(k_gather_pos, dim3(eb), dim3(256), 0, s2, (const int32_t*)g->out_eid, m,
+                       (const uint32_t*)rk[R], g->out_to_in);
+    if (two && hipEventRecord(S->out_done, s2) != hipSuccess) return TC_E_HIP;
+    // this stream: the run table, with the pair sort's spare buffer as scratch
+    if (!build_pair_hash(rk[Pr], g, m, rk[Pfree], (uint32_t*)rv[Pfree], part, pe, tab, st))
+      return TC_E_WORKSPACE;
+    if (two && hipStreamWaitEvent(st, S->out_done, 0) != hipSuccess) return TC_E_HIP;
     if (hipGetLastError() != hipSuccess) return TC_E_HIP;
     return TC_OK;
   }
