@@ -277,19 +277,24 @@ struct PathRec {
   uint32_t li;
 };
 
-__global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
+// Seven wavefronts per SIMD (at most 72 VGPRs): the kernel waits on L2 and
+// HBM round trips, and this occupancy measured fastest (6: -4%, 8: -5%).
+__global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
   __shared__ PathRec s_path[kSBlock];
   __shared__ uint32_t s_nvalid;
   __shared__ uint32_t s_mask[kSBlock];     // pairs still needed by each accepted path
   __shared__ uint32_t s_off[kSBlock + 1];  // exclusive prefix of their counts
   __shared__ uint32_t s_wsum[kSWaves];
-  __shared__ uint32_t s_glen[kMaxPairs][kSBlock];  // gate window length per accepted path
   __shared__ uint32_t s_qcnt[kSWaves];
   __shared__ uint32_t s_qbase;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int nm = A.plan.n_motifs;
   const int np = A.plan.n_pairs;
+  // gate window length per (gate, accepted path), after the block sums in
+  // dynamic LDS (sized for the plan's gates only)
+  uint32_t* s_glen = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(s_dyn_sums) +
+                                                 sums_bytes(kSWaves, A.nd, nm));
   sums_clear<kSWaves>(A);
   const uint32_t n_units = A.tiles_per_delta * (uint32_t)A.nd;
   for (uint32_t unit = blockIdx.x; unit < n_units; unit += gridDim.x) {
@@ -397,7 +402,7 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
                   &lo, &hi);
       A.win_lo[win_index(A, d, q, P.li)] = lo;
       A.win_len[win_index(A, d, q, P.li)] = hi - lo;
-      s_glen[gi][sidx] = hi - lo;
+      s_glen[gi * kSBlock + sidx] = hi - lo;
     }
     __threadfence_block();
     __syncthreads();
@@ -407,7 +412,7 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
       if (tid < nvalid) {
         for (int j = 0; j < nm; ++j)
           if (A.plan.n_lists[j] >= 2 &&
-              s_glen[A.plan.gate_index[A.plan.list_pair[j][0]]][tid] != 0)
+              s_glen[A.plan.gate_index[A.plan.list_pair[j][0]] * kSBlock + tid] != 0)
             mask |= A.plan.rest_mask[j];
       }
       const uint32_t cnt = (uint32_t)__popc(mask);
@@ -453,7 +458,7 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
         if (l == 0) {
           X = 1;
         } else if (l == 1) {
-          X = s_glen[A.plan.gate_index[A.plan.list_pair[j][0]]][my_sidx];
+          X = s_glen[A.plan.gate_index[A.plan.list_pair[j][0]] * kSBlock + my_sidx];
         } else {
           // an empty list gives 0 unless the lists before it could already
           // hold 2^64 chains (then the count must run to flag it)
@@ -464,7 +469,7 @@ __global__ __launch_bounds__(kSBlock) void k_paths(SampleArgs A) {
             const uint32_t q = A.plan.list_pair[j][r];
             const uint32_t gi = A.plan.gate_index[q];
             const uint32_t len =
-                gi != 0xFFu ? s_glen[gi][my_sidx] : A.win_len[win_index(A, d, (int)q, li)];
+                gi != 0xFFu ? s_glen[gi * kSBlock + my_sidx] : A.win_len[win_index(A, d, (int)q, li)];
             if (len == 0) {
               empty = true;
               break;
@@ -1218,8 +1223,8 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, A.item_count);
     {
       TimedLaunch tl("k_paths", st);
-      hipLaunchKernelGGL(k_paths, dim3(pblocks), dim3(kSBlock), sums_bytes(kSWaves, nd, nm), st,
-                         A);
+      hipLaunchKernelGGL(k_paths, dim3(pblocks), dim3(kSBlock),
+                         sums_bytes(kSWaves, nd, nm) + (size_t)plan.n_gates * kSBlock * 4, st, A);
     }
     if (plan.max_lists >= 2) {
       {
