@@ -592,7 +592,9 @@ __device__ __forceinline__ void item_done(const SampleArgs& A, int d, int j, uin
 // level: an LDS binary search gives pos = #{L_{r-1} < key}, P_{r-1}[pos] comes
 // from the lane holding prefix entry pos - 1, and a wavefront scan with a
 // carry across chunks gives P_r.
-constexpr int kRegKeys = 2048;
+// 1,024 keys (4 KB of LDS per one-wavefront block) keep the pass at the 7
+// wavefronts per SIMD its registers allow; 2,048 keys capped it at 5.
+constexpr int kRegKeys = 1024;
 template <int CH>
 __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A) {
   __shared__ uint32_t s_key[kRegKeys];
