@@ -70,8 +70,10 @@ def algorithmic_bytes(kernel, m, units):
       k_windows        per edge: read src, dst, t (16 B), write lo_in, a,
                        lo_out, b (16 B)
       k_scan_apply     per edge: read a, b (8 B), write S (8 B)
-      k_radix_scatter  per element and pass: read and write a 4-byte key and a
-                       4-byte value (16 B)"""
+      k_radix_scatter  per element and pass: read and write a 4-byte key and its
+                       12-byte payload {eid, other vertex, t - t_min} (32 B; the
+                       record-carrying sorts of a graph whose times span less
+                       than 2^32)"""
     if kernel == "k_paths":
         per = 8 * math.ceil(math.log2(m + 1)) + 32 + 2 * 16
     elif kernel == "k_windows":
@@ -79,7 +81,7 @@ def algorithmic_bytes(kernel, m, units):
     elif kernel == "k_scan_apply":
         per = 16
     elif kernel == "k_radix_scatter":
-        per = 16
+        per = 32
     else:
         return None, None
     return per * units, per
