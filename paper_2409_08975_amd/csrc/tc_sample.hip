@@ -816,7 +816,9 @@ constexpr int kWTile = kWBlock * kWPer;  // entries of B per step, of A per tile
 constexpr int kDefaultWideBlocks = 1024;
 constexpr int kMaxWideBlocks = 2048;
 
-__global__ __launch_bounds__(kWBlock) void k_listcount_wide(SampleArgs A, uint64_t* pscratch) {
+// Seven wavefronts per SIMD (72 VGPRs): measured 7% faster than the
+// compiler's unbounded 105 VGPRs (4 per SIMD) on the batched workload.
+__global__ __launch_bounds__(kWBlock, 7) void k_listcount_wide(SampleArgs A, uint64_t* pscratch) {
   __shared__ int64_t sA[kWTile];
   __shared__ uint64_t sP[kWTile + 1];
   __shared__ uint64_t s_wsum[kWWaves];
