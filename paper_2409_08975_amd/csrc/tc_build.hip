@@ -22,6 +22,7 @@
 namespace tc {
 
 constexpr int kSortBlock = 256;
+constexpr uint32_t kXcds = 8;  // accelerator complex dies of an MI355X, each with its own L2
 constexpr int kSortItems = 16;
 constexpr int kRecItems = 8;  // record-carrying sorts: 2048-entry tiles (LDS holds 16 B/entry)
 constexpr int kRecTile = kSortBlock * kRecItems;
@@ -238,8 +239,16 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
   constexpr int kTile = kSortBlock * ITEMS;
   constexpr int kWaves = kSortBlock / kWave;
   constexpr int kSub = kWave * ITEMS;  // entries per wavefront
+  // XCD-aware tile order.  Workgroups are dealt to the XCDs round robin
+  // (block b to XCD b mod 8), and each XCD has its own L2.  Neighbouring
+  // tiles write neighbouring pieces of every digit run, so each XCD takes a
+  // contiguous range of tiles: partial cache lines then meet in one L2
+  // instead of being written back piecewise from several.
+  const uint32_t nb = gridDim.x, xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+  const uint32_t q = nb / kXcds, rem = nb % kXcds;
+  const uint32_t tile = xcd * q + (xcd < rem ? xcd : rem) + slot;
   if (dev_m) m = (int64_t)*dev_m < m ? (int64_t)*dev_m : m;
-  if ((int64_t)blockIdx.x * kTile >= m) return;
+  if ((int64_t)tile * kTile >= m) return;
   __shared__ uint32_t s_base[256];
   __shared__ uint32_t s_excl[256];
   __shared__ uint32_t s_wcnt[kWaves][256];  // per-wavefront running digit counts
@@ -248,11 +257,11 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
   __shared__ V s_val[kTile];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t start = (int64_t)blockIdx.x * kTile;
+  const int64_t start = (int64_t)tile * kTile;
   const int len = (int)((m - start) < kTile ? (m - start) : kTile);
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-  s_base[tid] = hist[(int64_t)tid * ntiles + blockIdx.x];
+  s_base[tid] = hist[(int64_t)tid * ntiles + tile];
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) s_wcnt[w][tid] = 0;
   __syncthreads();
