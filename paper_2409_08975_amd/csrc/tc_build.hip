@@ -7,7 +7,9 @@
 //
 // Radix sort design (gfx950, wave64): 8-bit digits, tiles of 4096 keys per
 // 256-thread block.  A pass is (1) per-tile digit histograms written
-// digit-major, (2) one exclusive scan of that [256][tiles] matrix, (3) a
+// tile-major (each tile's 256 counts are one contiguous kilobyte), (2) a
+// column scan of that [tiles][256] matrix that turns every count into the
+// tile's global offset for its digit, (3) a
 // scatter that ranks keys stably inside the tile with wavefront ballots
 // (8 ballots give the lanes sharing a digit), stages the tile in LDS in
 // digit order and writes each digit run to its global slot with coalesced
@@ -29,6 +31,7 @@ constexpr int kRecTile = kSortBlock * kRecItems;
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanBlock * kScanItems;
+constexpr int kColChunk = 32;  // tiles per chunk of the histogram column scan
 
 // ---------------------------------------------------------------- scans ----
 // Exclusive scan of u32 in three kernels: tile sums, one-block scan of the
@@ -207,7 +210,6 @@ __global__ __launch_bounds__(256) void k_vertex_keys(const int32_t* __restrict__
 template <typename K, int ITEMS>
 __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__ keys, int64_t m,
                                                            int shift, uint32_t* __restrict__ hist,
-                                                           int64_t ntiles,
                                                            const uint32_t* __restrict__ dev_m) {
   __shared__ uint32_t s_h[256];
   if (dev_m) m = (int64_t)*dev_m < m ? (int64_t)*dev_m : m;
@@ -220,7 +222,94 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__
     if (i < m) atomicAdd(&s_h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = s_h[threadIdx.x];
+  hist[(int64_t)blockIdx.x * 256 + threadIdx.x] = s_h[threadIdx.x];
+}
+
+// Column scan of the tile-major histogram: hist[t][d] becomes the position
+// of tile t's first key of digit d in the pass output, i.e. the keys of all
+// smaller digits plus the keys of digit d in tiles before t.  Three kernels:
+// per-chunk column sums, an exclusive scan of each digit's chunk sums (which
+// also leaves the digit totals in row `nchunks`), and an in-place walk of
+// every chunk that adds the digit base.  Every access reads or writes whole
+// 1 KB rows except the per-digit chunk scan, which touches nchunks*256 words.
+__global__ __launch_bounds__(256) void k_col_sum(const uint32_t* __restrict__ hist,
+                                                 int64_t ntiles, uint32_t* __restrict__ csum) {
+  const int64_t t0 = (int64_t)blockIdx.x * kColChunk;
+  const int d = threadIdx.x;
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kColChunk; ++j) {
+    // clamped index: every load is issued unconditionally
+    const int64_t t = t0 + j < ntiles ? t0 + j : ntiles - 1;
+    const uint32_t v = hist[t * 256 + d];
+    s += (t0 + j < ntiles) ? v : 0u;
+  }
+  csum[(int64_t)blockIdx.x * 256 + d] = s;
+}
+
+// one block per digit (blockIdx.x), chunks spread over the block's threads
+__global__ __launch_bounds__(256) void k_col_scan(uint32_t* __restrict__ csum, int64_t nchunks) {
+  __shared__ uint32_t s_w[256 / kWave];
+  const int d = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < nchunks; base += 256) {
+    const int64_t c = base + threadIdx.x;
+    const uint32_t v = c < nchunks ? csum[c * 256 + d] : 0u;
+    const uint32_t inc = wave_inclusive_scan(v);
+    if (lane == 63) s_w[wave] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 256 / kWave; ++w) {
+      off += w < wave ? s_w[w] : 0u;
+      tot += s_w[w];
+    }
+    if (c < nchunks) csum[c * 256 + d] = carry + off + inc - v;
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) csum[nchunks * 256 + d] = carry;
+}
+
+// one block per chunk; thread d walks the chunk's tiles for digit d
+__global__ __launch_bounds__(256) void k_col_apply(uint32_t* __restrict__ hist, int64_t ntiles,
+                                                   const uint32_t* __restrict__ csum,
+                                                   int64_t nchunks) {
+  __shared__ uint32_t s_w[256 / kWave];
+  const int d = threadIdx.x, lane = d & 63, wave = d >> 6;
+  // digit base: exclusive scan of the digit totals over d
+  const uint32_t tot = csum[nchunks * 256 + d];
+  const uint32_t inc = wave_inclusive_scan(tot);
+  if (lane == 63) s_w[wave] = inc;
+  __syncthreads();
+  uint32_t run = inc - tot;
+  for (int w = 0; w < wave; ++w) run += s_w[w];
+  run += csum[(int64_t)blockIdx.x * 256 + d];
+  const int64_t t0 = (int64_t)blockIdx.x * kColChunk;
+  uint32_t v[kColChunk];
+#pragma unroll
+  for (int j = 0; j < kColChunk; ++j) {
+    const int64_t t = t0 + j < ntiles ? t0 + j : ntiles - 1;
+    v[j] = hist[t * 256 + d];
+  }
+#pragma unroll
+  for (int j = 0; j < kColChunk; ++j) {
+    if (t0 + j < ntiles) hist[(t0 + j) * 256 + d] = run;
+    run += v[j];
+  }
+}
+
+size_t col_scan_scratch_elems(int64_t ntiles) {
+  return (size_t)256 * ((ntiles + kColChunk - 1) / kColChunk + 1);
+}
+
+void col_scan(uint32_t* hist, int64_t ntiles, uint32_t* csum, hipStream_t st) {
+  const int64_t nchunks = (ntiles + kColChunk - 1) / kColChunk;
+  hipLaunchKernelGGL(k_col_sum, dim3((unsigned)nchunks), dim3(256), 0, st,
+                     (const uint32_t*)hist, ntiles, csum);
+  hipLaunchKernelGGL(k_col_scan, dim3(256), dim3(256), 0, st, csum, nchunks);
+  hipLaunchKernelGGL(k_col_apply, dim3((unsigned)nchunks), dim3(256), 0, st, hist, ntiles,
+                     (const uint32_t*)csum, nchunks);
 }
 
 template <typename K, typename V, int ITEMS>
@@ -230,7 +319,6 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
                                                               V* __restrict__ vout, int64_t m,
                                                               int shift,
                                                               const uint32_t* __restrict__ hist,
-                                                              int64_t ntiles,
                                                               const uint32_t* __restrict__ dev_m) {
   // Each wavefront owns a contiguous quarter of the tile and ranks its keys
   // in order with ballots (no block barrier inside); one block-wide pass then
@@ -261,7 +349,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
   const int len = (int)((m - start) < kTile ? (m - start) : kTile);
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-  s_base[tid] = hist[(int64_t)tid * ntiles + tile];
+  s_base[tid] = hist[(int64_t)tile * 256 + tid];
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) s_wcnt[w][tid] = 0;
   __syncthreads();
@@ -341,7 +429,7 @@ int radix_sort(K* k0, V* v0, K* k1, V* v1, int64_t m, int bits, uint32_t* hist,
   if (m <= 0) return 0;
   constexpr int kTile = kSortBlock * ITEMS;
   const int64_t ntiles = (m + kTile - 1) / kTile;
-  if (part_elems < scan_u32_scratch_elems(256 * ntiles)) return -1;
+  if (part_elems < col_scan_scratch_elems(ntiles)) return -1;
   int cur = 0;
   for (int shift = 0; shift < bits; shift += 8) {
     K* ki = cur ? k1 : k0;
@@ -349,13 +437,13 @@ int radix_sort(K* k0, V* v0, K* k1, V* v1, int64_t m, int bits, uint32_t* hist,
     K* ko = cur ? k0 : k1;
     V* vo = cur ? v0 : v1;
     hipLaunchKernelGGL((k_radix_hist<K, ITEMS>), dim3((unsigned)ntiles), dim3(kSortBlock), 0, st,
-                       (const K*)ki, m, shift, hist, ntiles, dev_m);
-    scan_u32(hist, 256 * ntiles, part, part_elems, st);
+                       (const K*)ki, m, shift, hist, dev_m);
+    col_scan(hist, ntiles, part, st);
     {
       TimedLaunch tl("k_radix_scatter", st);
       hipLaunchKernelGGL((k_radix_scatter<K, V, ITEMS>), dim3((unsigned)ntiles), dim3(kSortBlock),
                          0, st, (const K*)ki, (const V*)vi, ko, vo, m, shift,
-                         (const uint32_t*)hist, ntiles, dev_m);
+                         (const uint32_t*)hist, dev_m);
     }
     cur ^= 1;
   }
@@ -611,8 +699,9 @@ static GraphLayout graph_layout(int32_t n, int64_t m) {
   L.vals1 = take((M + 1) * 4);
   if (o < rec_end) o = rec_end;
   L.hist = take((size_t)256 * ntiles * 4);
-  // scan scratch: the larger of the histogram scan and the (m + 1)-entry run scan
-  L.part_elems = scan_u32_scratch_elems(256 * ntiles + 1);
+  // scan scratch: the larger of the histogram column scan and the
+  // (m + 1)-entry run scan
+  L.part_elems = col_scan_scratch_elems(ntiles);
   if (scan_u32_scratch_elems(m + 1) > L.part_elems) L.part_elems = scan_u32_scratch_elems(m + 1);
   L.part = take(L.part_elems * 4);
   // histogram and scan scratch of the side stream
