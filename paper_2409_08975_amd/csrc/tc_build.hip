@@ -209,7 +209,8 @@ __global__ __launch_bounds__(256) void k_vertex_keys(const int32_t* __restrict__
 // capacity the grid was sized for.
 template <typename K, int ITEMS>
 __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__ keys, int64_t m,
-                                                           int shift, uint32_t* __restrict__ hist,
+                                                           int shift, uint32_t mask,
+                                                           uint32_t* __restrict__ hist,
                                                            const uint32_t* __restrict__ dev_m) {
   __shared__ uint32_t s_h[256];
   if (dev_m) m = (int64_t)*dev_m < m ? (int64_t)*dev_m : m;
@@ -219,7 +220,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
     int64_t i = start + (int64_t)r * kSortBlock + threadIdx.x;
-    if (i < m) atomicAdd(&s_h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+    if (i < m) atomicAdd(&s_h[(uint32_t)(keys[i] >> shift) & mask], 1u);
   }
   __syncthreads();
   hist[(int64_t)blockIdx.x * 256 + threadIdx.x] = s_h[threadIdx.x];
@@ -317,7 +318,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
                                                               const V* __restrict__ vin,
                                                               K* __restrict__ kout,
                                                               V* __restrict__ vout, int64_t m,
-                                                              int shift,
+                                                              int shift, int dbits,
                                                               const uint32_t* __restrict__ hist,
                                                               const uint32_t* __restrict__ dev_m) {
   // Each wavefront owns a contiguous quarter of the tile and ranks its keys
@@ -327,6 +328,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
   constexpr int kTile = kSortBlock * ITEMS;
   constexpr int kWaves = kSortBlock / kWave;
   constexpr int kSub = kWave * ITEMS;  // entries per wavefront
+  const uint32_t mask = (1u << dbits) - 1u;
   // XCD-aware tile order.  Workgroups are dealt to the XCDs round robin
   // (block b to XCD b mod 8), and each XCD has its own L2.  Neighbouring
   // tiles write neighbouring pieces of every digit run, so each XCD takes a
@@ -363,11 +365,12 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
     const bool valid = idx < len;
     key[r] = valid ? kin[start + idx] : (K)0;
     if (valid) val[r] = vin[start + idx];
-    const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+    const uint32_t d = (uint32_t)(key[r] >> shift) & mask;
     uint64_t vb = __ballot(valid);
     uint64_t peers = valid ? vb : ~vb;
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
+      if (b >= dbits) break;  // uniform: the digit has dbits bits
       const bool bit = (d >> b) & 1u;
       const uint64_t bb = __ballot(bit);
       peers &= bit ? bb : ~bb;
@@ -402,7 +405,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
   for (int r = 0; r < ITEMS; ++r) {
     const int idx = wave * kSub + r * kWave + lane;
     if (idx < len) {
-      const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+      const uint32_t d = (uint32_t)(key[r] >> shift) & mask;
       const uint32_t pos = s_excl[d] + s_wcnt[wave][d] + rank[r];
       s_key[pos] = key[r];
       s_val[pos] = val[r];
@@ -411,7 +414,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
   __syncthreads();
   for (int i = tid; i < len; i += kSortBlock) {
     const K k = s_key[i];
-    const uint32_t d = (uint32_t)(k >> shift) & 255u;
+    const uint32_t d = (uint32_t)(k >> shift) & mask;
     const int64_t gpos = (int64_t)s_base[d] + (i - (int64_t)s_excl[d]);
     kout[gpos] = k;
     vout[gpos] = s_val[i];
@@ -431,21 +434,28 @@ int radix_sort(K* k0, V* v0, K* k1, V* v1, int64_t m, int bits, uint32_t* hist,
   const int64_t ntiles = (m + kTile - 1) / kTile;
   if (part_elems < col_scan_scratch_elems(ntiles)) return -1;
   int cur = 0;
-  for (int shift = 0; shift < bits; shift += 8) {
+  // ceil(bits / 8) passes with digit widths as equal as possible (narrow
+  // ones first): fewer distinct digits per tile means longer runs in the
+  // scatter's output, and fewer partly written cache lines
+  const int npass = (bits + 7) / 8;
+  for (int p = 0, shift = 0; p < npass; ++p) {
+    const int dbits = (bits - shift) / (npass - p);
+    const uint32_t mask = (1u << dbits) - 1u;
     K* ki = cur ? k1 : k0;
     V* vi = cur ? v1 : v0;
     K* ko = cur ? k0 : k1;
     V* vo = cur ? v0 : v1;
     hipLaunchKernelGGL((k_radix_hist<K, ITEMS>), dim3((unsigned)ntiles), dim3(kSortBlock), 0, st,
-                       (const K*)ki, m, shift, hist, dev_m);
+                       (const K*)ki, m, shift, mask, hist, dev_m);
     col_scan(hist, ntiles, part, st);
     {
       TimedLaunch tl("k_radix_scatter", st);
       hipLaunchKernelGGL((k_radix_scatter<K, V, ITEMS>), dim3((unsigned)ntiles), dim3(kSortBlock),
-                         0, st, (const K*)ki, (const V*)vi, ko, vo, m, shift,
+                         0, st, (const K*)ki, (const V*)vi, ko, vo, m, shift, dbits,
                          (const uint32_t*)hist, dev_m);
     }
     cur ^= 1;
+    shift += dbits;
   }
   return cur;
 }
