@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <mutex>
+#include <type_traits>
 
 #include "tc_device.h"
 #include "tc_internal.h"
@@ -206,7 +207,14 @@ __global__ __launch_bounds__(256) void k_vertex_keys(const int32_t* __restrict__
 
 // ----------------------------------------------------------- radix pass ----
 // `dev_m` (optional) holds the element count on the device; m is then the
-// capacity the grid was sized for.
+// capacity the grid was sized for.  A sort moves either (key, value) pairs
+// from two arrays, or (V = NoVal) whole 16-byte records whose first word is
+// the key.
+struct NoVal {};
+__device__ __forceinline__ uint32_t sort_key(uint32_t k) { return k; }
+__device__ __forceinline__ uint64_t sort_key(uint64_t k) { return k; }
+__device__ __forceinline__ uint32_t sort_key(const uint4& r) { return r.x; }
+
 template <typename K, int ITEMS>
 __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__ keys, int64_t m,
                                                            int shift, uint32_t mask,
@@ -220,7 +228,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
     int64_t i = start + (int64_t)r * kSortBlock + threadIdx.x;
-    if (i < m) atomicAdd(&s_h[(uint32_t)(keys[i] >> shift) & mask], 1u);
+    if (i < m) atomicAdd(&s_h[(uint32_t)(sort_key(keys[i]) >> shift) & mask], 1u);
   }
   __syncthreads();
   hist[(int64_t)blockIdx.x * 256 + threadIdx.x] = s_h[threadIdx.x];
@@ -328,6 +336,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
   constexpr int kTile = kSortBlock * ITEMS;
   constexpr int kWaves = kSortBlock / kWave;
   constexpr int kSub = kWave * ITEMS;  // entries per wavefront
+  constexpr bool kHasVal = !std::is_same<V, NoVal>::value;
   const uint32_t mask = (1u << dbits) - 1u;
   // XCD-aware tile order.  Workgroups are dealt to the XCDs round robin
   // (block b to XCD b mod 8), and each XCD has its own L2.  Neighbouring
@@ -344,7 +353,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
   __shared__ uint32_t s_wcnt[kWaves][256];  // per-wavefront running digit counts
   __shared__ uint32_t s_wsum[kWaves];
   __shared__ K s_key[kTile];
-  __shared__ V s_val[kTile];
+  __shared__ V s_val[kHasVal ? kTile : 1];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t start = (int64_t)tile * kTile;
@@ -363,9 +372,11 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
   for (int r = 0; r < ITEMS; ++r) {
     const int idx = wave * kSub + r * kWave + lane;
     const bool valid = idx < len;
-    key[r] = valid ? kin[start + idx] : (K)0;
-    if (valid) val[r] = vin[start + idx];
-    const uint32_t d = (uint32_t)(key[r] >> shift) & mask;
+    key[r] = valid ? kin[start + idx] : K{};
+    if constexpr (kHasVal) {
+      if (valid) val[r] = vin[start + idx];
+    }
+    const uint32_t d = (uint32_t)(sort_key(key[r]) >> shift) & mask;
     uint64_t vb = __ballot(valid);
     uint64_t peers = valid ? vb : ~vb;
 #pragma unroll
@@ -405,19 +416,19 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
   for (int r = 0; r < ITEMS; ++r) {
     const int idx = wave * kSub + r * kWave + lane;
     if (idx < len) {
-      const uint32_t d = (uint32_t)(key[r] >> shift) & mask;
+      const uint32_t d = (uint32_t)(sort_key(key[r]) >> shift) & mask;
       const uint32_t pos = s_excl[d] + s_wcnt[wave][d] + rank[r];
       s_key[pos] = key[r];
-      s_val[pos] = val[r];
+      if constexpr (kHasVal) s_val[pos] = val[r];
     }
   }
   __syncthreads();
   for (int i = tid; i < len; i += kSortBlock) {
     const K k = s_key[i];
-    const uint32_t d = (uint32_t)(k >> shift) & mask;
+    const uint32_t d = (uint32_t)(sort_key(k) >> shift) & mask;
     const int64_t gpos = (int64_t)s_base[d] + (i - (int64_t)s_excl[d]);
     kout[gpos] = k;
-    vout[gpos] = s_val[i];
+    if constexpr (kHasVal) vout[gpos] = s_val[i];
   }
 }
 
@@ -592,49 +603,40 @@ int pair_hash_log2(int64_t m) {
 }
 
 // ---------------------------------------------- sorts carrying their payload ---
-// When the time range fits 32 bits every sort moves its whole record:
-// key (u32) + payload {eid, other vertex, t - t_min}, so each column of the
-// three orders comes out of the last pass in order, with no random gathers.
+// When the time range fits 32 bits every sort moves its whole record, one
+// 16-byte word per edge: key (u32) + payload {eid, other vertex, t - t_min},
+// so each column of the three orders comes out of the last pass in order,
+// with no random gathers, and each digit run of a pass is one contiguous
+// stretch of records.
 __global__ __launch_bounds__(256) void k_rec_init(const int32_t* __restrict__ src,
                                                   const int32_t* __restrict__ dst,
                                                   const int64_t* __restrict__ t, int64_t m,
-                                                  int64_t tmin, uint32_t* __restrict__ k,
-                                                  uint3* __restrict__ v) {
+                                                  int64_t tmin, uint4* __restrict__ rec) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) {
-    k[i] = (uint32_t)(t[i] - tmin);
-    v[i] = make_uint3((uint32_t)i, (uint32_t)src[i], (uint32_t)dst[i]);
-  }
+  if (i < m)
+    rec[i] = make_uint4((uint32_t)(t[i] - tmin), (uint32_t)i, (uint32_t)src[i], (uint32_t)dst[i]);
 }
 
-// MODE 0: (t, {eid, src, dst}) -> (src, {eid, dst, t})   out-CSR input
-// MODE 1: (t, {eid, src, dst}) -> (dst, {eid, src, t})   in-CSR input
-// MODE 2: (dst, {eid, src, t}) -> (src, {eid, dst, t})   pair-index input
+// MODE 0: (t, eid, src, dst) -> (src, eid, dst, t)   out-CSR input
+// MODE 1: (t, eid, src, dst) -> (dst, eid, src, t)   in-CSR input
+// MODE 2: (dst, eid, src, t) -> (src, eid, dst, t)   pair-index input
 template <int MODE>
-__global__ __launch_bounds__(256) void k_rekey(const uint32_t* __restrict__ kin,
-                                               const uint3* __restrict__ vin, int64_t m,
-                                               uint32_t* __restrict__ kout,
-                                               uint3* __restrict__ vout) {
+__global__ __launch_bounds__(256) void k_rekey(const uint4* __restrict__ in, int64_t m,
+                                               uint4* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) {
-    const uint32_t k = kin[i];
-    const uint3 v = vin[i];
-    if (MODE == 0) {
-      kout[i] = v.y;
-      vout[i] = make_uint3(v.x, v.z, k);
-    } else if (MODE == 1) {
-      kout[i] = v.z;
-      vout[i] = make_uint3(v.x, v.y, k);
-    } else {
-      kout[i] = v.y;
-      vout[i] = make_uint3(v.x, k, v.z);
-    }
+    const uint4 r = in[i];
+    if (MODE == 0)
+      out[i] = make_uint4(r.z, r.y, r.w, r.x);
+    else if (MODE == 1)
+      out[i] = make_uint4(r.w, r.y, r.z, r.x);
+    else
+      out[i] = make_uint4(r.z, r.y, r.x, r.w);
   }
 }
 
-// sorted (key, {eid, other, t - t_min}) -> columns of one order
-__global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ k,
-                                              const uint3* __restrict__ v, int64_t m,
+// sorted (key, eid, other, t - t_min) -> columns of one order
+__global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ in, int64_t m,
                                               int64_t tmin, int32_t* __restrict__ key_col,
                                               int32_t* __restrict__ other_col,
                                               int64_t* __restrict__ t_col,
@@ -642,13 +644,13 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ k,
                                               uint4* __restrict__ rec) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) {
-    const uint3 r = v[i];
-    if (key_col) key_col[i] = (int32_t)k[i];
-    const int64_t te = tmin + (int64_t)r.z;
-    other_col[i] = (int32_t)r.y;
+    const uint4 r = in[i];
+    key_col[i] = (int32_t)r.x;
+    const int64_t te = tmin + (int64_t)r.w;
+    other_col[i] = (int32_t)r.z;
     t_col[i] = te;
-    eid_col[i] = (int32_t)r.x;
-    if (rec) rec[i] = make_uint4(r.y, r.x, (uint32_t)te, (uint32_t)(te >> 32));
+    eid_col[i] = (int32_t)r.y;
+    if (rec) rec[i] = make_uint4(r.z, r.y, (uint32_t)te, (uint32_t)(te >> 32));
   }
 }
 
@@ -659,7 +661,7 @@ struct GraphLayout {
   size_t out_off, in_off, out_src, out_dst, out_eid, out_t, in_src, in_eid, in_dst, in_t,
       out_to_in, pair_dst, out_rec, in_rec,
       pair_eid, pair_t, pair_hash, pair_skip, status, tminmax, keys0, keys1, vals0, vals1, hist, part,
-      part_elems, rk[4], rv[4], hist2, part2, total;
+      part_elems, rr[4], hist2, part2, total;
 };
 
 static GraphLayout graph_layout(int32_t n, int64_t m) {
@@ -694,13 +696,12 @@ static GraphLayout graph_layout(int32_t n, int64_t m) {
       take((size_t)(skip_level_len(m, 1) + skip_level_len(m, 2) + skip_level_len(m, 3)) * 8);
   L.status = take(4);
   L.tminmax = take(16);
-  // sort scratch: four (u32 key, 12-byte payload) buffers for the
-  // record-carrying sorts (two per concurrent branch), aliased by the
+  // sort scratch: four 16-byte-record buffers for the record-carrying
+  // sorts (two per concurrent branch), aliased by the
   // 64-bit-key buffers of the wide-time path (the two paths never run in the
   // same build)
   const size_t region = o;
-  for (int b = 0; b < 4; ++b) L.rk[b] = take((M + 1) * 4);
-  for (int b = 0; b < 4; ++b) L.rv[b] = take((M + 1) * 12);
+  for (int b = 0; b < 4; ++b) L.rr[b] = take((M + 1) * 16);
   const size_t rec_end = o;
   o = region;
   L.keys0 = take((M + 1) * 8);
@@ -852,18 +853,15 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     // bound); the out-CSR sort and the out-to-in positions (bandwidth bound)
     // run meanwhile on a second stream.  Buffers: T (time order), B and T
     // (in-CSR, pair index), A and C (out-CSR).
-    uint32_t* rk[4];
-    uint3* rv[4];
-    for (int b = 0; b < 4; ++b) {
-      rk[b] = (uint32_t*)(base + L.rk[b]);
-      rv[b] = (uint3*)(base + L.rv[b]);
-    }
+    const size_t M = (size_t)m;  // each record buffer holds M + 1 records
+    uint4* rr[4];
+    for (int b = 0; b < 4; ++b) rr[b] = (uint4*)(base + L.rr[b]);
     uint32_t* hist2 = (uint32_t*)(base + L.hist2);
     uint32_t* part2 = (uint32_t*)(base + L.part2);
     auto sort_rec = [&](int from, int tmp, int bits, uint32_t* h, uint32_t* pt,
                         hipStream_t s) -> int {
-      const int w = radix_sort<uint32_t, uint3, kRecItems>(rk[from], rv[from], rk[tmp], rv[tmp],
-                                                            m, bits, h, pt, pe, s);
+      const int w = radix_sort<uint4, NoVal, kRecItems>(rr[from], (NoVal*)nullptr, rr[tmp],
+                                                         (NoVal*)nullptr, m, bits, h, pt, pe, s);
       return w < 0 ? -1 : (w ? tmp : from);
     };
     SideStream* S = side_stream();
@@ -871,56 +869,56 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     if (S) lock = std::unique_lock<std::mutex>(S->mu);
     const bool two = S && side_ready(S);
     hipStream_t s2 = two ? S->s : st;
-    hipLaunchKernelGGL(k_rec_init, dim3(eb), dim3(256), 0, st, src, dst, t, m, tmin, rk[0], rv[0]);
+    hipLaunchKernelGGL(k_rec_init, dim3(eb), dim3(256), 0, st, src, dst, t, m, tmin, rr[0]);
     const int T = sort_rec(0, 1, tbits, hist, part, st);  // time order
     if (T < 0) return TC_E_WORKSPACE;
     int others[3], no = 0;
     for (int b = 0; b < 4; ++b)
       if (b != T) others[no++] = b;
     const int A = others[0], B = others[1], C = others[2];
-    hipLaunchKernelGGL(k_rekey<0>, dim3(eb), dim3(256), 0, st, (const uint32_t*)rk[T],
-                       (const uint3*)rv[T], m, rk[A], rv[A]);
-    hipLaunchKernelGGL(k_rekey<1>, dim3(eb), dim3(256), 0, st, (const uint32_t*)rk[T],
-                       (const uint3*)rv[T], m, rk[B], rv[B]);
+    hipLaunchKernelGGL(k_rekey<0>, dim3(eb), dim3(256), 0, st, (const uint4*)rr[T], m, rr[A]);
+    hipLaunchKernelGGL(k_rekey<1>, dim3(eb), dim3(256), 0, st, (const uint4*)rr[T], m, rr[B]);
     // in-CSR: stable by dst
     const int I = sort_rec(B, T, vbits, hist, part, st);
     if (I < 0) return TC_E_WORKSPACE;
     const int Ifree = (I == B) ? T : B;
-    hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint32_t*)rk[I],
-                       (const uint3*)rv[I], m, tmin, g->in_dst, g->in_src, g->in_t, g->in_eid,
-                       (uint4*)g->in_rec);
+    hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint4*)rr[I], m, tmin,
+                       g->in_dst, g->in_src, g->in_t, g->in_eid, (uint4*)g->in_rec);
     hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
-                       (const uint32_t*)rk[I], m, n, g->in_off);
+                       (const uint32_t*)g->in_dst, m, n, g->in_off);
     // pair index: the in-order (dst, t, eid) stably by src
-    hipLaunchKernelGGL(k_rekey<2>, dim3(eb), dim3(256), 0, st, (const uint32_t*)rk[I],
-                       (const uint3*)rv[I], m, rk[Ifree], rv[Ifree]);
+    hipLaunchKernelGGL(k_rekey<2>, dim3(eb), dim3(256), 0, st, (const uint4*)rr[I], m, rr[Ifree]);
     const int Pr = sort_rec(Ifree, I, vbits, hist, part, st);
     if (Pr < 0) return TC_E_WORKSPACE;
     const int Pfree = (Pr == I) ? Ifree : I;
-    hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint32_t*)rk[Pr],
-                       (const uint3*)rv[Pr], m, tmin, (int32_t*)nullptr, g->pair_dst,
-                       g->pair_t, g->pair_eid, (uint4*)nullptr);
+    // the pair sort's spare buffer holds the pair sources and the run-table
+    // scratch: three arrays of m + 1 words
+    uint32_t* psrc = (uint32_t*)rr[Pfree];
+    uint32_t* run_of = psrc + (M + 1);
+    uint32_t* run_start = psrc + 2 * (M + 1);
+    hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint4*)rr[Pr], m, tmin,
+                       (int32_t*)psrc, g->pair_dst, g->pair_t, g->pair_eid, (uint4*)nullptr);
     if (two) {
       if (hipEventRecord(S->fork, st) != hipSuccess ||
           hipStreamWaitEvent(s2, S->fork, 0) != hipSuccess)
         return TC_E_HIP;
     }
     // second stream: out-CSR (stable by src), then out_to_in[p] = in-CSR
-    // position of out_eid[p] through the key buffer of the finished sort
+    // position of out_eid[p] through the buffer of the finished sort
     const int R = sort_rec(A, C, vbits, hist2, part2, s2);
     if (R < 0) return TC_E_WORKSPACE;
-    hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, s2, (const uint32_t*)rk[R],
-                       (const uint3*)rv[R], m, tmin, g->out_src, g->out_dst, g->out_t,
-                       g->out_eid, (uint4*)g->out_rec);
+    hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, s2, (const uint4*)rr[R], m, tmin,
+                       g->out_src, g->out_dst, g->out_t, g->out_eid, (uint4*)g->out_rec);
     hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, s2,
-                       (const uint32_t*)rk[R], m, n, g->out_off);
+                       (const uint32_t*)g->out_src, m, n, g->out_off);
+    uint32_t* pos_of = (uint32_t*)rr[R];
     hipLaunchKernelGGL(k_scatter_pos, dim3(eb), dim3(256), 0, s2, (const int32_t*)g->in_eid, m,
-                       rk[R]);
+                       pos_of);
     hipLaunchKernelGGL(k_gather_pos, dim3(eb), dim3(256), 0, s2, (const int32_t*)g->out_eid, m,
-                       (const uint32_t*)rk[R], g->out_to_in);
+                       (const uint32_t*)pos_of, g->out_to_in);
     if (two && hipEventRecord(S->out_done, s2) != hipSuccess) return TC_E_HIP;
-    // this stream: the run table, with the pair sort's spare buffer as scratch
-    if (!build_pair_hash(rk[Pr], g, m, rk[Pfree], (uint32_t*)rv[Pfree], part, pe, tab, st))
+    // this stream: the run table
+    if (!build_pair_hash(psrc, g, m, run_of, run_start, part, pe, tab, st))
       return TC_E_WORKSPACE;
     if (two && hipStreamWaitEvent(st, S->out_done, 0) != hipSuccess) return TC_E_HIP;
     if (hipGetLastError() != hipSuccess) return TC_E_HIP;
