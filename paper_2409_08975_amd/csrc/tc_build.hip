@@ -34,6 +34,8 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanBlock * kScanItems;
 constexpr int kColChunk = 32;  // tiles per chunk of the histogram column scan
 
+static unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
 // ---------------------------------------------------------------- scans ----
 // Exclusive scan of u32 in three kernels: tile sums, one-block scan of the
 // tile sums, tile scans with the tile offset added.
@@ -215,6 +217,32 @@ __device__ __forceinline__ uint32_t sort_key(uint32_t k) { return k; }
 __device__ __forceinline__ uint64_t sort_key(uint64_t k) { return k; }
 __device__ __forceinline__ uint32_t sort_key(const uint4& r) { return r.x; }
 
+// Re-keying of a 16-byte edge record between the sorts of the build:
+//   RX_NONE  identity
+//   RX_OUT   (t, eid, src, dst) -> (src, eid, dst, t)   out-CSR input
+//   RX_IN    (t, eid, src, dst) -> (dst, eid, src, t)   in-CSR input
+//   RX_PAIR  (dst, eid, src, t) -> (src, eid, dst, t)   pair-index input
+enum { RX_NONE = 0, RX_OUT = 1, RX_IN = 2, RX_PAIR = 3 };
+__device__ __forceinline__ uint4 rec_xform(const uint4& r, int xf) {
+  if (xf == RX_OUT) return make_uint4(r.z, r.y, r.w, r.x);
+  if (xf == RX_IN) return make_uint4(r.w, r.y, r.z, r.x);
+  if (xf == RX_PAIR) return make_uint4(r.z, r.y, r.x, r.w);
+  return r;
+}
+
+// the re-keying of a sort with no pass (a key of zero bits), in place:
+// every element is read and written by the same thread
+__global__ __launch_bounds__(256) void k_rec_xform(uint4* __restrict__ a, int64_t m,
+                                                   int xf1, uint4* __restrict__ out2, int xf2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) {
+    const uint4 r = a[i];
+    a[i] = rec_xform(r, xf1);
+    if (out2) out2[i] = rec_xform(r, xf2);
+  }
+}
+
+
 template <typename K, int ITEMS>
 __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__ keys, int64_t m,
                                                            int shift, uint32_t mask,
@@ -328,7 +356,9 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
                                                               V* __restrict__ vout, int64_t m,
                                                               int shift, int dbits,
                                                               const uint32_t* __restrict__ hist,
-                                                              const uint32_t* __restrict__ dev_m) {
+                                                              const uint32_t* __restrict__ dev_m,
+                                                              int xf1, K* __restrict__ kout2,
+                                                              int xf2) {
   // Each wavefront owns a contiguous quarter of the tile and ranks its keys
   // in order with ballots (no block barrier inside); one block-wide pass then
   // offsets every wavefront's digit counts by those of the wavefronts before
@@ -427,7 +457,13 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
     const K k = s_key[i];
     const uint32_t d = (uint32_t)(sort_key(k) >> shift) & mask;
     const int64_t gpos = (int64_t)s_base[d] + (i - (int64_t)s_excl[d]);
-    kout[gpos] = k;
+    if constexpr (std::is_same<K, uint4>::value) {
+      // records: the last pass of a sort can re-key them for the next sort
+      kout[gpos] = rec_xform(k, xf1);
+      if (kout2) kout2[gpos] = rec_xform(k, xf2);
+    } else {
+      kout[gpos] = k;
+    }
     if constexpr (kHasVal) vout[gpos] = s_val[i];
   }
 }
@@ -436,10 +472,13 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
 // Ping-pongs between (k0, v0) and (k1, v1); returns 0 if the result is in
 // buffer 0, 1 if in buffer 1.
 // returns -1 if the scan scratch is too small (nothing enqueued then)
+// Records (K = uint4) leave the sort re-keyed by xf1, and if `extra` is given
+// a second copy re-keyed by xf2 goes there.
 template <typename K, typename V = int32_t, int ITEMS = kSortItems>
 int radix_sort(K* k0, V* v0, K* k1, V* v1, int64_t m, int bits, uint32_t* hist,
                uint32_t* part, size_t part_elems, hipStream_t st,
-               const uint32_t* dev_m = nullptr) {
+               const uint32_t* dev_m = nullptr, int xf1 = RX_NONE, K* extra = nullptr,
+               int xf2 = RX_NONE) {
   if (m <= 0) return 0;
   constexpr int kTile = kSortBlock * ITEMS;
   const int64_t ntiles = (m + kTile - 1) / kTile;
@@ -449,7 +488,13 @@ int radix_sort(K* k0, V* v0, K* k1, V* v1, int64_t m, int bits, uint32_t* hist,
   // ones first): fewer distinct digits per tile means longer runs in the
   // scatter's output, and fewer partly written cache lines
   const int npass = (bits + 7) / 8;
+  if constexpr (std::is_same<K, uint4>::value) {
+    if (npass == 0 && (xf1 != RX_NONE || extra))
+      hipLaunchKernelGGL(k_rec_xform, dim3(blocks_for(m, 256)), dim3(256), 0, st, k0, m, xf1,
+                         extra, xf2);
+  }
   for (int p = 0, shift = 0; p < npass; ++p) {
+    const bool last = p + 1 == npass;
     const int dbits = (bits - shift) / (npass - p);
     const uint32_t mask = (1u << dbits) - 1u;
     K* ki = cur ? k1 : k0;
@@ -463,7 +508,8 @@ int radix_sort(K* k0, V* v0, K* k1, V* v1, int64_t m, int bits, uint32_t* hist,
       TimedLaunch tl("k_radix_scatter", st);
       hipLaunchKernelGGL((k_radix_scatter<K, V, ITEMS>), dim3((unsigned)ntiles), dim3(kSortBlock),
                          0, st, (const K*)ki, (const V*)vi, ko, vo, m, shift, dbits,
-                         (const uint32_t*)hist, dev_m);
+                         (const uint32_t*)hist, dev_m, last ? xf1 : (int)RX_NONE,
+                         last ? extra : (K*)nullptr, last ? xf2 : (int)RX_NONE);
     }
     cur ^= 1;
     shift += dbits;
@@ -617,24 +663,6 @@ __global__ __launch_bounds__(256) void k_rec_init(const int32_t* __restrict__ sr
     rec[i] = make_uint4((uint32_t)(t[i] - tmin), (uint32_t)i, (uint32_t)src[i], (uint32_t)dst[i]);
 }
 
-// MODE 0: (t, eid, src, dst) -> (src, eid, dst, t)   out-CSR input
-// MODE 1: (t, eid, src, dst) -> (dst, eid, src, t)   in-CSR input
-// MODE 2: (dst, eid, src, t) -> (src, eid, dst, t)   pair-index input
-template <int MODE>
-__global__ __launch_bounds__(256) void k_rekey(const uint4* __restrict__ in, int64_t m,
-                                               uint4* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) {
-    const uint4 r = in[i];
-    if (MODE == 0)
-      out[i] = make_uint4(r.z, r.y, r.w, r.x);
-    else if (MODE == 1)
-      out[i] = make_uint4(r.w, r.y, r.z, r.x);
-    else
-      out[i] = make_uint4(r.z, r.y, r.x, r.w);
-  }
-}
-
 // sorted (key, eid, other, t - t_min) -> columns of one order
 __global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ in, int64_t m,
                                               int64_t tmin, int32_t* __restrict__ key_col,
@@ -755,7 +783,6 @@ size_t graph_workspace_bytes(int32_t n, int64_t m) { return graph_layout(n, m).t
 
 static int bitlen(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
 
-static unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // Runs of equal (src, dst) in the pair index -> hash table.  psrc holds the
 // sorted src keys; run_of and run_start are free buffers of m + 1 entries.
@@ -851,17 +878,20 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     // record-carrying sorts.  This stream sorts by time, then the in-CSR and
     // the pair index, then builds the run table (random atomics, latency
     // bound); the out-CSR sort and the out-to-in positions (bandwidth bound)
-    // run meanwhile on a second stream.  Buffers: T (time order), B and T
-    // (in-CSR, pair index), A and C (out-CSR).
+    // run meanwhile on a second stream.  Four record buffers: the time sort
+    // ping-pongs in 0 and 1, the in-CSR sort in 2 and the free one of those,
+    // the pair sort in 3 and the one the in-CSR sort left free, and the
+    // out-CSR sort in A (the time sort's result) and the in-CSR result.
     const size_t M = (size_t)m;  // each record buffer holds M + 1 records
     uint4* rr[4];
     for (int b = 0; b < 4; ++b) rr[b] = (uint4*)(base + L.rr[b]);
     uint32_t* hist2 = (uint32_t*)(base + L.hist2);
     uint32_t* part2 = (uint32_t*)(base + L.part2);
-    auto sort_rec = [&](int from, int tmp, int bits, uint32_t* h, uint32_t* pt,
-                        hipStream_t s) -> int {
-      const int w = radix_sort<uint4, NoVal, kRecItems>(rr[from], (NoVal*)nullptr, rr[tmp],
-                                                         (NoVal*)nullptr, m, bits, h, pt, pe, s);
+    auto sort_rec = [&](int from, int tmp, int bits, uint32_t* h, uint32_t* pt, hipStream_t s,
+                        int xf1 = RX_NONE, int extra = -1, int xf2 = RX_NONE) -> int {
+      const int w = radix_sort<uint4, NoVal, kRecItems>(
+          rr[from], (NoVal*)nullptr, rr[tmp], (NoVal*)nullptr, m, bits, h, pt, pe, s, nullptr,
+          xf1, extra < 0 ? (uint4*)nullptr : rr[extra], xf2);
       return w < 0 ? -1 : (w ? tmp : from);
     };
     SideStream* S = side_stream();
@@ -870,27 +900,24 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     const bool two = S && side_ready(S);
     hipStream_t s2 = two ? S->s : st;
     hipLaunchKernelGGL(k_rec_init, dim3(eb), dim3(256), 0, st, src, dst, t, m, tmin, rr[0]);
-    const int T = sort_rec(0, 1, tbits, hist, part, st);  // time order
-    if (T < 0) return TC_E_WORKSPACE;
-    int others[3], no = 0;
-    for (int b = 0; b < 4; ++b)
-      if (b != T) others[no++] = b;
-    const int A = others[0], B = others[1], C = others[2];
-    hipLaunchKernelGGL(k_rekey<0>, dim3(eb), dim3(256), 0, st, (const uint4*)rr[T], m, rr[A]);
-    hipLaunchKernelGGL(k_rekey<1>, dim3(eb), dim3(256), 0, st, (const uint4*)rr[T], m, rr[B]);
-    // in-CSR: stable by dst
-    const int I = sort_rec(B, T, vbits, hist, part, st);
+    // time order; its last pass leaves the records re-keyed as the input of
+    // the out-CSR sort (buffer A, the sort's own) and of the in-CSR sort (B)
+    const int A = sort_rec(0, 1, tbits, hist, part, st, RX_OUT, 2, RX_IN);
+    if (A < 0) return TC_E_WORKSPACE;
+    const int B = 2, F = 1 - A;
+    // in-CSR: stable by dst; a second copy of the result, re-keyed, is the
+    // pair index input (buffer 3)
+    const int I = sort_rec(B, F, vbits, hist, part, st, RX_NONE, 3, RX_PAIR);
     if (I < 0) return TC_E_WORKSPACE;
-    const int Ifree = (I == B) ? T : B;
+    const int Ifree = (I == B) ? F : B;
     hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint4*)rr[I], m, tmin,
                        g->in_dst, g->in_src, g->in_t, g->in_eid, (uint4*)g->in_rec);
     hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
                        (const uint32_t*)g->in_dst, m, n, g->in_off);
     // pair index: the in-order (dst, t, eid) stably by src
-    hipLaunchKernelGGL(k_rekey<2>, dim3(eb), dim3(256), 0, st, (const uint4*)rr[I], m, rr[Ifree]);
-    const int Pr = sort_rec(Ifree, I, vbits, hist, part, st);
+    const int Pr = sort_rec(3, Ifree, vbits, hist, part, st);
     if (Pr < 0) return TC_E_WORKSPACE;
-    const int Pfree = (Pr == I) ? Ifree : I;
+    const int Pfree = (Pr == 3) ? Ifree : 3;
     // the pair sort's spare buffer holds the pair sources and the run-table
     // scratch: three arrays of m + 1 words
     uint32_t* psrc = (uint32_t*)rr[Pfree];
@@ -903,9 +930,10 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
           hipStreamWaitEvent(s2, S->fork, 0) != hipSuccess)
         return TC_E_HIP;
     }
-    // second stream: out-CSR (stable by src), then out_to_in[p] = in-CSR
-    // position of out_eid[p] through the buffer of the finished sort
-    const int R = sort_rec(A, C, vbits, hist2, part2, s2);
+    // second stream: out-CSR (stable by src), with the in-CSR records'
+    // buffer (emitted before the fork) as its spare, then out_to_in[p] =
+    // in-CSR position of out_eid[p] through the buffer of the finished sort
+    const int R = sort_rec(A, I, vbits, hist2, part2, s2);
     if (R < 0) return TC_E_WORKSPACE;
     hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, s2, (const uint4*)rr[R], m, tmin,
                        g->out_src, g->out_dst, g->out_t, g->out_eid, (uint4*)g->out_rec);

@@ -30,7 +30,7 @@ KERNEL_SRC = {
     "k_scan_tiles": "tc_weights.hip", "k_scan_apply": "tc_weights.hip",
     "k_tree_level": "tc_weights.hip", "k_radix_scatter": "tc_build.hip",
     "k_radix_hist": "tc_build.hip", "k_hash_insert": "tc_build.hip", "k_emit": "tc_build.hip",
-    "k_rekey": "tc_build.hip",
+    "k_rec_xform": "tc_build.hip",
 }
 
 

@@ -274,6 +274,20 @@ def test_single_vertex_and_wide_time_range(tcb, torch_mod):
         check_sample(tcb, G, Wt, og, ow, SIX, 5000, seed=3)
 
 
+def test_equal_timestamps(tcb, torch_mod):
+    # one timestamp for every edge: the time sort has no pass, so its re-keying
+    # of the records for the next two sorts runs on its own
+    g = sg.gen_micro(21, n=40, m=5000, t_span=10)
+    g.t = np.full(g.m, 123456789, np.int64)
+    G, og = build_both(tcb, torch_mod, g)
+    check_graph(G, og, g)
+    for delta in (0, 5):
+        Wt = tcb.tc_path_weights(G, delta)
+        ow = og.weights(delta)
+        check_weights(Wt, ow, g, og)
+        check_sample(tcb, G, Wt, og, ow, SIX, 3000, seed=4)
+
+
 def test_range_errors(tcb, torch_mod):
     s = torch_mod.tensor([0, 1], dtype=torch_mod.int32, device="cuda")
     d = torch_mod.tensor([1, 3], dtype=torch_mod.int32, device="cuda")
