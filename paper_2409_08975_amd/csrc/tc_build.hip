@@ -29,102 +29,9 @@ constexpr uint32_t kXcds = 8;  // accelerator complex dies of an MI355X, each wi
 constexpr int kSortItems = 16;
 constexpr int kRecItems = 8;  // record-carrying sorts: 2048-entry tiles (LDS holds 16 B/entry)
 constexpr int kRecTile = kSortBlock * kRecItems;
-constexpr int kScanBlock = 256;
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kScanBlock * kScanItems;
 constexpr int kColChunk = 32;  // tiles per chunk of the histogram column scan
 
 static unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
-
-// ---------------------------------------------------------------- scans ----
-// Exclusive scan of u32 in three kernels: tile sums, one-block scan of the
-// tile sums, tile scans with the tile offset added.
-__global__ __launch_bounds__(kScanBlock) void k_tile_sum_u32(const uint32_t* __restrict__ in,
-                                                           int64_t n, uint32_t* __restrict__ part) {
-  __shared__ uint32_t s_w[kScanBlock / kWave];
-  int64_t base = (int64_t)blockIdx.x * kScanTile;
-  uint32_t s = 0;
-#pragma unroll
-  for (int j = 0; j < kScanItems; ++j) {
-    int64_t i = base + (int64_t)j * kScanBlock + threadIdx.x;
-    if (i < n) s += in[i];
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
-  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t t = 0;
-    for (int w = 0; w < kScanBlock / kWave; ++w) t += s_w[w];
-    part[blockIdx.x] = t;
-  }
-}
-
-// single block of 1024 threads; any length, chunked with a running carry
-__global__ __launch_bounds__(1024) void k_scan_small_u32(uint32_t* __restrict__ a, int64_t n) {
-  __shared__ uint32_t s_w[16];
-  __shared__ uint32_t s_carry;
-  if (threadIdx.x == 0) s_carry = 0;
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int64_t base = 0; base < n; base += 1024) {
-    int64_t i = base + threadIdx.x;
-    uint32_t v = i < n ? a[i] : 0;
-    uint32_t inc = wave_inclusive_scan(v);
-    if (lane == 63) s_w[wave] = inc;
-    __syncthreads();
-    uint32_t wo = 0;
-    for (int w = 0; w < wave; ++w) wo += s_w[w];
-    uint32_t carry = s_carry;
-    if (i < n) a[i] = carry + wo + inc - v;
-    __syncthreads();
-    if (threadIdx.x == 1023) s_carry = carry + wo + inc;
-    __syncthreads();
-  }
-}
-
-__global__ __launch_bounds__(kScanBlock) void k_tile_scan_u32(const uint32_t* __restrict__ in,
-                                                            uint32_t* __restrict__ out, int64_t n,
-                                                            const uint32_t* __restrict__ part) {
-  __shared__ uint32_t s_w[kScanBlock / kWave];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // blocked arrangement: thread owns kScanItems consecutive elements
-  int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems];
-  uint32_t s = 0;
-#pragma unroll
-  for (int j = 0; j < kScanItems; ++j) {
-    v[j] = (base + j < n) ? in[base + j] : 0;
-    s += v[j];
-  }
-  uint32_t inc = wave_inclusive_scan(s);
-  if (lane == 63) s_w[wave] = inc;
-  __syncthreads();
-  uint32_t run = part[blockIdx.x] + inc - s;
-  for (int w = 0; w < wave; ++w) run += s_w[w];
-#pragma unroll
-  for (int j = 0; j < kScanItems; ++j) {
-    if (base + j < n) out[base + j] = run;
-    run += v[j];
-  }
-}
-
-size_t scan_u32_scratch_elems(int64_t n) {
-  return (size_t)((n + kScanTile - 1) / kScanTile) + 1;
-}
-
-// in-place exclusive scan of a[0..n); `part` must hold scan_u32_scratch_elems(n)
-// entries (checked: returns false and enqueues nothing otherwise)
-bool scan_u32(uint32_t* a, int64_t n, uint32_t* part, size_t part_elems, hipStream_t st) {
-  if (n <= 0) return true;
-  if (part_elems < scan_u32_scratch_elems(n)) return false;
-  int64_t tiles = (n + kScanTile - 1) / kScanTile;
-  hipLaunchKernelGGL(k_tile_sum_u32, dim3((unsigned)tiles), dim3(kScanBlock), 0, st, a, n, part);
-  hipLaunchKernelGGL(k_scan_small_u32, dim3(1), dim3(1024), 0, st, part, tiles);
-  hipLaunchKernelGGL(k_tile_scan_u32, dim3((unsigned)tiles), dim3(kScanBlock), 0, st, a, a, n,
-                     (const uint32_t*)part);
-  return true;
-}
 
 // ------------------------------------------------------------ validation ---
 __global__ void k_init_build(uint32_t* status, uint64_t* tminmax) {
@@ -575,27 +482,6 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ a, int6
 // src << 32 | dst).  A slot is 16 bytes {key, run start, run end}, so a hit
 // costs one 16-byte load.  The capacity is a power of two above 1.25 m, so
 // the load factor stays below 0.8 and a probe always reaches an empty slot.
-__global__ __launch_bounds__(256) void k_run_flags(const uint32_t* __restrict__ psrc,
-                                                   const int32_t* __restrict__ pdst, int64_t m,
-                                                   uint32_t* __restrict__ flag) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m)
-    flag[i] = (i == 0 || psrc[i] != psrc[i - 1] || pdst[i] != pdst[i - 1]) ? 1u : 0u;
-  else if (i == m)
-    flag[i] = 0u;
-}
-
-// flag has been scanned in place: flag[i] = run index of a run starting at i
-__global__ __launch_bounds__(256) void k_run_starts(const uint32_t* __restrict__ psrc,
-                                                    const int32_t* __restrict__ pdst, int64_t m,
-                                                    const uint32_t* __restrict__ run_of,
-                                                    uint32_t* __restrict__ run_start) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m && (i == 0 || psrc[i] != psrc[i - 1] || pdst[i] != pdst[i - 1]))
-    run_start[run_of[i]] = (uint32_t)i;
-  if (i == m) run_start[run_of[m]] = (uint32_t)m;  // sentinel after the last run
-}
-
 __global__ __launch_bounds__(256) void k_hash_clear(PairSlot* __restrict__ tab, int64_t cap) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < cap) {
@@ -605,15 +491,33 @@ __global__ __launch_bounds__(256) void k_hash_clear(PairSlot* __restrict__ tab, 
   }
 }
 
+// One thread per pair-index position.  The thread at the first position of
+// a (src, dst) run finds where the run ends -- galloping over the sorted
+// keys, then bisecting the last gap, so a run of length L costs O(log L)
+// probes and most runs (a single edge) one -- and inserts {key, start, end}.
 __global__ __launch_bounds__(256) void k_hash_insert(const uint32_t* __restrict__ psrc,
-                                                     const int32_t* __restrict__ pdst,
-                                                     const uint32_t* __restrict__ run_start,
-                                                     const uint32_t* __restrict__ n_runs,
+                                                     const int32_t* __restrict__ pdst, int64_t m,
                                                      PairSlot* __restrict__ tab, int log2cap) {
-  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= *n_runs) return;
-  const uint32_t s0 = run_start[r], s1 = run_start[r + 1];
-  const uint64_t key = pair_key(psrc[s0], pdst[s0]);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  auto key_at = [&](int64_t j) { return pair_key(psrc[j], (uint32_t)pdst[j]); };
+  const uint64_t key = key_at(i);
+  if (i > 0 && key_at(i - 1) == key) return;
+  int64_t lo = i, hi, step = 1;  // key_at(lo) == key
+  for (;;) {
+    hi = lo + step;
+    if (hi >= m || key_at(hi) != key) break;
+    lo = hi;
+    step <<= 1;
+  }
+  if (hi > m) hi = m;  // hi == m, or key_at(hi) != key
+  while (hi - lo > 1) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (key_at(mid) == key)
+      lo = mid;
+    else
+      hi = mid;
+  }
   const uint64_t mask = (1ull << log2cap) - 1;
   uint64_t h = pair_hash(key, log2cap);
   for (uint64_t probe = 0; probe <= mask; ++probe) {
@@ -621,8 +525,8 @@ __global__ __launch_bounds__(256) void k_hash_insert(const uint32_t* __restrict_
         atomicCAS((unsigned long long*)&tab[h].key, (unsigned long long)kPairEmpty,
                   (unsigned long long)key);
     if (prev == kPairEmpty) {
-      tab[h].start = s0;
-      tab[h].end = s1;
+      tab[h].start = (uint32_t)i;
+      tab[h].end = (uint32_t)hi;
       return;
     }
     h = (h + 1) & mask;
@@ -738,10 +642,8 @@ static GraphLayout graph_layout(int32_t n, int64_t m) {
   L.vals1 = take((M + 1) * 4);
   if (o < rec_end) o = rec_end;
   L.hist = take((size_t)256 * ntiles * 4);
-  // scan scratch: the larger of the histogram column scan and the
-  // (m + 1)-entry run scan
+  // scan scratch of the histogram column scan
   L.part_elems = col_scan_scratch_elems(ntiles);
-  if (scan_u32_scratch_elems(m + 1) > L.part_elems) L.part_elems = scan_u32_scratch_elems(m + 1);
   L.part = take(L.part_elems * 4);
   // histogram and scan scratch of the side stream
   L.hist2 = take((size_t)256 * ntiles * 4);
@@ -784,25 +686,17 @@ size_t graph_workspace_bytes(int32_t n, int64_t m) { return graph_layout(n, m).t
 static int bitlen(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
 
 
-// Runs of equal (src, dst) in the pair index -> hash table.  psrc holds the
-// sorted src keys; run_of and run_start are free buffers of m + 1 entries.
-static bool build_pair_hash(const uint32_t* psrc, const tc_graph* g, int64_t m, uint32_t* run_of,
-                            uint32_t* run_start, uint32_t* part, size_t pe, PairSlot* tab,
+// The pair-run table and the sampled pair times, from the pair index's
+// sorted src keys.
+static void build_pair_hash(const uint32_t* psrc, const tc_graph* g, int64_t m, PairSlot* tab,
                             hipStream_t st) {
-  hipLaunchKernelGGL(k_run_flags, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st, psrc,
-                     (const int32_t*)g->pair_dst, m, run_of);
-  if (!scan_u32(run_of, m + 1, part, pe, st)) return false;
-  hipLaunchKernelGGL(k_run_starts, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st, psrc,
-                     (const int32_t*)g->pair_dst, m, (const uint32_t*)run_of, run_start);
   {
     const int64_t n1 = skip_level_len(m, 1), n2 = skip_level_len(m, 2), n3 = skip_level_len(m, 3);
     hipLaunchKernelGGL(k_pair_skip, dim3(blocks_for(n1 + n2 + n3, 256)), dim3(256), 0, st,
                        (const int64_t*)g->pair_t, n1, n2, n3, g->pair_skip);
   }
   hipLaunchKernelGGL(k_hash_insert, dim3(blocks_for(m, 256)), dim3(256), 0, st, psrc,
-                     (const int32_t*)g->pair_dst, (const uint32_t*)run_start,
-                     (const uint32_t*)(run_of + m), tab, g->pair_hash_log2);
-  return true;
+                     (const int32_t*)g->pair_dst, m, tab, g->pair_hash_log2);
 }
 
 tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
@@ -882,7 +776,6 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     // ping-pongs in 0 and 1, the in-CSR sort in 2 and the free one of those,
     // the pair sort in 3 and the one the in-CSR sort left free, and the
     // out-CSR sort in A (the time sort's result) and the in-CSR result.
-    const size_t M = (size_t)m;  // each record buffer holds M + 1 records
     uint4* rr[4];
     for (int b = 0; b < 4; ++b) rr[b] = (uint4*)(base + L.rr[b]);
     uint32_t* hist2 = (uint32_t*)(base + L.hist2);
@@ -918,11 +811,8 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     const int Pr = sort_rec(3, Ifree, vbits, hist, part, st);
     if (Pr < 0) return TC_E_WORKSPACE;
     const int Pfree = (Pr == 3) ? Ifree : 3;
-    // the pair sort's spare buffer holds the pair sources and the run-table
-    // scratch: three arrays of m + 1 words
+    // the pair sort's spare buffer holds the pair sources
     uint32_t* psrc = (uint32_t*)rr[Pfree];
-    uint32_t* run_of = psrc + (M + 1);
-    uint32_t* run_start = psrc + 2 * (M + 1);
     hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint4*)rr[Pr], m, tmin,
                        (int32_t*)psrc, g->pair_dst, g->pair_t, g->pair_eid, (uint4*)nullptr);
     if (two) {
@@ -946,8 +836,7 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
                        (const uint32_t*)pos_of, g->out_to_in);
     if (two && hipEventRecord(S->out_done, s2) != hipSuccess) return TC_E_HIP;
     // this stream: the run table
-    if (!build_pair_hash(psrc, g, m, run_of, run_start, part, pe, tab, st))
-      return TC_E_WORKSPACE;
+    build_pair_hash(psrc, g, m, tab, st);
     if (two && hipStreamWaitEvent(st, S->out_done, 0) != hipSuccess) return TC_E_HIP;
     if (hipGetLastError() != hipSuccess) return TC_E_HIP;
     return TC_OK;
@@ -1031,9 +920,7 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
                        (const int32_t*)sv, m, dst, t, (int32_t*)nullptr, g->pair_dst, g->pair_t,
                        g->pair_eid, (uint4*)nullptr);
     // 5. pair-run hash table (the sorted src keys are still in sk)
-    uint32_t* run_of = w ? k0 : k1;                        // the free key buffer (m + 1)
-    uint32_t* run_start = (uint32_t*)(w ? vals0 : vals1);  // the free value buffer (m + 1)
-    if (!build_pair_hash(sk, g, m, run_of, run_start, part, pe, tab, st)) return TC_E_WORKSPACE;
+    build_pair_hash(sk, g, m, tab, st);
   }
   if (hipGetLastError() != hipSuccess) return TC_E_HIP;
   return TC_OK;
