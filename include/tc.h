@@ -175,13 +175,21 @@ typedef struct tc_result {
  *   reg_waves   wavefronts of the register ListCount pass
  *   fast_waves  wavefronts of the LDS-key ListCount pass (64..8192)
  *   wide_blocks 256-thread blocks of the merged ListCount pass for lists
- *               over 1024 entries (64..2048; 1 MiB of workspace each) */
+ *               over lds_list_cap entries (64..2048; 1 MiB of workspace each)
+ *   reg_list_cap  longest list the register ListCount pass takes: 128 or
+ *               256 entries (two or four 64-entry chunks per lane); items
+ *               with a longer list go to the LDS-key pass
+ *   lds_list_cap  longest list the one-wavefront LDS-key pass takes
+ *               (256..1024); items with a longer list go to the merged
+ *               pass, where 256 lanes work on one item instead of 64 */
 typedef struct {
   int32_t chunk_log2;
   int32_t path_blocks;
   int32_t reg_waves;
   int32_t fast_waves;
   int32_t wide_blocks;
+  int32_t reg_list_cap;
+  int32_t lds_list_cap;
 } tc_tuning;
 
 /* Library version string (host, static storage). */
@@ -263,7 +271,8 @@ tc_status tc_batch_estimate(const tc_graph *g, const tc_weights *const *w, int32
 
 /* Autotuner: times tc_batch_estimate with k_probe samples for candidate
  * tunings (coordinate descent over chunk_log2, path_blocks, reg_waves,
- * fast_waves, wide_blocks) with HIP events on `stream`, and returns the fastest in *best
+ * fast_waves, wide_blocks, reg_list_cap, lds_list_cap) with HIP events on
+ * `stream`, and returns the fastest in *best
  * and its time in *best_ms.  Synchronises the stream; `out` receives the
  * probe results.  ws must hold tc_batch_workspace_bytes(k_probe, ...). */
 tc_status tc_autotune(const tc_graph *g, const tc_weights *const *w, int32_t n_deltas,

@@ -87,15 +87,17 @@ class tc_result(ctypes.Structure):
 class tc_tuning(ctypes.Structure):
     _fields_ = [("chunk_log2", ctypes.c_int32), ("path_blocks", ctypes.c_int32),
                 ("reg_waves", ctypes.c_int32), ("fast_waves", ctypes.c_int32),
-                ("wide_blocks", ctypes.c_int32)]
+                ("wide_blocks", ctypes.c_int32), ("reg_list_cap", ctypes.c_int32),
+                ("lds_list_cap", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 def make_tuning(chunk_log2=22, path_blocks=0, reg_waves=10240, fast_waves=5120,
-                wide_blocks=1024) -> tc_tuning:
-    return tc_tuning(chunk_log2, path_blocks, reg_waves, fast_waves, wide_blocks)
+                wide_blocks=1024, reg_list_cap=256, lds_list_cap=1024) -> tc_tuning:
+    return tc_tuning(chunk_log2, path_blocks, reg_waves, fast_waves, wide_blocks, reg_list_cap,
+                     lds_list_cap)
 
 
 _lib = None

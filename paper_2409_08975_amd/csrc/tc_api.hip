@@ -169,19 +169,27 @@ tc_status tc_autotune(const tc_graph* g, const tc_weights* const* w, int32_t n_d
   tc_tuning cur = tc::default_tuning();
   double cur_ms = 0;
   tc_status s = run(cur, &cur_ms);
-  const int32_t chunks[] = {20, 21, 22};
-  const int32_t pblocks[] = {0, 1024, 4096};
-  const int32_t rwaves[] = {5120, 10240, 20480};
-  const int32_t fwaves[] = {2560, 5120, 8192};
-  const int32_t wblocks[] = {512, 1024, 2048};
-  for (int dim = 0; dim < 5 && s == TC_OK; ++dim) {
+  // candidate values per knob (a knob with fewer repeats its last one)
+  const int32_t cand[7][3] = {
+      {20, 21, 22},         // chunk_log2
+      {0, 1024, 4096},      // path_blocks
+      {5120, 10240, 20480}, // reg_waves
+      {2560, 5120, 8192},   // fast_waves
+      {512, 1024, 2048},    // wide_blocks
+      {128, 256, 256},      // reg_list_cap: lanes hold 2 or 4 list entries
+      {256, 512, 1024},     // lds_list_cap: 64 lanes per item up to it, 256 above
+  };
+  for (int dim = 0; dim < 7 && s == TC_OK; ++dim) {
     for (int c = 0; c < 3 && s == TC_OK; ++c) {
+      if (c > 0 && cand[dim][c] == cand[dim][c - 1]) continue;
       tc_tuning t = cur;
-      if (dim == 0) t.chunk_log2 = chunks[c];
-      if (dim == 1) t.path_blocks = pblocks[c];
-      if (dim == 2) t.reg_waves = rwaves[c];
-      if (dim == 3) t.fast_waves = fwaves[c];
-      if (dim == 4) t.wide_blocks = wblocks[c];
+      if (dim == 0) t.chunk_log2 = cand[dim][c];
+      if (dim == 1) t.path_blocks = cand[dim][c];
+      if (dim == 2) t.reg_waves = cand[dim][c];
+      if (dim == 3) t.fast_waves = cand[dim][c];
+      if (dim == 4) t.wide_blocks = cand[dim][c];
+      if (dim == 5) t.reg_list_cap = cand[dim][c];
+      if (dim == 6) t.lds_list_cap = cand[dim][c];
       double ms = 0;
       s = run(t, &ms);
       if (s == TC_OK && ms < cur_ms) {

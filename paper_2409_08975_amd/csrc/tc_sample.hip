@@ -109,6 +109,7 @@ struct SampleArgs {
   uint32_t* samp_h;  // [nd][chunk] proposal factor of each accepted sample
   uint64_t* fast_p;  // [fast waves][2][kKeyCap + 1]
   uint64_t* wide_p;  // [wide blocks][2][kWideCap + 1]
+  uint32_t lds_cap;  // longest list of the LDS-key pass (at most kKeyCap)
   MotifPlan plan;
 };
 
@@ -746,7 +747,7 @@ __global__ __launch_bounds__(kWave) void k_listcount_lds(SampleArgs A, uint64_t*
       maxlen = len_r > maxlen ? len_r : maxlen;
       base = first_r < base ? first_r : base;
     }
-    const bool fwd = maxlen > (uint32_t)kKeyCap || A.D[d].delta >= ((int64_t)1 << 32);
+    const bool fwd = maxlen > A.lds_cap || A.D[d].delta >= ((int64_t)1 << 32);
     U128 total{0, 0};
     if (!fwd) {
       const uint32_t lo0 = lane_u32(my_lo, 0), len0 = lane_u32(my_len, 0);
@@ -1079,6 +1080,8 @@ SampleTuning default_tuning() {
   t.reg_waves = 10240;
   t.fast_waves = 5120;
   t.wide_blocks = kDefaultWideBlocks;
+  t.reg_list_cap = 256;
+  t.lds_list_cap = kKeyCap;
   return t;
 }
 
@@ -1207,6 +1210,8 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
   A.samp_h = (uint32_t*)(base + L.samp_h);
   A.wide_p = (uint64_t*)(base + L.wide_p);
   A.plan = plan;
+  A.lds_cap = (uint32_t)(tune.lds_list_cap < kWave ? kWave
+                         : (tune.lds_list_cap > kKeyCap ? kKeyCap : tune.lds_list_cap));
   // the estimate pointers go to the device through a small kernel argument
   // copy, so the call stays capturable (no host-to-device memcpy)
   EstPtrs ep;
@@ -1233,8 +1238,14 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
     if (plan.max_lists >= 2) {
       {
         TimedLaunch tl("k_listcount_reg", st);
-        hipLaunchKernelGGL(k_listcount_reg<4>, dim3(reg_waves), dim3(kWave), sums_bytes(1, nd, nm),
-                           st, A);
+        // lists of up to 128 entries (two chunks per lane, fewer registers)
+        // or up to 256 (four)
+        if (tune.reg_list_cap <= 2 * kWave)
+          hipLaunchKernelGGL(k_listcount_reg<2>, dim3(reg_waves), dim3(kWave),
+                             sums_bytes(1, nd, nm), st, A);
+        else
+          hipLaunchKernelGGL(k_listcount_reg<4>, dim3(reg_waves), dim3(kWave),
+                             sums_bytes(1, nd, nm), st, A);
       }
       {
         TimedLaunch tl("k_listcount_lds", st);

@@ -66,12 +66,18 @@ def test_batch_equals_single_delta_calls_and_oracle(tcb, tiny):
                               E.est.view(np.uint64))
 
 
-@pytest.mark.parametrize("tuning", [
+TUNINGS = [
     dict(chunk_log2=12, path_blocks=0, reg_waves=5120, fast_waves=5120, wide_blocks=1024),
-    dict(chunk_log2=16, path_blocks=7, reg_waves=64, fast_waves=64, wide_blocks=64),
-    dict(chunk_log2=22, path_blocks=1, reg_waves=100, fast_waves=16384, wide_blocks=2048),
-    dict(chunk_log2=10, path_blocks=3000, reg_waves=1, fast_waves=1, wide_blocks=1),
-])
+    dict(chunk_log2=16, path_blocks=7, reg_waves=64, fast_waves=64, wide_blocks=64,
+         reg_list_cap=128, lds_list_cap=256),
+    dict(chunk_log2=22, path_blocks=1, reg_waves=100, fast_waves=16384, wide_blocks=2048,
+         reg_list_cap=256, lds_list_cap=512),
+    dict(chunk_log2=10, path_blocks=3000, reg_waves=1, fast_waves=1, wide_blocks=1,
+         reg_list_cap=1, lds_list_cap=1),
+]
+
+
+@pytest.mark.parametrize("tuning", TUNINGS)
 def test_batch_results_independent_of_tuning(tcb, tiny, tuning):
     g, G, og, Ws = tiny
     k = 40000
@@ -80,6 +86,46 @@ def test_batch_results_independent_of_tuning(tcb, tiny, tuning):
                                 tuning=tcb.make_tuning(**tuning))
     for a, b in zip(ref, got):
         same_result(a, b)
+
+
+@pytest.fixture(scope="module")
+def mid_lists(tcb, torch_mod):
+    """The spine A->B->C->D (30 x 1 x 30 copies) and list pairs A->D, B->D
+    whose windows hold about 60..800 entries: with the list caps of the
+    tunings above, items move between the register tier (up to 128 or 256
+    entries), the one-wavefront LDS tier (up to 256..1024) and the merged
+    block-per-item tier."""
+    rng = np.random.default_rng(77)
+    A_, B_, C_, D_ = 0, 1, 2, 3
+    src = [A_] * 30 + [B_] + [C_] * 30
+    dst = [B_] * 30 + [C_] + [D_] * 30
+    t = list(range(1, 31)) + [40] + list(range(41, 71))
+    n_ad, n_bd, span = 1200, 500, 3000
+    src += [A_] * n_ad + [B_] * n_bd
+    dst += [D_] * (n_ad + n_bd)
+    t += (100 + rng.integers(0, span, size=n_ad + n_bd)).tolist()
+    g = sg.TemporalGraph(4, np.array(src, np.int32), np.array(dst, np.int32),
+                         np.array(t, np.int64))
+    G, og = build_both(tcb, torch_mod, g)
+    motif = [(A_, B_), (B_, C_), (C_, D_), (A_, D_), (B_, D_), (A_, D_)]
+    Ws = [tcb.tc_path_weights(G, d) for d in (400, 1000, 2500)]
+    return G, og, [motif, motif[:5], motif[:4]], Ws
+
+
+@pytest.mark.parametrize("tuning", TUNINGS)
+def test_list_caps_route_items_without_changing_results(tcb, mid_lists, tuning):
+    G, og, motifs, Ws = mid_lists
+    k = 6000
+    got = tcb.tc_batch_estimate(G, Ws, motifs, k, 13, per_sample=True,
+                                tuning=tcb.make_tuning(**tuning))
+    for d, W in enumerate(Ws):
+        ref = tcb.tc_sample_estimate(G, W, motifs, k, 13, per_sample=True)
+        same_result(got[d], ref)
+    # and the default launch shape against the oracle, at the widest delta
+    mb = [sg.motif_bytes(M) for M in motifs]
+    E = og.sample(og.weights(2500), mb, k, 13, per_sample=True)
+    assert got[2].counts() == E.cnt
+    assert np.array_equal(_u64(got[2].X), E.X)
 
 
 def test_batch_max_deltas_and_subsets(tcb, tiny):
