@@ -110,6 +110,7 @@ struct SampleArgs {
   uint64_t* fast_p;  // [fast waves][2][kKeyCap + 1]
   uint64_t* wide_p;  // [wide blocks][2][kWideCap + 1]
   uint32_t lds_cap;  // longest list of the LDS-key pass (at most kKeyCap)
+  struct SpreadSums* spread;  // [kSpread][nd][n_motifs]
   MotifPlan plan;
 };
 
@@ -232,7 +233,22 @@ __device__ __forceinline__ double square_term(uint64_t X, uint32_t hp) {
   return __dmul_rn(v, v);
 }
 
-// after a barrier: thread (d, j) adds the slots of all wavefronts to the outputs
+// Blocks add their sums into one of kSpread copies of the (delta, motif)
+// totals (copy blockIdx mod kSpread), so that thousands of blocks do not
+// serialise on the same few words in L2; k_finalize reduces the copies in
+// a fixed order.
+constexpr int kSpread = 64;
+struct SpreadSums {
+  uint64_t lo, hi, hits;
+  double m2;
+};
+
+__device__ __forceinline__ SpreadSums* spread_slot(const SampleArgs& A, int s, int d, int j) {
+  return &A.spread[(s * A.nd + d) * A.plan.n_motifs + j];
+}
+
+// after a barrier: thread (d, j) adds the slots of all wavefronts to the
+// block's copy of the totals
 template <int NW>
 __device__ void sums_flush(const SampleArgs& A) {
   const int nm = A.plan.n_motifs;
@@ -249,20 +265,19 @@ __device__ void sums_flush(const SampleArgs& A) {
       sq += p->m2;
       if (p->ovf) ovf = true;
     }
-    uint64_t* cnt = A.D[d].cnt;
+    SpreadSums* t = spread_slot(A, (int)(blockIdx.x % kSpread), d, j);
     if (sum.lo | sum.hi) {
-      const uint64_t old = atomicAdd((unsigned long long*)&cnt[2 * j], (unsigned long long)sum.lo);
+      const uint64_t old = atomicAdd((unsigned long long*)&t->lo, (unsigned long long)sum.lo);
       const uint64_t carry = (old + sum.lo < old) ? 1ull : 0ull;
       const uint64_t add_hi = sum.hi + carry;
       if (add_hi < sum.hi) ovf = true;
       if (add_hi) {
-        const uint64_t old_hi =
-            atomicAdd((unsigned long long*)&cnt[2 * j + 1], (unsigned long long)add_hi);
+        const uint64_t old_hi = atomicAdd((unsigned long long*)&t->hi, (unsigned long long)add_hi);
         if (old_hi + add_hi < old_hi) ovf = true;
       }
     }
-    if (h) atomicAdd((unsigned long long*)&A.D[d].hits[j], (unsigned long long)h);
-    if (A.D[d].m2 && sq != 0.0) atomicAdd(&A.D[d].m2[j], sq);
+    if (h) atomicAdd((unsigned long long*)&t->hits, (unsigned long long)h);
+    if (A.D[d].m2 && sq != 0.0) atomicAdd(&t->m2, sq);
     if (ovf) atomicOr(A.D[d].status, TC_F_OVERFLOW | TC_F_MOTIF(j));
   }
 }
@@ -663,6 +678,41 @@ __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A) {
       uint64_t bound;
       const bool exact64 = !sat && !__builtin_mul_overflow((uint64_t)len, t_prev, &bound);
       uint64_t Pn[CH];
+      if (exact64 && bound < (1ull << 32)) {
+        // Every prefix of the previous level is at most T_{r-1} and every
+        // prefix of this one at most |L_r| T_{r-1} < 2^32: the level runs in
+        // 32 bits (one lane exchange per gathered value, a 32-bit scan).
+        uint32_t carry32 = 0;
+#pragma unroll
+        for (int h = 0; h < CH; ++h) {
+          Pn[h] = 0;
+          if ((uint32_t)h < nch) {  // uniform over the wavefront
+            const uint32_t i = h * kWave + lane;
+            const bool act = i < len;
+            uint32_t pos = 0;
+            if (act) pos = lower_bound<uint32_t>(kprev, 0u, prev_len, kcur[i]);
+            const uint32_t q = pos - 1;
+            const int src = (int)(q & 63u);
+            const uint32_t hsrc = q >> 6;
+            uint32_t c = 0;
+#pragma unroll
+            for (int g = 0; g < CH; ++g) {
+              if ((uint32_t)g < pch) {
+                const uint32_t v32 = (uint32_t)__shfl((uint32_t)P[g], src, kWave);
+                if (hsrc == (uint32_t)g) c = v32;
+              }
+            }
+            if (!act || pos == 0) c = 0;
+            const uint32_t inc = scan_dpp(c);
+            Pn[h] = (uint64_t)(carry32 + inc);
+            carry32 += lane_u32(inc, kWave - 1);
+          }
+        }
+        t_prev = carry32;
+#pragma unroll
+        for (int h = 0; h < CH; ++h) P[h] = Pn[h];
+        continue;
+      }
       uint64_t carry = 0;
       U128 total{0, 0};
 #pragma unroll
@@ -1030,6 +1080,8 @@ __global__ __launch_bounds__(kSBlock) void k_listcount_big(SampleArgs A) {
 
 __global__ void k_zero_result(SampleArgs A) {
   const int nm = A.plan.n_motifs;
+  for (int i = threadIdx.x; i < kSpread * A.nd * nm; i += blockDim.x)
+    A.spread[i] = SpreadSums{0, 0, 0, 0.0};
   for (int i = threadIdx.x; i < A.nd * nm; i += blockDim.x) {
     const int d = i / nm, j = i - d * nm;
     A.D[d].cnt[2 * j] = 0;
@@ -1056,14 +1108,36 @@ __global__ void k_zero_counters(uint32_t* p) {
 
 // C_hat = (cnt / k) * W, each integer rounded to nearest-even binary64; with
 // a proposal, C_hat = ((cnt * 2^-64) / k) * Q
-__global__ void k_finalize(SampleArgs A, double* const* est) {
+// One wavefront per (delta, motif): lane s holds copy s of the totals, and
+// fixed-order wavefront sums give cnt (128-bit, with overflow), hits and m2.
+__global__ __launch_bounds__(1024) void k_finalize(SampleArgs A, double* const* est) {
   const int nm = A.plan.n_motifs;
-  for (int i = threadIdx.x; i < A.nd * nm; i += blockDim.x) {
+  const int lane = threadIdx.x & 63, wave = (int)uni(threadIdx.x >> 6);
+  static_assert(kSpread == kWave, "one lane per copy of the totals");
+  for (int i = wave; i < A.nd * nm; i += (int)(blockDim.x >> 6)) {  // uniform per wavefront
     const int d = i / nm, j = i - d * nm;
-    const uint64_t W = A.D[d].S[A.m];
-    double c = u128_to_double(A.D[d].cnt[2 * j], A.D[d].cnt[2 * j + 1]);
-    if (A.D[d].h) c = ldexp(c, -64);
-    est[d][j] = (W == 0) ? 0.0 : __dmul_rn(__ddiv_rn(c, (double)A.k), (double)W);
+    const SpreadSums v = *spread_slot(A, lane, d, j);
+    bool ovf = false;
+    const U128 c128 = wave_sum128c(U128{v.lo, v.hi}, &ovf);
+    ovf = __ballot(ovf) != 0;  // a carry seen on any lane's path
+    uint64_t h = v.hits;
+    double sq = v.m2;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      h += __shfl_xor(h, off, kWave);
+      sq += __shfl_xor(sq, off, kWave);
+    }
+    if (lane == 0) {
+      A.D[d].cnt[2 * j] = c128.lo;
+      A.D[d].cnt[2 * j + 1] = c128.hi;
+      A.D[d].hits[j] = h;
+      if (A.D[d].m2) A.D[d].m2[j] = sq;
+      if (ovf) atomicOr(A.D[d].status, TC_F_OVERFLOW | TC_F_MOTIF(j));
+      const uint64_t W = A.D[d].S[A.m];
+      double c = u128_to_double(c128.lo, c128.hi);
+      if (A.D[d].h) c = ldexp(c, -64);
+      est[d][j] = (W == 0) ? 0.0 : __dmul_rn(__ddiv_rn(c, (double)A.k), (double)W);
+    }
   }
   __syncthreads();
   if ((int)threadIdx.x < A.nd && *A.D[threadIdx.x].wstatus)
@@ -1102,7 +1176,8 @@ static int wide_blocks_for(const SampleTuning& t) {
 }
 
 struct SampleLayout {
-  size_t win_lo, win_len, code, mid, wide, big, counters, fast_p, wide_p, est_ptrs, samp_h, total;
+  size_t win_lo, win_len, code, mid, wide, big, counters, fast_p, wide_p, est_ptrs, samp_h, spread,
+      total;
   uint64_t chunk, cap;
   int fast_waves, wide_blocks;
 };
@@ -1130,6 +1205,7 @@ static SampleLayout sample_layout(uint64_t k, int nd, int32_t n_motifs, const Sa
   L.wide_p = take((size_t)L.wide_blocks * 2 * (kWideCap + 1) * 8);
   L.est_ptrs = take(kMaxDeltas * sizeof(double*));
   L.samp_h = take((size_t)nd * L.chunk * 4);
+  L.spread = take((size_t)kSpread * nd * n_motifs * sizeof(SpreadSums));
   L.total = o;
   return L;
 }
@@ -1209,6 +1285,7 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
   A.fast_p = (uint64_t*)(base + L.fast_p);
   A.samp_h = (uint32_t*)(base + L.samp_h);
   A.wide_p = (uint64_t*)(base + L.wide_p);
+  A.spread = (SpreadSums*)(base + L.spread);
   A.plan = plan;
   A.lds_cap = (uint32_t)(tune.lds_list_cap < kWave ? kWave
                          : (tune.lds_list_cap > kKeyCap ? kKeyCap : tune.lds_list_cap));
@@ -1218,7 +1295,7 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
   for (int d = 0; d < kMaxDeltas; ++d) ep.p[d] = est_host[d];
   double** est_dev = (double**)(base + L.est_ptrs);
   hipLaunchKernelGGL(k_store_ptrs, dim3(1), dim3(kMaxDeltas), 0, st, ep, est_dev);
-  hipLaunchKernelGGL(k_zero_result, dim3(1), dim3(128), 0, st, A);
+  hipLaunchKernelGGL(k_zero_result, dim3(1), dim3(1024), 0, st, A);
   const int nm = plan.n_motifs;
   const unsigned reg_waves = (unsigned)(tune.reg_waves < 64 ? 64 : tune.reg_waves);
   for (uint64_t c0 = 0; c0 < k; c0 += L.chunk) {
@@ -1264,7 +1341,7 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
       }
     }
   }
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(128), 0, st, A, (double* const*)est_dev);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, A, (double* const*)est_dev);
   if (hipGetLastError() != hipSuccess) return TC_E_HIP;
   return TC_OK;
 }
