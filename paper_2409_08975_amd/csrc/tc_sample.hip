@@ -591,6 +591,31 @@ __device__ uint64_t sweep(const int64_t* __restrict__ pair_t, uint32_t (&ptr)[ML
   return X;
 }
 
+// Items a one-wavefront pass hands on to a later pass.  Lane i holds the
+// i-th, and they are queued with one reservation per 64 items (or at the end
+// of the pass), instead of one atomic per item on the shared counter.  Call
+// with the whole wavefront active; n is uniform.
+struct FwdBuf {
+  uint32_t code;  // this lane's held item
+  uint32_t n;     // items held
+};
+
+__device__ __forceinline__ void fwd_flush(FwdBuf& f, uint32_t* count, uint32_t* queue) {
+  if (f.n == 0) return;
+  const int lane = threadIdx.x & 63;
+  uint32_t base = 0;
+  if (lane == 0) base = atomicAdd(count, f.n);
+  base = (uint32_t)__builtin_amdgcn_readfirstlane(base);
+  if ((uint32_t)lane < f.n) queue[base + lane] = f.code;
+  f.n = 0;
+}
+
+__device__ __forceinline__ void fwd_push(FwdBuf& f, uint32_t code, uint32_t* count,
+                                         uint32_t* queue) {
+  if ((uint32_t)(threadIdx.x & 63) == f.n) f.code = code;
+  if (++f.n == (uint32_t)kWave) fwd_flush(f, count, queue);
+}
+
 // record one item's count (lane 0 of a one-wavefront block)
 __device__ __forceinline__ void item_done(const SampleArgs& A, int d, int j, uint32_t li,
                                           uint64_t X) {
@@ -616,6 +641,7 @@ __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A) {
   __shared__ uint32_t s_key[kRegKeys];
   const int lane = threadIdx.x;
   sums_clear<1>(A);
+  FwdBuf fb{0u, 0u};  // items for the LDS-key pass
 
   const uint32_t n_items = *A.item_count;
   for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -647,7 +673,7 @@ __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A) {
     const uint32_t total_keys = lane_u32(incl, kWave - 1);
     if (maxlen > (uint32_t)(kWave * CH) || total_keys > (uint32_t)kRegKeys ||
         A.D[d].delta >= ((int64_t)1 << 32)) {
-      if (lane == 0) A.mid_code[atomicAdd(A.mid_count, 1u)] = code;
+      fwd_push(fb, code, A.mid_count, A.mid_code);
       continue;
     }
     for (int r = 0; r < l; ++r) {
@@ -756,6 +782,7 @@ __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A) {
     if (lane == 0) item_done(A, d, j, li, t_prev);
     __threadfence_block();
   }
+  fwd_flush(fb, A.mid_count, A.mid_code);
   __syncthreads();
   sums_flush<1>(A);
 }
@@ -771,6 +798,7 @@ __global__ __launch_bounds__(kWave) void k_listcount_lds(SampleArgs A, uint64_t*
                       pscratch + ((uint64_t)blockIdx.x * 2 + 1) * (kKeyCap + 1)};
   const int lane = threadIdx.x;
   sums_clear<1>(A);
+  FwdBuf fb{0u, 0u};  // items for the merged pass
   const uint32_t n_items = *A.mid_count;
   // items are dealt round robin (the loop index is uniform over the
   // wavefront; no shared counter is contended)
@@ -837,13 +865,12 @@ __global__ __launch_bounds__(kWave) void k_listcount_lds(SampleArgs A, uint64_t*
         __threadfence_block();
       }
     }
-    if (lane == 0) {
-      if (fwd)
-        A.wide_code[atomicAdd(A.wide_count, 1u)] = code;
-      else
-        item_done(A, d, j, li, total.lo);
-    }
+    if (fwd)
+      fwd_push(fb, code, A.wide_count, A.wide_code);
+    else if (lane == 0)
+      item_done(A, d, j, li, total.lo);
   }
+  fwd_flush(fb, A.wide_count, A.wide_code);
   __syncthreads();
   sums_flush<1>(A);
 }
