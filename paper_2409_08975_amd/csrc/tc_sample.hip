@@ -82,6 +82,11 @@ struct SampleArgs {
   int64_t m;
   uint64_t tree_off[kMaxTreeLevels];
   int32_t tree_levels;
+  // the top levels of every delta's tree (levels tree_cache_lo..tree_levels,
+  // the last tree_cache_words words of the tree) are searched from LDS
+  int32_t tree_cache_lo;
+  uint32_t tree_cache_words;
+  uint64_t tree_cache_base;  // word offset of level tree_cache_lo
   // deltas
   int32_t nd;
   DeltaArgs D[kMaxDeltas];
@@ -143,10 +148,18 @@ __device__ __forceinline__ int32_t slot_vertex(int s, int32_t x, int32_t u, int3
 // upper_bound(S, r) - 1 through the 16-ary tree: one 128-byte node per
 // level, bisected (four 8-byte probes inside one cache line rather than the
 // whole node, which keeps the vector-memory traffic of a lane per level low)
+// s_tree holds the cached top levels of D's tree (see SampleArgs)
 __device__ __forceinline__ uint32_t tree_search(const SampleArgs& A, const DeltaArgs& D,
-                                                uint64_t r) {
+                                                const uint64_t* s_tree, uint64_t r) {
   uint64_t i = 0;
-  for (int L = A.tree_levels; L >= 0; --L) {
+  int L = A.tree_levels;
+  for (; L >= 1 && L >= A.tree_cache_lo; --L) {  // uniform bounds
+    const uint64_t* lvl = s_tree + (A.tree_off[L] - A.tree_cache_base);
+    const uint64_t node = (L == A.tree_levels) ? 0 : i;
+    const uint32_t cnt = upper_bound<uint64_t>(lvl + 16 * node, 0u, 16u, r);  // entries <= r
+    i = 16 * node + cnt - 1;
+  }
+  for (; L >= 0; --L) {
     const uint64_t* lvl = (L == 0) ? D.S : D.tree + A.tree_off[L];
     const uint64_t node = (L == A.tree_levels) ? 0 : i;
     const uint32_t cnt = upper_bound<uint64_t>(lvl + 16 * node, 0u, 16u, r);  // entries <= r
@@ -287,6 +300,13 @@ __device__ __forceinline__ void flag_status(const SampleArgs& A, int d, uint32_t
 }
 
 // ---- paths ------------------------------------------------------------------
+// Words of the search tree's top levels kept in LDS by the path kernel (the
+// levels above the first one that would not fit; 16 + 32 + 320 words for
+// m = 2*10^7), and their place after the gate window lengths.
+constexpr int kTreeCache = 384;
+__host__ __device__ inline size_t tree_cache_at(int n_gates) {
+  return ((size_t)n_gates * kSBlock * 4 + 15) & ~(size_t)15;
+}
 struct PathRec {
   int32_t x, u, v, y;
   int64_t t1, t3;
@@ -311,6 +331,10 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
   // dynamic LDS (sized for the plan's gates only)
   uint32_t* s_glen = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(s_dyn_sums) +
                                                  sums_bytes(kSWaves, A.nd, nm));
+  // then the cached top levels of the current delta's tree
+  uint64_t* s_tree = reinterpret_cast<uint64_t*>(
+      reinterpret_cast<char*>(s_glen) + tree_cache_at(A.plan.n_gates));
+  int cached_d = -1;
   sums_clear<kSWaves>(A);
   const uint32_t n_units = A.tiles_per_delta * (uint32_t)A.nd;
   for (uint32_t unit = blockIdx.x; unit < n_units; unit += gridDim.x) {
@@ -320,6 +344,11 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
     const uint64_t W = D.S[A.m];
     __syncthreads();  // the previous unit's LDS use is over
     if (tid == 0) s_nvalid = 0;
+    if (d != cached_d) {  // uniform over the block
+      for (uint32_t k = tid; k < A.tree_cache_words; k += kSBlock)
+        s_tree[k] = D.tree[A.tree_cache_base + k];
+      cached_d = d;
+    }
     __syncthreads();
     uint32_t st_bits = 0;
     const uint32_t li = tile * kSBlock + tid;  // sample index inside the chunk
@@ -352,7 +381,7 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
           st_bits |= TC_F_RNG;
           r = 0;
         }
-        const uint32_t p = tree_search(A, D, r);  // S[p] <= r < S[p+1]
+        const uint32_t p = tree_search(A, D, s_tree, r);  // S[p] <= r < S[p+1]
         const uint4 pr0 = D.prec[2 * (uint64_t)p], pr1 = D.prec[2 * (uint64_t)p + 1];
         const uint32_t ap = pr0.y, bp = pr0.w;
         uint32_t j1, j3;
@@ -1268,6 +1297,16 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
     const STree T = stree_layout(g->m);
     A.tree_levels = T.levels;
     for (int L2 = 0; L2 < kMaxTreeLevels; ++L2) A.tree_off[L2] = L2 <= T.levels ? T.offset[L2] : 0;
+    // the lowest level whose tail of the tree still fits the LDS cache
+    A.tree_cache_lo = T.levels + 1;  // none
+    A.tree_cache_base = T.total_words;
+    A.tree_cache_words = 0;
+    for (int L2 = T.levels; L2 >= 1; --L2) {
+      if (T.total_words - T.offset[L2] > (size_t)kTreeCache) break;
+      A.tree_cache_lo = L2;
+      A.tree_cache_base = T.offset[L2];
+      A.tree_cache_words = (uint32_t)(T.total_words - T.offset[L2]);
+    }
   }
   A.nd = nd;
   double* est_host[kMaxDeltas] = {};
@@ -1337,7 +1376,9 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
     {
       TimedLaunch tl("k_paths", st);
       hipLaunchKernelGGL(k_paths, dim3(pblocks), dim3(kSBlock),
-                         sums_bytes(kSWaves, nd, nm) + (size_t)plan.n_gates * kSBlock * 4, st, A);
+                         sums_bytes(kSWaves, nd, nm) + tree_cache_at(plan.n_gates) +
+                             (size_t)kTreeCache * 8,
+                         st, A);
     }
     if (plan.max_lists >= 2) {
       {
