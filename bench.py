@@ -437,6 +437,13 @@ def main():
                 "traffic": d.get("hbm_bytes_per_launch"), "kernel": dom,
                 "ms_per_launch": round(d["ms_per_launch"], 4),
                 "alg_bytes_per_unit": d.get("alg_bytes_per_unit")}
+    if roofline["traffic"]:
+        # the HBM bytes the kernel actually moves (counters) over the live
+        # launch time: how busy the memory system is, beside the algorithmic
+        # fraction above
+        tgbs = roofline["traffic"] / (d["ms_per_launch"] * 1e-3) / 1e9
+        roofline["traffic_GBs"] = round(tgbs, 1)
+        roofline["traffic_frac"] = round(tgbs / HBM_PEAK_GBS, 4)
     log(f"[bench] kernels: " + ", ".join(f"{k_}={v['ms_per_step']:.3f}ms" for k_, v in kernels.items()))
 
     out = {
