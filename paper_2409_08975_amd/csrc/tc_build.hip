@@ -137,6 +137,16 @@ __device__ __forceinline__ uint4 rec_xform(const uint4& r, int xf) {
   return r;
 }
 
+// The input edge columns, read directly by the first pass of the time sort
+// (which builds each record (t - t_min, eid, src, dst) as it loads it);
+// t == nullptr for every other pass.
+struct EdgeCols {
+  const int32_t* src;
+  const int32_t* dst;
+  const int64_t* t;
+  int64_t tmin;
+};
+
 // the re-keying of a sort with no pass (a key of zero bits), in place:
 // every element is read and written by the same thread
 __global__ __launch_bounds__(256) void k_rec_xform(uint4* __restrict__ a, int64_t m,
@@ -154,7 +164,8 @@ template <typename K, int ITEMS>
 __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__ keys, int64_t m,
                                                            int shift, uint32_t mask,
                                                            uint32_t* __restrict__ hist,
-                                                           const uint32_t* __restrict__ dev_m) {
+                                                           const uint32_t* __restrict__ dev_m,
+                                                           EdgeCols ec) {
   __shared__ uint32_t s_h[256];
   if (dev_m) m = (int64_t)*dev_m < m ? (int64_t)*dev_m : m;
   s_h[threadIdx.x] = 0;
@@ -163,7 +174,10 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
     int64_t i = start + (int64_t)r * kSortBlock + threadIdx.x;
-    if (i < m) atomicAdd(&s_h[(uint32_t)(sort_key(keys[i]) >> shift) & mask], 1u);
+    if (i < m) {
+      const uint64_t key = ec.t ? (uint64_t)(ec.t[i] - ec.tmin) : (uint64_t)sort_key(keys[i]);
+      atomicAdd(&s_h[(uint32_t)(key >> shift) & mask], 1u);
+    }
   }
   __syncthreads();
   hist[(int64_t)blockIdx.x * 256 + threadIdx.x] = s_h[threadIdx.x];
@@ -265,7 +279,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
                                                               const uint32_t* __restrict__ hist,
                                                               const uint32_t* __restrict__ dev_m,
                                                               int xf1, K* __restrict__ kout2,
-                                                              int xf2) {
+                                                              int xf2, EdgeCols ec) {
   // Each wavefront owns a contiguous quarter of the tile and ranks its keys
   // in order with ballots (no block barrier inside); one block-wide pass then
   // offsets every wavefront's digit counts by those of the wavefronts before
@@ -309,7 +323,18 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
   for (int r = 0; r < ITEMS; ++r) {
     const int idx = wave * kSub + r * kWave + lane;
     const bool valid = idx < len;
-    key[r] = valid ? kin[start + idx] : K{};
+    if constexpr (std::is_same<K, uint4>::value) {
+      if (ec.t) {  // uniform: the first pass of the time sort builds the records
+        const int64_t g = start + idx;
+        key[r] = valid ? make_uint4((uint32_t)(ec.t[g] - ec.tmin), (uint32_t)g,
+                                    (uint32_t)ec.src[g], (uint32_t)ec.dst[g])
+                       : K{};
+      } else {
+        key[r] = valid ? kin[start + idx] : K{};
+      }
+    } else {
+      key[r] = valid ? kin[start + idx] : K{};
+    }
     if constexpr (kHasVal) {
       if (valid) val[r] = vin[start + idx];
     }
@@ -385,7 +410,7 @@ template <typename K, typename V = int32_t, int ITEMS = kSortItems>
 int radix_sort(K* k0, V* v0, K* k1, V* v1, int64_t m, int bits, uint32_t* hist,
                uint32_t* part, size_t part_elems, hipStream_t st,
                const uint32_t* dev_m = nullptr, int xf1 = RX_NONE, K* extra = nullptr,
-               int xf2 = RX_NONE) {
+               int xf2 = RX_NONE, const EdgeCols* first = nullptr) {
   if (m <= 0) return 0;
   constexpr int kTile = kSortBlock * ITEMS;
   const int64_t ntiles = (m + kTile - 1) / kTile;
@@ -408,15 +433,17 @@ int radix_sort(K* k0, V* v0, K* k1, V* v1, int64_t m, int bits, uint32_t* hist,
     V* vi = cur ? v1 : v0;
     K* ko = cur ? k0 : k1;
     V* vo = cur ? v0 : v1;
+    // with `first`, pass 0 reads the edge columns instead of k0 (K = uint4)
+    const EdgeCols ec = (p == 0 && first) ? *first : EdgeCols{nullptr, nullptr, nullptr, 0};
     hipLaunchKernelGGL((k_radix_hist<K, ITEMS>), dim3((unsigned)ntiles), dim3(kSortBlock), 0, st,
-                       (const K*)ki, m, shift, mask, hist, dev_m);
+                       (const K*)ki, m, shift, mask, hist, dev_m, ec);
     col_scan(hist, ntiles, part, st);
     {
       TimedLaunch tl("k_radix_scatter", st);
       hipLaunchKernelGGL((k_radix_scatter<K, V, ITEMS>), dim3((unsigned)ntiles), dim3(kSortBlock),
                          0, st, (const K*)ki, (const V*)vi, ko, vo, m, shift, dbits,
                          (const uint32_t*)hist, dev_m, last ? xf1 : (int)RX_NONE,
-                         last ? extra : (K*)nullptr, last ? xf2 : (int)RX_NONE);
+                         last ? extra : (K*)nullptr, last ? xf2 : (int)RX_NONE, ec);
     }
     cur ^= 1;
     shift += dbits;
@@ -781,10 +808,11 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     uint32_t* hist2 = (uint32_t*)(base + L.hist2);
     uint32_t* part2 = (uint32_t*)(base + L.part2);
     auto sort_rec = [&](int from, int tmp, int bits, uint32_t* h, uint32_t* pt, hipStream_t s,
-                        int xf1 = RX_NONE, int extra = -1, int xf2 = RX_NONE) -> int {
+                        int xf1 = RX_NONE, int extra = -1, int xf2 = RX_NONE,
+                        const EdgeCols* first = nullptr) -> int {
       const int w = radix_sort<uint4, NoVal, kRecItems>(
           rr[from], (NoVal*)nullptr, rr[tmp], (NoVal*)nullptr, m, bits, h, pt, pe, s, nullptr,
-          xf1, extra < 0 ? (uint4*)nullptr : rr[extra], xf2);
+          xf1, extra < 0 ? (uint4*)nullptr : rr[extra], xf2, first);
       return w < 0 ? -1 : (w ? tmp : from);
     };
     SideStream* S = side_stream();
@@ -792,10 +820,14 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     if (S) lock = std::unique_lock<std::mutex>(S->mu);
     const bool two = S && side_ready(S);
     hipStream_t s2 = two ? S->s : st;
-    hipLaunchKernelGGL(k_rec_init, dim3(eb), dim3(256), 0, st, src, dst, t, m, tmin, rr[0]);
-    // time order; its last pass leaves the records re-keyed as the input of
-    // the out-CSR sort (buffer A, the sort's own) and of the in-CSR sort (B)
-    const int A = sort_rec(0, 1, tbits, hist, part, st, RX_OUT, 2, RX_IN);
+    // time order.  Its first pass reads the edge columns and builds the
+    // records as it loads them (with no pass, k_rec_init builds them); its
+    // last pass leaves them re-keyed as the input of the out-CSR sort
+    // (buffer A, the sort's own) and of the in-CSR sort (B)
+    const EdgeCols ec{src, dst, t, tmin};
+    if (tbits == 0)
+      hipLaunchKernelGGL(k_rec_init, dim3(eb), dim3(256), 0, st, src, dst, t, m, tmin, rr[0]);
+    const int A = sort_rec(0, 1, tbits, hist, part, st, RX_OUT, 2, RX_IN, tbits ? &ec : nullptr);
     if (A < 0) return TC_E_WORKSPACE;
     const int B = 2, F = 1 - A;
     // in-CSR: stable by dst; a second copy of the result, re-keyed, is the
