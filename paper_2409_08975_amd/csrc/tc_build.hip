@@ -50,15 +50,28 @@ __global__ __launch_bounds__(256) void k_validate(const int32_t* __restrict__ sr
   const int64_t lim = (int64_t)1 << 62;
   uint64_t mn = ~0ull, mx = 0;
   uint32_t bad = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    int32_t s = src[i], d = dst[i];
-    int64_t tt = t[i];
+  auto check = [&](int32_t s, int32_t d, int64_t tt) {
     if (s < 0 || s >= n || d < 0 || d >= n || tt >= lim || tt <= -lim) bad = 1;
-    uint64_t key = (uint64_t)tt ^ (1ull << 63);
+    const uint64_t key = (uint64_t)tt ^ (1ull << 63);
     mn = key < mn ? key : mn;
     mx = key > mx ? key : mx;
+  };
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // four edges per step, their loads issued together (all in bounds)
+  for (; i + 3 * stride < m; i += 4 * stride) {
+    int32_t sv[4], dv[4];
+    int64_t tv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      sv[u] = src[i + u * stride];
+      dv[u] = dst[i + u * stride];
+      tv[u] = t[i + u * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) check(sv[u], dv[u], tv[u]);
   }
+  for (; i < m; i += stride) check(src[i], dst[i], t[i]);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     uint64_t a = __shfl_xor(mn, off, kWave);
@@ -769,6 +782,12 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     hipLaunchKernelGGL(k_validate, dim3(vb), dim3(256), 0, st, src, dst, t, m, n, g->status,
                        tminmax);
   }
+  // the run table is cleared while the host waits for the validation below
+  {
+    const int64_t cap = (int64_t)1 << g->pair_hash_log2;
+    hipLaunchKernelGGL(k_hash_clear, dim3(blocks_for(cap, 256)), dim3(256), 0, st,
+                       (PairSlot*)g->pair_hash, cap);
+  }
   uint32_t h_status = 0;
   uint64_t h_mm[2] = {0, 0};
   if (hipMemcpyAsync(&h_status, g->status, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -784,9 +803,7 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
 
   const int tbits = bitlen((uint64_t)(tmax - tmin));
   const int vbits = bitlen((uint64_t)(n - 1));
-  const int64_t cap = (int64_t)1 << g->pair_hash_log2;
   PairSlot* tab = (PairSlot*)g->pair_hash;
-  hipLaunchKernelGGL(k_hash_clear, dim3(blocks_for(cap, 256)), dim3(256), 0, st, tab, cap);
   if (m == 0) {
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for((int64_t)n + 1, 256)), dim3(256), 0, st,
                        g->out_off, (int64_t)n + 1, 0u);
