@@ -8,7 +8,7 @@
 // lo_in[p] + a[p] = #{in-CSR entries <= (u, t)}; the in-CSR order q is sorted
 // by (v, t), so v's out-window bounds are ranks of (v, t) and (v, t + delta)
 // in the out-CSR.  Each rank sequence is one merge-path pass:
-//   k_mp_split    splits the merged sequence (queries + data) into tiles of
+//   k_mp_split4   splits the merged sequence (queries + data) into tiles of
 //                 kMPTile entries by a binary search on each tile diagonal,
 //   k_mp_rank     stages the tile's data keys in LDS and ranks each of the
 //                 tile's queries there,
@@ -48,10 +48,22 @@ __device__ __forceinline__ bool before(int32_t dv, int64_t dt, int32_t qv, int64
 
 // split[b] = number of queries among the first min(b * kMPTile, nq + nd)
 // entries of the merge (a query is taken first unless a data entry is ranked
-// before it)
-template <bool UPPER>
-__global__ __launch_bounds__(256) void k_mp_split(KeyCols Q, int64_t nq, KeyCols D, int64_t nd,
-                                                  int64_t nsplit, uint32_t* __restrict__ split) {
+// before it), by a bisection on the diagonal.
+// The four splits of the weights (two per window side) in one launch:
+// blockIdx.y picks the job.  Each diagonal's search is a short serial chain,
+// so one job alone leaves the GPU mostly idle.
+struct SplitJob {
+  KeyCols Q, D;
+  uint32_t* split;
+  int32_t upper;
+};
+struct SplitJobs {
+  SplitJob j[4];
+};
+
+__global__ __launch_bounds__(256) void k_mp_split4(SplitJobs J, int64_t nq, int64_t nd,
+                                                   int64_t nsplit) {
+  const SplitJob& S = J.j[blockIdx.y];
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nsplit) return;
   const int64_t d = b * kMPTile < nq + nd ? b * kMPTile : nq + nd;
@@ -60,12 +72,16 @@ __global__ __launch_bounds__(256) void k_mp_split(KeyCols Q, int64_t nq, KeyCols
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
     const int64_t j = d - mid - 1;
-    if (!before<UPPER>(D.v[j], D.t[j] + D.shift, Q.v[mid], Q.t[mid] + Q.shift))
+    const bool bef = S.upper ? before<true>(S.D.v[j], S.D.t[j] + S.D.shift, S.Q.v[mid],
+                                            S.Q.t[mid] + S.Q.shift)
+                             : before<false>(S.D.v[j], S.D.t[j] + S.D.shift, S.Q.v[mid],
+                                             S.Q.t[mid] + S.Q.shift);
+    if (!bef)
       lo = mid + 1;
     else
       hi = mid;
   }
-  split[b] = (uint32_t)lo;
+  S.split[b] = (uint32_t)lo;
 }
 
 // rank of every query of the tile: out[i] = rank, or with `sub`
@@ -374,7 +390,7 @@ static WeightsLayout weights_layout(int64_t m) {
   L.tile_off = take(ntiles * 8);
   L.lo_out_q = take(M * 4);
   L.win_q = take(M * 8);
-  L.split = take((size_t)((2 * M + kMPTile - 1) / kMPTile + 2) * 4);
+  L.split = take((size_t)4 * ((2 * M + kMPTile - 1) / kMPTile + 2) * 4);  // four jobs
   L.prec = take(M * 32);
   L.total = o;
   return L;
@@ -412,22 +428,25 @@ tc_status path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_byt
     const unsigned rb = (unsigned)(nsplit - 1);
     const KeyCols outk{g->out_src, g->out_t, 0};
     const KeyCols ink{g->in_dst, g->in_t, 0};
-    // u's in-window [t - delta, t] for every out-CSR position p
+    // u's in-window [t - delta, t] for every out-CSR position p, and v's
+    // out-window [t, t + delta] for every in-CSR position q
     const KeyCols q_lo{g->out_src, g->out_t, -delta};
-    hipLaunchKernelGGL(k_mp_split<false>, dim3(sb), dim3(256), 0, st, q_lo, m, ink, m, nsplit, split);
-    hipLaunchKernelGGL(k_mp_rank<false>, dim3(rb), dim3(kMPBlock), 0, st, q_lo, m, ink, m,
-                       (const uint32_t*)split, (const uint32_t*)nullptr, w->lo_in, (uint2*)nullptr);
-    hipLaunchKernelGGL(k_mp_split<true>, dim3(sb), dim3(256), 0, st, outk, m, ink, m, nsplit, split);
-    hipLaunchKernelGGL(k_mp_rank<true>, dim3(rb), dim3(kMPBlock), 0, st, outk, m, ink, m,
-                       (const uint32_t*)split, (const uint32_t*)w->lo_in, w->a, (uint2*)nullptr);
-    // v's out-window [t, t + delta] for every in-CSR position q
-    hipLaunchKernelGGL(k_mp_split<false>, dim3(sb), dim3(256), 0, st, ink, m, outk, m, nsplit, split);
-    hipLaunchKernelGGL(k_mp_rank<false>, dim3(rb), dim3(kMPBlock), 0, st, ink, m, outk, m,
-                       (const uint32_t*)split, (const uint32_t*)nullptr, lo_out_q, (uint2*)nullptr);
     const KeyCols q_hi{g->in_dst, g->in_t, delta};
-    hipLaunchKernelGGL(k_mp_split<true>, dim3(sb), dim3(256), 0, st, q_hi, m, outk, m, nsplit, split);
+    uint32_t* sp[4];
+    for (int c = 0; c < 4; ++c) sp[c] = split + (size_t)c * (size_t)(nsplit + 1);
+    const SplitJobs J{{{q_lo, ink, sp[0], 0}, {outk, ink, sp[1], 1}, {ink, outk, sp[2], 0},
+                       {q_hi, outk, sp[3], 1}}};
+    hipLaunchKernelGGL(k_mp_split4, dim3(sb, 4), dim3(256), 0, st, J, m, m, nsplit);
+    hipLaunchKernelGGL(k_mp_rank<false>, dim3(rb), dim3(kMPBlock), 0, st, q_lo, m, ink, m,
+                       (const uint32_t*)sp[0], (const uint32_t*)nullptr, w->lo_in,
+                       (uint2*)nullptr);
+    hipLaunchKernelGGL(k_mp_rank<true>, dim3(rb), dim3(kMPBlock), 0, st, outk, m, ink, m,
+                       (const uint32_t*)sp[1], (const uint32_t*)w->lo_in, w->a, (uint2*)nullptr);
+    hipLaunchKernelGGL(k_mp_rank<false>, dim3(rb), dim3(kMPBlock), 0, st, ink, m, outk, m,
+                       (const uint32_t*)sp[2], (const uint32_t*)nullptr, lo_out_q,
+                       (uint2*)nullptr);
     hipLaunchKernelGGL(k_mp_rank<true>, dim3(rb), dim3(kMPBlock), 0, st, q_hi, m, outk, m,
-                       (const uint32_t*)split, (const uint32_t*)lo_out_q, (uint32_t*)nullptr,
+                       (const uint32_t*)sp[3], (const uint32_t*)lo_out_q, (uint32_t*)nullptr,
                        win_q);
     hipLaunchKernelGGL(k_combine, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
                        (const uint32_t*)g->out_to_in, (const uint2*)win_q,
