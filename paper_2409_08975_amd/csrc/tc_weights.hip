@@ -174,37 +174,37 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const uint64_t* __restrict_
                                                      int64_t ntiles, uint64_t* __restrict__ tile_off,
                                                      uint64_t* __restrict__ S, int64_t m,
                                                      uint32_t* __restrict__ status) {
+  // Thread t owns the consecutive tiles [t c, (t + 1) c): it sums them with
+  // independent loads, one block scan orders the thread sums, and it writes
+  // its tiles' offsets from its exclusive prefix.
   __shared__ U128 s_w[16];
-  __shared__ U128 s_carry;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (threadIdx.x == 0) s_carry = U128{0, 0};
-  __syncthreads();
-  for (int64_t base = 0; base < ntiles; base += 1024) {
-    const int64_t i = base + threadIdx.x;
-    U128 v = (i < ntiles) ? U128{tile_sums[2 * i], tile_sums[2 * i + 1]} : U128{0, 0};
-    U128 inc = v;
+  const int64_t c = (ntiles + 1023) / 1024;
+  const int64_t b0 = (int64_t)threadIdx.x * c;
+  const int64_t b1 = b0 + c < ntiles ? b0 + c : ntiles;
+  U128 v{0, 0};
+#pragma unroll 8
+  for (int64_t i = b0; i < b1; ++i) v = add128(v, U128{tile_sums[2 * i], tile_sums[2 * i + 1]});
+  U128 inc = v;
 #pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      U128 o{__shfl_up(inc.lo, off, kWave), __shfl_up(inc.hi, off, kWave)};
-      if (lane >= off) inc = add128(inc, o);
-    }
-    if (lane == 63) s_w[wave] = inc;
-    __syncthreads();
-    U128 pre = s_carry;
-    for (int w = 0; w < wave; ++w) pre = add128(pre, s_w[w]);
-    // exclusive = pre + inc - v
-    U128 excl = pre;
-    {
-      U128 d{inc.lo - v.lo, inc.hi - v.hi - (inc.lo < v.lo ? 1ull : 0ull)};
-      excl = add128(excl, d);
-    }
-    if (i < ntiles) tile_off[i] = excl.lo;
-    __syncthreads();
-    if (threadIdx.x == 1023) s_carry = add128(pre, inc);
-    __syncthreads();
+  for (int off = 1; off < kWave; off <<= 1) {
+    U128 o{__shfl_up(inc.lo, off, kWave), __shfl_up(inc.hi, off, kWave)};
+    if (lane >= off) inc = add128(inc, o);
   }
-  if (threadIdx.x == 0) {
-    const U128 W = s_carry;
+  if (lane == 63) s_w[wave] = inc;
+  __syncthreads();
+  U128 run{0, 0};
+  for (int w = 0; w < wave; ++w) run = add128(run, s_w[w]);
+  // exclusive prefix of this thread = waves before + inc - v
+  run = add128(run, U128{inc.lo - v.lo, inc.hi - v.hi - (inc.lo < v.lo ? 1ull : 0ull)});
+#pragma unroll 8
+  for (int64_t i = b0; i < b1; ++i) {
+    tile_off[i] = run.lo;  // modulo 2^64 (only used when W < 2^64)
+    run = add128(run, U128{tile_sums[2 * i], tile_sums[2 * i + 1]});
+  }
+  if (threadIdx.x == 1023) {  // its run ends at the total
+    U128 W{0, 0};
+    for (int w = 0; w < 16; ++w) W = add128(W, s_w[w]);
     S[m] = W.lo;
     *status = (W.hi != 0) ? TC_F_OVERFLOW : 0u;
   }
