@@ -27,7 +27,7 @@ namespace tc {
 constexpr int kSortBlock = 256;
 constexpr uint32_t kXcds = 8;  // accelerator complex dies of an MI355X, each with its own L2
 constexpr int kSortItems = 16;
-constexpr int kRecItems = 8;  // record-carrying sorts: 2048-entry tiles (LDS holds 16 B/entry)
+constexpr int kRecItems = 6;  // record-carrying sorts: 1536-entry tiles (LDS holds 16 B/entry)
 constexpr int kRecTile = kSortBlock * kRecItems;
 constexpr int kColChunk = 32;  // tiles per chunk of the histogram column scan
 
@@ -645,7 +645,7 @@ static GraphLayout graph_layout(int32_t n, int64_t m) {
     return at;
   };
   const size_t M = (size_t)m;
-  // histograms sized for the smaller (2048-entry) tiles of the record sorts
+  // histograms sized for the smaller (1536-entry) tiles of the record sorts
   const int64_t ntiles = (m + kRecTile - 1) / kRecTile;
   L.out_off = take(((size_t)n + 1) * 4);
   L.in_off = take(((size_t)n + 1) * 4);
