@@ -173,7 +173,7 @@ tc_status tc_autotune(const tc_graph* g, const tc_weights* const* w, int32_t n_d
   const int32_t cand[7][3] = {
       {20, 21, 22},         // chunk_log2
       {0, 1024, 4096},      // path_blocks
-      {5120, 10240, 20480}, // reg_waves
+      {20480, 40960, 81920}, // reg_waves
       {2560, 5120, 8192},   // fast_waves
       {512, 1024, 2048},    // wide_blocks
       {128, 256, 256},      // reg_list_cap: lanes hold 2 or 4 list entries

@@ -1207,8 +1207,8 @@ SampleTuning default_tuning() {
   SampleTuning t;
   t.chunk_log2 = kLiBits;
   t.path_blocks = 0;
-  t.reg_waves = 10240;
-  t.fast_waves = 5120;
+  t.reg_waves = 40960;
+  t.fast_waves = 8192;
   t.wide_blocks = kDefaultWideBlocks;
   t.reg_list_cap = 256;
   t.lds_list_cap = kKeyCap;
