@@ -26,13 +26,13 @@
 
 namespace tc {
 
-constexpr int kWBlock = 256;
-constexpr int kWItems = 8;
+constexpr int kWBlock = 512;
+constexpr int kWItems = 4;
 constexpr int kWTile = kWBlock * kWItems;  // 2048 edges per tile
 
 // ---- merge-path sorted search on (vertex, time) keys -------------------------
 constexpr int kMPTile = 2048;   // merged entries (queries + data) per block
-constexpr int kMPBlock = 256;
+constexpr int kMPBlock = 512;
 
 struct KeyCols {
   const int32_t* v;  // vertex column
