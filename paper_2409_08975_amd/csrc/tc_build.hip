@@ -608,12 +608,16 @@ __global__ __launch_bounds__(256) void k_rec_init(const int32_t* __restrict__ sr
 }
 
 // sorted (key, eid, other, t - t_min) -> columns of one order
+// With `off` (n + 1 entries), also the CSR offsets of the sorted keys:
+// off[v] = first position whose key is >= v, written by the thread of the
+// position where the key passes v (grid of m + 1 threads).
 __global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ in, int64_t m,
                                               int64_t tmin, int32_t* __restrict__ key_col,
                                               int32_t* __restrict__ other_col,
                                               int64_t* __restrict__ t_col,
                                               int32_t* __restrict__ eid_col,
-                                              uint4* __restrict__ rec) {
+                                              uint4* __restrict__ rec, int32_t n,
+                                              uint32_t* __restrict__ off) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) {
     const uint4 r = in[i];
@@ -623,6 +627,11 @@ __global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ in, int6
     t_col[i] = te;
     eid_col[i] = (int32_t)r.y;
     if (rec) rec[i] = make_uint4(r.z, r.y, (uint32_t)te, (uint32_t)(te >> 32));
+  }
+  if (off && i <= m) {
+    const int64_t prev = (i == 0) ? -1 : (int64_t)in[i - 1].x;
+    const int64_t cur = (i == m) ? (int64_t)n : (int64_t)in[i].x;
+    for (int64_t v = prev + 1; v <= cur; ++v) off[v] = (uint32_t)i;
   }
 }
 
@@ -852,10 +861,9 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     const int I = sort_rec(B, F, vbits, hist, part, st, RX_NONE, 3, RX_PAIR);
     if (I < 0) return TC_E_WORKSPACE;
     const int Ifree = (I == B) ? F : B;
-    hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint4*)rr[I], m, tmin,
-                       g->in_dst, g->in_src, g->in_t, g->in_eid, (uint4*)g->in_rec);
-    hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
-                       (const uint32_t*)g->in_dst, m, n, g->in_off);
+    hipLaunchKernelGGL(k_emit, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
+                       (const uint4*)rr[I], m, tmin, g->in_dst, g->in_src, g->in_t, g->in_eid,
+                       (uint4*)g->in_rec, n, g->in_off);
     // pair index: the in-order (dst, t, eid) stably by src
     const int Pr = sort_rec(3, Ifree, vbits, hist, part, st);
     if (Pr < 0) return TC_E_WORKSPACE;
@@ -863,7 +871,8 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     // the pair sort's spare buffer holds the pair sources
     uint32_t* psrc = (uint32_t*)rr[Pfree];
     hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint4*)rr[Pr], m, tmin,
-                       (int32_t*)psrc, g->pair_dst, g->pair_t, g->pair_eid, (uint4*)nullptr);
+                       (int32_t*)psrc, g->pair_dst, g->pair_t, g->pair_eid, (uint4*)nullptr, n,
+                       (uint32_t*)nullptr);
     if (two) {
       if (hipEventRecord(S->fork, st) != hipSuccess ||
           hipStreamWaitEvent(s2, S->fork, 0) != hipSuccess)
@@ -874,10 +883,9 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     // in-CSR position of out_eid[p] through the buffer of the finished sort
     const int R = sort_rec(A, I, vbits, hist2, part2, s2);
     if (R < 0) return TC_E_WORKSPACE;
-    hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, s2, (const uint4*)rr[R], m, tmin,
-                       g->out_src, g->out_dst, g->out_t, g->out_eid, (uint4*)g->out_rec);
-    hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, s2,
-                       (const uint32_t*)g->out_src, m, n, g->out_off);
+    hipLaunchKernelGGL(k_emit, dim3(blocks_for(m + 1, 256)), dim3(256), 0, s2,
+                       (const uint4*)rr[R], m, tmin, g->out_src, g->out_dst, g->out_t,
+                       g->out_eid, (uint4*)g->out_rec, n, g->out_off);
     uint32_t* pos_of = (uint32_t*)rr[R];
     hipLaunchKernelGGL(k_scatter_pos, dim3(eb), dim3(256), 0, s2, (const int32_t*)g->in_eid, m,
                        pos_of);
