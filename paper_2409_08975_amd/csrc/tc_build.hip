@@ -610,14 +610,17 @@ __global__ __launch_bounds__(256) void k_rec_init(const int32_t* __restrict__ sr
 // sorted (key, eid, other, t - t_min) -> columns of one order
 // With `off` (n + 1 entries), also the CSR offsets of the sorted keys:
 // off[v] = first position whose key is >= v, written by the thread of the
-// position where the key passes v (grid of m + 1 threads).
+// position where the key passes v (grid of m + 1 threads).  With `pos_of`
+// (eid -> in-CSR position), also to_in[i] = pos_of[eid of position i].
 __global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ in, int64_t m,
                                               int64_t tmin, int32_t* __restrict__ key_col,
                                               int32_t* __restrict__ other_col,
                                               int64_t* __restrict__ t_col,
                                               int32_t* __restrict__ eid_col,
                                               uint4* __restrict__ rec, int32_t n,
-                                              uint32_t* __restrict__ off) {
+                                              uint32_t* __restrict__ off,
+                                              const uint32_t* __restrict__ pos_of,
+                                              uint32_t* __restrict__ to_in) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) {
     const uint4 r = in[i];
@@ -627,6 +630,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ in, int6
     t_col[i] = te;
     eid_col[i] = (int32_t)r.y;
     if (rec) rec[i] = make_uint4(r.z, r.y, (uint32_t)te, (uint32_t)(te >> 32));
+    if (pos_of) to_in[i] = pos_of[r.y];
   }
   if (off && i <= m) {
     const int64_t prev = (i == 0) ? -1 : (int64_t)in[i - 1].x;
@@ -863,7 +867,8 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     const int Ifree = (I == B) ? F : B;
     hipLaunchKernelGGL(k_emit, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
                        (const uint4*)rr[I], m, tmin, g->in_dst, g->in_src, g->in_t, g->in_eid,
-                       (uint4*)g->in_rec, n, g->in_off);
+                       (uint4*)g->in_rec, n, g->in_off, (const uint32_t*)nullptr,
+                       (uint32_t*)nullptr);
     // pair index: the in-order (dst, t, eid) stably by src
     const int Pr = sort_rec(3, Ifree, vbits, hist, part, st);
     if (Pr < 0) return TC_E_WORKSPACE;
@@ -872,25 +877,25 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     uint32_t* psrc = (uint32_t*)rr[Pfree];
     hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint4*)rr[Pr], m, tmin,
                        (int32_t*)psrc, g->pair_dst, g->pair_t, g->pair_eid, (uint4*)nullptr, n,
-                       (uint32_t*)nullptr);
+                       (uint32_t*)nullptr, (const uint32_t*)nullptr, (uint32_t*)nullptr);
     if (two) {
       if (hipEventRecord(S->fork, st) != hipSuccess ||
           hipStreamWaitEvent(s2, S->fork, 0) != hipSuccess)
         return TC_E_HIP;
     }
     // second stream: out-CSR (stable by src), with the in-CSR records'
-    // buffer (emitted before the fork) as its spare, then out_to_in[p] =
-    // in-CSR position of out_eid[p] through the buffer of the finished sort
+    // buffer (emitted before the fork) as its spare
     const int R = sort_rec(A, I, vbits, hist2, part2, s2);
     if (R < 0) return TC_E_WORKSPACE;
-    hipLaunchKernelGGL(k_emit, dim3(blocks_for(m + 1, 256)), dim3(256), 0, s2,
-                       (const uint4*)rr[R], m, tmin, g->out_src, g->out_dst, g->out_t,
-                       g->out_eid, (uint4*)g->out_rec, n, g->out_off);
-    uint32_t* pos_of = (uint32_t*)rr[R];
+    // in-CSR position by eid in the sort's spare buffer, then the out-CSR
+    // columns with out_to_in gathered through it
+    uint32_t* pos_of = (uint32_t*)rr[R == A ? I : A];
     hipLaunchKernelGGL(k_scatter_pos, dim3(eb), dim3(256), 0, s2, (const int32_t*)g->in_eid, m,
                        pos_of);
-    hipLaunchKernelGGL(k_gather_pos, dim3(eb), dim3(256), 0, s2, (const int32_t*)g->out_eid, m,
-                       (const uint32_t*)pos_of, g->out_to_in);
+    hipLaunchKernelGGL(k_emit, dim3(blocks_for(m + 1, 256)), dim3(256), 0, s2,
+                       (const uint4*)rr[R], m, tmin, g->out_src, g->out_dst, g->out_t,
+                       g->out_eid, (uint4*)g->out_rec, n, g->out_off, (const uint32_t*)pos_of,
+                       g->out_to_in);
     if (two && hipEventRecord(S->out_done, s2) != hipSuccess) return TC_E_HIP;
     // this stream: the run table
     build_pair_hash(psrc, g, m, tab, st);
