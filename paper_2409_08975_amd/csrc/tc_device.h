@@ -295,6 +295,68 @@ __device__ __forceinline__ uint32_t run_upper_bound(const int64_t* __restrict__ 
   return upper_bound<int64_t>(pair_t, lo, hi, t);  // at most 16 times, one or two lines
 }
 
+// Two bisections over the same sorted array, one step of each per round so
+// that their loads are in flight together.  On return lo_x is the first
+// index in [lo_x, lo_x + n_x) whose value exceeds k_x (or lo_x + n_x).  A
+// finished search probes the other's index and ignores the value, so every
+// load stays inside a range the caller searches.
+__device__ __forceinline__ void upper_bound_pair(const int64_t* __restrict__ a, uint32_t& lo_a,
+                                                 uint32_t n_a, int64_t k_a, uint32_t& lo_b,
+                                                 uint32_t n_b, int64_t k_b) {
+  while ((n_a | n_b) != 0u) {
+    const uint32_t h_a = n_a >> 1, h_b = n_b >> 1;
+    const uint32_t m_a = lo_a + h_a, m_b = lo_b + h_b;
+    const int64_t v_a = a[n_a ? m_a : m_b];
+    const int64_t v_b = a[n_b ? m_b : m_a];
+    const bool go_a = n_a != 0u && !(k_a < v_a);
+    const bool go_b = n_b != 0u && !(k_b < v_b);
+    lo_a = go_a ? m_a + 1 : lo_a;
+    lo_b = go_b ? m_b + 1 : lo_b;
+    n_a = n_a == 0u ? 0u : (go_a ? n_a - h_a - 1 : h_a);
+    n_b = n_b == 0u ? 0u : (go_b ? n_b - h_b - 1 : h_b);
+  }
+}
+
+// Both ends of a window inside the run [r0, r1) of the pair index:
+// *ra = first position with time > t_a and *rb = first position with time
+// > t_b (at least *ra).  The two searches of run_upper_bound run in lockstep
+// over the run, level by level, so a window costs one chain of dependent
+// reads instead of two.
+__device__ __forceinline__ void run_window(const int64_t* __restrict__ pair_t,
+                                           const int64_t* __restrict__ skip, int64_t m,
+                                           uint32_t r0, uint32_t r1, int64_t t_a, int64_t t_b,
+                                           uint32_t* ra, uint32_t* rb) {
+  const int64_t n1 = skip_level_len(m, 1), n2 = skip_level_len(m, 2);
+  uint32_t lo_a = r0, hi_a = r1, lo_b = r0, hi_b = r1;
+  for (int k = 3; k >= 1; --k) {
+    const int sh = 4 * k;
+    const uint32_t i0_a = (uint32_t)(((uint64_t)lo_a + ((uint64_t)1 << sh) - 1) >> sh);
+    const uint32_t i1_a = hi_a > lo_a ? (hi_a - 1) >> sh : 0u;
+    const uint32_t i0_b = (uint32_t)(((uint64_t)lo_b + ((uint64_t)1 << sh) - 1) >> sh);
+    const uint32_t i1_b = hi_b > lo_b ? (hi_b - 1) >> sh : 0u;
+    // samples i0..i1 lie in [lo, hi); a range of 16 or fewer is left to the
+    // last step
+    const uint32_t c_a = (hi_a - lo_a > 16u && i1_a >= i0_a) ? i1_a - i0_a + 1 : 0u;
+    const uint32_t c_b = (hi_b - lo_b > 16u && i1_b >= i0_b) ? i1_b - i0_b + 1 : 0u;
+    if ((c_a | c_b) == 0u) continue;
+    const int64_t* C = skip + (k == 1 ? 0 : (k == 2 ? n1 : n1 + n2));
+    uint32_t j_a = i0_a, j_b = i0_b;
+    upper_bound_pair(C, j_a, c_a, t_a, j_b, c_b, t_b);
+    const uint32_t le_a = j_a - i0_a, le_b = j_b - i0_b;  // samples with time <= t
+    if (c_a) {
+      if (le_a > 0) lo_a = ((i0_a + le_a - 1) << sh) + 1;
+      if (le_a < c_a) hi_a = (i0_a + le_a) << sh;
+    }
+    if (c_b) {
+      if (le_b > 0) lo_b = ((i0_b + le_b - 1) << sh) + 1;
+      if (le_b < c_b) hi_b = (i0_b + le_b) << sh;
+    }
+  }
+  upper_bound_pair(pair_t, lo_a, hi_a - lo_a, t_a, lo_b, hi_b - lo_b, t_b);
+  *ra = lo_a;
+  *rb = lo_b > lo_a ? lo_b : lo_a;
+}
+
 // [start, end) of the run of edges a -> b in the pair index (empty if none)
 __device__ __forceinline__ void pair_run(const PairSlot* __restrict__ tab, int log2cap, int32_t a,
                                          int32_t b, uint32_t* start, uint32_t* end) {

@@ -135,10 +135,7 @@ __device__ __forceinline__ void pair_window(const SampleArgs& A, int32_t va, int
                                             uint32_t* hi) {
   uint32_t r0, r1;
   pair_run(A.pair_hash, A.pair_hash_log2, va, vb, &r0, &r1);
-  const uint32_t l = run_upper_bound(A.pair_t, A.pair_skip, A.m, r0, r1, t_lo);
-  const uint32_t h = run_upper_bound(A.pair_t, A.pair_skip, A.m, l, r1, t_hi);
-  *lo = l;
-  *hi = h;
+  run_window(A.pair_t, A.pair_skip, A.m, r0, r1, t_lo, t_hi, lo, hi);
 }
 
 __device__ __forceinline__ int32_t slot_vertex(int s, int32_t x, int32_t u, int32_t v, int32_t y) {
