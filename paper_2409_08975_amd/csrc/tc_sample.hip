@@ -145,6 +145,17 @@ __device__ __forceinline__ int32_t slot_vertex(int s, int32_t x, int32_t u, int3
 // upper_bound(S, r) - 1 through the 16-ary tree: one 128-byte node per
 // level, bisected (four 8-byte probes inside one cache line rather than the
 // whole node, which keeps the vector-memory traffic of a lane per level low)
+// Entries <= r of a sorted 16-entry node (upper_bound over it) in two
+// rounds: the three quarter boundaries, then the four entries of the
+// quarter, instead of four dependent probes.
+__device__ __forceinline__ uint32_t node_count16(const uint64_t* __restrict__ node, uint64_t r) {
+  const uint32_t q = (node[3] <= r ? 1u : 0u) + (node[7] <= r ? 1u : 0u) +
+                     (node[11] <= r ? 1u : 0u);
+  const uint64_t* e = node + 4 * q;
+  return 4 * q + (e[0] <= r ? 1u : 0u) + (e[1] <= r ? 1u : 0u) + (e[2] <= r ? 1u : 0u) +
+         (e[3] <= r ? 1u : 0u);
+}
+
 // s_tree holds the cached top levels of D's tree (see SampleArgs)
 __device__ __forceinline__ uint32_t tree_search(const SampleArgs& A, const DeltaArgs& D,
                                                 const uint64_t* s_tree, uint64_t r) {
@@ -153,14 +164,12 @@ __device__ __forceinline__ uint32_t tree_search(const SampleArgs& A, const Delta
   for (; L >= 1 && L >= A.tree_cache_lo; --L) {  // uniform bounds
     const uint64_t* lvl = s_tree + (A.tree_off[L] - A.tree_cache_base);
     const uint64_t node = (L == A.tree_levels) ? 0 : i;
-    const uint32_t cnt = upper_bound<uint64_t>(lvl + 16 * node, 0u, 16u, r);  // entries <= r
-    i = 16 * node + cnt - 1;
+    i = 16 * node + node_count16(lvl + 16 * node, r) - 1;  // entries <= r, minus one
   }
   for (; L >= 0; --L) {
     const uint64_t* lvl = (L == 0) ? D.S : D.tree + A.tree_off[L];
     const uint64_t node = (L == A.tree_levels) ? 0 : i;
-    const uint32_t cnt = upper_bound<uint64_t>(lvl + 16 * node, 0u, 16u, r);  // entries <= r
-    i = 16 * node + cnt - 1;
+    i = 16 * node + node_count16(lvl + 16 * node, r) - 1;  // entries <= r, minus one
   }
   return (uint32_t)i;
 }
