@@ -247,52 +247,9 @@ __host__ __device__ __forceinline__ uint64_t pair_hash(uint64_t key, int log2cap
   return (key * 0x9E3779B97F4A7C15ull) >> (64 - log2cap);
 }
 
-// First index in [lo, hi) with a[idx] > key, searched outward from lo:
-// probes lo, lo+1, lo+3, lo+7, ... until one exceeds key, then bisects the
-// last gap.  When the answer is near lo (a short time window starting at lo)
-// the probes stay in the cache lines already fetched.
-template <typename T>
-__device__ __forceinline__ uint32_t upper_bound_from(const T* __restrict__ a, uint32_t lo,
-                                                     uint32_t hi, T key) {
-  uint32_t step = 1, prev = lo;  // every index below prev holds a value <= key
-  uint32_t probe = lo;
-  while (probe < hi && a[probe] <= key) {
-    prev = probe + 1;
-    probe = lo + 2 * step - 1;
-    step *= 2;
-  }
-  return upper_bound<T>(a, prev, probe < hi ? probe : hi, key);
-}
-
 // Entries of sampled level k (pair_t[16^k i]) of a pair index of m entries.
 __host__ __device__ __forceinline__ int64_t skip_level_len(int64_t m, int k) {
   return (m + ((int64_t)1 << (4 * k)) - 1) >> (4 * k);
-}
-
-// First position in [lo, hi) whose time exceeds t (hi if none), where
-// [lo, hi) lies inside one run of the pair index (times sorted).  Equal to
-// upper_bound over pair_t.  From the coarsest level down, a bisection over
-// the samples of level k inside the range cuts it to the gap between two
-// neighbouring samples; the last step bisects at most 16 consecutive times
-// (one or two cache lines).  The probes of a long run thus fall mostly on
-// the small sampled levels, which stay in cache, instead of on pair_t.
-__device__ __forceinline__ uint32_t run_upper_bound(const int64_t* __restrict__ pair_t,
-                                                   const int64_t* __restrict__ skip, int64_t m,
-                                                   uint32_t lo, uint32_t hi, int64_t t) {
-  const int64_t n1 = skip_level_len(m, 1), n2 = skip_level_len(m, 2);
-  for (int k = 3; k >= 1; --k) {
-    if (hi - lo <= 16u) break;
-    const int sh = 4 * k;
-    const uint32_t i0 = (uint32_t)(((uint64_t)lo + ((uint64_t)1 << sh) - 1) >> sh);
-    const uint32_t i1 = (hi - 1) >> sh;  // samples i0..i1 lie in [lo, hi)
-    if (i1 < i0) continue;
-    const int64_t* C = skip + (k == 1 ? 0 : (k == 2 ? n1 : n1 + n2));
-    const uint32_t cnt = i1 - i0 + 1;
-    const uint32_t n_le = upper_bound<int64_t>(C, i0, i1 + 1, t) - i0;  // samples with time <= t
-    if (n_le > 0) lo = ((i0 + n_le - 1) << sh) + 1;
-    if (n_le < cnt) hi = (i0 + n_le) << sh;
-  }
-  return upper_bound<int64_t>(pair_t, lo, hi, t);  // at most 16 times, one or two lines
 }
 
 // Two bisections over the same sorted array, one step of each per round so
@@ -317,11 +274,15 @@ __device__ __forceinline__ void upper_bound_pair(const int64_t* __restrict__ a, 
   }
 }
 
-// Both ends of a window inside the run [r0, r1) of the pair index:
-// *ra = first position with time > t_a and *rb = first position with time
-// > t_b (at least *ra).  The two searches of run_upper_bound run in lockstep
-// over the run, level by level, so a window costs one chain of dependent
-// reads instead of two.
+// Both ends of a window inside the run [r0, r1) of the pair index (times
+// sorted): *ra = first position with time > t_a and *rb = first position
+// with time > t_b (at least *ra).  For each end, from the coarsest sampled
+// level down, a bisection over the samples pair_t[16^k i] inside its range
+// cuts the range to the gap between two neighbouring samples; the last step
+// bisects at most 16 consecutive times (one or two cache lines).  The probes
+// of a long run thus fall mostly on the small sampled levels, which stay in
+// cache.  The two ends are searched in lockstep, so a window costs one chain
+// of dependent reads instead of two.
 __device__ __forceinline__ void run_window(const int64_t* __restrict__ pair_t,
                                            const int64_t* __restrict__ skip, int64_t m,
                                            uint32_t r0, uint32_t r1, int64_t t_a, int64_t t_b,
