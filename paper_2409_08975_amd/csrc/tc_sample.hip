@@ -943,8 +943,12 @@ __global__ __launch_bounds__(kWBlock, 7) void k_listcount_wide(SampleArgs A, uin
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   uint64_t* Pbuf[2] = {pscratch + (uint64_t)blockIdx.x * 2 * (kWideCap + 1),
                        pscratch + ((uint64_t)blockIdx.x * 2 + 1) * (kWideCap + 1)};
-  sums_clear<1>(A);
+  // Blocks past the item count leave at once (uniformly): the others keep
+  // claiming until the counter passes the count, so every item is taken,
+  // and an empty pass costs no contended claims.
   const uint32_t n_items = *A.wide_count;
+  if (blockIdx.x >= n_items) return;
+  sums_clear<1>(A);
   if (tid == 0) s_item = atomicAdd(A.wide_next, 1u);
   __syncthreads();
   uint32_t it = uni(s_item);
@@ -1093,9 +1097,10 @@ __global__ __launch_bounds__(kWBlock, 7) void k_listcount_wide(SampleArgs A, uin
 // Items with a list longer than kWideCap: one thread per item.
 __global__ __launch_bounds__(kSBlock) void k_listcount_big(SampleArgs A) {
   const int tid = threadIdx.x, wave = tid >> 6;
+  const uint32_t n_items = *A.big_count;
+  if ((uint64_t)blockIdx.x * kSBlock >= n_items) return;  // uniform: no item for this block
   sums_clear<kSWaves>(A);
   __syncthreads();
-  const uint32_t n_items = *A.big_count;
   for (uint32_t it = blockIdx.x * kSBlock + tid; it < n_items; it += gridDim.x * kSBlock) {
     uint32_t li;
     int j, d;
