@@ -311,19 +311,27 @@ __global__ __launch_bounds__(kWBlock) void k_scan_apply(const uint32_t* __restri
 // at most 16 entries.  upper_bound(S, r) - 1 is then found by reading one
 // 128-byte node per level: at each level the node is the last entry <= r of
 // the level above, and counting its entries <= r gives the next index.
-__global__ __launch_bounds__(256) void k_tree_level(const uint64_t* __restrict__ S, int64_t m,
-                                                    uint64_t stride, uint64_t* __restrict__ lvl,
-                                                    int64_t n_padded) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_padded) return;
-  const uint64_t at = (uint64_t)i * stride;
-  lvl[i] = (at <= (uint64_t)m) ? S[at] : ~0ull;
-}
+// All levels of the search tree over S in one launch (level L holds
+// S[16^L i], or ~0 past m), plus S's padding to a multiple of 16: thread e
+// below `words` writes tree word e, the next `pad` threads the padding.
+struct TreeShape {
+  int32_t levels;
+  uint64_t offset[kMaxTreeLevels + 1];  // word offset of level L (1-based), then the total
+};
 
-__global__ __launch_bounds__(256) void k_pad_s(uint64_t* __restrict__ S, int64_t m,
-                                               int64_t n_padded) {
-  const int64_t i = m + 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_padded) S[i] = ~0ull;
+__global__ __launch_bounds__(256) void k_tree(uint64_t* __restrict__ S, int64_t m,
+                                              uint64_t* __restrict__ tree, TreeShape T,
+                                              int64_t pad) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t words = (int64_t)T.offset[T.levels + 1];
+  if (e < words) {
+    int L = 1;
+    while (L < T.levels && (uint64_t)e >= T.offset[L + 1]) ++L;
+    const uint64_t at = ((uint64_t)e - T.offset[L]) << (4 * L);
+    tree[e] = (at <= (uint64_t)m) ? S[at] : ~0ull;
+  } else if (e < words + pad) {
+    S[m + 1 + (e - words)] = ~0ull;
+  }
 }
 
 STree stree_layout(int64_t m) {
@@ -351,16 +359,14 @@ static void build_tree(tc_weights* w, hipStream_t st) {
   const int64_t m = w->m;
   const STree T = stree_layout(m);
   const int64_t pad = T.count[0] - (m + 1);
-  if (pad > 0)
-    hipLaunchKernelGGL(k_pad_s, dim3((unsigned)((pad + 255) / 256)), dim3(256), 0, st, w->S, m,
-                       T.count[0]);
-  uint64_t stride = 1;
-  for (int L = 1; L <= T.levels; ++L) {
-    stride *= 16;
-    hipLaunchKernelGGL(k_tree_level, dim3((unsigned)((T.count[L] + 255) / 256)), dim3(256), 0, st,
-                       (const uint64_t*)w->S, m, stride,
-                       (uint64_t*)w->scratch + T.offset[L], T.count[L]);
-  }
+  TreeShape sh{};
+  sh.levels = T.levels;
+  for (int L = 1; L <= T.levels; ++L) sh.offset[L] = T.offset[L];
+  sh.offset[T.levels + 1] = T.total_words;
+  const int64_t n = (int64_t)T.total_words + pad;
+  if (n > 0)
+    hipLaunchKernelGGL(k_tree, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w->S, m,
+                       (uint64_t*)w->scratch, sh, pad);
 }
 
 struct WeightsLayout {
