@@ -868,6 +868,11 @@ __global__ __launch_bounds__(kWave) void k_listcount_lds(SampleArgs A, uint64_t*
         s_key[0][i] = (uint32_t)(A.pair_t[lo0 + i] - base);
       __threadfence_block();
       int pb = 0;
+      // Level totals: T_0 = |L_0| and T_r <= |L_r| T_{r-1}.  While that bound
+      // is below 2^64 the running 64-bit carry is the exact total (no 128-bit
+      // sums); below 2^32 the level's prefix sums are kept as 32-bit words.
+      uint64_t t_prev = lane_u32(my_len, 0);
+      bool sat = false, prev32 = false;
       for (int r = 1; r < l; ++r) {
         const uint32_t prev_len = lane_u32(my_len, r - 1);
         const uint32_t lo = lane_u32(my_lo, r);
@@ -876,9 +881,17 @@ __global__ __launch_bounds__(kWave) void k_listcount_lds(SampleArgs A, uint64_t*
         uint32_t* kcur = s_key[r & 1];
         const uint64_t* Pprev = s_p[pb ^ 1];
         uint64_t* Pcur = s_p[pb];
+        uint64_t bound;
+        const bool exact64 = !sat && !__builtin_mul_overflow((uint64_t)len, t_prev, &bound);
+        const bool cur32 = exact64 && bound < (1ull << 32);
         total = U128{0, 0};
         uint64_t carry = 0;
-        if (lane == 0) Pcur[0] = 0;
+        if (lane == 0) {
+          if (cur32)
+            reinterpret_cast<uint32_t*>(Pcur)[0] = 0u;
+          else
+            Pcur[0] = 0;
+        }
         for (uint32_t c0 = 0; c0 < len; c0 += kWave) {
           const uint32_t i = c0 + lane;
           const bool act = i < len;
@@ -887,18 +900,35 @@ __global__ __launch_bounds__(kWave) void k_listcount_lds(SampleArgs A, uint64_t*
             const uint32_t key = (uint32_t)(A.pair_t[lo + i] - base);
             kcur[i] = key;
             const uint32_t pos = lower_bound<uint32_t>(kprev, 0u, prev_len, key);
-            c = (r == 1) ? (uint64_t)pos : Pprev[pos];
+            c = (r == 1) ? (uint64_t)pos
+                         : (prev32 ? (uint64_t)reinterpret_cast<const uint32_t*>(Pprev)[pos]
+                                   : Pprev[pos]);
           }
           const uint64_t inc = scan_dpp(c);
-          if (act) Pcur[i + 1] = carry + inc;
-          total = add128(total, wave_sum128_dpp(c));
+          if (act) {
+            if (cur32)
+              reinterpret_cast<uint32_t*>(Pcur)[i + 1] = (uint32_t)(carry + inc);
+            else
+              Pcur[i + 1] = carry + inc;
+          }
+          if (!exact64) total = add128(total, wave_sum128_dpp(c));
           carry += lane_u64(inc, kWave - 1);
         }
-        total = U128{uni64(total.lo), uni64(total.hi)};
-        if (total.hi != 0 && lane == 0) flag_status(A, d, TC_F_OVERFLOW | TC_F_MOTIF(j));
+        if (exact64) {
+          t_prev = carry;
+        } else {
+          total = U128{uni64(total.lo), uni64(total.hi)};
+          if (total.hi != 0) {
+            sat = true;
+            if (lane == 0) flag_status(A, d, TC_F_OVERFLOW | TC_F_MOTIF(j));
+          }
+          t_prev = total.hi ? ~0ull : total.lo;
+        }
+        prev32 = cur32;
         pb ^= 1;
         __threadfence_block();
       }
+      total = U128{t_prev, 0};
     }
     if (fwd)
       fwd_push(fb, code, A.wide_count, A.wide_code);
