@@ -999,13 +999,28 @@ __global__ __launch_bounds__(kWBlock, 7) void k_listcount_wide(SampleArgs A, uin
     maxlen = uni(maxlen);
     U128 total{0, 0};
     if (maxlen <= (uint32_t)kWideCap) {
+      // As in the one-wavefront pass: while T_r <= |L_r| T_{r-1} stays below
+      // 2^64 the running carry is the exact level total (no 128-bit sums),
+      // and below 2^32 the level's prefix sums are stored as 32-bit words.
+      uint64_t t_prev = uni(s_len[0]);
+      bool sat = false, prev32 = false;
       for (int r = 1; r < l; ++r) {
         const uint32_t loA = uni(s_lo[r - 1]), nA = uni(s_len[r - 1]);
         const uint32_t loB = uni(s_lo[r]), nB = uni(s_len[r]);
         const uint64_t* Pprev = Pbuf[(r - 1) & 1];
         uint64_t* Pcur = Pbuf[r & 1];
+        const uint32_t* Pprev32 = reinterpret_cast<const uint32_t*>(Pprev);
+        uint32_t* Pcur32 = reinterpret_cast<uint32_t*>(Pcur);
         const bool keep = r + 1 < l;  // P_r is read by the next level
-        if (keep && tid == 0) Pcur[0] = 0;
+        uint64_t bound;
+        const bool exact64 = !sat && !__builtin_mul_overflow((uint64_t)nB, t_prev, &bound);
+        const bool cur32 = exact64 && bound < (1ull << 32);
+        if (keep && tid == 0) {
+          if (cur32)
+            Pcur32[0] = 0u;
+          else
+            Pcur[0] = 0;
+        }
         total = U128{0, 0};
         uint64_t carry = 0;
         uint32_t a0 = 0, b0 = 0;
@@ -1014,7 +1029,8 @@ __global__ __launch_bounds__(kWBlock, 7) void k_listcount_wide(SampleArgs A, uin
           const uint32_t nb = nB - b0 < (uint32_t)kWTile ? nB - b0 : (uint32_t)kWTile;
           for (uint32_t i = tid; i < na; i += kWBlock) sA[i] = A.pair_t[loA + a0 + i];
           for (uint32_t i = tid; i <= na; i += kWBlock)
-            sP[i] = (r == 1) ? (uint64_t)(a0 + i) : Pprev[a0 + i];
+            sP[i] = (r == 1) ? (uint64_t)(a0 + i)
+                             : (prev32 ? (uint64_t)Pprev32[a0 + i] : Pprev[a0 + i]);
           int64_t key[kWPer];
 #pragma unroll
           for (int e = 0; e < kWPer; ++e) {
@@ -1037,42 +1053,53 @@ __global__ __launch_bounds__(kWBlock, 7) void k_listcount_wide(SampleArgs A, uin
           }
           // inclusive prefix of this thread's four counts, then across the block
           uint64_t run[kWPer];
-          U128 tsum{0, 0};
 #pragma unroll
-          for (int e = 0; e < kWPer; ++e) {
-            run[e] = (e ? run[e - 1] : 0ull) + c[e];
-            tsum = add128(tsum, U128{c[e], 0});
-          }
+          for (int e = 0; e < kWPer; ++e) run[e] = (e ? run[e - 1] : 0ull) + c[e];
           const uint64_t incl = scan_dpp(run[kWPer - 1]);
-          // tsum.hi <= 3 (four values below 2^64 each)
-          U128 wsum = wave_sum128_dpp(tsum.lo);
-          wsum.hi += lane_u32(scan_dpp((uint32_t)tsum.hi), kWave - 1);
+          if (!exact64) {
+            U128 tsum{0, 0};
+#pragma unroll
+            for (int e = 0; e < kWPer; ++e) tsum = add128(tsum, U128{c[e], 0});
+            // tsum.hi <= 3 (four values below 2^64 each)
+            U128 wsum = wave_sum128_dpp(tsum.lo);
+            wsum.hi += lane_u32(scan_dpp((uint32_t)tsum.hi), kWave - 1);
+            if (lane == kWave - 1) {
+              s_wlo[wave] = wsum.lo;
+              s_whi[wave] = wsum.hi;
+            }
+          }
           const uint32_t wset = lane_u32(scan_dpp(nset), kWave - 1);
           if (lane == kWave - 1) {
             s_wsum[wave] = incl;
-            s_wlo[wave] = wsum.lo;
-            s_whi[wave] = wsum.hi;
             s_wset[wave] = wset;
           }
           __syncthreads();
           uint64_t before = carry + incl - run[kWPer - 1];
           uint32_t nr = 0;
-          U128 step{0, 0};
 #pragma unroll
           for (int w = 0; w < kWWaves; ++w) {
             if (w < wave) before += s_wsum[w];
             nr += s_wset[w];
-            step = add128(step, U128{s_wlo[w], s_whi[w]});
           }
           nr = uni(nr);
           if (keep) {
 #pragma unroll
             for (int e = 0; e < kWPer; ++e) {
               const uint32_t bi = (uint32_t)(tid * kWPer + e);
-              if (bi < nr) Pcur[b0 + bi + 1] = before + run[e];
+              if (bi < nr) {
+                if (cur32)
+                  Pcur32[b0 + bi + 1] = (uint32_t)(before + run[e]);
+                else
+                  Pcur[b0 + bi + 1] = before + run[e];
+              }
             }
           }
-          total = add128(total, U128{uni64(step.lo), uni64(step.hi)});
+          if (!exact64) {
+            U128 step{0, 0};
+#pragma unroll
+            for (int w = 0; w < kWWaves; ++w) step = add128(step, U128{s_wlo[w], s_whi[w]});
+            total = add128(total, U128{uni64(step.lo), uni64(step.hi)});
+          }
           uint64_t blk = 0;
 #pragma unroll
           for (int w = 0; w < kWWaves; ++w) blk += s_wsum[w];
@@ -1105,10 +1132,20 @@ __global__ __launch_bounds__(kWBlock, 7) void k_listcount_wide(SampleArgs A, uin
           }
           __syncthreads();  // the tiles are rewritten by the next step
         }
-        if (uni64(total.hi) != 0 && tid == 0) flag_status(A, d, TC_F_OVERFLOW | TC_F_MOTIF(j));
+        if (exact64) {
+          t_prev = carry;
+        } else {
+          if (uni64(total.hi) != 0) {
+            sat = true;
+            if (tid == 0) flag_status(A, d, TC_F_OVERFLOW | TC_F_MOTIF(j));
+          }
+          t_prev = total.hi ? ~0ull : total.lo;
+        }
+        prev32 = cur32;
         __threadfence_block();
         __syncthreads();  // P_r complete before the next level reads it
       }
+      total = U128{t_prev, 0};
     }
     if (tid == 0) {
       if (maxlen > (uint32_t)kWideCap)
