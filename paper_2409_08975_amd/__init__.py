@@ -191,6 +191,10 @@ class Graph:
     def m(self):
         return self.c.m
 
+    def status(self):
+        """The build's device status word (TC_F_* bits; synchronises)."""
+        return int(self.view("status", torch.int32, 1).item()) & 0xFFFFFFFF
+
     def view(self, name, dtype, length):
         """Tensor view of one device array of the graph (no copy)."""
         ptr = getattr(self.c, name)

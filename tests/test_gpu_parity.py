@@ -54,6 +54,7 @@ def build_both(tcb, torch, g):
 
 
 def check_graph(G, og, g):
+    assert G.status() == 0
     A = G.arrays()
     o = og.orders()
     assert np.array_equal(A["out_eid"].cpu().numpy(), o["out_eid"])
