@@ -89,8 +89,6 @@ typedef struct tc_graph {
   uint32_t *in_off;                   /* [n+1] */
   int32_t *in_src, *in_eid, *in_dst;
   int64_t *in_t;                      /* [m] each */
-  uint32_t *out_to_in;                /* [m]: in-CSR position of the edge at
-                                         out-CSR position p */
   int32_t *pair_dst, *pair_eid;
   int64_t *pair_t;                    /* [m] each */
   uint32_t *status;                   /* device status word of the build       */

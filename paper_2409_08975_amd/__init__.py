@@ -67,7 +67,7 @@ class tc_graph(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("t_min", ctypes.c_int64),
                 ("t_max", ctypes.c_int64), ("out_off", _P), ("out_src", _P), ("out_dst", _P),
                 ("out_eid", _P), ("out_t", _P), ("in_off", _P), ("in_src", _P), ("in_eid", _P),
-                ("in_dst", _P), ("in_t", _P), ("out_to_in", _P), ("pair_dst", _P),
+                ("in_dst", _P), ("in_t", _P), ("pair_dst", _P),
                 ("pair_eid", _P), ("pair_t", _P),
                 ("status", _P), ("pair_hash", _P), ("pair_hash_log2", ctypes.c_int32),
                 ("out_rec", _P), ("in_rec", _P), ("pair_skip", _P)]
@@ -211,7 +211,7 @@ class Graph:
                              ("out_eid", torch.int32, m), ("out_t", torch.int64, m),
                              ("in_src", torch.int32, m), ("in_eid", torch.int32, m),
                              ("in_dst", torch.int32, m), ("in_t", torch.int64, m),
-                             ("out_to_in", torch.int32, m), ("pair_dst", torch.int32, m),
+                             ("pair_dst", torch.int32, m),
                              ("pair_eid", torch.int32, m), ("pair_t", torch.int64, m)]:
             d[name] = self.view(name, dt, ln)
         return d

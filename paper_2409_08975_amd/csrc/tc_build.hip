@@ -495,21 +495,6 @@ __global__ __launch_bounds__(256) void k_offsets(const uint32_t* __restrict__ sk
   for (int64_t v = prev + 1; v <= cur; ++v) off[v] = (uint32_t)i;
 }
 
-// pos_of[order[i]] = i
-__global__ __launch_bounds__(256) void k_scatter_pos(const int32_t* __restrict__ order, int64_t m,
-                                                     uint32_t* __restrict__ pos_of) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) pos_of[order[i]] = (uint32_t)i;
-}
-
-// out[i] = pos_of[order[i]]
-__global__ __launch_bounds__(256) void k_gather_pos(const int32_t* __restrict__ order, int64_t m,
-                                                    const uint32_t* __restrict__ pos_of,
-                                                    uint32_t* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) out[i] = pos_of[order[i]];
-}
-
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ a, int64_t n,
                                                   uint32_t v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -610,17 +595,14 @@ __global__ __launch_bounds__(256) void k_rec_init(const int32_t* __restrict__ sr
 // sorted (key, eid, other, t - t_min) -> columns of one order
 // With `off` (n + 1 entries), also the CSR offsets of the sorted keys:
 // off[v] = first position whose key is >= v, written by the thread of the
-// position where the key passes v (grid of m + 1 threads).  With `pos_of`
-// (eid -> in-CSR position), also to_in[i] = pos_of[eid of position i].
+// position where the key passes v (grid of m + 1 threads).
 __global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ in, int64_t m,
                                               int64_t tmin, int32_t* __restrict__ key_col,
                                               int32_t* __restrict__ other_col,
                                               int64_t* __restrict__ t_col,
                                               int32_t* __restrict__ eid_col,
                                               uint4* __restrict__ rec, int32_t n,
-                                              uint32_t* __restrict__ off,
-                                              const uint32_t* __restrict__ pos_of,
-                                              uint32_t* __restrict__ to_in) {
+                                              uint32_t* __restrict__ off) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) {
     const uint4 r = in[i];
@@ -630,7 +612,6 @@ __global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ in, int6
     t_col[i] = te;
     eid_col[i] = (int32_t)r.y;
     if (rec) rec[i] = make_uint4(r.z, r.y, (uint32_t)te, (uint32_t)(te >> 32));
-    if (pos_of) to_in[i] = pos_of[r.y];
   }
   if (off && i <= m) {
     const int64_t prev = (i == 0) ? -1 : (int64_t)in[i - 1].x;
@@ -644,7 +625,7 @@ static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct GraphLayout {
   size_t out_off, in_off, out_src, out_dst, out_eid, out_t, in_src, in_eid, in_dst, in_t,
-      out_to_in, pair_dst, out_rec, in_rec,
+      pair_dst, out_rec, in_rec,
       pair_eid, pair_t, pair_hash, pair_skip, status, tminmax, keys0, keys1, vals0, vals1, hist, part,
       part_elems, rr[4], hist2, part2, total;
 };
@@ -669,7 +650,6 @@ static GraphLayout graph_layout(int32_t n, int64_t m) {
   L.in_src = take(M * 4);
   L.in_eid = take(M * 4);
   L.in_dst = take(M * 4);
-  L.out_to_in = take(M * 4);
   L.in_t = take(M * 8);
   L.pair_dst = take(M * 4);
   L.pair_eid = take(M * 4);
@@ -768,7 +748,6 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   g->in_src = (int32_t*)(base + L.in_src);
   g->in_eid = (int32_t*)(base + L.in_eid);
   g->in_dst = (int32_t*)(base + L.in_dst);
-  g->out_to_in = (uint32_t*)(base + L.out_to_in);
   g->in_t = (int64_t*)(base + L.in_t);
   g->pair_dst = (int32_t*)(base + L.pair_dst);
   g->pair_eid = (int32_t*)(base + L.pair_eid);
@@ -867,8 +846,7 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     const int Ifree = (I == B) ? F : B;
     hipLaunchKernelGGL(k_emit, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
                        (const uint4*)rr[I], m, tmin, g->in_dst, g->in_src, g->in_t, g->in_eid,
-                       (uint4*)g->in_rec, n, g->in_off, (const uint32_t*)nullptr,
-                       (uint32_t*)nullptr);
+                       (uint4*)g->in_rec, n, g->in_off);
     // pair index: the in-order (dst, t, eid) stably by src
     const int Pr = sort_rec(3, Ifree, vbits, hist, part, st);
     if (Pr < 0) return TC_E_WORKSPACE;
@@ -877,7 +855,7 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     uint32_t* psrc = (uint32_t*)rr[Pfree];
     hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint4*)rr[Pr], m, tmin,
                        (int32_t*)psrc, g->pair_dst, g->pair_t, g->pair_eid, (uint4*)nullptr, n,
-                       (uint32_t*)nullptr, (const uint32_t*)nullptr, (uint32_t*)nullptr);
+                       (uint32_t*)nullptr);
     if (two) {
       if (hipEventRecord(S->fork, st) != hipSuccess ||
           hipStreamWaitEvent(s2, S->fork, 0) != hipSuccess)
@@ -887,15 +865,9 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     // buffer (emitted before the fork) as its spare
     const int R = sort_rec(A, I, vbits, hist2, part2, s2);
     if (R < 0) return TC_E_WORKSPACE;
-    // in-CSR position by eid in the sort's spare buffer, then the out-CSR
-    // columns with out_to_in gathered through it
-    uint32_t* pos_of = (uint32_t*)rr[R == A ? I : A];
-    hipLaunchKernelGGL(k_scatter_pos, dim3(eb), dim3(256), 0, s2, (const int32_t*)g->in_eid, m,
-                       pos_of);
     hipLaunchKernelGGL(k_emit, dim3(blocks_for(m + 1, 256)), dim3(256), 0, s2,
                        (const uint4*)rr[R], m, tmin, g->out_src, g->out_dst, g->out_t,
-                       g->out_eid, (uint4*)g->out_rec, n, g->out_off, (const uint32_t*)pos_of,
-                       g->out_to_in);
+                       g->out_eid, (uint4*)g->out_rec, n, g->out_off);
     if (two && hipEventRecord(S->out_done, s2) != hipSuccess) return TC_E_HIP;
     // this stream: the run table
     build_pair_hash(psrc, g, m, tab, st);
@@ -963,13 +935,6 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   } else {
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for((int64_t)n + 1, 256)), dim3(256), 0, st,
                        g->in_off, (int64_t)n + 1, 0u);
-  }
-  // 3b. out_to_in[p] = in-CSR position of out_eid[p]
-  if (m > 0) {
-    hipLaunchKernelGGL(k_scatter_pos, dim3(eb), dim3(256), 0, st, (const int32_t*)g->in_eid, m,
-                       (uint32_t*)vals0);
-    hipLaunchKernelGGL(k_gather_pos, dim3(eb), dim3(256), 0, st, (const int32_t*)g->out_eid, m,
-                       (const uint32_t*)vals0, g->out_to_in);
   }
   // 4. pair index: the in-order (dst, t, eid) stably sorted by src
   if (m > 0) {

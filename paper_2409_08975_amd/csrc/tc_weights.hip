@@ -13,8 +13,9 @@
 //   k_mp_rank     stages the tile's data keys in LDS and ranks each of the
 //                 tile's queries there,
 // so every array is read once, coalesced.  Then:
-//   k_combine     per p: gathers v's window through the p -> q map, writes
-//                 lo_out, b and the 128-bit sum of a*b per 2048-edge tile.
+//   k_combine     per p: v's window (the last rank pass stored it by edge id),
+//                 writes lo_out, b and the 128-bit sum of a*b per 2048-edge
+//                 tile.
 //   k_scan_tiles  one block scans the tile sums in 128-bit arithmetic, so
 //                 W >= 2^64 is detected exactly, and writes S[m] = W.
 //   k_scan_apply  per tile: w = a*b, block-wide exclusive scan, plus the
@@ -85,13 +86,15 @@ __global__ __launch_bounds__(256) void k_mp_split4(SplitJobs J, int64_t nq, int6
 }
 
 // rank of every query of the tile: out[i] = rank, or with `sub`
-// pair_out[i] = {sub[i], rank - sub[i]} (a window's start and length)
+// pair_out[i] = {sub[i], rank - sub[i]} (a window's start and length),
+// stored at pair_out[eid[i]] when `eid` is given
 template <bool UPPER>
 __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, KeyCols D, int64_t nd,
                                                       const uint32_t* __restrict__ split,
                                                       const uint32_t* __restrict__ sub,
                                                       uint32_t* __restrict__ out,
-                                                      uint2* __restrict__ pair_out) {
+                                                      uint2* __restrict__ pair_out,
+                                                      const int32_t* __restrict__ eid) {
   __shared__ int32_t s_v[kMPTile];
   __shared__ int64_t s_t[kMPTile];
   const int64_t b = blockIdx.x;
@@ -119,17 +122,16 @@ __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, Key
     const uint32_t rank = (uint32_t)(i0 + lo);
     if (pair_out) {
       const uint32_t s0 = sub[i];
-      pair_out[i] = make_uint2(s0, rank - s0);
+      pair_out[eid ? eid[i] : i] = make_uint2(s0, rank - s0);
     } else {
       out[i] = sub ? rank - sub[i] : rank;
     }
   }
 }
 
-// per p: v's window from its in-CSR position, the path record, and the
-// tile sums of a * b
-__global__ __launch_bounds__(kWBlock) void k_combine(const uint32_t* __restrict__ out_to_in,
-                                                     const uint2* __restrict__ win_q,
+// per p: v's window (by edge id), the path record, and the tile sums of a * b
+__global__ __launch_bounds__(kWBlock) void k_combine(const int32_t* __restrict__ out_eid,
+                                                     const uint2* __restrict__ win_e,
                                                      const uint32_t* __restrict__ lo_in,
                                                      const uint32_t* __restrict__ a,
                                                      const int32_t* __restrict__ out_src,
@@ -146,7 +148,7 @@ __global__ __launch_bounds__(kWBlock) void k_combine(const uint32_t* __restrict_
   for (int r = 0; r < kWItems; ++r) {
     const int64_t p = start + (int64_t)r * kWBlock + threadIdx.x;
     if (p < m) {
-      const uint2 wq = win_q[out_to_in[p]];
+      const uint2 wq = win_e[out_eid[p]];
       const uint32_t bb = wq.y, ap = a[p];
       lo_out[p] = wq.x;
       b_out[p] = bb;
@@ -370,7 +372,7 @@ static void build_tree(tc_weights* w, hipStream_t st) {
 }
 
 struct WeightsLayout {
-  size_t lo_in, a, lo_out, b, S, status, tile_sums, tile_off, tree, lo_out_q, win_q, split, prec,
+  size_t lo_in, a, lo_out, b, S, status, tile_sums, tile_off, tree, lo_out_q, win_e, split, prec,
       total;
 };
 
@@ -395,7 +397,7 @@ static WeightsLayout weights_layout(int64_t m) {
   L.tile_sums = take(ntiles * 16);
   L.tile_off = take(ntiles * 8);
   L.lo_out_q = take(M * 4);
-  L.win_q = take(M * 8);
+  L.win_e = take(M * 8);
   L.split = take((size_t)4 * ((2 * M + kMPTile - 1) / kMPTile + 2) * 4);  // four jobs
   L.prec = take(M * 32);
   L.total = o;
@@ -425,7 +427,7 @@ tc_status path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_byt
   uint64_t* tile_off = (uint64_t*)(base + L.tile_off);
   const int64_t ntiles = (m + kWTile - 1) / kWTile;
   uint32_t* lo_out_q = (uint32_t*)(base + L.lo_out_q);
-  uint2* win_q = (uint2*)(base + L.win_q);
+  uint2* win_e = (uint2*)(base + L.win_e);
   uint32_t* split = (uint32_t*)(base + L.split);
   if (m > 0) {
     TimedLaunch tl("k_windows", st);
@@ -445,17 +447,18 @@ tc_status path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_byt
     hipLaunchKernelGGL(k_mp_split4, dim3(sb, 4), dim3(256), 0, st, J, m, m, nsplit);
     hipLaunchKernelGGL(k_mp_rank<false>, dim3(rb), dim3(kMPBlock), 0, st, q_lo, m, ink, m,
                        (const uint32_t*)sp[0], (const uint32_t*)nullptr, w->lo_in,
-                       (uint2*)nullptr);
+                       (uint2*)nullptr, (const int32_t*)nullptr);
     hipLaunchKernelGGL(k_mp_rank<true>, dim3(rb), dim3(kMPBlock), 0, st, outk, m, ink, m,
-                       (const uint32_t*)sp[1], (const uint32_t*)w->lo_in, w->a, (uint2*)nullptr);
+                       (const uint32_t*)sp[1], (const uint32_t*)w->lo_in, w->a, (uint2*)nullptr,
+                       (const int32_t*)nullptr);
     hipLaunchKernelGGL(k_mp_rank<false>, dim3(rb), dim3(kMPBlock), 0, st, ink, m, outk, m,
                        (const uint32_t*)sp[2], (const uint32_t*)nullptr, lo_out_q,
-                       (uint2*)nullptr);
+                       (uint2*)nullptr, (const int32_t*)nullptr);
     hipLaunchKernelGGL(k_mp_rank<true>, dim3(rb), dim3(kMPBlock), 0, st, q_hi, m, outk, m,
                        (const uint32_t*)sp[3], (const uint32_t*)lo_out_q, (uint32_t*)nullptr,
-                       win_q);
+                       win_e, (const int32_t*)g->in_eid);
     hipLaunchKernelGGL(k_combine, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
-                       (const uint32_t*)g->out_to_in, (const uint2*)win_q,
+                       (const int32_t*)g->out_eid, (const uint2*)win_e,
                        (const uint32_t*)w->lo_in, (const uint32_t*)w->a,
                        (const int32_t*)g->out_src, (const int32_t*)g->out_dst,
                        (const int64_t*)g->out_t, m, w->lo_out, w->b, (uint4*)w->prec, tile_sums);
