@@ -595,14 +595,17 @@ __global__ __launch_bounds__(256) void k_rec_init(const int32_t* __restrict__ sr
 // sorted (key, eid, other, t - t_min) -> columns of one order
 // With `off` (n + 1 entries), also the CSR offsets of the sorted keys:
 // off[v] = first position whose key is >= v, written by the thread of the
-// position where the key passes v (grid of m + 1 threads).
+// position where the key passes v (grid of m + 1 threads).  With `skip`
+// (the pair index), also the sampled levels skip_k[i] = t[16^k i], k = 1..3,
+// from the times this pass writes anyway.
 __global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ in, int64_t m,
                                               int64_t tmin, int32_t* __restrict__ key_col,
                                               int32_t* __restrict__ other_col,
                                               int64_t* __restrict__ t_col,
                                               int32_t* __restrict__ eid_col,
                                               uint4* __restrict__ rec, int32_t n,
-                                              uint32_t* __restrict__ off) {
+                                              uint32_t* __restrict__ off,
+                                              int64_t* __restrict__ skip) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) {
     const uint4 r = in[i];
@@ -612,6 +615,12 @@ __global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ in, int6
     t_col[i] = te;
     eid_col[i] = (int32_t)r.y;
     if (rec) rec[i] = make_uint4(r.z, r.y, (uint32_t)te, (uint32_t)(te >> 32));
+    if (skip && (i & 15) == 0) {
+      const int64_t n1 = skip_level_len(m, 1), n2 = skip_level_len(m, 2);
+      skip[i >> 4] = te;
+      if ((i & 255) == 0) skip[n1 + (i >> 8)] = te;
+      if ((i & 4095) == 0) skip[n1 + n2 + (i >> 12)] = te;
+    }
   }
   if (off && i <= m) {
     const int64_t prev = (i == 0) ? -1 : (int64_t)in[i - 1].x;
@@ -722,8 +731,8 @@ static int bitlen(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
 // The pair-run table and the sampled pair times, from the pair index's
 // sorted src keys.
 static void build_pair_hash(const uint32_t* psrc, const tc_graph* g, int64_t m, PairSlot* tab,
-                            hipStream_t st) {
-  {
+                            hipStream_t st, bool with_skip) {
+  if (with_skip) {
     const int64_t n1 = skip_level_len(m, 1), n2 = skip_level_len(m, 2), n3 = skip_level_len(m, 3);
     hipLaunchKernelGGL(k_pair_skip, dim3(blocks_for(n1 + n2 + n3, 256)), dim3(256), 0, st,
                        (const int64_t*)g->pair_t, n1, n2, n3, g->pair_skip);
@@ -846,7 +855,7 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     const int Ifree = (I == B) ? F : B;
     hipLaunchKernelGGL(k_emit, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
                        (const uint4*)rr[I], m, tmin, g->in_dst, g->in_src, g->in_t, g->in_eid,
-                       (uint4*)g->in_rec, n, g->in_off);
+                       (uint4*)g->in_rec, n, g->in_off, (int64_t*)nullptr);
     // pair index: the in-order (dst, t, eid) stably by src
     const int Pr = sort_rec(3, Ifree, vbits, hist, part, st);
     if (Pr < 0) return TC_E_WORKSPACE;
@@ -855,7 +864,7 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     uint32_t* psrc = (uint32_t*)rr[Pfree];
     hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint4*)rr[Pr], m, tmin,
                        (int32_t*)psrc, g->pair_dst, g->pair_t, g->pair_eid, (uint4*)nullptr, n,
-                       (uint32_t*)nullptr);
+                       (uint32_t*)nullptr, g->pair_skip);
     if (two) {
       if (hipEventRecord(S->fork, st) != hipSuccess ||
           hipStreamWaitEvent(s2, S->fork, 0) != hipSuccess)
@@ -867,10 +876,10 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     if (R < 0) return TC_E_WORKSPACE;
     hipLaunchKernelGGL(k_emit, dim3(blocks_for(m + 1, 256)), dim3(256), 0, s2,
                        (const uint4*)rr[R], m, tmin, g->out_src, g->out_dst, g->out_t,
-                       g->out_eid, (uint4*)g->out_rec, n, g->out_off);
+                       g->out_eid, (uint4*)g->out_rec, n, g->out_off, (int64_t*)nullptr);
     if (two && hipEventRecord(S->out_done, s2) != hipSuccess) return TC_E_HIP;
-    // this stream: the run table
-    build_pair_hash(psrc, g, m, tab, st);
+    // this stream: the run table (the pair emit wrote the sampled levels)
+    build_pair_hash(psrc, g, m, tab, st, false);
     if (two && hipStreamWaitEvent(st, S->out_done, 0) != hipSuccess) return TC_E_HIP;
     if (hipGetLastError() != hipSuccess) return TC_E_HIP;
     return TC_OK;
@@ -947,7 +956,7 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
                        (const int32_t*)sv, m, dst, t, (int32_t*)nullptr, g->pair_dst, g->pair_t,
                        g->pair_eid, (uint4*)nullptr);
     // 5. pair-run hash table (the sorted src keys are still in sk)
-    build_pair_hash(sk, g, m, tab, st);
+    build_pair_hash(sk, g, m, tab, st, true);
   }
   if (hipGetLastError() != hipSuccess) return TC_E_HIP;
   return TC_OK;
