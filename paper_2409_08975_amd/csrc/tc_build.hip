@@ -636,7 +636,7 @@ struct GraphLayout {
   size_t out_off, in_off, out_src, out_dst, out_eid, out_t, in_src, in_eid, in_dst, in_t,
       pair_dst, out_rec, in_rec,
       pair_eid, pair_t, pair_hash, pair_skip, status, tminmax, keys0, keys1, vals0, vals1, hist, part,
-      part_elems, rr[4], hist2, part2, total;
+      part_elems, rr[4], total;
 };
 
 static GraphLayout graph_layout(int32_t n, int64_t m) {
@@ -687,9 +687,6 @@ static GraphLayout graph_layout(int32_t n, int64_t m) {
   // scan scratch of the histogram column scan
   L.part_elems = col_scan_scratch_elems(ntiles);
   L.part = take(L.part_elems * 4);
-  // histogram and scan scratch of the side stream
-  L.hist2 = take((size_t)256 * ntiles * 4);
-  L.part2 = take(L.part_elems * 4);
   L.total = o;
   return L;
 }
@@ -730,6 +727,12 @@ static int bitlen(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
 
 // The pair-run table and the sampled pair times, from the pair index's
 // sorted src keys.
+static void clear_pair_hash(const tc_graph* g, hipStream_t st) {
+  const int64_t cap = (int64_t)1 << g->pair_hash_log2;
+  hipLaunchKernelGGL(k_hash_clear, dim3(blocks_for(cap, 256)), dim3(256), 0, st,
+                     (PairSlot*)g->pair_hash, cap);
+}
+
 static void build_pair_hash(const uint32_t* psrc, const tc_graph* g, int64_t m, PairSlot* tab,
                             hipStream_t st, bool with_skip) {
   if (with_skip) {
@@ -783,12 +786,6 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     hipLaunchKernelGGL(k_validate, dim3(vb), dim3(256), 0, st, src, dst, t, m, n, g->status,
                        tminmax);
   }
-  // the run table is cleared while the host waits for the validation below
-  {
-    const int64_t cap = (int64_t)1 << g->pair_hash_log2;
-    hipLaunchKernelGGL(k_hash_clear, dim3(blocks_for(cap, 256)), dim3(256), 0, st,
-                       (PairSlot*)g->pair_hash, cap);
-  }
   uint32_t h_status = 0;
   uint64_t h_mm[2] = {0, 0};
   if (hipMemcpyAsync(&h_status, g->status, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -806,6 +803,7 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   const int vbits = bitlen((uint64_t)(n - 1));
   PairSlot* tab = (PairSlot*)g->pair_hash;
   if (m == 0) {
+    clear_pair_hash(g, st);
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for((int64_t)n + 1, 256)), dim3(256), 0, st,
                        g->out_off, (int64_t)n + 1, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for((int64_t)n + 1, 256)), dim3(256), 0, st,
@@ -814,17 +812,15 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     return TC_OK;
   }
   if (tbits <= 32) {
-    // record-carrying sorts.  This stream sorts by time, then the in-CSR and
-    // the pair index, then builds the run table (random atomics, latency
-    // bound); the out-CSR sort and the out-to-in positions (bandwidth bound)
-    // run meanwhile on a second stream.  Four record buffers: the time sort
-    // ping-pongs in 0 and 1, the in-CSR sort in 2 and the free one of those,
-    // the pair sort in 3 and the one the in-CSR sort left free, and the
-    // out-CSR sort in A (the time sort's result) and the in-CSR result.
+    // record-carrying sorts.  This stream sorts by time, then the in-CSR,
+    // the pair index and the out-CSR (bandwidth bound).  A second stream
+    // clears the run table during the sorts and builds it (random atomics,
+    // latency bound) beside the out-CSR sort.  Four record buffers: the time
+    // sort ping-pongs in 0 and 1, the in-CSR sort in 2 and the free one of
+    // those, the pair sort in 3 and the one the in-CSR sort left free, and
+    // the out-CSR sort in A (the time sort's result) and the in-CSR result.
     uint4* rr[4];
     for (int b = 0; b < 4; ++b) rr[b] = (uint4*)(base + L.rr[b]);
-    uint32_t* hist2 = (uint32_t*)(base + L.hist2);
-    uint32_t* part2 = (uint32_t*)(base + L.part2);
     auto sort_rec = [&](int from, int tmp, int bits, uint32_t* h, uint32_t* pt, hipStream_t s,
                         int xf1 = RX_NONE, int extra = -1, int xf2 = RX_NONE,
                         const EdgeCols* first = nullptr) -> int {
@@ -847,6 +843,14 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
       hipLaunchKernelGGL(k_rec_init, dim3(eb), dim3(256), 0, st, src, dst, t, m, tmin, rr[0]);
     const int A = sort_rec(0, 1, tbits, hist, part, st, RX_OUT, 2, RX_IN, tbits ? &ec : nullptr);
     if (A < 0) return TC_E_WORKSPACE;
+    // the second stream clears the run table meanwhile (ordered after the
+    // caller's earlier work on this stream)
+    if (two) {
+      if (hipEventRecord(S->fork, st) != hipSuccess ||
+          hipStreamWaitEvent(s2, S->fork, 0) != hipSuccess)
+        return TC_E_HIP;
+    }
+    clear_pair_hash(g, s2);
     const int B = 2, F = 1 - A;
     // in-CSR: stable by dst; a second copy of the result, re-keyed, is the
     // pair index input (buffer 3)
@@ -870,21 +874,23 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
           hipStreamWaitEvent(s2, S->fork, 0) != hipSuccess)
         return TC_E_HIP;
     }
-    // second stream: out-CSR (stable by src), with the in-CSR records'
-    // buffer (emitted before the fork) as its spare
-    const int R = sort_rec(A, I, vbits, hist2, part2, s2);
+    // second stream: the run table, after its clear (the pair emit wrote
+    // the sampled levels)
+    build_pair_hash(psrc, g, m, tab, s2, false);
+    if (two && hipEventRecord(S->out_done, s2) != hipSuccess) return TC_E_HIP;
+    // this stream, meanwhile: out-CSR (stable by src), with the in-CSR
+    // records' buffer (emitted before the fork) as its spare
+    const int R = sort_rec(A, I, vbits, hist, part, st);
     if (R < 0) return TC_E_WORKSPACE;
-    hipLaunchKernelGGL(k_emit, dim3(blocks_for(m + 1, 256)), dim3(256), 0, s2,
+    hipLaunchKernelGGL(k_emit, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
                        (const uint4*)rr[R], m, tmin, g->out_src, g->out_dst, g->out_t,
                        g->out_eid, (uint4*)g->out_rec, n, g->out_off, (int64_t*)nullptr);
-    if (two && hipEventRecord(S->out_done, s2) != hipSuccess) return TC_E_HIP;
-    // this stream: the run table (the pair emit wrote the sampled levels)
-    build_pair_hash(psrc, g, m, tab, st, false);
     if (two && hipStreamWaitEvent(st, S->out_done, 0) != hipSuccess) return TC_E_HIP;
     if (hipGetLastError() != hipSuccess) return TC_E_HIP;
     return TC_OK;
   }
   // wide time range: 64-bit time keys, columns gathered after each sort
+  clear_pair_hash(g, st);
   // 1. time order: stable by t (initial order = eid)
   int32_t* torder;
   if (m > 0) {
