@@ -668,8 +668,10 @@ static GraphLayout graph_layout(int32_t n, int64_t m) {
   L.pair_hash = take(sizeof(PairSlot) << pair_hash_log2(m));
   L.pair_skip =
       take((size_t)(skip_level_len(m, 1) + skip_level_len(m, 2) + skip_level_len(m, 3)) * 8);
-  L.status = take(4);
-  L.tminmax = take(16);
+  // the status word and, 16 bytes on, the time min/max keys: one 32-byte
+  // read-back after the validation
+  L.status = take(32);
+  L.tminmax = L.status + 16;
   // sort scratch: four 16-byte-record buffers for the record-carrying
   // sorts (two per concurrent branch), aliased by the
   // 64-bit-key buffers of the wide-time path (the two paths never run in the
@@ -786,15 +788,20 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     hipLaunchKernelGGL(k_validate, dim3(vb), dim3(256), 0, st, src, dst, t, m, n, g->status,
                        tminmax);
   }
-  uint32_t h_status = 0;
-  uint64_t h_mm[2] = {0, 0};
-  if (hipMemcpyAsync(&h_status, g->status, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipMemcpyAsync(h_mm, tminmax, 16, hipMemcpyDeviceToHost, st) != hipSuccess ||
+  // read back into pinned memory (one per host thread, kept for the
+  // process): a pageable copy is staged, and its latency sits between the
+  // validation and the first sort
+  static thread_local uint64_t* pinned = nullptr;
+  if (!pinned && hipHostMalloc((void**)&pinned, 32, hipHostMallocDefault) != hipSuccess)
+    pinned = nullptr;
+  uint64_t local[4] = {0, 0, 0, 0};
+  uint64_t* rb = pinned ? pinned : local;
+  if (hipMemcpyAsync(rb, g->status, 32, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return TC_E_HIP;
-  if (h_status != 0) return TC_E_RANGE;
-  const int64_t tmin = m > 0 ? (int64_t)(h_mm[0] ^ (1ull << 63)) : 0;
-  const int64_t tmax = m > 0 ? (int64_t)(h_mm[1] ^ (1ull << 63)) : 0;
+  if ((uint32_t)rb[0] != 0) return TC_E_RANGE;
+  const int64_t tmin = m > 0 ? (int64_t)(rb[2] ^ (1ull << 63)) : 0;
+  const int64_t tmax = m > 0 ? (int64_t)(rb[3] ^ (1ull << 63)) : 0;
   g->t_min = tmin;
   g->t_max = tmax;
   const unsigned eb = blocks_for(m > 0 ? m : 1, 256);
