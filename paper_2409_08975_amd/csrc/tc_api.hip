@@ -57,7 +57,7 @@ tc_status compile_motifs(const tc_motif* motifs, int32_t n_motifs, MotifPlan* pl
 
 extern "C" {
 
-const char* tc_version(void) { return "tc 0.1 gfx950"; }
+const char* tc_version(void) { return "tc 0.2 gfx950"; }
 
 tc_status tc_graph_workspace_bytes(int32_t n, int64_t m, size_t* bytes) {
   if (!bytes || n < 1 || m < 0 || m >= ((int64_t)1 << 31)) return TC_E_ARG;
