@@ -167,6 +167,16 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _on_stream(stream, *tensors):
+    """Tie tensors allocated on the current stream to the explicit stream
+    their kernels are enqueued on, so the caching allocator does not hand
+    their memory to other work before those kernels are done."""
+    if stream is not None:
+        for t in tensors:
+            if t is not None:
+                t.record_stream(stream)
+
+
 def make_motif(edges, nv: int = 4) -> tc_motif:
     m = tc_motif()
     m.nv = nv
@@ -327,6 +337,7 @@ def tc_build_graph(n: int, src: torch.Tensor, dst: torch.Tensor, t: torch.Tensor
     nbytes = graph_workspace_bytes(n, m)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=src.device)
     g = tc_graph()
+    _on_stream(stream, ws, src, dst, t)
     _check(lib().tc_build_graph(n, m, _ptr(src), _ptr(dst), _ptr(t), _ptr(ws), nbytes,
                                 _stream(stream), ctypes.byref(g)), "tc_build_graph")
     return Graph(g, ws, (src, dst, t))
@@ -336,6 +347,7 @@ def tc_path_weights(graph: Graph, delta: int, stream=None) -> Weights:
     nbytes = weights_workspace_bytes(graph.m)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=graph.ws.device)
     w = tc_weights()
+    _on_stream(stream, ws)
     _check(lib().tc_path_weights(ctypes.byref(graph.c), int(delta), _ptr(ws), nbytes,
                                  _stream(stream), ctypes.byref(w)), "tc_path_weights")
     return Weights(w, ws, graph)
@@ -383,6 +395,8 @@ def tc_sample_estimate(graph: Graph, weights: Weights, motifs, k: int, seed: int
     dev = graph.ws.device
     if out is None:
         out = new_result(nm, k, dev, per_sample, moments)
+        _on_stream(stream, out.cnt, out.hits, out.estimate, out.status, out.e1, out.e2, out.e3,
+                   out.X, out.P, out.m2)
     r = _c_result(out)
     ws = _sample_ws(k, nm, dev, 1, stream) if workspace is None else workspace
     _check(lib().tc_sample_estimate(ctypes.byref(graph.c), ctypes.byref(weights.c), arr, nm,
@@ -413,6 +427,8 @@ def tc_batch_estimate(graph: Graph, weights, motifs, k: int, seed: int, stream_i
     dev = graph.ws.device
     if outs is None:
         outs = [new_result(nm, k, dev, per_sample) for _ in range(nd)]
+        for o in outs:
+            _on_stream(stream, o.cnt, o.hits, o.estimate, o.status, o.e1, o.e2, o.e3, o.X, o.P)
     args = _BatchArgs(weights, outs)
     ws = _sample_ws(k, nm, dev, nd, stream) if workspace is None else workspace
     _check(lib().tc_batch_estimate(ctypes.byref(graph.c), ctypes.cast(args.wp, _P), nd, arr, nm,
@@ -451,6 +467,7 @@ def tc_edge_features(graph: Graph, weights: Weights, stream=None) -> torch.Tenso
     _check(lib().tc_features_workspace_bytes(graph.m, ctypes.byref(b)),
            "tc_features_workspace_bytes")
     ws = torch.empty(b.value, dtype=torch.uint8, device=graph.ws.device)
+    _on_stream(stream, feat, ws)
     _check(lib().tc_edge_features(ctypes.byref(graph.c), ctypes.byref(weights.c), _ptr(feat),
                                   _ptr(ws), b.value, _stream(stream)), "tc_edge_features")
     return feat
@@ -460,6 +477,7 @@ def tc_mlp_forward(params: torch.Tensor, feat: torch.Tensor, n: int | None = Non
                    stream=None, out: torch.Tensor | None = None) -> torch.Tensor:
     n = feat.shape[0] if n is None else n
     g = torch.empty(n, dtype=torch.float32, device=feat.device) if out is None else out
+    _on_stream(stream, g)
     _check(lib().tc_mlp_forward(_ptr(params), _ptr(feat), int(n), _ptr(g), _stream(stream)),
            "tc_mlp_forward")
     return g
@@ -480,6 +498,7 @@ def tc_mlp_grad(params, feat, rows, X, n: int | None = None, label_cap: float = 
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     nb = mlp_workspace_bytes(n)
     ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    _on_stream(stream, grad, loss, ws)
     _check(lib().tc_mlp_grad(_ptr(params), _ptr(feat), int(feat.shape[0]), _ptr(rows), _ptr(X),
                              int(n), float(label_cap), _ptr(grad), _ptr(loss), _ptr(ws), nb,
                              _stream(stream)), "tc_mlp_grad")
@@ -499,6 +518,7 @@ def tc_mlp_train(params, opt, feat, rows, X, batch: int, epochs: int, lr: float,
     losses = torch.empty(epochs, dtype=torch.float32, device=dev)
     nb = mlp_workspace_bytes(batch)
     ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    _on_stream(stream, losses, ws)
     _check(lib().tc_mlp_train(_ptr(params), _ptr(opt), _ptr(feat), int(feat.shape[0]), _ptr(rows),
                               _ptr(X), int(n), float(label_cap), int(batch), int(epochs),
                               float(lr), int(seed), int(step0), _ptr(losses), _ptr(ws),
@@ -512,6 +532,7 @@ def tc_quantize_proposal(weights: Weights, g: torch.Tensor, eps: float = 0.1,
     scores are divided by their maximum first."""
     h = torch.empty(weights.c.m, dtype=torch.int32, device=g.device)
     gmax = torch.empty(1, dtype=torch.float32, device=g.device) if normalize else None
+    _on_stream(stream, h, gmax)
     _check(lib().tc_quantize_proposal(ctypes.byref(weights.c), _ptr(g), float(eps), _ptr(gmax),
                                       _ptr(h), _stream(stream)), "tc_quantize_proposal")
     return h
@@ -531,6 +552,7 @@ def tc_proposal_weights(graph: Graph, weights: Weights, h: torch.Tensor,
     nb = proposal_workspace_bytes(graph.m)
     ws = torch.empty(nb, dtype=torch.uint8, device=graph.ws.device)
     wq = tc_weights()
+    _on_stream(stream, ws, h)
     _check(lib().tc_proposal_weights(ctypes.byref(graph.c), ctypes.byref(weights.c), _ptr(h),
                                      _ptr(ws), nb, ctypes.byref(wq), _stream(stream)),
            "tc_proposal_weights")

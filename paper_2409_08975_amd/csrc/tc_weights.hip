@@ -253,26 +253,25 @@ __global__ __launch_bounds__(kWBlock) void k_scan_apply(const uint32_t* __restri
   uint64_t w[kWItems];
   uint64_t s = 0;
   if (p0 + kWItems <= m) {
-    const uint4* a4 = reinterpret_cast<const uint4*>(a + p0);
-    const uint4* b4 = reinterpret_cast<const uint4*>(b + p0);
-    uint4 aa0 = a4[0], aa1 = a4[1], bb0 = b4[0], bb1 = b4[1];
-    uint32_t av[8] = {aa0.x, aa0.y, aa0.z, aa0.w, aa1.x, aa1.y, aa1.z, aa1.w};
-    uint32_t bv[8] = {bb0.x, bb0.y, bb0.z, bb0.w, bb1.x, bb1.y, bb1.z, bb1.w};
-    if (H) {
-      const uint4* h4 = reinterpret_cast<const uint4*>(h + p0);
-      const uint4 hh0 = h4[0], hh1 = h4[1];
-      const uint32_t hv[8] = {hh0.x, hh0.y, hh0.z, hh0.w, hh1.x, hh1.y, hh1.z, hh1.w};
+    // kWItems consecutive words per array, as kWItems / 4 aligned 16-byte
+    // loads (p0 is a multiple of kWItems): nothing past p0 + kWItems is read
+    static_assert(kWItems % 4 == 0, "16-byte loads of whole items");
+    uint32_t av[kWItems], bv[kWItems], hv[kWItems];
 #pragma unroll
-      for (int j = 0; j < kWItems; ++j) {
-        w[j] = (uint64_t)av[j] * (uint64_t)bv[j] * (uint64_t)hv[j];
-        s += w[j];
+    for (int q = 0; q < kWItems / 4; ++q) {
+      const uint4 aa = reinterpret_cast<const uint4*>(a + p0)[q];
+      const uint4 bb = reinterpret_cast<const uint4*>(b + p0)[q];
+      av[4 * q] = aa.x, av[4 * q + 1] = aa.y, av[4 * q + 2] = aa.z, av[4 * q + 3] = aa.w;
+      bv[4 * q] = bb.x, bv[4 * q + 1] = bb.y, bv[4 * q + 2] = bb.z, bv[4 * q + 3] = bb.w;
+      if (H) {
+        const uint4 hh = reinterpret_cast<const uint4*>(h + p0)[q];
+        hv[4 * q] = hh.x, hv[4 * q + 1] = hh.y, hv[4 * q + 2] = hh.z, hv[4 * q + 3] = hh.w;
       }
-    } else {
+    }
 #pragma unroll
-      for (int j = 0; j < kWItems; ++j) {
-        w[j] = (uint64_t)av[j] * (uint64_t)bv[j];
-        s += w[j];
-      }
+    for (int j = 0; j < kWItems; ++j) {
+      w[j] = (uint64_t)av[j] * (uint64_t)bv[j] * (H ? (uint64_t)hv[j] : 1ull);
+      s += w[j];
     }
   } else {
 #pragma unroll

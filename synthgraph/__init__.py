@@ -272,6 +272,16 @@ def gen_overflow_layers(l1: int, l2: int, l3: int) -> TemporalGraph:
     return TemporalGraph(4, src, dst, t, name="overflow-layers")
 
 
+def relabel_spread(g: TemporalGraph, n_new: int, seed: int) -> TemporalGraph:
+    """The same edges with vertex ids mapped injectively onto random ids in
+    [0, n_new) (n_new >= g.n): exercises wide vertex ids (more radix passes,
+    large offset arrays) on a small edge list."""
+    rng = np.random.default_rng(seed)
+    ids = np.sort(rng.choice(n_new, size=g.n, replace=False)).astype(np.int32)
+    rng.shuffle(ids)
+    return TemporalGraph(n_new, ids[g.src], ids[g.dst], g.t.copy(), name=g.name + "-spread")
+
+
 def random_bf16_bits(seed: int, shape, exp_lo: int = 118, exp_hi: int = 129) -> np.ndarray:
     """bfloat16 bit patterns (uint16) with random sign, a biased exponent in
     [exp_lo, exp_hi] and random 7-bit mantissa: magnitudes roughly

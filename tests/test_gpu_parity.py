@@ -200,6 +200,30 @@ def test_determinism_repeat_runs(tcb, tiny):
     assert np.array_equal(a.estimate.cpu().numpy(), b.estimate.cpu().numpy())
 
 
+def test_counter_high_word_crossed(tcb, tiny):
+    """Samples i0 .. i0 + k - 1 straddle i = 2^32: the Philox counter's
+    second word changes inside the call."""
+    g, G, og = tiny
+    Wt = tcb.tc_path_weights(G, 20000)
+    ow = og.weights(20000)
+    i0 = (1 << 32) - 1000
+    check_sample(tcb, G, Wt, og, ow, SIX, 2000, seed=5, stream=3, i0=i0)
+    # and far above: the high word well past zero
+    check_sample(tcb, G, Wt, og, ow, SIX, 1500, seed=6, stream=0, i0=(1 << 40) + 77)
+
+
+def test_wide_vertex_ids_four_pass_sorts(tcb, torch_mod):
+    """Vertex ids spread over [0, 2^26): 26-bit keys take four radix passes
+    per vertex sort and the offset arrays have 2^26 + 1 entries."""
+    g = sg.relabel_spread(sg.gen_tiny(), 1 << 26, seed=41)
+    G, og = build_both(tcb, torch_mod, g)
+    check_graph(G, og, g)
+    Wt = tcb.tc_path_weights(G, 20000)
+    ow = og.weights(20000)
+    check_weights(Wt, ow, g, og)
+    check_sample(tcb, G, Wt, og, ow, SIX, 40000, seed=2)
+
+
 # --------------------------------------------------- micro / edge cases ----
 @pytest.mark.parametrize("seed", range(6))
 def test_planted_micro(tcb, torch_mod, seed):

@@ -96,6 +96,114 @@ def test_forward_bf16_close_to_exact():
     assert np.max(np.abs(a - b)) < 0.05
 
 
+def _torch_forward(P, F):
+    """The same network through torch.nn.functional in float64 on the CPU: a
+    library implementation of linear, ReLU and sigmoid, independent of the
+    oracle's numpy code.  torch's linear takes weights as [out, in], which is
+    the row = unit layout of the parameter vector."""
+    import torch
+    import torch.nn.functional as tF
+    p = torch.from_numpy(np.asarray(P, np.float64))
+    x = torch.from_numpy(np.asarray(F, np.float64))
+    W1 = p[learn.OFF_W1:learn.OFF_B1].reshape(64, 8)
+    W2 = p[learn.OFF_W2:learn.OFF_B2].reshape(64, 64)
+    w3 = p[learn.OFF_W3:learn.OFF_B3].reshape(1, 64)
+    h1 = tF.relu(tF.linear(x, W1, p[learn.OFF_B1:learn.OFF_W2]))
+    h2 = tF.relu(tF.linear(h1, W2, p[learn.OFF_B2:learn.OFF_W3]))
+    z3 = tF.linear(h2, w3, p[learn.OFF_B3:learn.OFF_B3 + 1])[:, 0]
+    return z3, torch.sigmoid(z3)
+
+
+def test_forward_and_loss_match_torch_float64():
+    import torch
+    import torch.nn.functional as tF
+    rng = np.random.default_rng(8)
+    P = rand_params(rng, scale=0.4)
+    F = rng.standard_normal((300, 8)) * 2.0
+    y = (rng.random(300) < 0.3).astype(np.float64)
+    c = learn.forward(P, F, bf16=False)
+    z3, g = _torch_forward(P, F)
+    assert np.allclose(c["z3"], z3.numpy(), rtol=1e-12, atol=1e-12)
+    assert np.allclose(c["g"], g.numpy(), rtol=1e-12, atol=1e-14)
+    ref = tF.binary_cross_entropy_with_logits(z3, torch.from_numpy(y)).item()
+    assert abs(learn.bce_loss(c["z3"], y) - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+def test_gradient_matches_torch_autograd_float64():
+    import torch
+    import torch.nn.functional as tF
+    rng = np.random.default_rng(9)
+    P = rand_params(rng, scale=0.4).astype(np.float64)
+    F = rng.standard_normal((64, 8))
+    y = (rng.random(64) < 0.5).astype(np.float64)
+    loss, G = learn.grad(P, F, y, bf16=False)
+    p = torch.from_numpy(P.copy()).requires_grad_(True)
+    x = torch.from_numpy(F)
+    h1 = tF.relu(tF.linear(x, p[learn.OFF_W1:learn.OFF_B1].reshape(64, 8),
+                           p[learn.OFF_B1:learn.OFF_W2]))
+    h2 = tF.relu(tF.linear(h1, p[learn.OFF_W2:learn.OFF_B2].reshape(64, 64),
+                           p[learn.OFF_B2:learn.OFF_W3]))
+    z3 = (h2 @ p[learn.OFF_W3:learn.OFF_B3]) + p[learn.OFF_B3]
+    L = tF.binary_cross_entropy_with_logits(z3, torch.from_numpy(y))
+    L.backward()
+    assert abs(loss - L.item()) <= 1e-12
+    assert np.allclose(G, p.grad.numpy(), rtol=1e-10, atol=1e-13)
+
+
+def _zero_params():
+    return np.zeros(learn.N_PARAMS, np.float32)
+
+
+def test_forward_hand_computed_constant_second_layer():
+    """W2 = 0 makes the output independent of the input:
+    g = sigmoid(sum_i w3_i relu(b2_i) + b3).  With b2 = (1, -1, 2, 0, ...),
+    w3 = (0.5, 3, 0.25, 7, ...) and b3 = -1 this is sigmoid(0.5 + 0.5 - 1) =
+    1/2; a missing second ReLU would add -3, a wrong output bias would move
+    it off 0."""
+    P = _zero_params()
+    P[learn.OFF_B2:learn.OFF_B2 + 4] = [1.0, -1.0, 2.0, 0.0]
+    P[learn.OFF_W3:learn.OFF_W3 + 4] = [0.5, 3.0, 0.25, 7.0]
+    P[learn.OFF_B3] = -1.0
+    P[learn.OFF_W1:learn.OFF_B1] = np.linspace(-1, 1, 512, dtype=np.float32)  # irrelevant
+    F = np.random.default_rng(0).standard_normal((5, 8))
+    for bf16 in (False, True):
+        c = learn.forward(P, F, bf16=bf16)
+        assert np.all(c["z3"] == 0.0) and np.all(c["g"] == 0.5)
+    # loss at z3 = 0 is ln 2 whatever the labels
+    assert abs(learn.bce_loss(np.zeros(4), [0, 1, 1, 0]) - math.log(2.0)) < 1e-15
+
+
+def test_forward_hand_computed_single_path():
+    """One live unit in each layer: unit 0 of layer 1 reads feature 2 only
+    (W1[0][2] = 2, row = unit), b1[0] = -1; unit 0 of layer 2 is
+    -h1_0 + 1; the output is that unit.  For f_2 = 3: z1 = 5, z2 = -4 ->
+    relu 0, g = sigmoid(b3) = sigmoid(0.25).  For f_2 = 0.2: z1 = -0.6 ->
+    relu 0, z2 = 1, g = sigmoid(1.25).  A transposed W1 (unit 2 reading
+    feature 0), a missing first ReLU (z2 = 1.6) or a missing second ReLU
+    (z2 = -4 kept) each change one of the two values."""
+    P = _zero_params()
+    P[learn.OFF_W1 + 0 * 8 + 2] = 2.0
+    P[learn.OFF_B1 + 0] = -1.0
+    P[learn.OFF_W2 + 0 * 64 + 0] = -1.0
+    P[learn.OFF_B2 + 0] = 1.0
+    P[learn.OFF_W3 + 0] = 1.0
+    P[learn.OFF_B3] = 0.25
+    F = np.zeros((3, 8))
+    F[0, 2] = 3.0
+    F[1, 2] = 0.2
+    F[2, 0] = 5.0        # feature 0 only: unit 0 sees nothing
+    c = learn.forward(P, F, bf16=False)
+    sig = lambda z: 1.0 / (1.0 + math.exp(-z))
+    assert np.allclose(c["z3"], [0.25, 1.25, 1.25], rtol=0, atol=1e-15)
+    assert np.allclose(c["g"], [sig(0.25), sig(1.25), sig(1.25)], rtol=0, atol=1e-15)
+    # every value here is exact in bfloat16
+    assert np.allclose(learn.forward(P, F, bf16=True)["z3"], [0.25, 1.25, 1.25], atol=0)
+    # loss against labels (1, 0, 1): -log g, -log(1 - g), -log g, averaged
+    y = np.array([1.0, 0.0, 1.0])
+    want = (-math.log(sig(0.25)) - math.log(1 - sig(1.25)) - math.log(sig(1.25))) / 3
+    assert abs(learn.bce_loss(c["z3"], y) - want) < 1e-15
+
+
 # --------------------------------------------------------- quantisation ----
 def test_quant_shift():
     assert learn.quant_shift(0) == 16
