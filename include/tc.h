@@ -16,9 +16,9 @@
  *     (host) pointers are read during the call only.
  *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
  *     Every call is stream-ordered and returns as soon as its kernels are
- *     enqueued, except tc_build_graph, which waits once for its own
- *     validation result (see there).
- *   - The library allocates no memory.  The caller provides workspaces of at
+ *     enqueued (tc_autotune alone waits, for its timings).
+ *   - The library allocates no device memory and creates no streams.  The
+ *     caller provides workspaces of at
  *     least the size reported by the *_workspace_bytes queries; tc_graph and
  *     tc_weights then hold pointers into those workspaces (borrowed: keep the
  *     workspace alive while the struct is used).  There is no free call.
@@ -43,7 +43,7 @@ extern "C" {
 typedef enum {
   TC_OK = 0,
   TC_E_ARG = -1,          /* null pointer, bad size, bad delta or k            */
-  TC_E_RANGE = -2,        /* vertex id outside [0, n) or |t| >= 2^62 (build)    */
+  TC_E_RANGE = -2,        /* reserved for host-side reporting of TC_F_RANGE     */
   TC_E_OVERFLOW = -3,     /* reserved for host-side reporting of TC_F_OVERFLOW  */
   TC_E_UNSUPPORTED = -4,  /* motif not anchored on the directed 3-path 0-1-2-3   */
   TC_E_WORKSPACE = -5,    /* workspace smaller than the query reported          */
@@ -82,7 +82,8 @@ typedef struct {
 typedef struct tc_graph {
   int32_t n;
   int64_t m;
-  int64_t t_min, t_max;               /* host copies, valid after the build   */
+  int64_t *t_range;                   /* [2] (device): t_min, t_max of the input
+                                         (0, 0 when m = 0 or the input is rejected) */
   uint32_t *out_off;                  /* [n+1] */
   int32_t *out_src, *out_dst, *out_eid;
   int64_t *out_t;                     /* [m] each */
@@ -199,13 +200,18 @@ tc_status tc_graph_workspace_bytes(int32_t n, int64_t m, size_t *bytes);
 
 /* Build the temporal adjacency of the multigraph given by src, dst, t
  * (device, [m] each, eid = index).  Requires 0 <= src, dst < n and
- * |t| < 2^62.  Enqueues the validation, three stable radix sorts and the
- * offset computation on `stream`, and waits once for the validation word and
- * the time range (so that a bad graph is reported here as TC_E_RANGE and the
- * number of radix passes follows the actual time range).  On TC_OK, *g
- * describes the graph and its arrays are ready in stream order.
+ * |t| < 2^62.  Enqueue only: the validation, the stable radix sorts (the
+ * number of time-sort passes that do work is decided on the device from the
+ * time range), the offsets and the pair-run table, all on `stream`, with no
+ * host synchronisation and no allocation, so the call can be captured in a
+ * HIP graph.  On TC_OK, *g describes the graph and its arrays are ready in
+ * stream order.  A bad vertex id or time sets TC_F_RANGE in the device word
+ * *g->status and leaves the arrays undefined; tc_path_weights on such a
+ * graph reports TC_F_RANGE in its own status word with W = 0, and the
+ * sampler then draws nothing.  The input arrays must stay alive until the
+ * enqueued work has run.
  * Errors: TC_E_ARG (null pointers, n < 1, m < 0, m >= 2^31),
- * TC_E_WORKSPACE, TC_E_RANGE, TC_E_HIP. */
+ * TC_E_WORKSPACE, TC_E_HIP. */
 tc_status tc_build_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                          const int64_t *t, void *ws, size_t ws_bytes, void *stream,
                          tc_graph *g);

@@ -64,8 +64,8 @@ class tc_motif(ctypes.Structure):
 
 
 class tc_graph(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("t_min", ctypes.c_int64),
-                ("t_max", ctypes.c_int64), ("out_off", _P), ("out_src", _P), ("out_dst", _P),
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("t_range", _P),
+                ("out_off", _P), ("out_src", _P), ("out_dst", _P),
                 ("out_eid", _P), ("out_t", _P), ("in_off", _P), ("in_src", _P), ("in_eid", _P),
                 ("in_dst", _P), ("in_t", _P), ("pair_dst", _P),
                 ("pair_eid", _P), ("pair_t", _P),
@@ -205,6 +205,18 @@ class Graph:
         """The build's device status word (TC_F_* bits; synchronises)."""
         return int(self.view("status", torch.int32, 1).item()) & 0xFFFFFFFF
 
+    def check(self, what="tc_build_graph"):
+        """Raise TCDeviceError if the build rejected its input (synchronises)."""
+        s = self.status()
+        if s:
+            raise TCDeviceError(s, what)
+        return self
+
+    def time_range(self):
+        """(t_min, t_max) of the input, from the device (synchronises)."""
+        tr = self.view("t_range", torch.int64, 2).cpu().tolist()
+        return tr[0], tr[1]
+
     def view(self, name, dtype, length):
         """Tensor view of one device array of the graph (no copy)."""
         ptr = getattr(self.c, name)
@@ -327,25 +339,38 @@ def _sample_ws(k: int, nm: int, device, nd: int = 1, stream=None) -> torch.Tenso
 
 
 def tc_build_graph(n: int, src: torch.Tensor, dst: torch.Tensor, t: torch.Tensor,
-                   stream=None) -> Graph:
-    """Build the temporal adjacency on the device (inputs: int32, int32, int64 CUDA tensors)."""
+                   stream=None, check: bool = False,
+                   workspace: torch.Tensor | None = None) -> Graph:
+    """Build the temporal adjacency on the device (inputs: int32, int32, int64
+    CUDA tensors).  Enqueue only; with check=True the call waits for the
+    validation and raises TCDeviceError on a bad vertex id or time."""
     assert src.is_cuda and dst.is_cuda and t.is_cuda
     assert src.dtype == torch.int32 and dst.dtype == torch.int32 and t.dtype == torch.int64
     src, dst, t = src.contiguous(), dst.contiguous(), t.contiguous()
     m = src.numel()
     assert dst.numel() == m and t.numel() == m
     nbytes = graph_workspace_bytes(n, m)
-    ws = torch.empty(nbytes, dtype=torch.uint8, device=src.device)
+    if workspace is not None:
+        assert workspace.numel() >= nbytes
+        ws = workspace
+    else:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=src.device)
     g = tc_graph()
     _on_stream(stream, ws, src, dst, t)
     _check(lib().tc_build_graph(n, m, _ptr(src), _ptr(dst), _ptr(t), _ptr(ws), nbytes,
                                 _stream(stream), ctypes.byref(g)), "tc_build_graph")
-    return Graph(g, ws, (src, dst, t))
+    G = Graph(g, ws, (src, dst, t))
+    return G.check() if check else G
 
 
-def tc_path_weights(graph: Graph, delta: int, stream=None) -> Weights:
+def tc_path_weights(graph: Graph, delta: int, stream=None,
+                    workspace: torch.Tensor | None = None) -> Weights:
     nbytes = weights_workspace_bytes(graph.m)
-    ws = torch.empty(nbytes, dtype=torch.uint8, device=graph.ws.device)
+    if workspace is not None:
+        assert workspace.numel() >= nbytes
+        ws = workspace
+    else:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=graph.ws.device)
     w = tc_weights()
     _on_stream(stream, ws)
     _check(lib().tc_path_weights(ctypes.byref(graph.c), int(delta), _ptr(ws), nbytes,

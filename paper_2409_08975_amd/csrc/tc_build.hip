@@ -5,19 +5,21 @@
 // timestamp ties keep increasing edge id (section III-A assumes time-sorted
 // per-vertex lists; the tie order is this library's convention).
 //
-// Radix sort design (gfx950, wave64): 8-bit digits, tiles of 4096 keys per
-// 256-thread block.  A pass is (1) per-tile digit histograms written
-// tile-major (each tile's 256 counts are one contiguous kilobyte), (2) a
-// column scan of that [tiles][256] matrix that turns every count into the
-// tile's global offset for its digit, (3) a
+// Radix sort design (gfx950, wave64): every sort moves 16-byte edge
+// records, tiles of 1536 records per 256-thread block.  A pass is (1)
+// per-tile digit histograms written tile-major (each tile's 256 counts are
+// one contiguous kilobyte), (2) a column scan of that [tiles][256] matrix
+// that turns every count into the tile's global offset for its digit, (3) a
 // scatter that ranks keys stably inside the tile with wavefront ballots
 // (8 ballots give the lanes sharing a digit), stages the tile in LDS in
 // digit order and writes each digit run to its global slot with coalesced
 // stores.
+//
+// The whole build is one stream-ordered launch sequence: it allocates
+// nothing, never waits on the device, and can be captured in a HIP graph.
+// The validation result and the time range stay on the device; the time
+// sort's passes read their plan from there (see BuildPlan).
 #include <hip/hip_runtime.h>
-
-#include <mutex>
-#include <type_traits>
 
 #include "tc_device.h"
 #include "tc_internal.h"
@@ -26,7 +28,6 @@ namespace tc {
 
 constexpr int kSortBlock = 256;
 constexpr uint32_t kXcds = 8;  // accelerator complex dies of an MI355X, each with its own L2
-constexpr int kSortItems = 16;
 constexpr int kRecItems = 6;  // record-carrying sorts: 1536-entry tiles (LDS holds 16 B/entry)
 constexpr int kRecTile = kSortBlock * kRecItems;
 constexpr int kColChunk = 32;  // tiles per chunk of the histogram column scan
@@ -102,41 +103,70 @@ __global__ __launch_bounds__(256) void k_validate(const int32_t* __restrict__ sr
   }
 }
 
-// ----------------------------------------------------------- key making ----
-template <typename K>
-__global__ __launch_bounds__(256) void k_time_keys(const int64_t* __restrict__ t, int64_t m,
-                                                   int64_t tmin, K* __restrict__ keys,
-                                                   int32_t* __restrict__ vals) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) {
-    keys[i] = (K)(uint64_t)(t[i] - tmin);
-    vals[i] = (int32_t)i;
-  }
+// ------------------------------------------------------------ sort plan ---
+// Every sort of the build moves whole 16-byte edge records.  The time sort
+// sorts the records by t - t_min, which needs up to 63 bits: up to four
+// passes over the low 32 bits, then (only when the range is wider than 32
+// bits) up to four over the high 32 bits.  How many of those eight launched
+// passes do work, their digit widths and their ping-pong buffers are decided
+// on the device from the validated time range (k_plan), so the host
+// enqueues the same launches whatever the data and never waits for the
+// device: the build is one stream-ordered sequence that a HIP graph can
+// capture.  A pass with no work leaves at once.
+constexpr int kTimePasses = 8;  // launched passes of the time sort (4 low + 4 high)
+
+struct BuildPlan {
+  int64_t tmin, tmax;  // time range (0, 0 for an empty or rejected input)
+  uint32_t bad;        // the validation set TC_F_RANGE: nothing after it runs
+  int32_t wide;        // the range needs more than 32 bits (high-word passes)
+  int32_t npass;       // passes of the time sort that do work
+  int32_t active[kTimePasses], order[kTimePasses], shift[kTimePasses], dbits[kTimePasses];
+};
+
+__device__ __forceinline__ int bitlen_dev(uint64_t x) { return x ? 64 - __clzll(x) : 0; }
+
+// ceil(bits / 8) passes with digit widths as equal as possible (narrow ones
+// first): fewer distinct digits per tile means longer runs in the scatter's
+// output, and fewer partly written cache lines
+__host__ __device__ inline void digit_plan(int bits, int npass, int i, int* shift, int* dbits) {
+  int sh = 0;
+  for (int q = 0; q < i; ++q) sh += (bits - sh) / (npass - q);
+  *shift = sh;
+  *dbits = (bits - sh) / (npass - i);
 }
 
-// keys[i] = vert[order[i]], vals[i] = order[i]
-__global__ __launch_bounds__(256) void k_vertex_keys(const int32_t* __restrict__ vert,
-                                                     const int32_t* __restrict__ order, int64_t m,
-                                                     uint32_t* __restrict__ keys,
-                                                     int32_t* __restrict__ vals) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) {
-    int32_t e = order[i];
-    keys[i] = (uint32_t)vert[e];
-    vals[i] = e;
+__global__ void k_plan(const uint32_t* __restrict__ status, const uint64_t* __restrict__ tminmax,
+                       int64_t m, BuildPlan* __restrict__ P) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  BuildPlan B;
+  B.bad = *status != 0 ? 1u : 0u;
+  B.tmin = B.tmax = 0;
+  B.wide = 0;
+  B.npass = 0;
+  for (int p = 0; p < kTimePasses; ++p) B.active[p] = B.order[p] = B.shift[p] = B.dbits[p] = 0;
+  if (!B.bad && m > 0) {
+    B.tmin = (int64_t)(tminmax[0] ^ (1ull << 63));
+    B.tmax = (int64_t)(tminmax[1] ^ (1ull << 63));
+    const int tbits = bitlen_dev((uint64_t)(B.tmax - B.tmin));
+    const int lo = tbits < 32 ? tbits : 32, hi = tbits - lo;
+    const int nlo = (lo + 7) / 8, nhi = (hi + 7) / 8;
+    for (int i = 0; i < nlo; ++i) {
+      B.active[i] = 1;
+      B.order[i] = i;
+      digit_plan(lo, nlo, i, &B.shift[i], &B.dbits[i]);
+    }
+    for (int i = 0; i < nhi; ++i) {
+      B.active[4 + i] = 1;
+      B.order[4 + i] = nlo + i;
+      digit_plan(hi, nhi, i, &B.shift[4 + i], &B.dbits[4 + i]);
+    }
+    B.npass = nlo + nhi;
+    B.wide = hi > 0 ? 1 : 0;
   }
+  *P = B;
 }
 
-// ----------------------------------------------------------- radix pass ----
-// `dev_m` (optional) holds the element count on the device; m is then the
-// capacity the grid was sized for.  A sort moves either (key, value) pairs
-// from two arrays, or (V = NoVal) whole 16-byte records whose first word is
-// the key.
-struct NoVal {};
-__device__ __forceinline__ uint32_t sort_key(uint32_t k) { return k; }
-__device__ __forceinline__ uint64_t sort_key(uint64_t k) { return k; }
-__device__ __forceinline__ uint32_t sort_key(const uint4& r) { return r.x; }
-
+// ------------------------------------------------------------ radix pass ---
 // Re-keying of a 16-byte edge record between the sorts of the build:
 //   RX_NONE  identity
 //   RX_OUT   (t, eid, src, dst) -> (src, eid, dst, t)   out-CSR input
@@ -150,18 +180,105 @@ __device__ __forceinline__ uint4 rec_xform(const uint4& r, int xf) {
   return r;
 }
 
-// The input edge columns, read directly by the first pass of the time sort
-// (which builds each record (t - t_min, eid, src, dst) as it loads it);
-// t == nullptr for every other pass.
+// The input edge columns (read by the first pass of the time sort, which
+// builds each record (t - t_min, eid, src, dst) as it loads it, and by the
+// first high-word pass, which re-keys each record with the high word of
+// t[eid] - t_min).
 struct EdgeCols {
   const int32_t* src;
   const int32_t* dst;
   const int64_t* t;
-  int64_t tmin;
 };
 
-// the re-keying of a sort with no pass (a key of zero bits), in place:
-// every element is read and written by the same thread
+// Where a pass reads its records from.
+enum { SRC_BUF = 0, SRC_COLS = 1, SRC_HIGH = 2 };
+
+// One launched radix pass.  With `plan` null the host planned it (the vertex
+// sorts: bit counts follow from n); otherwise it is pass `pass` of the time
+// sort and everything below `plan` is resolved on the device.
+struct RecPass {
+  const BuildPlan* plan;
+  int pass;
+  const uint4* in;  // host-planned input
+  uint4* out;       // host-planned output
+  uint4* buf[2];    // time sort: the ping-pong buffers (the sort ends in buf[0])
+  int shift, dbits;
+  int xf1;          // re-keying of the output (last pass of a sort)
+  uint4* out2;      // second, re-keyed copy (last pass), or null
+  int xf2;
+  EdgeCols ec;
+};
+
+struct PassCfg {
+  bool active;
+  int shift, dbits, src, xf1, xf2;
+  int64_t tmin;
+  const uint4* in;
+  uint4* out;
+  uint4* out2;
+};
+
+__device__ __forceinline__ PassCfg resolve(const RecPass& R) {
+  PassCfg c;
+  c.tmin = 0;
+  if (!R.plan) {
+    c.active = true;
+    c.shift = R.shift;
+    c.dbits = R.dbits;
+    c.src = SRC_BUF;
+    c.in = R.in;
+    c.out = R.out;
+    c.xf1 = R.xf1;
+    c.out2 = R.out2;
+    c.xf2 = R.xf2;
+    return c;
+  }
+  const BuildPlan& P = *R.plan;
+  const int p = R.pass;
+  c.active = P.active[p] != 0 && P.bad == 0;
+  c.shift = P.shift[p];
+  c.dbits = P.dbits[p];
+  c.tmin = P.tmin;
+  // active pass i of n writes buf[(n - 1 - i) & 1], so the last one writes
+  // buf[0]; pass 0 reads the edge columns, the others the previous output
+  const int i = P.order[p], n = P.npass;
+  c.out = R.buf[(n - 1 - i) & 1];
+  c.in = R.buf[(n - i) & 1];
+  c.src = i == 0 ? SRC_COLS : (p == 4 ? SRC_HIGH : SRC_BUF);
+  const bool last = i == n - 1;
+  c.xf1 = last ? R.xf1 : RX_NONE;
+  c.out2 = last ? R.out2 : nullptr;
+  c.xf2 = last ? R.xf2 : RX_NONE;
+  return c;
+}
+
+__device__ __forceinline__ uint4 load_rec(const PassCfg& c, const EdgeCols& ec, int64_t g) {
+  if (c.src == SRC_COLS)
+    return make_uint4((uint32_t)(uint64_t)(ec.t[g] - c.tmin), (uint32_t)g, (uint32_t)ec.src[g],
+                      (uint32_t)ec.dst[g]);
+  uint4 r = c.in[g];
+  if (c.src == SRC_HIGH) r.x = (uint32_t)((uint64_t)(ec.t[r.y] - c.tmin) >> 32);
+  return r;
+}
+
+// With no active time pass (every time equal): the records built from the
+// edge columns, re-keyed like the last pass of the time sort would leave them.
+__global__ __launch_bounds__(256) void k_rec_init(EdgeCols ec, int64_t m,
+                                                  const BuildPlan* __restrict__ plan,
+                                                  uint4* __restrict__ out, int xf1,
+                                                  uint4* __restrict__ out2, int xf2) {
+  if (plan->npass != 0 || plan->bad) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) {
+    const uint4 r = make_uint4((uint32_t)(uint64_t)(ec.t[i] - plan->tmin), (uint32_t)i,
+                               (uint32_t)ec.src[i], (uint32_t)ec.dst[i]);
+    out[i] = rec_xform(r, xf1);
+    out2[i] = rec_xform(r, xf2);
+  }
+}
+
+// the re-keying of a vertex sort with no pass (n = 1), in place: every
+// element is read and written by the same thread
 __global__ __launch_bounds__(256) void k_rec_xform(uint4* __restrict__ a, int64_t m,
                                                    int xf1, uint4* __restrict__ out2, int xf2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -172,15 +289,13 @@ __global__ __launch_bounds__(256) void k_rec_xform(uint4* __restrict__ a, int64_
   }
 }
 
-
-template <typename K, int ITEMS>
-__global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__ keys, int64_t m,
-                                                           int shift, uint32_t mask,
-                                                           uint32_t* __restrict__ hist,
-                                                           const uint32_t* __restrict__ dev_m,
-                                                           EdgeCols ec) {
+template <int ITEMS>
+__global__ __launch_bounds__(kSortBlock) void k_radix_hist(RecPass R, int64_t m,
+                                                           uint32_t* __restrict__ hist) {
   __shared__ uint32_t s_h[256];
-  if (dev_m) m = (int64_t)*dev_m < m ? (int64_t)*dev_m : m;
+  const PassCfg c = resolve(R);
+  if (!c.active) return;
+  const uint32_t mask = (1u << c.dbits) - 1u;
   s_h[threadIdx.x] = 0;
   __syncthreads();
   int64_t start = (int64_t)blockIdx.x * (kSortBlock * ITEMS);
@@ -188,8 +303,9 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__
   for (int r = 0; r < ITEMS; ++r) {
     int64_t i = start + (int64_t)r * kSortBlock + threadIdx.x;
     if (i < m) {
-      const uint64_t key = ec.t ? (uint64_t)(ec.t[i] - ec.tmin) : (uint64_t)sort_key(keys[i]);
-      atomicAdd(&s_h[(uint32_t)(key >> shift) & mask], 1u);
+      const uint32_t key = c.src == SRC_COLS ? (uint32_t)(uint64_t)(R.ec.t[i] - c.tmin)
+                                             : load_rec(c, R.ec, i).x;
+      atomicAdd(&s_h[(key >> c.shift) & mask], 1u);
     }
   }
   __syncthreads();
@@ -203,8 +319,19 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__
 // also leaves the digit totals in row `nchunks`), and an in-place walk of
 // every chunk that adds the digit base.  Every access reads or writes whole
 // 1 KB rows except the per-digit chunk scan, which touches nchunks*256 words.
+// `gate` (time sort passes) skips a pass the plan leaves idle.
+struct PassGate {
+  const BuildPlan* plan;
+  int pass;
+};
+__device__ __forceinline__ bool idle(const PassGate& G) {
+  return G.plan && (G.plan->bad || !G.plan->active[G.pass]);
+}
+
 __global__ __launch_bounds__(256) void k_col_sum(const uint32_t* __restrict__ hist,
-                                                 int64_t ntiles, uint32_t* __restrict__ csum) {
+                                                 int64_t ntiles, uint32_t* __restrict__ csum,
+                                                 PassGate gate) {
+  if (idle(gate)) return;
   const int64_t t0 = (int64_t)blockIdx.x * kColChunk;
   const int d = threadIdx.x;
   uint32_t s = 0;
@@ -219,7 +346,9 @@ __global__ __launch_bounds__(256) void k_col_sum(const uint32_t* __restrict__ hi
 }
 
 // one block per digit (blockIdx.x), chunks spread over the block's threads
-__global__ __launch_bounds__(256) void k_col_scan(uint32_t* __restrict__ csum, int64_t nchunks) {
+__global__ __launch_bounds__(256) void k_col_scan(uint32_t* __restrict__ csum, int64_t nchunks,
+                                                  PassGate gate) {
+  if (idle(gate)) return;
   __shared__ uint32_t s_w[256 / kWave];
   const int d = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t carry = 0;
@@ -245,7 +374,8 @@ __global__ __launch_bounds__(256) void k_col_scan(uint32_t* __restrict__ csum, i
 // one block per chunk; thread d walks the chunk's tiles for digit d
 __global__ __launch_bounds__(256) void k_col_apply(uint32_t* __restrict__ hist, int64_t ntiles,
                                                    const uint32_t* __restrict__ csum,
-                                                   int64_t nchunks) {
+                                                   int64_t nchunks, PassGate gate) {
+  if (idle(gate)) return;
   __shared__ uint32_t s_w[256 / kWave];
   const int d = threadIdx.x, lane = d & 63, wave = d >> 6;
   // digit base: exclusive scan of the digit totals over d
@@ -274,25 +404,18 @@ size_t col_scan_scratch_elems(int64_t ntiles) {
   return (size_t)256 * ((ntiles + kColChunk - 1) / kColChunk + 1);
 }
 
-void col_scan(uint32_t* hist, int64_t ntiles, uint32_t* csum, hipStream_t st) {
+void col_scan(uint32_t* hist, int64_t ntiles, uint32_t* csum, PassGate gate, hipStream_t st) {
   const int64_t nchunks = (ntiles + kColChunk - 1) / kColChunk;
   hipLaunchKernelGGL(k_col_sum, dim3((unsigned)nchunks), dim3(256), 0, st,
-                     (const uint32_t*)hist, ntiles, csum);
-  hipLaunchKernelGGL(k_col_scan, dim3(256), dim3(256), 0, st, csum, nchunks);
+                     (const uint32_t*)hist, ntiles, csum, gate);
+  hipLaunchKernelGGL(k_col_scan, dim3(256), dim3(256), 0, st, csum, nchunks, gate);
   hipLaunchKernelGGL(k_col_apply, dim3((unsigned)nchunks), dim3(256), 0, st, hist, ntiles,
-                     (const uint32_t*)csum, nchunks);
+                     (const uint32_t*)csum, nchunks, gate);
 }
 
-template <typename K, typename V, int ITEMS>
-__global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restrict__ kin,
-                                                              const V* __restrict__ vin,
-                                                              K* __restrict__ kout,
-                                                              V* __restrict__ vout, int64_t m,
-                                                              int shift, int dbits,
-                                                              const uint32_t* __restrict__ hist,
-                                                              const uint32_t* __restrict__ dev_m,
-                                                              int xf1, K* __restrict__ kout2,
-                                                              int xf2, EdgeCols ec) {
+template <int ITEMS>
+__global__ __launch_bounds__(kSortBlock) void k_radix_scatter(RecPass R, int64_t m,
+                                                              const uint32_t* __restrict__ hist) {
   // Each wavefront owns a contiguous quarter of the tile and ranks its keys
   // in order with ballots (no block barrier inside); one block-wide pass then
   // offsets every wavefront's digit counts by those of the wavefronts before
@@ -300,7 +423,9 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
   constexpr int kTile = kSortBlock * ITEMS;
   constexpr int kWaves = kSortBlock / kWave;
   constexpr int kSub = kWave * ITEMS;  // entries per wavefront
-  constexpr bool kHasVal = !std::is_same<V, NoVal>::value;
+  const PassCfg c = resolve(R);
+  if (!c.active) return;
+  const int shift = c.shift, dbits = c.dbits;
   const uint32_t mask = (1u << dbits) - 1u;
   // XCD-aware tile order.  Workgroups are dealt to the XCDs round robin
   // (block b to XCD b mod 8), and each XCD has its own L2.  Neighbouring
@@ -310,14 +435,12 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
   const uint32_t nb = gridDim.x, xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
   const uint32_t q = nb / kXcds, rem = nb % kXcds;
   const uint32_t tile = xcd * q + (xcd < rem ? xcd : rem) + slot;
-  if (dev_m) m = (int64_t)*dev_m < m ? (int64_t)*dev_m : m;
   if ((int64_t)tile * kTile >= m) return;
   __shared__ uint32_t s_base[256];
   __shared__ uint32_t s_excl[256];
   __shared__ uint32_t s_wcnt[kWaves][256];  // per-wavefront running digit counts
   __shared__ uint32_t s_wsum[kWaves];
-  __shared__ K s_key[kTile];
-  __shared__ V s_val[kHasVal ? kTile : 1];
+  __shared__ uint4 s_key[kTile];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t start = (int64_t)tile * kTile;
@@ -329,29 +452,14 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
   for (int w = 0; w < kWaves; ++w) s_wcnt[w][tid] = 0;
   __syncthreads();
 
-  K key[ITEMS];
-  V val[ITEMS];
+  uint4 key[ITEMS];
   uint32_t rank[ITEMS];  // rank among the wavefront's keys of the same digit
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
     const int idx = wave * kSub + r * kWave + lane;
     const bool valid = idx < len;
-    if constexpr (std::is_same<K, uint4>::value) {
-      if (ec.t) {  // uniform: the first pass of the time sort builds the records
-        const int64_t g = start + idx;
-        key[r] = valid ? make_uint4((uint32_t)(ec.t[g] - ec.tmin), (uint32_t)g,
-                                    (uint32_t)ec.src[g], (uint32_t)ec.dst[g])
-                       : K{};
-      } else {
-        key[r] = valid ? kin[start + idx] : K{};
-      }
-    } else {
-      key[r] = valid ? kin[start + idx] : K{};
-    }
-    if constexpr (kHasVal) {
-      if (valid) val[r] = vin[start + idx];
-    }
-    const uint32_t d = (uint32_t)(sort_key(key[r]) >> shift) & mask;
+    key[r] = valid ? load_rec(c, R.ec, start + idx) : uint4{};
+    const uint32_t d = (key[r].x >> shift) & mask;
     uint64_t vb = __ballot(valid);
     uint64_t peers = valid ? vb : ~vb;
 #pragma unroll
@@ -375,9 +483,9 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
     uint32_t tot = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) {
-      const uint32_t c = s_wcnt[w][tid];
+      const uint32_t cw = s_wcnt[w][tid];
       s_wcnt[w][tid] = tot;  // exclusive prefix over wavefronts
-      tot += c;
+      tot += cw;
     }
     const uint32_t inc = wave_inclusive_scan(tot);
     if (lane == 63) s_wsum[wave] = inc;
@@ -391,110 +499,94 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
   for (int r = 0; r < ITEMS; ++r) {
     const int idx = wave * kSub + r * kWave + lane;
     if (idx < len) {
-      const uint32_t d = (uint32_t)(sort_key(key[r]) >> shift) & mask;
-      const uint32_t pos = s_excl[d] + s_wcnt[wave][d] + rank[r];
-      s_key[pos] = key[r];
-      if constexpr (kHasVal) s_val[pos] = val[r];
+      const uint32_t d = (key[r].x >> shift) & mask;
+      s_key[s_excl[d] + s_wcnt[wave][d] + rank[r]] = key[r];
     }
   }
   __syncthreads();
   for (int i = tid; i < len; i += kSortBlock) {
-    const K k = s_key[i];
-    const uint32_t d = (uint32_t)(sort_key(k) >> shift) & mask;
+    const uint4 k = s_key[i];
+    const uint32_t d = (k.x >> shift) & mask;
     const int64_t gpos = (int64_t)s_base[d] + (i - (int64_t)s_excl[d]);
-    if constexpr (std::is_same<K, uint4>::value) {
-      // records: the last pass of a sort can re-key them for the next sort
-      kout[gpos] = rec_xform(k, xf1);
-      if (kout2) kout2[gpos] = rec_xform(k, xf2);
-    } else {
-      kout[gpos] = k;
-    }
-    if constexpr (kHasVal) vout[gpos] = s_val[i];
+    // the last pass of a sort can re-key the records for the next sort
+    c.out[gpos] = rec_xform(k, c.xf1);
+    if (c.out2) c.out2[gpos] = rec_xform(k, c.xf2);
   }
 }
 
-// Sort (keys, vals) of length m by the low `bits` bits of the key, stably.
-// Ping-pongs between (k0, v0) and (k1, v1); returns 0 if the result is in
-// buffer 0, 1 if in buffer 1.
-// returns -1 if the scan scratch is too small (nothing enqueued then)
-// Records (K = uint4) leave the sort re-keyed by xf1, and if `extra` is given
-// a second copy re-keyed by xf2 goes there.
-template <typename K, typename V = int32_t, int ITEMS = kSortItems>
-int radix_sort(K* k0, V* v0, K* k1, V* v1, int64_t m, int bits, uint32_t* hist,
-               uint32_t* part, size_t part_elems, hipStream_t st,
-               const uint32_t* dev_m = nullptr, int xf1 = RX_NONE, K* extra = nullptr,
-               int xf2 = RX_NONE, const EdgeCols* first = nullptr) {
+// Host-planned stable sort of m records by the low `bits` bits of their
+// first word (a vertex id), ping-ponging between k0 and k1; returns 0 if the
+// result is in k0, 1 if in k1, -1 if the scan scratch is too small (nothing
+// enqueued then).  The result is re-keyed by xf1, and if `extra` is given a
+// second copy re-keyed by xf2 goes there.
+template <int ITEMS>
+int radix_sort(uint4* k0, uint4* k1, int64_t m, int bits, uint32_t* hist, uint32_t* part,
+               size_t part_elems, hipStream_t st, int xf1 = RX_NONE, uint4* extra = nullptr,
+               int xf2 = RX_NONE) {
   if (m <= 0) return 0;
   constexpr int kTile = kSortBlock * ITEMS;
   const int64_t ntiles = (m + kTile - 1) / kTile;
   if (part_elems < col_scan_scratch_elems(ntiles)) return -1;
   int cur = 0;
-  // ceil(bits / 8) passes with digit widths as equal as possible (narrow
-  // ones first): fewer distinct digits per tile means longer runs in the
-  // scatter's output, and fewer partly written cache lines
   const int npass = (bits + 7) / 8;
-  if constexpr (std::is_same<K, uint4>::value) {
-    if (npass == 0 && (xf1 != RX_NONE || extra))
-      hipLaunchKernelGGL(k_rec_xform, dim3(blocks_for(m, 256)), dim3(256), 0, st, k0, m, xf1,
-                         extra, xf2);
-  }
-  for (int p = 0, shift = 0; p < npass; ++p) {
+  if (npass == 0 && (xf1 != RX_NONE || extra))
+    hipLaunchKernelGGL(k_rec_xform, dim3(blocks_for(m, 256)), dim3(256), 0, st, k0, m, xf1,
+                       extra, xf2);
+  for (int p = 0; p < npass; ++p) {
     const bool last = p + 1 == npass;
-    const int dbits = (bits - shift) / (npass - p);
-    const uint32_t mask = (1u << dbits) - 1u;
-    K* ki = cur ? k1 : k0;
-    V* vi = cur ? v1 : v0;
-    K* ko = cur ? k0 : k1;
-    V* vo = cur ? v0 : v1;
-    // with `first`, pass 0 reads the edge columns instead of k0 (K = uint4)
-    const EdgeCols ec = (p == 0 && first) ? *first : EdgeCols{nullptr, nullptr, nullptr, 0};
-    hipLaunchKernelGGL((k_radix_hist<K, ITEMS>), dim3((unsigned)ntiles), dim3(kSortBlock), 0, st,
-                       (const K*)ki, m, shift, mask, hist, dev_m, ec);
-    col_scan(hist, ntiles, part, st);
+    RecPass R{};
+    R.plan = nullptr;
+    R.in = cur ? k1 : k0;
+    R.out = cur ? k0 : k1;
+    digit_plan(bits, npass, p, &R.shift, &R.dbits);
+    R.xf1 = last ? xf1 : (int)RX_NONE;
+    R.out2 = last ? extra : nullptr;
+    R.xf2 = last ? xf2 : (int)RX_NONE;
+    hipLaunchKernelGGL((k_radix_hist<ITEMS>), dim3((unsigned)ntiles), dim3(kSortBlock), 0, st, R,
+                       m, hist);
+    col_scan(hist, ntiles, part, PassGate{nullptr, 0}, st);
     {
       TimedLaunch tl("k_radix_scatter", st);
-      hipLaunchKernelGGL((k_radix_scatter<K, V, ITEMS>), dim3((unsigned)ntiles), dim3(kSortBlock),
-                         0, st, (const K*)ki, (const V*)vi, ko, vo, m, shift, dbits,
-                         (const uint32_t*)hist, dev_m, last ? xf1 : (int)RX_NONE,
-                         last ? extra : (K*)nullptr, last ? xf2 : (int)RX_NONE, ec);
+      hipLaunchKernelGGL((k_radix_scatter<ITEMS>), dim3((unsigned)ntiles), dim3(kSortBlock), 0,
+                         st, R, m, (const uint32_t*)hist);
     }
     cur ^= 1;
-    shift += dbits;
   }
   return cur;
 }
 
-// -------------------------------------------------------- columns/offsets ---
-// Gather the columns of one order.  key_col receives the sort key (the
-// vertex), the optional other columns come from the input arrays.
-__global__ __launch_bounds__(256) void k_gather_order(
-    const uint32_t* __restrict__ skeys, const int32_t* __restrict__ order, int64_t m,
-    const int32_t* __restrict__ other_v, const int64_t* __restrict__ t,
-    int32_t* __restrict__ key_col, int32_t* __restrict__ other_col, int64_t* __restrict__ t_col,
-    int32_t* __restrict__ eid_col, uint4* __restrict__ rec) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) {
-    int32_t e = order[i];
-    if (key_col) key_col[i] = (int32_t)skeys[i];
-    const int32_t o = other_v[e];
-    const int64_t te = t[e];
-    if (other_col) other_col[i] = o;
-    t_col[i] = te;
-    eid_col[i] = e;
-    if (rec) rec[i] = make_uint4((uint32_t)o, (uint32_t)e, (uint32_t)te, (uint32_t)(te >> 32));
+// The time sort: kTimePasses launched passes planned on the device (see
+// BuildPlan).  It reads the edge columns and leaves the time-ordered records
+// re-keyed by xf1 in buf[0] and by xf2 in out2.
+template <int ITEMS>
+bool time_sort(const BuildPlan* plan, const EdgeCols& ec, uint4* b0, uint4* b1, int64_t m,
+               uint32_t* hist, uint32_t* part, size_t part_elems, hipStream_t st, int xf1,
+               uint4* out2, int xf2) {
+  constexpr int kTile = kSortBlock * ITEMS;
+  const int64_t ntiles = (m + kTile - 1) / kTile;
+  if (part_elems < col_scan_scratch_elems(ntiles)) return false;
+  hipLaunchKernelGGL(k_rec_init, dim3(blocks_for(m, 256)), dim3(256), 0, st, ec, m, plan, b0,
+                     xf1, out2, xf2);
+  for (int p = 0; p < kTimePasses; ++p) {
+    RecPass R{};
+    R.plan = plan;
+    R.pass = p;
+    R.buf[0] = b0;
+    R.buf[1] = b1;
+    R.xf1 = xf1;
+    R.out2 = out2;
+    R.xf2 = xf2;
+    R.ec = ec;
+    hipLaunchKernelGGL((k_radix_hist<ITEMS>), dim3((unsigned)ntiles), dim3(kSortBlock), 0, st, R,
+                       m, hist);
+    col_scan(hist, ntiles, part, PassGate{plan, p}, st);
+    hipLaunchKernelGGL((k_radix_scatter<ITEMS>), dim3((unsigned)ntiles), dim3(kSortBlock), 0, st,
+                       R, m, (const uint32_t*)hist);
   }
+  return true;
 }
 
-// off[v] = first position whose sorted key is >= v, for v in [0, n]
-__global__ __launch_bounds__(256) void k_offsets(const uint32_t* __restrict__ skeys, int64_t m,
-                                                 int32_t n, uint32_t* __restrict__ off) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i > m) return;
-  int64_t prev = (i == 0) ? -1 : (int64_t)skeys[i - 1];
-  int64_t cur = (i == m) ? (int64_t)n : (int64_t)skeys[i];
-  for (int64_t v = prev + 1; v <= cur; ++v) off[v] = (uint32_t)i;
-}
-
+// -------------------------------------------------------- columns/offsets ---
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ a, int64_t n,
                                                   uint32_t v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -519,7 +611,8 @@ __global__ __launch_bounds__(256) void k_hash_clear(PairSlot* __restrict__ tab, 
 // One thread per pair-index position.  The thread at the first position of
 // a (src, dst) run finds where the run ends -- galloping over the sorted
 // keys, then bisecting the last gap, so a run of length L costs O(log L)
-// probes and most runs (a single edge) one -- and inserts {key, start, end}.
+// probes and most runs (a single edge) one -- and inserts {key, start, end}:
+// a compare-and-swap claims the slot's key, one 8-byte store fills the run.
 __global__ __launch_bounds__(256) void k_hash_insert(const uint32_t* __restrict__ psrc,
                                                      const int32_t* __restrict__ pdst, int64_t m,
                                                      PairSlot* __restrict__ tab, int log2cap) {
@@ -550,25 +643,11 @@ __global__ __launch_bounds__(256) void k_hash_insert(const uint32_t* __restrict_
         atomicCAS((unsigned long long*)&tab[h].key, (unsigned long long)kPairEmpty,
                   (unsigned long long)key);
     if (prev == kPairEmpty) {
-      tab[h].start = (uint32_t)i;
-      tab[h].end = (uint32_t)hi;
+      *reinterpret_cast<uint2*>(&tab[h].start) = make_uint2((uint32_t)i, (uint32_t)hi);
       return;
     }
     h = (h + 1) & mask;
   }
-}
-
-// Sampled levels of the pair times: level k holds pair_t[16^k i].
-__global__ __launch_bounds__(256) void k_pair_skip(const int64_t* __restrict__ pair_t, int64_t n1,
-                                                   int64_t n2, int64_t n3,
-                                                   int64_t* __restrict__ skip) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n1)
-    skip[i] = pair_t[i << 4];
-  else if (i < n1 + n2)
-    skip[i] = pair_t[(i - n1) << 8];
-  else if (i < n1 + n2 + n3)
-    skip[i] = pair_t[(i - n1 - n2) << 12];
 }
 
 int pair_hash_log2(int64_t m) {
@@ -577,40 +656,31 @@ int pair_hash_log2(int64_t m) {
   return lg;
 }
 
-// ---------------------------------------------- sorts carrying their payload ---
-// When the time range fits 32 bits every sort moves its whole record, one
-// 16-byte word per edge: key (u32) + payload {eid, other vertex, t - t_min},
-// so each column of the three orders comes out of the last pass in order,
-// with no random gathers, and each digit run of a pass is one contiguous
-// stretch of records.
-__global__ __launch_bounds__(256) void k_rec_init(const int32_t* __restrict__ src,
-                                                  const int32_t* __restrict__ dst,
-                                                  const int64_t* __restrict__ t, int64_t m,
-                                                  int64_t tmin, uint4* __restrict__ rec) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m)
-    rec[i] = make_uint4((uint32_t)(t[i] - tmin), (uint32_t)i, (uint32_t)src[i], (uint32_t)dst[i]);
-}
-
-// sorted (key, eid, other, t - t_min) -> columns of one order
+// sorted records (key, eid, other, t - t_min) -> columns of one order.  The
+// time is t_min + the record's time word, or, when the range is wider than
+// 32 bits, read back from the input by edge id.
 // With `off` (n + 1 entries), also the CSR offsets of the sorted keys:
 // off[v] = first position whose key is >= v, written by the thread of the
 // position where the key passes v (grid of m + 1 threads).  With `skip`
 // (the pair index), also the sampled levels skip_k[i] = t[16^k i], k = 1..3,
-// from the times this pass writes anyway.
+// from the times this pass writes anyway.  A rejected input (bad vertex id or
+// time) writes nothing.
 __global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ in, int64_t m,
-                                              int64_t tmin, int32_t* __restrict__ key_col,
+                                              const BuildPlan* __restrict__ plan,
+                                              const int64_t* __restrict__ t_in,
+                                              int32_t* __restrict__ key_col,
                                               int32_t* __restrict__ other_col,
                                               int64_t* __restrict__ t_col,
                                               int32_t* __restrict__ eid_col,
                                               uint4* __restrict__ rec, int32_t n,
                                               uint32_t* __restrict__ off,
                                               int64_t* __restrict__ skip) {
+  if (plan->bad) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) {
     const uint4 r = in[i];
     key_col[i] = (int32_t)r.x;
-    const int64_t te = tmin + (int64_t)r.w;
+    const int64_t te = plan->wide ? t_in[r.y] : plan->tmin + (int64_t)r.w;
     other_col[i] = (int32_t)r.z;
     t_col[i] = te;
     eid_col[i] = (int32_t)r.y;
@@ -629,14 +699,21 @@ __global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ in, int6
   }
 }
 
+// the validation word and the time range of the plan, for tc_graph
+__global__ void k_trange(const BuildPlan* __restrict__ plan, int64_t* __restrict__ tr) {
+  if (threadIdx.x == 0) {
+    tr[0] = plan->tmin;
+    tr[1] = plan->tmax;
+  }
+}
+
 // --------------------------------------------------------------- layout ----
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct GraphLayout {
   size_t out_off, in_off, out_src, out_dst, out_eid, out_t, in_src, in_eid, in_dst, in_t,
-      pair_dst, out_rec, in_rec,
-      pair_eid, pair_t, pair_hash, pair_skip, status, tminmax, keys0, keys1, vals0, vals1, hist, part,
-      part_elems, rr[4], total;
+      pair_dst, out_rec, in_rec, pair_eid, pair_t, pair_hash, pair_skip, status, tminmax, trange,
+      plan, hist, part, part_elems, rr[4], total;
 };
 
 static GraphLayout graph_layout(int32_t n, int64_t m) {
@@ -648,7 +725,6 @@ static GraphLayout graph_layout(int32_t n, int64_t m) {
     return at;
   };
   const size_t M = (size_t)m;
-  // histograms sized for the smaller (1536-entry) tiles of the record sorts
   const int64_t ntiles = (m + kRecTile - 1) / kRecTile;
   L.out_off = take(((size_t)n + 1) * 4);
   L.in_off = take(((size_t)n + 1) * 4);
@@ -668,23 +744,12 @@ static GraphLayout graph_layout(int32_t n, int64_t m) {
   L.pair_hash = take(sizeof(PairSlot) << pair_hash_log2(m));
   L.pair_skip =
       take((size_t)(skip_level_len(m, 1) + skip_level_len(m, 2) + skip_level_len(m, 3)) * 8);
-  // the status word and, 16 bytes on, the time min/max keys: one 32-byte
-  // read-back after the validation
-  L.status = take(32);
-  L.tminmax = L.status + 16;
-  // sort scratch: four 16-byte-record buffers for the record-carrying
-  // sorts (two per concurrent branch), aliased by the
-  // 64-bit-key buffers of the wide-time path (the two paths never run in the
-  // same build)
-  const size_t region = o;
+  L.status = take(16);
+  L.tminmax = take(16);
+  L.trange = take(16);
+  L.plan = take(sizeof(BuildPlan));
+  // sort scratch: four 16-byte-record buffers
   for (int b = 0; b < 4; ++b) L.rr[b] = take((M + 1) * 16);
-  const size_t rec_end = o;
-  o = region;
-  L.keys0 = take((M + 1) * 8);
-  L.keys1 = take((M + 1) * 8);
-  L.vals0 = take((M + 1) * 4);
-  L.vals1 = take((M + 1) * 4);
-  if (o < rec_end) o = rec_end;
   L.hist = take((size_t)256 * ntiles * 4);
   // scan scratch of the histogram column scan
   L.part_elems = col_scan_scratch_elems(ntiles);
@@ -693,57 +758,15 @@ static GraphLayout graph_layout(int32_t n, int64_t m) {
   return L;
 }
 
-// Second stream of a device for the build's independent branch, created once
-// (default priority); the mutex also keeps two builds from interleaving their
-// use of it and of its events.
-struct SideStream {
-  std::mutex mu;
-  hipStream_t s = nullptr;
-  hipEvent_t fork = nullptr, out_done = nullptr;
-  bool ok = false, tried = false;
-};
-static SideStream g_side[64];
-
-static SideStream* side_stream() {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
-  SideStream* S = &g_side[dev];
-  return S;
-}
-
-// with S->mu held
-static bool side_ready(SideStream* S) {
-  if (!S->tried) {
-    S->tried = true;
-    S->ok = hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking) == hipSuccess &&
-            hipEventCreateWithFlags(&S->fork, hipEventDisableTiming) == hipSuccess &&
-            hipEventCreateWithFlags(&S->out_done, hipEventDisableTiming) == hipSuccess;
-  }
-  return S->ok;
-}
-
 size_t graph_workspace_bytes(int32_t n, int64_t m) { return graph_layout(n, m).total; }
 
 static int bitlen(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
 
-
-// The pair-run table and the sampled pair times, from the pair index's
-// sorted src keys.
+// The pair-run table from the pair index's sorted src keys.
 static void clear_pair_hash(const tc_graph* g, hipStream_t st) {
   const int64_t cap = (int64_t)1 << g->pair_hash_log2;
   hipLaunchKernelGGL(k_hash_clear, dim3(blocks_for(cap, 256)), dim3(256), 0, st,
                      (PairSlot*)g->pair_hash, cap);
-}
-
-static void build_pair_hash(const uint32_t* psrc, const tc_graph* g, int64_t m, PairSlot* tab,
-                            hipStream_t st, bool with_skip) {
-  if (with_skip) {
-    const int64_t n1 = skip_level_len(m, 1), n2 = skip_level_len(m, 2), n3 = skip_level_len(m, 3);
-    hipLaunchKernelGGL(k_pair_skip, dim3(blocks_for(n1 + n2 + n3, 256)), dim3(256), 0, st,
-                       (const int64_t*)g->pair_t, n1, n2, n3, g->pair_skip);
-  }
-  hipLaunchKernelGGL(k_hash_insert, dim3(blocks_for(m, 256)), dim3(256), 0, st, psrc,
-                     (const int32_t*)g->pair_dst, m, tab, g->pair_hash_log2);
 }
 
 tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
@@ -767,20 +790,19 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   g->pair_eid = (int32_t*)(base + L.pair_eid);
   g->pair_t = (int64_t*)(base + L.pair_t);
   g->status = (uint32_t*)(base + L.status);
+  g->t_range = (int64_t*)(base + L.trange);
   g->pair_hash = (void*)(base + L.pair_hash);
   g->pair_hash_log2 = pair_hash_log2(m);
   g->pair_skip = (int64_t*)(base + L.pair_skip);
   g->out_rec = (void*)(base + L.out_rec);
   g->in_rec = (void*)(base + L.in_rec);
   uint64_t* tminmax = (uint64_t*)(base + L.tminmax);
-  void* keys0 = base + L.keys0;
-  void* keys1 = base + L.keys1;
-  int32_t* vals0 = (int32_t*)(base + L.vals0);
-  int32_t* vals1 = (int32_t*)(base + L.vals1);
+  BuildPlan* plan = (BuildPlan*)(base + L.plan);
   uint32_t* hist = (uint32_t*)(base + L.hist);
   uint32_t* part = (uint32_t*)(base + L.part);
   const size_t pe = L.part_elems;
 
+  // validation and the sort plan, on the device
   hipLaunchKernelGGL(k_init_build, dim3(1), dim3(64), 0, st, g->status, tminmax);
   if (m > 0) {
     unsigned vb = blocks_for(m, 256);
@@ -788,189 +810,60 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     hipLaunchKernelGGL(k_validate, dim3(vb), dim3(256), 0, st, src, dst, t, m, n, g->status,
                        tminmax);
   }
-  // read back into pinned memory (one per host thread, kept for the
-  // process): a pageable copy is staged, and its latency sits between the
-  // validation and the first sort
-  static thread_local uint64_t* pinned = nullptr;
-  if (!pinned && hipHostMalloc((void**)&pinned, 32, hipHostMallocDefault) != hipSuccess)
-    pinned = nullptr;
-  uint64_t local[4] = {0, 0, 0, 0};
-  uint64_t* rb = pinned ? pinned : local;
-  if (hipMemcpyAsync(rb, g->status, 32, hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    return TC_E_HIP;
-  if ((uint32_t)rb[0] != 0) return TC_E_RANGE;
-  const int64_t tmin = m > 0 ? (int64_t)(rb[2] ^ (1ull << 63)) : 0;
-  const int64_t tmax = m > 0 ? (int64_t)(rb[3] ^ (1ull << 63)) : 0;
-  g->t_min = tmin;
-  g->t_max = tmax;
-  const unsigned eb = blocks_for(m > 0 ? m : 1, 256);
-
-  const int tbits = bitlen((uint64_t)(tmax - tmin));
-  const int vbits = bitlen((uint64_t)(n - 1));
-  PairSlot* tab = (PairSlot*)g->pair_hash;
-  if (m == 0) {
-    clear_pair_hash(g, st);
-    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for((int64_t)n + 1, 256)), dim3(256), 0, st,
-                       g->out_off, (int64_t)n + 1, 0u);
-    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for((int64_t)n + 1, 256)), dim3(256), 0, st,
-                       g->in_off, (int64_t)n + 1, 0u);
-    if (hipGetLastError() != hipSuccess) return TC_E_HIP;
-    return TC_OK;
-  }
-  if (tbits <= 32) {
-    // record-carrying sorts.  This stream sorts by time, then the in-CSR,
-    // the pair index and the out-CSR (bandwidth bound).  A second stream
-    // clears the run table during the sorts and builds it (random atomics,
-    // latency bound) beside the out-CSR sort.  Four record buffers: the time
-    // sort ping-pongs in 0 and 1, the in-CSR sort in 2 and the free one of
-    // those, the pair sort in 3 and the one the in-CSR sort left free, and
-    // the out-CSR sort in A (the time sort's result) and the in-CSR result.
-    uint4* rr[4];
-    for (int b = 0; b < 4; ++b) rr[b] = (uint4*)(base + L.rr[b]);
-    auto sort_rec = [&](int from, int tmp, int bits, uint32_t* h, uint32_t* pt, hipStream_t s,
-                        int xf1 = RX_NONE, int extra = -1, int xf2 = RX_NONE,
-                        const EdgeCols* first = nullptr) -> int {
-      const int w = radix_sort<uint4, NoVal, kRecItems>(
-          rr[from], (NoVal*)nullptr, rr[tmp], (NoVal*)nullptr, m, bits, h, pt, pe, s, nullptr,
-          xf1, extra < 0 ? (uint4*)nullptr : rr[extra], xf2, first);
-      return w < 0 ? -1 : (w ? tmp : from);
-    };
-    SideStream* S = side_stream();
-    std::unique_lock<std::mutex> lock;
-    if (S) lock = std::unique_lock<std::mutex>(S->mu);
-    const bool two = S && side_ready(S);
-    hipStream_t s2 = two ? S->s : st;
-    // time order.  Its first pass reads the edge columns and builds the
-    // records as it loads them (with no pass, k_rec_init builds them); its
-    // last pass leaves them re-keyed as the input of the out-CSR sort
-    // (buffer A, the sort's own) and of the in-CSR sort (B)
-    const EdgeCols ec{src, dst, t, tmin};
-    if (tbits == 0)
-      hipLaunchKernelGGL(k_rec_init, dim3(eb), dim3(256), 0, st, src, dst, t, m, tmin, rr[0]);
-    const int A = sort_rec(0, 1, tbits, hist, part, st, RX_OUT, 2, RX_IN, tbits ? &ec : nullptr);
-    if (A < 0) return TC_E_WORKSPACE;
-    // the second stream clears the run table meanwhile (ordered after the
-    // caller's earlier work on this stream)
-    if (two) {
-      if (hipEventRecord(S->fork, st) != hipSuccess ||
-          hipStreamWaitEvent(s2, S->fork, 0) != hipSuccess)
-        return TC_E_HIP;
-    }
-    clear_pair_hash(g, s2);
-    const int B = 2, F = 1 - A;
-    // in-CSR: stable by dst; a second copy of the result, re-keyed, is the
-    // pair index input (buffer 3)
-    const int I = sort_rec(B, F, vbits, hist, part, st, RX_NONE, 3, RX_PAIR);
-    if (I < 0) return TC_E_WORKSPACE;
-    const int Ifree = (I == B) ? F : B;
-    hipLaunchKernelGGL(k_emit, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
-                       (const uint4*)rr[I], m, tmin, g->in_dst, g->in_src, g->in_t, g->in_eid,
-                       (uint4*)g->in_rec, n, g->in_off, (int64_t*)nullptr);
-    // pair index: the in-order (dst, t, eid) stably by src
-    const int Pr = sort_rec(3, Ifree, vbits, hist, part, st);
-    if (Pr < 0) return TC_E_WORKSPACE;
-    const int Pfree = (Pr == 3) ? Ifree : 3;
-    // the pair sort's spare buffer holds the pair sources
-    uint32_t* psrc = (uint32_t*)rr[Pfree];
-    hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint4*)rr[Pr], m, tmin,
-                       (int32_t*)psrc, g->pair_dst, g->pair_t, g->pair_eid, (uint4*)nullptr, n,
-                       (uint32_t*)nullptr, g->pair_skip);
-    if (two) {
-      if (hipEventRecord(S->fork, st) != hipSuccess ||
-          hipStreamWaitEvent(s2, S->fork, 0) != hipSuccess)
-        return TC_E_HIP;
-    }
-    // second stream: the run table, after its clear (the pair emit wrote
-    // the sampled levels)
-    build_pair_hash(psrc, g, m, tab, s2, false);
-    if (two && hipEventRecord(S->out_done, s2) != hipSuccess) return TC_E_HIP;
-    // this stream, meanwhile: out-CSR (stable by src), with the in-CSR
-    // records' buffer (emitted before the fork) as its spare
-    const int R = sort_rec(A, I, vbits, hist, part, st);
-    if (R < 0) return TC_E_WORKSPACE;
-    hipLaunchKernelGGL(k_emit, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
-                       (const uint4*)rr[R], m, tmin, g->out_src, g->out_dst, g->out_t,
-                       g->out_eid, (uint4*)g->out_rec, n, g->out_off, (int64_t*)nullptr);
-    if (two && hipStreamWaitEvent(st, S->out_done, 0) != hipSuccess) return TC_E_HIP;
-    if (hipGetLastError() != hipSuccess) return TC_E_HIP;
-    return TC_OK;
-  }
-  // wide time range: 64-bit time keys, columns gathered after each sort
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, st, (const uint32_t*)g->status,
+                     (const uint64_t*)tminmax, m, plan);
+  hipLaunchKernelGGL(k_trange, dim3(1), dim3(64), 0, st, (const BuildPlan*)plan, g->t_range);
   clear_pair_hash(g, st);
-  // 1. time order: stable by t (initial order = eid)
-  int32_t* torder;
-  if (m > 0) {
-    int where;
-    if (tbits <= 32) {
-      hipLaunchKernelGGL((k_time_keys<uint32_t>), dim3(eb), dim3(256), 0, st, t, m, tmin,
-                         (uint32_t*)keys0, vals0);
-      where = radix_sort<uint32_t>((uint32_t*)keys0, vals0, (uint32_t*)keys1, vals1, m, tbits,
-                                   hist, part, pe, st);
-    } else {
-      hipLaunchKernelGGL((k_time_keys<uint64_t>), dim3(eb), dim3(256), 0, st, t, m, tmin,
-                         (uint64_t*)keys0, vals0);
-      where = radix_sort<uint64_t>((uint64_t*)keys0, vals0, (uint64_t*)keys1, vals1, m, tbits,
-                                   hist, part, pe, st);
-    }
-    if (where < 0) return TC_E_WORKSPACE;
-    torder = where ? vals1 : vals0;
-  } else {
-    torder = vals0;
-  }
-  // the time order is kept in the eid column of the pair index until the
-  // pair sort needs it (pair_eid is rewritten at the end)
-  int32_t* torder_keep = g->pair_eid;
-  if (m > 0 &&
-      hipMemcpyAsync(torder_keep, torder, (size_t)m * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
-    return TC_E_HIP;
-  uint32_t* k0 = (uint32_t*)keys0;
-  uint32_t* k1 = (uint32_t*)keys1;
-  // 2. out-CSR: stable by src
-  if (m > 0) {
-    hipLaunchKernelGGL(k_vertex_keys, dim3(eb), dim3(256), 0, st, src, torder_keep, m, k0, vals0);
-    int w = radix_sort<uint32_t>(k0, vals0, k1, vals1, m, vbits, hist, part, pe, st);
-    if (w < 0) return TC_E_WORKSPACE;
-    uint32_t* sk = w ? k1 : k0;
-    int32_t* sv = w ? vals1 : vals0;
-    hipLaunchKernelGGL(k_gather_order, dim3(eb), dim3(256), 0, st, (const uint32_t*)sk,
-                       (const int32_t*)sv, m, dst, t, g->out_src, g->out_dst, g->out_t,
-                       g->out_eid, (uint4*)g->out_rec);
-    hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
-                       (const uint32_t*)sk, m, n, g->out_off);
-  } else {
+  if (m == 0) {
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for((int64_t)n + 1, 256)), dim3(256), 0, st,
                        g->out_off, (int64_t)n + 1, 0u);
-  }
-  // 3. in-CSR: stable by dst
-  if (m > 0) {
-    hipLaunchKernelGGL(k_vertex_keys, dim3(eb), dim3(256), 0, st, dst, torder_keep, m, k0, vals0);
-    int w = radix_sort<uint32_t>(k0, vals0, k1, vals1, m, vbits, hist, part, pe, st);
-    if (w < 0) return TC_E_WORKSPACE;
-    uint32_t* sk = w ? k1 : k0;
-    int32_t* sv = w ? vals1 : vals0;
-    hipLaunchKernelGGL(k_gather_order, dim3(eb), dim3(256), 0, st, (const uint32_t*)sk,
-                       (const int32_t*)sv, m, src, t, g->in_dst, g->in_src, g->in_t,
-                       g->in_eid, (uint4*)g->in_rec);
-    hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
-                       (const uint32_t*)sk, m, n, g->in_off);
-  } else {
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for((int64_t)n + 1, 256)), dim3(256), 0, st,
                        g->in_off, (int64_t)n + 1, 0u);
+    if (hipGetLastError() != hipSuccess) return TC_E_HIP;
+    return TC_OK;
   }
-  // 4. pair index: the in-order (dst, t, eid) stably sorted by src
-  if (m > 0) {
-    hipLaunchKernelGGL(k_vertex_keys, dim3(eb), dim3(256), 0, st, src, g->in_eid, m, k0, vals0);
-    int w = radix_sort<uint32_t>(k0, vals0, k1, vals1, m, vbits, hist, part, pe, st);
-    if (w < 0) return TC_E_WORKSPACE;
-    uint32_t* sk = w ? k1 : k0;
-    int32_t* sv = w ? vals1 : vals0;
-    hipLaunchKernelGGL(k_gather_order, dim3(eb), dim3(256), 0, st, (const uint32_t*)sk,
-                       (const int32_t*)sv, m, dst, t, (int32_t*)nullptr, g->pair_dst, g->pair_t,
-                       g->pair_eid, (uint4*)nullptr);
-    // 5. pair-run hash table (the sorted src keys are still in sk)
-    build_pair_hash(sk, g, m, tab, st, true);
-  }
+  const int vbits = bitlen((uint64_t)(n - 1));
+  const unsigned eb = blocks_for(m, 256);
+  uint4* rr[4];
+  for (int b = 0; b < 4; ++b) rr[b] = (uint4*)(base + L.rr[b]);
+  // 1. time order, ending in rr[0] re-keyed as the out-CSR input and in rr[2]
+  //    re-keyed as the in-CSR input
+  const EdgeCols ec{src, dst, t};
+  if (!time_sort<kRecItems>(plan, ec, rr[0], rr[1], m, hist, part, pe, st, RX_OUT, rr[2], RX_IN))
+    return TC_E_WORKSPACE;
+  auto sort_rec = [&](int from, int tmp, int xf1 = RX_NONE, int extra = -1,
+                      int xf2 = RX_NONE) -> int {
+    const int w = radix_sort<kRecItems>(rr[from], rr[tmp], m, vbits, hist, part, pe, st, xf1,
+                                        extra < 0 ? (uint4*)nullptr : rr[extra], xf2);
+    return w < 0 ? -1 : (w ? tmp : from);
+  };
+  // 2. in-CSR: stable by dst; a second copy of the result, re-keyed, is the
+  //    pair index input (rr[3])
+  const int I = sort_rec(2, 1, RX_NONE, 3, RX_PAIR);
+  if (I < 0) return TC_E_WORKSPACE;
+  const int Ifree = (I == 2) ? 1 : 2;
+  hipLaunchKernelGGL(k_emit, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st, (const uint4*)rr[I],
+                     m, (const BuildPlan*)plan, t, g->in_dst, g->in_src, g->in_t, g->in_eid,
+                     (uint4*)g->in_rec, n, g->in_off, (int64_t*)nullptr);
+  // 3. pair index: the in-order (dst, t, eid) stably by src
+  const int Pr = sort_rec(3, Ifree);
+  if (Pr < 0) return TC_E_WORKSPACE;
+  const int Pfree = (Pr == 3) ? Ifree : 3;
+  // the pair sort's spare buffer holds the pair sources
+  uint32_t* psrc = (uint32_t*)rr[Pfree];
+  hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint4*)rr[Pr], m,
+                     (const BuildPlan*)plan, t, (int32_t*)psrc, g->pair_dst, g->pair_t,
+                     g->pair_eid, (uint4*)nullptr, n, (uint32_t*)nullptr, g->pair_skip);
+  // 4. the run table (its clear was enqueued first)
+  hipLaunchKernelGGL(k_hash_insert, dim3(eb), dim3(256), 0, st, (const uint32_t*)psrc,
+                     (const int32_t*)g->pair_dst, m, (PairSlot*)g->pair_hash, g->pair_hash_log2);
+  // 5. out-CSR: stable by src, from the time order in rr[0]; the in-CSR
+  //    records' buffer (emitted above) is its spare
+  const int R = sort_rec(0, I);
+  if (R < 0) return TC_E_WORKSPACE;
+  hipLaunchKernelGGL(k_emit, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st, (const uint4*)rr[R],
+                     m, (const BuildPlan*)plan, t, g->out_src, g->out_dst, g->out_t, g->out_eid,
+                     (uint4*)g->out_rec, n, g->out_off, (int64_t*)nullptr);
   if (hipGetLastError() != hipSuccess) return TC_E_HIP;
   return TC_OK;
 }

@@ -102,8 +102,12 @@ struct Deg2 {
 constexpr int kPBlock = 256, kPItems = 8, kPTile = kPBlock * kPItems;
 
 // per tile: wrapping sum of the values
+// Kernels that gather through the graph's vertex ids leave a rejected graph
+// (non-zero build status) alone.
 __global__ __launch_bounds__(kPBlock) void k_deg2_tiles(Deg2 f, int64_t m,
-                                                       uint64_t* __restrict__ tile_sums) {
+                                                       uint64_t* __restrict__ tile_sums,
+                                                       const uint32_t* __restrict__ gstatus) {
+  if (*gstatus) return;
   __shared__ uint64_t s_w[kPBlock / kWave];
   uint64_t s = 0;
   const int64_t p0 = (int64_t)blockIdx.x * kPTile + (int64_t)threadIdx.x * kPItems;
@@ -146,7 +150,9 @@ __global__ __launch_bounds__(1024) void k_deg2_scan_tiles(uint64_t* __restrict__
 // per tile: exclusive prefix sums ps[i] (wrapping), ps[m] = total
 __global__ __launch_bounds__(kPBlock) void k_deg2_apply(Deg2 f, int64_t m,
                                                        const uint64_t* __restrict__ tile_off,
-                                                       uint64_t* __restrict__ ps) {
+                                                       uint64_t* __restrict__ ps,
+                                                       const uint32_t* __restrict__ gstatus) {
+  if (*gstatus) return;
   __shared__ uint64_t s_w[kPBlock / kWave];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t p0 = (int64_t)blockIdx.x * kPTile + (int64_t)threadIdx.x * kPItems;
@@ -176,9 +182,9 @@ __global__ __launch_bounds__(256) void k_features(
     int32_t pair_hash_log2, const uint32_t* __restrict__ lo_in, const uint32_t* __restrict__ a,
     const uint32_t* __restrict__ lo_out, const uint32_t* __restrict__ b,
     const uint64_t* __restrict__ ps_in, const uint64_t* __restrict__ ps_out, int64_t delta,
-    int64_t m, uint4* __restrict__ feat) {
+    int64_t m, uint4* __restrict__ feat, const uint32_t* __restrict__ gstatus) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= m) return;
+  if (p >= m || *gstatus) return;
   const int32_t u = out_src[p], v = out_dst[p];
   const int64_t t = out_t[p];
   const uint32_t ap = a[p], bp = b[p];
@@ -653,10 +659,11 @@ tc_status edge_features(const tc_graph* g, const tc_weights* w, uint16_t* feat, 
   for (int side = 0; side < 2; ++side) {
     const Deg2 f = side == 0 ? fin : fout;
     uint64_t* ps = side == 0 ? ps_in : ps_out;
-    hipLaunchKernelGGL(k_deg2_tiles, dim3((unsigned)ntiles), dim3(kPBlock), 0, st, f, m, tiles);
+    hipLaunchKernelGGL(k_deg2_tiles, dim3((unsigned)ntiles), dim3(kPBlock), 0, st, f, m, tiles,
+                       (const uint32_t*)g->status);
     hipLaunchKernelGGL(k_deg2_scan_tiles, dim3(1), dim3(1024), 0, st, tiles, ntiles);
     hipLaunchKernelGGL(k_deg2_apply, dim3((unsigned)ntiles), dim3(kPBlock), 0, st, f, m,
-                       (const uint64_t*)tiles, ps);
+                       (const uint64_t*)tiles, ps, (const uint32_t*)g->status);
   }
   {
     TimedLaunch tl("k_features", st);
@@ -666,7 +673,7 @@ tc_status edge_features(const tc_graph* g, const tc_weights* w, uint16_t* feat, 
                        (const int64_t*)g->pair_t, (const PairSlot*)g->pair_hash,
                        g->pair_hash_log2, w->lo_in, w->a, w->lo_out, w->b,
                        (const uint64_t*)ps_in, (const uint64_t*)ps_out, w->delta, m,
-                       (uint4*)feat);
+                       (uint4*)feat, (const uint32_t*)g->status);
   }
   return hipGetLastError() == hipSuccess ? TC_OK : TC_E_HIP;
 }

@@ -94,7 +94,9 @@ __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, Key
                                                       const uint32_t* __restrict__ sub,
                                                       uint32_t* __restrict__ out,
                                                       uint2* __restrict__ pair_out,
-                                                      const int32_t* __restrict__ eid) {
+                                                      const int32_t* __restrict__ eid,
+                                                      const uint32_t* __restrict__ gstatus) {
+  if (*gstatus) return;  // a rejected graph: its arrays are not sorted
   __shared__ int32_t s_v[kMPTile];
   __shared__ int64_t s_t[kMPTile];
   const int64_t b = blockIdx.x;
@@ -140,7 +142,9 @@ __global__ __launch_bounds__(kWBlock) void k_combine(const int32_t* __restrict__
                                                      uint32_t* __restrict__ lo_out,
                                                      uint32_t* __restrict__ b_out,
                                                      uint4* __restrict__ prec,
-                                                     uint64_t* __restrict__ tile_sums) {
+                                                     uint64_t* __restrict__ tile_sums,
+                                                     const uint32_t* __restrict__ gstatus) {
+  if (*gstatus) return;  // a rejected graph: its edge ids are not a permutation
   __shared__ U128 s_w[kWBlock / kWave];
   const int64_t start = (int64_t)blockIdx.x * kWTile;
   U128 acc{0, 0};
@@ -172,10 +176,21 @@ __global__ __launch_bounds__(kWBlock) void k_combine(const int32_t* __restrict__
 
 // One block of 1024 threads: exclusive scan of the 128-bit tile sums; the
 // offsets are stored modulo 2^64 (only meaningful when W < 2^64).
+// A non-zero `upstream` word (the graph's build status, or the status of the
+// weights a proposal is built on) makes the total 0 and is passed on.
 __global__ __launch_bounds__(1024) void k_scan_tiles(const uint64_t* __restrict__ tile_sums,
                                                      int64_t ntiles, uint64_t* __restrict__ tile_off,
                                                      uint64_t* __restrict__ S, int64_t m,
-                                                     uint32_t* __restrict__ status) {
+                                                     uint32_t* __restrict__ status,
+                                                     const uint32_t* __restrict__ upstream) {
+  if (*upstream) {
+    for (int64_t i = threadIdx.x; i < ntiles; i += 1024) tile_off[i] = 0;
+    if (threadIdx.x == 0) {
+      S[m] = 0;
+      *status = *upstream & (TC_F_RANGE | TC_F_OVERFLOW);
+    }
+    return;
+  }
   // Thread t owns the consecutive tiles [t c, (t + 1) c): it sums them with
   // independent loads, one block scan orders the thread sums, and it writes
   // its tiles' offsets from its exclusive prefix.
@@ -446,24 +461,25 @@ tc_status path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_byt
     hipLaunchKernelGGL(k_mp_split4, dim3(sb, 4), dim3(256), 0, st, J, m, m, nsplit);
     hipLaunchKernelGGL(k_mp_rank<false>, dim3(rb), dim3(kMPBlock), 0, st, q_lo, m, ink, m,
                        (const uint32_t*)sp[0], (const uint32_t*)nullptr, w->lo_in,
-                       (uint2*)nullptr, (const int32_t*)nullptr);
+                       (uint2*)nullptr, (const int32_t*)nullptr, (const uint32_t*)g->status);
     hipLaunchKernelGGL(k_mp_rank<true>, dim3(rb), dim3(kMPBlock), 0, st, outk, m, ink, m,
                        (const uint32_t*)sp[1], (const uint32_t*)w->lo_in, w->a, (uint2*)nullptr,
-                       (const int32_t*)nullptr);
+                       (const int32_t*)nullptr, (const uint32_t*)g->status);
     hipLaunchKernelGGL(k_mp_rank<false>, dim3(rb), dim3(kMPBlock), 0, st, ink, m, outk, m,
                        (const uint32_t*)sp[2], (const uint32_t*)nullptr, lo_out_q,
-                       (uint2*)nullptr, (const int32_t*)nullptr);
+                       (uint2*)nullptr, (const int32_t*)nullptr, (const uint32_t*)g->status);
     hipLaunchKernelGGL(k_mp_rank<true>, dim3(rb), dim3(kMPBlock), 0, st, q_hi, m, outk, m,
                        (const uint32_t*)sp[3], (const uint32_t*)lo_out_q, (uint32_t*)nullptr,
-                       win_e, (const int32_t*)g->in_eid);
+                       win_e, (const int32_t*)g->in_eid, (const uint32_t*)g->status);
     hipLaunchKernelGGL(k_combine, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
                        (const int32_t*)g->out_eid, (const uint2*)win_e,
                        (const uint32_t*)w->lo_in, (const uint32_t*)w->a,
                        (const int32_t*)g->out_src, (const int32_t*)g->out_dst,
-                       (const int64_t*)g->out_t, m, w->lo_out, w->b, (uint4*)w->prec, tile_sums);
+                       (const int64_t*)g->out_t, m, w->lo_out, w->b, (uint4*)w->prec, tile_sums,
+                       (const uint32_t*)g->status);
   }
   hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, (const uint64_t*)tile_sums, ntiles,
-                     tile_off, w->S, m, w->status);
+                     tile_off, w->S, m, w->status, (const uint32_t*)g->status);
   if (ntiles > 0) {
     TimedLaunch tl("k_scan_apply", st);
     hipLaunchKernelGGL(k_scan_apply<false>, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
@@ -519,7 +535,7 @@ tc_status proposal_weights(const tc_weights* w, const uint32_t* h, void* ws, siz
     hipLaunchKernelGGL(k_qtile_sums, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
                        (const uint32_t*)w->a, (const uint32_t*)w->b, h, m, tile_sums);
   hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, (const uint64_t*)tile_sums, ntiles,
-                     tile_off, wq->S, m, wq->status);
+                     tile_off, wq->S, m, wq->status, (const uint32_t*)w->status);
   if (ntiles > 0)
     hipLaunchKernelGGL(k_scan_apply<true>, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
                        (const uint32_t*)w->a, (const uint32_t*)w->b, h, m,

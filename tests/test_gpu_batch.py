@@ -200,6 +200,63 @@ def test_batch_graph_capture_replays(tcb, tiny, torch_mod):
             same_result(a, b)
 
 
+@pytest.mark.parametrize("wide", [False, True])
+def test_whole_path_graph_capture_replays(tcb, torch_mod, wide):
+    """Build, weights and sampling captured together in one HIP graph (the
+    build enqueues a fixed launch sequence and waits for nothing), replayed
+    three times with every workspace and output poisoned in between; each
+    replay must give the graph arrays, S and the sampled results of the
+    eager calls bit for bit.  `wide` takes a time range over 2^32, whose
+    high-word sort passes are switched on by the device."""
+    torch = torch_mod
+    g = sg.gen_tiny()
+    if wide:
+        g.t = g.t * (2**20) - 2**40
+    delta = 20000 * (2**20 if wide else 1)
+    k, seed = 30000, 21
+    s, d, t = (torch.from_numpy(g.src).cuda(), torch.from_numpy(g.dst).cuda(),
+               torch.from_numpy(g.t).cuda())
+    G = tcb.tc_build_graph(g.n, s, d, t, check=True)
+    W = tcb.tc_path_weights(G, delta)
+    R = tcb.tc_sample_estimate(G, W, SIX, k, seed, per_sample=True)
+    torch.cuda.synchronize()
+    R.check()
+    dev = s.device
+    ws_g = torch.empty(tcb.graph_workspace_bytes(g.n, g.m), dtype=torch.uint8, device=dev)
+    ws_w = torch.empty(tcb.weights_workspace_bytes(g.m), dtype=torch.uint8, device=dev)
+    ws_s = torch.empty(tcb.sample_workspace_bytes(k, len(SIX)), dtype=torch.uint8, device=dev)
+    out = tcb.new_result(len(SIX), k, dev, per_sample=True)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        G2 = tcb.tc_build_graph(g.n, s, d, t, workspace=ws_g)
+        W2 = tcb.tc_path_weights(G2, delta, workspace=ws_w)
+        tcb.tc_sample_estimate(G2, W2, SIX, k, seed, out=out, workspace=ws_s)
+    torch.cuda.synchronize()
+    ref_g = {kk: v.cpu() for kk, v in G.arrays().items()}
+    ref_S = _u64(W.arrays()["S"])
+    for rep in range(3):
+        for buf in (ws_g, ws_w, ws_s):
+            buf.fill_(0xA5)
+        out.cnt.fill_(-1)
+        out.estimate.fill_(float("nan"))
+        out.status.fill_(-1)
+        out.X.fill_(-7)
+        out.e1.fill_(-3)
+        # unrelated eager work between replays
+        tcb.tc_path_weights(G, delta + 1)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert G2.status() == 0
+        for kk, v in G2.arrays().items():
+            assert torch.equal(v.cpu(), ref_g[kk]), kk
+        assert G2.time_range() == G.time_range()
+        assert np.array_equal(_u64(W2.arrays()["S"]), ref_S)
+        same_result(out, R)
+
+
 def test_autotune_returns_usable_tuning(tcb, tiny):
     g, G, og, Ws = tiny
     best, ms = tcb.tc_autotune(G, Ws, SIX, 100000, seed=1)

@@ -314,19 +314,33 @@ def test_equal_timestamps(tcb, torch_mod):
 
 
 def test_range_errors(tcb, torch_mod):
+    """A bad vertex id or time is reported in the build's device status word;
+    the weights of such a graph carry TC_F_RANGE with W = 0 and the sampler
+    draws nothing (no kernel reads through the unsorted arrays)."""
+    cases = [([0, 1], [1, 3], [0, 1]),            # dst == n
+             ([0, -1], [1, 2], [0, 1]),           # negative id
+             ([0, 1], [1, 2], [0, 2**62]),        # |t| = 2^62
+             ([0, 1], [1, 2], [-(2**62), 5])]
+    for s_, d_, t_ in cases:
+        s = torch_mod.tensor(s_, dtype=torch_mod.int32, device="cuda")
+        d = torch_mod.tensor(d_, dtype=torch_mod.int32, device="cuda")
+        t = torch_mod.tensor(t_, dtype=torch_mod.int64, device="cuda")
+        G = tcb.tc_build_graph(3, s, d, t)
+        assert G.status() == tcb.TC_F_RANGE
+        with pytest.raises(tcb.TCDeviceError):
+            G.check()
+        with pytest.raises(tcb.TCDeviceError):
+            tcb.tc_build_graph(3, s, d, t, check=True)
+        Wt = tcb.tc_path_weights(G, 10)
+        assert Wt.status() == tcb.TC_F_RANGE and Wt.total() == 0
+        R = tcb.tc_sample_estimate(G, Wt, SIX, 1000, 1, per_sample=True)
+        assert (int(R.status.item()) & tcb.TC_F_RANGE) != 0
+        assert R.counts() == [0] * 6
     s = torch_mod.tensor([0, 1], dtype=torch_mod.int32, device="cuda")
-    d = torch_mod.tensor([1, 3], dtype=torch_mod.int32, device="cuda")
-    t = torch_mod.tensor([0, 1], dtype=torch_mod.int64, device="cuda")
-    with pytest.raises(tcb.TCError) as e:
-        tcb.tc_build_graph(3, s, d, t)
-    assert e.value.code == tcb.TC_E_RANGE
     d = torch_mod.tensor([1, 2], dtype=torch_mod.int32, device="cuda")
-    t = torch_mod.tensor([0, 2**62], dtype=torch_mod.int64, device="cuda")
-    with pytest.raises(tcb.TCError):
-        tcb.tc_build_graph(3, s, d, t)
     t = torch_mod.tensor([-(2**62) + 1, 2**62 - 1], dtype=torch_mod.int64, device="cuda")
-    G = tcb.tc_build_graph(3, s, d, t)
-    assert G.c.t_min == -(2**62) + 1 and G.c.t_max == 2**62 - 1
+    G = tcb.tc_build_graph(3, s, d, t, check=True)
+    assert G.time_range() == (-(2**62) + 1, 2**62 - 1)
 
 
 def test_weight_overflow(tcb, torch_mod):
