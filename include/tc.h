@@ -174,7 +174,7 @@ typedef struct tc_result {
  *   reg_waves   wavefronts of the register ListCount pass
  *   fast_waves  wavefronts of the LDS-key ListCount pass (64..8192)
  *   wide_blocks 256-thread blocks of the merged ListCount pass for lists
- *               over lds_list_cap entries (64..2048; 1 MiB of workspace each)
+ *               over lds_list_cap entries (16..2048; 1 MiB of workspace each)
  *   reg_list_cap  longest list the register ListCount pass takes: 128 or
  *               256 entries (two or four 64-entry chunks per lane); items
  *               with a longer list go to the LDS-key pass
@@ -256,6 +256,21 @@ tc_status tc_sample_estimate(const tc_graph *g, const tc_weights *w, const tc_mo
                              int32_t n_motifs, uint64_t k, uint64_t seed, uint32_t stream_id,
                              uint64_t i0, void *ws, size_t ws_bytes, tc_result *out,
                              void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * tc_sample_estimate with the same arguments and results, but no workspace
+ * argument.  Its scratch is a library-owned static device array of 80 MiB,
+ * one per GPU, held until the process ends; the call allocates nothing and
+ * clears what must start at zero.  Calls that overlap on one GPU (several
+ * streams or threads at once) share that array and race: order them.
+ * It runs in chunks of 2^16 samples; a call whose scratch would exceed the
+ * array returns TC_E_WORKSPACE (no valid call does: any k, 1..16 motifs).
+ * Errors: as tc_sample_estimate. */
+tc_status tc_sample_estimate_noalloc(const tc_graph *g, const tc_weights *w,
+                                     const tc_motif *motifs, int32_t n_motifs, uint64_t k,
+                                     uint64_t seed, uint32_t stream_id, uint64_t i0,
+                                     tc_result *out, void *stream);
 
 /* Batched Estimate: n_deltas (1..8) weight sets of the same graph (one per
  * delta, from tc_path_weights) and n_motifs motifs sharing the anchor, in one

@@ -30,7 +30,7 @@ _STATUS_NAMES = {0: "TC_OK", -1: "TC_E_ARG", -2: "TC_E_RANGE", -3: "TC_E_OVERFLO
 
 EXPORTED = ["tc_version", "tc_graph_workspace_bytes", "tc_build_graph",
             "tc_weights_workspace_bytes", "tc_path_weights", "tc_sample_workspace_bytes",
-            "tc_sample_estimate", "tc_batch_workspace_bytes", "tc_batch_estimate",
+            "tc_sample_estimate", "tc_sample_estimate_noalloc", "tc_batch_workspace_bytes", "tc_batch_estimate",
             "tc_autotune", "tc_features_workspace_bytes", "tc_edge_features", "tc_mlp_forward", "tc_mlp_workspace_bytes",
             "tc_mlp_grad", "tc_mlp_adam", "tc_mlp_train", "tc_quantize_proposal",
             "tc_proposal_workspace_bytes", "tc_proposal_weights", "tc_timing_enable",
@@ -122,6 +122,10 @@ def lib():
         L.tc_sample_estimate.argtypes = [ctypes.POINTER(tc_graph), ctypes.POINTER(tc_weights),
                                          ctypes.POINTER(tc_motif), I32, U64, U64, U32, U64,
                                          _P, SZ, ctypes.POINTER(tc_result), _P]
+        L.tc_sample_estimate_noalloc.argtypes = [ctypes.POINTER(tc_graph),
+                                                 ctypes.POINTER(tc_weights),
+                                                 ctypes.POINTER(tc_motif), I32, U64, U64, U32,
+                                                 U64, ctypes.POINTER(tc_result), _P]
         L.tc_batch_workspace_bytes.argtypes = [U64, I32, I32, ctypes.POINTER(SZ)]
         L.tc_batch_estimate.argtypes = [ctypes.POINTER(tc_graph), _P, I32,
                                         ctypes.POINTER(tc_motif), I32, U64, U64, U32, U64,
@@ -428,6 +432,24 @@ def tc_sample_estimate(graph: Graph, weights: Weights, motifs, k: int, seed: int
                                     int(k), int(seed), int(stream_id), int(i0), _ptr(ws),
                                     ws.numel(), ctypes.byref(r), _stream(stream)),
            "tc_sample_estimate")
+    return out
+
+
+def tc_sample_estimate_noalloc(graph: Graph, weights: Weights, motifs, k: int, seed: int,
+                               stream_id: int = 0, i0: int = 0, per_sample: bool = False,
+                               stream=None, out: Result | None = None) -> Result:
+    """tc_sample_estimate on the library's static per-GPU scratch (no
+    workspace is allocated for the call)."""
+    nm, arr = _motif_array(motifs)
+    if out is None:
+        out = new_result(nm, k, graph.ws.device, per_sample)
+        _on_stream(stream, out.cnt, out.hits, out.estimate, out.status, out.e1, out.e2, out.e3,
+                   out.X, out.P)
+    r = _c_result(out)
+    _check(lib().tc_sample_estimate_noalloc(ctypes.byref(graph.c), ctypes.byref(weights.c), arr,
+                                            nm, int(k), int(seed), int(stream_id), int(i0),
+                                            ctypes.byref(r), _stream(stream)),
+           "tc_sample_estimate_noalloc")
     return out
 
 

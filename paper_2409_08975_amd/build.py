@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtc.so")
 SOURCES = ["tc_api.hip", "tc_build.hip", "tc_weights.hip", "tc_sample.hip", "tc_learn.hip",
-           "tc_timing.hip"]
+           "tc_timing.hip", "tc_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -1305,7 +1305,7 @@ static int fast_waves_for(const SampleTuning& t) {
 }
 
 static int wide_blocks_for(const SampleTuning& t) {
-  return t.wide_blocks < 64 ? 64
+  return t.wide_blocks < 16 ? 16
                             : (t.wide_blocks > kMaxWideBlocks ? kMaxWideBlocks : t.wide_blocks);
 }
 
