@@ -45,7 +45,7 @@ def lib():
         P, I64, U64, I32, U32 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64,
                                  ctypes.c_int32, ctypes.c_uint32)
         L.or_graph_new.restype = P
-        L.or_graph_new.argtypes = [I32, I64, P, P, P, P]
+        L.or_graph_new.argtypes = [I32, I64, P, P, P, P, ctypes.c_int]
         L.or_graph_free.argtypes = [P]
         L.or_graph_orders.argtypes = [P, P, P, P, P, P]
         L.or_weights.argtypes = [P, I64, P, P, P, P, P, ctypes.c_int]
@@ -140,7 +140,7 @@ class Estimate:
 class OracleGraph:
     """Temporal adjacency of one input graph, built by the oracle."""
 
-    def __init__(self, n: int, src, dst, t):
+    def __init__(self, n: int, src, dst, t, threads: int = 1):
         self.n = int(n)
         self.src = np.ascontiguousarray(src, dtype=np.int32)
         self.dst = np.ascontiguousarray(dst, dtype=np.int32)
@@ -148,14 +148,14 @@ class OracleGraph:
         self.m = int(self.src.shape[0])
         st = ctypes.c_int(0)
         self.h = lib().or_graph_new(self.n, self.m, _p(self.src), _p(self.dst), _p(self.t),
-                                    ctypes.byref(st))
+                                    ctypes.byref(st), int(threads))
         self.status = st.value
         if not self.h:
             raise ValueError(f"oracle rejected the graph (status {st.value})")
 
     @classmethod
-    def from_graph(cls, g):
-        return cls(g.n, g.src, g.dst, g.t)
+    def from_graph(cls, g, threads: int = 1):
+        return cls(g.n, g.src, g.dst, g.t, threads)
 
     def __del__(self):
         h = getattr(self, "h", None)

@@ -45,6 +45,7 @@
 // integer generation in an interval", ACM TOMACS 2019), which makes every
 // value exactly uniform.
 #include <algorithm>
+#include <parallel/algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -140,8 +141,20 @@ bool lemire32(uint32_t x, uint32_t s, uint32_t* out) {
 }
 
 // ---- adjacency build --------------------------------------------------------
+// Stable sort of edge ids; with several threads libstdc++'s parallel stable
+// sort (a multiway merge sort), whose result is the same unique stable order.
+template <typename Less>
+void stable_sort_ids(std::vector<int32_t>& v, Less less, int nthreads) {
+  if (nthreads > 1 && v.size() > 100000) {
+    omp_set_num_threads(nthreads);
+    __gnu_parallel::stable_sort(v.begin(), v.end(), less);
+  } else {
+    std::stable_sort(v.begin(), v.end(), less);
+  }
+}
+
 int build(Graph& G, int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
-          const int64_t* t) {
+          const int64_t* t, int nthreads) {
   G.n = n;
   G.m = m;
   for (int64_t e = 0; e < m; ++e) {
@@ -155,23 +168,23 @@ int build(Graph& G, int32_t n, int64_t m, const int32_t* src, const int32_t* dst
   std::iota(ids.begin(), ids.end(), 0);
   // out lists: by (src, t, eid)
   G.out_ord = ids;
-  std::stable_sort(G.out_ord.begin(), G.out_ord.end(), [&](int32_t a, int32_t b) {
+  stable_sort_ids(G.out_ord, [&](int32_t a, int32_t b) {
     if (G.src[a] != G.src[b]) return G.src[a] < G.src[b];
     return G.t[a] < G.t[b];
-  });
+  }, nthreads);
   // in lists: by (dst, t, eid)
   G.in_ord = ids;
-  std::stable_sort(G.in_ord.begin(), G.in_ord.end(), [&](int32_t a, int32_t b) {
+  stable_sort_ids(G.in_ord, [&](int32_t a, int32_t b) {
     if (G.dst[a] != G.dst[b]) return G.dst[a] < G.dst[b];
     return G.t[a] < G.t[b];
-  });
+  }, nthreads);
   // pair lists L_{u,v}: by (src, dst, t, eid)
   G.pair_ord = ids;
-  std::stable_sort(G.pair_ord.begin(), G.pair_ord.end(), [&](int32_t a, int32_t b) {
+  stable_sort_ids(G.pair_ord, [&](int32_t a, int32_t b) {
     if (G.src[a] != G.src[b]) return G.src[a] < G.src[b];
     if (G.dst[a] != G.dst[b]) return G.dst[a] < G.dst[b];
     return G.t[a] < G.t[b];
-  });
+  }, nthreads);
   G.out_off.assign(n + 1, 0);
   G.in_off.assign(n + 1, 0);
   for (int64_t e = 0; e < m; ++e) {
@@ -184,6 +197,7 @@ int build(Graph& G, int32_t n, int64_t m, const int32_t* src, const int32_t* dst
   }
   G.out_t.resize(m); G.in_t.resize(m); G.pair_t.resize(m);
   G.out_dst.resize(m); G.in_src.resize(m); G.pair_dst.resize(m);
+#pragma omp parallel for num_threads(nthreads) schedule(static)
   for (int64_t p = 0; p < m; ++p) {
     G.out_t[p] = G.t[G.out_ord[p]];
     G.out_dst[p] = G.dst[G.out_ord[p]];
@@ -317,9 +331,9 @@ int or_lemire64(uint64_t x, uint64_t s, uint64_t* out) { return lemire64(x, s, o
 int or_lemire32(uint32_t x, uint32_t s, uint32_t* out) { return lemire32(x, s, out) ? 1 : 0; }
 
 void* or_graph_new(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
-                   const int64_t* t, int* status) {
+                   const int64_t* t, int* status, int nthreads) {
   Graph* G = new Graph();
-  *status = build(*G, n, m, src, dst, t);
+  *status = build(*G, n, m, src, dst, t, nthreads < 1 ? 1 : nthreads);
   if (*status != OR_OK) {
     delete G;
     return nullptr;

@@ -2,12 +2,16 @@
 HBM traffic per kernel), written for the ``profiles/`` folder.
 
   python -m paper_2409_08975_amd.rocprof_summary stats <run_results.db> <out.txt> <command>
-  python -m paper_2409_08975_amd.rocprof_summary pmc <fetch.db> <write.db> <out.txt> <fetch cmd> <write cmd>
+  python -m paper_2409_08975_amd.rocprof_summary pmc <fetch.db> <write.db> <out.txt> <fetch cmd> <write cmd> [meta]
 
 The traffic summary scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch) by
 what the same counters read for a 1 GiB device-to-device copy recorded in
 the same run (bench.py --calib-copy), and tags each kernel with a hash of its
 source file so a reader can tell whether the figures still describe the code.
+Launches that moved less than 64 KiB (time-sort passes that the device plan
+leaves idle) are left out of the per-launch averages; the totals count every
+launch.  `meta` (key=value words) describes the profiled run, e.g. how many
+steps it timed.
 """
 from __future__ import annotations
 
@@ -30,8 +34,14 @@ KERNEL_SRC = {
     "k_scan_tiles": "tc_weights.hip", "k_scan_apply": "tc_weights.hip",
     "k_tree": "tc_weights.hip", "k_radix_scatter": "tc_build.hip",
     "k_radix_hist": "tc_build.hip", "k_hash_insert": "tc_build.hip", "k_emit": "tc_build.hip",
-    "k_rec_xform": "tc_build.hip",
+    "k_rec_xform": "tc_build.hip", "k_mp_split4": "tc_weights.hip", "k_rec_init": "tc_build.hip",
+    "k_col_sum": "tc_build.hip", "k_col_scan": "tc_build.hip", "k_col_apply": "tc_build.hip",
+    "k_hash_clear": "tc_build.hip", "k_validate": "tc_build.hip", "k_plan": "tc_build.hip",
+    "k_init_build": "tc_build.hip", "k_trange": "tc_build.hip",
+    "k_zero_result": "tc_sample.hip", "k_store_ptrs": "tc_sample.hip",
+    "k_zero_counters": "tc_sample.hip", "k_finalize": "tc_sample.hip",
 }
+IDLE_BYTES = 64 * 1024
 
 
 def short_name(n: str) -> str:
@@ -90,7 +100,7 @@ def _counter_rows(db: str, counter: str):
     return rows
 
 
-def pmc_text(fetch_db: str, write_db: str, fetch_cmd: str, write_cmd: str) -> str:
+def pmc_text(fetch_db: str, write_db: str, fetch_cmd: str, write_cmd: str, meta: str = "") -> str:
     fetch = _counter_rows(fetch_db, "FETCH_SIZE")
     write = _counter_rows(write_db, "WRITE_SIZE")
     fc = [v for n, v in fetch if "copyBuffer" in n and v * 1024 > CALIB_BYTES / 4]
@@ -99,37 +109,60 @@ def pmc_text(fetch_db: str, write_db: str, fetch_cmd: str, write_cmd: str) -> st
         raise SystemExit("no 1 GiB calibration copy in the counter runs (bench.py --calib-copy)")
     ff = CALIB_BYTES / (fc[0] * 1024.0)
     wf = CALIB_BYTES / (wc[0] * 1024.0)
-    agg = collections.OrderedDict()
-    for rows, key in ((fetch, "f"), (write, "w")):
+    # the two runs launch the same kernels in the same order: pair them up
+    per = collections.OrderedDict()
+    for rows, key, fac in ((fetch, "f", ff), (write, "w", wf)):
+        cnt = collections.Counter()
         for n, v in rows:
-            a = agg.setdefault(short_name(n), {"f": 0.0, "w": 0.0, "nf": 0, "nw": 0})
-            a[key] += v * 1024.0
-            a["n" + key] += 1
+            sn = short_name(n)
+            lst = per.setdefault(sn, [])
+            i = cnt[sn]
+            cnt[sn] += 1
+            while len(lst) <= i:
+                lst.append({"f": 0.0, "w": 0.0})
+            lst[i][key] = v * 1024.0 * fac
     lines = ["# HBM traffic per kernel launch from rocprofv3 counters",
              f"# fetch run: {fetch_cmd}", f"# write run: {write_cmd}",
              f"# calibration: 1 GiB device copy reads FETCH_SIZE={fc[0]:.0f} KiB "
              f"(factor {ff:.4f}) and WRITE_SIZE={wc[0]:.0f} KiB (factor {wf:.4f})",
-             f"# {'kernel':44s} {'launches':>8s} {'read MB':>10s} {'write MB':>10s}  per launch, scaled"]
+             "# per launch: average over launches that moved at least 64 KiB; total: every "
+             "launch of the run",
+             f"# {'kernel':44s} {'launches':>8s} {'active':>6s} {'read MB':>10s} {'write MB':>10s}"
+             f" {'total MB':>10s}"]
     keyed = []
-    for n, a in agg.items():
-        if a["nf"] == 0 or "copyBuffer" in n:
+    for n, lst in per.items():
+        if "copyBuffer" in n:
             continue
-        rf = a["f"] / a["nf"] * ff
-        rw = a["w"] / max(1, a["nw"]) * wf
-        lines.append(f"  {n[:44]:44s} {a['nf']:8d} {rf / 1e6:10.2f} {rw / 1e6:10.2f}")
+        act = [x for x in lst if x["f"] + x["w"] >= IDLE_BYTES]
+        rf = sum(x["f"] for x in act) / max(1, len(act))
+        rw = sum(x["w"] for x in act) / max(1, len(act))
+        tot = sum(x["f"] + x["w"] for x in lst)
+        lines.append(f"  {n[:44]:44s} {len(lst):8d} {len(act):6d} {rf / 1e6:10.2f} "
+                     f"{rw / 1e6:10.2f} {tot / 1e6:10.2f}")
         sha = source_sha(n)
         if sha is not None:
-            keyed.append(f"kernel={base_name(n)} src_sha={sha} hbm_bytes_per_launch={rf + rw:.0f} "
-                         f"read_bytes_per_launch={rf:.0f} write_bytes_per_launch={rw:.0f} "
-                         f"launches={a['nf']}")
-    # one keyed line per kernel base name (the first instantiation listed)
-    seen, uniq = set(), []
-    for k in keyed:
-        b = k.split()[0]
-        if b not in seen:
-            seen.add(b)
-            uniq.append(k)
-    return "\n".join(lines) + "\n\n" + "\n".join(uniq) + "\n"
+            keyed.append((base_name(n), sha, rf, rw, tot, len(lst), len(act)))
+    # one keyed line per kernel base name (instantiations summed)
+    merged = collections.OrderedDict()
+    for b, sha, rf, rw, tot, nl, na in keyed:
+        if b not in merged:
+            merged[b] = [sha, rf * na, rw * na, tot, nl, na]
+        else:
+            e = merged[b]
+            e[1] += rf * na
+            e[2] += rw * na
+            e[3] += tot
+            e[4] += nl
+            e[5] += na
+    out = []
+    if meta:
+        out.append("meta " + meta)
+    for b, (sha, rfa, rwa, tot, nl, na) in merged.items():
+        na1 = max(1, na)
+        out.append(f"kernel={b} src_sha={sha} hbm_bytes_per_launch={(rfa + rwa) / na1:.0f} "
+                   f"read_bytes_per_launch={rfa / na1:.0f} write_bytes_per_launch={rwa / na1:.0f} "
+                   f"launches={nl} active_launches={na} total_bytes={tot:.0f}")
+    return "\n".join(lines) + "\n\n" + "\n".join(out) + "\n"
 
 
 def main(argv):
@@ -138,7 +171,7 @@ def main(argv):
         with open(argv[2], "w") as f:
             f.write(text)
     elif len(argv) >= 6 and argv[0] == "pmc":
-        text = pmc_text(argv[1], argv[2], argv[4], argv[5])
+        text = pmc_text(argv[1], argv[2], argv[4], argv[5], argv[6] if len(argv) > 6 else "")
         with open(argv[3], "w") as f:
             f.write(text)
     else:
