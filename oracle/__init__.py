@@ -49,6 +49,12 @@ def lib():
         L.or_graph_free.argtypes = [P]
         L.or_graph_orders.argtypes = [P, P, P, P, P, P]
         L.or_weights.argtypes = [P, I64, P, P, P, P, P, ctypes.c_int]
+        L.or_weights_class.argtypes = [P, I64, P, P, P, P, P, P, ctypes.c_int]
+        L.or_anchor.argtypes = [P, P, P, P, P]
+        L.or_sample_cls.argtypes = [P, I64, P, P, P, P, P, P, P, P, ctypes.c_int, U64, U64, U32,
+                                    U64, P, P, P, P, P, P, P, P, P, P, ctypes.c_int]
+        L.or_enumerate.argtypes = [P, I64, P, P, P, P, P, P, P, ctypes.c_int, U64, U64, P, P, P,
+                                   P, P, P, P, P, P, ctypes.c_int]
         L.or_check_motif.argtypes = [P, P, I64, I32, I32, I32, P]
         L.or_sample.argtypes = [P, I64, P, P, P, P, P, P, ctypes.c_int, U64, U64, U32, U64,
                                 P, P, P, P, P, P, P, ctypes.c_int]
@@ -56,7 +62,7 @@ def lib():
                                    U64, P, P, P, P, P, P, P, P, P, ctypes.c_int]
         L.or_proposal_scan.argtypes = [P, P, P, P, P]
         L.or_features.argtypes = [P, I64, P, P, P, P, P, ctypes.c_int]
-        L.or_exhaustive.argtypes = [P, P, I64, P, P, P, P, P, P, P, ctypes.c_int]
+        L.or_exhaustive.argtypes = [P, P, I64, P, P, P, P, P, P, P, P, ctypes.c_int]
         L.or_list_lengths.argtypes = [P, P, I64, I32, I32, I32, P]
         L.or_brute_count.argtypes = [P, P, I64, P, ctypes.c_int]
         L.or_list_count.argtypes = [P, P, ctypes.c_int, P]
@@ -69,6 +75,32 @@ def lib():
 
 def _p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# Anchor classes as 4 bytes {mode1, after1, mode3, after3}: mode 0 = no edge
+# on that side, 1 = an in-edge, 2 = an out-edge of the centre's endpoint;
+# after 0 = window [t - delta, t], 1 = [t, t + delta].  Side 1 is the centre
+# edge's source u, side 3 its destination v.
+SIDE_NONE, SIDE_IN, SIDE_OUT = 0, 1, 2
+SPINE_CLASS = bytes([SIDE_IN, 0, SIDE_OUT, 1])  # <-,+,<,>
+
+
+def class_bytes(mode1, after1, mode3, after3) -> bytes:
+    return bytes([mode1, after1, mode3, after3])
+
+
+def anchor(motif: bytes):
+    """(class bytes, number of anchor edges, their rank order as 0 = e1,
+    1 = centre, 2 = e3, motif edge of e1 / centre / e3) of a motif's anchor,
+    or None if it has none."""
+    mb = np.frombuffer(motif, dtype=np.uint8).copy()
+    cls = np.zeros(4, np.uint8)
+    na = np.zeros(1, np.int32)
+    order = np.zeros(3, np.int32)
+    ae = np.zeros(3, np.int32)
+    if lib().or_anchor(_p(mb), _p(cls), _p(na), _p(order), _p(ae)) != OR_OK:
+        return None
+    return bytes(cls), int(na[0]), order[:int(na[0])].tolist(), ae.tolist()
 
 
 def default_threads() -> int:
@@ -117,6 +149,7 @@ class Weights:
     status: int
 
     h: np.ndarray | None = None  # proposal h_int per scan position (S is then Q)
+    cls: bytes = SPINE_CLASS     # the anchor class of the windows
 
     @property
     def W(self) -> int:
@@ -135,6 +168,7 @@ class Estimate:
     X: np.ndarray | None = None  # [n_motifs, k]
     P: np.ndarray | None = None  # [k] scan position of the centre edge
     m2: np.ndarray | None = None  # [n_motifs] sum of (X / h)^2
+    xmax: np.ndarray | None = None  # [n_motifs] largest X
 
 
 class OracleGraph:
@@ -173,16 +207,19 @@ class OracleGraph:
         lib().or_graph_orders(self.h, _p(out), _p(inn), _p(pr), _p(oo), _p(io))
         return dict(out_eid=out, in_eid=inn, pair_eid=pr, out_off=oo, in_off=io)
 
-    def weights(self, delta: int, threads: int | None = None) -> Weights:
+    def weights(self, delta: int, threads: int | None = None, cls: bytes | None = None) -> Weights:
+        """Preprocess(delta) for an anchor class (default <-,+,<,>): per scan
+        position the two sides' windows (lo1, a) and (lo3, b) and S."""
         m = self.m
         lo_in = np.zeros(m, np.uint32)
         a = np.zeros(m, np.uint32)
         lo_out = np.zeros(m, np.uint32)
         b = np.zeros(m, np.uint32)
         S = np.zeros(m + 1, np.uint64)
-        st = lib().or_weights(self.h, int(delta), _p(lo_in), _p(a), _p(lo_out), _p(b), _p(S),
-                              threads or default_threads())
-        return Weights(int(delta), lo_in, a, lo_out, b, S, st)
+        c = np.frombuffer(cls or SPINE_CLASS, dtype=np.uint8).copy()
+        st = lib().or_weights_class(self.h, int(delta), _p(c), _p(lo_in), _p(a), _p(lo_out), _p(b),
+                                    _p(S), threads or default_threads())
+        return Weights(int(delta), lo_in, a, lo_out, b, S, st, None, bytes(cls or SPINE_CLASS))
 
     def check_motif(self, motif: bytes, delta: int, e1: int, e2: int, e3: int):
         X = np.zeros(1, np.uint64)
@@ -200,6 +237,7 @@ class OracleGraph:
         hits = np.zeros(nm, np.uint64)
         est = np.zeros(nm, np.float64)
         m2 = np.zeros(nm, np.float64)
+        xmax = np.zeros(nm, np.uint64)
         e1 = e2 = e3 = X = P = None
         null = ctypes.c_void_p(0)
         if per_sample:
@@ -209,15 +247,49 @@ class OracleGraph:
             X = np.zeros(nm * k, np.uint64)
             P = np.zeros(k, np.uint32)
         hq = _p(w.h) if w.h is not None else null
-        st = lib().or_sample_ex(self.h, w.delta, _p(w.lo_in), _p(w.a), _p(w.lo_out), _p(w.b),
-                                _p(w.S), hq, _p(mb), nm, int(k), int(seed), int(stream), int(i0),
+        c = np.frombuffer(w.cls, dtype=np.uint8).copy()
+        st = lib().or_sample_cls(self.h, w.delta, _p(c), _p(w.lo_in), _p(w.a), _p(w.lo_out),
+                                 _p(w.b), _p(w.S), hq, _p(mb), nm, int(k), int(seed), int(stream),
+                                 int(i0), _p(e1) if per_sample else null,
+                                 _p(e2) if per_sample else null, _p(e3) if per_sample else null,
+                                 _p(X) if per_sample else null, _p(P) if per_sample else null,
+                                 _p(cnt), _p(hits), _p(est), _p(m2), _p(xmax),
+                                 threads or default_threads())
+        cc = [int(cnt[2 * j]) | (int(cnt[2 * j + 1]) << 64) for j in range(nm)]
+        return Estimate(cc, hits, est, st, e1, e2, e3, None if X is None else X.reshape(nm, k),
+                        P, m2, xmax)
+
+    def enumerate(self, w: Weights, motifs, r0: int = 0, count: int | None = None,
+                  per_sample: bool = False, threads: int | None = None) -> Estimate:
+        """Exhaustive mode: CheckMotif over the anchors of ranks r0 .. r0 +
+        count - 1 of the integer CDF (all W of them by default); over all of
+        them cnt is the exact count C."""
+        if count is None:
+            count = max(0, w.W - r0)
+        mb = np.frombuffer(b"".join(motifs), dtype=np.uint8).copy()
+        nm = len(motifs)
+        cnt = np.zeros(2 * nm, np.uint64)
+        hits = np.zeros(nm, np.uint64)
+        est = np.zeros(nm, np.float64)
+        m2 = np.zeros(nm, np.float64)
+        xmax = np.zeros(nm, np.uint64)
+        null = ctypes.c_void_p(0)
+        e1 = e2 = e3 = X = None
+        if per_sample:
+            e1 = np.zeros(count, np.int32)
+            e2 = np.zeros(count, np.int32)
+            e3 = np.zeros(count, np.int32)
+            X = np.zeros(nm * count, np.uint64)
+        c = np.frombuffer(w.cls, dtype=np.uint8).copy()
+        st = lib().or_enumerate(self.h, w.delta, _p(c), _p(w.lo_in), _p(w.a), _p(w.lo_out),
+                                _p(w.b), _p(w.S), _p(mb), nm, int(r0), int(count),
                                 _p(e1) if per_sample else null, _p(e2) if per_sample else null,
                                 _p(e3) if per_sample else null, _p(X) if per_sample else null,
-                                _p(P) if per_sample else null, _p(cnt), _p(hits), _p(est),
-                                _p(m2), threads or default_threads())
-        c = [int(cnt[2 * j]) | (int(cnt[2 * j + 1]) << 64) for j in range(nm)]
-        return Estimate(c, hits, est, st, e1, e2, e3, None if X is None else X.reshape(nm, k),
-                        P, m2)
+                                _p(cnt), _p(hits), _p(est), _p(m2), _p(xmax),
+                                threads or default_threads())
+        cc = [int(cnt[2 * j]) | (int(cnt[2 * j + 1]) << 64) for j in range(nm)]
+        return Estimate(cc, hits, est, st, e1, e2, e3,
+                        None if X is None else X.reshape(nm, count), None, m2, xmax)
 
     def proposal(self, w: Weights, h_int) -> Weights:
         """Weight set of the proposal q_p = w_p * h_p: same windows, S = the
@@ -226,7 +298,7 @@ class OracleGraph:
         assert h.shape[0] == self.m
         Q = np.zeros(self.m + 1, np.uint64)
         st = lib().or_proposal_scan(self.h, _p(w.a), _p(w.b), _p(h), _p(Q))
-        return Weights(w.delta, w.lo_in, w.a, w.lo_out, w.b, Q, st, h)
+        return Weights(w.delta, w.lo_in, w.a, w.lo_out, w.b, Q, st, h, w.cls)
 
     def features(self, w: Weights, threads: int | None = None) -> np.ndarray:
         """Per-edge proposal features [m, 8] in binary64 (scan order)."""
@@ -241,8 +313,10 @@ class OracleGraph:
         s1 = np.zeros(2, np.uint64)
         s2 = np.zeros(2, np.uint64)
         nz = np.zeros(1, np.uint64)
-        st = lib().or_exhaustive(self.h, _p(mb), w.delta, _p(w.lo_in), _p(w.a), _p(w.lo_out),
-                                 _p(w.b), _p(s1), _p(s2), _p(nz), threads or default_threads())
+        c = np.frombuffer(w.cls, dtype=np.uint8).copy()
+        st = lib().or_exhaustive(self.h, _p(mb), w.delta, _p(c), _p(w.lo_in), _p(w.a),
+                                 _p(w.lo_out), _p(w.b), _p(s1), _p(s2), _p(nz),
+                                 threads or default_threads())
         return (st, int(s1[0]) | (int(s1[1]) << 64), int(s2[0]) | (int(s2[1]) << 64), int(nz[0]))
 
     def list_lengths(self, motif: bytes, delta: int, e1: int, e2: int, e3: int):

@@ -11,6 +11,9 @@ for micro graphs (tens of edges); they pin the C++ oracle.
   remaining conditions (endpoint map consistent and 1-1, span <= delta).
 * ``enumerate_paths``: every delta-centred <-,+,<,>> 3-path (Definitions of a
   delta-centred 3-path and of its class; closed windows as in Claim "count").
+* ``enumerate_class_paths``: the same for any anchor class (section III:
+  the classes <alpha_1, alpha_3, beta_1, beta_3>; a side may also have no
+  edge, which gives the wedges of the 3-vertex case).
 * ``list_count_bruteforce``: number of strictly increasing chains across
   lists, by product enumeration.
 """
@@ -58,6 +61,34 @@ def enumerate_paths(src, dst, t, delta):
         outs = [e for e in range(m) if int(src[e]) == v and t2 <= int(t[e]) <= t2 + delta]
         for e1 in ins:
             for e3 in outs:
+                paths.append((e1, e2, e3))
+    return paths
+
+
+def enumerate_class_paths(src, dst, t, delta, cls):
+    """All (e1, e2, e3) of an anchor class given as 4 bytes {mode1, after1,
+    mode3, after3}: e2 = (u, v, t2) any edge; e1 an edge at u (mode 1: an
+    in-edge x -> u, mode 2: an out-edge u -> x; mode 0: none, e1 = -1) with
+    t1 in [t2 - delta, t2] (after1 = 0) or [t2, t2 + delta] (after1 = 1); e3
+    likewise at v.  Windows are closed; e1 and e3 may be any edges (even e2)."""
+    m = len(src)
+
+    def side(at, t2, mode, after):
+        if mode == 0:
+            return [-1]
+        lo, hi = (t2, t2 + delta) if after else (t2 - delta, t2)
+        out = []
+        for e in range(m):
+            ends = int(dst[e]) if mode == 1 else int(src[e])
+            if ends == at and lo <= int(t[e]) <= hi:
+                out.append(e)
+        return out
+
+    paths = []
+    for e2 in range(m):
+        u, v, t2 = int(src[e2]), int(dst[e2]), int(t[e2])
+        for e1 in side(u, t2, cls[0], cls[1]):
+            for e3 in side(v, t2, cls[2], cls[3]):
                 paths.append((e1, e2, e3))
     return paths
 

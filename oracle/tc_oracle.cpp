@@ -63,23 +63,158 @@ const int kMaxAttempts = 1024;
 
 enum { OR_OK = 0, OR_RANGE = 1, OR_OVERFLOW = 2, OR_RNG = 4, OR_ARG = 8 };
 
+// An anchor class (section III: the 16 classes <alpha_1, alpha_3, beta_1,
+// beta_3> of delta-centred 3-paths, and the wedges of the 3-vertex case):
+// for the side at the centre edge's source u (side 1, edge e1) and the side
+// at its destination v (side 3, edge e3), whether the side has an edge, whether
+// that edge is an in-edge (-) or an out-edge (+) of u (resp. v), and whether
+// it comes before the centre edge (window [t - delta, t]) or after it
+// ([t, t + delta]).  Stored as 4 bytes {mode1, after1, mode3, after3}.
+enum { SIDE_NONE = 0, SIDE_IN = 1, SIDE_OUT = 2 };
+struct Class {
+  int mode[2];   // side 1, side 3
+  int after[2];
+};
+const Class kSpineClass = {{SIDE_IN, SIDE_OUT}, {0, 1}};
+
+bool parse_class(const uint8_t* c, Class* K) {
+  if (!c) { *K = kSpineClass; return true; }
+  for (int s = 0; s < 2; ++s) {
+    K->mode[s] = c[2 * s];
+    K->after[s] = c[2 * s + 1];
+    if (K->mode[s] > SIDE_OUT || K->after[s] > 1) return false;
+  }
+  return K->mode[0] != SIDE_NONE || K->mode[1] != SIDE_NONE;
+}
+
+bool same_class(const Class& a, const Class& b) {
+  for (int s = 0; s < 2; ++s) {
+    if (a.mode[s] != b.mode[s]) return false;
+    if (a.mode[s] != SIDE_NONE && a.after[s] != b.after[s]) return false;
+  }
+  return true;
+}
+
+// A motif with its anchor (Algorithm Estimate: an anchor path that holds
+// the motif edge of time rank 0).  Edge i of the motif has rank i.
 struct Motif {
   int nv, ne;
   int src[16], dst[16];
+  Class cls;
+  int aedge[3];   // motif edge of e1 (side 1), e2 (centre), e3 (side 3); -1 = no edge
+  int na;         // anchor edges: 3 (a path) or 2 (a wedge)
+  int order[3];   // anchor edges by increasing rank, as 0 = e1, 1 = e2, 2 = e3
+  int slot[16];   // motif vertex -> position in phi = (x, u, v, y)
+  int nl;         // non-anchor edges, in rank order
+  int lslot_a[16], lslot_b[16], lseg[16];  // their pairs and segments
 };
+
+// The anchor of M (the choice the library makes too):
+//  4 vertices: every (e1, e2, e3) of distinct motif edges that is a path
+//    x - u - v - y over four distinct vertices, centre e2 = (u -> v) as
+//    directed in the motif, holding rank 0; the one whose sorted ranks are
+//    lexicographically smallest, then the smallest centre rank, then the
+//    smallest e1 rank.
+//  3 vertices: every (centre, side edge) pair of distinct motif edges over
+//    three distinct vertices holding rank 0, the side edge meeting the
+//    centre in one vertex; smallest sorted ranks, then smallest centre rank.
+// Returns false when there is none (e.g. a 3-star).
+bool compile_anchor(Motif* M) {
+  const int ne = M->ne;
+  int best[3] = {-1, -1, -1};
+  long best_key = -1;
+  auto touches = [&](int e, int a) { return M->src[e] == a || M->dst[e] == a; };
+  auto other = [&](int e, int a) { return M->src[e] == a ? M->dst[e] : M->src[e]; };
+  if (M->nv == 4) {
+    for (int c = 0; c < ne; ++c) {
+      const int U = M->src[c], V = M->dst[c];
+      for (int e1 = 0; e1 < ne; ++e1) {
+        if (e1 == c || !touches(e1, U) || touches(e1, V)) continue;
+        const int X = other(e1, U);
+        for (int e3 = 0; e3 < ne; ++e3) {
+          if (e3 == c || e3 == e1 || !touches(e3, V) || touches(e3, U)) continue;
+          const int Y = other(e3, V);
+          if (Y == X) continue;
+          if (c != 0 && e1 != 0 && e3 != 0) continue;
+          int r[3] = {e1, c, e3};
+          std::sort(r, r + 3);
+          const long key = (((((long)r[0] * 16 + r[1]) * 16 + r[2]) * 16 + c) * 16 + e1);
+          if (best_key < 0 || key < best_key) {
+            best_key = key;
+            best[0] = e1; best[1] = c; best[2] = e3;
+          }
+        }
+      }
+    }
+  } else if (M->nv == 3) {
+    for (int c = 0; c < ne; ++c) {
+      const int U = M->src[c], V = M->dst[c];
+      for (int e = 0; e < ne; ++e) {
+        if (e == c || touches(e, U) == touches(e, V)) continue;  // meets exactly one end
+        if (c != 0 && e != 0) continue;
+        const int lo = std::min(c, e), hi = std::max(c, e);
+        const long key = ((long)lo * 16 + hi) * 16 + c;
+        if (best_key < 0 || key < best_key) {
+          best_key = key;
+          best[1] = c;
+          best[0] = touches(e, U) ? e : -1;
+          best[2] = touches(e, U) ? -1 : e;
+        }
+      }
+    }
+  }
+  if (best_key < 0) return false;
+  for (int i = 0; i < 3; ++i) M->aedge[i] = best[i];
+  const int c = best[1], U = M->src[c], V = M->dst[c];
+  for (int i = 0; i < 16; ++i) M->slot[i] = -1;
+  M->slot[U] = 1;
+  M->slot[V] = 2;
+  M->na = 1;
+  for (int s = 0; s < 2; ++s) {
+    const int e = best[2 * s];
+    const int at = s == 0 ? U : V;
+    if (e < 0) {
+      M->cls.mode[s] = SIDE_NONE;
+      M->cls.after[s] = 0;
+      continue;
+    }
+    ++M->na;
+    M->cls.mode[s] = (M->dst[e] == at) ? SIDE_IN : SIDE_OUT;
+    M->cls.after[s] = e > c ? 1 : 0;
+    M->slot[other(e, at)] = s == 0 ? 0 : 3;
+  }
+  for (int v = 0; v < M->nv; ++v)
+    if (M->slot[v] < 0) return false;  // a vertex the anchor does not reach
+  // anchor edges by rank
+  int k = 0;
+  for (int r = 0; r < ne; ++r)
+    for (int i = 0; i < 3; ++i)
+      if (best[i] == r) M->order[k++] = i;
+  // the other edges: lists, each bounded by the anchor edges around it
+  M->nl = 0;
+  for (int r = 0; r < ne; ++r) {
+    if (r == best[0] || r == best[1] || r == best[2]) continue;
+    int below = 0;
+    for (int i = 0; i < 3; ++i)
+      if (best[i] >= 0 && best[i] < r) ++below;
+    M->lslot_a[M->nl] = M->slot[M->src[r]];
+    M->lslot_b[M->nl] = M->slot[M->dst[r]];
+    M->lseg[M->nl] = below - 1;
+    ++M->nl;
+  }
+  return true;
+}
 
 bool parse_motif(const uint8_t* d, Motif* M) {
   M->nv = d[0];
   M->ne = d[1];
-  if (M->nv != 4 || M->ne < 3 || M->ne > 16) return false;
+  if (M->nv < 3 || M->nv > 4 || M->ne < 2 || M->ne > 16) return false;
   for (int i = 0; i < M->ne; ++i) {
     M->src[i] = d[2 + i];
     M->dst[i] = d[18 + i];
     if (M->src[i] >= M->nv || M->dst[i] >= M->nv || M->src[i] == M->dst[i]) return false;
   }
-  // the anchor is the directed 3-path formed by ranks 0, 1, 2: A->B->C->D
-  return M->src[0] == 0 && M->dst[0] == 1 && M->src[1] == 1 && M->dst[1] == 2 &&
-         M->src[2] == 2 && M->dst[2] == 3;
+  return compile_anchor(M);
 }
 
 struct Graph {
@@ -255,54 +390,96 @@ bool list_count(const std::vector<std::vector<int64_t>>& L, u128* X) {
   return true;
 }
 
-// CheckMotif for the path (e1, e2, e3) with e1 = (x,u,t1), e2 = (u,v,t2),
-// e3 = (v,y,t3), all given by edge id.
+// The edge of an anchor side at the centre edge's endpoint `at` (u for
+// side 1, v for side 3): position `pos` of the in-CSR or the out-CSR.
+int32_t side_edge(const Graph& G, int mode, int64_t pos) {
+  return mode == SIDE_IN ? G.in_ord[pos] : G.out_ord[pos];
+}
+
+// CheckMotif (Algorithm CheckMotif, generalised to the anchor classes) for
+// the anchor (e1, e2, e3) given by edge ids (-1 for an absent side): the
+// number of M-matches in which these edges are the images of the motif's
+// anchor edges.  phi = (x, u, v, y) with e2 = (u -> v); x is e1's other end
+// at u, y is e3's other end at v.  The anchor must span distinct vertices,
+// its times must strictly increase in rank order and lie within delta of
+// the first; each other motif edge of rank r is then looked for among the
+// edges of its pair with time after the anchor edge ranked just below r and
+// before the one ranked just above it (or at most the first time + delta),
+// and ListCount counts the strictly increasing chains through those lists.
 int check_motif(const Graph& G, const Motif& M, int64_t delta, int32_t e1, int32_t e2,
-                int32_t e3, uint64_t* X) {
-  int32_t x = G.src[e1], u = G.dst[e1];
-  int32_t u2 = G.src[e2], v = G.dst[e2];
-  int32_t v3 = G.src[e3], y = G.dst[e3];
+                int32_t e3, u128* X) {
   *X = 0;
-  if (u != u2 || v != v3) return OR_ARG;  // not a 3-path
-  int64_t t1 = G.t[e1], t2 = G.t[e2], t3 = G.t[e3];
-  int32_t phi[4] = {x, u, v, y};
+  const int32_t u = G.src[e2], v = G.dst[e2];
+  int32_t phi[4] = {-1, u, v, -1};
+  const int32_t ae[3] = {e1, e2, e3};
+  for (int s = 0; s < 2; ++s) {
+    const int32_t e = ae[2 * s];
+    const int mode = M.cls.mode[s];
+    if ((mode == SIDE_NONE) != (e < 0)) return OR_ARG;
+    if (mode == SIDE_NONE) continue;
+    const int32_t at = s == 0 ? u : v;
+    if (mode == SIDE_IN && G.dst[e] != at) return OR_ARG;
+    if (mode == SIDE_OUT && G.src[e] != at) return OR_ARG;
+    phi[s == 0 ? 0 : 3] = mode == SIDE_IN ? G.src[e] : G.dst[e];
+  }
   for (int i = 0; i < 4; ++i)
     for (int j = i + 1; j < 4; ++j)
-      if (phi[i] == phi[j]) return OR_OK;
-  if (t3 > t1 + delta) return OR_OK;
-  if (!(t1 < t2 && t2 < t3)) return OR_OK;
+      if (phi[i] >= 0 && phi[i] == phi[j]) return OR_OK;
+  int64_t T[3];
+  for (int k = 0; k < M.na; ++k) T[k] = G.t[ae[M.order[k]]];
+  for (int k = 1; k < M.na; ++k)
+    if (!(T[k - 1] < T[k])) return OR_OK;
+  if (T[M.na - 1] - T[0] > delta) return OR_OK;
   std::vector<std::vector<int64_t>> L;
-  for (int r = 3; r < M.ne; ++r) {
+  for (int i = 0; i < M.nl; ++i) {
+    const int sg = M.lseg[i];
+    const int64_t lo = T[sg];
+    const int64_t hi = sg + 1 < M.na ? T[sg + 1] - 1 : T[0] + delta;
     int64_t f, l;
-    pair_window(G, phi[M.src[r]], phi[M.dst[r]], t3, t1 + delta, &f, &l);
+    pair_window(G, phi[M.lslot_a[i]], phi[M.lslot_b[i]], lo, hi, &f, &l);
     L.emplace_back(G.pair_t.begin() + f, G.pair_t.begin() + l);
   }
-  u128 c;
-  if (!list_count(L, &c)) return OR_OVERFLOW;
-  *X = (uint64_t)c;
+  if (!list_count(L, X)) return OR_OVERFLOW;
   return OR_OK;
 }
 
-int window_weights(const Graph& G, int64_t delta, uint32_t* lo_in, uint32_t* a,
-                   uint32_t* lo_out, uint32_t* b, uint64_t* S, int nthreads) {
+// Preprocess for an anchor class: per scan position p (out-CSR order, centre
+// edge (u, v, t)) the window of each side -- the in- or out-edges of u
+// (side 1) resp. v (side 3) with time in [t - delta, t] or [t, t + delta],
+// closed -- as its first position in the in- or out-CSR and its size; an
+// absent side counts 1.  w_p = a_p * b_p (Claim "count" and the remark after
+// it: d^{alpha_1}_u times d^{alpha_3}_v over the class's intervals), S its
+// exact running total.
+int window_weights(const Graph& G, int64_t delta, const Class& K, uint32_t* lo1, uint32_t* a,
+                   uint32_t* lo3, uint32_t* b, uint64_t* S, int nthreads) {
   int64_t m = G.m;
 #pragma omp parallel for num_threads(nthreads) schedule(static)
   for (int64_t p = 0; p < m; ++p) {
     int32_t e = G.out_ord[p];
-    int32_t u = G.src[e], v = G.dst[e];
+    const int32_t ends[2] = {G.src[e], G.dst[e]};
     int64_t t = G.t[e];
-    auto ib = G.in_t.begin();
-    // d^-_u[t - delta, t]: closed window in u's in-list
-    int64_t i0 = std::lower_bound(ib + G.in_off[u], ib + G.in_off[u + 1], t - delta) - ib;
-    int64_t i1 = std::upper_bound(ib + G.in_off[u], ib + G.in_off[u + 1], t) - ib;
-    auto ob = G.out_t.begin();
-    // d^+_v[t, t + delta]: closed window in v's out-list
-    int64_t o0 = std::lower_bound(ob + G.out_off[v], ob + G.out_off[v + 1], t) - ob;
-    int64_t o1 = std::upper_bound(ob + G.out_off[v], ob + G.out_off[v + 1], t + delta) - ob;
-    lo_in[p] = (uint32_t)i0;
-    a[p] = (uint32_t)(i1 - i0);
-    lo_out[p] = (uint32_t)o0;
-    b[p] = (uint32_t)(o1 - o0);
+    uint32_t lo[2], cnt[2];
+    for (int s = 0; s < 2; ++s) {
+      if (K.mode[s] == SIDE_NONE) {
+        lo[s] = 0;
+        cnt[s] = 1;
+        continue;
+      }
+      const int32_t w = ends[s];
+      const std::vector<int64_t>& tt = K.mode[s] == SIDE_IN ? G.in_t : G.out_t;
+      const std::vector<uint32_t>& off = K.mode[s] == SIDE_IN ? G.in_off : G.out_off;
+      const int64_t from = K.after[s] ? t : t - delta;
+      const int64_t to = K.after[s] ? t + delta : t;
+      auto beg = tt.begin() + off[w], end = tt.begin() + off[w + 1];
+      const int64_t i0 = std::lower_bound(beg, end, from) - tt.begin();
+      const int64_t i1 = std::upper_bound(beg, end, to) - tt.begin();
+      lo[s] = (uint32_t)i0;
+      cnt[s] = (uint32_t)(i1 - i0);
+    }
+    lo1[p] = lo[0];
+    a[p] = cnt[0];
+    lo3[p] = lo[1];
+    b[p] = cnt[1];
   }
   u128 run = 0;
   int st = OR_OK;
@@ -313,6 +490,21 @@ int window_weights(const Graph& G, int64_t delta, uint32_t* lo_in, uint32_t* a,
   if (run > kU64Max) st = OR_OVERFLOW;
   S[m] = (uint64_t)run;
   return st;
+}
+
+// The motifs of one call share the anchor's class, its number of edges and
+// their rank order (so one sampled anchor serves every motif).
+int parse_motifs(const uint8_t* motifs, int n, const Class& K, std::vector<Motif>* Ms) {
+  Ms->resize(n);
+  for (int j = 0; j < n; ++j) {
+    if (!parse_motif(motifs + 34 * j, &(*Ms)[j])) return OR_ARG;
+    const Motif& A = (*Ms)[0];
+    const Motif& B = (*Ms)[j];
+    if (!same_class(B.cls, K) || B.na != A.na) return OR_ARG;
+    for (int k = 0; k < B.na; ++k)
+      if (B.order[k] != A.order[k]) return OR_ARG;
+  }
+  return OR_OK;
 }
 
 double u128_over_k_times_w(u128 cnt, uint64_t k, uint64_t W) {
@@ -356,21 +548,51 @@ void or_graph_orders(void* h, int32_t* out_ord, int32_t* in_ord, int32_t* pair_o
 int or_weights(void* h, int64_t delta, uint32_t* lo_in, uint32_t* a, uint32_t* lo_out,
                uint32_t* b, uint64_t* S, int nthreads) {
   if (delta < 0 || delta > kTLimit) return OR_ARG;
-  return window_weights(*(Graph*)h, delta, lo_in, a, lo_out, b, S, nthreads);
+  return window_weights(*(Graph*)h, delta, kSpineClass, lo_in, a, lo_out, b, S, nthreads);
 }
 
-// One delta-centred path given by edge ids -> CheckMotif count.
+// Preprocess for the class given by 4 bytes {mode1, after1, mode3, after3}.
+int or_weights_class(void* h, int64_t delta, const uint8_t* cls, uint32_t* lo1, uint32_t* a,
+                     uint32_t* lo3, uint32_t* b, uint64_t* S, int nthreads) {
+  Class K;
+  if (delta < 0 || delta > kTLimit || !parse_class(cls, &K)) return OR_ARG;
+  return window_weights(*(Graph*)h, delta, K, lo1, a, lo3, b, S, nthreads);
+}
+
+// The class of a motif's anchor (4 bytes), its number of anchor edges and
+// their rank order; OR_ARG when the motif has no anchor.
+int or_anchor(const uint8_t* motif, uint8_t* cls, int32_t* na, int32_t* order, int32_t* aedge) {
+  Motif M;
+  if (!parse_motif(motif, &M)) return OR_ARG;
+  for (int s = 0; s < 2; ++s) {
+    cls[2 * s] = (uint8_t)M.cls.mode[s];
+    cls[2 * s + 1] = (uint8_t)M.cls.after[s];
+  }
+  *na = M.na;
+  for (int k = 0; k < 3; ++k) {
+    order[k] = k < M.na ? M.order[k] : -1;
+    aedge[k] = M.aedge[k];
+  }
+  return OR_OK;
+}
+
+// One anchor given by edge ids (-1 for an absent side) -> CheckMotif count.
 int or_check_motif(void* h, const uint8_t* motif, int64_t delta, int32_t e1, int32_t e2,
                    int32_t e3, uint64_t* X) {
   Motif M;
   if (!parse_motif(motif, &M)) return OR_ARG;
-  return check_motif(*(Graph*)h, M, delta, e1, e2, e3, X);
+  u128 c = 0;
+  const int st = check_motif(*(Graph*)h, M, delta, e1, e2, e3, &c);
+  *X = (uint64_t)c;
+  return st;
 }
 
-// Estimate(M, k) for a batch of motifs that share the anchor: samples
-// i0 .. i0+k-1 of (seed, stream).  Optional per-sample outputs (null = off):
-// e1/e2/e3 edge ids [k], X motif-major [n_motifs * k], P the scan position of
-// the centre edge [k].  cnt holds (lo, hi) per motif.
+// Estimate(M, k) for a batch of motifs that share the anchor (class `cls`,
+// null = the <-,+,<,>> class): samples i0 .. i0+k-1 of (seed, stream).
+// Optional per-sample outputs (null = off): e1/e2/e3 edge ids [k] (-1 for an
+// absent side), X motif-major [n_motifs * k], P the scan position of the
+// centre edge [k].  cnt holds (lo, hi) per motif; xmax (null = off) the
+// largest X.
 //
 // With a proposal h (null = plain sampler), S must be the scan of
 // q_p = w_p * h_p and Q = S[m]: the centre edge is drawn with probability
@@ -378,20 +600,20 @@ int or_check_motif(void* h, const uint8_t* motif, int64_t delta, int32_t e1, int
 // unbiased per-sample value is Y = X * Q / h_p.  cnt then accumulates
 // floor(X * 2^64 / h_p) in 128 bits and est = (cnt * 2^-64 / k) * Q.
 // m2 (null = off) receives sum over samples of (X / h_p)^2 in binary64.
-int or_sample_ex(void* hg, int64_t delta, const uint32_t* lo_in, const uint32_t* a,
-                 const uint32_t* lo_out, const uint32_t* b, const uint64_t* S,
-                 const uint32_t* hq, const uint8_t* motifs, int n_motifs, uint64_t k,
-                 uint64_t seed, uint32_t stream, uint64_t i0, int32_t* e1o, int32_t* e2o,
-                 int32_t* e3o, uint64_t* Xo, uint32_t* Po, uint64_t* cnt, uint64_t* hits,
-                 double* est, double* m2o, int nthreads) {
+int or_sample_cls(void* hg, int64_t delta, const uint8_t* cls, const uint32_t* lo1,
+                  const uint32_t* a, const uint32_t* lo3, const uint32_t* b, const uint64_t* S,
+                  const uint32_t* hq, const uint8_t* motifs, int n_motifs, uint64_t k,
+                  uint64_t seed, uint32_t stream, uint64_t i0, int32_t* e1o, int32_t* e2o,
+                  int32_t* e3o, uint64_t* Xo, uint32_t* Po, uint64_t* cnt, uint64_t* hits,
+                  double* est, double* m2o, uint64_t* xmax, int nthreads) {
   Graph& G = *(Graph*)hg;
-  if (n_motifs < 1 || n_motifs > 16 || k < 1) return OR_ARG;
-  std::vector<Motif> Ms(n_motifs);
-  for (int j = 0; j < n_motifs; ++j)
-    if (!parse_motif(motifs + 34 * j, &Ms[j])) return OR_ARG;
+  Class K;
+  if (n_motifs < 1 || n_motifs > 16 || k < 1 || !parse_class(cls, &K)) return OR_ARG;
+  std::vector<Motif> Ms;
+  if (parse_motifs(motifs, n_motifs, K, &Ms) != OR_OK) return OR_ARG;
   const uint64_t W = S[G.m];  // W, or Q with a proposal
   std::vector<u128> c(n_motifs, 0);
-  std::vector<uint64_t> hh(n_motifs, 0);
+  std::vector<uint64_t> hh(n_motifs, 0), mx(n_motifs, 0);
   std::vector<double> mm(n_motifs, 0.0);
   int status = OR_OK;
   if (W == 0) {
@@ -403,6 +625,7 @@ int or_sample_ex(void* hg, int64_t delta, const uint32_t* lo_in, const uint32_t*
   } else {
     std::vector<std::vector<u128>> pc(nthreads, std::vector<u128>(n_motifs, 0));
     std::vector<std::vector<uint64_t>> ph(nthreads, std::vector<uint64_t>(n_motifs, 0));
+    std::vector<std::vector<uint64_t>> px(nthreads, std::vector<uint64_t>(n_motifs, 0));
     std::vector<std::vector<double>> pm(nthreads, std::vector<double>(n_motifs, 0.0));
     std::vector<int> pst(nthreads, OR_OK);
 #pragma omp parallel for num_threads(nthreads) schedule(static)
@@ -420,6 +643,8 @@ int or_sample_ex(void* hg, int64_t delta, const uint32_t* lo_in, const uint32_t*
       if (!ok) { pst[tid] |= OR_RNG; continue; }
       // pick e with probability w_e / W (or q_e / Q): S[p] <= r < S[p+1]
       int64_t p = std::upper_bound(S, S + G.m + 1, r) - S - 1;
+      // then a uniform edge in each side's window (an absent side has one
+      // position and takes no edge)
       uint32_t j1 = 0, j3 = 0;
       ok = false;
       for (uint32_t n = 0; n < (uint32_t)kMaxAttempts && !ok; ++n) {
@@ -434,14 +659,15 @@ int or_sample_ex(void* hg, int64_t delta, const uint32_t* lo_in, const uint32_t*
       }
       if (!ok) { pst[tid] |= OR_RNG; continue; }
       int32_t e2 = G.out_ord[p];
-      int32_t e1 = G.in_ord[lo_in[p] + j1];
-      int32_t e3 = G.out_ord[lo_out[p] + j3];
+      int32_t e1 = K.mode[0] == SIDE_NONE ? -1 : side_edge(G, K.mode[0], lo1[p] + j1);
+      int32_t e3 = K.mode[1] == SIDE_NONE ? -1 : side_edge(G, K.mode[1], lo3[p] + j3);
       if (e1o) { e1o[ii] = e1; e2o[ii] = e2; e3o[ii] = e3; }
       if (Po) Po[ii] = (uint32_t)p;
       const uint32_t hp = hq ? hq[p] : 1u;
       for (int j = 0; j < n_motifs; ++j) {
-        uint64_t X = 0;
-        int st = check_motif(G, Ms[j], delta, e1, e2, e3, &X);
+        u128 X128 = 0;
+        int st = check_motif(G, Ms[j], delta, e1, e2, e3, &X128);
+        const uint64_t X = (uint64_t)X128;
         // an overflow also names its motif (bit 8 + j)
         pst[tid] |= st | ((st & OR_OVERFLOW) ? (1 << (8 + j)) : 0);
         if (Xo) Xo[(uint64_t)j * k + ii] = X;
@@ -449,6 +675,7 @@ int or_sample_ex(void* hg, int64_t delta, const uint32_t* lo_in, const uint32_t*
         if (pc[tid][j] + add < pc[tid][j]) pst[tid] |= OR_OVERFLOW | (1 << (8 + j));
         pc[tid][j] += add;
         ph[tid][j] += X > 0;
+        px[tid][j] = std::max(px[tid][j], X);
         const double v = (double)X / (double)hp;
         pm[tid][j] += v * v;
       }
@@ -460,6 +687,7 @@ int or_sample_ex(void* hg, int64_t delta, const uint32_t* lo_in, const uint32_t*
         c[j] += pc[tid][j];
         hh[j] += ph[tid][j];
         mm[j] += pm[tid][j];
+        mx[j] = std::max(mx[j], px[tid][j]);
       }
     }
   }
@@ -476,8 +704,19 @@ int or_sample_ex(void* hg, int64_t delta, const uint32_t* lo_in, const uint32_t*
       est[j] = u128_over_k_times_w(c[j], k, W);
     }
     if (m2o) m2o[j] = mm[j];
+    if (xmax) xmax[j] = mx[j];
   }
   return status;
+}
+
+int or_sample_ex(void* hg, int64_t delta, const uint32_t* lo_in, const uint32_t* a,
+                 const uint32_t* lo_out, const uint32_t* b, const uint64_t* S,
+                 const uint32_t* hq, const uint8_t* motifs, int n_motifs, uint64_t k,
+                 uint64_t seed, uint32_t stream, uint64_t i0, int32_t* e1o, int32_t* e2o,
+                 int32_t* e3o, uint64_t* Xo, uint32_t* Po, uint64_t* cnt, uint64_t* hits,
+                 double* est, double* m2o, int nthreads) {
+  return or_sample_cls(hg, delta, nullptr, lo_in, a, lo_out, b, S, hq, motifs, n_motifs, k, seed,
+                       stream, i0, e1o, e2o, e3o, Xo, Po, cnt, hits, est, m2o, nullptr, nthreads);
 }
 
 int or_sample(void* h, int64_t delta, const uint32_t* lo_in, const uint32_t* a,
@@ -487,6 +726,81 @@ int or_sample(void* h, int64_t delta, const uint32_t* lo_in, const uint32_t* a,
               uint64_t* cnt, uint64_t* hits, double* est, int nthreads) {
   return or_sample_ex(h, delta, lo_in, a, lo_out, b, S, nullptr, motifs, n_motifs, k, seed,
                       stream, i0, e1o, e2o, e3o, Xo, nullptr, cnt, hits, est, nullptr, nthreads);
+}
+
+// Exhaustive mode: the anchors of ranks r0 .. r0 + count - 1 (clipped to W)
+// in the order of the integer CDF -- rank r is centre p with
+// S[p] <= r < S[p+1] and j = r - S[p] = j1 * b_p + j3 -- each run through
+// CheckMotif for every motif.  Over all W ranks cnt is the exact count C
+// (proof of Claim "est": every match has exactly one anchor), hits the
+// anchors with a match, m2 the sum of X^2 (binary64) and xmax the largest X:
+// the B statistics (number of matches sharing an anchor) over anchors with
+// a match are cnt / hits, sqrt(m2 / hits - (cnt / hits)^2) and xmax.
+// Per-rank outputs as in or_sample_cls (index r - r0); est = cnt in binary64.
+int or_enumerate(void* hg, int64_t delta, const uint8_t* cls, const uint32_t* lo1,
+                 const uint32_t* a, const uint32_t* lo3, const uint32_t* b, const uint64_t* S,
+                 const uint8_t* motifs, int n_motifs, uint64_t r0, uint64_t count, int32_t* e1o,
+                 int32_t* e2o, int32_t* e3o, uint64_t* Xo, uint64_t* cnt, uint64_t* hits,
+                 double* est, double* m2o, uint64_t* xmax, int nthreads) {
+  Graph& G = *(Graph*)hg;
+  Class K;
+  if (n_motifs < 1 || n_motifs > 16 || !parse_class(cls, &K)) return OR_ARG;
+  std::vector<Motif> Ms;
+  if (parse_motifs(motifs, n_motifs, K, &Ms) != OR_OK) return OR_ARG;
+  const uint64_t W = S[G.m];
+  std::vector<std::vector<u128>> pc(nthreads, std::vector<u128>(n_motifs, 0));
+  std::vector<std::vector<uint64_t>> ph(nthreads, std::vector<uint64_t>(n_motifs, 0));
+  std::vector<std::vector<uint64_t>> px(nthreads, std::vector<uint64_t>(n_motifs, 0));
+  std::vector<std::vector<double>> pm(nthreads, std::vector<double>(n_motifs, 0.0));
+  std::vector<int> pst(nthreads, OR_OK);
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 256)
+  for (int64_t ii = 0; ii < (int64_t)count; ++ii) {
+    int tid = omp_get_thread_num();
+    const uint64_t r = r0 + (uint64_t)ii;
+    if (r >= W || r < r0) {
+      if (e1o) { e1o[ii] = -1; e2o[ii] = -1; e3o[ii] = -1; }
+      if (Xo) for (int j = 0; j < n_motifs; ++j) Xo[(uint64_t)j * count + ii] = 0;
+      continue;
+    }
+    const int64_t p = std::upper_bound(S, S + G.m + 1, r) - S - 1;
+    const uint64_t jj = r - S[p];
+    const uint32_t j1 = (uint32_t)(jj / b[p]), j3 = (uint32_t)(jj % b[p]);
+    int32_t e2 = G.out_ord[p];
+    int32_t e1 = K.mode[0] == SIDE_NONE ? -1 : side_edge(G, K.mode[0], lo1[p] + j1);
+    int32_t e3 = K.mode[1] == SIDE_NONE ? -1 : side_edge(G, K.mode[1], lo3[p] + j3);
+    if (e1o) { e1o[ii] = e1; e2o[ii] = e2; e3o[ii] = e3; }
+    for (int j = 0; j < n_motifs; ++j) {
+      u128 X128 = 0;
+      int st = check_motif(G, Ms[j], delta, e1, e2, e3, &X128);
+      const uint64_t X = (uint64_t)X128;
+      pst[tid] |= st | ((st & OR_OVERFLOW) ? (1 << (8 + j)) : 0);
+      if (Xo) Xo[(uint64_t)j * count + ii] = X;
+      pc[tid][j] += X;
+      ph[tid][j] += X > 0;
+      px[tid][j] = std::max(px[tid][j], X);
+      pm[tid][j] += (double)X * (double)X;
+    }
+  }
+  int status = OR_OK;
+  for (int j = 0; j < n_motifs; ++j) {
+    u128 c = 0;
+    uint64_t h = 0, mx = 0;
+    double mm = 0.0;
+    for (int tid = 0; tid < nthreads; ++tid) {
+      c += pc[tid][j];
+      h += ph[tid][j];
+      mm += pm[tid][j];
+      mx = std::max(mx, px[tid][j]);
+    }
+    cnt[2 * j] = (uint64_t)c;
+    cnt[2 * j + 1] = (uint64_t)(c >> 64);
+    hits[j] = h;
+    est[j] = (double)c;
+    if (m2o) m2o[j] = mm;
+    if (xmax) xmax[j] = mx;
+  }
+  for (int tid = 0; tid < nthreads; ++tid) status |= pst[tid];
+  return status;
 }
 
 // Scan of the proposal weights q_p = a_p * b_p * h_p (exact, 128-bit
@@ -569,12 +883,13 @@ void or_features(void* hg, int64_t delta, const uint32_t* lo_in, const uint32_t*
 // Sum of CheckMotif over every delta-centred <-,+,<,>> path (all W of them):
 // by the proof of Claim "est" this equals the number of M-matches.  Also
 // returns sum X^2 and the number of paths with X > 0.
-int or_exhaustive(void* h, const uint8_t* motif, int64_t delta, const uint32_t* lo_in,
-                  const uint32_t* a, const uint32_t* lo_out, const uint32_t* b,
+int or_exhaustive(void* h, const uint8_t* motif, int64_t delta, const uint8_t* cls,
+                  const uint32_t* lo1, const uint32_t* a, const uint32_t* lo3, const uint32_t* b,
                   uint64_t* sum_x, uint64_t* sum_x2, uint64_t* nonzero, int nthreads) {
   Graph& G = *(Graph*)h;
   Motif M;
-  if (!parse_motif(motif, &M)) return OR_ARG;
+  Class K;
+  if (!parse_motif(motif, &M) || !parse_class(cls, &K) || !same_class(M.cls, K)) return OR_ARG;
   std::vector<u128> s1(nthreads, 0), s2(nthreads, 0);
   std::vector<uint64_t> nz(nthreads, 0);
   std::vector<int> pst(nthreads, OR_OK);
@@ -583,11 +898,12 @@ int or_exhaustive(void* h, const uint8_t* motif, int64_t delta, const uint32_t* 
     int tid = omp_get_thread_num();
     for (uint32_t j1 = 0; j1 < a[p]; ++j1)
       for (uint32_t j3 = 0; j3 < b[p]; ++j3) {
-        uint64_t X;
-        pst[tid] |= check_motif(G, M, delta, G.in_ord[lo_in[p] + j1], G.out_ord[p],
-                                G.out_ord[lo_out[p] + j3], &X);
+        u128 X = 0;
+        const int32_t e1 = K.mode[0] == SIDE_NONE ? -1 : side_edge(G, K.mode[0], lo1[p] + j1);
+        const int32_t e3 = K.mode[1] == SIDE_NONE ? -1 : side_edge(G, K.mode[1], lo3[p] + j3);
+        pst[tid] |= check_motif(G, M, delta, e1, G.out_ord[p], e3, &X);
         s1[tid] += X;
-        s2[tid] += (u128)X * X;
+        s2[tid] += X * X;
         nz[tid] += X > 0;
       }
   }
@@ -717,19 +1033,30 @@ int or_list_lengths(void* h, const uint8_t* motif, int64_t delta, int32_t e1, in
   Graph& G = *(Graph*)h;
   Motif M;
   if (!parse_motif(motif, &M)) return -2;
-  int32_t x = G.src[e1], u = G.dst[e1], v = G.dst[e2], y = G.dst[e3];
-  int64_t t1 = G.t[e1], t2 = G.t[e2], t3 = G.t[e3];
-  int32_t phi[4] = {x, u, v, y};
+  const int32_t u = G.src[e2], v = G.dst[e2];
+  int32_t phi[4] = {-1, u, v, -1};
+  const int32_t ae[3] = {e1, e2, e3};
+  for (int s = 0; s < 2; ++s) {
+    const int32_t e = ae[2 * s];
+    if ((M.cls.mode[s] == SIDE_NONE) != (e < 0)) return -2;
+    if (e >= 0) phi[s == 0 ? 0 : 3] = M.cls.mode[s] == SIDE_IN ? G.src[e] : G.dst[e];
+  }
   for (int i = 0; i < 4; ++i)
     for (int j = i + 1; j < 4; ++j)
-      if (phi[i] == phi[j]) return -1;
-  if (t3 > t1 + delta || !(t1 < t2 && t2 < t3)) return -1;
-  for (int r = 3; r < M.ne; ++r) {
+      if (phi[i] >= 0 && phi[i] == phi[j]) return -1;
+  int64_t T[3];
+  for (int k = 0; k < M.na; ++k) T[k] = G.t[ae[M.order[k]]];
+  for (int k = 1; k < M.na; ++k)
+    if (!(T[k - 1] < T[k])) return -1;
+  if (T[M.na - 1] - T[0] > delta) return -1;
+  for (int i = 0; i < M.nl; ++i) {
+    const int sg = M.lseg[i];
+    const int64_t hi = sg + 1 < M.na ? T[sg + 1] - 1 : T[0] + delta;
     int64_t f, l;
-    pair_window(G, phi[M.src[r]], phi[M.dst[r]], t3, t1 + delta, &f, &l);
-    lens[r - 3] = l - f;
+    pair_window(G, phi[M.lslot_a[i]], phi[M.lslot_b[i]], T[sg], hi, &f, &l);
+    lens[i] = l - f;
   }
-  return M.ne - 3;
+  return M.nl;
 }
 
 }  // extern "C"
