@@ -45,7 +45,7 @@ typedef enum {
   TC_E_ARG = -1,          /* null pointer, bad size, bad delta or k            */
   TC_E_RANGE = -2,        /* reserved for host-side reporting of TC_F_RANGE     */
   TC_E_OVERFLOW = -3,     /* reserved for host-side reporting of TC_F_OVERFLOW  */
-  TC_E_UNSUPPORTED = -4,  /* motif not anchored on the directed 3-path 0-1-2-3   */
+  TC_E_UNSUPPORTED = -4,  /* motif without an anchor path or wedge              */
   TC_E_WORKSPACE = -5,    /* workspace smaller than the query reported          */
   TC_E_HIP = -6           /* a HIP runtime call failed                          */
 } tc_status;
@@ -59,15 +59,48 @@ typedef enum {
 #define TC_F_MOTIF(j) (1u << (8 + (j)))
 
 /* A temporal motif: H's edges listed in pi order (edge i has time rank i),
- * vertices 0..nv-1.  Supported: nv == 4, 3 <= ne <= 16, no self-loops, and
- * ranks 0, 1, 2 equal to 0->1, 1->2, 2->3.  That 3-path (A->B->C->D) holds the
- * pi-earliest edge and is the anchor S (section III-B; Algorithm Estimate
- * chooses an anchor containing the earliest edge).  Every later edge must
- * then fall in (t3, t1 + delta], which is how CheckMotif bounds its lists. */
+ * vertices 0..nv-1 (nv = 3 or 4), 2 <= ne <= 16, no self-loops.  Its anchor S
+ * (section III-B; Algorithm Estimate chooses an anchor holding the earliest
+ * edge) is found by the library:
+ *   nv = 4: a temporal 3-path x - u - v - y over four distinct vertices, its
+ *     centre edge u -> v, holding rank 0: among all, the one with the
+ *     lexicographically smallest sorted ranks, then the smallest centre
+ *     rank, then the smallest rank of the edge at u;
+ *   nv = 3: a wedge, centre edge u -> v plus one edge meeting u or v and
+ *     reaching the third vertex, holding rank 0: smallest sorted ranks, then
+ *     the smallest centre rank (so the centre is the earliest edge, the
+ *     "base" edge of the wedge).
+ * A motif with no such anchor (a 3-star, fewer than 3 vertices) gives
+ * TC_E_UNSUPPORTED.  The anchor's class (tc_class) says which weights it is
+ * sampled from; every other motif edge of rank r is looked for between the
+ * anchor edges ranked just below and just above r (or up to the first
+ * anchor time + delta), which is how CheckMotif bounds its lists. */
 typedef struct {
   uint8_t nv, ne;
   uint8_t src[16], dst[16];
 } tc_motif;
+
+/* Anchor class (section III: the classes <alpha_1, alpha_3, beta_1, beta_3>
+ * of delta-centred 3-paths, and the wedges of the 3-vertex case).  For the
+ * side at the centre edge's source u (side 1) and at its destination v
+ * (side 3): mode TC_SIDE_NONE (no edge: a wedge), TC_SIDE_IN (an in-edge,
+ * alpha = -) or TC_SIDE_OUT (an out-edge, alpha = +); after = 0 for an edge
+ * before the centre (window [t - delta, t], beta = <), 1 for one after it
+ * ([t, t + delta], beta = >).  At least one side has an edge.  The class
+ * <-,+,<,>> of the paper's presentation is {IN, 0, OUT, 1}. */
+#define TC_SIDE_NONE 0
+#define TC_SIDE_IN 1
+#define TC_SIDE_OUT 2
+typedef struct {
+  uint8_t mode1, after1, mode3, after3;
+} tc_class;
+
+/* The anchor of a motif: its class, the number of anchor edges (3 for a
+ * path, 2 for a wedge) and, in order[0..n_anchor-1], the anchor edges by
+ * increasing rank (0 = the edge at u, 1 = the centre, 2 = the edge at v).
+ * Errors: TC_E_ARG (null), TC_E_UNSUPPORTED (no anchor). */
+tc_status tc_motif_anchor(const tc_motif *motif, tc_class *cls, int32_t *n_anchor,
+                          int32_t *order);
 
 /* Time-sorted temporal adjacency (section III-A assumes per-vertex in- and
  * out-lists sorted by time; section III-B uses the per-pair lists L_{u,v}).
@@ -109,14 +142,17 @@ typedef struct tc_graph {
 } tc_graph;
 
 /* Per-edge window metadata and the exact integer CDF of the path weights,
- * all indexed by scan position p (out-CSR order):
- *   lo_in[p] = first position in the in-CSR of u's in-edges with time in
- *              [t - delta, t];  a[p] = their number  (d^-_u[t - delta, t])
- *   lo_out[p], b[p] likewise for v's out-edges in [t, t + delta]
- *              (d^+_v[t, t + delta])
+ * all indexed by scan position p (out-CSR order), centre edge (u, v, t):
+ *   lo_in[p], a[p]: side 1's window -- u's in-edges (in-CSR positions) or
+ *              out-edges (out-CSR positions) with time in [t - delta, t] or
+ *              [t, t + delta] as the class says: its first position and its
+ *              size (d^{alpha_1}_u over the interval); 0 and 1 when side 1
+ *              has no edge.  For the class {IN, 0, OUT, 1}: d^-_u[t - delta, t]
+ *   lo_out[p], b[p]: side 3's window at v likewise (d^+_v[t, t + delta])
  *   S[p] = sum_{q < p} a[q] * b[q]  (exclusive scan), S[m] = W_delta.
- * Claim "count" gives w_e = a * b; Algorithm Preprocess computes it with
- * four binary searches per edge.  Windows are closed on both ends. */
+ * Claim "count" and the remark after it give w_e = a * b; Algorithm
+ * Preprocess computes it with four binary searches per edge.  Windows are
+ * closed on both ends. */
 typedef struct tc_weights {
   int64_t delta;
   int64_t m;
@@ -133,6 +169,7 @@ typedef struct tc_weights {
                                          lo_out, b; i32 u, v; i64 t} of the scan
                                          positions (what the sampler needs of the
                                          centre edge, in one access)              */
+  tc_class cls;                       /* anchor class of the windows           */
 } tc_weights;
 
 /* Outputs of tc_sample_estimate, all (device), caller-allocated.
@@ -150,6 +187,7 @@ typedef struct tc_weights {
  *                        (X_ij / h_p)^2 in binary64 (h = 1 for the method's
  *                        weights), for variance estimates; its summation
  *                        order is not fixed (NULL = off)
+ *   xmax               : optional [n_motifs] largest X_ij (NULL = off)
  * With a proposal weight set (w->h != NULL) the estimator is importance
  * sampling: a path centred at p has probability h[p] / Q, Q = S[m], and
  * contributes Y = X * Q / h[p].  cnt_j then holds the exact 128-bit sum of
@@ -164,6 +202,7 @@ typedef struct tc_result {
   uint64_t *X;
   uint32_t *P;
   double *m2;
+  uint64_t *xmax;
 } tc_result;
 
 /* Launch-shape choices of the sampler.  They change speed only, never a
@@ -220,11 +259,19 @@ tc_status tc_build_graph(int32_t n, int64_t m, const int32_t *src, const int32_t
 tc_status tc_weights_workspace_bytes(int64_t m, size_t *bytes);
 
 /* Preprocess(delta): window metadata and S for every edge (Algorithm
- * Preprocess with Claim "count").  0 <= delta <= 2^62.  Enqueue only; W
- * stays on the device as S[m]; TC_F_OVERFLOW is set in *w->status when the
- * exact total reaches 2^64.  Errors: TC_E_ARG, TC_E_WORKSPACE, TC_E_HIP. */
+ * Preprocess with Claim "count") for the class {IN, 0, OUT, 1}.
+ * 0 <= delta <= 2^62.  Enqueue only; W stays on the device as S[m];
+ * TC_F_OVERFLOW is set in *w->status when the exact total reaches 2^64.
+ * Errors: TC_E_ARG, TC_E_WORKSPACE, TC_E_HIP. */
 tc_status tc_path_weights(const tc_graph *g, int64_t delta, void *ws, size_t ws_bytes,
                           void *stream, tc_weights *w);
+
+/* Preprocess(delta) for any anchor class (section III; the weight of a
+ * class is the product of its two sides' temporal degrees over the class's
+ * intervals, the remark after Claim "count").  The same workspace size as
+ * tc_path_weights.  Errors: as tc_path_weights, TC_E_ARG for a bad class. */
+tc_status tc_path_weights_class(const tc_graph *g, int64_t delta, const tc_class *cls, void *ws,
+                                size_t ws_bytes, void *stream, tc_weights *w);
 
 /* Workspace size in bytes for tc_sample_estimate with k samples and n_motifs
  * motifs (per-sample pair windows and the closure work queue of one chunk of
@@ -232,8 +279,10 @@ tc_status tc_path_weights(const tc_graph *g, int64_t delta, void *ws, size_t ws_
  * 1..16). */
 tc_status tc_sample_workspace_bytes(uint64_t k, int32_t n_motifs, size_t *bytes);
 
-/* Estimate(M, k) for n_motifs motifs (host array, 1..16) that share the
- * anchor: samples i0 .. i0+k-1 (k >= 1) of the counter-based stream
+/* Estimate(M, k) for n_motifs motifs (host array, 1..16) whose anchors have
+ * w's class, the same number of edges and the same rank order of those
+ * edges (TC_E_ARG otherwise): samples i0 .. i0+k-1 (k >= 1) of the
+ * counter-based stream
  * (seed, stream_id).  For each sample i (Algorithm Sample, then CheckMotif):
  *   Philox4x32-10 (Salmon et al., SC 2011) with counter
  *   (i mod 2^32, i div 2^32, attempt, stream_id) and key
@@ -241,12 +290,18 @@ tc_status tc_sample_workspace_bytes(uint64_t k, int32_t n_motifs, size_t *bytes)
  *   r = floor((x0 + 2^32 x1) * W / 2^64), j1 = floor(x2 * a_p / 2^32),
  *   j3 = floor(x3 * b_p / 2^32), each taken from the first attempt that
  *   passes Lemire's rejection test (exactly uniform);
- *   p is the edge with S[p] <= r < S[p+1]; e2 = out-CSR[p],
- *   e1 = in-CSR[lo_in[p] + j1], e3 = out-CSR[lo_out[p] + j3];
- *   X = 0 unless the four vertices are distinct, t1 < t2 < t3 and
- *   t3 - t1 <= delta; otherwise X = the number of strictly increasing
- *   chains l_3 < ... < l_{ne-1} with l_r a timestamp in (t3, t1 + delta] of
- *   the pair (phi(src_r), phi(dst_r)), phi = (x, u, v, y)  (ListCount).
+ *   p is the edge with S[p] <= r < S[p+1]; e2 = out-CSR[p] = (u, v, t2),
+ *   e1 = position lo_in[p] + j1 of the in- or out-CSR (side 1's mode),
+ *   e3 = position lo_out[p] + j3 likewise (an absent side: no edge, -1);
+ *   x is e1's other end, y is e3's other end, phi = (x, u, v, y);
+ *   X = 0 unless the anchor's vertices are distinct, its times strictly
+ *   increase in rank order and its last time is at most its first + delta;
+ *   otherwise X = the number of strictly increasing chains, in rank order,
+ *   of times of the motif's other edges, edge r taking the times of the pair
+ *   (phi(src_r), phi(dst_r)) after the anchor time ranked just below r and
+ *   before the one ranked just above it, or up to the first anchor time +
+ *   delta (ListCount).  For the spine motifs (ranks 0, 1, 2 = 0->1->2->3)
+ *   every list is the pair's times in (t3, t1 + delta].
  * W == 0 gives cnt = hits = 0, estimate 0, e* = -1, X = 0.
  * ws (device) is scratch of at least tc_sample_workspace_bytes(k, n_motifs)
  * bytes, reused across the call's chunks; calls that share it must be
@@ -256,6 +311,22 @@ tc_status tc_sample_estimate(const tc_graph *g, const tc_weights *w, const tc_mo
                              int32_t n_motifs, uint64_t k, uint64_t seed, uint32_t stream_id,
                              uint64_t i0, void *ws, size_t ws_bytes, tc_result *out,
                              void *stream);
+
+/* Exhaustive mode (the identity in the proof of Claim "est": every match has
+ * exactly one anchor, so the sum of CheckMotif over all W anchors is the
+ * count C): the anchors of ranks r0 .. r0 + count - 1 of the integer CDF,
+ * rank r being the centre p with S[p] <= r < S[p+1] and the window picks
+ * j1 = (r - S[p]) div b[p], j3 = (r - S[p]) mod b[p]; ranks at or past W
+ * contribute nothing.  Outputs as tc_sample_estimate, sample index r - r0
+ * (no random numbers are drawn): cnt = sum of X (exactly C when the ranks
+ * cover 0 .. W-1), hits = anchors with a match, m2 = sum of X^2, xmax = the
+ * largest X -- with hits, the statistics of B, the number of matches
+ * sharing one anchor (B_avg = cnt / hits, B_std from m2, B_max = xmax);
+ * estimate = cnt in binary64.  ws as for tc_sample_estimate with k = count.
+ * Errors: as tc_sample_estimate (count >= 1). */
+tc_status tc_exhaustive_count(const tc_graph *g, const tc_weights *w, const tc_motif *motifs,
+                              int32_t n_motifs, uint64_t r0, uint64_t count, void *ws,
+                              size_t ws_bytes, tc_result *out, void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc):

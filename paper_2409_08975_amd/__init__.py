@@ -29,7 +29,8 @@ _STATUS_NAMES = {0: "TC_OK", -1: "TC_E_ARG", -2: "TC_E_RANGE", -3: "TC_E_OVERFLO
                  -4: "TC_E_UNSUPPORTED", -5: "TC_E_WORKSPACE", -6: "TC_E_HIP"}
 
 EXPORTED = ["tc_version", "tc_graph_workspace_bytes", "tc_build_graph",
-            "tc_weights_workspace_bytes", "tc_path_weights", "tc_sample_workspace_bytes",
+            "tc_weights_workspace_bytes", "tc_path_weights", "tc_path_weights_class",
+            "tc_motif_anchor", "tc_exhaustive_count", "tc_sample_workspace_bytes",
             "tc_sample_estimate", "tc_sample_estimate_noalloc", "tc_batch_workspace_bytes", "tc_batch_estimate",
             "tc_autotune", "tc_features_workspace_bytes", "tc_edge_features", "tc_mlp_forward", "tc_mlp_workspace_bytes",
             "tc_mlp_grad", "tc_mlp_adam", "tc_mlp_train", "tc_quantize_proposal",
@@ -63,6 +64,23 @@ class tc_motif(ctypes.Structure):
                 ("src", ctypes.c_uint8 * 16), ("dst", ctypes.c_uint8 * 16)]
 
 
+TC_SIDE_NONE, TC_SIDE_IN, TC_SIDE_OUT = 0, 1, 2
+
+
+class tc_class(ctypes.Structure):
+    """Anchor class: side 1 (at the centre's source u) and side 3 (at its
+    destination v), each with a mode (none / in-edge / out-edge) and whether
+    its edge comes after the centre."""
+    _fields_ = [("mode1", ctypes.c_uint8), ("after1", ctypes.c_uint8),
+                ("mode3", ctypes.c_uint8), ("after3", ctypes.c_uint8)]
+
+    def as_tuple(self):
+        return (self.mode1, self.after1, self.mode3, self.after3)
+
+
+SPINE_CLASS = (TC_SIDE_IN, 0, TC_SIDE_OUT, 1)
+
+
 class tc_graph(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("t_range", _P),
                 ("out_off", _P), ("out_src", _P), ("out_dst", _P),
@@ -76,12 +94,12 @@ class tc_graph(ctypes.Structure):
 class tc_weights(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_int64), ("m", ctypes.c_int64), ("lo_in", _P), ("a", _P),
                 ("lo_out", _P), ("b", _P), ("S", _P), ("status", _P), ("scratch", _P),
-                ("h", _P), ("prec", _P)]
+                ("h", _P), ("prec", _P), ("cls", tc_class)]
 
 
 class tc_result(ctypes.Structure):
     _fields_ = [("cnt", _P), ("hits", _P), ("estimate", _P), ("status", _P), ("e1", _P),
-                ("e2", _P), ("e3", _P), ("X", _P), ("P", _P), ("m2", _P)]
+                ("e2", _P), ("e3", _P), ("X", _P), ("P", _P), ("m2", _P), ("xmax", _P)]
 
 
 class tc_tuning(ctypes.Structure):
@@ -118,6 +136,14 @@ def lib():
         L.tc_weights_workspace_bytes.argtypes = [I64, ctypes.POINTER(SZ)]
         L.tc_path_weights.argtypes = [ctypes.POINTER(tc_graph), I64, _P, SZ, _P,
                                       ctypes.POINTER(tc_weights)]
+        L.tc_path_weights_class.argtypes = [ctypes.POINTER(tc_graph), I64,
+                                            ctypes.POINTER(tc_class), _P, SZ, _P,
+                                            ctypes.POINTER(tc_weights)]
+        L.tc_motif_anchor.argtypes = [ctypes.POINTER(tc_motif), ctypes.POINTER(tc_class),
+                                      ctypes.POINTER(I32), ctypes.POINTER(I32)]
+        L.tc_exhaustive_count.argtypes = [ctypes.POINTER(tc_graph), ctypes.POINTER(tc_weights),
+                                          ctypes.POINTER(tc_motif), I32, U64, U64, _P, SZ,
+                                          ctypes.POINTER(tc_result), _P]
         L.tc_sample_workspace_bytes.argtypes = [U64, I32, ctypes.POINTER(SZ)]
         L.tc_sample_estimate.argtypes = [ctypes.POINTER(tc_graph), ctypes.POINTER(tc_weights),
                                          ctypes.POINTER(tc_motif), I32, U64, U64, U32, U64,
@@ -181,9 +207,11 @@ def _on_stream(stream, *tensors):
                 t.record_stream(stream)
 
 
-def make_motif(edges, nv: int = 4) -> tc_motif:
+def make_motif(edges, nv: int | None = None) -> tc_motif:
+    """Motif descriptor of an edge list in pi order; nv defaults to the
+    number of vertices the edges use (3 or 4)."""
     m = tc_motif()
-    m.nv = nv
+    m.nv = nv if nv is not None else 1 + max(max(a, b) for a, b in edges)
     m.ne = len(edges)
     for i, (a, b) in enumerate(edges):
         m.src[i] = a
@@ -287,6 +315,7 @@ class Result:
     X: torch.Tensor | None = None  # int64 [n_motifs, k] (u64 bit patterns)
     P: torch.Tensor | None = None  # int32 [k] centre scan positions (u32 bit patterns)
     m2: torch.Tensor | None = None  # float64 [n_motifs] sum of (X / h)^2
+    xmax: torch.Tensor | None = None  # int64 [n_motifs] largest X (u64 bit patterns)
 
     def counts(self):
         c = self.cnt.cpu().tolist()
@@ -368,7 +397,9 @@ def tc_build_graph(n: int, src: torch.Tensor, dst: torch.Tensor, t: torch.Tensor
 
 
 def tc_path_weights(graph: Graph, delta: int, stream=None,
-                    workspace: torch.Tensor | None = None) -> Weights:
+                    workspace: torch.Tensor | None = None, cls=None) -> Weights:
+    """Preprocess(delta) for an anchor class (a tuple (mode1, after1, mode3,
+    after3) or a tc_class; default: the <-,+,<,>> class)."""
     nbytes = weights_workspace_bytes(graph.m)
     if workspace is not None:
         assert workspace.numel() >= nbytes
@@ -377,9 +408,27 @@ def tc_path_weights(graph: Graph, delta: int, stream=None,
         ws = torch.empty(nbytes, dtype=torch.uint8, device=graph.ws.device)
     w = tc_weights()
     _on_stream(stream, ws)
-    _check(lib().tc_path_weights(ctypes.byref(graph.c), int(delta), _ptr(ws), nbytes,
-                                 _stream(stream), ctypes.byref(w)), "tc_path_weights")
+    if cls is None:
+        _check(lib().tc_path_weights(ctypes.byref(graph.c), int(delta), _ptr(ws), nbytes,
+                                     _stream(stream), ctypes.byref(w)), "tc_path_weights")
+    else:
+        c = cls if isinstance(cls, tc_class) else tc_class(*cls)
+        _check(lib().tc_path_weights_class(ctypes.byref(graph.c), int(delta), ctypes.byref(c),
+                                           _ptr(ws), nbytes, _stream(stream), ctypes.byref(w)),
+               "tc_path_weights_class")
     return Weights(w, ws, graph)
+
+
+def tc_motif_anchor(edges, nv: int | None = None):
+    """(class tuple, number of anchor edges, their rank order) of a motif's
+    anchor; raises TCError(TC_E_UNSUPPORTED) if it has none."""
+    m = make_motif(edges, nv)
+    c = tc_class()
+    na = ctypes.c_int32(0)
+    order = (ctypes.c_int32 * 3)()
+    _check(lib().tc_motif_anchor(ctypes.byref(m), ctypes.byref(c), ctypes.byref(na), order),
+           "tc_motif_anchor")
+    return c.as_tuple(), na.value, list(order)[:na.value]
 
 
 def new_result(n_motifs: int, k: int, device, per_sample: bool = False,
@@ -399,6 +448,7 @@ def new_result(n_motifs: int, k: int, device, per_sample: bool = False,
         out.P = torch.empty(k, dtype=torch.int32, device=device)
     if moments:
         out.m2 = torch.zeros(nm, dtype=torch.float64, device=device)
+    out.xmax = torch.zeros(nm, dtype=torch.int64, device=device)
     return out
 
 
@@ -406,12 +456,15 @@ def _c_result(out: Result) -> tc_result:
     return tc_result(_ptr(out.cnt).value, _ptr(out.hits).value, _ptr(out.estimate).value,
                      _ptr(out.status).value, _ptr(out.e1).value, _ptr(out.e2).value,
                      _ptr(out.e3).value, _ptr(out.X).value, _ptr(out.P).value,
-                     _ptr(out.m2).value)
+                     _ptr(out.m2).value, _ptr(out.xmax).value)
 
 
 def _motif_array(motifs):
+    """Motifs as edge lists (vertex count inferred) or (edges, nv) pairs."""
     nm = len(motifs)
-    return nm, (tc_motif * nm)(*[make_motif(m) for m in motifs])
+    ms = [make_motif(m[0], m[1]) if isinstance(m, tuple) and len(m) == 2 and
+          isinstance(m[1], int) else make_motif(m) for m in motifs]
+    return nm, (tc_motif * nm)(*ms)
 
 
 def tc_sample_estimate(graph: Graph, weights: Weights, motifs, k: int, seed: int,
@@ -432,6 +485,29 @@ def tc_sample_estimate(graph: Graph, weights: Weights, motifs, k: int, seed: int
                                     int(k), int(seed), int(stream_id), int(i0), _ptr(ws),
                                     ws.numel(), ctypes.byref(r), _stream(stream)),
            "tc_sample_estimate")
+    return out
+
+
+def tc_exhaustive_count(graph: Graph, weights: Weights, motifs, r0: int = 0,
+                        count: int | None = None, per_sample: bool = False, stream=None,
+                        out: Result | None = None,
+                        workspace: torch.Tensor | None = None) -> Result:
+    """Exhaustive mode: CheckMotif over the anchors of CDF ranks r0 .. r0 +
+    count - 1 (all W of them by default: W is read from the device); cnt is
+    then the exact count, hits / m2 / xmax give the B statistics."""
+    nm, arr = _motif_array(motifs)
+    if count is None:
+        count = max(1, weights.total() - r0)
+    dev = graph.ws.device
+    if out is None:
+        out = new_result(nm, count, dev, per_sample, moments=True)
+        _on_stream(stream, out.cnt, out.hits, out.estimate, out.status, out.e1, out.e2, out.e3,
+                   out.X, out.P, out.m2, out.xmax)
+    r = _c_result(out)
+    ws = _sample_ws(count, nm, dev, 1, stream) if workspace is None else workspace
+    _check(lib().tc_exhaustive_count(ctypes.byref(graph.c), ctypes.byref(weights.c), arr, nm,
+                                     int(r0), int(count), _ptr(ws), ws.numel(), ctypes.byref(r),
+                                     _stream(stream)), "tc_exhaustive_count")
     return out
 
 

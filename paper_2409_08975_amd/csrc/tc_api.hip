@@ -6,35 +6,133 @@
 
 namespace tc {
 
+const tc_class kSpineClass = {TC_SIDE_IN, 0, TC_SIDE_OUT, 1};
+
+bool same_class(const tc_class& a, const tc_class& b) {
+  if (a.mode1 != b.mode1 || a.mode3 != b.mode3) return false;
+  if (a.mode1 != TC_SIDE_NONE && a.after1 != b.after1) return false;
+  if (a.mode3 != TC_SIDE_NONE && a.after3 != b.after3) return false;
+  return true;
+}
+
+// The anchor rule of tc.h: candidates hold rank 0 (edge index 0); the best
+// has the smallest sorted ranks, then the smallest centre rank, then (paths)
+// the smallest rank of the edge at u.
+bool motif_anchor(const tc_motif& M, MotifAnchor* A) {
+  const int ne = M.ne;
+  auto meets = [&](int e, int vtx) { return M.src[e] == vtx || M.dst[e] == vtx; };
+  auto far_end = [&](int e, int vtx) { return M.src[e] == vtx ? (int)M.dst[e] : (int)M.src[e]; };
+  uint32_t best = 0xFFFFFFFFu;
+  int e1b = -1, cb = -1, e3b = -1;
+  for (int c = 0; c < ne; ++c) {
+    const int U = M.src[c], V = M.dst[c];
+    if (M.nv == 4) {
+      for (int e1 = 0; e1 < ne; ++e1) {
+        if (e1 == c || !meets(e1, U) || meets(e1, V)) continue;
+        for (int e3 = 0; e3 < ne; ++e3) {
+          if (e3 == c || e3 == e1 || !meets(e3, V) || meets(e3, U)) continue;
+          if (far_end(e3, V) == far_end(e1, U)) continue;
+          if (c != 0 && e1 != 0 && e3 != 0) continue;
+          int r0 = e1, r1 = c, r2 = e3, tmp;
+          if (r0 > r1) { tmp = r0; r0 = r1; r1 = tmp; }
+          if (r1 > r2) { tmp = r1; r1 = r2; r2 = tmp; }
+          if (r0 > r1) { tmp = r0; r0 = r1; r1 = tmp; }
+          const uint32_t key = ((((uint32_t)r0 * 16 + r1) * 16 + r2) * 16 + c) * 16 + e1;
+          if (key < best) { best = key; e1b = e1; cb = c; e3b = e3; }
+        }
+      }
+    } else if (M.nv == 3) {
+      for (int e = 0; e < ne; ++e) {
+        if (e == c || meets(e, U) == meets(e, V)) continue;
+        if (c != 0 && e != 0) continue;
+        const uint32_t lo = c < e ? c : e, hi = c < e ? e : c;
+        const uint32_t key = (lo * 16 + hi) * 16 + c;
+        if (key < best) {
+          best = key;
+          cb = c;
+          e1b = meets(e, U) ? e : -1;
+          e3b = meets(e, U) ? -1 : e;
+        }
+      }
+    }
+  }
+  if (cb < 0) return false;
+  const int U = M.src[cb], V = M.dst[cb];
+  for (int i = 0; i < 16; ++i) A->slot[i] = -1;
+  A->slot[U] = 1;
+  A->slot[V] = 2;
+  A->aedge[0] = e1b;
+  A->aedge[1] = cb;
+  A->aedge[2] = e3b;
+  A->n_anchor = 1;
+  A->cls = tc_class{TC_SIDE_NONE, 0, TC_SIDE_NONE, 0};
+  if (e1b >= 0) {
+    ++A->n_anchor;
+    A->cls.mode1 = M.dst[e1b] == U ? TC_SIDE_IN : TC_SIDE_OUT;
+    A->cls.after1 = e1b > cb ? 1 : 0;
+    A->slot[far_end(e1b, U)] = 0;
+  }
+  if (e3b >= 0) {
+    ++A->n_anchor;
+    A->cls.mode3 = M.dst[e3b] == V ? TC_SIDE_IN : TC_SIDE_OUT;
+    A->cls.after3 = e3b > cb ? 1 : 0;
+    A->slot[far_end(e3b, V)] = 3;
+  }
+  for (int vtx = 0; vtx < M.nv; ++vtx)
+    if (A->slot[vtx] < 0) return false;
+  int k = 0;
+  for (int r = 0; r < ne; ++r)
+    for (int i = 0; i < 3; ++i)
+      if (A->aedge[i] == r) A->order[k++] = i;
+  for (; k < 3; ++k) A->order[k] = -1;
+  return true;
+}
+
 tc_status compile_motifs(const tc_motif* motifs, int32_t n_motifs, MotifPlan* plan) {
   if (!motifs || n_motifs < 1 || n_motifs > kMaxMotifs) return TC_E_ARG;
   *plan = MotifPlan{};
   plan->n_motifs = n_motifs;
   for (int j = 0; j < n_motifs; ++j) {
     const tc_motif& M = motifs[j];
-    if (M.nv != 4 || M.ne < 3 || M.ne > 16) return TC_E_UNSUPPORTED;
+    if (M.nv < 3 || M.nv > 4 || M.ne < 2 || M.ne > 16) return TC_E_UNSUPPORTED;
     for (int e = 0; e < M.ne; ++e)
-      if (M.src[e] >= 4 || M.dst[e] >= 4 || M.src[e] == M.dst[e]) return TC_E_UNSUPPORTED;
-    // anchor: ranks 0, 1, 2 form the directed 3-path 0 -> 1 -> 2 -> 3
-    if (!(M.src[0] == 0 && M.dst[0] == 1 && M.src[1] == 1 && M.dst[1] == 2 && M.src[2] == 2 &&
-          M.dst[2] == 3))
-      return TC_E_UNSUPPORTED;
-    // phi maps motif vertex 0..3 to (x, u, v, y), which are slots 0..3; each
-    // later edge is a list over the pair (phi(src), phi(dst))
-    plan->n_lists[j] = M.ne - 3;
-    if (plan->n_lists[j] > plan->max_lists) plan->max_lists = plan->n_lists[j];
-    for (int e = 3; e < M.ne; ++e) {
+      if (M.src[e] >= M.nv || M.dst[e] >= M.nv || M.src[e] == M.dst[e]) return TC_E_UNSUPPORTED;
+    MotifAnchor A;
+    if (!motif_anchor(M, &A)) return TC_E_UNSUPPORTED;
+    // every motif of one call samples the same anchors
+    if (j == 0) {
+      plan->cls = A.cls;
+      plan->n_anchor = A.n_anchor;
+      for (int i = 0; i < 3; ++i) plan->order[i] = A.order[i];
+    } else {
+      if (!same_class(A.cls, plan->cls) || A.n_anchor != plan->n_anchor) return TC_E_ARG;
+      for (int i = 0; i < A.n_anchor; ++i)
+        if (A.order[i] != plan->order[i]) return TC_E_ARG;
+    }
+    // each later edge is a list over a window key (slot pair, segment)
+    int nl = 0;
+    for (int r = 0; r < M.ne; ++r) {
+      if (r == A.aedge[0] || r == A.aedge[1] || r == A.aedge[2]) continue;
+      int below = 0;
+      for (int i = 0; i < 3; ++i)
+        if (A.aedge[i] >= 0 && A.aedge[i] < r) ++below;
+      const uint8_t sa = (uint8_t)A.slot[M.src[r]], sb = (uint8_t)A.slot[M.dst[r]];
+      const uint8_t seg = (uint8_t)(below - 1);
       int q = 0;
       while (q < plan->n_pairs &&
-             !(plan->pair_a[q] == M.src[e] && plan->pair_b[q] == M.dst[e]))
+             !(plan->pair_a[q] == sa && plan->pair_b[q] == sb && plan->pair_seg[q] == seg))
         ++q;
       if (q == plan->n_pairs) {
-        plan->pair_a[q] = M.src[e];
-        plan->pair_b[q] = M.dst[e];
+        if (plan->n_pairs == kMaxPairs) return TC_E_UNSUPPORTED;
+        plan->pair_a[q] = sa;
+        plan->pair_b[q] = sb;
+        plan->pair_seg[q] = seg;
         plan->n_pairs++;
       }
-      plan->list_pair[j][e - 3] = (uint8_t)q;
+      plan->list_pair[j][nl++] = (uint8_t)q;
     }
+    plan->n_lists[j] = nl;
+    if (nl > plan->max_lists) plan->max_lists = nl;
   }
   uint32_t gate_mask = 0;
   for (int j = 0; j < n_motifs; ++j)
@@ -82,7 +180,32 @@ tc_status tc_path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_
                           void* stream, tc_weights* w) {
   if (!g || !w || !ws) return TC_E_ARG;
   if (delta < 0 || delta > ((int64_t)1 << 62)) return TC_E_ARG;
-  return tc::path_weights(g, delta, ws, ws_bytes, (hipStream_t)stream, w);
+  return tc::path_weights(g, delta, tc::kSpineClass, ws, ws_bytes, (hipStream_t)stream, w);
+}
+
+tc_status tc_path_weights_class(const tc_graph* g, int64_t delta, const tc_class* cls, void* ws,
+                                size_t ws_bytes, void* stream, tc_weights* w) {
+  if (!g || !w || !ws || !cls) return TC_E_ARG;
+  if (delta < 0 || delta > ((int64_t)1 << 62)) return TC_E_ARG;
+  if (cls->mode1 > TC_SIDE_OUT || cls->mode3 > TC_SIDE_OUT || cls->after1 > 1 ||
+      cls->after3 > 1 || (cls->mode1 == TC_SIDE_NONE && cls->mode3 == TC_SIDE_NONE))
+    return TC_E_ARG;
+  return tc::path_weights(g, delta, *cls, ws, ws_bytes, (hipStream_t)stream, w);
+}
+
+tc_status tc_motif_anchor(const tc_motif* motif, tc_class* cls, int32_t* n_anchor,
+                          int32_t* order) {
+  if (!motif || !cls || !n_anchor || !order) return TC_E_ARG;
+  const tc_motif& M = *motif;
+  if (M.nv < 3 || M.nv > 4 || M.ne < 2 || M.ne > 16) return TC_E_UNSUPPORTED;
+  for (int e = 0; e < M.ne; ++e)
+    if (M.src[e] >= M.nv || M.dst[e] >= M.nv || M.src[e] == M.dst[e]) return TC_E_UNSUPPORTED;
+  tc::MotifAnchor A;
+  if (!tc::motif_anchor(M, &A)) return TC_E_UNSUPPORTED;
+  *cls = A.cls;
+  *n_anchor = A.n_anchor;
+  for (int i = 0; i < 3; ++i) order[i] = A.order[i];
+  return TC_OK;
 }
 
 tc_status tc_sample_workspace_bytes(uint64_t k, int32_t n_motifs, size_t* bytes) {
@@ -117,6 +240,8 @@ tc_status tc_batch_estimate(const tc_graph* g, const tc_weights* const* w, int32
   tc::MotifPlan plan;
   tc_status s = tc::compile_motifs(motifs, n_motifs, &plan);
   if (s != TC_OK) return s;
+  for (int d = 0; d < n_deltas; ++d)
+    if (!tc::same_class(plan.cls, w[d]->cls)) return TC_E_ARG;
   if (!ws) return TC_E_ARG;
   const tc::SampleTuning t = tuning ? *tuning : tc::default_tuning();
   return tc::sample_batch(g, w, n_deltas, plan, k, seed, stream_id, i0, out, t, ws, ws_bytes,
@@ -132,11 +257,28 @@ tc_status tc_sample_estimate(const tc_graph* g, const tc_weights* w, const tc_mo
   tc::MotifPlan plan;
   tc_status s = tc::compile_motifs(motifs, n_motifs, &plan);
   if (s != TC_OK) return s;
+  if (!tc::same_class(plan.cls, w->cls)) return TC_E_ARG;
   if (!ws) return TC_E_ARG;
   const tc_weights* wl[1] = {w};
   tc_result* ol[1] = {out};
   return tc::sample_batch(g, wl, 1, plan, k, seed, stream_id, i0, ol, tc::default_tuning(), ws,
                           ws_bytes, (hipStream_t)stream);
+}
+
+tc_status tc_exhaustive_count(const tc_graph* g, const tc_weights* w, const tc_motif* motifs,
+                              int32_t n_motifs, uint64_t r0, uint64_t count, void* ws,
+                              size_t ws_bytes, tc_result* out, void* stream) {
+  if (!g || !w || check_result(out) != TC_OK) return TC_E_ARG;
+  if (count < 1 || w->m != g->m || w->h) return TC_E_ARG;
+  tc::MotifPlan plan;
+  tc_status s = tc::compile_motifs(motifs, n_motifs, &plan);
+  if (s != TC_OK) return s;
+  if (!tc::same_class(plan.cls, w->cls)) return TC_E_ARG;
+  if (!ws) return TC_E_ARG;
+  const tc_weights* wl[1] = {w};
+  tc_result* ol[1] = {out};
+  return tc::sample_batch(g, wl, 1, plan, count, 0, 0, r0, ol, tc::default_tuning(), ws, ws_bytes,
+                          (hipStream_t)stream, true);
 }
 
 tc_status tc_autotune(const tc_graph* g, const tc_weights* const* w, int32_t n_deltas,
@@ -218,6 +360,7 @@ tc_status tc_features_workspace_bytes(int64_t m, size_t* bytes) {
 tc_status tc_edge_features(const tc_graph* g, const tc_weights* w, uint16_t* feat, void* ws,
                            size_t ws_bytes, void* stream) {
   if (!g || !w || !feat || !ws || w->m != g->m || !aligned16(feat)) return TC_E_ARG;
+  if (!tc::same_class(w->cls, tc::kSpineClass)) return TC_E_UNSUPPORTED;
   return tc::edge_features(g, w, feat, ws, ws_bytes, (hipStream_t)stream);
 }
 

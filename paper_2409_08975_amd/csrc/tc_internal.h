@@ -25,32 +25,51 @@ struct STree {
 STree stree_layout(int64_t m);
 
 size_t weights_workspace_bytes(int64_t m);
-tc_status path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_bytes,
-                       hipStream_t st, tc_weights* w);
+tc_status path_weights(const tc_graph* g, int64_t delta, const tc_class& cls, void* ws,
+                       size_t ws_bytes, hipStream_t st, tc_weights* w);
 
-// Compiled form of a batch of motifs that share the anchor 0->1->2->3:
-// for motif j, ranks 3..ne-1 become lists over vertex slots of
-// phi = (x, u, v, y).
-// The distinct pairs used by any list of the batch are looked up once per
-// sample (at most 12 ordered pairs of 4 vertices).
+// Compiled form of a batch of motifs that share the anchor's class, its
+// number of edges and their rank order.  phi = (x, u, v, y) are the vertex
+// slots 0..3 (u -> v the centre edge, x the other end of the side-1 edge, y
+// of the side-3 edge).  Every non-anchor motif edge becomes a list over a
+// window key: a pair of slots and a segment s, the times after the anchor
+// edge of rank position s and before the next one (or up to the first
+// anchor time + delta).  The distinct window keys of the batch are searched
+// once per sample (at most 16).
 constexpr int kMaxMotifs = 16;
 constexpr int kMaxLists = 13;
-constexpr int kMaxPairs = 12;
+constexpr int kMaxPairs = 16;
 // A motif's first list gates it: when that window is empty its count is 0
-// and its other lists are never needed.  The gate pairs are therefore
+// and its other lists are never needed.  The gate keys are therefore
 // searched for every accepted path, the others only for live motifs.
 struct MotifPlan {
   int32_t n_motifs;
   int32_t n_pairs;
   int32_t max_lists;
-  uint8_t pair_a[kMaxPairs], pair_b[kMaxPairs];  // vertex slots of each pair
+  tc_class cls;                                 // the anchor class of every motif
+  int32_t n_anchor;                             // 3 (path) or 2 (wedge)
+  int32_t order[3];                             // anchor edges by rank: 0 = e1, 1 = centre, 2 = e3
+  uint8_t pair_a[kMaxPairs], pair_b[kMaxPairs];  // vertex slots of each window key
+  uint8_t pair_seg[kMaxPairs];                  // its segment
   int32_t n_lists[kMaxMotifs];
-  uint8_t list_pair[kMaxMotifs][kMaxLists];     // pair index of each list
+  uint8_t list_pair[kMaxMotifs][kMaxLists];     // window key of each list
   int32_t n_gates;
-  uint8_t gate_pair[kMaxPairs];                 // distinct first-list pairs
-  uint8_t gate_index[kMaxPairs];                // pair -> its gate index, or 0xFF
-  uint16_t rest_mask[kMaxMotifs];               // other pairs of each motif (not gates)
+  uint8_t gate_pair[kMaxPairs];                 // distinct first-list keys
+  uint8_t gate_index[kMaxPairs];                // key -> its gate index, or 0xFF
+  uint16_t rest_mask[kMaxMotifs];               // other keys of each motif (not gates)
 };
+
+// The anchor of one motif (the rule stated in tc.h).
+struct MotifAnchor {
+  tc_class cls;
+  int32_t n_anchor;
+  int32_t order[3];
+  int32_t aedge[3];  // motif edge of e1, centre, e3 (-1 = none)
+  int32_t slot[16];  // motif vertex -> slot of phi
+};
+bool motif_anchor(const tc_motif& M, MotifAnchor* A);
+bool same_class(const tc_class& a, const tc_class& b);
+extern const tc_class kSpineClass;
 
 tc_status compile_motifs(const tc_motif* motifs, int32_t n_motifs, MotifPlan* plan);
 
@@ -60,10 +79,12 @@ typedef tc_tuning SampleTuning;
 SampleTuning default_tuning();
 // Workspace of sample_batch; with t == NULL, room for any tuning.
 size_t sample_workspace_bytes(uint64_t k, int nd, int32_t n_motifs, const SampleTuning* t);
+// With `exhaustive` the samples are the anchors of CDF ranks i0 .. i0 + k - 1
+// (no random numbers) and the estimate is the count itself.
 tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
                        const MotifPlan& plan, uint64_t k, uint64_t seed, uint32_t stream_id,
                        uint64_t i0, tc_result* const* out, const SampleTuning& tune, void* ws,
-                       size_t ws_bytes, hipStream_t st);
+                       size_t ws_bytes, hipStream_t st, bool exhaustive = false);
 
 // Proposal weights (scan of a * b * h) and the learned proposal.
 size_t proposal_workspace_bytes(int64_t m);

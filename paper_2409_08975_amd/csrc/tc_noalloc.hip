@@ -61,6 +61,7 @@ extern "C" tc_status tc_sample_estimate_noalloc(const tc_graph* g, const tc_weig
   tc::MotifPlan plan;
   const tc_status s = tc::compile_motifs(motifs, n_motifs, &plan);
   if (s != TC_OK) return s;
+  if (!tc::same_class(plan.cls, w->cls)) return TC_E_ARG;
   const tc::SampleTuning tune = tc::noalloc_tuning();
   if (tc::sample_workspace_bytes(k, 1, n_motifs, &tune) > tc::kNoAllocScratchBytes)
     return TC_E_WORKSPACE;

@@ -1,25 +1,30 @@
 // Sample + CheckMotif + ListCount + reduction (Algorithms Sample,
 // CheckMotif, ListCount and the last line of Estimate), for one or several
 // values of delta at once (each delta with its own weights, all motifs
-// sharing the anchor, sample i of every delta drawn from the same counter).
+// sharing the anchor's class and rank order, sample i of every delta drawn
+// from the same counter).
 //
 // The samples are processed in chunks of `chunk` samples per delta.  Per chunk:
 //   k_paths          persistent: each block takes (delta, 256-sample tile)
 //                    work units.  Per sample: a Philox4x32-10 block keyed by
 //                    (seed, stream) at counter (i, attempt); r uniform in
-//                    [0, W) by Lemire reduction of a 64-bit draw; p with
+//                    [0, W) by Lemire reduction of a 64-bit draw (or, in the
+//                    exhaustive mode, r = the sample's CDF rank); p with
 //                    S[p] <= r < S[p+1] through the 16-ary search tree over S;
-//                    j1, j3 uniform inside the two windows; gathers give
-//                    e1 = (x, u, t1), e2 = (u, v, t2), e3 = (v, y, t3).
-//                    CheckMotif rejects unless x, u, v, y are distinct,
-//                    t1 < t2 < t3 and t3 - t1 <= delta.  The accepted paths of
-//                    the tile are compacted in LDS and the window
-//                    (t3, t1 + delta] of every distinct pair used by the
-//                    motifs is found once per path (hash lookup of the pair's
-//                    run, two binary searches on time), spread over the block.
-//                    A motif with no list counts 1, with one list its length,
-//                    with an empty list 0; every other (sample, motif) is
-//                    queued.
+//                    j1, j3 uniform inside the two side windows; gathers give
+//                    the centre e2 = (u, v, t2) and the side edges e1 at u and
+//                    e3 at v (either may be absent: a wedge), phi = (x, u, v, y).
+//                    CheckMotif rejects unless the anchor's vertices are
+//                    distinct, its times strictly increase in rank order and
+//                    its span is at most delta.  The accepted anchors of the
+//                    tile are compacted in LDS and the window of every
+//                    distinct list key (a vertex pair of phi and a segment
+//                    between anchor times; for the spine motifs the pair's
+//                    times in (t3, t1 + delta]) is found once per anchor
+//                    (hash lookup of the pair's run, two binary searches on
+//                    time), spread over the block.  A motif with no list
+//                    counts 1, with one list its length, with an empty list
+//                    0; every other (sample, motif) is queued.
 //   k_listcount_reg  one wavefront per queued item, lists up to 256 entries.
 //                    ListCount level by level:
 //                      c_1[i] = #{j : L_0[j] < L_1[i]},
@@ -68,6 +73,7 @@ struct DeltaArgs {
   const uint32_t* h;  // proposal factors (importance sampling) or null
   uint32_t* P;
   double* m2;
+  uint64_t* xmax;
 };
 
 struct SampleArgs {
@@ -93,8 +99,9 @@ struct SampleArgs {
   // sampling
   uint64_t k;
   uint64_t seed;
-  uint64_t i0;
+  uint64_t i0;       // first counter, or (exhaustive) first CDF rank
   uint32_t stream_id;
+  int32_t exhaustive;  // anchors of CDF ranks i0 .. i0 + k - 1 instead of random draws
   uint64_t c0;     // first sample (0-based, relative to i0) of this chunk
   uint32_t clen;   // samples per delta in this chunk
   uint32_t chunk;  // stride of the per-sample window arrays
@@ -177,7 +184,7 @@ __device__ __forceinline__ uint32_t tree_search(const SampleArgs& A, const Delta
 // ---- per-block sums of (delta, motif) and their flush -------------------------
 // Dynamic LDS: slot (w, d, j) at w * nd * nm + d * nm + j for NW wavefronts.
 struct BlockSums {
-  uint64_t lo, hi, hits;
+  uint64_t lo, hi, hits, xmax;
   double m2;
   uint32_t ovf;
 };
@@ -195,7 +202,7 @@ __device__ __forceinline__ BlockSums* sums_slot(const SampleArgs& A, int w, int 
 template <int NW>
 __device__ __forceinline__ void sums_clear(const SampleArgs& A) {
   for (int i = threadIdx.x; i < NW * A.nd * A.plan.n_motifs; i += blockDim.x)
-    s_dyn_sums[i] = BlockSums{0, 0, 0, 0.0, 0u};
+    s_dyn_sums[i] = BlockSums{0, 0, 0, 0, 0.0, 0u};
 }
 
 // 128-bit add that reports a carry out (a total >= 2^128)
@@ -218,13 +225,15 @@ __device__ __forceinline__ double wave_sumf64(double v) {
   return v;
 }
 
-__device__ __forceinline__ void sums_add(BlockSums* p, U128 v, uint64_t h, double sq, bool ovf) {
+__device__ __forceinline__ void sums_add(BlockSums* p, U128 v, uint64_t h, double sq, bool ovf,
+                                         uint64_t xm) {
   bool o = ovf;
   const U128 r = add128c(U128{p->lo, p->hi}, v, &o);
   p->lo = r.lo;
   p->hi = r.hi;
   p->hits += h;
   p->m2 += sq;
+  p->xmax = xm > p->xmax ? xm : p->xmax;
   if (o) p->ovf = 1u;
 }
 
@@ -258,7 +267,7 @@ __device__ __forceinline__ double square_term(uint64_t X, uint32_t hp) {
 // a fixed order.
 constexpr int kSpread = 64;
 struct SpreadSums {
-  uint64_t lo, hi, hits;
+  uint64_t lo, hi, hits, xmax;
   double m2;
 };
 
@@ -274,7 +283,7 @@ __device__ void sums_flush(const SampleArgs& A) {
   for (int i = threadIdx.x; i < A.nd * nm; i += blockDim.x) {
     const int d = i / nm, j = i - d * nm;
     U128 sum{0, 0};
-    uint64_t h = 0;
+    uint64_t h = 0, xm = 0;
     double sq = 0.0;
     bool ovf = false;
     for (int w = 0; w < NW; ++w) {
@@ -282,6 +291,7 @@ __device__ void sums_flush(const SampleArgs& A) {
       sum = add128c(sum, U128{p->lo, p->hi}, &ovf);
       h += p->hits;
       sq += p->m2;
+      xm = p->xmax > xm ? p->xmax : xm;
       if (p->ovf) ovf = true;
     }
     SpreadSums* t = spread_slot(A, (int)(blockIdx.x % kSpread), d, j);
@@ -296,6 +306,7 @@ __device__ void sums_flush(const SampleArgs& A) {
       }
     }
     if (h) atomicAdd((unsigned long long*)&t->hits, (unsigned long long)h);
+    if (xm) atomicMax((unsigned long long*)&t->xmax, (unsigned long long)xm);
     if (A.D[d].m2 && sq != 0.0) atomicAdd(&t->m2, sq);
     if (ovf) atomicOr(A.D[d].status, TC_F_OVERFLOW | TC_F_MOTIF(j));
   }
@@ -313,11 +324,24 @@ constexpr int kTreeCache = 384;
 __host__ __device__ inline size_t tree_cache_at(int n_gates) {
   return ((size_t)n_gates * kSBlock * 4 + 15) & ~(size_t)15;
 }
+// An accepted anchor: phi = (x, u, v, y) (x or y is -1 for a wedge's absent
+// side) and its times by increasing rank T[0] < T[1] (< T[2]).
 struct PathRec {
   int32_t x, u, v, y;
-  int64_t t1, t3;
+  int64_t T[3];
   uint32_t li;
 };
+
+// Window of list key q of an accepted anchor: the pair's times after the
+// anchor time of its segment and before the next anchor time, or up to the
+// first anchor time + delta after the last one (integer times, so "before
+// T" is "at most T - 1").
+__device__ __forceinline__ void key_window(const SampleArgs& A, const PathRec& P, int q,
+                                           int64_t delta, int64_t* lo, int64_t* hi) {
+  const int sg = A.plan.pair_seg[q];
+  *lo = P.T[sg];
+  *hi = sg + 1 < A.plan.n_anchor ? P.T[sg + 1] - 1 : P.T[0] + delta;
+}
 
 // Seven wavefronts per SIMD (at most 72 VGPRs): the kernel waits on L2 and
 // HBM round trips, and this occupancy measured fastest (6: -4%, 8: -5%).
@@ -361,11 +385,14 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
     const bool active = li < A.clen && *D.wstatus == 0;
     const uint64_t ii = A.c0 + li;  // output index
     bool valid = false;
-    int32_t x = 0, u = 0, v = 0, y = 0;
-    int64_t t1 = 0, t3 = 0;
+    int32_t x = -1, u = 0, v = 0, y = -1;
+    int64_t Tk[3] = {0, 0, 0};
     uint32_t hp = 1;
+    // in exhaustive mode the sample is the anchor of CDF rank i0 + ii
+    const uint64_t rank = A.i0 + ii;
+    const bool none = W == 0 || (A.exhaustive && rank >= W);
     if (active) {
-      if (W == 0) {
+      if (none) {
         if (D.P) D.P[ii] = 0xFFFFFFFFu;
         if (D.e1) {
           D.e1[ii] = -1;
@@ -375,53 +402,84 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
         if (D.X)
           for (int j = 0; j < nm; ++j) D.X[(uint64_t)j * A.k + ii] = 0;
       } else {
-        const uint64_t i = A.i0 + ii;  // counter of the random stream
-        const Words4 blk0 = philox_block(A.seed, A.stream_id, i, 0);
         uint64_t r;
-        bool ok = range64((uint64_t)blk0.x0 | ((uint64_t)blk0.x1 << 32), W, &r);
-        for (uint32_t att = 1; !ok && att < kMaxAttempts; ++att) {
-          const Words4 bk = philox_block(A.seed, A.stream_id, i, att);
-          ok = range64((uint64_t)bk.x0 | ((uint64_t)bk.x1 << 32), W, &r);
-        }
-        if (!ok) {
-          st_bits |= TC_F_RNG;
-          r = 0;
+        Words4 blk0{0, 0, 0, 0};
+        const uint64_t i = A.i0 + ii;  // counter of the random stream
+        if (A.exhaustive) {
+          r = rank;
+        } else {
+          blk0 = philox_block(A.seed, A.stream_id, i, 0);
+          bool ok = range64((uint64_t)blk0.x0 | ((uint64_t)blk0.x1 << 32), W, &r);
+          for (uint32_t att = 1; !ok && att < kMaxAttempts; ++att) {
+            const Words4 bk = philox_block(A.seed, A.stream_id, i, att);
+            ok = range64((uint64_t)bk.x0 | ((uint64_t)bk.x1 << 32), W, &r);
+          }
+          if (!ok) {
+            st_bits |= TC_F_RNG;
+            r = 0;
+          }
         }
         const uint32_t p = tree_search(A, D, s_tree, r);  // S[p] <= r < S[p+1]
         const uint4 pr0 = D.prec[2 * (uint64_t)p], pr1 = D.prec[2 * (uint64_t)p + 1];
         const uint32_t ap = pr0.y, bp = pr0.w;
         uint32_t j1, j3;
-        ok = range32(blk0.x2, ap, &j1);
-        for (uint32_t att = 1; !ok && att < kMaxAttempts; ++att)
-          ok = range32(philox_block(A.seed, A.stream_id, i, att).x2, ap, &j1);
-        if (!ok) {
-          st_bits |= TC_F_RNG;
-          j1 = 0;
-        }
-        ok = range32(blk0.x3, bp, &j3);
-        for (uint32_t att = 1; !ok && att < kMaxAttempts; ++att)
-          ok = range32(philox_block(A.seed, A.stream_id, i, att).x3, bp, &j3);
-        if (!ok) {
-          st_bits |= TC_F_RNG;
-          j3 = 0;
+        if (A.exhaustive) {
+          // rank r - S[p] = j1 * b + j3 (b >= 1: w_p = a * b > 0 here)
+          const uint64_t jj = r - D.S[p];
+          j1 = (uint32_t)(jj / bp);
+          j3 = (uint32_t)(jj - (uint64_t)j1 * bp);
+        } else {
+          bool ok = range32(blk0.x2, ap, &j1);
+          for (uint32_t att = 1; !ok && att < kMaxAttempts; ++att)
+            ok = range32(philox_block(A.seed, A.stream_id, i, att).x2, ap, &j1);
+          if (!ok) {
+            st_bits |= TC_F_RNG;
+            j1 = 0;
+          }
+          ok = range32(blk0.x3, bp, &j3);
+          for (uint32_t att = 1; !ok && att < kMaxAttempts; ++att)
+            ok = range32(philox_block(A.seed, A.stream_id, i, att).x3, bp, &j3);
+          if (!ok) {
+            st_bits |= TC_F_RNG;
+            j3 = 0;
+          }
         }
         u = (int32_t)pr1.x;
         v = (int32_t)pr1.y;
         const int64_t t2 = (int64_t)(((uint64_t)pr1.w << 32) | pr1.z);
-        const uint4 er1 = A.in_rec[pr0.x + j1];   // e1 = (x, u, t1)
-        const uint4 er3 = A.out_rec[pr0.z + j3];  // e3 = (v, y, t3)
-        x = (int32_t)er1.x;
-        t1 = (int64_t)(((uint64_t)er1.w << 32) | er1.z);
-        y = (int32_t)er3.x;
-        t3 = (int64_t)(((uint64_t)er3.w << 32) | er3.z);
+        // the side edges: a record {other end, eid, t} of the in- or out-CSR
+        const int m1 = A.plan.cls.mode1, m3 = A.plan.cls.mode3;
+        int64_t ts[3] = {0, t2, 0};
+        int32_t eid1 = -1, eid3 = -1;
+        if (m1 != TC_SIDE_NONE) {
+          const uint4 er1 = (m1 == TC_SIDE_IN ? A.in_rec : A.out_rec)[pr0.x + j1];
+          x = (int32_t)er1.x;
+          eid1 = (int32_t)er1.y;
+          ts[0] = (int64_t)(((uint64_t)er1.w << 32) | er1.z);
+        }
+        if (m3 != TC_SIDE_NONE) {
+          const uint4 er3 = (m3 == TC_SIDE_IN ? A.in_rec : A.out_rec)[pr0.z + j3];
+          y = (int32_t)er3.x;
+          eid3 = (int32_t)er3.y;
+          ts[2] = (int64_t)(((uint64_t)er3.w << 32) | er3.z);
+        }
         if (D.e1) {
-          D.e1[ii] = (int32_t)er1.y;
+          D.e1[ii] = eid1;
           D.e2[ii] = A.out_eid[p];
-          D.e3[ii] = (int32_t)er3.y;
+          D.e3[ii] = eid3;
         }
         if (D.P) D.P[ii] = p;
-        valid = x != u && x != v && x != y && u != v && u != y && v != y && t1 < t2 &&
-                t2 < t3 && (t3 - t1) <= D.delta;
+        // CheckMotif: distinct vertices, times strictly increasing in rank
+        // order, all within delta of the first
+        const bool has1 = m1 != TC_SIDE_NONE, has3 = m3 != TC_SIDE_NONE;
+        valid = u != v && (!has1 || (x != u && x != v)) && (!has3 || (y != u && y != v)) &&
+                (!(has1 && has3) || x != y);
+        const int na = A.plan.n_anchor;
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk)
+          Tk[kk] = kk < na ? ts[A.plan.order[kk]] : 0;
+        for (int kk = 1; kk < na; ++kk) valid = valid && Tk[kk - 1] < Tk[kk];
+        valid = valid && (Tk[na - 1] - Tk[0]) <= D.delta;
         if (D.h && valid) {
           hp = D.h[p];
           A.samp_h[(uint64_t)d * A.chunk + li] = hp;
@@ -436,7 +494,7 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
       if (lane == 0 && mask) base = atomicAdd(&s_nvalid, (uint32_t)__popcll(mask));
       base = __shfl(base, 0, kWave);
       my_sidx = base + (uint32_t)__popcll(mask & lt_mask);
-      if (valid) s_path[my_sidx] = PathRec{x, u, v, y, t1, t3, li};
+      if (valid) s_path[my_sidx] = PathRec{x, u, v, y, {Tk[0], Tk[1], Tk[2]}, li};
     }
     __syncthreads();
     // phase A: the gate pairs of every accepted path, one (path, pair)
@@ -447,10 +505,11 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
       const uint32_t gi = task / nvalid, sidx = task - gi * nvalid;
       const uint32_t q = A.plan.gate_pair[gi];
       const PathRec P = s_path[sidx];
+      int64_t tlo, thi;
+      key_window(A, P, (int)q, D.delta, &tlo, &thi);
       uint32_t lo, hi;
       pair_window(A, slot_vertex(A.plan.pair_a[q], P.x, P.u, P.v, P.y),
-                  slot_vertex(A.plan.pair_b[q], P.x, P.u, P.v, P.y), P.t3, P.t1 + D.delta,
-                  &lo, &hi);
+                  slot_vertex(A.plan.pair_b[q], P.x, P.u, P.v, P.y), tlo, thi, &lo, &hi);
       A.win_lo[win_index(A, d, q, P.li)] = lo;
       A.win_len[win_index(A, d, q, P.li)] = hi - lo;
       s_glen[gi * kSBlock + sidx] = hi - lo;
@@ -489,10 +548,11 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
         for (uint32_t skip = task - s_off[sidx]; skip > 0; --skip) mk &= mk - 1;
         const uint32_t q = (uint32_t)__ffs(mk) - 1;
         const PathRec P = s_path[sidx];
+        int64_t tlo, thi;
+        key_window(A, P, (int)q, D.delta, &tlo, &thi);
         uint32_t lo, hi;
         pair_window(A, slot_vertex(A.plan.pair_a[q], P.x, P.u, P.v, P.y),
-                    slot_vertex(A.plan.pair_b[q], P.x, P.u, P.v, P.y), P.t3, P.t1 + D.delta,
-                    &lo, &hi);
+                    slot_vertex(A.plan.pair_b[q], P.x, P.u, P.v, P.y), tlo, thi, &lo, &hi);
         A.win_lo[win_index(A, d, q, P.li)] = lo;
         A.win_len[win_index(A, d, q, P.li)] = hi - lo;
       }
@@ -532,7 +592,7 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
       }
       if (defer) dmask |= 1u << j;
       wdefer += (uint32_t)__popcll(__ballot(defer));
-      if (active && W != 0 && !defer && D.X) D.X[(uint64_t)j * A.k + ii] = X;
+      if (active && !none && !defer && D.X) D.X[(uint64_t)j * A.k + ii] = X;
       const uint64_t Xc = defer ? 0ull : X;
       // most wavefronts close no path of a motif: their sums are all zero
       const uint64_t nz = __ballot(Xc != 0);
@@ -540,8 +600,14 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
         bool ovf = false;
         const U128 sx = wave_sum128c(contribution(Xc, D.h != nullptr, hp), &ovf);
         const double sq = D.m2 ? wave_sumf64(square_term(Xc, hp)) : 0.0;
+        uint64_t xm = Xc;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          const uint64_t o = __shfl_xor(xm, off, kWave);
+          xm = o > xm ? o : xm;
+        }
         if (lane == 0)
-          sums_add(sums_slot(A, wave, d, j), sx, (uint64_t)__popcll(nz), sq, ovf);
+          sums_add(sums_slot(A, wave, d, j), sx, (uint64_t)__popcll(nz), sq, ovf, xm);
       }
     }
     // queue the deferred (sample, motif) items of the unit with one
@@ -658,7 +724,7 @@ __device__ __forceinline__ void item_done(const SampleArgs& A, int d, int j, uin
   if (D.X) D.X[(uint64_t)j * A.k + A.c0 + li] = X;
   const uint32_t hp = D.h ? A.samp_h[(uint64_t)d * A.chunk + li] : 1u;
   sums_add(sums_slot(A, 0, d, j), contribution(X, D.h != nullptr, hp), X != 0 ? 1ull : 0ull,
-           D.m2 ? square_term(X, hp) : 0.0, false);
+           D.m2 ? square_term(X, hp) : 0.0, false, X);
 }
 
 // Register-resident wavefront ListCount (64-thread blocks) for items whose
@@ -1199,6 +1265,7 @@ __global__ __launch_bounds__(kSBlock) void k_listcount_big(SampleArgs A) {
     // few items: this wavefront's slot, updated with LDS atomics
     BlockSums* slot = sums_slot(A, wave, d, j);
     atomicAdd((unsigned long long*)&slot->hits, X != 0 ? 1ull : 0ull);
+    if (X) atomicMax((unsigned long long*)&slot->xmax, (unsigned long long)X);
     if (D.m2 && X) atomicAdd(&slot->m2, square_term(X, hp));
     const uint64_t old = atomicAdd((unsigned long long*)&slot->lo, (unsigned long long)c.lo);
     const uint64_t add_hi = c.hi + ((old + c.lo < old) ? 1ull : 0ull);
@@ -1215,13 +1282,14 @@ __global__ __launch_bounds__(kSBlock) void k_listcount_big(SampleArgs A) {
 __global__ void k_zero_result(SampleArgs A) {
   const int nm = A.plan.n_motifs;
   for (int i = threadIdx.x; i < kSpread * A.nd * nm; i += blockDim.x)
-    A.spread[i] = SpreadSums{0, 0, 0, 0.0};
+    A.spread[i] = SpreadSums{0, 0, 0, 0, 0.0};
   for (int i = threadIdx.x; i < A.nd * nm; i += blockDim.x) {
     const int d = i / nm, j = i - d * nm;
     A.D[d].cnt[2 * j] = 0;
     A.D[d].cnt[2 * j + 1] = 0;
     A.D[d].hits[j] = 0;
     if (A.D[d].m2) A.D[d].m2[j] = 0.0;
+    if (A.D[d].xmax) A.D[d].xmax[j] = 0;
   }
   if ((int)threadIdx.x < A.nd) *A.D[threadIdx.x].status = 0;
 }
@@ -1254,23 +1322,28 @@ __global__ __launch_bounds__(1024) void k_finalize(SampleArgs A, double* const* 
     bool ovf = false;
     const U128 c128 = wave_sum128c(U128{v.lo, v.hi}, &ovf);
     ovf = __ballot(ovf) != 0;  // a carry seen on any lane's path
-    uint64_t h = v.hits;
+    uint64_t h = v.hits, xm = v.xmax;
     double sq = v.m2;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       h += __shfl_xor(h, off, kWave);
       sq += __shfl_xor(sq, off, kWave);
+      const uint64_t o = __shfl_xor(xm, off, kWave);
+      xm = o > xm ? o : xm;
     }
     if (lane == 0) {
       A.D[d].cnt[2 * j] = c128.lo;
       A.D[d].cnt[2 * j + 1] = c128.hi;
       A.D[d].hits[j] = h;
       if (A.D[d].m2) A.D[d].m2[j] = sq;
+      if (A.D[d].xmax) A.D[d].xmax[j] = xm;
       if (ovf) atomicOr(A.D[d].status, TC_F_OVERFLOW | TC_F_MOTIF(j));
       const uint64_t W = A.D[d].S[A.m];
       double c = u128_to_double(c128.lo, c128.hi);
       if (A.D[d].h) c = ldexp(c, -64);
-      est[d][j] = (W == 0) ? 0.0 : __dmul_rn(__ddiv_rn(c, (double)A.k), (double)W);
+      // exhaustive mode: the count itself
+      est[d][j] = A.exhaustive ? c
+                               : ((W == 0) ? 0.0 : __dmul_rn(__ddiv_rn(c, (double)A.k), (double)W));
     }
   }
   __syncthreads();
@@ -1357,7 +1430,7 @@ size_t sample_workspace_bytes(uint64_t k, int nd, int32_t n_motifs, const Sample
 tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
                        const MotifPlan& plan, uint64_t k, uint64_t seed, uint32_t stream_id,
                        uint64_t i0, tc_result* const* out, const SampleTuning& tune, void* ws,
-                       size_t ws_bytes, hipStream_t st) {
+                       size_t ws_bytes, hipStream_t st, bool exhaustive) {
   if (nd < 1 || nd > kMaxDeltas) return TC_E_ARG;
   const SampleLayout L = sample_layout(k, nd, plan.n_motifs, tune);
   if (!ws || ws_bytes < L.total) return TC_E_WORKSPACE;
@@ -1408,12 +1481,14 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
     D.h = w[d]->h;
     D.P = out[d]->P;
     D.m2 = out[d]->m2;
+    D.xmax = out[d]->xmax;
     est_host[d] = out[d]->estimate;
   }
   A.k = k;
   A.seed = seed;
   A.i0 = i0;
   A.stream_id = stream_id;
+  A.exhaustive = exhaustive ? 1 : 0;
   A.chunk = (uint32_t)L.chunk;
   A.win_lo = (uint32_t*)(base + L.win_lo);
   A.win_len = (uint32_t*)(base + L.win_len);

@@ -1,6 +1,8 @@
 // Preprocess(delta): per-edge window degrees and the exact integer CDF of the
 // path weights (Algorithm Preprocess with Claim "count":
-// w_e = d^-_u[t - delta, t] * d^+_v[t, t + delta]).
+// w_e = d^-_u[t - delta, t] * d^+_v[t, t + delta], and for the other anchor
+// classes d^{alpha_1}_u * d^{alpha_3}_v over the class's intervals, a side
+// without an edge counting 1).  Described below for the class <-,+,<,>>.
 //
 // The window bounds are ranks of sorted query sequences in sorted adjacency
 // arrays on the composite key (vertex, time): the out-CSR order p is sorted
@@ -131,11 +133,13 @@ __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, Key
   }
 }
 
-// per p: v's window (by edge id), the path record, and the tile sums of a * b
+// per p: side 3's window (the last rank pass stored it by edge id), the path
+// record, and the tile sums of a * b.  An absent side has the window {0, 1}
+// (one position, no edge); side 1's is then written here too.
 __global__ __launch_bounds__(kWBlock) void k_combine(const int32_t* __restrict__ out_eid,
                                                      const uint2* __restrict__ win_e,
-                                                     const uint32_t* __restrict__ lo_in,
-                                                     const uint32_t* __restrict__ a,
+                                                     uint32_t* __restrict__ lo_in,
+                                                     uint32_t* __restrict__ a,
                                                      const int32_t* __restrict__ out_src,
                                                      const int32_t* __restrict__ out_dst,
                                                      const int64_t* __restrict__ out_t, int64_t m,
@@ -143,7 +147,8 @@ __global__ __launch_bounds__(kWBlock) void k_combine(const int32_t* __restrict__
                                                      uint32_t* __restrict__ b_out,
                                                      uint4* __restrict__ prec,
                                                      uint64_t* __restrict__ tile_sums,
-                                                     const uint32_t* __restrict__ gstatus) {
+                                                     const uint32_t* __restrict__ gstatus,
+                                                     int side1, int side3) {
   if (*gstatus) return;  // a rejected graph: its edge ids are not a permutation
   __shared__ U128 s_w[kWBlock / kWave];
   const int64_t start = (int64_t)blockIdx.x * kWTile;
@@ -152,12 +157,20 @@ __global__ __launch_bounds__(kWBlock) void k_combine(const int32_t* __restrict__
   for (int r = 0; r < kWItems; ++r) {
     const int64_t p = start + (int64_t)r * kWBlock + threadIdx.x;
     if (p < m) {
-      const uint2 wq = win_e[out_eid[p]];
-      const uint32_t bb = wq.y, ap = a[p];
+      const uint2 wq = side3 ? win_e[out_eid[p]] : make_uint2(0u, 1u);
+      uint32_t l1 = 0, ap = 1;
+      if (side1) {
+        l1 = lo_in[p];
+        ap = a[p];
+      } else {
+        lo_in[p] = 0;
+        a[p] = 1;
+      }
+      const uint32_t bb = wq.y;
       lo_out[p] = wq.x;
       b_out[p] = bb;
       const int64_t t = out_t[p];
-      prec[2 * p] = make_uint4(lo_in[p], ap, wq.x, bb);
+      prec[2 * p] = make_uint4(l1, ap, wq.x, bb);
       prec[2 * p + 1] =
           make_uint4((uint32_t)out_src[p], (uint32_t)out_dst[p], (uint32_t)t, (uint32_t)(t >> 32));
       acc = add128(acc, U128{(uint64_t)ap * (uint64_t)bb, 0});
@@ -420,14 +433,15 @@ static WeightsLayout weights_layout(int64_t m) {
 
 size_t weights_workspace_bytes(int64_t m) { return weights_layout(m).total; }
 
-tc_status path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_bytes,
-                       hipStream_t st, tc_weights* w) {
+tc_status path_weights(const tc_graph* g, int64_t delta, const tc_class& cls, void* ws,
+                       size_t ws_bytes, hipStream_t st, tc_weights* w) {
   const int64_t m = g->m;
   WeightsLayout L = weights_layout(m);
   if (ws_bytes < L.total) return TC_E_WORKSPACE;
   char* base = (char*)ws;
   w->delta = delta;
   w->m = m;
+  w->cls = cls;
   w->lo_in = (uint32_t*)(base + L.lo_in);
   w->a = (uint32_t*)(base + L.a);
   w->lo_out = (uint32_t*)(base + L.lo_out);
@@ -443,43 +457,64 @@ tc_status path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_byt
   uint32_t* lo_out_q = (uint32_t*)(base + L.lo_out_q);
   uint2* win_e = (uint2*)(base + L.win_e);
   uint32_t* split = (uint32_t*)(base + L.split);
+  const uint32_t* gst = (const uint32_t*)g->status;
   if (m > 0) {
     TimedLaunch tl("k_windows", st);
     const int64_t nsplit = (2 * m + kMPTile - 1) / kMPTile + 1;
     const unsigned sb = (unsigned)((nsplit + 255) / 256);
     const unsigned rb = (unsigned)(nsplit - 1);
+    // (vertex, time) keys: the out-CSR sorted by (source, time), the in-CSR
+    // by (destination, time)
     const KeyCols outk{g->out_src, g->out_t, 0};
     const KeyCols ink{g->in_dst, g->in_t, 0};
-    // u's in-window [t - delta, t] for every out-CSR position p, and v's
-    // out-window [t, t + delta] for every in-CSR position q
-    const KeyCols q_lo{g->out_src, g->out_t, -delta};
-    const KeyCols q_hi{g->in_dst, g->in_t, delta};
+    const bool s1 = cls.mode1 != TC_SIDE_NONE, s3 = cls.mode3 != TC_SIDE_NONE;
+    // Side 1: for every scan position p (out-CSR order, queries (u, t)) the
+    // window of u's in- or out-edges; side 3: for every in-CSR position q
+    // (queries (v, t): each edge seen from its destination) the window of
+    // v's in- or out-edges.  A window [from, to] is the rank of (w, from)
+    // counted with "<" and of (w, to) counted with "<=".
+    auto shifted = [&](const KeyCols& q, int64_t sh) { return KeyCols{q.v, q.t, sh}; };
+    const int64_t lo1 = cls.after1 ? 0 : -delta, hi1 = cls.after1 ? delta : 0;
+    const int64_t lo3 = cls.after3 ? 0 : -delta, hi3 = cls.after3 ? delta : 0;
+    const KeyCols d1 = cls.mode1 == TC_SIDE_IN ? ink : outk;
+    const KeyCols d3 = cls.mode3 == TC_SIDE_IN ? ink : outk;
     uint32_t* sp[4];
     for (int c = 0; c < 4; ++c) sp[c] = split + (size_t)c * (size_t)(nsplit + 1);
-    const SplitJobs J{{{q_lo, ink, sp[0], 0}, {outk, ink, sp[1], 1}, {ink, outk, sp[2], 0},
-                       {q_hi, outk, sp[3], 1}}};
-    hipLaunchKernelGGL(k_mp_split4, dim3(sb, 4), dim3(256), 0, st, J, m, m, nsplit);
-    hipLaunchKernelGGL(k_mp_rank<false>, dim3(rb), dim3(kMPBlock), 0, st, q_lo, m, ink, m,
-                       (const uint32_t*)sp[0], (const uint32_t*)nullptr, w->lo_in,
-                       (uint2*)nullptr, (const int32_t*)nullptr, (const uint32_t*)g->status);
-    hipLaunchKernelGGL(k_mp_rank<true>, dim3(rb), dim3(kMPBlock), 0, st, outk, m, ink, m,
-                       (const uint32_t*)sp[1], (const uint32_t*)w->lo_in, w->a, (uint2*)nullptr,
-                       (const int32_t*)nullptr, (const uint32_t*)g->status);
-    hipLaunchKernelGGL(k_mp_rank<false>, dim3(rb), dim3(kMPBlock), 0, st, ink, m, outk, m,
-                       (const uint32_t*)sp[2], (const uint32_t*)nullptr, lo_out_q,
-                       (uint2*)nullptr, (const int32_t*)nullptr, (const uint32_t*)g->status);
-    hipLaunchKernelGGL(k_mp_rank<true>, dim3(rb), dim3(kMPBlock), 0, st, q_hi, m, outk, m,
-                       (const uint32_t*)sp[3], (const uint32_t*)lo_out_q, (uint32_t*)nullptr,
-                       win_e, (const int32_t*)g->in_eid, (const uint32_t*)g->status);
+    SplitJobs J{};
+    int nj = 0;
+    if (s1) {
+      J.j[nj++] = SplitJob{shifted(outk, lo1), d1, sp[0], 0};
+      J.j[nj++] = SplitJob{shifted(outk, hi1), d1, sp[1], 1};
+    }
+    if (s3) {
+      J.j[nj++] = SplitJob{shifted(ink, lo3), d3, sp[2], 0};
+      J.j[nj++] = SplitJob{shifted(ink, hi3), d3, sp[3], 1};
+    }
+    hipLaunchKernelGGL(k_mp_split4, dim3(sb, nj), dim3(256), 0, st, J, m, m, nsplit);
+    if (s1) {
+      hipLaunchKernelGGL(k_mp_rank<false>, dim3(rb), dim3(kMPBlock), 0, st, shifted(outk, lo1), m,
+                         d1, m, (const uint32_t*)sp[0], (const uint32_t*)nullptr, w->lo_in,
+                         (uint2*)nullptr, (const int32_t*)nullptr, gst);
+      hipLaunchKernelGGL(k_mp_rank<true>, dim3(rb), dim3(kMPBlock), 0, st, shifted(outk, hi1), m,
+                         d1, m, (const uint32_t*)sp[1], (const uint32_t*)w->lo_in, w->a,
+                         (uint2*)nullptr, (const int32_t*)nullptr, gst);
+    }
+    if (s3) {
+      hipLaunchKernelGGL(k_mp_rank<false>, dim3(rb), dim3(kMPBlock), 0, st, shifted(ink, lo3), m,
+                         d3, m, (const uint32_t*)sp[2], (const uint32_t*)nullptr, lo_out_q,
+                         (uint2*)nullptr, (const int32_t*)nullptr, gst);
+      hipLaunchKernelGGL(k_mp_rank<true>, dim3(rb), dim3(kMPBlock), 0, st, shifted(ink, hi3), m,
+                         d3, m, (const uint32_t*)sp[3], (const uint32_t*)lo_out_q,
+                         (uint32_t*)nullptr, win_e, (const int32_t*)g->in_eid, gst);
+    }
     hipLaunchKernelGGL(k_combine, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
-                       (const int32_t*)g->out_eid, (const uint2*)win_e,
-                       (const uint32_t*)w->lo_in, (const uint32_t*)w->a,
+                       (const int32_t*)g->out_eid, (const uint2*)win_e, w->lo_in, w->a,
                        (const int32_t*)g->out_src, (const int32_t*)g->out_dst,
                        (const int64_t*)g->out_t, m, w->lo_out, w->b, (uint4*)w->prec, tile_sums,
-                       (const uint32_t*)g->status);
+                       gst, s1 ? 1 : 0, s3 ? 1 : 0);
   }
   hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, (const uint64_t*)tile_sums, ntiles,
-                     tile_off, w->S, m, w->status, (const uint32_t*)g->status);
+                     tile_off, w->S, m, w->status, gst);
   if (ntiles > 0) {
     TimedLaunch tl("k_scan_apply", st);
     hipLaunchKernelGGL(k_scan_apply<false>, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,

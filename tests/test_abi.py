@@ -88,7 +88,7 @@ def test_host_argument_errors_return_before_any_launch(tcb):
                              ctypes.byref(w)) == tcb.TC_E_ARG
     fake = ctypes.c_void_p(256).value
     r = tcb.tc_result(fake, fake, fake, fake, None, None, None, None)
-    bad = [(0, 1), (2, 1), (1, 2)]  # not anchored on 0->1->2->3
+    bad = [(0, 1), (0, 2), (0, 3)]  # a 3-star: no anchor path
     arr = (tcb.tc_motif * 1)(tcb.make_motif(bad))
     assert L.tc_sample_estimate(ctypes.byref(g), ctypes.byref(w), arr, 1, 10, 1, 0, 0,
                                 ctypes.c_void_p(fake), 1 << 40, ctypes.byref(r), None) == tcb.TC_E_UNSUPPORTED
@@ -106,6 +106,34 @@ def test_host_argument_errors_return_before_any_launch(tcb):
     arr = (tcb.tc_motif * 1)(tcb.make_motif(ok))
     assert L.tc_sample_estimate(ctypes.byref(g), ctypes.byref(w), arr, 1, 10, 1, 0, 0,
                                 ctypes.c_void_p(fake), 1 << 40, ctypes.byref(r), None) == tcb.TC_E_ARG
+
+
+def test_anchor_and_class_host_checks(tcb):
+    L = tcb.lib()
+    assert tcb.tc_motif_anchor([(0, 1), (1, 2), (2, 3), (3, 0)]) == (tcb.SPINE_CLASS, 3, [0, 1, 2])
+    # a wedge (3 vertices): base 0 -> 1 first, then 0 -> 2 from 0's out-list
+    assert tcb.tc_motif_anchor([(0, 1), (0, 2), (2, 1)]) == ((2, 1, 0, 0), 2, [1, 0])
+    with pytest.raises(tcb.TCError) as e:
+        tcb.tc_motif_anchor([(0, 1), (0, 2), (0, 3)])
+    assert e.value.code == tcb.TC_E_UNSUPPORTED
+    g = tcb.tc_graph()
+    w = tcb.tc_weights()
+    g.m = w.m = 10
+    for bad in ((0, 0, 0, 0), (3, 0, 2, 1), (1, 2, 2, 1)):
+        c = tcb.tc_class(*bad)
+        assert L.tc_path_weights_class(ctypes.byref(g), 5, ctypes.byref(c), ctypes.c_void_p(1), 0,
+                                       None, ctypes.byref(w)) == tcb.TC_E_ARG
+    fake = ctypes.c_void_p(256).value
+    r = tcb.tc_result(fake, fake, fake, fake, None, None, None, None)
+    arr = (tcb.tc_motif * 1)(tcb.make_motif([(0, 1), (1, 2), (2, 3), (3, 0)]))
+    assert L.tc_exhaustive_count(ctypes.byref(g), ctypes.byref(w), arr, 1, 0, 0,
+                                 ctypes.c_void_p(fake), 1 << 40, ctypes.byref(r),
+                                 None) == tcb.TC_E_ARG  # count = 0
+    # weights of another class than the motifs' anchors
+    w.cls = tcb.tc_class(2, 1, 0, 0)
+    assert L.tc_exhaustive_count(ctypes.byref(g), ctypes.byref(w), arr, 1, 0, 5,
+                                 ctypes.c_void_p(fake), 1 << 40, ctypes.byref(r),
+                                 None) == tcb.TC_E_ARG
 
 
 def test_binding_raises_without_library(tmp_path, monkeypatch):
