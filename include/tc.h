@@ -52,10 +52,13 @@ typedef enum {
 
 /* Bits of a device status word. */
 #define TC_F_RANGE 1u     /* bad vertex id or timestamp                              */
-#define TC_F_OVERFLOW 2u  /* W >= 2^64, or a ListCount partial total >= 2^64          */
+#define TC_F_OVERFLOW 2u  /* W >= 2^64; a count cnt >= 2^128; or, with a proposal
+                             weight set, a per-sample X >= 2^64                     */
 #define TC_F_RNG 4u       /* 1024 consecutive rejections in the range reduction       */
 /* With TC_F_OVERFLOW from the sampler, bit 8 + j names each motif j whose
- * count reached 2^64; the counts of the other motifs of the call stay exact. */
+ * count overflowed; the counts of the other motifs of the call stay exact.
+ * Per-sample counts X are exact up to 2^128 (ListCount in 128 bits where a
+ * level's total reaches 2^64). */
 #define TC_F_MOTIF(j) (1u << (8 + (j)))
 
 /* A temporal motif: H's edges listed in pi order (edge i has time rank i),
@@ -180,7 +183,8 @@ typedef struct tc_weights {
  *   status             : TC_F_* bits (OR of the weights' status and the
  *                        sampler's own)
  *   e1, e2, e3         : optional [k] edge ids of the sampled path (NULL=off)
- *   X                  : optional [n_motifs * k], motif-major (NULL = off)
+ *   X                  : optional [n_motifs * k], motif-major, saturated at
+ *                        2^64 - 1 (cnt has the exact sum) (NULL = off)
  *   P                  : optional [k] scan position of the centre edge
  *                        (all ones when W = 0; NULL = off)
  *   m2                 : optional [n_motifs] sum over samples of

@@ -133,9 +133,9 @@ def list_count(lists):
     for i, l in enumerate(lists):
         off[i + 1] = off[i] + len(l)
     vals = np.ascontiguousarray(vals)
-    X = np.zeros(1, dtype=np.uint64)
+    X = np.zeros(2, dtype=np.uint64)
     st = lib().or_list_count(_p(vals), _p(off), len(lists), _p(X))
-    return st, int(X[0])
+    return st, int(X[0]) | (int(X[1]) << 64)
 
 
 @dataclass

@@ -362,33 +362,43 @@ void pair_window(const Graph& G, int32_t a, int32_t b, int64_t lo_t, int64_t hi_
 // ListCount: number of chains l_1 < l_2 < ... < l_l with l_r drawn from the
 // sorted list L_r.  cnt_1 is all ones; cnt_r[i] sums cnt_{r-1}[j] over the
 // entries of L_{r-1} strictly before L_r[i], found with one pointer that only
-// moves forward.  Returns false when any list's total reaches 2^64.
+// moves forward.  Counts are kept in 128 bits; returns false only if a
+// level's total reaches 2^128.
+bool add_u128(u128* acc, u128 v) {
+  const u128 r = *acc + v;
+  const bool ok = r >= *acc;
+  *acc = r;
+  return ok;
+}
+
 bool list_count(const std::vector<std::vector<int64_t>>& L, u128* X) {
   size_t l = L.size();
   if (l == 0) { *X = 1; return true; }
   std::vector<u128> prev(L[0].size(), 1), cur;
-  if ((u128)L[0].size() > kU64Max) return false;
+  bool ok = true;
   for (size_t r = 1; r < l; ++r) {
     cur.assign(L[r].size(), 0);
     size_t j = 0;
     u128 run = 0;
     for (size_t i = 0; i < L[r].size(); ++i) {
       while (j < L[r - 1].size() && L[r - 1][j] < L[r][i]) {
-        run += prev[j];
+        ok = add_u128(&run, prev[j]) && ok;
         ++j;
       }
       cur[i] = run;
     }
     u128 total = 0;
-    for (u128 c : cur) total += c;
-    if (total > kU64Max) return false;
+    for (u128 c : cur) ok = add_u128(&total, c) && ok;
     prev.swap(cur);
   }
   u128 s = 0;
-  for (u128 c : prev) s += c;
+  for (u128 c : prev) ok = add_u128(&s, c) && ok;
   *X = s;
-  return true;
+  return ok;
 }
+
+// A per-sample count as one 64-bit word: saturated at 2^64 - 1.
+uint64_t sat64(u128 x) { return (x >> 64) ? kU64Max : (uint64_t)x; }
 
 // The edge of an anchor side at the centre edge's endpoint `at` (u for
 // side 1, v for side 3): position `pos` of the in-CSR or the out-CSR.
@@ -583,7 +593,7 @@ int or_check_motif(void* h, const uint8_t* motif, int64_t delta, int32_t e1, int
   if (!parse_motif(motif, &M)) return OR_ARG;
   u128 c = 0;
   const int st = check_motif(*(Graph*)h, M, delta, e1, e2, e3, &c);
-  *X = (uint64_t)c;
+  *X = sat64(c);
   return st;
 }
 
@@ -665,17 +675,17 @@ int or_sample_cls(void* hg, int64_t delta, const uint8_t* cls, const uint32_t* l
       if (Po) Po[ii] = (uint32_t)p;
       const uint32_t hp = hq ? hq[p] : 1u;
       for (int j = 0; j < n_motifs; ++j) {
-        u128 X128 = 0;
-        int st = check_motif(G, Ms[j], delta, e1, e2, e3, &X128);
-        const uint64_t X = (uint64_t)X128;
+        u128 X = 0;
+        int st = check_motif(G, Ms[j], delta, e1, e2, e3, &X);
+        // an importance-sampling term floor(X 2^64 / h) needs X < 2^64
+        if (hq && (X >> 64)) st |= OR_OVERFLOW;
         // an overflow also names its motif (bit 8 + j)
         pst[tid] |= st | ((st & OR_OVERFLOW) ? (1 << (8 + j)) : 0);
-        if (Xo) Xo[(uint64_t)j * k + ii] = X;
-        u128 add = hq ? (((u128)X << 64) / hp) : (u128)X;
-        if (pc[tid][j] + add < pc[tid][j]) pst[tid] |= OR_OVERFLOW | (1 << (8 + j));
-        pc[tid][j] += add;
+        if (Xo) Xo[(uint64_t)j * k + ii] = sat64(X);
+        u128 add = hq ? ((X << 64) / hp) : X;
+        if (!add_u128(&pc[tid][j], add)) pst[tid] |= OR_OVERFLOW | (1 << (8 + j));
         ph[tid][j] += X > 0;
-        px[tid][j] = std::max(px[tid][j], X);
+        px[tid][j] = std::max(px[tid][j], sat64(X));
         const double v = (double)X / (double)hp;
         pm[tid][j] += v * v;
       }
@@ -683,8 +693,7 @@ int or_sample_cls(void* hg, int64_t delta, const uint8_t* cls, const uint32_t* l
     for (int tid = 0; tid < nthreads; ++tid) {
       status |= pst[tid];
       for (int j = 0; j < n_motifs; ++j) {
-        if (c[j] + pc[tid][j] < c[j]) status |= OR_OVERFLOW | (1 << (8 + j));
-        c[j] += pc[tid][j];
+        if (!add_u128(&c[j], pc[tid][j])) status |= OR_OVERFLOW | (1 << (8 + j));
         hh[j] += ph[tid][j];
         mm[j] += pm[tid][j];
         mx[j] = std::max(mx[j], px[tid][j]);
@@ -770,14 +779,13 @@ int or_enumerate(void* hg, int64_t delta, const uint8_t* cls, const uint32_t* lo
     int32_t e3 = K.mode[1] == SIDE_NONE ? -1 : side_edge(G, K.mode[1], lo3[p] + j3);
     if (e1o) { e1o[ii] = e1; e2o[ii] = e2; e3o[ii] = e3; }
     for (int j = 0; j < n_motifs; ++j) {
-      u128 X128 = 0;
-      int st = check_motif(G, Ms[j], delta, e1, e2, e3, &X128);
-      const uint64_t X = (uint64_t)X128;
+      u128 X = 0;
+      int st = check_motif(G, Ms[j], delta, e1, e2, e3, &X);
+      if (!add_u128(&pc[tid][j], X)) st |= OR_OVERFLOW;
       pst[tid] |= st | ((st & OR_OVERFLOW) ? (1 << (8 + j)) : 0);
-      if (Xo) Xo[(uint64_t)j * count + ii] = X;
-      pc[tid][j] += X;
+      if (Xo) Xo[(uint64_t)j * count + ii] = sat64(X);
       ph[tid][j] += X > 0;
-      px[tid][j] = std::max(px[tid][j], X);
+      px[tid][j] = std::max(px[tid][j], sat64(X));
       pm[tid][j] += (double)X * (double)X;
     }
   }
@@ -787,7 +795,7 @@ int or_enumerate(void* hg, int64_t delta, const uint8_t* cls, const uint32_t* lo
     uint64_t h = 0, mx = 0;
     double mm = 0.0;
     for (int tid = 0; tid < nthreads; ++tid) {
-      c += pc[tid][j];
+      if (!add_u128(&c, pc[tid][j])) status |= OR_OVERFLOW | (1 << (8 + j));
       h += ph[tid][j];
       mm += pm[tid][j];
       mx = std::max(mx, px[tid][j]);
@@ -902,8 +910,8 @@ int or_exhaustive(void* h, const uint8_t* motif, int64_t delta, const uint8_t* c
         const int32_t e1 = K.mode[0] == SIDE_NONE ? -1 : side_edge(G, K.mode[0], lo1[p] + j1);
         const int32_t e3 = K.mode[1] == SIDE_NONE ? -1 : side_edge(G, K.mode[1], lo3[p] + j3);
         pst[tid] |= check_motif(G, M, delta, e1, G.out_ord[p], e3, &X);
-        s1[tid] += X;
-        s2[tid] += X * X;
+        if (!add_u128(&s1[tid], X) || (X >> 64) || !add_u128(&s2[tid], X * X))
+          pst[tid] |= OR_OVERFLOW;
         nz[tid] += X > 0;
       }
   }
@@ -1013,14 +1021,16 @@ int or_brute_count(void* h, const uint8_t* motif_bytes, int64_t delta, uint64_t*
 }
 
 // ListCount on caller-provided sorted lists (for pinning against product
-// enumeration): lists concatenated in `vals`, list r spans [off[r], off[r+1]).
+// enumeration): lists concatenated in `vals`, list r spans [off[r], off[r+1]);
+// X receives the 128-bit count as (low, high) words.
 int or_list_count(const int64_t* vals, const int64_t* off, int l, uint64_t* X) {
   std::vector<std::vector<int64_t>> L(l);
   for (int r = 0; r < l; ++r) L[r].assign(vals + off[r], vals + off[r + 1]);
   u128 c;
-  if (!list_count(L, &c)) return OR_OVERFLOW;
-  *X = (uint64_t)c;
-  return OR_OK;
+  const bool ok = list_count(L, &c);
+  X[0] = (uint64_t)c;
+  X[1] = (uint64_t)(c >> 64);
+  return ok ? OR_OK : OR_OVERFLOW;
 }
 
 int or_max_threads(void) { return omp_get_max_threads(); }

@@ -39,8 +39,7 @@
 //                    entries: each level as a merge of L_{r-1} and L_r in
 //                    LDS tiles, prefix sums in per-block scratch.
 //   k_listcount_big  longer still: one thread per item, merged time sweep.
-// Each level total is summed in 128 bits (a total >= 2^64 sets the overflow
-// bit).  Block sums are 128-bit and reach the outputs with one set of
+// A level total of 2^64 or more hands the item to the 128-bit pass.  Block sums are 128-bit and reach the outputs with one set of
 // atomics per block, so cnt is exact whatever the launch shape, the item
 // order or the tuning.
 #include <hip/hip_runtime.h>
@@ -336,8 +335,14 @@ struct PathRec {
 // anchor time of its segment and before the next anchor time, or up to the
 // first anchor time + delta after the last one (integer times, so "before
 // T" is "at most T - 1").
+template <bool GENERAL>
 __device__ __forceinline__ void key_window(const SampleArgs& A, const PathRec& P, int q,
                                            int64_t delta, int64_t* lo, int64_t* hi) {
+  if (!GENERAL) {  // the spine's lists all come after t3: (t3, t1 + delta]
+    *lo = P.T[2];
+    *hi = P.T[0] + delta;
+    return;
+  }
   const int sg = A.plan.pair_seg[q];
   *lo = P.T[sg];
   *hi = sg + 1 < A.plan.n_anchor ? P.T[sg + 1] - 1 : P.T[0] + delta;
@@ -345,6 +350,11 @@ __device__ __forceinline__ void key_window(const SampleArgs& A, const PathRec& P
 
 // Seven wavefronts per SIMD (at most 72 VGPRs): the kernel waits on L2 and
 // HBM round trips, and this occupancy measured fastest (6: -4%, 8: -5%).
+// GENERAL = false is the form for the <-,+,<,>> class with the anchor ranks
+// in path order (e1, centre, e3) and random draws, with those choices fixed
+// at compile time (fewer live registers); GENERAL = true reads them from the
+// plan (any class, wedges, the exhaustive mode).
+template <bool GENERAL>
 __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
   __shared__ PathRec s_path[kSBlock];
   __shared__ uint32_t s_nvalid;
@@ -390,7 +400,8 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
     uint32_t hp = 1;
     // in exhaustive mode the sample is the anchor of CDF rank i0 + ii
     const uint64_t rank = A.i0 + ii;
-    const bool none = W == 0 || (A.exhaustive && rank >= W);
+    const bool exh = GENERAL && A.exhaustive;
+    const bool none = W == 0 || (exh && rank >= W);
     if (active) {
       if (none) {
         if (D.P) D.P[ii] = 0xFFFFFFFFu;
@@ -405,7 +416,7 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
         uint64_t r;
         Words4 blk0{0, 0, 0, 0};
         const uint64_t i = A.i0 + ii;  // counter of the random stream
-        if (A.exhaustive) {
+        if (exh) {
           r = rank;
         } else {
           blk0 = philox_block(A.seed, A.stream_id, i, 0);
@@ -423,7 +434,7 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
         const uint4 pr0 = D.prec[2 * (uint64_t)p], pr1 = D.prec[2 * (uint64_t)p + 1];
         const uint32_t ap = pr0.y, bp = pr0.w;
         uint32_t j1, j3;
-        if (A.exhaustive) {
+        if (exh) {
           // rank r - S[p] = j1 * b + j3 (b >= 1: w_p = a * b > 0 here)
           const uint64_t jj = r - D.S[p];
           j1 = (uint32_t)(jj / bp);
@@ -448,7 +459,8 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
         v = (int32_t)pr1.y;
         const int64_t t2 = (int64_t)(((uint64_t)pr1.w << 32) | pr1.z);
         // the side edges: a record {other end, eid, t} of the in- or out-CSR
-        const int m1 = A.plan.cls.mode1, m3 = A.plan.cls.mode3;
+        const int m1 = GENERAL ? (int)A.plan.cls.mode1 : TC_SIDE_IN;
+        const int m3 = GENERAL ? (int)A.plan.cls.mode3 : TC_SIDE_OUT;
         int64_t ts[3] = {0, t2, 0};
         int32_t eid1 = -1, eid3 = -1;
         if (m1 != TC_SIDE_NONE) {
@@ -474,10 +486,10 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
         const bool has1 = m1 != TC_SIDE_NONE, has3 = m3 != TC_SIDE_NONE;
         valid = u != v && (!has1 || (x != u && x != v)) && (!has3 || (y != u && y != v)) &&
                 (!(has1 && has3) || x != y);
-        const int na = A.plan.n_anchor;
+        const int na = GENERAL ? A.plan.n_anchor : 3;
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk)
-          Tk[kk] = kk < na ? ts[A.plan.order[kk]] : 0;
+          Tk[kk] = kk < na ? ts[GENERAL ? A.plan.order[kk] : kk] : 0;
         for (int kk = 1; kk < na; ++kk) valid = valid && Tk[kk - 1] < Tk[kk];
         valid = valid && (Tk[na - 1] - Tk[0]) <= D.delta;
         if (D.h && valid) {
@@ -506,7 +518,7 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
       const uint32_t q = A.plan.gate_pair[gi];
       const PathRec P = s_path[sidx];
       int64_t tlo, thi;
-      key_window(A, P, (int)q, D.delta, &tlo, &thi);
+      key_window<GENERAL>(A, P, (int)q, D.delta, &tlo, &thi);
       uint32_t lo, hi;
       pair_window(A, slot_vertex(A.plan.pair_a[q], P.x, P.u, P.v, P.y),
                   slot_vertex(A.plan.pair_b[q], P.x, P.u, P.v, P.y), tlo, thi, &lo, &hi);
@@ -549,7 +561,7 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
         const uint32_t q = (uint32_t)__ffs(mk) - 1;
         const PathRec P = s_path[sidx];
         int64_t tlo, thi;
-        key_window(A, P, (int)q, D.delta, &tlo, &thi);
+        key_window<GENERAL>(A, P, (int)q, D.delta, &tlo, &thi);
         uint32_t lo, hi;
         pair_window(A, slot_vertex(A.plan.pair_a[q], P.x, P.u, P.v, P.y),
                     slot_vertex(A.plan.pair_b[q], P.x, P.u, P.v, P.y), tlo, thi, &lo, &hi);
@@ -646,16 +658,29 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
 // ranges [ptr, end)) by a merged sweep in time order: f[r] counts chains
 // ending in list r at times seen so far; a group of c equal times at the head
 // of list r adds c * f[r-1] (f[-1] = 1), lists taken last to first so equal
-// times never chain.
-template <int ML, bool CHECKED>
-__device__ uint64_t sweep(const int64_t* __restrict__ pair_t, uint32_t (&ptr)[ML],
-                          const uint32_t (&end)[ML], int l, bool* overflow) {
+// times never chain.  Counts are 128-bit; *overflow is set when one reaches
+// 2^128.  This is the pass for the longest lists and for the items whose
+// count reaches 2^64.
+__device__ __forceinline__ U128 mul_u64_u128(uint64_t c, U128 f, bool* overflow) {
+  // c * f modulo 2^128, flagging a product of 2^128 or more
+  const uint64_t lo = c * f.lo;
+  const uint64_t carry = __umul64hi(c, f.lo);
+  const uint64_t hi_lo = c * f.hi;
+  if (__umul64hi(c, f.hi) != 0) *overflow = true;
+  const uint64_t hi = hi_lo + carry;
+  if (hi < hi_lo) *overflow = true;
+  return U128{lo, hi};
+}
+
+template <int ML>
+__device__ U128 sweep128(const int64_t* __restrict__ pair_t, uint32_t (&ptr)[ML],
+                         const uint32_t (&end)[ML], int l, bool* overflow) {
   const int64_t kNone = INT64_MAX;
   int64_t head[ML], nxt[ML];
-  uint64_t f[ML];
+  U128 f[ML];
 #pragma unroll
   for (int r = 0; r < ML; ++r) {
-    f[r] = 0;
+    f[r] = U128{0, 0};
     head[r] = (r < l && ptr[r] < end[r]) ? pair_t[ptr[r]] : kNone;
     nxt[r] = (r < l && ptr[r] + 1 < end[r]) ? pair_t[ptr[r] + 1] : kNone;
   }
@@ -674,18 +699,15 @@ __device__ uint64_t sweep(const int64_t* __restrict__ pair_t, uint32_t (&ptr)[ML
           head[r] = nxt[r];
           nxt[r] = (ptr[r] + 1 < end[r]) ? pair_t[ptr[r] + 1] : kNone;
         } while (head[r] == tmin);
-        const uint64_t prev = (r == 0) ? 1ull : f[r - 1];
-        if (CHECKED) {
-          uint64_t add;
-          if (__builtin_mul_overflow(c, prev, &add)) *overflow = true;
-          if (__builtin_add_overflow(f[r], add, &f[r])) *overflow = true;
-        } else {
-          f[r] += c * prev;
-        }
+        const U128 prev = (r == 0) ? U128{1, 0} : f[r - 1];
+        const U128 add = mul_u64_u128(c, prev, overflow);
+        const U128 sum = add128(f[r], add);
+        if (sum.hi < f[r].hi || (sum.hi == f[r].hi && sum.lo < f[r].lo)) *overflow = true;
+        f[r] = sum;
       }
     }
   }
-  uint64_t X = 0;
+  U128 X{0, 0};
 #pragma unroll
   for (int r = 0; r < ML; ++r)
     if (r == l - 1) X = f[r];
@@ -879,8 +901,12 @@ __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A) {
 #pragma unroll
       for (int h = 0; h < CH; ++h) P[h] = Pn[h];
     }
-    if (sat && lane == 0) flag_status(A, d, TC_F_OVERFLOW | TC_F_MOTIF(j));
-    if (lane == 0) item_done(A, d, j, li, t_prev);
+    // a level total of 2^64 or more: the 128-bit pass counts the item
+    if (sat) {
+      if (lane == 0) A.big_code[atomicAdd(A.big_count, 1u)] = code;
+    } else if (lane == 0) {
+      item_done(A, d, j, li, t_prev);
+    }
     __threadfence_block();
   }
   fwd_flush(fb, A.mid_count, A.mid_code);
@@ -928,6 +954,7 @@ __global__ __launch_bounds__(kWave) void k_listcount_lds(SampleArgs A, uint64_t*
     }
     const bool fwd = maxlen > A.lds_cap || A.D[d].delta >= ((int64_t)1 << 32);
     U128 total{0, 0};
+    bool sat = false;  // a level total reached 2^64
     if (!fwd) {
       const uint32_t lo0 = lane_u32(my_lo, 0), len0 = lane_u32(my_len, 0);
       for (uint32_t i = lane; i < len0; i += kWave)
@@ -938,7 +965,7 @@ __global__ __launch_bounds__(kWave) void k_listcount_lds(SampleArgs A, uint64_t*
       // is below 2^64 the running 64-bit carry is the exact total (no 128-bit
       // sums); below 2^32 the level's prefix sums are kept as 32-bit words.
       uint64_t t_prev = lane_u32(my_len, 0);
-      bool sat = false, prev32 = false;
+      bool prev32 = false;
       for (int r = 1; r < l; ++r) {
         const uint32_t prev_len = lane_u32(my_len, r - 1);
         const uint32_t lo = lane_u32(my_lo, r);
@@ -984,10 +1011,7 @@ __global__ __launch_bounds__(kWave) void k_listcount_lds(SampleArgs A, uint64_t*
           t_prev = carry;
         } else {
           total = U128{uni64(total.lo), uni64(total.hi)};
-          if (total.hi != 0) {
-            sat = true;
-            if (lane == 0) flag_status(A, d, TC_F_OVERFLOW | TC_F_MOTIF(j));
-          }
+          if (total.hi != 0) sat = true;  // the 128-bit pass takes the item
           t_prev = total.hi ? ~0ull : total.lo;
         }
         prev32 = cur32;
@@ -998,7 +1022,9 @@ __global__ __launch_bounds__(kWave) void k_listcount_lds(SampleArgs A, uint64_t*
     }
     if (fwd)
       fwd_push(fb, code, A.wide_count, A.wide_code);
-    else if (lane == 0)
+    else if (sat) {
+      if (lane == 0) A.big_code[atomicAdd(A.big_count, 1u)] = code;
+    } else if (lane == 0)
       item_done(A, d, j, li, total.lo);
   }
   fwd_flush(fb, A.wide_count, A.wide_code);
@@ -1064,12 +1090,13 @@ __global__ __launch_bounds__(kWBlock, 7) void k_listcount_wide(SampleArgs A, uin
     for (int r = 0; r < l; ++r) maxlen = s_len[r] > maxlen ? s_len[r] : maxlen;
     maxlen = uni(maxlen);
     U128 total{0, 0};
+    bool sat = false;  // a level total reached 2^64
     if (maxlen <= (uint32_t)kWideCap) {
       // As in the one-wavefront pass: while T_r <= |L_r| T_{r-1} stays below
       // 2^64 the running carry is the exact level total (no 128-bit sums),
       // and below 2^32 the level's prefix sums are stored as 32-bit words.
       uint64_t t_prev = uni(s_len[0]);
-      bool sat = false, prev32 = false;
+      bool prev32 = false;
       for (int r = 1; r < l; ++r) {
         const uint32_t loA = uni(s_lo[r - 1]), nA = uni(s_len[r - 1]);
         const uint32_t loB = uni(s_lo[r]), nB = uni(s_len[r]);
@@ -1201,10 +1228,7 @@ __global__ __launch_bounds__(kWBlock, 7) void k_listcount_wide(SampleArgs A, uin
         if (exact64) {
           t_prev = carry;
         } else {
-          if (uni64(total.hi) != 0) {
-            sat = true;
-            if (tid == 0) flag_status(A, d, TC_F_OVERFLOW | TC_F_MOTIF(j));
-          }
+          if (uni64(total.hi) != 0) sat = true;  // the 128-bit pass takes the item
           t_prev = total.hi ? ~0ull : total.lo;
         }
         prev32 = cur32;
@@ -1214,7 +1238,7 @@ __global__ __launch_bounds__(kWBlock, 7) void k_listcount_wide(SampleArgs A, uin
       total = U128{t_prev, 0};
     }
     if (tid == 0) {
-      if (maxlen > (uint32_t)kWideCap)
+      if (maxlen > (uint32_t)kWideCap || sat)
         A.big_code[atomicAdd(A.big_count, 1u)] = code;
       else
         item_done(A, d, j, li, total.lo);
@@ -1227,7 +1251,10 @@ __global__ __launch_bounds__(kWBlock, 7) void k_listcount_wide(SampleArgs A, uin
   sums_flush<1>(A);
 }
 
-// Items with a list longer than kWideCap: one thread per item.
+// Items with a list longer than kWideCap, and items whose count reaches 2^64:
+// one thread per item, 128-bit counts.  The per-sample output X saturates at
+// 2^64 - 1; cnt takes the exact value.  An importance-sampling term
+// floor(X 2^64 / h) needs X < 2^64: beyond, the motif's overflow bit is set.
 __global__ __launch_bounds__(kSBlock) void k_listcount_big(SampleArgs A) {
   const int tid = threadIdx.x, wave = tid >> 6;
   const uint32_t n_items = *A.big_count;
@@ -1240,8 +1267,6 @@ __global__ __launch_bounds__(kSBlock) void k_listcount_big(SampleArgs A) {
     decode(A.big_code[it], &li, &j, &d);
     const int l = A.plan.n_lists[j];
     uint32_t ptr[kMaxLists], end[kMaxLists];
-    uint64_t prod = 1;
-    bool big = false;
 #pragma unroll
     for (int r = 0; r < kMaxLists; ++r) {
       ptr[r] = 0;
@@ -1249,24 +1274,27 @@ __global__ __launch_bounds__(kSBlock) void k_listcount_big(SampleArgs A) {
       if (r < l) {
         const uint64_t wi = win_index(A, d, A.plan.list_pair[j][r], li);
         ptr[r] = A.win_lo[wi];
-        const uint32_t len = A.win_len[wi];
-        end[r] = ptr[r] + len;
-        if (__builtin_mul_overflow(prod, (uint64_t)len, &prod)) big = true;
+        end[r] = ptr[r] + A.win_len[wi];
       }
     }
     bool ovf = false;
-    const uint64_t X = big ? sweep<kMaxLists, true>(A.pair_t, ptr, end, l, &ovf)
-                           : sweep<kMaxLists, false>(A.pair_t, ptr, end, l, &ovf);
-    if (ovf) flag_status(A, d, TC_F_OVERFLOW | TC_F_MOTIF(j));
+    const U128 X = sweep128<kMaxLists>(A.pair_t, ptr, end, l, &ovf);
     const DeltaArgs& D = A.D[d];
-    if (D.X) D.X[(uint64_t)j * A.k + A.c0 + li] = X;
+    const uint64_t X64 = X.hi ? ~0ull : X.lo;  // saturated
+    if (D.h && X.hi) ovf = true;
+    if (ovf) flag_status(A, d, TC_F_OVERFLOW | TC_F_MOTIF(j));
+    if (D.X) D.X[(uint64_t)j * A.k + A.c0 + li] = X64;
     const uint32_t hp = D.h ? A.samp_h[(uint64_t)d * A.chunk + li] : 1u;
-    const U128 c = contribution(X, D.h != nullptr, hp);
+    const U128 c = D.h ? contribution(X64, true, hp) : X;
+    const bool nz = (X.lo | X.hi) != 0;
     // few items: this wavefront's slot, updated with LDS atomics
     BlockSums* slot = sums_slot(A, wave, d, j);
-    atomicAdd((unsigned long long*)&slot->hits, X != 0 ? 1ull : 0ull);
-    if (X) atomicMax((unsigned long long*)&slot->xmax, (unsigned long long)X);
-    if (D.m2 && X) atomicAdd(&slot->m2, square_term(X, hp));
+    atomicAdd((unsigned long long*)&slot->hits, nz ? 1ull : 0ull);
+    if (nz) atomicMax((unsigned long long*)&slot->xmax, (unsigned long long)X64);
+    if (D.m2 && nz) {
+      const double v = __ddiv_rn(u128_to_double(X.lo, X.hi), (double)hp);
+      atomicAdd(&slot->m2, __dmul_rn(v, v));
+    }
     const uint64_t old = atomicAdd((unsigned long long*)&slot->lo, (unsigned long long)c.lo);
     const uint64_t add_hi = c.hi + ((old + c.lo < old) ? 1ull : 0ull);
     if (add_hi < c.hi) atomicOr(&slot->ovf, 1u);
@@ -1528,7 +1556,12 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, A.item_count);
     {
       TimedLaunch tl("k_paths", st);
-      hipLaunchKernelGGL(k_paths, dim3(pblocks), dim3(kSBlock),
+      // the compile-time form needs the class <-,+,<,>>, anchor edges in path
+      // order and every list after the last anchor edge (anchor ranks 0, 1, 2)
+      bool general = exhaustive || !same_class(plan.cls, kSpineClass) || plan.n_anchor != 3 ||
+                     plan.order[0] != 0 || plan.order[1] != 1 || plan.order[2] != 2;
+      for (int q = 0; q < plan.n_pairs; ++q) general = general || plan.pair_seg[q] != 2;
+      hipLaunchKernelGGL(general ? k_paths<true> : k_paths<false>, dim3(pblocks), dim3(kSBlock),
                          sums_bytes(kSWaves, nd, nm) + tree_cache_at(plan.n_gates) +
                              (size_t)kTreeCache * 8,
                          st, A);
@@ -1557,7 +1590,9 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
       }
       {
         TimedLaunch tl("k_listcount_big", st);
-        hipLaunchKernelGGL(k_listcount_big, dim3(64), dim3(kSBlock), sums_bytes(kSWaves, nd, nm),
+        // one thread per item: enough blocks for every CU (blocks with no
+        // item leave at once)
+        hipLaunchKernelGGL(k_listcount_big, dim3(1024), dim3(kSBlock), sums_bytes(kSWaves, nd, nm),
                            st, A);
       }
     }

@@ -361,11 +361,13 @@ def test_weight_overflow(tcb, torch_mod):
     check_sample(tcb, G, Wt, og, ow, [M40], 20000, seed=1)
 
 
-def test_listcount_overflow_flag(tcb, torch_mod):
+def test_listcount_counts_beyond_2e64(tcb, torch_mod):
     """A 16-edge motif (13 lists, the most the descriptor allows) with 32
     edges per list in disjoint increasing time blocks: every draw of one of
-    the 64*64 planted spines has 32^13 = 2^65 chains, so both sides must flag
-    the overflow (and agree on everything else)."""
+    the 64*64 planted spines has 32^13 = 2^65 chains.  Such counts go to the
+    128-bit ListCount pass: cnt is exact (its sum over samples, compared with
+    the oracle's 128-bit arithmetic), the per-sample X saturates at 2^64 - 1,
+    and nothing is flagged."""
     A_, B_, C_, D_ = 0, 1, 2, 3
     ranks = [(D_, A_), (A_, C_), (B_, D_), (D_, C_), (C_, B_), (B_, A_), (A_, D_), (C_, A_),
              (D_, B_), (A_, B_), (B_, C_), (C_, D_), (D_, A_)]
@@ -387,15 +389,21 @@ def test_listcount_overflow_flag(tcb, torch_mod):
     Wt = tcb.tc_path_weights(G, delta)
     ow = og.weights(delta)
     check_weights(Wt, ow, g, og)
-    R, E = check_sample(tcb, G, Wt, og, ow, [motif], 20000, seed=1, per_sample=False)
-    assert E.status == 2 | (1 << 8)  # overflow, naming motif 0
-    # an overflowing motif beside one that does not: the other count stays exact
+    R, E = check_sample(tcb, G, Wt, og, ow, [motif], 20000, seed=1, per_sample=True)
+    assert E.status == 0
+    hits = int(E.hits[0])
+    assert hits > 0 and E.cnt[0] == hits * 32**13
+    assert (E.X[0][E.X[0] != 0] == np.uint64(2**64 - 1)).all()
+    # beside a motif with small counts: both exact
     R, E = check_sample(tcb, G, Wt, og, ow, [motif, M40], 20000, seed=1, per_sample=False)
-    assert E.status == 2 | (1 << 8)
-    assert R.counts()[1] == E.cnt[1] and int(R.hits[1].item()) == int(E.hits[1])
-    assert R.estimate[1].item() == E.est[1]
-    # the same graph with the 4-cycle only: no overflow, full parity
+    assert E.status == 0 and R.counts()[0] == E.cnt[0] > 2**64
+    # the same graph with the 4-cycle only
     check_sample(tcb, G, Wt, og, ow, [M40, motif[:9]], 20000, seed=1, per_sample=True)
+    # importance sampling cannot take a count of 2^64 or more: flagged
+    h = torch_mod.full((g.m,), 2, dtype=torch_mod.int32, device="cuda")
+    Wq = tcb.tc_proposal_weights(G, Wt, h)
+    Rq = tcb.tc_sample_estimate(G, Wq, [motif, M40], 20000, 1)
+    assert (int(Rq.status.item()) & 0xFFFFFFFF) == 2 | (1 << 8)
 
 
 LONG_CASES = {

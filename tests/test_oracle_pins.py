@@ -212,11 +212,20 @@ def test_list_count_blocks_closed_form_and_overflow():
         lists.append(list(range(base, base + s)))
         base += s
     assert oracle.list_count(lists) == (0, math.prod(sizes))
-    big = [list(range(r * 4096, r * 4096 + 2048)) for r in range(6)]  # 2^66 chains
-    assert oracle.list_count(big)[0] == oracle.OR_OVERFLOW
+    # beyond 2^64: counts are 128-bit (2048^6 = 2^66 chains, exactly)
+    big = [list(range(r * 4096, r * 4096 + 2048)) for r in range(6)]
+    assert oracle.list_count(big) == (0, 2048**6)
     ok = [list(range(r * 4096, r * 4096 + 2048)) for r in range(5)] + [list(range(6 * 4096, 6 * 4096 + 511))]
     st, X = oracle.list_count(ok)
     assert st == 0 and X == 2048**5 * 511
+    # and interleaved lists whose chain count passes 2^64: a closed form --
+    # L_r = {r, r + 13, r + 26, ...} (n entries each, 13 lists): a chain picks
+    # one entry per list with strictly increasing times, i.e. block indices
+    # b_1 <= b_2 <= ... <= b_13 in [0, n): C(n + 12, 13)
+    n = 400
+    inter = [[r + 13 * i for i in range(n)] for r in range(13)]
+    st, X = oracle.list_count(inter)
+    assert st == 0 and X == math.comb(n + 12, 13) and X > 2**64
 
 
 def test_fig1_walkthrough_fragments():
