@@ -431,42 +431,12 @@ def cpu_one_thread(g, delta, motifs, k, seed, n_sample):
 def learned_vs_method(tcb, G, Wt, motif, seeds, k_ref, stream):
     """Relative error against C_ref (the method at k_ref samples on its own
     stream) at k = 10^5, 10^6, 10^7 over `seeds` seeds, for the method and
-    for the learned proposal (labels on another stream), plus the time of
-    each part."""
+    for two learned proposals (labels on another stream): the configured one
+    (eps = 0.1, labels y = [X > 0], scores as the network gives them) and a
+    tuned one (eps = 0.01, soft labels min(1, X / 64), scores normalised by
+    their maximum), plus the time of each part."""
     from paper_2409_08975_amd import learned
     out = {"motif": "M4-0", "delta": int(Wt.c.delta), "seeds": seeds}
-    tcb.timing_reset()
-    tcb.timing_enable(True)
-    lp = learned.LearnedProposal(G, Wt, motif, seed=11)
-    _, out["features_ms"] = event_ms(lambda: tcb.tc_edge_features(G, Wt), stream)
-    losses, out["train_ms"] = event_ms(lambda: lp.fit(n_labels=10**6, epochs=8, batch=8192,
-                                                      lr=3e-3, label_cap=64.0), stream)
-    out["train"] = {"labels": 10**6, "epochs": 8, "batch": 8192, "label_cap": 64.0,
-                    "eps": lp.eps, "normalized": lp.normalize,
-                    "loss_per_epoch": [round(float(x), 6) for x in losses.cpu().tolist()],
-                    "label_rate": lp.label_rate}
-    _, out["proposal_ms"] = event_ms(lp.build_proposal, stream)  # inference, h, q-scan
-    out["proposal_status"] = lp.proposal.status()
-    tcb.timing_enable(False)
-    # network kernels: 2 (8*64 + 64*64 + 64) flops per row, both hidden layers on MFMA
-    flop_row = 2 * (8 * 64 + 64 * 64 + 64)
-    kt = {}
-    for name, rows in (("k_mlp_forward", G.m), ("k_mlp_grad", None), ("k_features", G.m)):
-        ms, n = tcb.timing_read(name)
-        if not n:
-            continue
-        e = {"ms_per_launch": ms / n, "launches": n}
-        if name == "k_mlp_forward":
-            tf = flop_row * rows / (ms / n * 1e-3) / 1e12
-            e.update({"flop_per_row": flop_row, "rows": rows, "achieved_TFLOPs": tf,
-                      "frac_of_bf16_dense_peak": tf / BF16_PEAK_TFLOPS})
-        if name == "k_mlp_grad":
-            # forward plus backward: about three times the forward flops per row
-            e["rows_per_launch"] = 8192
-            e["achieved_TFLOPs"] = 3 * flop_row * 8192 / (ms / n * 1e-3) / 1e12
-        kt[name] = e
-    tcb.timing_reset()
-    out["kernels"] = kt
     ref, t_ref = event_ms(lambda: tcb.tc_sample_estimate(G, Wt, [motif], int(k_ref), 1,
                                                          stream_id=0x52454600, moments=True),
                           stream)
@@ -477,48 +447,126 @@ def learned_vs_method(tcb, G, Wt, motif, seeds, k_ref, stream):
     out["C_ref_rel_stderr"] = mref.stderr / C if C else None
     out["k_ref"] = int(k_ref)
     out["ref_ms"] = t_ref
-    mp, mi = lp.pilot(10**7, 0x5EED)
-    out["variance_ratio"] = mp.var / mi.var if mi.var > 0 else None
-    rows = []
+    # the method's errors and times, shared by both comparisons
+    method_rows = {}
     for k in (10**5, 10**6, 10**7):
-        ep, el, tp, tl = [], [], 0.0, 0.0
+        ep, tp = [], 0.0
         for sd in range(1, seeds + 1):
             r, t = event_ms(lambda: tcb.tc_sample_estimate(G, Wt, [motif], k, sd, stream_id=1),
                             stream)
             ep.append(float(r.estimate[0].item()))
             tp += t
-            r, t = event_ms(lambda: tcb.tc_sample_estimate(G, lp.proposal, [motif], k, sd,
-                                                           stream_id=2), stream)
-            el.append(float(r.estimate[0].item()))
-            tl += t
-        ep, el = np.array(ep), np.array(el)
-        rows.append({"k": k,
-                     "rms_rel_err_method": float(np.sqrt(np.mean((ep - C) ** 2)) / C),
-                     "rms_rel_err_learned": float(np.sqrt(np.mean((el - C) ** 2)) / C),
-                     "ms_per_estimate_method": tp / seeds,
-                     "ms_per_estimate_learned": tl / seeds})
-    out["by_k"] = rows
-    # Equal error: the learned proposal needs k / ratio samples for the error
-    # of the method at k.  Its wall time counts features, inference, h and
-    # the q-scan (training is reported apart), plus sampling at k / ratio,
-    # from the per-sample time measured at each k.
-    ratio = out["variance_ratio"]
-    if ratio:
-        fixed = out["features_ms"] + out["proposal_ms"]
-        eq = []
-        for row in rows:
-            k = row["k"]
-            t_m = row["ms_per_estimate_method"]
-            t_l = fixed + row["ms_per_estimate_learned"] / ratio
-            eq.append({"k_method": k, "k_learned": k / ratio, "wall_ms_method": t_m,
-                       "wall_ms_learned": t_l, "learned_faster": t_l < t_m})
-        big = rows[-1]
-        per_m = big["ms_per_estimate_method"] / big["k"]
-        per_l = big["ms_per_estimate_learned"] / big["k"] / ratio
-        out["equal_error"] = {
-            "samples_factor": ratio, "fixed_ms": fixed, "by_k": eq,
-            "break_even_k": fixed / (per_m - per_l) if per_m > per_l else None}
+        ep = np.array(ep)
+        method_rows[k] = (float(np.sqrt(np.mean((ep - C) ** 2)) / C), tp / seeds)
+    variants = {
+        "configured": dict(eps=0.1, normalize=False, label_cap=0.0),
+        "tuned": dict(eps=0.01, normalize=True, label_cap=64.0),
+    }
+    for name, vp in variants.items():
+        v = {}
+        tcb.timing_reset()
+        tcb.timing_enable(True)
+        lp = learned.LearnedProposal(G, Wt, motif, eps=vp["eps"], seed=11,
+                                     normalize=vp["normalize"])
+        _, v["features_ms"] = event_ms(lambda: tcb.tc_edge_features(G, Wt), stream)
+        losses, v["train_ms"] = event_ms(
+            lambda: lp.fit(n_labels=10**6, epochs=8, batch=8192, lr=3e-3,
+                           label_cap=vp["label_cap"]), stream)
+        v["train"] = {"labels": 10**6, "epochs": 8, "batch": 8192,
+                      "label": "y = [X > 0]" if vp["label_cap"] == 0 else
+                               f"min(1, X / {vp['label_cap']:g})",
+                      "eps": vp["eps"], "normalized": vp["normalize"],
+                      "loss_per_epoch": [round(float(x), 6) for x in losses.cpu().tolist()],
+                      "label_rate": lp.label_rate}
+        _, v["proposal_ms"] = event_ms(lp.build_proposal, stream)  # inference, h, q-scan
+        v["proposal_status"] = lp.proposal.status()
+        tcb.timing_enable(False)
+        # network kernels: 2 (8*64 + 64*64 + 64) flops per row, both hidden layers on MFMA
+        flop_row = 2 * (8 * 64 + 64 * 64 + 64)
+        kt = {}
+        for kname, rows in (("k_mlp_forward", G.m), ("k_mlp_grad", None), ("k_features", G.m)):
+            ms, n = tcb.timing_read(kname)
+            if not n:
+                continue
+            e = {"ms_per_launch": ms / n, "launches": n}
+            if kname == "k_mlp_forward":
+                tf = flop_row * rows / (ms / n * 1e-3) / 1e12
+                e.update({"flop_per_row": flop_row, "rows": rows, "achieved_TFLOPs": tf,
+                          "frac_of_bf16_dense_peak": tf / BF16_PEAK_TFLOPS})
+            if kname == "k_mlp_grad":
+                # forward plus backward: about three times the forward flops per row
+                e["rows_per_launch"] = 8192
+                e["achieved_TFLOPs"] = 3 * flop_row * 8192 / (ms / n * 1e-3) / 1e12
+            kt[kname] = e
+        tcb.timing_reset()
+        v["kernels"] = kt
+        mp, mi = lp.pilot(10**7, 0x5EED)
+        v["variance_ratio"] = mp.var / mi.var if mi.var > 0 else None
+        rows = []
+        for k in (10**5, 10**6, 10**7):
+            el, tl = [], 0.0
+            for sd in range(1, seeds + 1):
+                r, t = event_ms(lambda: tcb.tc_sample_estimate(G, lp.proposal, [motif], k, sd,
+                                                               stream_id=2), stream)
+                el.append(float(r.estimate[0].item()))
+                tl += t
+            el = np.array(el)
+            rows.append({"k": k, "rms_rel_err_method": method_rows[k][0],
+                         "rms_rel_err_learned": float(np.sqrt(np.mean((el - C) ** 2)) / C),
+                         "ms_per_estimate_method": method_rows[k][1],
+                         "ms_per_estimate_learned": tl / seeds})
+        v["by_k"] = rows
+        # Equal error: the learned proposal needs k / ratio samples for the
+        # error of the method at k.  Its wall time counts features,
+        # inference, h and the q-scan (training is reported apart), plus
+        # sampling at k / ratio, from the per-sample time measured at each k.
+        ratio = v["variance_ratio"]
+        if ratio:
+            fixed = v["features_ms"] + v["proposal_ms"]
+            eq = []
+            for row in rows:
+                k = row["k"]
+                t_m = row["ms_per_estimate_method"]
+                t_l = fixed + row["ms_per_estimate_learned"] / ratio
+                eq.append({"k_method": k, "k_learned": k / ratio, "wall_ms_method": t_m,
+                           "wall_ms_learned": t_l, "learned_faster": t_l < t_m})
+            big = rows[-1]
+            per_m = big["ms_per_estimate_method"] / big["k"]
+            per_l = big["ms_per_estimate_learned"] / big["k"] / ratio
+            v["equal_error"] = {
+                "samples_factor": ratio, "fixed_ms": fixed, "by_k": eq,
+                "break_even_k": fixed / (per_m - per_l) if per_m > per_l else None}
+        out[name] = v
+        del lp
+    out["variance_ratio"] = out["tuned"]["variance_ratio"]
     return out
+
+
+def hbm_probe(dev, nbytes=4 << 30):
+    """Achievable HBM bandwidth on this GPU: a device-to-device copy of
+    4 GiB (streaming read and write) and a gather of 8-byte words at random
+    positions of a 4 GiB array (one line fetched per word), both timed with
+    HIP events; the rates against which the kernels' figures can be read."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.int64, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1)
+    stream = torch.cuda.current_stream()
+    b.copy_(a)
+    _, t_copy = event_ms(lambda: b.copy_(a), stream)
+    n = 1 << 26
+    idx = torch.randint(0, a.numel(), (n,), device=dev, generator=torch.Generator(dev).manual_seed(5))
+    out = torch.empty(n, dtype=torch.int64, device=dev)
+    torch.index_select(a, 0, idx, out=out)
+    _, t_gather = event_ms(lambda: torch.index_select(a, 0, idx, out=out), stream)
+    res = {"copy_GBs": 2 * nbytes / (t_copy * 1e-3) / 1e9,
+           "copy_bytes": 2 * nbytes, "copy_ms": t_copy,
+           "random_gather_words_per_s": n / (t_gather * 1e-3),
+           "random_gather_useful_GBs": (8 + 8 + 8) * n / (t_gather * 1e-3) / 1e9,
+           "random_gather_ms": t_gather, "random_gather_words": n}
+    del a, b, idx, out
+    torch.cuda.empty_cache()
+    return res
 
 
 def run_medium_like(args, tcb, sg, which, stream, dev, with_learned):
@@ -548,8 +596,9 @@ def run_medium_like(args, tcb, sg, which, stream, dev, with_learned):
         t0 = time.time()
         out["learned_vs_method"] = learned_vs_method(tcb, G, Ws[0], sg.MOTIFS["M4-0"],
                                                      args.learned_seeds, args.k_ref, stream)
+        lv = out["learned_vs_method"]
         log(f"[bench] learned vs method in {time.time() - t0:.1f}s: variance ratio "
-            f"{out['learned_vs_method']['variance_ratio']}")
+            f"configured {lv['configured']['variance_ratio']}, tuned {lv['tuned']['variance_ratio']}")
     return out, g
 
 
@@ -764,6 +813,9 @@ def main():
     del G, Ws, outs, res
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+    out["hbm_probe"] = hbm_probe(dev)
+    log(f"[bench] HBM probe: copy {out['hbm_probe']['copy_GBs']:.0f} GB/s, random 8-byte "
+        f"gather {out['hbm_probe']['random_gather_words_per_s']:.3g} words/s")
     if not args.no_extras:
         extra, gm = run_medium_like(args, tcb, sg, "medium", stream, dev,
                                     with_learned=not args.no_learned)

@@ -253,3 +253,46 @@ def test_trained_proposal_reduces_variance(tcb, torch_mod):
     assert mi.var < mp.var
     z = (mp.estimate - mi.estimate) / math.sqrt(mp.stderr ** 2 + mi.stderr ** 2)
     assert abs(z) < 5.0
+
+
+@pytest.fixture(scope="module")
+def medium_graph(tcb, torch_mod):
+    """The learned-proposal workload: the medium graph (10^6 vertices,
+    2*10^7 edges), delta = 86,400."""
+    torch = torch_mod
+    g = sg.gen_medium()
+    G = tcb.tc_build_graph(g.n, *[torch.from_numpy(a).cuda() for a in (g.src, g.dst, g.t)],
+                           check=True)
+    Wt = tcb.tc_path_weights(G, 86400)
+    return G, Wt
+
+
+@pytest.mark.parametrize("variant", ["configured", "tuned"])
+def test_learned_proposal_on_medium_graph(tcb, medium_graph, variant):
+    """On the medium graph with 10^6 training labels: the configured
+    proposal (eps = 0.1, labels y = [X > 0]) and the tuned one (eps = 0.01,
+    soft labels, normalised scores).  Each estimate agrees with the method's
+    within their standard errors (unbiasedness), and each lowers the
+    per-sample variance (measured ratios 1.034 for the configured proposal,
+    1.346 for the tuned one; asserted: above 1.0 and above 1.2 -- the runs
+    are deterministic, the margins allow for changes of launch shape)."""
+    from paper_2409_08975_amd import learned
+    G, Wt = medium_graph
+    if variant == "configured":
+        lp = learned.LearnedProposal(G, Wt, M40, eps=0.1, seed=11, normalize=False)
+        losses = lp.fit(n_labels=10**6, epochs=8, batch=8192, lr=3e-3, label_cap=0.0)
+        margin = 1.0
+    else:
+        lp = learned.LearnedProposal(G, Wt, M40, eps=0.01, seed=11, normalize=True)
+        losses = lp.fit(n_labels=10**6, epochs=8, batch=8192, lr=3e-3, label_cap=64.0)
+        margin = 1.2
+    losses = losses.cpu().numpy()
+    assert np.all(np.isfinite(losses))
+    lp.build_proposal()
+    assert lp.proposal.status() == 0
+    mp, mi = lp.pilot(10**7, 0x5EED)
+    ratio = mp.var / mi.var
+    print(f"{variant}: variance ratio (method / learned) = {ratio:.3f}")
+    z = (mp.estimate - mi.estimate) / math.sqrt(mp.stderr ** 2 + mi.stderr ** 2)
+    assert abs(z) < 5.0
+    assert ratio > margin
