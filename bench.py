@@ -5,7 +5,8 @@ graph (5*10^7 vertices, 3*10^8 edges, Zipf(1.9) endpoints with hubs over 10^6
 edges, Geometric(0.5) repeats per pair, times uniform over seven years), the
 4-cycle motif M4-0, delta in {3,600; 86,400} and k = 10^8 samples per delta.
 A step is one pass of the whole hot path: adjacency build (tc_build_graph),
-weights and scan for both deltas (tc_path_weights), and sampling with closure
+weights and scan for both deltas in one call (tc_path_weights_batch), and
+sampling with closure
 and reduction for both deltas in one batched launch sequence
 (tc_batch_estimate).  The edge arrays are resident in HBM before the timed
 region.  `value` is samples per second of the whole step (2 * 10^8 samples
@@ -43,7 +44,7 @@ KERNEL_SRC = {"k_paths": "tc_sample.hip", "k_listcount_reg": "tc_sample.hip",
               "k_windows": "tc_weights.hip", "k_scan_apply": "tc_weights.hip",
               "k_radix_scatter": "tc_build.hip"}
 # the kernels each timed span covers, for counter-based traffic per span
-SPAN_KERNELS = {"k_windows": ["k_mp_split4", "k_mp_rank", "k_combine"]}
+SPAN_KERNELS = {"k_windows": ["k_mp_split", "k_mp_rank", "k_combine"]}
 PMC_FILES = {"bitcoin": os.path.join(ROOT, "profiles", "pmc_traffic_bitcoin.txt"),
              "medium": os.path.join(ROOT, "profiles", "pmc_traffic_medium.txt")}
 # stages of a step -> kernels whose counter traffic makes up the stage
@@ -51,7 +52,7 @@ STAGE_KERNELS = {
     "build": ["k_init_build", "k_validate", "k_plan", "k_trange", "k_hash_clear", "k_rec_init",
               "k_radix_hist", "k_col_sum", "k_col_scan", "k_col_apply", "k_radix_scatter",
               "k_rec_xform", "k_emit", "k_hash_insert"],
-    "weights": ["k_mp_split4", "k_mp_rank", "k_combine", "k_scan_tiles", "k_scan_apply",
+    "weights": ["k_mp_split", "k_mp_rank", "k_combine", "k_scan_tiles", "k_scan_apply",
                 "k_tree"],
     "sample": ["k_zero_result", "k_store_ptrs", "k_zero_counters", "k_paths", "k_listcount_reg",
                "k_listcount_lds", "k_listcount_wide", "k_listcount_big", "k_finalize"],
@@ -89,23 +90,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_alg_bytes(kernel, m, units):
+def kernel_alg_bytes(kernel, m, units, nd=1):
     """Algorithmic bytes of one launch: a per-unit figure times the units the
     launch processes.  Data-dependent searches inside adjacency lists and
     pair runs are not counted, so these are lower bounds.
       k_paths          per sample: ceil(log2(m+1)) probes of S (8 B each), the
                        centre edge with its window metadata (32 B), the two end
                        edges (16 B each)
-      k_windows        per edge: read the (vertex, time) keys of both CSRs
-                       (24 B), write lo_in, a, lo_out, b (16 B) and the 32-byte
-                       path record
+      k_windows        per edge of a call over nd deltas: read the (vertex,
+                       time) keys of both CSRs once (24 B), and per delta write
+                       lo_in, a, lo_out, b (16 B) and the 32-byte path record
       k_scan_apply     per edge: read a, b (8 B), write S (8 B)
       k_radix_scatter  per element and pass: read and write a 16-byte edge
                        record (32 B)"""
     if kernel == "k_paths":
         per = 8 * math.ceil(math.log2(m + 1)) + 32 + 2 * 16
     elif kernel == "k_windows":
-        per = 24 + 16 + 32
+        per = 24 + (16 + 32) * nd
     elif kernel == "k_scan_apply":
         per = 16
     elif kernel == "k_radix_scatter":
@@ -115,15 +116,15 @@ def kernel_alg_bytes(kernel, m, units):
     return per * units, per
 
 
-def stage_alg_bytes(stage, m, k_total):
+def stage_alg_bytes(stage, m, k_total, nd=1):
     """Algorithmic bytes of a stage per step (the floors of the hot-path
     scope): build 64 B per edge (input 16 B + three 16-byte orders), weights
-    40 B per edge and delta (in and out keys 16 B, S 8 B, window metadata
-    16 B), sampling per sample as k_paths above."""
+    per edge the in and out keys once (16 B) and per delta S (8 B) and the
+    window metadata (16 B), sampling per sample as k_paths above."""
     if stage == "build":
         return 64 * m
     if stage == "weights":
-        return 40 * m
+        return (16 + 24 * nd) * m
     if stage == "sample":
         return (8 * math.ceil(math.log2(m + 1)) + 64) * k_total
     return None
@@ -226,8 +227,9 @@ def cpu_threads():
 
 # ------------------------------------------------------------ step runs -----
 def run_steps(tcb, g, deltas, motifs, k, seed, steps, warmup, stream, dev, label):
-    """Time `steps` whole-path steps (build, weights per delta, sampling of
-    every delta in one batched sequence).  Returns a dict of figures."""
+    """Time `steps` whole-path steps (build, the weights of every delta in one
+    batched call, sampling of every delta in one batched sequence).  Returns
+    a dict of figures."""
     import torch
     src = torch.from_numpy(g.src).to(dev)
     dst = torch.from_numpy(g.dst).to(dev)
@@ -239,16 +241,14 @@ def run_steps(tcb, g, deltas, motifs, k, seed, steps, warmup, stream, dev, label
     outs = [tcb.new_result(nm, k, dev) for _ in deltas]
 
     def step():
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(nd + 3)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ev[0].record(stream)
         G = tcb.tc_build_graph(g.n, src, dst, tt)
         ev[1].record(stream)
-        Ws = []
-        for i, d in enumerate(deltas):
-            Ws.append(tcb.tc_path_weights(G, d))
-            ev[2 + i].record(stream)
+        Ws = tcb.tc_path_weights_batch(G, deltas)
+        ev[2].record(stream)
         tcb.tc_batch_estimate(G, Ws, motifs, k, seed, outs=outs, workspace=ws_s)
-        ev[nd + 2].record(stream)
+        ev[3].record(stream)
         return G, Ws, ev
 
     for i in range(warmup):
@@ -286,18 +286,18 @@ def run_steps(tcb, g, deltas, motifs, k, seed, steps, warmup, stream, dev, label
     for o in outs:
         o.check()
     build = np.mean([e[0].elapsed_time(e[1]) for e in evs])
-    wts = [float(np.mean([e[1 + i].elapsed_time(e[2 + i]) for e in evs])) for i in range(nd)]
-    samp = np.mean([e[nd + 1].elapsed_time(e[nd + 2]) for e in evs])
+    wts = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    samp = np.mean([e[2].elapsed_time(e[3]) for e in evs])
     ms_per_step = t_total * 1000.0 / steps
     log(f"[bench] {label}: {steps} steps, {ms_per_step:.3f} ms/step; build {build:.3f} ms, "
-        f"weights {', '.join(f'{x:.3f}' for x in wts)} ms, sampling {samp:.3f} ms")
+        f"weights ({nd} deltas) {wts:.3f} ms, sampling {samp:.3f} ms")
     res = {"ms_per_step": ms_per_step, "build_ms": float(build), "weights_ms": wts,
-           "sample_ms": float(samp), "ktime": ktime, "G": G, "Ws": Ws, "outs": outs,
+           "sample_ms": float(samp), "ktime": ktime, "G": G, "Ws": Ws, "outs": outs, "nd": nd,
            "tensors": (src, dst, tt)}
     return res
 
 
-def kernel_table(ktime, m, k_total, steps, workload):
+def kernel_table(ktime, m, k_total, steps, workload, nd=1):
     kernels = {}
     for kname, (ms, n) in ktime.items():
         per_launch_ms = ms / n
@@ -309,7 +309,7 @@ def kernel_table(ktime, m, k_total, steps, workload):
         elif kname in ("k_windows", "k_scan_apply", "k_radix_scatter"):
             u = m
         if u is not None:
-            alg, per = kernel_alg_bytes(kname, m, u)
+            alg, per = kernel_alg_bytes(kname, m, u, nd if kname == "k_windows" else 1)
             gbs = alg / (per_launch_ms * 1e-3) / 1e9
             entry.update({"alg_bytes_per_unit": per, "alg_bytes_per_launch": alg,
                           "achieved_GBs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS})
@@ -339,18 +339,15 @@ def roofline_of(kernels):
 
 def stage_table(res, m, k_total, workload):
     out = {}
-    spans = [("build", res["build_ms"])] + \
-        [(f"weights[{i}]", w) for i, w in enumerate(res["weights_ms"])] + \
-        [("sample", res["sample_ms"])]
+    spans = [("build", res["build_ms"]), ("weights", res["weights_ms"]),
+             ("sample", res["sample_ms"])]
     for name, ms in spans:
-        base = name.split("[")[0]
-        alg = stage_alg_bytes(base, m, k_total)
+        base = name
+        alg = stage_alg_bytes(base, m, k_total, res["nd"])
         e = {"ms": ms, "alg_bytes": alg, "alg_GBs": alg / (ms * 1e-3) / 1e9,
              "alg_frac_of_hbm_peak": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         tr = stage_traffic(workload, base)
         if tr is not None:
-            if base == "weights":
-                tr /= max(1, len(res["weights_ms"]))
             e["hbm_bytes"] = tr
             e["hbm_GBs"] = tr / (ms * 1e-3) / 1e9
         out[name] = e
@@ -584,7 +581,7 @@ def run_medium_like(args, tcb, sg, which, stream, dev, with_learned):
     out = {
         "workload": f"{g.name}: n={g.n} m={g.m} delta={delta} k={k} motifs={','.join(names)}",
         "ms_per_step": res["ms_per_step"], "samples_per_s": k / (res["ms_per_step"] * 1e-3),
-        "stages_ms": {"build": res["build_ms"], "weights": res["weights_ms"][0],
+        "stages_ms": {"build": res["build_ms"], "weights": res["weights_ms"],
                       "sample": res["sample_ms"]},
         "stages": stage_table(res, g.m, k, which),
         "W": Ws[0].total(), "cnt": [str(c) for c in outs[0].counts()],
@@ -630,12 +627,8 @@ def run_batched(args):
     nd, nm = len(deltas), len(motifs)
     G, t_build = event_ms(lambda: tcb.tc_build_graph(n, src, dst, tt), stream)
     G.check()
-    Ws, t_w = [], []
-    for d in deltas:
-        W, t = event_ms(lambda: tcb.tc_path_weights(G, d), stream)
-        Ws.append(W)
-        t_w.append(t)
-    log(f"[bench] eager build {t_build:.1f} ms, weights {', '.join(f'{x:.1f}' for x in t_w)} ms")
+    Ws, t_w = event_ms(lambda: tcb.tc_path_weights_batch(G, deltas), stream)
+    log(f"[bench] eager build {t_build:.1f} ms, weights of {nd} deltas {t_w:.1f} ms")
     best, probe_ms = tcb.tc_autotune(G, Ws, motifs, 2**22, seed=7)
     log(f"[bench] autotuned {best.as_dict()} ({probe_ms:.2f} ms per 2^22-sample probe)")
     ws = torch.empty(tcb.batch_workspace_bytes(k, nd, nm), dtype=torch.uint8, device=dev)
@@ -649,15 +642,14 @@ def run_batched(args):
         raise tcb.TCDeviceError(max(ref_status), "batched reference")
     # the whole path in one graph, on workspaces allocated beforehand
     ws_g = torch.empty(tcb.graph_workspace_bytes(n, m), dtype=torch.uint8, device=dev)
-    ws_w = [torch.empty(tcb.weights_workspace_bytes(m), dtype=torch.uint8, device=dev)
-            for _ in deltas]
+    ws_w = torch.empty(tcb.weights_batch_workspace_bytes(m, nd), dtype=torch.uint8, device=dev)
     outs = [tcb.new_result(nm, k, dev) for _ in deltas]
     side = torch.cuda.Stream()
     side.wait_stream(stream)
     cg = torch.cuda.CUDAGraph()
     with torch.cuda.graph(cg, stream=side):
         G2 = tcb.tc_build_graph(n, src, dst, tt, workspace=ws_g)
-        W2 = [tcb.tc_path_weights(G2, d, workspace=w) for d, w in zip(deltas, ws_w)]
+        W2 = tcb.tc_path_weights_batch(G2, deltas, workspace=ws_w)
         tcb.tc_batch_estimate(G2, W2, motifs, k, seed, tuning=best, outs=outs, workspace=ws)
     torch.cuda.synchronize()
     for _ in range(args.warmup):
@@ -709,7 +701,7 @@ def run_batched(args):
                    "n": n, "m": m, "deltas": deltas, "k_per_delta": k,
                    "motifs": sg.SIX_MOTIFS, "seed": seed},
         "tuning": best.as_dict(), "autotune_probe_ms": probe_ms,
-        "eager_build_ms": t_build, "eager_weights_ms": dict(zip(map(str, deltas), t_w)),
+        "eager_build_ms": t_build, "eager_weights_ms": t_w,
         "W": {str(d): W.total() for d, W in zip(deltas, Ws)},
         "estimate": {str(d): e for d, e in zip(deltas, ref_est)},
         "overflowed_motifs": {str(d): [sg.SIX_MOTIFS[j] for j in range(nm) if st & (1 << (8 + j))]
@@ -782,12 +774,12 @@ def main():
     if args.profile_run:
         res = run_steps(tcb, g, deltas, motifs, k, seed, 1, 0, stream, dev, "bitcoin profile")
         print(json.dumps({"profile_run": "bitcoin", "ms_per_step": res["ms_per_step"],
-                          "weights_calls": len(deltas), "profile_steps": 1}), flush=True)
+                          "weights_calls": 1, "profile_steps": 1}), flush=True)
         return
     res = run_steps(tcb, g, deltas, motifs, k, seed, args.steps, args.warmup, stream, dev,
                     "bitcoin")
     k_total = k * len(deltas)
-    kernels = kernel_table(res["ktime"], g.m, k_total, args.steps, "bitcoin")
+    kernels = kernel_table(res["ktime"], g.m, k_total, args.steps, "bitcoin", len(deltas))
     G, Ws, outs = res["G"], res["Ws"], res["outs"]
     out = {
         "metric": "sampled temporal 3-paths/sec and rel. error vs exact at fixed k; "
@@ -802,7 +794,7 @@ def main():
                    "seed": seed},
         "roofline": roofline_of(kernels),
         "stages": stage_table(res, g.m, k_total, "bitcoin"),
-        "edges_per_s_weights": [g.m / (t * 1e-3) for t in res["weights_ms"]],
+        "edge_deltas_per_s_weights": len(deltas) * g.m / (res["weights_ms"] * 1e-3),
         "sample_stage_samples_per_s": k_total / (res["sample_ms"] * 1e-3),
         "W": {str(d): W.total() for d, W in zip(deltas, Ws)},
         "cnt": {str(d): [str(c) for c in o.counts()] for d, o in zip(deltas, outs)},

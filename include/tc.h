@@ -277,6 +277,22 @@ tc_status tc_path_weights(const tc_graph *g, int64_t delta, void *ws, size_t ws_
 tc_status tc_path_weights_class(const tc_graph *g, int64_t delta, const tc_class *cls, void *ws,
                                 size_t ws_bytes, void *stream, tc_weights *w);
 
+/* Workspace size in bytes for tc_path_weights_batch with n_deltas deltas
+ * (1..8) on a graph with m edges.  Errors: TC_E_ARG. */
+tc_status tc_weights_batch_workspace_bytes(int64_t m, int32_t n_deltas, size_t *bytes);
+
+/* Preprocess for n_deltas deltas (host array, 1..8, each 0..2^62) of one
+ * anchor class (cls NULL: {IN, 0, OUT, 1}) in one launch sequence.  w (host
+ * array of n_deltas) receives the weights of deltas[i] in w[i], equal word
+ * for word to what tc_path_weights_class gives for that delta; all of them
+ * live in ws, which must outlive their use.  Each side's window bound at the
+ * centre time does not depend on delta and is ranked once; the side-3
+ * windows of all deltas reach the out-CSR order in one scatter and one
+ * gather.  Enqueue only.  Errors: TC_E_ARG, TC_E_WORKSPACE, TC_E_HIP. */
+tc_status tc_path_weights_batch(const tc_graph *g, const int64_t *deltas, int32_t n_deltas,
+                                const tc_class *cls, void *ws, size_t ws_bytes, void *stream,
+                                tc_weights *w);
+
 /* Workspace size in bytes for tc_sample_estimate with k samples and n_motifs
  * motifs (per-sample pair windows and the closure work queue of one chunk of
  * at most 2^22 samples).  Errors: TC_E_ARG (null, k < 1, n_motifs not in

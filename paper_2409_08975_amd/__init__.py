@@ -30,6 +30,7 @@ _STATUS_NAMES = {0: "TC_OK", -1: "TC_E_ARG", -2: "TC_E_RANGE", -3: "TC_E_OVERFLO
 
 EXPORTED = ["tc_version", "tc_graph_workspace_bytes", "tc_build_graph",
             "tc_weights_workspace_bytes", "tc_path_weights", "tc_path_weights_class",
+            "tc_weights_batch_workspace_bytes", "tc_path_weights_batch",
             "tc_motif_anchor", "tc_exhaustive_count", "tc_sample_workspace_bytes",
             "tc_sample_estimate", "tc_sample_estimate_noalloc", "tc_batch_workspace_bytes", "tc_batch_estimate",
             "tc_autotune", "tc_features_workspace_bytes", "tc_edge_features", "tc_mlp_forward", "tc_mlp_workspace_bytes",
@@ -139,6 +140,9 @@ def lib():
         L.tc_path_weights_class.argtypes = [ctypes.POINTER(tc_graph), I64,
                                             ctypes.POINTER(tc_class), _P, SZ, _P,
                                             ctypes.POINTER(tc_weights)]
+        L.tc_weights_batch_workspace_bytes.argtypes = [I64, I32, ctypes.POINTER(SZ)]
+        L.tc_path_weights_batch.argtypes = [ctypes.POINTER(tc_graph), _P, I32,
+                                            ctypes.POINTER(tc_class), _P, SZ, _P, _P]
         L.tc_motif_anchor.argtypes = [ctypes.POINTER(tc_motif), ctypes.POINTER(tc_class),
                                       ctypes.POINTER(I32), ctypes.POINTER(I32)]
         L.tc_exhaustive_count.argtypes = [ctypes.POINTER(tc_graph), ctypes.POINTER(tc_weights),
@@ -341,6 +345,13 @@ def weights_workspace_bytes(m: int) -> int:
     return b.value
 
 
+def weights_batch_workspace_bytes(m: int, n_deltas: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().tc_weights_batch_workspace_bytes(m, int(n_deltas), ctypes.byref(b)),
+           "tc_weights_batch_workspace_bytes")
+    return b.value
+
+
 def sample_workspace_bytes(k: int, n_motifs: int) -> int:
     b = ctypes.c_size_t(0)
     _check(lib().tc_sample_workspace_bytes(int(k), int(n_motifs), ctypes.byref(b)),
@@ -417,6 +428,32 @@ def tc_path_weights(graph: Graph, delta: int, stream=None,
                                            _ptr(ws), nbytes, _stream(stream), ctypes.byref(w)),
                "tc_path_weights_class")
     return Weights(w, ws, graph)
+
+
+def tc_path_weights_batch(graph: Graph, deltas, stream=None,
+                          workspace: torch.Tensor | None = None, cls=None) -> list:
+    """Preprocess for several deltas of one anchor class in one launch
+    sequence; returns one Weights per delta (all in one workspace)."""
+    nd = len(deltas)
+    nbytes = weights_batch_workspace_bytes(graph.m, nd)
+    if workspace is not None:
+        assert workspace.numel() >= nbytes
+        ws = workspace
+    else:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=graph.ws.device)
+    ds = (ctypes.c_int64 * nd)(*[int(d) for d in deltas])
+    ws_arr = (tc_weights * nd)()
+    c = None
+    if cls is not None:
+        c = cls if isinstance(cls, tc_class) else tc_class(*cls)
+    _on_stream(stream, ws)
+    _check(lib().tc_path_weights_batch(ctypes.byref(graph.c), ds, nd,
+                                       ctypes.byref(c) if c is not None else None, _ptr(ws),
+                                       nbytes, _stream(stream), ws_arr), "tc_path_weights_batch")
+    out = []
+    for i in range(nd):
+        out.append(Weights(tc_weights.from_buffer_copy(ws_arr[i]), ws, graph))
+    return out
 
 
 def tc_motif_anchor(edges, nv: int | None = None):

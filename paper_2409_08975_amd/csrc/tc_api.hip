@@ -170,6 +170,11 @@ tc_status tc_build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t
   return tc::build_graph(n, m, src, dst, t, ws, ws_bytes, (hipStream_t)stream, g);
 }
 
+static bool class_ok(const tc_class* cls) {
+  return cls->mode1 <= TC_SIDE_OUT && cls->mode3 <= TC_SIDE_OUT && cls->after1 <= 1 &&
+         cls->after3 <= 1 && !(cls->mode1 == TC_SIDE_NONE && cls->mode3 == TC_SIDE_NONE);
+}
+
 tc_status tc_weights_workspace_bytes(int64_t m, size_t* bytes) {
   if (!bytes || m < 0 || m >= ((int64_t)1 << 31)) return TC_E_ARG;
   *bytes = tc::weights_workspace_bytes(m);
@@ -187,10 +192,27 @@ tc_status tc_path_weights_class(const tc_graph* g, int64_t delta, const tc_class
                                 size_t ws_bytes, void* stream, tc_weights* w) {
   if (!g || !w || !ws || !cls) return TC_E_ARG;
   if (delta < 0 || delta > ((int64_t)1 << 62)) return TC_E_ARG;
-  if (cls->mode1 > TC_SIDE_OUT || cls->mode3 > TC_SIDE_OUT || cls->after1 > 1 ||
-      cls->after3 > 1 || (cls->mode1 == TC_SIDE_NONE && cls->mode3 == TC_SIDE_NONE))
-    return TC_E_ARG;
+  if (!class_ok(cls)) return TC_E_ARG;
   return tc::path_weights(g, delta, *cls, ws, ws_bytes, (hipStream_t)stream, w);
+}
+
+tc_status tc_weights_batch_workspace_bytes(int64_t m, int32_t n_deltas, size_t* bytes) {
+  if (!bytes || m < 0 || m >= ((int64_t)1 << 31) || n_deltas < 1 || n_deltas > tc::kMaxDeltas)
+    return TC_E_ARG;
+  *bytes = tc::weights_batch_workspace_bytes(m, n_deltas);
+  return TC_OK;
+}
+
+tc_status tc_path_weights_batch(const tc_graph* g, const int64_t* deltas, int32_t n_deltas,
+                                const tc_class* cls, void* ws, size_t ws_bytes, void* stream,
+                                tc_weights* w) {
+  if (!g || !deltas || !w || !ws) return TC_E_ARG;
+  if (n_deltas < 1 || n_deltas > tc::kMaxDeltas) return TC_E_ARG;
+  for (int i = 0; i < n_deltas; ++i)
+    if (deltas[i] < 0 || deltas[i] > ((int64_t)1 << 62)) return TC_E_ARG;
+  if (cls && !class_ok(cls)) return TC_E_ARG;
+  return tc::path_weights_batch(g, deltas, n_deltas, cls ? *cls : tc::kSpineClass, ws, ws_bytes,
+                                (hipStream_t)stream, w);
 }
 
 tc_status tc_motif_anchor(const tc_motif* motif, tc_class* cls, int32_t* n_anchor,

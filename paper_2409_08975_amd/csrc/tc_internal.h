@@ -24,9 +24,18 @@ struct STree {
 };
 STree stree_layout(int64_t m);
 
+// Several deltas share one weights or sampling launch sequence.
+constexpr int kMaxDeltas = 8;
+
 size_t weights_workspace_bytes(int64_t m);
 tc_status path_weights(const tc_graph* g, int64_t delta, const tc_class& cls, void* ws,
                        size_t ws_bytes, hipStream_t st, tc_weights* w);
+// nd (1..kMaxDeltas) deltas of one class in one launch sequence; w[i] is
+// what path_weights gives for deltas[i]
+size_t weights_batch_workspace_bytes(int64_t m, int nd);
+tc_status path_weights_batch(const tc_graph* g, const int64_t* deltas, int nd,
+                             const tc_class& cls, void* ws, size_t ws_bytes, hipStream_t st,
+                             tc_weights* w);
 
 // Compiled form of a batch of motifs that share the anchor's class, its
 // number of edges and their rank order.  phi = (x, u, v, y) are the vertex
@@ -74,7 +83,6 @@ extern const tc_class kSpineClass;
 tc_status compile_motifs(const tc_motif* motifs, int32_t n_motifs, MotifPlan* plan);
 
 // Several deltas share one sampling launch sequence.
-constexpr int kMaxDeltas = 8;
 typedef tc_tuning SampleTuning;
 SampleTuning default_tuning();
 // Workspace of sample_batch; with t == NULL, room for any tuning.

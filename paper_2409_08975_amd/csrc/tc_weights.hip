@@ -2,22 +2,29 @@
 // path weights (Algorithm Preprocess with Claim "count":
 // w_e = d^-_u[t - delta, t] * d^+_v[t, t + delta], and for the other anchor
 // classes d^{alpha_1}_u * d^{alpha_3}_v over the class's intervals, a side
-// without an edge counting 1).  Described below for the class <-,+,<,>>.
+// without an edge counting 1), for one or several deltas of one class.
 //
 // The window bounds are ranks of sorted query sequences in sorted adjacency
-// arrays on the composite key (vertex, time): the out-CSR order p is sorted
-// by (u, t), so lo_in[p] = #{in-CSR entries < (u, t - delta)} and
-// lo_in[p] + a[p] = #{in-CSR entries <= (u, t)}; the in-CSR order q is sorted
-// by (v, t), so v's out-window bounds are ranks of (v, t) and (v, t + delta)
-// in the out-CSR.  Each rank sequence is one merge-path pass:
-//   k_mp_split4   splits the merged sequence (queries + data) into tiles of
-//                 kMPTile entries by a binary search on each tile diagonal,
+// arrays on the composite key (vertex, time).  For the class <-,+,<,>>: the
+// out-CSR order p is sorted by (u, t), so lo_in[p] = #{in-CSR entries <
+// (u, t - delta)} and lo_in[p] + a[p] = #{in-CSR entries <= (u, t)}; the
+// in-CSR order q is sorted by (v, t), so v's out-window bounds are ranks of
+// (v, t) and (v, t + delta) in the out-CSR.  One bound of each side is the
+// rank of the centre time itself and does not depend on delta: it is ranked
+// once per call, and each delta adds one rank pass per side.  Each rank
+// sequence is one merge-path pass:
+//   k_mp_split    splits the merged sequence (queries + data) into tiles of
+//                 kMPTile entries by a binary search on each tile diagonal
+//                 (every pass of the call in one launch),
 //   k_mp_rank     stages the tile's data keys in LDS and ranks each of the
 //                 tile's queries there,
-// so every array is read once, coalesced.  Then:
-//   k_combine     per p: v's window (the last rank pass stored it by edge id),
-//                 writes lo_out, b and the 128-bit sum of a*b per 2048-edge
-//                 tile.
+// so every array is read once per pass, coalesced.  Side 3 comes out in
+// in-CSR order: its last pass writes one record per edge id holding the
+// delta-free bound and every delta's rank, so a single scatter and a single
+// gather carry all deltas to out-CSR order.  Then:
+//   k_combine     per p: each delta's side-3 window from the record, the
+//                 path records and the 128-bit tile sums of a*b per 2048-edge
+//                 tile, for every delta.
 //   k_scan_tiles  one block scans the tile sums in 128-bit arithmetic, so
 //                 W >= 2^64 is detected exactly, and writes S[m] = W.
 //   k_scan_apply  per tile: w = a*b, block-wide exclusive scan, plus the
@@ -52,20 +59,21 @@ __device__ __forceinline__ bool before(int32_t dv, int64_t dt, int32_t qv, int64
 // split[b] = number of queries among the first min(b * kMPTile, nq + nd)
 // entries of the merge (a query is taken first unless a data entry is ranked
 // before it), by a bisection on the diagonal.
-// The four splits of the weights (two per window side) in one launch:
-// blockIdx.y picks the job.  Each diagonal's search is a short serial chain,
-// so one job alone leaves the GPU mostly idle.
+// Every split of the call (per side: the delta-free bound, then one per
+// delta) in one launch: blockIdx.y picks the job.  Each diagonal's search is
+// a short serial chain, so one job alone leaves the GPU mostly idle.
+constexpr int kMaxJobs = 2 + 2 * kMaxDeltas;
 struct SplitJob {
   KeyCols Q, D;
   uint32_t* split;
   int32_t upper;
 };
 struct SplitJobs {
-  SplitJob j[4];
+  SplitJob j[kMaxJobs];
 };
 
-__global__ __launch_bounds__(256) void k_mp_split4(SplitJobs J, int64_t nq, int64_t nd,
-                                                   int64_t nsplit) {
+__global__ __launch_bounds__(256) void k_mp_split(SplitJobs J, int64_t nq, int64_t nd,
+                                                  int64_t nsplit) {
   const SplitJob& S = J.j[blockIdx.y];
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nsplit) return;
@@ -87,16 +95,74 @@ __global__ __launch_bounds__(256) void k_mp_split4(SplitJobs J, int64_t nq, int6
   S.split[b] = (uint32_t)lo;
 }
 
-// rank of every query of the tile: out[i] = rank, or with `sub`
-// pair_out[i] = {sub[i], rank - sub[i]} (a window's start and length),
-// stored at pair_out[eid[i]] when `eid` is given
+// What a rank pass stores for query i (rank = its rank in the data):
+//   RO_PLAIN  out[i] = rank (a delta-free bound, or a delta's bound kept for
+//             the side-3 record)
+//   RO_SIDE1  side 1's window from the delta-free bound F[i] and this
+//             delta's rank: a window after the centre time has lo = F and
+//             len = rank - F, one before it lo = rank and len = F - rank.
+//             F may share storage with lo or len: it is read first, by the
+//             thread that writes them.
+//   RO_REC    side 3's record of query i's edge, at rec[eid[i] * stride]:
+//             F[i], the other deltas' ranks R[0..nr)[i], this rank, zeros.
+enum { RO_PLAIN = 0, RO_SIDE1 = 1, RO_REC = 2 };
+constexpr int kMaxRecWords = 12;
+struct RankOut {
+  int mode, after, nr, stride;
+  uint32_t* out;
+  const uint32_t* F;
+  uint32_t* lo;
+  uint32_t* len;
+  const uint32_t* R[kMaxDeltas];
+  uint32_t* rec;
+  const int32_t* eid;
+};
+
+// record words per edge: the delta-free bound and one rank per delta,
+// rounded up to 8 or a multiple of 16 bytes
+static inline int rec_stride(int nd) {
+  const int w = 1 + nd;
+  return w <= 2 ? 2 : ((w + 3) / 4) * 4;
+}
+
+__device__ __forceinline__ void store_rank(const RankOut& O, int64_t i, uint32_t rank) {
+  if (O.mode == RO_PLAIN) {
+    O.out[i] = rank;
+    return;
+  }
+  const uint32_t f = O.F[i];
+  if (O.mode == RO_SIDE1) {
+    O.lo[i] = O.after ? f : rank;
+    O.len[i] = O.after ? rank - f : f - rank;
+    return;
+  }
+  const int64_t e = O.eid[i];
+  if (O.stride == 2) {
+    reinterpret_cast<uint2*>(O.rec)[e] = make_uint2(f, rank);
+    return;
+  }
+  uint32_t w[kMaxRecWords];
+  w[0] = f;
+#pragma unroll
+  for (int j = 0; j < kMaxRecWords - 1; ++j) {
+    uint32_t v = 0;
+    if (j < O.nr)
+      v = O.R[j & (kMaxDeltas - 1)][i];
+    else if (j == O.nr)
+      v = rank;
+    w[1 + j] = v;
+  }
+  uint4* r4 = reinterpret_cast<uint4*>(O.rec) + e * (O.stride / 4);
+#pragma unroll
+  for (int q = 0; q < kMaxRecWords / 4; ++q)
+    if (q < O.stride / 4) r4[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+}
+
+// rank of every query of the tile, stored as O says
 template <bool UPPER>
 __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, KeyCols D, int64_t nd,
                                                       const uint32_t* __restrict__ split,
-                                                      const uint32_t* __restrict__ sub,
-                                                      uint32_t* __restrict__ out,
-                                                      uint2* __restrict__ pair_out,
-                                                      const int32_t* __restrict__ eid,
+                                                      RankOut O,
                                                       const uint32_t* __restrict__ gstatus) {
   if (*gstatus) return;  // a rejected graph: its arrays are not sorted
   __shared__ int32_t s_v[kMPTile];
@@ -123,67 +189,106 @@ __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, Key
       lo = go ? mid + 1 : lo;
       n = go ? n - half - 1 : half;
     }
-    const uint32_t rank = (uint32_t)(i0 + lo);
-    if (pair_out) {
-      const uint32_t s0 = sub[i];
-      pair_out[eid ? eid[i] : i] = make_uint2(s0, rank - s0);
-    } else {
-      out[i] = sub ? rank - sub[i] : rank;
-    }
+    store_rank(O, i, (uint32_t)(i0 + lo));
   }
 }
 
-// per p: side 3's window (the last rank pass stored it by edge id), the path
-// record, and the tile sums of a * b.  An absent side has the window {0, 1}
-// (one position, no edge); side 1's is then written here too.
+// Per p, for every delta of the call: side 3's window from the record of
+// p's edge, the path record, and the tile sums of a * b.  An absent side has
+// the window {0, 1} (one position, no edge); side 1's is then written here.
+struct CombineOut {
+  int nd, side1, side3, after3, stride;
+  uint32_t* lo_in[kMaxDeltas];
+  uint32_t* a[kMaxDeltas];
+  uint32_t* lo_out[kMaxDeltas];
+  uint32_t* b[kMaxDeltas];
+  uint4* prec[kMaxDeltas];
+  uint64_t* tile_sums[kMaxDeltas];
+};
+
 __global__ __launch_bounds__(kWBlock) void k_combine(const int32_t* __restrict__ out_eid,
-                                                     const uint2* __restrict__ win_e,
-                                                     uint32_t* __restrict__ lo_in,
-                                                     uint32_t* __restrict__ a,
+                                                     const uint32_t* __restrict__ rec,
                                                      const int32_t* __restrict__ out_src,
                                                      const int32_t* __restrict__ out_dst,
                                                      const int64_t* __restrict__ out_t, int64_t m,
-                                                     uint32_t* __restrict__ lo_out,
-                                                     uint32_t* __restrict__ b_out,
-                                                     uint4* __restrict__ prec,
-                                                     uint64_t* __restrict__ tile_sums,
-                                                     const uint32_t* __restrict__ gstatus,
-                                                     int side1, int side3) {
+                                                     CombineOut C,
+                                                     const uint32_t* __restrict__ gstatus) {
   if (*gstatus) return;  // a rejected graph: its edge ids are not a permutation
-  __shared__ U128 s_w[kWBlock / kWave];
+  __shared__ U128 s_w[kMaxDeltas][kWBlock / kWave];
   const int64_t start = (int64_t)blockIdx.x * kWTile;
-  U128 acc{0, 0};
-#pragma unroll 4
+  U128 acc[kMaxDeltas];
+#pragma unroll
+  for (int i = 0; i < kMaxDeltas; ++i) acc[i] = U128{0, 0};
   for (int r = 0; r < kWItems; ++r) {
     const int64_t p = start + (int64_t)r * kWBlock + threadIdx.x;
     if (p < m) {
-      const uint2 wq = side3 ? win_e[out_eid[p]] : make_uint2(0u, 1u);
-      uint32_t l1 = 0, ap = 1;
-      if (side1) {
-        l1 = lo_in[p];
-        ap = a[p];
-      } else {
-        lo_in[p] = 0;
-        a[p] = 1;
+      uint32_t w[kMaxRecWords];
+#pragma unroll
+      for (int j = 0; j < kMaxRecWords; ++j) w[j] = 0;
+      if (C.side3) {
+        const int64_t e = out_eid[p];
+        if (C.stride == 2) {
+          const uint2 v = reinterpret_cast<const uint2*>(rec)[e];
+          w[0] = v.x;
+          w[1] = v.y;
+        } else {
+          const uint4* r4 = reinterpret_cast<const uint4*>(rec) + e * (C.stride / 4);
+#pragma unroll
+          for (int q = 0; q < kMaxRecWords / 4; ++q)
+            if (q < C.stride / 4) {
+              const uint4 v = r4[q];
+              w[4 * q] = v.x, w[4 * q + 1] = v.y, w[4 * q + 2] = v.z, w[4 * q + 3] = v.w;
+            }
+        }
       }
-      const uint32_t bb = wq.y;
-      lo_out[p] = wq.x;
-      b_out[p] = bb;
       const int64_t t = out_t[p];
-      prec[2 * p] = make_uint4(l1, ap, wq.x, bb);
-      prec[2 * p + 1] =
+      const uint4 edge =
           make_uint4((uint32_t)out_src[p], (uint32_t)out_dst[p], (uint32_t)t, (uint32_t)(t >> 32));
-      acc = add128(acc, U128{(uint64_t)ap * (uint64_t)bb, 0});
+#pragma unroll
+      for (int i = 0; i < kMaxDeltas; ++i) {
+        if (i < C.nd) {
+          uint32_t l3 = 0, b3 = 1;
+          if (C.side3) {
+            const uint32_t f = w[0], rk = w[1 + i];
+            l3 = C.after3 ? f : rk;
+            b3 = C.after3 ? rk - f : f - rk;
+          }
+          uint32_t l1 = 0, a1 = 1;
+          if (C.side1) {
+            l1 = C.lo_in[i][p];
+            a1 = C.a[i][p];
+          } else {
+            C.lo_in[i][p] = 0;
+            C.a[i][p] = 1;
+          }
+          C.lo_out[i][p] = l3;
+          C.b[i][p] = b3;
+          C.prec[i][2 * p] = make_uint4(l1, a1, l3, b3);
+          C.prec[i][2 * p + 1] = edge;
+          acc[i] = add128(acc[i], U128{(uint64_t)a1 * (uint64_t)b3, 0});
+        }
+      }
     }
   }
-  acc = wave_sum128(acc);
-  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < kMaxDeltas; ++i) {
+    if (i < C.nd) {
+      const U128 s = wave_sum128(acc[i]);
+      if (lane == 0) s_w[i][wave] = s;
+    }
+  }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < C.nd) {
+    const int i = threadIdx.x;
     U128 t{0, 0};
-    for (int w = 0; w < kWBlock / kWave; ++w) t = add128(t, s_w[w]);
-    tile_sums[2 * blockIdx.x] = t.lo;
-    tile_sums[2 * blockIdx.x + 1] = t.hi;
+    for (int q = 0; q < kWBlock / kWave; ++q) t = add128(t, s_w[i][q]);
+    uint64_t* ts = nullptr;
+#pragma unroll
+    for (int j = 0; j < kMaxDeltas; ++j)
+      if (j == i) ts = C.tile_sums[j];
+    ts[2 * blockIdx.x] = t.lo;
+    ts[2 * blockIdx.x + 1] = t.hi;
   }
 }
 
@@ -398,9 +503,9 @@ static void build_tree(tc_weights* w, hipStream_t st) {
                        (uint64_t*)w->scratch, sh, pad);
 }
 
+// The arrays one weights set owns (they stay valid as long as the workspace).
 struct WeightsLayout {
-  size_t lo_in, a, lo_out, b, S, status, tile_sums, tile_off, tree, lo_out_q, win_e, split, prec,
-      total;
+  size_t lo_in, a, lo_out, b, S, tree, status, tile_sums, tile_off, prec, total;
 };
 
 static WeightsLayout weights_layout(int64_t m) {
@@ -423,44 +528,67 @@ static WeightsLayout weights_layout(int64_t m) {
   L.status = take(4);
   L.tile_sums = take(ntiles * 16);
   L.tile_off = take(ntiles * 8);
-  L.lo_out_q = take(M * 4);
-  L.win_e = take(M * 8);
-  L.split = take((size_t)4 * ((2 * M + kMPTile - 1) / kMPTile + 2) * 4);  // four jobs
   L.prec = take(M * 32);
   L.total = o;
   return L;
 }
 
-size_t weights_workspace_bytes(int64_t m) { return weights_layout(m).total; }
+// A call over nd deltas: nd weights sets, then the scratch of the call (the
+// side-3 records by edge id and the merge splits of every pass).
+struct BatchLayout {
+  size_t own, rec, split, total;
+  int64_t nsplit;
+};
 
-tc_status path_weights(const tc_graph* g, int64_t delta, const tc_class& cls, void* ws,
-                       size_t ws_bytes, hipStream_t st, tc_weights* w) {
+static BatchLayout batch_layout(int64_t m, int nd) {
+  BatchLayout L;
+  L.own = weights_layout(m).total;
+  L.nsplit = (2 * m + kMPTile - 1) / kMPTile + 1;
+  L.rec = L.own * (size_t)nd;
+  const size_t rec_bytes = align256((size_t)m * (size_t)rec_stride(nd) * 4 + 1);
+  L.split = L.rec + rec_bytes;
+  L.total = L.split + align256((size_t)(2 + 2 * nd) * (size_t)(L.nsplit + 1) * 4);
+  return L;
+}
+
+size_t weights_workspace_bytes(int64_t m) { return batch_layout(m, 1).total; }
+size_t weights_batch_workspace_bytes(int64_t m, int nd) { return batch_layout(m, nd).total; }
+
+tc_status path_weights_batch(const tc_graph* g, const int64_t* deltas, int nd,
+                             const tc_class& cls, void* ws, size_t ws_bytes, hipStream_t st,
+                             tc_weights* w) {
   const int64_t m = g->m;
-  WeightsLayout L = weights_layout(m);
-  if (ws_bytes < L.total) return TC_E_WORKSPACE;
-  char* base = (char*)ws;
-  w->delta = delta;
-  w->m = m;
-  w->cls = cls;
-  w->lo_in = (uint32_t*)(base + L.lo_in);
-  w->a = (uint32_t*)(base + L.a);
-  w->lo_out = (uint32_t*)(base + L.lo_out);
-  w->b = (uint32_t*)(base + L.b);
-  w->S = (uint64_t*)(base + L.S);
-  w->status = (uint32_t*)(base + L.status);
-  w->scratch = base + L.tree;  // search tree over S
-  w->h = nullptr;
-  w->prec = base + L.prec;
-  uint64_t* tile_sums = (uint64_t*)(base + L.tile_sums);
-  uint64_t* tile_off = (uint64_t*)(base + L.tile_off);
+  if (nd < 1 || nd > kMaxDeltas) return TC_E_ARG;
+  const BatchLayout B = batch_layout(m, nd);
+  if (ws_bytes < B.total) return TC_E_WORKSPACE;
+  const WeightsLayout L = weights_layout(m);
   const int64_t ntiles = (m + kWTile - 1) / kWTile;
-  uint32_t* lo_out_q = (uint32_t*)(base + L.lo_out_q);
-  uint2* win_e = (uint2*)(base + L.win_e);
-  uint32_t* split = (uint32_t*)(base + L.split);
+  uint64_t* tile_sums[kMaxDeltas];
+  uint64_t* tile_off[kMaxDeltas];
+  for (int i = 0; i < nd; ++i) {
+    char* base = (char*)ws + (size_t)i * B.own;
+    tc_weights* W = &w[i];
+    W->delta = deltas[i];
+    W->m = m;
+    W->cls = cls;
+    W->lo_in = (uint32_t*)(base + L.lo_in);
+    W->a = (uint32_t*)(base + L.a);
+    W->lo_out = (uint32_t*)(base + L.lo_out);
+    W->b = (uint32_t*)(base + L.b);
+    W->S = (uint64_t*)(base + L.S);
+    W->status = (uint32_t*)(base + L.status);
+    W->scratch = base + L.tree;  // search tree over S
+    W->h = nullptr;
+    W->prec = base + L.prec;
+    tile_sums[i] = (uint64_t*)(base + L.tile_sums);
+    tile_off[i] = (uint64_t*)(base + L.tile_off);
+  }
+  uint32_t* rec = (uint32_t*)((char*)ws + B.rec);
+  uint32_t* split = (uint32_t*)((char*)ws + B.split);
   const uint32_t* gst = (const uint32_t*)g->status;
   if (m > 0) {
     TimedLaunch tl("k_windows", st);
-    const int64_t nsplit = (2 * m + kMPTile - 1) / kMPTile + 1;
+    const int64_t nsplit = B.nsplit;
     const unsigned sb = (unsigned)((nsplit + 255) / 256);
     const unsigned rb = (unsigned)(nsplit - 1);
     // (vertex, time) keys: the out-CSR sorted by (source, time), the in-CSR
@@ -472,58 +600,122 @@ tc_status path_weights(const tc_graph* g, int64_t delta, const tc_class& cls, vo
     // window of u's in- or out-edges; side 3: for every in-CSR position q
     // (queries (v, t): each edge seen from its destination) the window of
     // v's in- or out-edges.  A window [from, to] is the rank of (w, from)
-    // counted with "<" and of (w, to) counted with "<=".
+    // counted with "<" and of (w, to) counted with "<=".  The bound at the
+    // centre time is delta-free: "<=" for a window before t, "<" for one
+    // after it; each delta's bound is (w, t - delta) with "<" or
+    // (w, t + delta) with "<=".
     auto shifted = [&](const KeyCols& q, int64_t sh) { return KeyCols{q.v, q.t, sh}; };
-    const int64_t lo1 = cls.after1 ? 0 : -delta, hi1 = cls.after1 ? delta : 0;
-    const int64_t lo3 = cls.after3 ? 0 : -delta, hi3 = cls.after3 ? delta : 0;
     const KeyCols d1 = cls.mode1 == TC_SIDE_IN ? ink : outk;
     const KeyCols d3 = cls.mode3 == TC_SIDE_IN ? ink : outk;
-    uint32_t* sp[4];
-    for (int c = 0; c < 4; ++c) sp[c] = split + (size_t)c * (size_t)(nsplit + 1);
     SplitJobs J{};
     int nj = 0;
+    auto job = [&](const KeyCols& q, const KeyCols& d, bool upper) {
+      J.j[nj] = SplitJob{q, d, split + (size_t)nj * (size_t)(nsplit + 1), upper ? 1 : 0};
+      return nj++;
+    };
+    int j1f = -1, j3f = -1, j1[kMaxDeltas], j3[kMaxDeltas];
+    auto dshift = [&](int after, int64_t d) { return after ? d : -d; };
     if (s1) {
-      J.j[nj++] = SplitJob{shifted(outk, lo1), d1, sp[0], 0};
-      J.j[nj++] = SplitJob{shifted(outk, hi1), d1, sp[1], 1};
+      j1f = job(outk, d1, !cls.after1);
+      for (int i = 0; i < nd; ++i) j1[i] = job(shifted(outk, dshift(cls.after1, deltas[i])), d1,
+                                               cls.after1 != 0);
     }
     if (s3) {
-      J.j[nj++] = SplitJob{shifted(ink, lo3), d3, sp[2], 0};
-      J.j[nj++] = SplitJob{shifted(ink, hi3), d3, sp[3], 1};
+      j3f = job(ink, d3, !cls.after3);
+      for (int i = 0; i < nd; ++i) j3[i] = job(shifted(ink, dshift(cls.after3, deltas[i])), d3,
+                                               cls.after3 != 0);
     }
-    hipLaunchKernelGGL(k_mp_split4, dim3(sb, nj), dim3(256), 0, st, J, m, m, nsplit);
+    if (nj > 0) hipLaunchKernelGGL(k_mp_split, dim3(sb, nj), dim3(256), 0, st, J, m, m, nsplit);
+    auto rank = [&](int jb, const RankOut& O) {
+      const SplitJob& S = J.j[jb];
+      if (S.upper)
+        hipLaunchKernelGGL(k_mp_rank<true>, dim3(rb), dim3(kMPBlock), 0, st, S.Q, m, S.D, m,
+                           (const uint32_t*)S.split, O, gst);
+      else
+        hipLaunchKernelGGL(k_mp_rank<false>, dim3(rb), dim3(kMPBlock), 0, st, S.Q, m, S.D, m,
+                           (const uint32_t*)S.split, O, gst);
+    };
     if (s1) {
-      hipLaunchKernelGGL(k_mp_rank<false>, dim3(rb), dim3(kMPBlock), 0, st, shifted(outk, lo1), m,
-                         d1, m, (const uint32_t*)sp[0], (const uint32_t*)nullptr, w->lo_in,
-                         (uint2*)nullptr, (const int32_t*)nullptr, gst);
-      hipLaunchKernelGGL(k_mp_rank<true>, dim3(rb), dim3(kMPBlock), 0, st, shifted(outk, hi1), m,
-                         d1, m, (const uint32_t*)sp[1], (const uint32_t*)w->lo_in, w->a,
-                         (uint2*)nullptr, (const int32_t*)nullptr, gst);
+      // the delta-free bound lives in the first set's lo_in (window after
+      // t) or a (before t) until that set's own pass, which runs last
+      uint32_t* F1 = cls.after1 ? w[0].lo_in : w[0].a;
+      RankOut O{};
+      O.mode = RO_PLAIN;
+      O.out = F1;
+      rank(j1f, O);
+      for (int i = nd - 1; i >= 0; --i) {
+        RankOut P{};
+        P.mode = RO_SIDE1;
+        P.after = cls.after1;
+        P.F = F1;
+        P.lo = w[i].lo_in;
+        P.len = w[i].a;
+        rank(j1[i], P);
+      }
     }
     if (s3) {
-      hipLaunchKernelGGL(k_mp_rank<false>, dim3(rb), dim3(kMPBlock), 0, st, shifted(ink, lo3), m,
-                         d3, m, (const uint32_t*)sp[2], (const uint32_t*)nullptr, lo_out_q,
-                         (uint2*)nullptr, (const int32_t*)nullptr, gst);
-      hipLaunchKernelGGL(k_mp_rank<true>, dim3(rb), dim3(kMPBlock), 0, st, shifted(ink, hi3), m,
-                         d3, m, (const uint32_t*)sp[3], (const uint32_t*)lo_out_q,
-                         (uint32_t*)nullptr, win_e, (const int32_t*)g->in_eid, gst);
+      // in-CSR order: the delta-free bound in the first set's lo_out, the
+      // ranks of all deltas but the last in their sets' b (k_combine
+      // overwrites both); the last pass writes the records
+      uint32_t* F3 = w[0].lo_out;
+      RankOut O{};
+      O.mode = RO_PLAIN;
+      O.out = F3;
+      rank(j3f, O);
+      for (int i = 0; i + 1 < nd; ++i) {
+        RankOut P{};
+        P.mode = RO_PLAIN;
+        P.out = w[i].b;
+        rank(j3[i], P);
+      }
+      RankOut P{};
+      P.mode = RO_REC;
+      P.after = cls.after3;
+      P.F = F3;
+      P.nr = nd - 1;
+      for (int i = 0; i + 1 < nd; ++i) P.R[i] = w[i].b;
+      P.stride = rec_stride(nd);
+      P.rec = rec;
+      P.eid = g->in_eid;
+      rank(j3[nd - 1], P);
+    }
+    CombineOut C{};
+    C.nd = nd;
+    C.side1 = s1 ? 1 : 0;
+    C.side3 = s3 ? 1 : 0;
+    C.after3 = cls.after3;
+    C.stride = rec_stride(nd);
+    for (int i = 0; i < nd; ++i) {
+      C.lo_in[i] = w[i].lo_in;
+      C.a[i] = w[i].a;
+      C.lo_out[i] = w[i].lo_out;
+      C.b[i] = w[i].b;
+      C.prec[i] = (uint4*)w[i].prec;
+      C.tile_sums[i] = tile_sums[i];
     }
     hipLaunchKernelGGL(k_combine, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
-                       (const int32_t*)g->out_eid, (const uint2*)win_e, w->lo_in, w->a,
+                       (const int32_t*)g->out_eid, (const uint32_t*)rec,
                        (const int32_t*)g->out_src, (const int32_t*)g->out_dst,
-                       (const int64_t*)g->out_t, m, w->lo_out, w->b, (uint4*)w->prec, tile_sums,
-                       gst, s1 ? 1 : 0, s3 ? 1 : 0);
+                       (const int64_t*)g->out_t, m, C, gst);
   }
-  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, (const uint64_t*)tile_sums, ntiles,
-                     tile_off, w->S, m, w->status, gst);
-  if (ntiles > 0) {
-    TimedLaunch tl("k_scan_apply", st);
-    hipLaunchKernelGGL(k_scan_apply<false>, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
-                       (const uint32_t*)w->a, (const uint32_t*)w->b, (const uint32_t*)nullptr, m,
-                       (const uint64_t*)tile_off, w->S);
+  for (int i = 0; i < nd; ++i) {
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, (const uint64_t*)tile_sums[i],
+                       ntiles, tile_off[i], w[i].S, m, w[i].status, gst);
+    if (ntiles > 0) {
+      TimedLaunch tl("k_scan_apply", st);
+      hipLaunchKernelGGL(k_scan_apply<false>, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
+                         (const uint32_t*)w[i].a, (const uint32_t*)w[i].b,
+                         (const uint32_t*)nullptr, m, (const uint64_t*)tile_off[i], w[i].S);
+    }
+    build_tree(&w[i], st);
   }
-  build_tree(w, st);
   if (hipGetLastError() != hipSuccess) return TC_E_HIP;
   return TC_OK;
+}
+
+tc_status path_weights(const tc_graph* g, int64_t delta, const tc_class& cls, void* ws,
+                       size_t ws_bytes, hipStream_t st, tc_weights* w) {
+  return path_weights_batch(g, &delta, 1, cls, ws, ws_bytes, st, w);
 }
 
 // Proposal weights: windows borrowed from w, S = scan of a * b * h.

@@ -142,3 +142,34 @@ def test_binding_raises_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(tcb, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         tcb.lib()
+
+
+def test_weights_batch_host_checks(tcb):
+    """The batched Preprocess's workspace grows with the number of deltas
+    and its argument errors return before anything is enqueued."""
+    L = tcb.lib()
+    one = tcb.weights_workspace_bytes(20000)
+    assert tcb.weights_batch_workspace_bytes(20000, 1) == one
+    b2 = tcb.weights_batch_workspace_bytes(20000, 2)
+    b8 = tcb.weights_batch_workspace_bytes(20000, 8)
+    assert 2 * (one - 20000 * 8) < b2 < 2 * one + 20000 * 16 and b8 > 8 * (one - 20000 * 8)
+    for nd in (0, 9):
+        with pytest.raises(tcb.TCError):
+            tcb.weights_batch_workspace_bytes(100, nd)
+    g = tcb.tc_graph()
+    g.m = 10
+    ws = (tcb.tc_weights * 8)()
+    fake = ctypes.c_void_p(256)
+    for ds in ([5, -1], [2**62 + 1], [1] * 9):
+        arr = (ctypes.c_int64 * len(ds))(*ds)
+        assert L.tc_path_weights_batch(ctypes.byref(g), arr, len(ds), None, fake, 1 << 40, None,
+                                       ws) == tcb.TC_E_ARG
+    arr = (ctypes.c_int64 * 2)(1, 2)
+    assert L.tc_path_weights_batch(ctypes.byref(g), arr, 0, None, fake, 1 << 40, None,
+                                   ws) == tcb.TC_E_ARG
+    c = tcb.tc_class(0, 0, 0, 0)
+    assert L.tc_path_weights_batch(ctypes.byref(g), arr, 2, ctypes.byref(c), fake, 1 << 40, None,
+                                   ws) == tcb.TC_E_ARG
+    assert L.tc_path_weights_batch(None, arr, 2, None, fake, 1 << 40, None, ws) == tcb.TC_E_ARG
+    assert L.tc_path_weights_batch(ctypes.byref(g), arr, 2, None, fake, 16, None,
+                                   ws) == tcb.TC_E_WORKSPACE
