@@ -44,7 +44,7 @@ KERNEL_SRC = {"k_paths": "tc_sample.hip", "k_listcount_reg": "tc_sample.hip",
               "k_windows": "tc_weights.hip", "k_scan_apply": "tc_weights.hip",
               "k_radix_scatter": "tc_build.hip"}
 # the kernels each timed span covers, for counter-based traffic per span
-SPAN_KERNELS = {"k_windows": ["k_mp_split", "k_mp_rank", "k_combine"]}
+SPAN_KERNELS = {"k_windows": ["k_mp_split_coarse", "k_mp_split", "k_mp_rank", "k_combine"]}
 PMC_FILES = {"bitcoin": os.path.join(ROOT, "profiles", "pmc_traffic_bitcoin.txt"),
              "medium": os.path.join(ROOT, "profiles", "pmc_traffic_medium.txt")}
 # stages of a step -> kernels whose counter traffic makes up the stage
@@ -52,7 +52,7 @@ STAGE_KERNELS = {
     "build": ["k_init_build", "k_validate", "k_plan", "k_trange", "k_hash_clear", "k_rec_init",
               "k_radix_hist", "k_col_sum", "k_col_scan", "k_col_apply", "k_radix_scatter",
               "k_rec_xform", "k_emit", "k_hash_insert"],
-    "weights": ["k_mp_split", "k_mp_rank", "k_combine", "k_scan_tiles", "k_scan_apply",
+    "weights": ["k_mp_split_coarse", "k_mp_split", "k_mp_rank", "k_combine", "k_scan_tiles", "k_scan_apply",
                 "k_tree"],
     "sample": ["k_zero_result", "k_store_ptrs", "k_zero_counters", "k_paths", "k_listcount_reg",
                "k_listcount_lds", "k_listcount_wide", "k_listcount_big", "k_finalize"],

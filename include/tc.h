@@ -1,12 +1,14 @@
 /* tc.h -- C ABI of the MI355X temporal 3-path sampling library (libtc.so).
  *
- * The library estimates the number of matches of a 4-vertex temporal motif
- * M = (H, pi, delta) in a directed temporal multigraph G by sampling
- * delta-centred <-,+,<,>> 3-paths (Pan, Bhalerao, Seshadhri, Talati,
- * "Accurate and Fast Estimation of Temporal Motifs using Path Sampling",
- * ICDM 2024).  Problem statement: section I-A (temporal multigraph, edges
- * (u, v, t) with integer t, parallel edges allowed; Definitions of a
- * temporal motif and of an M-match).  The three calls below are the three
+ * The library estimates the number of matches of a 3- or 4-vertex temporal
+ * motif M = (H, pi, delta) in a directed temporal multigraph G by sampling
+ * delta-centred 3-paths of the motif's anchor class, or wedges for 3-vertex
+ * motifs (Pan, Bhalerao, Seshadhri, Talati, "Accurate and Fast Estimation
+ * of Temporal Motifs using Path Sampling", ICDM 2024), and counts them
+ * exactly by visiting every anchor (tc_exhaustive_count).  Problem
+ * statement: section I-A (temporal multigraph, edges (u, v, t) with integer
+ * t, parallel edges allowed; Definitions of a temporal motif and of an
+ * M-match).  The three calls below are the three
  * phases of Algorithm Estimate: the time-sorted adjacency it assumes,
  * Preprocess (per-edge weights and their total W), and the loop of Sample +
  * CheckMotif that ends in C_hat = (cnt / k) * W.
@@ -364,7 +366,8 @@ tc_status tc_sample_estimate_noalloc(const tc_graph *g, const tc_weights *w,
                                      tc_result *out, void *stream);
 
 /* Batched Estimate: n_deltas (1..8) weight sets of the same graph (one per
- * delta, from tc_path_weights) and n_motifs motifs sharing the anchor, in one
+ * delta, from tc_path_weights, tc_path_weights_class or tc_path_weights_batch)
+ * and n_motifs motifs sharing the anchor, in one
  * launch sequence: the path kernel is persistent over (delta, sample tile)
  * work and every ListCount pass serves all deltas.  Sample i of every delta
  * uses the counter of sample i of a single tc_sample_estimate call with the

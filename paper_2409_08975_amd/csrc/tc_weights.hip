@@ -60,9 +60,14 @@ __device__ __forceinline__ bool before(int32_t dv, int64_t dt, int32_t qv, int64
 // entries of the merge (a query is taken first unless a data entry is ranked
 // before it), by a bisection on the diagonal.
 // Every split of the call (per side: the delta-free bound, then one per
-// delta) in one launch: blockIdx.y picks the job.  Each diagonal's search is
-// a short serial chain, so one job alone leaves the GPU mostly idle.
+// delta) in one launch: blockIdx.y picks the job.  Two launches: every
+// kSplitStride-th diagonal (and the last) bisects the whole range; the
+// others bisect only between the splits of their two coarse neighbours (the
+// split grows with the diagonal), a window of at most kSplitStride tiles
+// whose probes stay in L2, where a full bisection reads a fresh line per
+// probe.
 constexpr int kMaxJobs = 2 + 2 * kMaxDeltas;
+constexpr int64_t kSplitStride = 32;
 struct SplitJob {
   KeyCols Q, D;
   uint32_t* split;
@@ -72,14 +77,8 @@ struct SplitJobs {
   SplitJob j[kMaxJobs];
 };
 
-__global__ __launch_bounds__(256) void k_mp_split(SplitJobs J, int64_t nq, int64_t nd,
-                                                  int64_t nsplit) {
-  const SplitJob& S = J.j[blockIdx.y];
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nsplit) return;
-  const int64_t d = b * kMPTile < nq + nd ? b * kMPTile : nq + nd;
-  int64_t lo = d - nd > 0 ? d - nd : 0;
-  int64_t hi = d < nq ? d : nq;
+__device__ __forceinline__ uint32_t split_search(const SplitJob& S, int64_t d, int64_t lo,
+                                                 int64_t hi) {
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
     const int64_t j = d - mid - 1;
@@ -92,7 +91,38 @@ __global__ __launch_bounds__(256) void k_mp_split(SplitJobs J, int64_t nq, int64
     else
       hi = mid;
   }
-  S.split[b] = (uint32_t)lo;
+  return (uint32_t)lo;
+}
+
+// coarse: thread c takes diagonal index c * kSplitStride (or the last one)
+__global__ __launch_bounds__(256) void k_mp_split_coarse(SplitJobs J, int64_t nq, int64_t nd,
+                                                         int64_t nsplit) {
+  const SplitJob& S = J.j[blockIdx.y];
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ncoarse = (nsplit - 1 + kSplitStride - 1) / kSplitStride + 1;
+  if (c >= ncoarse) return;
+  const int64_t b = c * kSplitStride < nsplit - 1 ? c * kSplitStride : nsplit - 1;
+  const int64_t d = b * kMPTile < nq + nd ? b * kMPTile : nq + nd;
+  const int64_t lo = d - nd > 0 ? d - nd : 0;
+  const int64_t hi = d < nq ? d : nq;
+  S.split[b] = split_search(S, d, lo, hi);
+}
+
+// fine: every other diagonal, inside its coarse neighbours' splits
+__global__ __launch_bounds__(256) void k_mp_split(SplitJobs J, int64_t nq, int64_t nd,
+                                                  int64_t nsplit) {
+  const SplitJob& S = J.j[blockIdx.y];
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nsplit - 1 || b % kSplitStride == 0) return;
+  const int64_t d = b * kMPTile < nq + nd ? b * kMPTile : nq + nd;
+  const int64_t bl = b - b % kSplitStride;
+  const int64_t br = bl + kSplitStride < nsplit - 1 ? bl + kSplitStride : nsplit - 1;
+  int64_t lo = d - nd > 0 ? d - nd : 0;
+  int64_t hi = d < nq ? d : nq;
+  const int64_t sl = S.split[bl], sr = S.split[br];
+  lo = sl > lo ? sl : lo;
+  hi = sr < hi ? sr : hi;
+  S.split[b] = split_search(S, d, lo, hi);
 }
 
 // What a rank pass stores for query i (rank = its rank in the data):
@@ -100,20 +130,24 @@ __global__ __launch_bounds__(256) void k_mp_split(SplitJobs J, int64_t nq, int64
 //             the side-3 record)
 //   RO_SIDE1  side 1's window from the delta-free bound F[i] and this
 //             delta's rank: a window after the centre time has lo = F and
-//             len = rank - F, one before it lo = rank and len = F - rank.
-//             F may share storage with lo or len: it is read first, by the
-//             thread that writes them.
+//             len = rank - F, one before it lo = rank and len = F - rank
 //   RO_REC    side 3's record of query i's edge, at rec[eid[i] * stride]:
 //             F[i], the other deltas' ranks R[0..nr)[i], this rank, zeros.
+// Every array a pass writes is distinct from every array it reads (the
+// pointers are restrict), so a query's loads never wait for the previous
+// query's stores; the bound and record inputs are loaded before the search.
 enum { RO_PLAIN = 0, RO_SIDE1 = 1, RO_REC = 2 };
 constexpr int kMaxRecWords = 12;
-struct RankOut {
+struct RankMode {
   int mode, after, nr, stride;
+  const uint32_t* R[kMaxDeltas];
+};
+struct RankOut {
+  RankMode M;
   uint32_t* out;
   const uint32_t* F;
   uint32_t* lo;
   uint32_t* len;
-  const uint32_t* R[kMaxDeltas];
   uint32_t* rec;
   const int32_t* eid;
 };
@@ -125,44 +159,16 @@ static inline int rec_stride(int nd) {
   return w <= 2 ? 2 : ((w + 3) / 4) * 4;
 }
 
-__device__ __forceinline__ void store_rank(const RankOut& O, int64_t i, uint32_t rank) {
-  if (O.mode == RO_PLAIN) {
-    O.out[i] = rank;
-    return;
-  }
-  const uint32_t f = O.F[i];
-  if (O.mode == RO_SIDE1) {
-    O.lo[i] = O.after ? f : rank;
-    O.len[i] = O.after ? rank - f : f - rank;
-    return;
-  }
-  const int64_t e = O.eid[i];
-  if (O.stride == 2) {
-    reinterpret_cast<uint2*>(O.rec)[e] = make_uint2(f, rank);
-    return;
-  }
-  uint32_t w[kMaxRecWords];
-  w[0] = f;
-#pragma unroll
-  for (int j = 0; j < kMaxRecWords - 1; ++j) {
-    uint32_t v = 0;
-    if (j < O.nr)
-      v = O.R[j & (kMaxDeltas - 1)][i];
-    else if (j == O.nr)
-      v = rank;
-    w[1 + j] = v;
-  }
-  uint4* r4 = reinterpret_cast<uint4*>(O.rec) + e * (O.stride / 4);
-#pragma unroll
-  for (int q = 0; q < kMaxRecWords / 4; ++q)
-    if (q < O.stride / 4) r4[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
-}
-
-// rank of every query of the tile, stored as O says
+// rank of every query of the tile, stored as M says
 template <bool UPPER>
 __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, KeyCols D, int64_t nd,
                                                       const uint32_t* __restrict__ split,
-                                                      RankOut O,
+                                                      RankMode M, uint32_t* __restrict__ out,
+                                                      const uint32_t* __restrict__ F,
+                                                      uint32_t* __restrict__ lo_out,
+                                                      uint32_t* __restrict__ len_out,
+                                                      uint32_t* __restrict__ rec,
+                                                      const int32_t* __restrict__ eid,
                                                       const uint32_t* __restrict__ gstatus) {
   if (*gstatus) return;  // a rejected graph: its arrays are not sorted
   __shared__ int32_t s_v[kMPTile];
@@ -181,6 +187,16 @@ __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, Key
   for (int64_t i = q0 + threadIdx.x; i < q1; i += kMPBlock) {
     const int32_t qv = Q.v[i];
     const int64_t qt = Q.t[i] + Q.shift;
+    // inputs of the store, loaded before the search
+    const uint32_t f = M.mode != RO_PLAIN ? F[i] : 0u;
+    int64_t e = 0;
+    uint32_t w[kMaxRecWords];
+    if (M.mode == RO_REC) {
+      e = eid[i];
+#pragma unroll
+      for (int j = 0; j < kMaxRecWords - 1; ++j)
+        w[1 + j] = j < M.nr ? M.R[j & (kMaxDeltas - 1)][i] : 0u;
+    }
     int lo = 0, n = nd_t;
     while (n > 0) {
       const int half = n >> 1;
@@ -189,7 +205,25 @@ __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, Key
       lo = go ? mid + 1 : lo;
       n = go ? n - half - 1 : half;
     }
-    store_rank(O, i, (uint32_t)(i0 + lo));
+    const uint32_t rank = (uint32_t)(i0 + lo);
+    if (M.mode == RO_PLAIN) {
+      out[i] = rank;
+    } else if (M.mode == RO_SIDE1) {
+      lo_out[i] = M.after ? f : rank;
+      len_out[i] = M.after ? rank - f : f - rank;
+    } else if (M.stride == 2) {
+      reinterpret_cast<uint2*>(rec)[e] = make_uint2(f, rank);
+    } else {
+      w[0] = f;
+#pragma unroll
+      for (int j = 0; j < kMaxRecWords - 1; ++j)
+        if (j == M.nr) w[1 + j] = rank;
+      uint4* r4 = reinterpret_cast<uint4*>(rec) + e * (M.stride / 4);
+#pragma unroll
+      for (int q = 0; q < kMaxRecWords / 4; ++q)
+        if (q < M.stride / 4)
+          r4[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+    }
   }
 }
 
@@ -625,56 +659,61 @@ tc_status path_weights_batch(const tc_graph* g, const int64_t* deltas, int nd,
       for (int i = 0; i < nd; ++i) j3[i] = job(shifted(ink, dshift(cls.after3, deltas[i])), d3,
                                                cls.after3 != 0);
     }
-    if (nj > 0) hipLaunchKernelGGL(k_mp_split, dim3(sb, nj), dim3(256), 0, st, J, m, m, nsplit);
+    if (nj > 0) {
+      const int64_t ncoarse = (nsplit - 1 + kSplitStride - 1) / kSplitStride + 1;
+      hipLaunchKernelGGL(k_mp_split_coarse, dim3((unsigned)((ncoarse + 255) / 256), nj), dim3(256),
+                         0, st, J, m, m, nsplit);
+      hipLaunchKernelGGL(k_mp_split, dim3(sb, nj), dim3(256), 0, st, J, m, m, nsplit);
+    }
     auto rank = [&](int jb, const RankOut& O) {
       const SplitJob& S = J.j[jb];
       if (S.upper)
         hipLaunchKernelGGL(k_mp_rank<true>, dim3(rb), dim3(kMPBlock), 0, st, S.Q, m, S.D, m,
-                           (const uint32_t*)S.split, O, gst);
+                           (const uint32_t*)S.split, O.M, O.out, O.F, O.lo, O.len, O.rec, O.eid,
+                           gst);
       else
         hipLaunchKernelGGL(k_mp_rank<false>, dim3(rb), dim3(kMPBlock), 0, st, S.Q, m, S.D, m,
-                           (const uint32_t*)S.split, O, gst);
+                           (const uint32_t*)S.split, O.M, O.out, O.F, O.lo, O.len, O.rec, O.eid,
+                           gst);
     };
+    // Temporaries live in arrays that k_combine writes last: the first
+    // set's lo_out holds side 1's delta-free bound while side 1's delta
+    // passes read it, then side 3's (in-CSR order); the sets' b hold side
+    // 3's ranks of all deltas but the last until the record pass.
+    uint32_t* Ftmp = w[0].lo_out;
     if (s1) {
-      // the delta-free bound lives in the first set's lo_in (window after
-      // t) or a (before t) until that set's own pass, which runs last
-      uint32_t* F1 = cls.after1 ? w[0].lo_in : w[0].a;
       RankOut O{};
-      O.mode = RO_PLAIN;
-      O.out = F1;
+      O.M.mode = RO_PLAIN;
+      O.out = Ftmp;
       rank(j1f, O);
-      for (int i = nd - 1; i >= 0; --i) {
+      for (int i = 0; i < nd; ++i) {
         RankOut P{};
-        P.mode = RO_SIDE1;
-        P.after = cls.after1;
-        P.F = F1;
+        P.M.mode = RO_SIDE1;
+        P.M.after = cls.after1;
+        P.F = Ftmp;
         P.lo = w[i].lo_in;
         P.len = w[i].a;
         rank(j1[i], P);
       }
     }
     if (s3) {
-      // in-CSR order: the delta-free bound in the first set's lo_out, the
-      // ranks of all deltas but the last in their sets' b (k_combine
-      // overwrites both); the last pass writes the records
-      uint32_t* F3 = w[0].lo_out;
       RankOut O{};
-      O.mode = RO_PLAIN;
-      O.out = F3;
+      O.M.mode = RO_PLAIN;
+      O.out = Ftmp;
       rank(j3f, O);
       for (int i = 0; i + 1 < nd; ++i) {
         RankOut P{};
-        P.mode = RO_PLAIN;
+        P.M.mode = RO_PLAIN;
         P.out = w[i].b;
         rank(j3[i], P);
       }
       RankOut P{};
-      P.mode = RO_REC;
-      P.after = cls.after3;
-      P.F = F3;
-      P.nr = nd - 1;
-      for (int i = 0; i + 1 < nd; ++i) P.R[i] = w[i].b;
-      P.stride = rec_stride(nd);
+      P.M.mode = RO_REC;
+      P.M.after = cls.after3;
+      P.F = Ftmp;
+      P.M.nr = nd - 1;
+      for (int i = 0; i + 1 < nd; ++i) P.M.R[i] = w[i].b;
+      P.M.stride = rec_stride(nd);
       P.rec = rec;
       P.eid = g->in_eid;
       rank(j3[nd - 1], P);
