@@ -11,10 +11,11 @@
 //     the lists L_{u,v}),
 //   * Preprocess: per-edge window degrees by binary search and
 //     w_e = d^-_u[t-delta, t] * d^+_v[t, t+delta] (Claim "count",
-//     Algorithm Preprocess), their running total as an exact integer CDF,
+//     Algorithm Preprocess), or for another anchor class (section III) the
+//     product of its two sides' degrees over their intervals, a side with no
+//     edge (a wedge) counting 1; their running total as an exact integer CDF,
 //   * Sample: pick e with probability w_e / W by searching the CDF, then a
-//     uniform in-edge of u and a uniform out-edge of v inside the windows
-//     (Algorithm Sample),
+//     uniform edge inside each side's window (Algorithm Sample),
 //   * CheckMotif + ListCount (Algorithms CheckMotif and ListCount),
 //   * Estimate: C_hat = (cnt / k) * W (Algorithm Estimate),
 //   * a definition-level backtracking count of M-matches (Definition of an
@@ -33,8 +34,17 @@
 //   * ListCount counts strictly increasing chains (ties are not matches) and
 //     walks each pair of neighbouring lists with one forward pointer, which
 //     is what its linear-time claim needs,
-//   * the non-anchor edges of the supported motifs all come after rank 2 in
-//     pi order, so every list is the pair's times in (t3, t1 + delta].
+//   * the anchor of a motif holds its earliest edge (Algorithm Estimate):
+//     a 3-path over four distinct vertices, or for three vertices a wedge
+//     whose centre is the earliest edge; ties between candidates go to the
+//     lexicographically smallest sorted ranks, then the smallest centre
+//     rank, then the smallest rank of the edge at u,
+//   * a non-anchor edge of rank r is looked for after the anchor time ranked
+//     just below r and before the one ranked just above it, or up to the
+//     first anchor time + delta (CheckMotif's list bounds), so for the
+//     spine motifs every list is the pair's times in (t3, t1 + delta],
+//   * exhaustive mode visits CDF rank r as the anchor p = UB(S, r) - 1 with
+//     j1 = (r - S[p]) div b[p] and j3 = (r - S[p]) mod b[p].
 //
 // Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel
 // random numbers: as easy as 1, 2, 3", SC 2011) with counter
