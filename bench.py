@@ -55,7 +55,7 @@ STAGE_KERNELS = {
     "weights": ["k_mp_split_coarse", "k_mp_split", "k_mp_rank", "k_combine", "k_scan_tiles", "k_scan_apply",
                 "k_tree"],
     "sample": ["k_zero_result", "k_store_ptrs", "k_zero_counters", "k_paths", "k_listcount_reg",
-               "k_listcount_lds", "k_listcount_wide", "k_listcount_big", "k_finalize"],
+               "k_listcount_lds", "k_listcount_wide", "k_listcount_w128", "k_listcount_big", "k_finalize"],
 }
 
 
@@ -674,7 +674,7 @@ def run_batched(args):
     tcb.timing_enable(False)
     kernels = {}
     for kname in ("k_paths", "k_listcount_reg", "k_listcount_lds", "k_listcount_wide",
-                  "k_listcount_big"):
+                  "k_listcount_w128", "k_listcount_big"):
         kms, nl = tcb.timing_read(kname)
         if nl:
             kernels[kname] = {"ms_total": kms, "launches": nl, "ms_per_launch": kms / nl}

@@ -38,10 +38,13 @@
 //   k_listcount_wide one 256-thread block per item, lists up to 65,536
 //                    entries: each level as a merge of L_{r-1} and L_r in
 //                    LDS tiles, prefix sums in per-block scratch.
-//   k_listcount_big  longer still: one thread per item, merged time sweep.
-// A level total of 2^64 or more hands the item to the 128-bit pass.  Block sums are 128-bit and reach the outputs with one set of
-// atomics per block, so cnt is exact whatever the launch shape, the item
-// order or the tuning.
+//   k_listcount_w128 items whose level total reached 2^64 in one of the
+//                    passes above: the merged pass in 128-bit arithmetic.
+//   k_listcount_big  lists longer than 65,536 entries: one thread per item,
+//                    merged time sweep in 128-bit counts.
+// Block sums are 128-bit and reach the outputs with one set of atomics per
+// block, so cnt is exact whatever the launch shape, the item order or the
+// tuning.
 #include <hip/hip_runtime.h>
 
 #include "tc_device.h"
@@ -117,6 +120,9 @@ struct SampleArgs {
   uint32_t* wide_next;
   uint32_t* big_code;
   uint32_t* big_count;
+  uint32_t* w128_code;  // items whose count reached 2^64, lists up to kWideCap
+  uint32_t* w128_count;
+  uint32_t* w128_next;
   uint32_t* samp_h;  // [nd][chunk] proposal factor of each accepted sample
   uint64_t* fast_p;  // [fast waves][2][kKeyCap + 1]
   uint64_t* wide_p;  // [wide blocks][2][kWideCap + 1]
@@ -903,7 +909,7 @@ __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A) {
     }
     // a level total of 2^64 or more: the 128-bit pass counts the item
     if (sat) {
-      if (lane == 0) A.big_code[atomicAdd(A.big_count, 1u)] = code;
+      if (lane == 0) A.w128_code[atomicAdd(A.w128_count, 1u)] = code;
     } else if (lane == 0) {
       item_done(A, d, j, li, t_prev);
     }
@@ -1023,7 +1029,7 @@ __global__ __launch_bounds__(kWave) void k_listcount_lds(SampleArgs A, uint64_t*
     if (fwd)
       fwd_push(fb, code, A.wide_count, A.wide_code);
     else if (sat) {
-      if (lane == 0) A.big_code[atomicAdd(A.big_count, 1u)] = code;
+      if (lane == 0) A.w128_code[atomicAdd(A.w128_count, 1u)] = code;
     } else if (lane == 0)
       item_done(A, d, j, li, total.lo);
   }
@@ -1238,8 +1244,10 @@ __global__ __launch_bounds__(kWBlock, 7) void k_listcount_wide(SampleArgs A, uin
       total = U128{t_prev, 0};
     }
     if (tid == 0) {
-      if (maxlen > (uint32_t)kWideCap || sat)
+      if (maxlen > (uint32_t)kWideCap)
         A.big_code[atomicAdd(A.big_count, 1u)] = code;
+      else if (sat)
+        A.w128_code[atomicAdd(A.w128_count, 1u)] = code;
       else
         item_done(A, d, j, li, total.lo);
       s_item = atomicAdd(A.wide_next, 1u);
@@ -1251,10 +1259,218 @@ __global__ __launch_bounds__(kWBlock, 7) void k_listcount_wide(SampleArgs A, uin
   sums_flush<1>(A);
 }
 
-// Items with a list longer than kWideCap, and items whose count reaches 2^64:
-// one thread per item, 128-bit counts.  The per-sample output X saturates at
-// 2^64 - 1; cnt takes the exact value.  An importance-sampling term
-// floor(X 2^64 / h) needs X < 2^64: beyond, the motif's overflow bit is set.
+// One item's count X (128 bits) into a block slot.  The per-sample output X
+// saturates at 2^64 - 1; cnt takes the exact value.  An importance-sampling
+// term floor(X 2^64 / h) needs X < 2^64: beyond, the motif's overflow bit is
+// set, as it is for a count of 2^128 or more (`ovf`).  Several threads may
+// add to one slot (LDS atomics).
+__device__ void item_done128(const SampleArgs& A, int d, int j, uint32_t li, U128 X, bool ovf,
+                             BlockSums* slot) {
+  const DeltaArgs& D = A.D[d];
+  const uint64_t X64 = X.hi ? ~0ull : X.lo;  // saturated
+  if (D.h && X.hi) ovf = true;
+  if (ovf) flag_status(A, d, TC_F_OVERFLOW | TC_F_MOTIF(j));
+  if (D.X) D.X[(uint64_t)j * A.k + A.c0 + li] = X64;
+  const uint32_t hp = D.h ? A.samp_h[(uint64_t)d * A.chunk + li] : 1u;
+  const U128 c = D.h ? contribution(X64, true, hp) : X;
+  const bool nz = (X.lo | X.hi) != 0;
+  atomicAdd((unsigned long long*)&slot->hits, nz ? 1ull : 0ull);
+  if (nz) atomicMax((unsigned long long*)&slot->xmax, (unsigned long long)X64);
+  if (D.m2 && nz) {
+    const double v = __ddiv_rn(u128_to_double(X.lo, X.hi), (double)hp);
+    atomicAdd(&slot->m2, __dmul_rn(v, v));
+  }
+  const uint64_t old = atomicAdd((unsigned long long*)&slot->lo, (unsigned long long)c.lo);
+  const uint64_t add_hi = c.hi + ((old + c.lo < old) ? 1ull : 0ull);
+  if (add_hi < c.hi) atomicOr(&slot->ovf, 1u);
+  if (add_hi) {
+    const uint64_t old_hi = atomicAdd((unsigned long long*)&slot->hi, (unsigned long long)add_hi);
+    if (old_hi + add_hi < old_hi) atomicOr(&slot->ovf, 1u);
+  }
+}
+
+// Items whose count reached 2^64 in a faster pass, lists up to kWideCap
+// entries: the merge of k_listcount_wide in 128-bit arithmetic.  Each level
+// merges L_{r-1} and L_r in tiles; P_{r-1} and P_r are 128-bit prefix sums
+// (lo and hi words interleaved), and the block scan of the settled counts
+// runs over 128-bit values with a carry across steps.  Any sum that passes
+// 2^128 is reported as an overflow.  A block uses the prefix scratch of two
+// merged-pass blocks, so the pass needs no workspace of its own.
+__global__ __launch_bounds__(kWBlock) void k_listcount_w128(SampleArgs A, uint64_t* pscratch) {
+  __shared__ int64_t sA[kWTile];
+  __shared__ uint64_t sPlo[kWTile + 1], sPhi[kWTile + 1];
+  __shared__ uint64_t s_wlo[kWWaves], s_whi[kWWaves];
+  __shared__ uint32_t s_wset[kWWaves];
+  __shared__ uint32_t s_lo[kMaxLists], s_len[kMaxLists];
+  __shared__ uint32_t s_item, s_last_pos;
+  __shared__ int64_t s_key0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint64_t* Pbuf[2] = {pscratch + (uint64_t)blockIdx.x * 4 * (kWideCap + 1),
+                       pscratch + ((uint64_t)blockIdx.x * 4 + 2) * (kWideCap + 1)};
+  const uint32_t n_items = *A.w128_count;
+  if (blockIdx.x >= n_items) return;  // uniform: the others claim every item
+  sums_clear<1>(A);
+  if (tid == 0) s_item = atomicAdd(A.w128_next, 1u);
+  __syncthreads();
+  uint32_t it = uni(s_item);
+  while (it < n_items) {
+    const uint32_t code = A.w128_code[it];
+    uint32_t li;
+    int j, d;
+    decode(code, &li, &j, &d);
+    const int l = A.plan.n_lists[j];
+    if (tid < l) {
+      const uint64_t wi = win_index(A, d, A.plan.list_pair[j][tid], li);
+      s_lo[tid] = A.win_lo[wi];
+      s_len[tid] = A.win_len[wi];
+    }
+    __syncthreads();
+    uint32_t maxlen = 0;
+    for (int r = 0; r < l; ++r) maxlen = s_len[r] > maxlen ? s_len[r] : maxlen;
+    maxlen = uni(maxlen);
+    bool ovf = false;
+    U128 total{uni(s_len[0]), 0};
+    if (maxlen <= (uint32_t)kWideCap) {
+      for (int r = 1; r < l; ++r) {
+        const uint32_t loA = uni(s_lo[r - 1]), nA = uni(s_len[r - 1]);
+        const uint32_t loB = uni(s_lo[r]), nB = uni(s_len[r]);
+        const uint64_t* Pprev = Pbuf[(r - 1) & 1];
+        uint64_t* Pcur = Pbuf[r & 1];
+        const bool keep = r + 1 < l;  // P_r is read by the next level
+        if (keep && tid == 0) {
+          Pcur[0] = 0;
+          Pcur[1] = 0;
+        }
+        U128 carry{0, 0};
+        uint32_t a0 = 0, b0 = 0;
+        while (b0 < nB) {
+          const uint32_t na = nA - a0 < (uint32_t)kWTile ? nA - a0 : (uint32_t)kWTile;
+          const uint32_t nb = nB - b0 < (uint32_t)kWTile ? nB - b0 : (uint32_t)kWTile;
+          for (uint32_t i = tid; i < na; i += kWBlock) sA[i] = A.pair_t[loA + a0 + i];
+          for (uint32_t i = tid; i <= na; i += kWBlock) {
+            if (r == 1) {
+              sPlo[i] = (uint64_t)(a0 + i);
+              sPhi[i] = 0;
+            } else {
+              sPlo[i] = Pprev[2 * (uint64_t)(a0 + i)];
+              sPhi[i] = Pprev[2 * (uint64_t)(a0 + i) + 1];
+            }
+          }
+          int64_t key[kWPer];
+#pragma unroll
+          for (int e = 0; e < kWPer; ++e) {
+            const uint32_t bi = (uint32_t)(tid * kWPer + e);
+            key[e] = bi < nb ? A.pair_t[loB + b0 + bi] : INT64_MAX;
+          }
+          __syncthreads();
+          const bool a_ends = a0 + na == nA;
+          const int64_t a_last = na ? sA[na - 1] : INT64_MIN;
+          U128 c[kWPer];
+          uint32_t pl[kWPer];
+          uint32_t nset = 0;
+#pragma unroll
+          for (int e = 0; e < kWPer; ++e) {
+            const uint32_t bi = (uint32_t)(tid * kWPer + e);
+            const bool set = bi < nb && (a_ends || key[e] <= a_last);
+            pl[e] = set ? lower_bound<int64_t>(sA, 0u, na, key[e]) : 0u;
+            c[e] = set ? U128{sPlo[pl[e]], sPhi[pl[e]]} : U128{0, 0};
+            nset += set ? 1u : 0u;
+          }
+          // inclusive prefix of this thread's counts, then across the wavefront
+          U128 run[kWPer];
+#pragma unroll
+          for (int e = 0; e < kWPer; ++e) run[e] = e ? add128c(run[e - 1], c[e], &ovf) : c[0];
+          const U128 mine = run[kWPer - 1];
+          U128 inc = mine;
+#pragma unroll
+          for (int off = 1; off < kWave; off <<= 1) {
+            const U128 o{__shfl_up(inc.lo, off, kWave), __shfl_up(inc.hi, off, kWave)};
+            if (lane >= off) inc = add128c(inc, o, &ovf);
+          }
+          const uint32_t wset = lane_u32(scan_dpp(nset), kWave - 1);
+          if (lane == kWave - 1) {
+            s_wlo[wave] = inc.lo;
+            s_whi[wave] = inc.hi;
+            s_wset[wave] = wset;
+          }
+          __syncthreads();
+          // this thread's exclusive prefix: the carry, the wavefronts before,
+          // then the lanes before inside its wavefront
+          U128 before = carry;
+          uint32_t nr = 0;
+          U128 blk{0, 0};
+#pragma unroll
+          for (int w = 0; w < kWWaves; ++w) {
+            const U128 ws{s_wlo[w], s_whi[w]};
+            if (w < wave) before = add128c(before, ws, &ovf);
+            blk = add128c(blk, ws, &ovf);
+            nr += s_wset[w];
+          }
+          nr = uni(nr);
+          before = add128(before, U128{inc.lo - mine.lo,
+                                       inc.hi - mine.hi - (inc.lo < mine.lo ? 1ull : 0ull)});
+          if (keep) {
+#pragma unroll
+            for (int e = 0; e < kWPer; ++e) {
+              const uint32_t bi = (uint32_t)(tid * kWPer + e);
+              if (bi < nr) {
+                const U128 v = add128(before, run[e]);
+                Pcur[2 * (uint64_t)(b0 + bi + 1)] = v.lo;
+                Pcur[2 * (uint64_t)(b0 + bi + 1) + 1] = v.hi;
+              }
+            }
+          }
+          carry = add128c(carry, U128{uni64(blk.lo), uni64(blk.hi)}, &ovf);
+          // the next step's start in A (as in k_listcount_wide)
+          if (nr == nb) {
+#pragma unroll
+            for (int e = 0; e < kWPer; ++e)
+              if ((uint32_t)(tid * kWPer + e) == nb - 1) s_last_pos = pl[e];
+          } else {
+#pragma unroll
+            for (int e = 0; e < kWPer; ++e)
+              if ((uint32_t)(tid * kWPer + e) == nr) s_key0 = key[e];
+          }
+          __syncthreads();
+          b0 += nr;
+          if (nr == nb) {
+            a0 += uni(s_last_pos);
+          } else {
+            a0 += na;
+            const uint32_t rem = nA - a0;
+            if (rem > (uint32_t)kWTile) {
+              const int64_t key0 = uni64s(s_key0);
+              const uint32_t stride = (rem + kWBlock - 1) / kWBlock;
+              const uint64_t q = (uint64_t)a0 + (uint64_t)(tid + 1) * stride - 1;
+              const bool below = q < nA && A.pair_t[loA + q] < key0;
+              const uint32_t nb_below = (uint32_t)__syncthreads_count(below);
+              a0 += uni(nb_below) * stride;
+            }
+          }
+          __syncthreads();  // the tiles are rewritten by the next step
+        }
+        total = U128{uni64(carry.lo), uni64(carry.hi)};
+        __threadfence_block();
+        __syncthreads();  // P_r complete before the next level reads it
+      }
+    }
+    const bool any_ovf = __syncthreads_or(ovf) != 0;
+    if (tid == 0) {
+      if (maxlen > (uint32_t)kWideCap)
+        A.big_code[atomicAdd(A.big_count, 1u)] = code;
+      else
+        item_done128(A, d, j, li, total, any_ovf, sums_slot(A, 0, d, j));
+      s_item = atomicAdd(A.w128_next, 1u);
+    }
+    __syncthreads();
+    it = uni(s_item);
+  }
+  __syncthreads();
+  sums_flush<1>(A);
+}
+
+// Items with a list longer than kWideCap: one thread per item, a merged time
+// sweep in 128-bit counts.
 __global__ __launch_bounds__(kSBlock) void k_listcount_big(SampleArgs A) {
   const int tid = threadIdx.x, wave = tid >> 6;
   const uint32_t n_items = *A.big_count;
@@ -1279,29 +1495,7 @@ __global__ __launch_bounds__(kSBlock) void k_listcount_big(SampleArgs A) {
     }
     bool ovf = false;
     const U128 X = sweep128<kMaxLists>(A.pair_t, ptr, end, l, &ovf);
-    const DeltaArgs& D = A.D[d];
-    const uint64_t X64 = X.hi ? ~0ull : X.lo;  // saturated
-    if (D.h && X.hi) ovf = true;
-    if (ovf) flag_status(A, d, TC_F_OVERFLOW | TC_F_MOTIF(j));
-    if (D.X) D.X[(uint64_t)j * A.k + A.c0 + li] = X64;
-    const uint32_t hp = D.h ? A.samp_h[(uint64_t)d * A.chunk + li] : 1u;
-    const U128 c = D.h ? contribution(X64, true, hp) : X;
-    const bool nz = (X.lo | X.hi) != 0;
-    // few items: this wavefront's slot, updated with LDS atomics
-    BlockSums* slot = sums_slot(A, wave, d, j);
-    atomicAdd((unsigned long long*)&slot->hits, nz ? 1ull : 0ull);
-    if (nz) atomicMax((unsigned long long*)&slot->xmax, (unsigned long long)X64);
-    if (D.m2 && nz) {
-      const double v = __ddiv_rn(u128_to_double(X.lo, X.hi), (double)hp);
-      atomicAdd(&slot->m2, __dmul_rn(v, v));
-    }
-    const uint64_t old = atomicAdd((unsigned long long*)&slot->lo, (unsigned long long)c.lo);
-    const uint64_t add_hi = c.hi + ((old + c.lo < old) ? 1ull : 0ull);
-    if (add_hi < c.hi) atomicOr(&slot->ovf, 1u);
-    if (add_hi) {
-      const uint64_t old_hi = atomicAdd((unsigned long long*)&slot->hi, (unsigned long long)add_hi);
-      if (old_hi + add_hi < old_hi) atomicOr(&slot->ovf, 1u);
-    }
+    item_done128(A, d, j, li, X, ovf, sums_slot(A, wave, d, j));
   }
   __syncthreads();
   sums_flush<kSWaves>(A);
@@ -1332,8 +1526,9 @@ __global__ void k_store_ptrs(EstPtrs ep, double** dst) {
 }
 
 __global__ void k_zero_counters(uint32_t* p) {
-  // item_count, (spare), wide_count, wide_next, big_count, mid_count
-  if (threadIdx.x < 6) p[threadIdx.x] = 0;
+  // item_count, (spare), wide_count, wide_next, big_count, mid_count,
+  // w128_count, w128_next
+  if (threadIdx.x < 8) p[threadIdx.x] = 0;
 }
 
 // C_hat = (cnt / k) * W, each integer rounded to nearest-even binary64; with
@@ -1411,8 +1606,8 @@ static int wide_blocks_for(const SampleTuning& t) {
 }
 
 struct SampleLayout {
-  size_t win_lo, win_len, code, mid, wide, big, counters, fast_p, wide_p, est_ptrs, samp_h, spread,
-      total;
+  size_t win_lo, win_len, code, mid, wide, big, w128, counters, fast_p, wide_p, est_ptrs, samp_h,
+      spread, total;
   uint64_t chunk, cap;
   int fast_waves, wide_blocks;
 };
@@ -1435,6 +1630,7 @@ static SampleLayout sample_layout(uint64_t k, int nd, int32_t n_motifs, const Sa
   L.mid = take(L.cap * 4);
   L.wide = take(L.cap * 4);
   L.big = take(L.cap * 4);
+  L.w128 = take(L.cap * 4);
   L.counters = take(32);
   L.fast_p = take((size_t)L.fast_waves * 2 * (kKeyCap + 1) * 8);
   L.wide_p = take((size_t)L.wide_blocks * 2 * (kWideCap + 1) * 8);
@@ -1529,6 +1725,9 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
   A.wide_next = A.item_count + 3;
   A.big_count = A.item_count + 4;
   A.mid_count = A.item_count + 5;
+  A.w128_code = (uint32_t*)(base + L.w128);
+  A.w128_count = A.item_count + 6;
+  A.w128_next = A.item_count + 7;
   A.fast_p = (uint64_t*)(base + L.fast_p);
   A.samp_h = (uint32_t*)(base + L.samp_h);
   A.wide_p = (uint64_t*)(base + L.wide_p);
@@ -1586,6 +1785,13 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
       {
         TimedLaunch tl("k_listcount_wide", st);
         hipLaunchKernelGGL(k_listcount_wide, dim3((unsigned)L.wide_blocks), dim3(kWBlock),
+                           sums_bytes(1, nd, nm), st, A, A.wide_p);
+      }
+      {
+        // two merged-pass blocks' prefix scratch per block (wide_blocks is
+        // at least 16)
+        TimedLaunch tl("k_listcount_w128", st);
+        hipLaunchKernelGGL(k_listcount_w128, dim3((unsigned)(L.wide_blocks / 2)), dim3(kWBlock),
                            sums_bytes(1, nd, nm), st, A, A.wide_p);
       }
       {

@@ -29,7 +29,7 @@ CALIB_BYTES = 1 << 30
 KERNEL_SRC = {
     "k_paths": "tc_sample.hip", "k_listcount_reg": "tc_sample.hip",
     "k_listcount_lds": "tc_sample.hip", "k_listcount_wide": "tc_sample.hip",
-    "k_listcount_big": "tc_sample.hip",
+    "k_listcount_big": "tc_sample.hip", "k_listcount_w128": "tc_sample.hip",
     "k_windows": "tc_weights.hip", "k_mp_rank": "tc_weights.hip", "k_combine": "tc_weights.hip",
     "k_scan_tiles": "tc_weights.hip", "k_scan_apply": "tc_weights.hip",
     "k_tree": "tc_weights.hip", "k_radix_scatter": "tc_build.hip",

@@ -406,6 +406,46 @@ def test_listcount_counts_beyond_2e64(tcb, torch_mod):
     assert (int(Rq.status.item()) & 0xFFFFFFFF) == 2 | (1 << 8)
 
 
+@pytest.mark.parametrize("per_block", [40, 200])
+def test_long_lists_counts_beyond_2e64(tcb, torch_mod, per_block):
+    """Counts beyond 2^64 from the LDS-key pass (lists of 280 entries) and
+    from the merged pass (1,400): the planted spines A->B->C->D (64 x 1 x 64)
+    and a motif with 13 lists alternating A->D and B->D, whose edges come in
+    13 increasing time blocks of per_block edges (blocks alternate the two
+    pairs).  D has no out-edges and A no in-edges, so W is the 4,096 spines
+    and every draw is one of them; its chain count is above 2^64 (6.7e20 and
+    8.2e29).  The 128-bit merged pass takes these items: cnt and the
+    saturated X equal the oracle's, nothing is flagged."""
+    A_, B_, C_, D_ = 0, 1, 2, 3
+    n_lists = 13
+    pairs = [(A_, D_) if r % 2 == 0 else (B_, D_) for r in range(n_lists)]
+    motif = [(A_, B_), (B_, C_), (C_, D_)] + pairs
+    p = q = 64
+    src = [A_] * p + [B_] + [C_] * q
+    dst = [B_] * p + [C_] + [D_] * q
+    t = list(range(1, p + 1)) + [p + 1] + list(range(p + 2, p + q + 2))
+    base = 1000
+    for (a, b) in pairs:
+        src += [a] * per_block
+        dst += [b] * per_block
+        t += list(range(base, base + per_block))
+        base += per_block + 5
+    g = sg.TemporalGraph(4, np.array(src, np.int32), np.array(dst, np.int32),
+                         np.array(t, np.int64))
+    G, og = build_both(tcb, torch_mod, g)
+    delta = base + 10
+    Wt = tcb.tc_path_weights(G, delta)
+    ow = og.weights(delta)
+    assert Wt.total() == p * q
+    k = 6000
+    R, E = check_sample(tcb, G, Wt, og, ow, [motif], k, seed=3, per_sample=True)
+    assert E.status == 0 and int(E.hits[0]) == k
+    assert E.cnt[0] > k * 2**64
+    assert (E.X[0] == np.uint64(2**64 - 1)).all()
+    R, E = check_sample(tcb, G, Wt, og, ow, [M40, motif], k, seed=4, per_sample=False)
+    assert E.status == 0 and R.counts()[1] == E.cnt[1] > 2**64
+
+
 LONG_CASES = {
     # name: (A->D edges, B->D edges, time span of the lists, delta offset)
     "wide_balanced": (3000, 2000, 4000, 0),
