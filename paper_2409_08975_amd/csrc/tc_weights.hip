@@ -154,13 +154,15 @@ struct RankOut {
 
 // record words per edge: the delta-free bound and one rank per delta,
 // rounded up to 8 or a multiple of 16 bytes
-static inline int rec_stride(int nd) {
+__host__ __device__ constexpr int rec_stride(int nd) {
   const int w = 1 + nd;
   return w <= 2 ? 2 : ((w + 3) / 4) * 4;
 }
 
-// rank of every query of the tile, stored as M says
-template <bool UPPER>
+// rank of every query of the tile, stored as MODE says (a compile-time
+// mode: the record mode's uniform state would otherwise cost the plain
+// passes scalar registers and a quarter of their resident blocks)
+template <bool UPPER, int MODE, int NR = 0>
 __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, KeyCols D, int64_t nd,
                                                       const uint32_t* __restrict__ split,
                                                       RankMode M, uint32_t* __restrict__ out,
@@ -188,14 +190,13 @@ __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, Key
     const int32_t qv = Q.v[i];
     const int64_t qt = Q.t[i] + Q.shift;
     // inputs of the store, loaded before the search
-    const uint32_t f = M.mode != RO_PLAIN ? F[i] : 0u;
+    const uint32_t f = MODE != RO_PLAIN ? F[i] : 0u;
     int64_t e = 0;
     uint32_t w[kMaxRecWords];
-    if (M.mode == RO_REC) {
+    if (MODE == RO_REC) {
       e = eid[i];
 #pragma unroll
-      for (int j = 0; j < kMaxRecWords - 1; ++j)
-        w[1 + j] = j < M.nr ? M.R[j & (kMaxDeltas - 1)][i] : 0u;
+      for (int j = 0; j < kMaxRecWords - 1; ++j) w[1 + j] = j < NR ? M.R[j][i] : 0u;
     }
     int lo = 0, n = nd_t;
     while (n > 0) {
@@ -206,24 +207,37 @@ __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, Key
       n = go ? n - half - 1 : half;
     }
     const uint32_t rank = (uint32_t)(i0 + lo);
-    if (M.mode == RO_PLAIN) {
+    if (MODE == RO_PLAIN) {
       out[i] = rank;
-    } else if (M.mode == RO_SIDE1) {
+    } else if (MODE == RO_SIDE1) {
       lo_out[i] = M.after ? f : rank;
       len_out[i] = M.after ? rank - f : f - rank;
-    } else if (M.stride == 2) {
+    } else if (rec_stride(NR + 1) == 2) {
       reinterpret_cast<uint2*>(rec)[e] = make_uint2(f, rank);
     } else {
+      constexpr int kStride = rec_stride(NR + 1);
       w[0] = f;
+      w[1 + NR] = rank;
+      uint4* r4 = reinterpret_cast<uint4*>(rec) + e * (kStride / 4);
 #pragma unroll
-      for (int j = 0; j < kMaxRecWords - 1; ++j)
-        if (j == M.nr) w[1 + j] = rank;
-      uint4* r4 = reinterpret_cast<uint4*>(rec) + e * (M.stride / 4);
-#pragma unroll
-      for (int q = 0; q < kMaxRecWords / 4; ++q)
-        if (q < M.stride / 4)
-          r4[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+      for (int q = 0; q < kStride / 4; ++q)
+        r4[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
     }
+  }
+}
+
+// the record pass for nr other deltas (0..7)
+template <bool UPPER>
+static decltype(&k_mp_rank<UPPER, RO_REC, 0>) rec_kernel(int nr) {
+  switch (nr) {
+    case 0: return k_mp_rank<UPPER, RO_REC, 0>;
+    case 1: return k_mp_rank<UPPER, RO_REC, 1>;
+    case 2: return k_mp_rank<UPPER, RO_REC, 2>;
+    case 3: return k_mp_rank<UPPER, RO_REC, 3>;
+    case 4: return k_mp_rank<UPPER, RO_REC, 4>;
+    case 5: return k_mp_rank<UPPER, RO_REC, 5>;
+    case 6: return k_mp_rank<UPPER, RO_REC, 6>;
+    default: return k_mp_rank<UPPER, RO_REC, 7>;
   }
 }
 
@@ -667,14 +681,16 @@ tc_status path_weights_batch(const tc_graph* g, const int64_t* deltas, int nd,
     }
     auto rank = [&](int jb, const RankOut& O) {
       const SplitJob& S = J.j[jb];
-      if (S.upper)
-        hipLaunchKernelGGL(k_mp_rank<true>, dim3(rb), dim3(kMPBlock), 0, st, S.Q, m, S.D, m,
-                           (const uint32_t*)S.split, O.M, O.out, O.F, O.lo, O.len, O.rec, O.eid,
-                           gst);
+      auto kern = k_mp_rank<false, RO_PLAIN>;
+      if (O.M.mode == RO_PLAIN)
+        kern = S.upper ? k_mp_rank<true, RO_PLAIN> : k_mp_rank<false, RO_PLAIN>;
+      else if (O.M.mode == RO_SIDE1)
+        kern = S.upper ? k_mp_rank<true, RO_SIDE1> : k_mp_rank<false, RO_SIDE1>;
       else
-        hipLaunchKernelGGL(k_mp_rank<false>, dim3(rb), dim3(kMPBlock), 0, st, S.Q, m, S.D, m,
-                           (const uint32_t*)S.split, O.M, O.out, O.F, O.lo, O.len, O.rec, O.eid,
-                           gst);
+        kern = S.upper ? rec_kernel<true>(O.M.nr) : rec_kernel<false>(O.M.nr);
+      hipLaunchKernelGGL(kern, dim3(rb), dim3(kMPBlock), 0, st, S.Q, m, S.D, m,
+                         (const uint32_t*)S.split, O.M, O.out, O.F, O.lo, O.len, O.rec, O.eid,
+                         gst);
     };
     // Temporaries live in arrays that k_combine writes last: the first
     // set's lo_out holds side 1's delta-free bound while side 1's delta
