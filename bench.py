@@ -82,7 +82,7 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="copy 1 GiB device-to-device first (reference for HBM counters)")
     ap.add_argument("--profile-run", action="store_true",
-                    help="one step of the headline workload and nothing else (for counter runs)")
+                    help="one step of the workload and nothing else (for counter runs)")
     return ap.parse_args()
 
 
@@ -629,6 +629,14 @@ def run_batched(args):
     G.check()
     Ws, t_w = event_ms(lambda: tcb.tc_path_weights_batch(G, deltas), stream)
     log(f"[bench] eager build {t_build:.1f} ms, weights of {nd} deltas {t_w:.1f} ms")
+    if args.profile_run:
+        # one eager pass with the default launch shape (for counter runs)
+        ws = torch.empty(tcb.batch_workspace_bytes(k, nd, nm), dtype=torch.uint8, device=dev)
+        res, t_s = event_ms(lambda: tcb.tc_batch_estimate(G, Ws, motifs, k, seed, workspace=ws),
+                            stream)
+        print(json.dumps({"profile_run": "batched", "build_ms": t_build, "weights_ms": t_w,
+                          "sample_ms": t_s, "profile_steps": 1}), flush=True)
+        return
     best, probe_ms = tcb.tc_autotune(G, Ws, motifs, 2**22, seed=7)
     log(f"[bench] autotuned {best.as_dict()} ({probe_ms:.2f} ms per 2^22-sample probe)")
     ws = torch.empty(tcb.batch_workspace_bytes(k, nd, nm), dtype=torch.uint8, device=dev)
@@ -717,24 +725,25 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
-    if args.workload == "batched":
-        run_batched(args)
-        return
     import torch
-
-    import paper_2409_08975_amd as tcb
-    import synthgraph as sg
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream()
     if args.calib_copy:
         a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.workload == "batched":
+        run_batched(args)
+        return
+
+    import paper_2409_08975_amd as tcb
+    import synthgraph as sg
+
+    stream = torch.cuda.current_stream()
 
     if args.workload in ("medium", "tiny"):
         extra, g = run_medium_like(args, tcb, sg, args.workload, stream, dev,

@@ -925,8 +925,12 @@ __global__ __launch_bounds__(kWave) void k_listcount_reg(SampleArgs A) {
 // current list sit in LDS as 32-bit offsets from the smallest head, the
 // prefix sums in per-wavefront scratch.  Longer lists or wider windows go to
 // the merged block-per-item pass.
+// CAP (512 or 1,024, at least the lds_list_cap knob) sizes the key tiles:
+// at 512 a wavefront takes 4 KB of LDS and eight fit per SIMD, at 1,024
+// five.
+template <int CAP>
 __global__ __launch_bounds__(kWave) void k_listcount_lds(SampleArgs A, uint64_t* pscratch) {
-  __shared__ uint32_t s_key[2][kKeyCap];
+  __shared__ uint32_t s_key[2][CAP];
   uint64_t* s_p[2] = {pscratch + (uint64_t)blockIdx.x * 2 * (kKeyCap + 1),
                       pscratch + ((uint64_t)blockIdx.x * 2 + 1) * (kKeyCap + 1)};
   const int lane = threadIdx.x;
@@ -1054,7 +1058,7 @@ constexpr int kWBlock = 256;
 constexpr int kWWaves = kWBlock / kWave;
 constexpr int kWPer = 4;
 constexpr int kWTile = kWBlock * kWPer;  // entries of B per step, of A per tile
-constexpr int kDefaultWideBlocks = 1024;
+constexpr int kDefaultWideBlocks = 2048;
 constexpr int kMaxWideBlocks = 2048;
 
 // Seven wavefronts per SIMD (72 VGPRs): measured 7% faster than the
@@ -1779,8 +1783,12 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
       }
       {
         TimedLaunch tl("k_listcount_lds", st);
-        hipLaunchKernelGGL(k_listcount_lds, dim3((unsigned)L.fast_waves), dim3(kWave),
-                           sums_bytes(1, nd, nm), st, A, A.fast_p);
+        if (A.lds_cap <= 512)
+          hipLaunchKernelGGL(k_listcount_lds<512>, dim3((unsigned)L.fast_waves), dim3(kWave),
+                             sums_bytes(1, nd, nm), st, A, A.fast_p);
+        else
+          hipLaunchKernelGGL(k_listcount_lds<kKeyCap>, dim3((unsigned)L.fast_waves), dim3(kWave),
+                             sums_bytes(1, nd, nm), st, A, A.fast_p);
       }
       {
         TimedLaunch tl("k_listcount_wide", st);
