@@ -218,14 +218,14 @@ typedef struct tc_result {
  *   path_blocks persistent blocks of the path kernel (0 = one per tile)
  *   reg_waves   wavefronts of the register ListCount pass
  *   fast_waves  wavefronts of the LDS-key ListCount pass (64..8192)
- *   wide_blocks 256-thread blocks of the merged ListCount pass for lists
- *               over lds_list_cap entries (16..2048; 1 MiB of workspace each)
+ *   wide_blocks 128-thread blocks of the merged ListCount pass for lists
+ *               over lds_list_cap entries (16..4096; 1 MiB of workspace each)
  *   reg_list_cap  longest list the register ListCount pass takes: 128 or
  *               256 entries (two or four 64-entry chunks per lane); items
  *               with a longer list go to the LDS-key pass
  *   lds_list_cap  longest list the one-wavefront LDS-key pass takes
  *               (256..1024); items with a longer list go to the merged
- *               pass, where 256 lanes work on one item instead of 64 */
+ *               pass, where 128 lanes work on one item instead of 64 */
 typedef struct {
   int32_t chunk_log2;
   int32_t path_blocks;

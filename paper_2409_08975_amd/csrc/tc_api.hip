@@ -339,7 +339,7 @@ tc_status tc_autotune(const tc_graph* g, const tc_weights* const* w, int32_t n_d
       {0, 1024, 4096},      // path_blocks
       {20480, 40960, 81920}, // reg_waves
       {2560, 5120, 8192},   // fast_waves
-      {512, 1024, 2048},    // wide_blocks
+      {1024, 2048, 4096},   // wide_blocks
       {128, 256, 256},      // reg_list_cap: lanes hold 2 or 4 list entries
       {256, 512, 1024},     // lds_list_cap: 64 lanes per item up to it, 256 above
   };

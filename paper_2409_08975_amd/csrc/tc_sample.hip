@@ -35,7 +35,7 @@
 //   k_listcount_lds  one wavefront per item, lists up to 1,024 entries: the
 //                    same recursion with keys in LDS and prefix sums in
 //                    per-wavefront scratch.
-//   k_listcount_wide one 256-thread block per item, lists up to 65,536
+//   k_listcount_wide one 128-thread block per item, lists up to 65,536
 //                    entries: each level as a merge of L_{r-1} and L_r in
 //                    LDS tiles, prefix sums in per-block scratch.
 //   k_listcount_w128 items whose level total reached 2^64 in one of the
@@ -1042,7 +1042,7 @@ __global__ __launch_bounds__(kWave) void k_listcount_lds(SampleArgs A, uint64_t*
   sums_flush<1>(A);
 }
 
-// Block-per-item ListCount for lists up to kWideCap entries (256 threads).
+// Block-per-item ListCount for lists up to kWideCap entries (128 threads).
 // Level r is a merge of the sorted times of L_{r-1} (A) and L_r (B): a step
 // stages a tile of A's times and of P_{r-1} in LDS and gives every thread four
 // consecutive entries of B; an entry is settled in this step when its time
@@ -1051,15 +1051,15 @@ __global__ __launch_bounds__(kWave) void k_listcount_lds(SampleArgs A, uint64_t*
 // and P_r over the settled entries is a block scan with a carry across steps.
 // Settled entries are a prefix of B's tile.  If all are settled the next step
 // starts A at the last one's position; otherwise the tile is used up and A
-// restarts past it, first jumping by a 256-way probe of A to within one tile
+// restarts past it, first jumping by a 128-way probe of A to within one tile
 // of the first unsettled time.  Each step settles B's tile or moves A by a
 // full tile, so a level reads A, B and P_{r-1} once, in coalesced tiles.
-constexpr int kWBlock = 256;
+constexpr int kWBlock = 128;
 constexpr int kWWaves = kWBlock / kWave;
 constexpr int kWPer = 4;
 constexpr int kWTile = kWBlock * kWPer;  // entries of B per step, of A per tile
-constexpr int kDefaultWideBlocks = 2048;
-constexpr int kMaxWideBlocks = 2048;
+constexpr int kDefaultWideBlocks = 4096;
+constexpr int kMaxWideBlocks = 4096;
 
 // Seven wavefronts per SIMD (72 VGPRs): measured 7% faster than the
 // compiler's unbounded 105 VGPRs (4 per SIMD) on the batched workload.

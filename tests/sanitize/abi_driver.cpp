@@ -58,6 +58,20 @@ int main() {
   if (tc_exhaustive_count(&g, &w, &M, 1, 0, 0, (void*)256, 1, &r, nullptr) != TC_E_ARG) ++bad;
   tc_class cz{0, 0, 0, 0};
   if (tc_path_weights_class(&g, 5, &cz, (void*)1, 0, nullptr, &w) != TC_E_ARG) ++bad;
+  // batched Preprocess: sizes and host errors
+  size_t b1 = 0, b2 = 0;
+  if (tc_weights_batch_workspace_bytes(1000, 1, &b1) != TC_OK) ++bad;
+  if (tc_weights_batch_workspace_bytes(1000, 2, &b2) != TC_OK || b2 <= b1) ++bad;
+  if (tc_weights_batch_workspace_bytes(1000, 9, &b2) != TC_E_ARG) ++bad;
+  tc_weights wb[8];
+  const int64_t ds[3] = {5, -1, 7};
+  if (tc_path_weights_batch(&g, ds, 3, nullptr, (void*)256, (size_t)1 << 40, nullptr, wb) !=
+      TC_E_ARG)
+    ++bad;
+  if (tc_path_weights_batch(&g, ds, 1, &cz, (void*)256, (size_t)1 << 40, nullptr, wb) != TC_E_ARG)
+    ++bad;
+  if (tc_path_weights_batch(&g, ds, 1, nullptr, (void*)256, 16, nullptr, wb) != TC_E_WORKSPACE)
+    ++bad;
   std::printf("abi driver: %d anchored random motifs, %d failures\n", anchored, bad);
   return bad == 0 && anchored > 0 ? 0 : 1;
 }
