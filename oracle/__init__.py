@@ -61,6 +61,10 @@ def lib():
         L.or_sample_ex.argtypes = [P, I64, P, P, P, P, P, P, P, ctypes.c_int, U64, U64, U32,
                                    U64, P, P, P, P, P, P, P, P, P, ctypes.c_int]
         L.or_proposal_scan.argtypes = [P, P, P, P, P]
+        L.or_sample_win.argtypes = [P, I64, P, P, P, P, P, P, P, P, P, P, ctypes.c_int, U64, U64,
+                                    U32, U64, P, P, P, P, P, P, P, P, P, P, ctypes.c_int]
+        L.or_window_factors.argtypes = [P, ctypes.c_int, U32, P, P]
+        L.or_proposal_window.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P]
         L.or_features.argtypes = [P, I64, P, P, P, P, P, ctypes.c_int]
         L.or_exhaustive.argtypes = [P, P, I64, P, P, P, P, P, P, P, P, ctypes.c_int]
         L.or_list_lengths.argtypes = [P, P, I64, I32, I32, I32, P]
@@ -150,6 +154,8 @@ class Weights:
 
     h: np.ndarray | None = None  # proposal h_int per scan position (S is then Q)
     cls: bytes = SPINE_CLASS     # the anchor class of the windows
+    ps1: np.ndarray | None = None  # window proposal: prefix sums of side 1's CSR factors
+    ps3: np.ndarray | None = None  # ... and of side 3's
 
     @property
     def W(self) -> int:
@@ -248,8 +254,11 @@ class OracleGraph:
             P = np.zeros(k, np.uint32)
         hq = _p(w.h) if w.h is not None else null
         c = np.frombuffer(w.cls, dtype=np.uint8).copy()
-        st = lib().or_sample_cls(self.h, w.delta, _p(c), _p(w.lo_in), _p(w.a), _p(w.lo_out),
-                                 _p(w.b), _p(w.S), hq, _p(mb), nm, int(k), int(seed), int(stream),
+        p1 = _p(w.ps1) if w.ps1 is not None else null
+        p3 = _p(w.ps3) if w.ps3 is not None else null
+        st = lib().or_sample_win(self.h, w.delta, _p(c), _p(w.lo_in), _p(w.a), _p(w.lo_out),
+                                 _p(w.b), _p(w.S), hq, p1, p3, _p(mb), nm, int(k), int(seed),
+                                 int(stream),
                                  int(i0), _p(e1) if per_sample else null,
                                  _p(e2) if per_sample else null, _p(e3) if per_sample else null,
                                  _p(X) if per_sample else null, _p(P) if per_sample else null,
@@ -299,6 +308,42 @@ class OracleGraph:
         Q = np.zeros(self.m + 1, np.uint64)
         st = lib().or_proposal_scan(self.h, _p(w.a), _p(w.b), _p(h), _p(Q))
         return Weights(w.delta, w.lo_in, w.a, w.lo_out, w.b, Q, st, h, w.cls)
+
+    def window_factors(self, quarter: int, cap: int):
+        """Per-entry factors of the window proposal (not part of the paper):
+        (f_in over in-CSR positions, f_out over out-CSR positions), each
+        min(cap, about (1 + degree of the far endpoint)^(quarter / 4)) in
+        integer square roots."""
+        f_in = np.zeros(self.m, np.uint32)
+        f_out = np.zeros(self.m, np.uint32)
+        st = lib().or_window_factors(self.h, int(quarter), int(cap), _p(f_in), _p(f_out))
+        if st:
+            raise ValueError(f"bad window factor parameters (status {st})")
+        return f_in, f_out
+
+    def proposal_window(self, w: Weights, h_int=None, f_in=None, f_out=None) -> Weights:
+        """Weight set of the window proposal q_p = h_p * G1_p * G3_p: each
+        side's edge is then drawn with probability proportional to its CSR
+        entry's factor (f_in for an in-edge side, f_out for an out-edge
+        side; None = 1)."""
+        null = ctypes.c_void_p(0)
+        h = None if h_int is None else np.ascontiguousarray(h_int, dtype=np.uint32)
+        fi = None if f_in is None else np.ascontiguousarray(f_in, dtype=np.uint32)
+        fo = None if f_out is None else np.ascontiguousarray(f_out, dtype=np.uint32)
+        ps_in = np.zeros(self.m + 1, np.uint64) if fi is not None else None
+        ps_out = np.zeros(self.m + 1, np.uint64) if fo is not None else None
+        Q = np.zeros(self.m + 1, np.uint64)
+        c = np.frombuffer(w.cls, dtype=np.uint8).copy()
+        st = lib().or_proposal_window(self.h, _p(c), _p(w.lo_in), _p(w.a), _p(w.lo_out), _p(w.b),
+                                      _p(h) if h is not None else null,
+                                      _p(fi) if fi is not None else null,
+                                      _p(fo) if fo is not None else null,
+                                      _p(ps_in) if ps_in is not None else null,
+                                      _p(ps_out) if ps_out is not None else null, _p(Q))
+        mode1, mode3 = w.cls[0], w.cls[2]
+        side = {1: ps_in, 2: ps_out, 0: None}
+        return Weights(w.delta, w.lo_in, w.a, w.lo_out, w.b, Q, st, h, w.cls,
+                       side[mode1], side[mode3])
 
     def features(self, w: Weights, threads: int | None = None) -> np.ndarray:
         """Per-edge proposal features [m, 8] in binary64 (scan order)."""

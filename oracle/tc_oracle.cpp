@@ -620,9 +620,19 @@ int or_check_motif(void* h, const uint8_t* motif, int64_t delta, int32_t e1, int
 // unbiased per-sample value is Y = X * Q / h_p.  cnt then accumulates
 // floor(X * 2^64 / h_p) in 128 bits and est = (cnt * 2^-64 / k) * Q.
 // m2 (null = off) receives sum over samples of (X / h_p)^2 in binary64.
-int or_sample_cls(void* hg, int64_t delta, const uint8_t* cls, const uint32_t* lo1,
+//
+// With window factors (ps1 / ps3: prefix sums of per-entry factors over the
+// CSR that side 1 / side 3 draws from, null = none; not part of the paper),
+// S must be the scan of q_p = h_p * G1_p * G3_p, G the sum of the factors
+// over the side's window, and each side's edge is the window entry j drawn
+// with probability g_j / G (a uniform integer u in [0, G), then the entry
+// whose prefix interval holds u).  A path then has probability
+// h_p g1 g3 / Q and cnt accumulates floor(X * 2^64 / (h_p g1 g3)); the
+// product must stay below 2^32 (else OR_OVERFLOW).
+int or_sample_win(void* hg, int64_t delta, const uint8_t* cls, const uint32_t* lo1,
                   const uint32_t* a, const uint32_t* lo3, const uint32_t* b, const uint64_t* S,
-                  const uint32_t* hq, const uint8_t* motifs, int n_motifs, uint64_t k,
+                  const uint32_t* hq, const uint64_t* ps1, const uint64_t* ps3,
+                  const uint8_t* motifs, int n_motifs, uint64_t k,
                   uint64_t seed, uint32_t stream, uint64_t i0, int32_t* e1o, int32_t* e2o,
                   int32_t* e3o, uint64_t* Xo, uint32_t* Po, uint64_t* cnt, uint64_t* hits,
                   double* est, double* m2o, uint64_t* xmax, int nthreads) {
@@ -632,6 +642,9 @@ int or_sample_cls(void* hg, int64_t delta, const uint8_t* cls, const uint32_t* l
   std::vector<Motif> Ms;
   if (parse_motifs(motifs, n_motifs, K, &Ms) != OR_OK) return OR_ARG;
   const uint64_t W = S[G.m];  // W, or Q with a proposal
+  if (K.mode[0] == SIDE_NONE) ps1 = nullptr;
+  if (K.mode[1] == SIDE_NONE) ps3 = nullptr;
+  const bool is_ = hq || ps1 || ps3;  // importance sampling
   std::vector<u128> c(n_motifs, 0);
   std::vector<uint64_t> hh(n_motifs, 0), mx(n_motifs, 0);
   std::vector<double> mm(n_motifs, 0.0);
@@ -663,36 +676,66 @@ int or_sample_cls(void* hg, int64_t delta, const uint8_t* cls, const uint32_t* l
       if (!ok) { pst[tid] |= OR_RNG; continue; }
       // pick e with probability w_e / W (or q_e / Q): S[p] <= r < S[p+1]
       int64_t p = std::upper_bound(S, S + G.m + 1, r) - S - 1;
-      // then a uniform edge in each side's window (an absent side has one
-      // position and takes no edge)
+      // then an edge in each side's window (an absent side has one
+      // position and takes no edge): uniform, or by the window factors
+      auto pick = [&](const uint64_t* ps, uint32_t lo, uint32_t len, int word, uint32_t* j,
+                      uint64_t* gj) -> bool {
+        uint64_t span = len;
+        if (ps) {
+          span = ps[lo + len] - ps[lo];
+          if (span > 0xFFFFFFFFull) {
+            pst[tid] |= OR_OVERFLOW;
+            span = 0xFFFFFFFFull;
+          }
+        }
+        uint32_t u = 0;
+        bool got = false;
+        for (uint32_t n = 0; n < (uint32_t)kMaxAttempts && !got; ++n) {
+          draw_block(seed, stream, i, n, x);
+          got = lemire32(x[word], (uint32_t)span, &u);
+        }
+        if (!got) return false;
+        *j = u;
+        *gj = 1;
+        if (ps) {
+          // the entry whose prefix interval [ps[lo+j] - ps[lo], ps[lo+j+1] - ps[lo]) holds u
+          *j = (uint32_t)(std::upper_bound(ps + lo, ps + lo + len + 1, ps[lo] + u) - (ps + lo) -
+                          1);
+          *gj = ps[lo + *j + 1] - ps[lo + *j];
+        }
+        return true;
+      };
       uint32_t j1 = 0, j3 = 0;
-      ok = false;
-      for (uint32_t n = 0; n < (uint32_t)kMaxAttempts && !ok; ++n) {
-        draw_block(seed, stream, i, n, x);
-        ok = lemire32(x[2], a[p], &j1);
+      uint64_t g1 = 1, g3 = 1;
+      if (!pick(K.mode[0] == SIDE_NONE ? nullptr : ps1, lo1[p], a[p], 2, &j1, &g1)) {
+        pst[tid] |= OR_RNG;
+        continue;
       }
-      if (!ok) { pst[tid] |= OR_RNG; continue; }
-      ok = false;
-      for (uint32_t n = 0; n < (uint32_t)kMaxAttempts && !ok; ++n) {
-        draw_block(seed, stream, i, n, x);
-        ok = lemire32(x[3], b[p], &j3);
+      if (!pick(K.mode[1] == SIDE_NONE ? nullptr : ps3, lo3[p], b[p], 3, &j3, &g3)) {
+        pst[tid] |= OR_RNG;
+        continue;
       }
-      if (!ok) { pst[tid] |= OR_RNG; continue; }
       int32_t e2 = G.out_ord[p];
       int32_t e1 = K.mode[0] == SIDE_NONE ? -1 : side_edge(G, K.mode[0], lo1[p] + j1);
       int32_t e3 = K.mode[1] == SIDE_NONE ? -1 : side_edge(G, K.mode[1], lo3[p] + j3);
       if (e1o) { e1o[ii] = e1; e2o[ii] = e2; e3o[ii] = e3; }
       if (Po) Po[ii] = (uint32_t)p;
-      const uint32_t hp = hq ? hq[p] : 1u;
+      // the path's proposal factor h_p g1 g3 (below 2^32)
+      u128 hpw = (u128)(hq ? hq[p] : 1u) * g1 * g3;
+      if (hpw > 0xFFFFFFFFull) {
+        pst[tid] |= OR_OVERFLOW;
+        hpw = 0xFFFFFFFFull;
+      }
+      const uint32_t hp = (uint32_t)hpw;
       for (int j = 0; j < n_motifs; ++j) {
         u128 X = 0;
         int st = check_motif(G, Ms[j], delta, e1, e2, e3, &X);
         // an importance-sampling term floor(X 2^64 / h) needs X < 2^64
-        if (hq && (X >> 64)) st |= OR_OVERFLOW;
+        if (is_ && (X >> 64)) st |= OR_OVERFLOW;
         // an overflow also names its motif (bit 8 + j)
         pst[tid] |= st | ((st & OR_OVERFLOW) ? (1 << (8 + j)) : 0);
         if (Xo) Xo[(uint64_t)j * k + ii] = sat64(X);
-        u128 add = hq ? ((X << 64) / hp) : X;
+        u128 add = is_ ? ((X << 64) / hp) : X;
         if (!add_u128(&pc[tid][j], add)) pst[tid] |= OR_OVERFLOW | (1 << (8 + j));
         ph[tid][j] += X > 0;
         px[tid][j] = std::max(px[tid][j], sat64(X));
@@ -716,7 +759,7 @@ int or_sample_cls(void* hg, int64_t delta, const uint8_t* cls, const uint32_t* l
     hits[j] = hh[j];
     if (W == 0) {
       est[j] = 0.0;
-    } else if (hq) {
+    } else if (is_) {
       const double cd = std::ldexp((double)c[j], -64);
       est[j] = (cd / (double)k) * (double)W;
     } else {
@@ -726,6 +769,17 @@ int or_sample_cls(void* hg, int64_t delta, const uint8_t* cls, const uint32_t* l
     if (xmax) xmax[j] = mx[j];
   }
   return status;
+}
+
+int or_sample_cls(void* hg, int64_t delta, const uint8_t* cls, const uint32_t* lo1,
+                  const uint32_t* a, const uint32_t* lo3, const uint32_t* b, const uint64_t* S,
+                  const uint32_t* hq, const uint8_t* motifs, int n_motifs, uint64_t k,
+                  uint64_t seed, uint32_t stream, uint64_t i0, int32_t* e1o, int32_t* e2o,
+                  int32_t* e3o, uint64_t* Xo, uint32_t* Po, uint64_t* cnt, uint64_t* hits,
+                  double* est, double* m2o, uint64_t* xmax, int nthreads) {
+  return or_sample_win(hg, delta, cls, lo1, a, lo3, b, S, hq, nullptr, nullptr, motifs, n_motifs,
+                       k, seed, stream, i0, e1o, e2o, e3o, Xo, Po, cnt, hits, est, m2o, xmax,
+                       nthreads);
 }
 
 int or_sample_ex(void* hg, int64_t delta, const uint32_t* lo_in, const uint32_t* a,
@@ -831,6 +885,82 @@ int or_proposal_scan(void* hg, const uint32_t* a, const uint32_t* b, const uint3
   for (int64_t p = 0; p < G.m; ++p) {
     Q[p] = (uint64_t)run;
     run += (u128)((uint64_t)a[p] * (uint64_t)b[p]) * hq[p];
+    if (run > kU64Max) st = OR_OVERFLOW;
+  }
+  Q[G.m] = (uint64_t)run;
+  return st;
+}
+
+// Window factors (not part of the paper): every in-CSR entry (an edge
+// x -> u) gets g(deg x) and every out-CSR entry (an edge v -> y) g(deg y),
+// deg the total degree (in + out) of the far endpoint, with
+//   g(d) = min(cap, F_q(1 + d)),  F_0 = 1, F_1 = r4, F_2 = r2, F_3 = r2 r4,
+//   F_4 = r2^2, where r2 = isqrt(1 + d) and r4 = isqrt(r2)
+// (integer square roots, so about (1 + d)^(q / 4)).
+static uint64_t isqrt64(uint64_t v) {
+  uint64_t r = (uint64_t)std::sqrt((double)v);
+  while (r > 0 && r * r > v) --r;
+  while ((r + 1) * (r + 1) <= v) ++r;
+  return r;
+}
+
+static uint32_t degree_factor(uint64_t d, int quarter, uint32_t cap) {
+  const uint64_t r2 = isqrt64(1 + d), r4 = isqrt64(r2);
+  const uint64_t f = quarter == 0 ? 1 : quarter == 1 ? r4 : quarter == 2 ? r2
+                   : quarter == 3 ? r2 * r4 : r2 * r2;
+  return (uint32_t)std::min<uint64_t>(f, cap);
+}
+
+int or_window_factors(void* hg, int quarter, uint32_t cap, uint32_t* f_in, uint32_t* f_out) {
+  Graph& G = *(Graph*)hg;
+  if (quarter < 0 || quarter > 4 || cap < 1 || cap > 65535) return OR_ARG;
+  auto deg = [&](int32_t v) -> uint64_t {
+    return (uint64_t)(G.out_off[v + 1] - G.out_off[v]) + (uint64_t)(G.in_off[v + 1] - G.in_off[v]);
+  };
+  for (int64_t i = 0; i < G.m; ++i) {
+    f_in[i] = degree_factor(deg(G.src[G.in_ord[i]]), quarter, cap);
+    f_out[i] = degree_factor(deg(G.dst[G.out_ord[i]]), quarter, cap);
+  }
+  return OR_OK;
+}
+
+// Scan of the window proposal q_p = h_p * G1_p * G3_p (h null = 1): G of a
+// side is the sum of the factors of its CSR (f_in for an in-edge side,
+// f_out for an out-edge side; a null array counts 1 per entry) over the
+// side's window, 1 for an absent side.  ps_in / ps_out (m + 1 words each)
+// receive the prefix sums of f_in / f_out when given.  OR_OVERFLOW if a
+// window sum reaches 2^32 or Q reaches 2^64.
+int or_proposal_window(void* hg, const uint8_t* cls, const uint32_t* lo1, const uint32_t* a,
+                       const uint32_t* lo3, const uint32_t* b, const uint32_t* hq,
+                       const uint32_t* f_in, const uint32_t* f_out, uint64_t* ps_in,
+                       uint64_t* ps_out, uint64_t* Q) {
+  Graph& G = *(Graph*)hg;
+  Class K;
+  if (!parse_class(cls, &K)) return OR_ARG;
+  if (f_in) {
+    uint64_t s = 0;
+    for (int64_t i = 0; i < G.m; ++i) { ps_in[i] = s; s += f_in[i]; }
+    ps_in[G.m] = s;
+  }
+  if (f_out) {
+    uint64_t s = 0;
+    for (int64_t i = 0; i < G.m; ++i) { ps_out[i] = s; s += f_out[i]; }
+    ps_out[G.m] = s;
+  }
+  int st = OR_OK;
+  auto side_sum = [&](int mode, uint32_t lo, uint32_t len) -> u128 {
+    if (mode == SIDE_NONE) return 1;
+    const uint64_t* ps = mode == SIDE_IN ? (f_in ? ps_in : nullptr) : (f_out ? ps_out : nullptr);
+    const uint64_t g = ps ? ps[lo + len] - ps[lo] : len;
+    if (g > 0xFFFFFFFFull) st = OR_OVERFLOW;
+    return g;
+  };
+  u128 run = 0;
+  for (int64_t p = 0; p < G.m; ++p) {
+    Q[p] = (uint64_t)run;
+    const u128 q = (u128)(hq ? hq[p] : 1u) * side_sum(K.mode[0], lo1[p], a[p]) *
+                   side_sum(K.mode[1], lo3[p], b[p]);
+    run += q;
     if (run > kU64Max) st = OR_OVERFLOW;
   }
   Q[G.m] = (uint64_t)run;
