@@ -428,10 +428,12 @@ def cpu_one_thread(g, delta, motifs, k, seed, n_sample):
 def learned_vs_method(tcb, G, Wt, motif, seeds, k_ref, stream):
     """Relative error against C_ref (the method at k_ref samples on its own
     stream) at k = 10^5, 10^6, 10^7 over `seeds` seeds, for the method and
-    for two learned proposals (labels on another stream): the configured one
-    (eps = 0.1, labels y = [X > 0], scores as the network gives them) and a
-    tuned one (eps = 0.01, soft labels min(1, X / 64), scores normalised by
-    their maximum), plus the time of each part."""
+    for three proposals (labels and pilots on another stream): the
+    configured centre proposal (eps = 0.1, labels y = [X > 0], scores as the
+    network gives them), a tuned one (eps = 0.01, soft labels min(1, X / 64),
+    scores normalised by their maximum) and the window proposal (degree
+    factors on the side edges, exponent and cap chosen by pilot runs), plus
+    the time of each part."""
     from paper_2409_08975_amd import learned
     out = {"motif": "M4-0", "delta": int(Wt.c.delta), "seeds": seeds}
     ref, t_ref = event_ms(lambda: tcb.tc_sample_estimate(G, Wt, [motif], int(k_ref), 1,
@@ -455,6 +457,41 @@ def learned_vs_method(tcb, G, Wt, motif, seeds, k_ref, stream):
             tp += t
         ep = np.array(ep)
         method_rows[k] = (float(np.sqrt(np.mean((ep - C) ** 2)) / C), tp / seeds)
+    def evaluate(v, proposal, fixed):
+        """Errors and times at each k, and the equal-error comparison: the
+        proposal needs k / ratio samples for the method's error at k; its
+        wall time counts the fixed cost of building the proposal set
+        (training reported apart) plus sampling at k / ratio."""
+        rows = []
+        for k in (10**5, 10**6, 10**7):
+            el, tl = [], 0.0
+            for sd in range(1, seeds + 1):
+                r, t = event_ms(lambda: tcb.tc_sample_estimate(G, proposal, [motif], k, sd,
+                                                               stream_id=2), stream)
+                el.append(float(r.estimate[0].item()))
+                tl += t
+            el = np.array(el)
+            rows.append({"k": k, "rms_rel_err_method": method_rows[k][0],
+                         "rms_rel_err_learned": float(np.sqrt(np.mean((el - C) ** 2)) / C),
+                         "ms_per_estimate_method": method_rows[k][1],
+                         "ms_per_estimate_learned": tl / seeds})
+        v["by_k"] = rows
+        ratio = v["variance_ratio"]
+        if ratio:
+            eq = []
+            for row in rows:
+                k = row["k"]
+                t_m = row["ms_per_estimate_method"]
+                t_l = fixed + row["ms_per_estimate_learned"] / ratio
+                eq.append({"k_method": k, "k_learned": k / ratio, "wall_ms_method": t_m,
+                           "wall_ms_learned": t_l, "learned_faster": t_l < t_m})
+            big = rows[-1]
+            per_m = big["ms_per_estimate_method"] / big["k"]
+            per_l = big["ms_per_estimate_learned"] / big["k"] / ratio
+            v["equal_error"] = {
+                "samples_factor": ratio, "fixed_ms": fixed, "by_k": eq,
+                "break_even_k": fixed / (per_m - per_l) if per_m > per_l else None}
+
     variants = {
         "configured": dict(eps=0.1, normalize=False, label_cap=0.0),
         "tuned": dict(eps=0.01, normalize=True, label_cap=64.0),
@@ -499,43 +536,27 @@ def learned_vs_method(tcb, G, Wt, motif, seeds, k_ref, stream):
         v["kernels"] = kt
         mp, mi = lp.pilot(10**7, 0x5EED)
         v["variance_ratio"] = mp.var / mi.var if mi.var > 0 else None
-        rows = []
-        for k in (10**5, 10**6, 10**7):
-            el, tl = [], 0.0
-            for sd in range(1, seeds + 1):
-                r, t = event_ms(lambda: tcb.tc_sample_estimate(G, lp.proposal, [motif], k, sd,
-                                                               stream_id=2), stream)
-                el.append(float(r.estimate[0].item()))
-                tl += t
-            el = np.array(el)
-            rows.append({"k": k, "rms_rel_err_method": method_rows[k][0],
-                         "rms_rel_err_learned": float(np.sqrt(np.mean((el - C) ** 2)) / C),
-                         "ms_per_estimate_method": method_rows[k][1],
-                         "ms_per_estimate_learned": tl / seeds})
-        v["by_k"] = rows
-        # Equal error: the learned proposal needs k / ratio samples for the
-        # error of the method at k.  Its wall time counts features,
-        # inference, h and the q-scan (training is reported apart), plus
-        # sampling at k / ratio, from the per-sample time measured at each k.
-        ratio = v["variance_ratio"]
-        if ratio:
-            fixed = v["features_ms"] + v["proposal_ms"]
-            eq = []
-            for row in rows:
-                k = row["k"]
-                t_m = row["ms_per_estimate_method"]
-                t_l = fixed + row["ms_per_estimate_learned"] / ratio
-                eq.append({"k_method": k, "k_learned": k / ratio, "wall_ms_method": t_m,
-                           "wall_ms_learned": t_l, "learned_faster": t_l < t_m})
-            big = rows[-1]
-            per_m = big["ms_per_estimate_method"] / big["k"]
-            per_l = big["ms_per_estimate_learned"] / big["k"] / ratio
-            v["equal_error"] = {
-                "samples_factor": ratio, "fixed_ms": fixed, "by_k": eq,
-                "break_even_k": fixed / (per_m - per_l) if per_m > per_l else None}
+        evaluate(v, lp.proposal, v["features_ms"] + v["proposal_ms"])
         out[name] = v
         del lp
-    out["variance_ratio"] = out["tuned"]["variance_ratio"]
+    # the window proposal: degree factors on the side edges as well (the
+    # exponent and cap chosen by pilot runs on the label stream)
+    v = {}
+    wp = learned.WindowProposal(G, Wt, motif)
+    _, v["fit_ms"] = event_ms(lambda: wp.fit(k_pilot=10**6), stream)
+    v["trials"] = [{"quarter": q, "cap": c, "pilot_var": var} for q, c, var in wp.trials]
+    if wp.choice is not None:
+        v["choice"] = {"quarter": wp.choice[0], "cap": wp.choice[1]}
+        _, v["proposal_ms"] = event_ms(lambda: wp.build(*wp.choice), stream)  # factors, q-scan
+        v["proposal_status"] = wp.proposal.status()
+        mp, mw = wp.pilot(10**7, 0x5EED)
+        v["variance_ratio"] = mp.var / mw.var if mw.var > 0 else None
+        evaluate(v, wp.proposal, v["proposal_ms"])
+    out["window"] = v
+    del wp
+    # the best learned variance ratio
+    cands = [out[n].get("variance_ratio") for n in ("tuned", "window")]
+    out["variance_ratio"] = max([c for c in cands if c] or [None])
     return out
 
 
@@ -595,7 +616,8 @@ def run_medium_like(args, tcb, sg, which, stream, dev, with_learned):
                                                      args.learned_seeds, args.k_ref, stream)
         lv = out["learned_vs_method"]
         log(f"[bench] learned vs method in {time.time() - t0:.1f}s: variance ratio "
-            f"configured {lv['configured']['variance_ratio']}, tuned {lv['tuned']['variance_ratio']}")
+            f"configured {lv['configured']['variance_ratio']}, tuned {lv['tuned']['variance_ratio']}"
+            f", window {lv['window'].get('variance_ratio')} {lv['window'].get('choice')}")
     return out, g
 
 

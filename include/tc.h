@@ -175,6 +175,11 @@ typedef struct tc_weights {
                                          positions (what the sampler needs of the
                                          centre edge, in one access)              */
   tc_class cls;                       /* anchor class of the windows           */
+  const uint64_t *ps1, *ps3;          /* NULL, or for a window proposal set
+                                         (tc_proposal_window) the prefix sums of
+                                         the entry factors over the CSR that side 1
+                                         resp. side 3 draws from ([m+1]); S is then
+                                         the scan of q = h * G1 * G3              */
 } tc_weights;
 
 /* Outputs of tc_sample_estimate, all (device), caller-allocated.
@@ -476,6 +481,38 @@ tc_status tc_quantize_proposal(const tc_weights *w, const float *g, float eps, f
 tc_status tc_proposal_workspace_bytes(int64_t m, size_t *bytes);
 tc_status tc_proposal_weights(const tc_graph *g, const tc_weights *w, const uint32_t *h,
                               void *ws, size_t ws_bytes, tc_weights *wq, void *stream);
+
+/* ---- Window proposal (not part of the paper) ------------------------------
+ * Importance sampling over the side edges as well as the centre edge: every
+ * entry of the in-CSR and of the out-CSR carries an integer factor
+ * f >= 1, a side's window has the factor sum G (1 for an absent side), the
+ * centre edge p is drawn with probability q_p / Q, q_p = h_p * G1_p * G3_p
+ * (h NULL = 1), and each side's edge is the window entry j drawn with
+ * probability f_j / G: a uniform integer u < G (Lemire's test on the same
+ * Philox word as the uniform pick), then the entry whose prefix interval
+ * holds u.  A path has probability h_p f1 f3 / Q and contributes
+ * X * Q / (h_p f1 f3); cnt holds the exact 128-bit sum of
+ * floor(X 2^64 / (h_p f1 f3)) and estimate = ((cnt 2^-64) / k) * Q, as for
+ * tc_proposal_weights.  The product h_p f1 f3 must stay below 2^32, each G
+ * below 2^32 and Q below 2^64 (TC_F_OVERFLOW otherwise: the set's status
+ * with Q = 0, or the sampler's).  With all factors 1 the draws equal those of
+ * the method (or of the centre proposal h) position for position.
+ *
+ * tc_window_factors fills f_in[i] (in-CSR position i, an edge x -> u) and
+ * f_out[o] (out-CSR position o, an edge v -> y) with min(cap, F(1 + d)) of
+ * the far endpoint's total degree d (in + out): F = 1, r4, r2, r2 r4 or r2^2
+ * for quarter = 0..4, with r2 = floor(sqrt(1 + d)), r4 = floor(sqrt(r2)),
+ * about (1 + d)^(quarter/4).  cap in 1..65535.
+ * tc_proposal_window builds the set wq from w (the method's weights: no h,
+ * no factors): the window arrays are borrowed from w, S, its tree, the
+ * prefix sums and the status live in ws.  f_in / f_out may be NULL (factor
+ * 1 for that CSR).  Errors: TC_E_ARG, TC_E_WORKSPACE, TC_E_HIP. */
+tc_status tc_window_factors(const tc_graph *g, int32_t quarter, uint32_t cap, uint32_t *f_in,
+                            uint32_t *f_out, void *stream);
+tc_status tc_proposal_window_workspace_bytes(int64_t m, size_t *bytes);
+tc_status tc_proposal_window(const tc_graph *g, const tc_weights *w, const uint32_t *h,
+                             const uint32_t *f_in, const uint32_t *f_out, void *ws,
+                             size_t ws_bytes, tc_weights *wq, void *stream);
 
 /* Profiling aid (not part of the method).  After tc_timing_enable(1) the
  * library records a pair of HIP events on the launch stream around each

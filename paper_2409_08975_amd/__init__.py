@@ -35,7 +35,8 @@ EXPORTED = ["tc_version", "tc_graph_workspace_bytes", "tc_build_graph",
             "tc_sample_estimate", "tc_sample_estimate_noalloc", "tc_batch_workspace_bytes", "tc_batch_estimate",
             "tc_autotune", "tc_features_workspace_bytes", "tc_edge_features", "tc_mlp_forward", "tc_mlp_workspace_bytes",
             "tc_mlp_grad", "tc_mlp_adam", "tc_mlp_train", "tc_quantize_proposal",
-            "tc_proposal_workspace_bytes", "tc_proposal_weights", "tc_timing_enable",
+            "tc_proposal_workspace_bytes", "tc_proposal_weights", "tc_window_factors",
+            "tc_proposal_window_workspace_bytes", "tc_proposal_window", "tc_timing_enable",
             "tc_timing_reset", "tc_timing_read"]
 MLP_PARAMS = 4801
 
@@ -95,7 +96,7 @@ class tc_graph(ctypes.Structure):
 class tc_weights(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_int64), ("m", ctypes.c_int64), ("lo_in", _P), ("a", _P),
                 ("lo_out", _P), ("b", _P), ("S", _P), ("status", _P), ("scratch", _P),
-                ("h", _P), ("prec", _P), ("cls", tc_class)]
+                ("h", _P), ("prec", _P), ("cls", tc_class), ("ps1", _P), ("ps3", _P)]
 
 
 class tc_result(ctypes.Structure):
@@ -177,6 +178,10 @@ def lib():
         L.tc_proposal_workspace_bytes.argtypes = [I64, ctypes.POINTER(SZ)]
         L.tc_proposal_weights.argtypes = [ctypes.POINTER(tc_graph), ctypes.POINTER(tc_weights),
                                           _P, _P, SZ, ctypes.POINTER(tc_weights), _P]
+        L.tc_window_factors.argtypes = [ctypes.POINTER(tc_graph), I32, U32, _P, _P, _P]
+        L.tc_proposal_window_workspace_bytes.argtypes = [I64, ctypes.POINTER(SZ)]
+        L.tc_proposal_window.argtypes = [ctypes.POINTER(tc_graph), ctypes.POINTER(tc_weights),
+                                         _P, _P, _P, _P, SZ, ctypes.POINTER(tc_weights), _P]
         L.tc_timing_enable.argtypes = [I32]
         L.tc_timing_reset.argtypes = []
         L.tc_timing_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -282,6 +287,7 @@ class Weights:
     graph: Graph
     base: "Weights | None" = None     # the method's weights a proposal set borrows from
     h: torch.Tensor | None = None     # proposal factors (int32 storage of uint32)
+    factors: tuple | None = None      # window proposal: (f_in, f_out) it was built from
 
     def view(self, name, dtype, length):
         ptr = getattr(self.c, name)
@@ -717,6 +723,42 @@ def tc_proposal_weights(graph: Graph, weights: Weights, h: torch.Tensor,
                                      _ptr(ws), nb, ctypes.byref(wq), _stream(stream)),
            "tc_proposal_weights")
     return Weights(wq, ws, graph, base=weights, h=h)
+
+
+def tc_window_factors(graph: Graph, quarter: int, cap: int, stream=None):
+    """Window-proposal factors (f_in over in-CSR positions, f_out over
+    out-CSR positions; int32 tensors holding uint32 values): min(cap, about
+    (1 + degree of the far endpoint)^(quarter / 4))."""
+    dev = graph.ws.device
+    f_in = torch.empty(graph.m, dtype=torch.int32, device=dev)
+    f_out = torch.empty(graph.m, dtype=torch.int32, device=dev)
+    _on_stream(stream, f_in, f_out)
+    _check(lib().tc_window_factors(ctypes.byref(graph.c), int(quarter), int(cap), _ptr(f_in),
+                                   _ptr(f_out), _stream(stream)), "tc_window_factors")
+    return f_in, f_out
+
+
+def tc_proposal_window(graph: Graph, weights: Weights, h: torch.Tensor | None = None,
+                       f_in: torch.Tensor | None = None, f_out: torch.Tensor | None = None,
+                       stream=None) -> Weights:
+    """Window proposal set: windows of `weights`, S = scan of h * G1 * G3,
+    side edges drawn by their entry factors."""
+    h = h.contiguous() if h is not None else None
+    f_in = f_in.contiguous() if f_in is not None else None
+    f_out = f_out.contiguous() if f_out is not None else None
+    b = ctypes.c_size_t(0)
+    _check(lib().tc_proposal_window_workspace_bytes(graph.m, ctypes.byref(b)),
+           "tc_proposal_window_workspace_bytes")
+    ws = torch.empty(b.value, dtype=torch.uint8, device=graph.ws.device)
+    wq = tc_weights()
+    _on_stream(stream, ws, *[x for x in (h, f_in, f_out) if x is not None])
+    null = None
+    _check(lib().tc_proposal_window(ctypes.byref(graph.c), ctypes.byref(weights.c),
+                                    _ptr(h) if h is not None else null,
+                                    _ptr(f_in) if f_in is not None else null,
+                                    _ptr(f_out) if f_out is not None else null, _ptr(ws), b.value,
+                                    ctypes.byref(wq), _stream(stream)), "tc_proposal_window")
+    return Weights(wq, ws, graph, base=weights, h=h, factors=(f_in, f_out))
 
 
 def timing_enable(on: bool = True) -> None:

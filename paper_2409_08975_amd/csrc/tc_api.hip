@@ -291,7 +291,7 @@ tc_status tc_exhaustive_count(const tc_graph* g, const tc_weights* w, const tc_m
                               int32_t n_motifs, uint64_t r0, uint64_t count, void* ws,
                               size_t ws_bytes, tc_result* out, void* stream) {
   if (!g || !w || check_result(out) != TC_OK) return TC_E_ARG;
-  if (count < 1 || w->m != g->m || w->h) return TC_E_ARG;
+  if (count < 1 || w->m != g->m || w->h || w->ps1 || w->ps3) return TC_E_ARG;
   tc::MotifPlan plan;
   tc_status s = tc::compile_motifs(motifs, n_motifs, &plan);
   if (s != TC_OK) return s;
@@ -440,8 +440,29 @@ tc_status tc_proposal_workspace_bytes(int64_t m, size_t* bytes) {
 
 tc_status tc_proposal_weights(const tc_graph* g, const tc_weights* w, const uint32_t* h,
                               void* ws, size_t ws_bytes, tc_weights* wq, void* stream) {
-  if (!g || !w || !h || !ws || !wq || w->m != g->m || w->h || !aligned16(h)) return TC_E_ARG;
+  if (!g || !w || !h || !ws || !wq || w->m != g->m || w->h || w->ps1 || w->ps3 || !aligned16(h))
+    return TC_E_ARG;
   return tc::proposal_weights(w, h, ws, ws_bytes, (hipStream_t)stream, wq);
+}
+
+tc_status tc_window_factors(const tc_graph* g, int32_t quarter, uint32_t cap, uint32_t* f_in,
+                            uint32_t* f_out, void* stream) {
+  if (!g || !f_in || !f_out || quarter < 0 || quarter > 4 || cap < 1 || cap > 65535)
+    return TC_E_ARG;
+  return tc::window_factors(g, quarter, cap, f_in, f_out, (hipStream_t)stream);
+}
+
+tc_status tc_proposal_window_workspace_bytes(int64_t m, size_t* bytes) {
+  if (!bytes || m < 0 || m >= ((int64_t)1 << 31)) return TC_E_ARG;
+  *bytes = tc::window_proposal_workspace_bytes(m);
+  return TC_OK;
+}
+
+tc_status tc_proposal_window(const tc_graph* g, const tc_weights* w, const uint32_t* h,
+                             const uint32_t* f_in, const uint32_t* f_out, void* ws,
+                             size_t ws_bytes, tc_weights* wq, void* stream) {
+  if (!g || !w || !ws || !wq || w->m != g->m || w->h || w->ps1 || w->ps3) return TC_E_ARG;
+  return tc::proposal_window(g, w, h, f_in, f_out, ws, ws_bytes, (hipStream_t)stream, wq);
 }
 
 }  // extern "C"

@@ -98,6 +98,13 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
 size_t proposal_workspace_bytes(int64_t m);
 tc_status proposal_weights(const tc_weights* w, const uint32_t* h, void* ws, size_t ws_bytes,
                            hipStream_t st, tc_weights* wq);
+// Window proposal (per-entry factors over the CSRs, q = h G1 G3).
+tc_status window_factors(const tc_graph* g, int quarter, uint32_t cap, uint32_t* f_in,
+                         uint32_t* f_out, hipStream_t st);
+size_t window_proposal_workspace_bytes(int64_t m);
+tc_status proposal_window(const tc_graph* g, const tc_weights* w, const uint32_t* h,
+                          const uint32_t* f_in, const uint32_t* f_out, void* ws, size_t ws_bytes,
+                          hipStream_t st, tc_weights* wq);
 size_t features_workspace_bytes(int64_t m);
 tc_status edge_features(const tc_graph* g, const tc_weights* w, uint16_t* feat, void* ws,
                         size_t ws_bytes, hipStream_t st);

@@ -73,6 +73,9 @@ struct DeltaArgs {
   int32_t* e3;
   uint64_t* X;
   const uint32_t* h;  // proposal factors (importance sampling) or null
+  const uint64_t* ps1;  // window proposal: prefix sums of side 1's entry factors, or null
+  const uint64_t* ps3;  // ... of side 3's
+  int32_t is;           // importance sampling (h, ps1 or ps3 set)
   uint32_t* P;
   double* m2;
   uint64_t* xmax;
@@ -360,6 +363,50 @@ __device__ __forceinline__ void key_window(const SampleArgs& A, const PathRec& P
 // in path order (e1, centre, e3) and random draws, with those choices fixed
 // at compile time (fewer live registers); GENERAL = true reads them from the
 // plan (any class, wedges, the exhaustive mode).
+// An edge of a side's window: a uniform position among its `len`, or with
+// window factors (prefix sums `ps` over the side's CSR) position j with
+// probability (ps[lo+j+1] - ps[lo+j]) / (ps[lo+len] - ps[lo]): a uniform
+// integer u below that sum, then the position whose prefix interval holds u
+// (bisection).  *g is the chosen position's factor (1 when uniform).  The
+// draw takes word `w3` (x3) or x2 of the first attempt passing Lemire's test.
+__device__ __forceinline__ uint32_t pick_side(const SampleArgs& A, uint64_t i, const Words4& blk0,
+                                              bool w3, const uint64_t* __restrict__ ps,
+                                              uint32_t lo, uint32_t len, uint64_t* g,
+                                              uint32_t* st) {
+  uint64_t base = 0, span = len;
+  if (ps) {
+    base = ps[lo];
+    span = ps[lo + len] - base;
+    if (span > 0xFFFFFFFFull) {  // the weight set is flagged too
+      *st |= TC_F_OVERFLOW;
+      span = 0xFFFFFFFFull;
+    }
+  }
+  uint32_t u = 0;
+  bool ok = range32(w3 ? blk0.x3 : blk0.x2, (uint32_t)span, &u);
+  for (uint32_t att = 1; !ok && att < kMaxAttempts; ++att) {
+    const Words4 bk = philox_block(A.seed, A.stream_id, i, att);
+    ok = range32(w3 ? bk.x3 : bk.x2, (uint32_t)span, &u);
+  }
+  if (!ok) {
+    *st |= TC_F_RNG;
+    u = 0;
+  }
+  *g = 1;
+  if (!ps) return u;
+  // ps[lo + j] - base <= u < ps[lo + j + 1] - base
+  uint32_t L = 0, H = len;
+  while (H - L > 1) {
+    const uint32_t mid = L + ((H - L) >> 1);
+    if (ps[lo + mid] - base <= (uint64_t)u)
+      L = mid;
+    else
+      H = mid;
+  }
+  *g = ps[lo + L + 1] - ps[lo + L];
+  return L;
+}
+
 template <bool GENERAL>
 __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
   __shared__ PathRec s_path[kSBlock];
@@ -440,26 +487,15 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
         const uint4 pr0 = D.prec[2 * (uint64_t)p], pr1 = D.prec[2 * (uint64_t)p + 1];
         const uint32_t ap = pr0.y, bp = pr0.w;
         uint32_t j1, j3;
+        uint64_t g1 = 1, g3 = 1;  // window factors of the picks
         if (exh) {
           // rank r - S[p] = j1 * b + j3 (b >= 1: w_p = a * b > 0 here)
           const uint64_t jj = r - D.S[p];
           j1 = (uint32_t)(jj / bp);
           j3 = (uint32_t)(jj - (uint64_t)j1 * bp);
         } else {
-          bool ok = range32(blk0.x2, ap, &j1);
-          for (uint32_t att = 1; !ok && att < kMaxAttempts; ++att)
-            ok = range32(philox_block(A.seed, A.stream_id, i, att).x2, ap, &j1);
-          if (!ok) {
-            st_bits |= TC_F_RNG;
-            j1 = 0;
-          }
-          ok = range32(blk0.x3, bp, &j3);
-          for (uint32_t att = 1; !ok && att < kMaxAttempts; ++att)
-            ok = range32(philox_block(A.seed, A.stream_id, i, att).x3, bp, &j3);
-          if (!ok) {
-            st_bits |= TC_F_RNG;
-            j3 = 0;
-          }
+          j1 = pick_side(A, i, blk0, false, D.ps1, pr0.x, ap, &g1, &st_bits);
+          j3 = pick_side(A, i, blk0, true, D.ps3, pr0.z, bp, &g3, &st_bits);
         }
         u = (int32_t)pr1.x;
         v = (int32_t)pr1.y;
@@ -498,8 +534,15 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
           Tk[kk] = kk < na ? ts[GENERAL ? A.plan.order[kk] : kk] : 0;
         for (int kk = 1; kk < na; ++kk) valid = valid && Tk[kk - 1] < Tk[kk];
         valid = valid && (Tk[na - 1] - Tk[0]) <= D.delta;
-        if (D.h && valid) {
-          hp = D.h[p];
+        if (D.is && valid) {
+          // the path's proposal factor h_p g1 g3 (below 2^32, else flagged)
+          const uint64_t hc = D.h ? (uint64_t)D.h[p] : 1ull;
+          uint64_t hw = hc * g1;
+          if (hw > 0xFFFFFFFFull || (hw *= g3) > 0xFFFFFFFFull) {
+            st_bits |= TC_F_OVERFLOW;
+            hw = 0xFFFFFFFFull;
+          }
+          hp = (uint32_t)hw;
           A.samp_h[(uint64_t)d * A.chunk + li] = hp;
         }
       }
@@ -616,7 +659,7 @@ __global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
       const uint64_t nz = __ballot(Xc != 0);
       if (nz) {
         bool ovf = false;
-        const U128 sx = wave_sum128c(contribution(Xc, D.h != nullptr, hp), &ovf);
+        const U128 sx = wave_sum128c(contribution(Xc, D.is != 0, hp), &ovf);
         const double sq = D.m2 ? wave_sumf64(square_term(Xc, hp)) : 0.0;
         uint64_t xm = Xc;
 #pragma unroll
@@ -750,8 +793,8 @@ __device__ __forceinline__ void item_done(const SampleArgs& A, int d, int j, uin
                                           uint64_t X) {
   const DeltaArgs& D = A.D[d];
   if (D.X) D.X[(uint64_t)j * A.k + A.c0 + li] = X;
-  const uint32_t hp = D.h ? A.samp_h[(uint64_t)d * A.chunk + li] : 1u;
-  sums_add(sums_slot(A, 0, d, j), contribution(X, D.h != nullptr, hp), X != 0 ? 1ull : 0ull,
+  const uint32_t hp = D.is ? A.samp_h[(uint64_t)d * A.chunk + li] : 1u;
+  sums_add(sums_slot(A, 0, d, j), contribution(X, D.is != 0, hp), X != 0 ? 1ull : 0ull,
            D.m2 ? square_term(X, hp) : 0.0, false, X);
 }
 
@@ -1272,11 +1315,11 @@ __device__ void item_done128(const SampleArgs& A, int d, int j, uint32_t li, U12
                              BlockSums* slot) {
   const DeltaArgs& D = A.D[d];
   const uint64_t X64 = X.hi ? ~0ull : X.lo;  // saturated
-  if (D.h && X.hi) ovf = true;
+  if (D.is && X.hi) ovf = true;
   if (ovf) flag_status(A, d, TC_F_OVERFLOW | TC_F_MOTIF(j));
   if (D.X) D.X[(uint64_t)j * A.k + A.c0 + li] = X64;
-  const uint32_t hp = D.h ? A.samp_h[(uint64_t)d * A.chunk + li] : 1u;
-  const U128 c = D.h ? contribution(X64, true, hp) : X;
+  const uint32_t hp = D.is ? A.samp_h[(uint64_t)d * A.chunk + li] : 1u;
+  const U128 c = D.is ? contribution(X64, true, hp) : X;
   const bool nz = (X.lo | X.hi) != 0;
   atomicAdd((unsigned long long*)&slot->hits, nz ? 1ull : 0ull);
   if (nz) atomicMax((unsigned long long*)&slot->xmax, (unsigned long long)X64);
@@ -1567,7 +1610,7 @@ __global__ __launch_bounds__(1024) void k_finalize(SampleArgs A, double* const* 
       if (ovf) atomicOr(A.D[d].status, TC_F_OVERFLOW | TC_F_MOTIF(j));
       const uint64_t W = A.D[d].S[A.m];
       double c = u128_to_double(c128.lo, c128.hi);
-      if (A.D[d].h) c = ldexp(c, -64);
+      if (A.D[d].is) c = ldexp(c, -64);
       // exhaustive mode: the count itself
       est[d][j] = A.exhaustive ? c
                                : ((W == 0) ? 0.0 : __dmul_rn(__ddiv_rn(c, (double)A.k), (double)W));
@@ -1707,6 +1750,10 @@ tc_status sample_batch(const tc_graph* g, const tc_weights* const* w, int nd,
     D.e3 = out[d]->e3;
     D.X = out[d]->X;
     D.h = w[d]->h;
+    // window factors only for a side that has an edge
+    D.ps1 = w[d]->cls.mode1 != TC_SIDE_NONE ? w[d]->ps1 : nullptr;
+    D.ps3 = w[d]->cls.mode3 != TC_SIDE_NONE ? w[d]->ps3 : nullptr;
+    D.is = (D.h || D.ps1 || D.ps3) ? 1 : 0;
     D.P = out[d]->P;
     D.m2 = out[d]->m2;
     D.xmax = out[d]->xmax;

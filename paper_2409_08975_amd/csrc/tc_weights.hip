@@ -627,6 +627,7 @@ tc_status path_weights_batch(const tc_graph* g, const int64_t* deltas, int nd,
     W->status = (uint32_t*)(base + L.status);
     W->scratch = base + L.tree;  // search tree over S
     W->h = nullptr;
+    W->ps1 = W->ps3 = nullptr;
     W->prec = base + L.prec;
     tile_sums[i] = (uint64_t*)(base + L.tile_sums);
     tile_off[i] = (uint64_t*)(base + L.tile_off);
@@ -822,6 +823,250 @@ tc_status proposal_weights(const tc_weights* w, const uint32_t* h, void* ws, siz
     hipLaunchKernelGGL(k_scan_apply<true>, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
                        (const uint32_t*)w->a, (const uint32_t*)w->b, h, m,
                        (const uint64_t*)tile_off, wq->S);
+  build_tree(wq, st);
+  if (hipGetLastError() != hipSuccess) return TC_E_HIP;
+  return TC_OK;
+}
+
+
+// ---- window proposal (not part of the paper) ---------------------------------
+// Per-entry factors g(deg) of the far endpoint of every in-CSR entry (an
+// edge x -> u: x) and out-CSR entry (v -> y: y), deg the total degree:
+// g(d) = min(cap, F_q(1 + d)) with F_0 = 1, F_1 = r4, F_2 = r2, F_3 = r2 r4,
+// F_4 = r2^2, r2 = floor(sqrt(1 + d)), r4 = floor(sqrt(r2)) -- integer
+// square roots, so the factors are exact and reproducible.
+__device__ __forceinline__ uint64_t isqrt_u64(uint64_t v) {
+  uint64_t r = (uint64_t)sqrt((double)v);
+  while (r > 0 && r * r > v) --r;
+  while ((r + 1) * (r + 1) <= v) ++r;
+  return r;
+}
+
+__device__ __forceinline__ uint32_t degree_factor(uint64_t d, int quarter, uint32_t cap) {
+  const uint64_t r2 = isqrt_u64(1 + d), r4 = isqrt_u64(r2);
+  const uint64_t f = quarter == 0 ? 1 : quarter == 1 ? r4 : quarter == 2 ? r2
+                   : quarter == 3 ? r2 * r4 : r2 * r2;
+  return (uint32_t)(f < cap ? f : cap);
+}
+
+__global__ __launch_bounds__(256) void k_window_factors(const int32_t* __restrict__ in_src,
+                                                        const int32_t* __restrict__ out_dst,
+                                                        const uint32_t* __restrict__ in_off,
+                                                        const uint32_t* __restrict__ out_off,
+                                                        int64_t m, int quarter, uint32_t cap,
+                                                        uint32_t* __restrict__ f_in,
+                                                        uint32_t* __restrict__ f_out,
+                                                        const uint32_t* __restrict__ gstatus) {
+  if (*gstatus) return;  // a rejected graph: its ids are not valid
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  auto deg = [&](int32_t v) -> uint64_t {
+    return (uint64_t)(out_off[v + 1] - out_off[v]) + (uint64_t)(in_off[v + 1] - in_off[v]);
+  };
+  f_in[i] = degree_factor(deg(in_src[i]), quarter, cap);
+  f_out[i] = degree_factor(deg(out_dst[i]), quarter, cap);
+}
+
+// 128-bit tile sums of a u32 array (tiles of kWTile entries)
+__global__ __launch_bounds__(kWBlock) void k_u32_tile_sums(const uint32_t* __restrict__ v,
+                                                         int64_t m,
+                                                         uint64_t* __restrict__ tile_sums) {
+  __shared__ uint64_t s_w[kWBlock / kWave];
+  const int64_t start = (int64_t)blockIdx.x * kWTile;
+  uint64_t acc = 0;
+#pragma unroll
+  for (int r = 0; r < kWItems; ++r) {
+    const int64_t p = start + (int64_t)r * kWBlock + threadIdx.x;
+    if (p < m) acc += v[p];
+  }
+  acc = wave_inclusive_scan(acc);
+  if ((threadIdx.x & 63) == 63) s_w[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+    for (int w = 0; w < kWBlock / kWave; ++w) t += s_w[w];
+    tile_sums[2 * blockIdx.x] = t;
+    tile_sums[2 * blockIdx.x + 1] = 0;
+  }
+}
+
+// exclusive prefix sums of u64 (or u32 widened) values per tile plus the
+// tile offset; `out` has m + 1 words (the last is written by k_scan_tiles)
+template <typename T>
+__global__ __launch_bounds__(kWBlock) void k_prefix_apply(const T* __restrict__ v, int64_t m,
+                                                        const uint64_t* __restrict__ tile_off,
+                                                        uint64_t* __restrict__ out) {
+  __shared__ uint64_t s_w[kWBlock / kWave];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t p0 = (int64_t)blockIdx.x * kWTile + (int64_t)threadIdx.x * kWItems;
+  uint64_t x[kWItems];
+  uint64_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kWItems; ++j) {
+    x[j] = p0 + j < m ? (uint64_t)v[p0 + j] : 0ull;
+    s += x[j];
+  }
+  const uint64_t inc = wave_inclusive_scan(s);
+  if (lane == 63) s_w[wave] = inc;
+  __syncthreads();
+  uint64_t run = tile_off[blockIdx.x] + inc - s;
+  for (int q = 0; q < wave; ++q) run += s_w[q];
+#pragma unroll
+  for (int j = 0; j < kWItems; ++j) {
+    if (p0 + j < m) out[p0 + j] = run;
+    run += x[j];
+  }
+}
+
+// the flag word starts as the weights' status (a rejected graph or an
+// overflowed weight set passes on)
+__global__ void k_copy_word(const uint32_t* __restrict__ from, uint32_t* __restrict__ to) {
+  if (threadIdx.x == 0) *to = *from;
+}
+
+// q_p = h_p * G1_p * G3_p per scan position (G a side's factor sum over its
+// window, the window size without factors, 1 for an absent side), stored in
+// q and summed per tile in 128 bits.  A window sum of 2^32 or more, or a
+// q_p of 2^64 or more, sets TC_F_OVERFLOW in *flag.
+__global__ __launch_bounds__(kWBlock) void k_qwin_tiles(
+    const uint32_t* __restrict__ lo1, const uint32_t* __restrict__ a,
+    const uint32_t* __restrict__ lo3, const uint32_t* __restrict__ b,
+    const uint32_t* __restrict__ h, const uint64_t* __restrict__ ps1,
+    const uint64_t* __restrict__ ps3, int mode1, int mode3, int64_t m,
+    uint64_t* __restrict__ q, uint64_t* __restrict__ tile_sums, uint32_t* __restrict__ flag,
+    const uint32_t* __restrict__ gstatus) {
+  // a rejected graph: its windows are undefined (the flag, set from the
+  // weights' status, already makes Q = 0)
+  if (*gstatus) return;
+  __shared__ U128 s_w[kWBlock / kWave];
+  const int64_t start = (int64_t)blockIdx.x * kWTile;
+  U128 acc{0, 0};
+  bool bad = false;
+#pragma unroll
+  for (int r = 0; r < kWItems; ++r) {
+    const int64_t p = start + (int64_t)r * kWBlock + threadIdx.x;
+    if (p < m) {
+      uint64_t G1 = 1, G3 = 1;
+      if (mode1 != TC_SIDE_NONE) G1 = ps1 ? ps1[lo1[p] + a[p]] - ps1[lo1[p]] : a[p];
+      if (mode3 != TC_SIDE_NONE) G3 = ps3 ? ps3[lo3[p] + b[p]] - ps3[lo3[p]] : b[p];
+      if (G1 > 0xFFFFFFFFull || G3 > 0xFFFFFFFFull) {
+        bad = true;
+        G1 = G1 > 0xFFFFFFFFull ? 0xFFFFFFFFull : G1;
+        G3 = G3 > 0xFFFFFFFFull ? 0xFFFFFFFFull : G3;
+      }
+      const uint64_t g13 = G1 * G3;  // below 2^64
+      const uint64_t hp = h ? (uint64_t)h[p] : 1ull;
+      const U128 qq{g13 * hp, __umul64hi(g13, hp)};
+      if (qq.hi) bad = true;
+      q[p] = qq.lo;
+      acc = add128(acc, qq);
+    }
+  }
+  if (bad) atomicOr(flag, TC_F_OVERFLOW);
+  acc = wave_sum128(acc);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    U128 t{0, 0};
+    for (int w = 0; w < kWBlock / kWave; ++w) t = add128(t, s_w[w]);
+    tile_sums[2 * blockIdx.x] = t.lo;
+    tile_sums[2 * blockIdx.x + 1] = t.hi;
+  }
+}
+
+struct WindowLayout {
+  size_t S, tree, status, flag, fstatus, tile_sums, tile_off, q, ps_in, ps_out, total;
+};
+
+static WindowLayout window_layout(int64_t m) {
+  WindowLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(bytes ? bytes : 1);
+    return at;
+  };
+  const size_t ntiles = (size_t)((m + kWTile - 1) / kWTile);
+  const STree T = stree_layout(m);
+  L.S = take((size_t)T.count[0] * 8);
+  L.tree = take(T.total_words * 8);
+  L.status = take(4);
+  L.flag = take(4);
+  L.fstatus = take(4);
+  L.tile_sums = take(ntiles * 16);
+  L.tile_off = take(ntiles * 8);
+  L.q = take((size_t)m * 8);
+  L.ps_in = take(((size_t)m + 1) * 8);
+  L.ps_out = take(((size_t)m + 1) * 8);
+  L.total = o;
+  return L;
+}
+
+size_t window_proposal_workspace_bytes(int64_t m) { return window_layout(m).total; }
+
+tc_status window_factors(const tc_graph* g, int quarter, uint32_t cap, uint32_t* f_in,
+                         uint32_t* f_out, hipStream_t st) {
+  const int64_t m = g->m;
+  if (m > 0)
+    hipLaunchKernelGGL(k_window_factors, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st,
+                       (const int32_t*)g->in_src, (const int32_t*)g->out_dst,
+                       (const uint32_t*)g->in_off, (const uint32_t*)g->out_off, m, quarter, cap,
+                       f_in, f_out, (const uint32_t*)g->status);
+  return hipGetLastError() == hipSuccess ? TC_OK : TC_E_HIP;
+}
+
+tc_status proposal_window(const tc_graph* g, const tc_weights* w, const uint32_t* h,
+                          const uint32_t* f_in, const uint32_t* f_out, void* ws, size_t ws_bytes,
+                          hipStream_t st, tc_weights* wq) {
+  const int64_t m = w->m;
+  const WindowLayout L = window_layout(m);
+  if (ws_bytes < L.total) return TC_E_WORKSPACE;
+  char* base = (char*)ws;
+  *wq = *w;
+  wq->S = (uint64_t*)(base + L.S);
+  wq->scratch = base + L.tree;
+  wq->status = (uint32_t*)(base + L.status);
+  wq->h = h;
+  uint32_t* flag = (uint32_t*)(base + L.flag);
+  uint32_t* fstatus = (uint32_t*)(base + L.fstatus);
+  uint64_t* tile_sums = (uint64_t*)(base + L.tile_sums);
+  uint64_t* tile_off = (uint64_t*)(base + L.tile_off);
+  uint64_t* q = (uint64_t*)(base + L.q);
+  uint64_t* ps_in = f_in ? (uint64_t*)(base + L.ps_in) : nullptr;
+  uint64_t* ps_out = f_out ? (uint64_t*)(base + L.ps_out) : nullptr;
+  const int64_t ntiles = (m + kWTile - 1) / kWTile;
+  const uint32_t* gst = (const uint32_t*)g->status;
+  // prefix sums of the factors (m + 1 words each; the total lands in [m])
+  auto prefix = [&](const uint32_t* f, uint64_t* ps) {
+    if (ntiles > 0)
+      hipLaunchKernelGGL(k_u32_tile_sums, dim3((unsigned)ntiles), dim3(kWBlock), 0, st, f, m,
+                         tile_sums);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, (const uint64_t*)tile_sums,
+                       ntiles, tile_off, ps, m, fstatus, gst);
+    if (ntiles > 0)
+      hipLaunchKernelGGL(k_prefix_apply<uint32_t>, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
+                         f, m, (const uint64_t*)tile_off, ps);
+  };
+  if (ps_in) prefix(f_in, ps_in);
+  if (ps_out) prefix(f_out, ps_out);
+  auto side_ps = [&](int mode) -> const uint64_t* {
+    return mode == TC_SIDE_IN ? ps_in : (mode == TC_SIDE_OUT ? ps_out : nullptr);
+  };
+  wq->ps1 = side_ps(w->cls.mode1);
+  wq->ps3 = side_ps(w->cls.mode3);
+  hipLaunchKernelGGL(k_copy_word, dim3(1), dim3(64), 0, st, (const uint32_t*)w->status, flag);
+  if (ntiles > 0)
+    hipLaunchKernelGGL(k_qwin_tiles, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
+                       (const uint32_t*)w->lo_in, (const uint32_t*)w->a,
+                       (const uint32_t*)w->lo_out, (const uint32_t*)w->b, h, wq->ps1, wq->ps3,
+                       (int)w->cls.mode1, (int)w->cls.mode3, m, q, tile_sums, flag, gst);
+  // a set flag (window sums or q_p out of range, or the weights' own status)
+  // makes Q = 0 and is reported in wq->status
+  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, (const uint64_t*)tile_sums, ntiles,
+                     tile_off, wq->S, m, wq->status, (const uint32_t*)flag);
+  if (ntiles > 0)
+    hipLaunchKernelGGL(k_prefix_apply<uint64_t>, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
+                       (const uint64_t*)q, m, (const uint64_t*)tile_off, wq->S);
   build_tree(wq, st);
   if (hipGetLastError() != hipSuccess) return TC_E_HIP;
   return TC_OK;

@@ -21,7 +21,8 @@ import numpy as np
 import torch
 
 from . import (MLP_PARAMS, Graph, Weights, new_result, tc_edge_features, tc_mlp_forward,
-               tc_mlp_train, tc_proposal_weights, tc_quantize_proposal, tc_sample_estimate)
+               tc_mlp_train, tc_proposal_weights, tc_proposal_window, tc_quantize_proposal,
+               tc_sample_estimate, tc_window_factors)
 
 LABEL_STREAM = 0x4C000000  # Philox stream of the training labels
 
@@ -59,7 +60,8 @@ def moments(result, weights: Weights, k: int, j: int = 0) -> Moments:
     total = int(weights.view("S", torch.int64, weights.c.m + 1)[-1].item()) & (2**64 - 1)
     cnt = result.counts()[j]
     m2 = float(result.m2[j].item())
-    mean_x = cnt / k if weights.h is None else cnt / 2.0**64 / k
+    # a proposal set (centre or window factors) accumulates floor(X 2^64 / h)
+    mean_x = cnt / k if weights.base is None else cnt / 2.0**64 / k
     var = total * total * (m2 / k - mean_x * mean_x)
     return Moments(float(result.estimate[j].item()), var, k)
 
@@ -116,3 +118,59 @@ class LearnedProposal:
         mp, mi = self.pilot(k_pilot, seed)
         self.pilot_ratio = mp.var / mi.var if mi.var > 0 else float("inf")
         return self.proposal if mi.var <= mp.var else self.weights
+
+
+class WindowProposal:
+    """Importance sampling over the side edges as well (tc_proposal_window):
+    every CSR entry carries the factor min(cap, (1 + degree of its far
+    endpoint)^(quarter / 4)) in integer square roots, each side's edge is
+    drawn by factor and the centre edge by h_p G1_p G3_p.  The heavy closure
+    counts of a path come from hub endpoints inside its windows, which a
+    factor on the centre edge alone cannot single out.  The exponent and the
+    cap are chosen from pilot runs (the lowest measured per-sample variance
+    among the candidates whose total fits 64 bits); an optional centre factor
+    h (from LearnedProposal) multiplies in."""
+
+    CANDIDATES = ((1, 65535), (2, 65535), (3, 65535), (2, 255), (3, 255))
+
+    def __init__(self, graph: Graph, weights: Weights, motif, h: torch.Tensor | None = None):
+        self.graph, self.weights, self.motif, self.h = graph, weights, motif, h
+        self.proposal: Weights | None = None
+        self.choice = None
+        self.trials = []
+
+    def build(self, quarter: int, cap: int) -> Weights:
+        f_in, f_out = tc_window_factors(self.graph, quarter, cap)
+        self.proposal = tc_proposal_window(self.graph, self.weights, self.h, f_in, f_out)
+        return self.proposal
+
+    def pilot(self, k: int, seed: int, stream_id: int = 0):
+        rp = tc_sample_estimate(self.graph, self.weights, [self.motif], k, seed,
+                                stream_id=stream_id, moments=True)
+        rw = tc_sample_estimate(self.graph, self.proposal, [self.motif], k, seed,
+                                stream_id=stream_id, moments=True)
+        return moments(rp, self.weights, k), moments(rw, self.proposal, k)
+
+    def fit(self, k_pilot: int = 10**6, seed: int = 0x5EED, candidates=None):
+        """Pick (quarter, cap) by pilot variance on the label stream."""
+        best = None
+        self.trials = []
+        for quarter, cap in candidates or self.CANDIDATES:
+            self.build(quarter, cap)
+            if self.proposal.status() != 0:  # total beyond 64 bits
+                self.trials.append((quarter, cap, None))
+                continue
+            r = tc_sample_estimate(self.graph, self.proposal, [self.motif], k_pilot, seed,
+                                   stream_id=LABEL_STREAM, moments=True)
+            if int(r.status.item()) & 0xFFFFFFFF:
+                self.trials.append((quarter, cap, None))
+                continue
+            v = moments(r, self.proposal, k_pilot).var
+            self.trials.append((quarter, cap, v))
+            if best is None or v < best[2]:
+                best = (quarter, cap, v)
+        if best is None:
+            self.proposal = None
+            return None
+        self.choice = best[:2]
+        return self.build(*self.choice)
