@@ -10,16 +10,16 @@
 // (u, t - delta)} and lo_in[p] + a[p] = #{in-CSR entries <= (u, t)}; the
 // in-CSR order q is sorted by (v, t), so v's out-window bounds are ranks of
 // (v, t) and (v, t + delta) in the out-CSR.  One bound of each side is the
-// rank of the centre time itself and does not depend on delta: it is ranked
-// once per call, and each delta adds one rank pass per side.  Each rank
-// sequence is one merge-path pass:
+// rank of the centre time itself and does not depend on delta.  Each side
+// is one merge-path pass over its queries and data:
 //   k_mp_split    splits the merged sequence (queries + data) into tiles of
 //                 kMPTile entries by a binary search on each tile diagonal
-//                 (every pass of the call in one launch),
-//   k_mp_rank     stages the tile's data keys in LDS and ranks each of the
-//                 tile's queries there,
-// so every array is read once per pass, coalesced.  Side 3 comes out in
-// in-CSR order: its last pass writes one record per edge id holding the
+//                 (both sides in one launch),
+//   k_mp_rank     stages the tile's data keys in LDS, ranks each of the
+//                 tile's queries there (the delta-free bound), and gallops
+//                 from that bound to every delta's bound,
+// so every array is read once per call, coalesced.  Side 3 comes out in
+// in-CSR order: its pass writes one record per edge id holding the
 // delta-free bound and every delta's rank, so a single scatter and a single
 // gather carry all deltas to out-CSR order.  Then:
 //   k_combine     per p: each delta's side-3 window from the record, the
@@ -59,14 +59,13 @@ __device__ __forceinline__ bool before(int32_t dv, int64_t dt, int32_t qv, int64
 // split[b] = number of queries among the first min(b * kMPTile, nq + nd)
 // entries of the merge (a query is taken first unless a data entry is ranked
 // before it), by a bisection on the diagonal.
-// Every split of the call (per side: the delta-free bound, then one per
-// delta) in one launch: blockIdx.y picks the job.  Two launches: every
+// The splits of both sides' passes in one launch: blockIdx.y picks the job.  Two launches: every
 // kSplitStride-th diagonal (and the last) bisects the whole range; the
 // others bisect only between the splits of their two coarse neighbours (the
 // split grows with the diagonal), a window of at most kSplitStride tiles
 // whose probes stay in L2, where a full bisection reads a fresh line per
 // probe.
-constexpr int kMaxJobs = 2 + 2 * kMaxDeltas;
+constexpr int kMaxJobs = 2;
 constexpr int64_t kSplitStride = 32;
 struct SplitJob {
   KeyCols Q, D;
@@ -125,31 +124,29 @@ __global__ __launch_bounds__(256) void k_mp_split(SplitJobs J, int64_t nq, int64
   S.split[b] = split_search(S, d, lo, hi);
 }
 
-// What a rank pass stores for query i (rank = its rank in the data):
-//   RO_PLAIN  out[i] = rank (a delta-free bound, or a delta's bound kept for
-//             the side-3 record)
-//   RO_SIDE1  side 1's window from the delta-free bound F[i] and this
-//             delta's rank: a window after the centre time has lo = F and
-//             len = rank - F, one before it lo = rank and len = F - rank
+// One rank pass per side.  Query i's rank in the data with the centre time
+// itself is the delta-free bound F; each delta's bound R is found from F by
+// galloping over the data (probe F -/+ 1, 2, 4, ... until the probe crosses
+// the delta's key, then bisect the last gap), reading the tile's LDS copy
+// where the probe lies inside the tile and the data columns elsewhere.  A
+// window before the centre time (UPPER: F counts "<=") has R = #{data <
+// (w, t - delta)} <= F; one after it (F counts "<") has R = #{data <=
+// (w, t + delta)} >= F.  The pass stores:
+//   RO_SIDE1  side 1's windows, for every delta: lo = F, len = R - F after
+//             the centre time, lo = R, len = F - R before it;
 //   RO_REC    side 3's record of query i's edge, at rec[eid[i] * stride]:
-//             F[i], the other deltas' ranks R[0..nr)[i], this rank, zeros.
-// Every array a pass writes is distinct from every array it reads (the
-// pointers are restrict), so a query's loads never wait for the previous
-// query's stores; the bound and record inputs are loaded before the search.
-enum { RO_PLAIN = 0, RO_SIDE1 = 1, RO_REC = 2 };
+//             F, then every delta's R in delta order, then zeros.
+// The inputs of a thread's queries are loaded before any of its stores, so
+// no load waits behind a store it might alias.
+enum { RO_SIDE1 = 1, RO_REC = 2 };
 constexpr int kMaxRecWords = 12;
+constexpr int kRankPer = kMPTile / kMPBlock;  // queries per thread at most
 struct RankMode {
-  int mode, after, nr, stride;
-  const uint32_t* R[kMaxDeltas];
-};
-struct RankOut {
-  RankMode M;
-  uint32_t* out;
-  const uint32_t* F;
-  uint32_t* lo;
-  uint32_t* len;
-  uint32_t* rec;
-  const int32_t* eid;
+  int nd, chain;            // chain: deltas ascending, each gallop starts at the last bound
+  int64_t dmax;             // the largest delta
+  int64_t dsh[kMaxDeltas];  // +delta (window after the centre time) or -delta
+  uint32_t* lo[kMaxDeltas];
+  uint32_t* len[kMaxDeltas];
 };
 
 // record words per edge: the delta-free bound and one rank per delta,
@@ -159,85 +156,299 @@ __host__ __device__ constexpr int rec_stride(int nd) {
   return w <= 2 ? 2 : ((w + 3) / 4) * 4;
 }
 
-// rank of every query of the tile, stored as MODE says (a compile-time
-// mode: the record mode's uniform state would otherwise cost the plain
-// passes scalar registers and a quarter of their resident blocks)
-template <bool UPPER, int MODE, int NR = 0>
+// Data entries [lo, hi) are in LDS, entry j at index j - base.
+struct TileKeys {
+  const int32_t* s_v;
+  const int64_t* s_t;
+  int64_t base, lo, hi;
+  KeyCols D;
+  __device__ __forceinline__ void get(int64_t j, int32_t* v, int64_t* t) const {
+    if (j >= lo && j < hi) {
+      *v = s_v[j - base];
+      *t = s_t[j - base];
+    } else {
+      *v = D.v[j];
+      *t = D.t[j] + D.shift;
+    }
+  }
+};
+
+// Gallop from a bound F to the rank of (qv, qt): backwards with "<" when
+// UPPER (every entry from F on is not before the key: F is the delta-free
+// bound or a smaller delta's rank), forwards with "<=" otherwise (every
+// entry below F is before it).  At most 2 log2(nd) + 2 probes.
+template <bool UPPER>
+__device__ __forceinline__ int64_t gallop(const TileKeys& K, int64_t nd, int64_t F, int32_t qv,
+                                          int64_t qt) {
+  int64_t lo, hi;  // entries <= lo are before the key, entries >= hi are not
+  int32_t v;
+  int64_t t;
+  if (UPPER) {
+    hi = F;
+    lo = -1;
+    for (int64_t step = 1;; step <<= 1) {
+      const int64_t j = hi - step;
+      if (j < 0) break;
+      K.get(j, &v, &t);
+      if (before<false>(v, t, qv, qt)) {
+        lo = j;
+        break;
+      }
+      hi = j;
+    }
+    while (hi - lo > 1) {
+      const int64_t mid = lo + ((hi - lo) >> 1);
+      K.get(mid, &v, &t);
+      if (before<false>(v, t, qv, qt))
+        lo = mid;
+      else
+        hi = mid;
+    }
+  } else {
+    lo = F - 1;
+    hi = nd;
+    for (int64_t step = 1;; step <<= 1) {
+      const int64_t j = lo + step;
+      if (j >= nd) break;
+      K.get(j, &v, &t);
+      if (!before<true>(v, t, qv, qt)) {
+        hi = j;
+        break;
+      }
+      lo = j;
+    }
+    while (hi - lo > 1) {
+      const int64_t mid = lo + ((hi - lo) >> 1);
+      K.get(mid, &v, &t);
+      if (before<true>(v, t, qv, qt))
+        lo = mid;
+      else
+        hi = mid;
+    }
+  }
+  return hi;
+}
+
+// The rank pass of one side (a compile-time mode and, for the record, delta
+// count: the record's unrolled state would otherwise cost the side-1 pass
+// registers and resident blocks)
+// The first entry in (lo, hi] that is not before (qv, qt) (counted with
+// "<=" when UQ), given that entry lo is before it (or lo = -1) and entry hi
+// is not (or hi = nd): galloping inwards from both ends, then bisecting, so
+// the cost follows the distance of the answer from the nearer end.
+template <bool UQ>
+__device__ __forceinline__ int64_t bracket(const TileKeys& K, int64_t lo, int64_t hi, int32_t qv,
+                                           int64_t qt) {
+  int32_t v;
+  int64_t t;
+  for (int64_t s = 1; hi - lo > 2 * s; s <<= 1) {
+    const int64_t a = lo + s, b = hi - s;
+    K.get(a, &v, &t);
+    const bool pa = before<UQ>(v, t, qv, qt);
+    K.get(b, &v, &t);
+    const bool pb = before<UQ>(v, t, qv, qt);
+    if (!pa) {
+      hi = a;
+      break;
+    }
+    if (pb) {
+      lo = b;
+      break;
+    }
+    lo = a;
+    hi = b;
+  }
+  while (hi - lo > 1) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    K.get(mid, &v, &t);
+    if (before<UQ>(v, t, qv, qt))
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return hi;
+}
+
+// Entries staged beside the tile for the delta windows that leave it: on
+// the side the windows extend to (before the tile for windows before the
+// centre time, after it otherwise), up to kExt entries, when the widest
+// window of the tile's first (or last) query reaches past the tile.
+constexpr int kExt = 1024;
+
+template <bool UPPER, int MODE, int ND = 0>
 __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, KeyCols D, int64_t nd,
                                                       const uint32_t* __restrict__ split,
-                                                      RankMode M, uint32_t* __restrict__ out,
-                                                      const uint32_t* __restrict__ F,
-                                                      uint32_t* __restrict__ lo_out,
-                                                      uint32_t* __restrict__ len_out,
-                                                      uint32_t* __restrict__ rec,
+                                                      RankMode M, uint32_t* __restrict__ rec,
                                                       const int32_t* __restrict__ eid,
                                                       const uint32_t* __restrict__ gstatus) {
   if (*gstatus) return;  // a rejected graph: its arrays are not sorted
-  __shared__ int32_t s_v[kMPTile];
-  __shared__ int64_t s_t[kMPTile];
+  __shared__ int32_t s_v[kMPTile + kExt];
+  __shared__ int64_t s_t[kMPTile + kExt];
+  __shared__ int s_ext;
   const int64_t b = blockIdx.x;
   const int64_t d0 = b * kMPTile;
   const int64_t d1 = d0 + kMPTile < nq + nd ? d0 + kMPTile : nq + nd;
   const int64_t q0 = split[b], q1 = split[b + 1];
   const int64_t i0 = d0 - q0, i1 = d1 - q1;
   const int nd_t = (int)(i1 - i0);
+  // LDS index k holds data entry base + k; the tile starts at toff
+  const int toff = UPPER ? kExt : 0;
+  const int64_t base = i0 - toff;
   for (int k = threadIdx.x; k < nd_t; k += kMPBlock) {
-    s_v[k] = D.v[i0 + k];
-    s_t[k] = D.t[i0 + k] + D.shift;
+    s_v[toff + k] = D.v[i0 + k];
+    s_t[toff + k] = D.t[i0 + k] + D.shift;
+  }
+  if (threadIdx.x == 0) {
+    // does the widest window of the outermost query leave the tile?
+    bool need = false;
+    if (q0 < q1) {
+      const int64_t qi = UPPER ? q0 : q1 - 1;
+      const int32_t v = Q.v[qi];
+      const int64_t t = Q.t[qi] + Q.shift + (UPPER ? -M.dmax : M.dmax);
+      if (UPPER && i0 > 0)
+        need = !before<false>(D.v[i0 - 1], D.t[i0 - 1] + D.shift, v, t);
+      else if (!UPPER && i1 < nd)
+        need = before<true>(D.v[i1], D.t[i1] + D.shift, v, t);
+    }
+    const int64_t room = UPPER ? i0 : nd - i1;
+    s_ext = need ? (int)(room < kExt ? room : kExt) : 0;
+  }
+  // this thread's queries: `per` consecutive ones (at most kRankPer),
+  // loaded before any store
+  const int per = (int)((q1 - q0 + kMPBlock - 1) / kMPBlock);
+  const int64_t qb = q0 + (int64_t)threadIdx.x * per;
+  const int mine = (int)(q1 - qb < 0 ? 0 : (q1 - qb < per ? q1 - qb : per));
+  int32_t qv[kRankPer];
+  int64_t qt[kRankPer], e[kRankPer];
+#pragma unroll
+  for (int r = 0; r < kRankPer; ++r) {
+    const bool ok = r < mine;
+    qv[r] = ok ? Q.v[qb + r] : 0;
+    qt[r] = ok ? Q.t[qb + r] + Q.shift : 0;
+    e[r] = MODE == RO_REC && ok ? eid[qb + r] : 0;
   }
   __syncthreads();
-  for (int64_t i = q0 + threadIdx.x; i < q1; i += kMPBlock) {
-    const int32_t qv = Q.v[i];
-    const int64_t qt = Q.t[i] + Q.shift;
-    // inputs of the store, loaded before the search
-    const uint32_t f = MODE != RO_PLAIN ? F[i] : 0u;
-    int64_t e = 0;
-    uint32_t w[kMaxRecWords];
-    if (MODE == RO_REC) {
-      e = eid[i];
+  const int ext = s_ext;
+  if (ext > 0) {
+    const int64_t x0 = UPPER ? i0 - ext : i1;
+    const int k0 = (int)(x0 - base);
+    for (int k = threadIdx.x; k < ext; k += kMPBlock) {
+      s_v[k0 + k] = D.v[x0 + k];
+      s_t[k0 + k] = D.t[x0 + k] + D.shift;
+    }
+    __syncthreads();
+  }
+  if (mine == 0) return;
+  const TileKeys K{s_v, s_t, base, UPPER ? i0 - ext : i0, UPPER ? i1 : i1 + ext, D};
+  const int32_t* tv = s_v + toff;
+  const int64_t* tt = s_t + toff;
+  // delta-free bounds: a bisection of the tile for the first query, then
+  // galloping on from the previous query's bound (the queries are sorted)
+  int64_t F[kRankPer];
 #pragma unroll
-      for (int j = 0; j < kMaxRecWords - 1; ++j) w[1 + j] = j < NR ? M.R[j][i] : 0u;
-    }
-    int lo = 0, n = nd_t;
-    while (n > 0) {
-      const int half = n >> 1;
-      const int mid = lo + half;
-      const bool go = before<UPPER>(s_v[mid], s_t[mid], qv, qt);
-      lo = go ? mid + 1 : lo;
-      n = go ? n - half - 1 : half;
-    }
-    const uint32_t rank = (uint32_t)(i0 + lo);
-    if (MODE == RO_PLAIN) {
-      out[i] = rank;
-    } else if (MODE == RO_SIDE1) {
-      lo_out[i] = M.after ? f : rank;
-      len_out[i] = M.after ? rank - f : f - rank;
-    } else if (rec_stride(NR + 1) == 2) {
-      reinterpret_cast<uint2*>(rec)[e] = make_uint2(f, rank);
+  for (int r = 0; r < kRankPer; ++r) {
+    if (r >= mine) break;
+    int lo, hi;
+    if (r == 0) {
+      lo = -1;
+      hi = nd_t;
     } else {
-      constexpr int kStride = rec_stride(NR + 1);
-      w[0] = f;
-      w[1 + NR] = rank;
-      uint4* r4 = reinterpret_cast<uint4*>(rec) + e * (kStride / 4);
+      lo = (int)(F[r - 1] - i0) - 1;
+      hi = nd_t;
+      for (int s = 1;; s <<= 1) {
+        const int j = lo + s;
+        if (j >= nd_t) break;
+        if (!before<UPPER>(tv[j], tt[j], qv[r], qt[r])) {
+          hi = j;
+          break;
+        }
+        lo = j;
+      }
+    }
+    while (hi - lo > 1) {
+      const int mid = lo + ((hi - lo) >> 1);
+      if (before<UPPER>(tv[mid], tt[mid], qv[r], qt[r]))
+        lo = mid;
+      else
+        hi = mid;
+    }
+    F[r] = i0 + hi;
+  }
+  // Each delta's bound: the thread's first query gallops from its
+  // delta-free bound (or from the previous delta's bound when the deltas
+  // ascend); every later query is bracketed by the previous query's bound
+  // for the same delta (its keys are not larger) and, before the centre
+  // time, by its own delta-free bound.
+  if (MODE == RO_SIDE1) {
+    int64_t from0 = F[0];
+    for (int k = 0; k < M.nd; ++k) {
+      const int64_t dk = M.dsh[k];
+      int64_t prev = 0;
 #pragma unroll
-      for (int q = 0; q < kStride / 4; ++q)
-        r4[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+      for (int r = 0; r < kRankPer; ++r) {
+        if (r >= mine) break;
+        int64_t R;
+        if (r == 0) {
+          R = gallop<UPPER>(K, nd, M.chain ? from0 : F[0], qv[0], qt[0] + dk);
+          from0 = R;
+        } else if (UPPER) {
+          R = bracket<false>(K, prev - 1, F[r], qv[r], qt[r] + dk);
+        } else {
+          R = gallop<false>(K, nd, F[r] > prev ? F[r] : prev, qv[r], qt[r] + dk);
+        }
+        prev = R;
+        M.lo[k][qb + r] = (uint32_t)(UPPER ? R : F[r]);
+        M.len[k][qb + r] = (uint32_t)(UPPER ? F[r] - R : R - F[r]);
+      }
+    }
+  } else {
+    constexpr int kStride = rec_stride(ND);
+    int64_t prevR[ND > 0 ? ND : 1];
+#pragma unroll
+    for (int r = 0; r < kRankPer; ++r) {
+      if (r >= mine) break;
+      uint32_t w[kMaxRecWords];
+#pragma unroll
+      for (int j = 0; j < kMaxRecWords; ++j) w[j] = 0;
+      w[0] = (uint32_t)F[r];
+#pragma unroll
+      for (int k = 0; k < ND; ++k) {
+        const int64_t key = qt[r] + M.dsh[k];
+        int64_t R;
+        if (r == 0)
+          R = gallop<UPPER>(K, nd, M.chain && k > 0 ? prevR[k > 0 ? k - 1 : 0] : F[0], qv[0],
+                            key);
+        else if (UPPER)
+          R = bracket<false>(K, prevR[k] - 1, F[r], qv[r], key);
+        else
+          R = gallop<false>(K, nd, F[r] > prevR[k] ? F[r] : prevR[k], qv[r], key);
+        prevR[k] = R;
+        w[1 + k] = (uint32_t)R;
+      }
+      if (kStride == 2) {
+        reinterpret_cast<uint2*>(rec)[e[r]] = make_uint2(w[0], w[1]);
+      } else {
+        uint4* r4 = reinterpret_cast<uint4*>(rec) + e[r] * (kStride / 4);
+#pragma unroll
+        for (int q = 0; q < kStride / 4; ++q)
+          r4[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+      }
     }
   }
 }
 
-// the record pass for nr other deltas (0..7)
+// the record pass for nd deltas (1..8)
 template <bool UPPER>
-static decltype(&k_mp_rank<UPPER, RO_REC, 0>) rec_kernel(int nr) {
-  switch (nr) {
-    case 0: return k_mp_rank<UPPER, RO_REC, 0>;
+static decltype(&k_mp_rank<UPPER, RO_REC, 1>) rec_kernel(int nd) {
+  switch (nd) {
     case 1: return k_mp_rank<UPPER, RO_REC, 1>;
     case 2: return k_mp_rank<UPPER, RO_REC, 2>;
     case 3: return k_mp_rank<UPPER, RO_REC, 3>;
     case 4: return k_mp_rank<UPPER, RO_REC, 4>;
     case 5: return k_mp_rank<UPPER, RO_REC, 5>;
     case 6: return k_mp_rank<UPPER, RO_REC, 6>;
-    default: return k_mp_rank<UPPER, RO_REC, 7>;
+    case 7: return k_mp_rank<UPPER, RO_REC, 7>;
+    default: return k_mp_rank<UPPER, RO_REC, 8>;
   }
 }
 
@@ -582,7 +793,7 @@ static WeightsLayout weights_layout(int64_t m) {
 }
 
 // A call over nd deltas: nd weights sets, then the scratch of the call (the
-// side-3 records by edge id and the merge splits of every pass).
+// side-3 records by edge id and the merge splits of both sides).
 struct BatchLayout {
   size_t own, rec, split, total;
   int64_t nsplit;
@@ -595,7 +806,7 @@ static BatchLayout batch_layout(int64_t m, int nd) {
   L.rec = L.own * (size_t)nd;
   const size_t rec_bytes = align256((size_t)m * (size_t)rec_stride(nd) * 4 + 1);
   L.split = L.rec + rec_bytes;
-  L.total = L.split + align256((size_t)(2 + 2 * nd) * (size_t)(L.nsplit + 1) * 4);
+  L.total = L.split + align256((size_t)kMaxJobs * (size_t)(L.nsplit + 1) * 4);
   return L;
 }
 
@@ -653,7 +864,6 @@ tc_status path_weights_batch(const tc_graph* g, const int64_t* deltas, int nd,
     // centre time is delta-free: "<=" for a window before t, "<" for one
     // after it; each delta's bound is (w, t - delta) with "<" or
     // (w, t + delta) with "<=".
-    auto shifted = [&](const KeyCols& q, int64_t sh) { return KeyCols{q.v, q.t, sh}; };
     const KeyCols d1 = cls.mode1 == TC_SIDE_IN ? ink : outk;
     const KeyCols d3 = cls.mode3 == TC_SIDE_IN ? ink : outk;
     SplitJobs J{};
@@ -662,78 +872,49 @@ tc_status path_weights_batch(const tc_graph* g, const int64_t* deltas, int nd,
       J.j[nj] = SplitJob{q, d, split + (size_t)nj * (size_t)(nsplit + 1), upper ? 1 : 0};
       return nj++;
     };
-    int j1f = -1, j3f = -1, j1[kMaxDeltas], j3[kMaxDeltas];
+    int j1f = -1, j3f = -1;
     auto dshift = [&](int after, int64_t d) { return after ? d : -d; };
-    if (s1) {
-      j1f = job(outk, d1, !cls.after1);
-      for (int i = 0; i < nd; ++i) j1[i] = job(shifted(outk, dshift(cls.after1, deltas[i])), d1,
-                                               cls.after1 != 0);
-    }
-    if (s3) {
-      j3f = job(ink, d3, !cls.after3);
-      for (int i = 0; i < nd; ++i) j3[i] = job(shifted(ink, dshift(cls.after3, deltas[i])), d3,
-                                               cls.after3 != 0);
-    }
+    if (s1) j1f = job(outk, d1, !cls.after1);
+    if (s3) j3f = job(ink, d3, !cls.after3);
     if (nj > 0) {
       const int64_t ncoarse = (nsplit - 1 + kSplitStride - 1) / kSplitStride + 1;
       hipLaunchKernelGGL(k_mp_split_coarse, dim3((unsigned)((ncoarse + 255) / 256), nj), dim3(256),
                          0, st, J, m, m, nsplit);
       hipLaunchKernelGGL(k_mp_split, dim3(sb, nj), dim3(256), 0, st, J, m, m, nsplit);
     }
-    auto rank = [&](int jb, const RankOut& O) {
-      const SplitJob& S = J.j[jb];
-      auto kern = k_mp_rank<false, RO_PLAIN>;
-      if (O.M.mode == RO_PLAIN)
-        kern = S.upper ? k_mp_rank<true, RO_PLAIN> : k_mp_rank<false, RO_PLAIN>;
-      else if (O.M.mode == RO_SIDE1)
-        kern = S.upper ? k_mp_rank<true, RO_SIDE1> : k_mp_rank<false, RO_SIDE1>;
-      else
-        kern = S.upper ? rec_kernel<true>(O.M.nr) : rec_kernel<false>(O.M.nr);
-      hipLaunchKernelGGL(kern, dim3(rb), dim3(kMPBlock), 0, st, S.Q, m, S.D, m,
-                         (const uint32_t*)S.split, O.M, O.out, O.F, O.lo, O.len, O.rec, O.eid,
-                         gst);
-    };
-    // Temporaries live in arrays that k_combine writes last: the first
-    // set's lo_out holds side 1's delta-free bound while side 1's delta
-    // passes read it, then side 3's (in-CSR order); the sets' b hold side
-    // 3's ranks of all deltas but the last until the record pass.
-    uint32_t* Ftmp = w[0].lo_out;
-    if (s1) {
-      RankOut O{};
-      O.M.mode = RO_PLAIN;
-      O.out = Ftmp;
-      rank(j1f, O);
-      for (int i = 0; i < nd; ++i) {
-        RankOut P{};
-        P.M.mode = RO_SIDE1;
-        P.M.after = cls.after1;
-        P.F = Ftmp;
-        P.lo = w[i].lo_in;
-        P.len = w[i].a;
-        rank(j1[i], P);
+    auto rank_mode = [&]() {
+      RankMode M{};
+      M.nd = nd;
+      M.chain = 1;
+      M.dmax = deltas[0];
+      for (int i = 1; i < nd; ++i) {
+        if (deltas[i] < deltas[i - 1]) M.chain = 0;
+        M.dmax = deltas[i] > M.dmax ? deltas[i] : M.dmax;
       }
+      return M;
+    };
+    if (s1) {
+      // side 1 in scan order: every delta's window straight into its set
+      const SplitJob& S = J.j[j1f];
+      RankMode M = rank_mode();
+      for (int i = 0; i < nd; ++i) {
+        M.dsh[i] = dshift(cls.after1, deltas[i]);
+        M.lo[i] = w[i].lo_in;
+        M.len[i] = w[i].a;
+      }
+      const auto kern = S.upper ? k_mp_rank<true, RO_SIDE1> : k_mp_rank<false, RO_SIDE1>;
+      hipLaunchKernelGGL(kern, dim3(rb), dim3(kMPBlock), 0, st, S.Q, m, S.D, m,
+                         (const uint32_t*)S.split, M, (uint32_t*)nullptr, (const int32_t*)nullptr,
+                         gst);
     }
     if (s3) {
-      RankOut O{};
-      O.M.mode = RO_PLAIN;
-      O.out = Ftmp;
-      rank(j3f, O);
-      for (int i = 0; i + 1 < nd; ++i) {
-        RankOut P{};
-        P.M.mode = RO_PLAIN;
-        P.out = w[i].b;
-        rank(j3[i], P);
-      }
-      RankOut P{};
-      P.M.mode = RO_REC;
-      P.M.after = cls.after3;
-      P.F = Ftmp;
-      P.M.nr = nd - 1;
-      for (int i = 0; i + 1 < nd; ++i) P.M.R[i] = w[i].b;
-      P.M.stride = rec_stride(nd);
-      P.rec = rec;
-      P.eid = g->in_eid;
-      rank(j3[nd - 1], P);
+      // side 3 in in-CSR order: one record per edge id
+      const SplitJob& S = J.j[j3f];
+      RankMode M = rank_mode();
+      for (int i = 0; i < nd; ++i) M.dsh[i] = dshift(cls.after3, deltas[i]);
+      const auto kern = S.upper ? rec_kernel<true>(nd) : rec_kernel<false>(nd);
+      hipLaunchKernelGGL(kern, dim3(rb), dim3(kMPBlock), 0, st, S.Q, m, S.D, m,
+                         (const uint32_t*)S.split, M, rec, (const int32_t*)g->in_eid, gst);
     }
     CombineOut C{};
     C.nd = nd;
