@@ -155,3 +155,40 @@ def test_batch_host_errors(tcb, tiny):
             tcb.tc_path_weights_batch(G, bad)
     with pytest.raises(tcb.TCError):
         tcb.tc_path_weights_batch(G, [1, 2], cls=(0, 0, 0, 0))
+
+
+def _hub_graph(seed=5, per_side=12000, others=400, span=100000):
+    """Two hubs with dense in- and out-lists (windows far wider than a rank
+    tile and its staged neighbours at the larger deltas), edges between the
+    hubs, and sparse noise."""
+    rng = np.random.default_rng(seed)
+    H, K = 0, 1
+    x = rng.integers(2, 2 + others, size=per_side)
+    y = rng.integers(2, 2 + others, size=per_side)
+    ns = rng.integers(2, 2 + others, size=3000)
+    nd = rng.integers(2, 2 + others, size=3000)
+    src = np.concatenate([x, np.full(per_side, H), np.full(2000, H), np.full(2000, K), ns])
+    dst = np.concatenate([np.full(per_side, H), y, np.full(2000, K), np.full(2000, H), nd])
+    t = rng.integers(0, span, size=src.size)
+    t[:50] = 777  # ties at one time
+    keep = src != dst
+    return sg.TemporalGraph(2 + others, src[keep].astype(np.int32), dst[keep].astype(np.int32),
+                            t[keep].astype(np.int64), name="hubs")
+
+
+@pytest.mark.parametrize("cls", PATH_CLASSES[:8] + WEDGE_CLASSES[:2] + WEDGE_CLASSES[4:6])
+def test_batch_hub_windows(tcb, torch_mod, cls):
+    """Windows of thousands of entries: the rank pass's galloping leaves the
+    tile and its staged entries, and later queries of a thread are bracketed
+    by the previous query's bound; ascending and unordered deltas."""
+    g = _hub_graph()
+    G, og = build_both(tcb, torch_mod, g)
+    for deltas in ([10, 1000, 20000, 90000], [90000, 0, 20000, 3]):
+        Ws = tcb.tc_path_weights_batch(G, deltas, cls=cls)
+        for W, d in zip(Ws, deltas):
+            ow = og.weights(d, cls=bytes(cls))
+            A = W.arrays()
+            for name in ("lo_in", "a", "lo_out", "b"):
+                assert np.array_equal(_u32(A[name]), getattr(ow, name)), (cls, d, name)
+            assert np.array_equal(_u64(A["S"]), ow.S)
+            assert W.status() == ow.status
