@@ -58,10 +58,21 @@ typedef short s16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // bfloat16 bits of a float, round to nearest even (NaN stays NaN)
+// bfloat16 rounded to nearest even (the conversion instruction; single
+// precision denormals are kept, so it agrees with the rounding rule on every
+// value but NaN), NaN made quiet keeping its top bits; a select, not a
+// branch, so a wavefront never splits here
 __device__ __forceinline__ uint16_t bf16_bits(float f) {
   const uint32_t u = __float_as_uint(f);
-  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40u);
-  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+  const uint16_t rne = __builtin_bit_cast(uint16_t, (__bf16)f);
+  return (u & 0x7FFFFFFFu) > 0x7F800000u ? (uint16_t)((u >> 16) | 0x40u) : rne;
+}
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+// two values that cannot be NaN (outputs of a ReLU), rounded to nearest even
+// in one instruction: a in the low half, b in the high half
+__device__ __forceinline__ uint32_t bf16x2_bits(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
 }
 __device__ __forceinline__ float bf16_val(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 __device__ __forceinline__ float bf16_round(float f) { return bf16_val(bf16_bits(f)); }
@@ -272,10 +283,14 @@ __device__ __forceinline__ void mlp_fwd(const MlpOps& o, const MlpVecs& sv, s16x
   }
 #pragma unroll
   for (int kc = 0; kc < 4; ++kc) {
-    uint16_t e[8];
-#pragma unroll
-    for (int s = 0; s < 8; ++s) e[s] = bf16_bits(fmaxf(r->z1[kc >> 1][8 * (kc & 1) + s], 0.0f));
-    r->h1[kc] = pack8(e);
+    const f32x16& z = r->z1[kc >> 1];
+    const int s0 = 8 * (kc & 1);
+    uint4 q;
+    q.x = bf16x2_bits(fmaxf(z[s0], 0.0f), fmaxf(z[s0 + 1], 0.0f));
+    q.y = bf16x2_bits(fmaxf(z[s0 + 2], 0.0f), fmaxf(z[s0 + 3], 0.0f));
+    q.z = bf16x2_bits(fmaxf(z[s0 + 4], 0.0f), fmaxf(z[s0 + 5], 0.0f));
+    q.w = bf16x2_bits(fmaxf(z[s0 + 6], 0.0f), fmaxf(z[s0 + 7], 0.0f));
+    r->h1[kc] = __builtin_bit_cast(bf16x8, q);
   }
   float part = 0.0f;
 #pragma unroll
@@ -288,8 +303,11 @@ __device__ __forceinline__ void mlp_fwd(const MlpOps& o, const MlpVecs& sv, s16x
       c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.w2[ob][kc], r->h1[kc], c, 0, 0, 0);
     r->z2[ob] = c;
 #pragma unroll
-    for (int v = 0; v < 16; ++v)
-      part += sv.w3[32 * ob + drow(v, h)] * bf16_round(fmaxf(c[v], 0.0f));
+    for (int v = 0; v < 16; v += 2) {
+      const uint32_t pr = bf16x2_bits(fmaxf(c[v], 0.0f), fmaxf(c[v + 1], 0.0f));
+      part += sv.w3[32 * ob + drow(v, h)] * __uint_as_float(pr << 16);
+      part += sv.w3[32 * ob + drow(v + 1, h)] * __uint_as_float(pr & 0xFFFF0000u);
+    }
   }
   part += __shfl_xor(part, 32, kWave);
   r->z3 = part + sv.b3;
