@@ -271,14 +271,15 @@ struct Fwd {
   float z3;
 };
 
-// forward of 32 edges; fb = features 4h..4h+3 of edge lane % 32
+// forward of 32 edges; fb = features 4h..4h+3 of edge lane % 32; z (zero)
+// offsets every read of the small vectors
 __device__ __forceinline__ void mlp_fwd(const MlpOps& o, const MlpVecs& sv, s16x4 fb, int h,
-                                        Fwd* r) {
+                                        Fwd* r, int z = 0) {
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb) {
     f32x16 c;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) c[v] = sv.b1[32 * rb + drow(v, h)];
+    for (int v = 0; v < 16; ++v) c[v] = sv.b1[32 * rb + drow(v, h) + z];
     r->z1[rb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(o.w1[rb], fb, c, 0, 0, 0);
   }
 #pragma unroll
@@ -297,7 +298,7 @@ __device__ __forceinline__ void mlp_fwd(const MlpOps& o, const MlpVecs& sv, s16x
   for (int ob = 0; ob < 2; ++ob) {
     f32x16 c;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) c[v] = sv.b2[32 * ob + drow(v, h)];
+    for (int v = 0; v < 16; ++v) c[v] = sv.b2[32 * ob + drow(v, h) + z];
 #pragma unroll
     for (int kc = 0; kc < 4; ++kc)
       c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.w2[ob][kc], r->h1[kc], c, 0, 0, 0);
@@ -305,8 +306,8 @@ __device__ __forceinline__ void mlp_fwd(const MlpOps& o, const MlpVecs& sv, s16x
 #pragma unroll
     for (int v = 0; v < 16; v += 2) {
       const uint32_t pr = bf16x2_bits(fmaxf(c[v], 0.0f), fmaxf(c[v + 1], 0.0f));
-      part += sv.w3[32 * ob + drow(v, h)] * __uint_as_float(pr << 16);
-      part += sv.w3[32 * ob + drow(v + 1, h)] * __uint_as_float(pr & 0xFFFF0000u);
+      part += sv.w3[32 * ob + drow(v, h) + z] * __uint_as_float(pr << 16);
+      part += sv.w3[32 * ob + drow(v + 1, h) + z] * __uint_as_float(pr & 0xFFFF0000u);
     }
   }
   part += __shfl_xor(part, 32, kWave);
@@ -346,8 +347,13 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P
   for (int64_t tile = wave_id; tile < tiles; tile += wstride) {
     const int64_t row = tile * 32 + (lane & 31);
     const s16x4 fb = row < n ? load_feat4(feat, row, h) : s16x4{0, 0, 0, 0};
+    // The small vectors are read from LDS in every tile: an offset the
+    // compiler cannot see to be zero keeps it from holding all 96 per-lane
+    // values in registers, which would leave room for two wavefronts per SIMD.
+    int z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
     Fwd r;
-    mlp_fwd(o, sv, fb, h, &r);
+    mlp_fwd(o, sv, fb, h, &r, z);
     if (h == 0 && row < n) g[row] = sigmoidf(r.z3);
   }
 }
