@@ -551,6 +551,38 @@ __global__ __launch_bounds__(kWBlock) void k_combine(const int32_t* __restrict__
   }
 }
 
+// The 16-ary search tree over S (level L holds S[16^L i], ~0 past m; S
+// itself padded with ~0 to a multiple of 16 words) is written by the scan
+// kernels as S is formed: the apply pass stores S[p] into every level whose
+// stride divides p < m, and the tile scan, which forms S[m], stores the
+// entries at and past m and the padding.  Reading every 16th word of S back
+// would fetch all of its lines.
+struct TreeOut {
+  uint64_t* tree;  // null: no tree
+  int32_t levels;
+  int64_t count0;                       // S padded to this many words
+  uint64_t offset[kMaxTreeLevels + 1];  // word offset of level L (1-based), then the total
+};
+
+__device__ __forceinline__ void tree_put(const TreeOut& T, int64_t p, uint64_t s) {
+  for (int L = 1; L <= T.levels; ++L) {
+    if (p & (((int64_t)1 << (4 * L)) - 1)) break;
+    T.tree[T.offset[L] + (uint64_t)(p >> (4 * L))] = s;
+  }
+}
+
+// one thread: the padding of S and every level's entries at and past m
+__device__ void tree_tail(const TreeOut& T, uint64_t* S, int64_t m, uint64_t W) {
+  for (int64_t e = m + 1; e < T.count0; ++e) S[e] = ~0ull;
+  for (int L = 1; L <= T.levels; ++L) {
+    const int sh = 4 * L;
+    const int64_t first = (m + ((int64_t)1 << sh) - 1) >> sh;  // first i with 16^L i >= m
+    const int64_t cnt = (int64_t)(T.offset[L + 1] - T.offset[L]);
+    for (int64_t i = first; i < cnt; ++i)
+      T.tree[T.offset[L] + (uint64_t)i] = ((i << sh) == m) ? W : ~0ull;
+  }
+}
+
 // One block of 1024 threads: exclusive scan of the 128-bit tile sums; the
 // offsets are stored modulo 2^64 (only meaningful when W < 2^64).
 // A non-zero `upstream` word (the graph's build status, or the status of the
@@ -559,12 +591,14 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const uint64_t* __restrict_
                                                      int64_t ntiles, uint64_t* __restrict__ tile_off,
                                                      uint64_t* __restrict__ S, int64_t m,
                                                      uint32_t* __restrict__ status,
-                                                     const uint32_t* __restrict__ upstream) {
+                                                     const uint32_t* __restrict__ upstream,
+                                                     TreeOut T) {
   if (*upstream) {
     for (int64_t i = threadIdx.x; i < ntiles; i += 1024) tile_off[i] = 0;
     if (threadIdx.x == 0) {
       S[m] = 0;
       *status = *upstream & (TC_F_RANGE | TC_F_OVERFLOW);
+      if (T.tree) tree_tail(T, S, m, 0);
     }
     return;
   }
@@ -601,6 +635,7 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const uint64_t* __restrict_
     for (int w = 0; w < 16; ++w) W = add128(W, s_w[w]);
     S[m] = W.lo;
     *status = (W.hi != 0) ? TC_F_OVERFLOW : 0u;
+    if (T.tree) tree_tail(T, S, m, W.lo);
   }
 }
 
@@ -638,7 +673,7 @@ __global__ __launch_bounds__(kWBlock) void k_scan_apply(const uint32_t* __restri
                                                       const uint32_t* __restrict__ b,
                                                       const uint32_t* __restrict__ h, int64_t m,
                                                       const uint64_t* __restrict__ tile_off,
-                                                      uint64_t* __restrict__ S) {
+                                                      uint64_t* __restrict__ S, TreeOut T) {
   __shared__ uint64_t s_w[kWBlock / kWave];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t p0 = (int64_t)blockIdx.x * kWTile + (int64_t)threadIdx.x * kWItems;
@@ -688,7 +723,10 @@ __global__ __launch_bounds__(kWBlock) void k_scan_apply(const uint32_t* __restri
     ulonglong2* S2 = reinterpret_cast<ulonglong2*>(S + p0);
 #pragma unroll
     for (int j = 0; j < kWItems / 2; ++j) S2[j] = make_ulonglong2(out[2 * j], out[2 * j + 1]);
+    // p0 is a multiple of kWItems: only it can be a multiple of 16
+    if (T.tree && (p0 & 15) == 0) tree_put(T, p0, out[0]);
   } else {
+    if (T.tree && p0 < m && (p0 & 15) == 0) tree_put(T, p0, run);
 #pragma unroll
     for (int j = 0; j < kWItems; ++j) {
       const int64_t p = p0 + j;
@@ -704,29 +742,6 @@ __global__ __launch_bounds__(kWBlock) void k_scan_apply(const uint32_t* __restri
 // at most 16 entries.  upper_bound(S, r) - 1 is then found by reading one
 // 128-byte node per level: at each level the node is the last entry <= r of
 // the level above, and counting its entries <= r gives the next index.
-// All levels of the search tree over S in one launch (level L holds
-// S[16^L i], or ~0 past m), plus S's padding to a multiple of 16: thread e
-// below `words` writes tree word e, the next `pad` threads the padding.
-struct TreeShape {
-  int32_t levels;
-  uint64_t offset[kMaxTreeLevels + 1];  // word offset of level L (1-based), then the total
-};
-
-__global__ __launch_bounds__(256) void k_tree(uint64_t* __restrict__ S, int64_t m,
-                                              uint64_t* __restrict__ tree, TreeShape T,
-                                              int64_t pad) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t words = (int64_t)T.offset[T.levels + 1];
-  if (e < words) {
-    int L = 1;
-    while (L < T.levels && (uint64_t)e >= T.offset[L + 1]) ++L;
-    const uint64_t at = ((uint64_t)e - T.offset[L]) << (4 * L);
-    tree[e] = (at <= (uint64_t)m) ? S[at] : ~0ull;
-  } else if (e < words + pad) {
-    S[m + 1 + (e - words)] = ~0ull;
-  }
-}
-
 STree stree_layout(int64_t m) {
   STree T;
   T.levels = 0;
@@ -747,19 +762,16 @@ STree stree_layout(int64_t m) {
 
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// search tree over w->S (padding first, then each level)
-static void build_tree(tc_weights* w, hipStream_t st) {
-  const int64_t m = w->m;
-  const STree T = stree_layout(m);
-  const int64_t pad = T.count[0] - (m + 1);
-  TreeShape sh{};
-  sh.levels = T.levels;
-  for (int L = 1; L <= T.levels; ++L) sh.offset[L] = T.offset[L];
-  sh.offset[T.levels + 1] = T.total_words;
-  const int64_t n = (int64_t)T.total_words + pad;
-  if (n > 0)
-    hipLaunchKernelGGL(k_tree, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w->S, m,
-                       (uint64_t*)w->scratch, sh, pad);
+// where the scan kernels write the search tree over w->S
+static TreeOut tree_out(const tc_weights* w) {
+  const STree T = stree_layout(w->m);
+  TreeOut o{};
+  o.tree = (uint64_t*)w->scratch;
+  o.levels = T.levels;
+  o.count0 = T.count[0];
+  for (int L = 1; L <= T.levels; ++L) o.offset[L] = T.offset[L];
+  o.offset[T.levels + 1] = T.total_words;
+  return o;
 }
 
 // The arrays one weights set owns (they stay valid as long as the workspace).
@@ -936,15 +948,15 @@ tc_status path_weights_batch(const tc_graph* g, const int64_t* deltas, int nd,
                        (const int64_t*)g->out_t, m, C, gst);
   }
   for (int i = 0; i < nd; ++i) {
+    const TreeOut T = tree_out(&w[i]);
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, (const uint64_t*)tile_sums[i],
-                       ntiles, tile_off[i], w[i].S, m, w[i].status, gst);
+                       ntiles, tile_off[i], w[i].S, m, w[i].status, gst, T);
     if (ntiles > 0) {
       TimedLaunch tl("k_scan_apply", st);
       hipLaunchKernelGGL(k_scan_apply<false>, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
                          (const uint32_t*)w[i].a, (const uint32_t*)w[i].b,
-                         (const uint32_t*)nullptr, m, (const uint64_t*)tile_off[i], w[i].S);
+                         (const uint32_t*)nullptr, m, (const uint64_t*)tile_off[i], w[i].S, T);
     }
-    build_tree(&w[i], st);
   }
   if (hipGetLastError() != hipSuccess) return TC_E_HIP;
   return TC_OK;
@@ -998,13 +1010,13 @@ tc_status proposal_weights(const tc_weights* w, const uint32_t* h, void* ws, siz
   if (ntiles > 0)
     hipLaunchKernelGGL(k_qtile_sums, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
                        (const uint32_t*)w->a, (const uint32_t*)w->b, h, m, tile_sums);
+  const TreeOut T = tree_out(wq);
   hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, (const uint64_t*)tile_sums, ntiles,
-                     tile_off, wq->S, m, wq->status, (const uint32_t*)w->status);
+                     tile_off, wq->S, m, wq->status, (const uint32_t*)w->status, T);
   if (ntiles > 0)
     hipLaunchKernelGGL(k_scan_apply<true>, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
                        (const uint32_t*)w->a, (const uint32_t*)w->b, h, m,
-                       (const uint64_t*)tile_off, wq->S);
-  build_tree(wq, st);
+                       (const uint64_t*)tile_off, wq->S, T);
   if (hipGetLastError() != hipSuccess) return TC_E_HIP;
   return TC_OK;
 }
@@ -1076,7 +1088,7 @@ __global__ __launch_bounds__(kWBlock) void k_u32_tile_sums(const uint32_t* __res
 template <typename T>
 __global__ __launch_bounds__(kWBlock) void k_prefix_apply(const T* __restrict__ v, int64_t m,
                                                         const uint64_t* __restrict__ tile_off,
-                                                        uint64_t* __restrict__ out) {
+                                                        uint64_t* __restrict__ out, TreeOut tr) {
   __shared__ uint64_t s_w[kWBlock / kWave];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t p0 = (int64_t)blockIdx.x * kWTile + (int64_t)threadIdx.x * kWItems;
@@ -1092,6 +1104,7 @@ __global__ __launch_bounds__(kWBlock) void k_prefix_apply(const T* __restrict__ 
   __syncthreads();
   uint64_t run = tile_off[blockIdx.x] + inc - s;
   for (int q = 0; q < wave; ++q) run += s_w[q];
+  if (tr.tree && p0 < m && (p0 & 15) == 0) tree_put(tr, p0, run);
 #pragma unroll
   for (int j = 0; j < kWItems; ++j) {
     if (p0 + j < m) out[p0 + j] = run;
@@ -1223,10 +1236,10 @@ tc_status proposal_window(const tc_graph* g, const tc_weights* w, const uint32_t
       hipLaunchKernelGGL(k_u32_tile_sums, dim3((unsigned)ntiles), dim3(kWBlock), 0, st, f, m,
                          tile_sums);
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, (const uint64_t*)tile_sums,
-                       ntiles, tile_off, ps, m, fstatus, gst);
+                       ntiles, tile_off, ps, m, fstatus, gst, TreeOut{});
     if (ntiles > 0)
       hipLaunchKernelGGL(k_prefix_apply<uint32_t>, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
-                         f, m, (const uint64_t*)tile_off, ps);
+                         f, m, (const uint64_t*)tile_off, ps, TreeOut{});
   };
   if (ps_in) prefix(f_in, ps_in);
   if (ps_out) prefix(f_out, ps_out);
@@ -1243,12 +1256,12 @@ tc_status proposal_window(const tc_graph* g, const tc_weights* w, const uint32_t
                        (int)w->cls.mode1, (int)w->cls.mode3, m, q, tile_sums, flag, gst);
   // a set flag (window sums or q_p out of range, or the weights' own status)
   // makes Q = 0 and is reported in wq->status
+  const TreeOut T = tree_out(wq);
   hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, (const uint64_t*)tile_sums, ntiles,
-                     tile_off, wq->S, m, wq->status, (const uint32_t*)flag);
+                     tile_off, wq->S, m, wq->status, (const uint32_t*)flag, T);
   if (ntiles > 0)
     hipLaunchKernelGGL(k_prefix_apply<uint64_t>, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,
-                       (const uint64_t*)q, m, (const uint64_t*)tile_off, wq->S);
-  build_tree(wq, st);
+                       (const uint64_t*)q, m, (const uint64_t*)tile_off, wq->S, T);
   if (hipGetLastError() != hipSuccess) return TC_E_HIP;
   return TC_OK;
 }
