@@ -53,7 +53,7 @@ STAGE_KERNELS = {
               "k_radix_hist", "k_col_sum", "k_col_scan", "k_col_apply", "k_radix_scatter",
               "k_rec_xform", "k_emit", "k_hash_insert"],
     "weights": ["k_mp_split_coarse", "k_mp_split", "k_mp_rank", "k_combine", "k_scan_tiles",
-                "k_scan_apply"],
+                "k_scan_tiles_sets", "k_scan_apply"],
     "sample": ["k_zero_result", "k_store_ptrs", "k_zero_counters", "k_paths", "k_listcount_reg",
                "k_listcount_lds", "k_listcount_wide", "k_listcount_w128", "k_listcount_big", "k_finalize"],
 }

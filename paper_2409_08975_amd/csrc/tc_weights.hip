@@ -587,12 +587,12 @@ __device__ void tree_tail(const TreeOut& T, uint64_t* S, int64_t m, uint64_t W) 
 // offsets are stored modulo 2^64 (only meaningful when W < 2^64).
 // A non-zero `upstream` word (the graph's build status, or the status of the
 // weights a proposal is built on) makes the total 0 and is passed on.
-__global__ __launch_bounds__(1024) void k_scan_tiles(const uint64_t* __restrict__ tile_sums,
-                                                     int64_t ntiles, uint64_t* __restrict__ tile_off,
-                                                     uint64_t* __restrict__ S, int64_t m,
-                                                     uint32_t* __restrict__ status,
-                                                     const uint32_t* __restrict__ upstream,
-                                                     TreeOut T) {
+__device__ __forceinline__ void scan_tiles(const uint64_t* __restrict__ tile_sums,
+                                           int64_t ntiles, uint64_t* __restrict__ tile_off,
+                                           uint64_t* __restrict__ S, int64_t m,
+                                           uint32_t* __restrict__ status,
+                                           const uint32_t* __restrict__ upstream,
+                                           const TreeOut& T) {
   if (*upstream) {
     for (int64_t i = threadIdx.x; i < ntiles; i += 1024) tile_off[i] = 0;
     if (threadIdx.x == 0) {
@@ -637,6 +637,29 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const uint64_t* __restrict_
     *status = (W.hi != 0) ? TC_F_OVERFLOW : 0u;
     if (T.tree) tree_tail(T, S, m, W.lo);
   }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_tiles(const uint64_t* __restrict__ tile_sums,
+                                                     int64_t ntiles, uint64_t* __restrict__ tile_off,
+                                                     uint64_t* __restrict__ S, int64_t m,
+                                                     uint32_t* __restrict__ status,
+                                                     const uint32_t* __restrict__ upstream,
+                                                     TreeOut T) {
+  scan_tiles(tile_sums, ntiles, tile_off, S, m, status, upstream, T);
+}
+
+// the tile scans of every weights set of a call, one block each
+struct ScanSets {
+  const uint64_t* tile_sums[kMaxDeltas];
+  uint64_t* tile_off[kMaxDeltas];
+  uint64_t* S[kMaxDeltas];
+  uint32_t* status[kMaxDeltas];
+  TreeOut T[kMaxDeltas];
+};
+__global__ __launch_bounds__(1024) void k_scan_tiles_sets(ScanSets J, int64_t ntiles, int64_t m,
+                                                          const uint32_t* __restrict__ upstream) {
+  const int i = blockIdx.x;
+  scan_tiles(J.tile_sums[i], ntiles, J.tile_off[i], J.S[i], m, J.status[i], upstream, J.T[i]);
 }
 
 // 128-bit tile sums of q = a * b * h (the proposal weights)
@@ -947,10 +970,17 @@ tc_status path_weights_batch(const tc_graph* g, const int64_t* deltas, int nd,
                        (const int32_t*)g->out_src, (const int32_t*)g->out_dst,
                        (const int64_t*)g->out_t, m, C, gst);
   }
+  ScanSets J{};
   for (int i = 0; i < nd; ++i) {
-    const TreeOut T = tree_out(&w[i]);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, (const uint64_t*)tile_sums[i],
-                       ntiles, tile_off[i], w[i].S, m, w[i].status, gst, T);
+    J.tile_sums[i] = tile_sums[i];
+    J.tile_off[i] = tile_off[i];
+    J.S[i] = w[i].S;
+    J.status[i] = w[i].status;
+    J.T[i] = tree_out(&w[i]);
+  }
+  hipLaunchKernelGGL(k_scan_tiles_sets, dim3((unsigned)nd), dim3(1024), 0, st, J, ntiles, m, gst);
+  for (int i = 0; i < nd; ++i) {
+    const TreeOut& T = J.T[i];
     if (ntiles > 0) {
       TimedLaunch tl("k_scan_apply", st);
       hipLaunchKernelGGL(k_scan_apply<false>, dim3((unsigned)ntiles), dim3(kWBlock), 0, st,

@@ -31,7 +31,7 @@ KERNEL_SRC = {
     "k_listcount_lds": "tc_sample.hip", "k_listcount_wide": "tc_sample.hip",
     "k_listcount_big": "tc_sample.hip", "k_listcount_w128": "tc_sample.hip",
     "k_windows": "tc_weights.hip", "k_mp_rank": "tc_weights.hip", "k_combine": "tc_weights.hip",
-    "k_scan_tiles": "tc_weights.hip", "k_scan_apply": "tc_weights.hip",
+    "k_scan_tiles": "tc_weights.hip", "k_scan_tiles_sets": "tc_weights.hip", "k_scan_apply": "tc_weights.hip",
     "k_radix_scatter": "tc_build.hip",
     "k_radix_hist": "tc_build.hip", "k_hash_insert": "tc_build.hip", "k_emit": "tc_build.hip",
     "k_rec_xform": "tc_build.hip", "k_mp_split": "tc_weights.hip",
