@@ -54,7 +54,8 @@ namespace tc {
 
 constexpr int kSBlock = 256;
 constexpr int kSWaves = kSBlock / kWave;
-constexpr int kLiBits = 22;  // local sample index bits of an item code
+constexpr int kLiBits = 24;  // local sample index bits of an item code (then 4 motif, 3 delta bits)
+static_assert(kLiBits + 4 + 3 <= 32 && kMaxDeltas <= 8, "item code: sample, motif, delta");
 constexpr int kKeyCap = 1024;
 constexpr int kWideCap = 65536;
 constexpr int kMaxFastWaves = 8192;
@@ -114,7 +115,7 @@ struct SampleArgs {
   // per-chunk scratch
   uint32_t* win_lo;   // [nd][kMaxPairs][chunk]
   uint32_t* win_len;  // [nd][kMaxPairs][chunk]
-  uint32_t* item_code;  // local sample | motif << 22 | delta << 26
+  uint32_t* item_code;  // local sample | motif << 24 | delta << 28
   uint32_t* item_count;
   uint32_t* mid_code;
   uint32_t* mid_count;
@@ -1638,7 +1639,7 @@ SampleTuning default_tuning() {
 
 static uint64_t chunk_for(uint64_t k, int nd, const SampleTuning& t) {
   const int lg = t.chunk_log2 < 10 ? 10 : (t.chunk_log2 > kLiBits ? kLiBits : t.chunk_log2);
-  uint64_t c = (1ull << lg) / (uint64_t)nd;  // all deltas of a chunk within 2^22 samples
+  uint64_t c = (1ull << lg) / (uint64_t)nd;  // all deltas of a chunk within 2^kLiBits samples
   if (c > k) c = k;
   return c < 1 ? 1 : c;
 }
