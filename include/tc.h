@@ -219,7 +219,7 @@ typedef struct tc_result {
 /* Launch-shape choices of the sampler.  They change speed only, never a
  * result (every output is a pure function of the inputs).
  *   chunk_log2  log2 of the samples processed per chunk over all deltas
- *               (10..24; the queue and window scratch scale with it)
+ *               (10..25; the queue and window scratch scale with it)
  *   path_blocks persistent blocks of the path kernel (0 = one per tile)
  *   reg_waves   wavefronts of the register ListCount pass
  *   fast_waves  wavefronts of the LDS-key ListCount pass (64..8192)

@@ -114,7 +114,7 @@ class tc_tuning(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-def make_tuning(chunk_log2=24, path_blocks=0, reg_waves=40960, fast_waves=8192,
+def make_tuning(chunk_log2=25, path_blocks=0, reg_waves=40960, fast_waves=8192,
                 wide_blocks=2048, reg_list_cap=256, lds_list_cap=1024) -> tc_tuning:
     return tc_tuning(chunk_log2, path_blocks, reg_waves, fast_waves, wide_blocks, reg_list_cap,
                      lds_list_cap)

@@ -335,7 +335,7 @@ tc_status tc_autotune(const tc_graph* g, const tc_weights* const* w, int32_t n_d
   tc_status s = run(cur, &cur_ms);
   // candidate values per knob (a knob with fewer repeats its last one)
   const int32_t cand[7][3] = {
-      {22, 23, 24},         // chunk_log2
+      {23, 24, 25},         // chunk_log2
       {0, 1024, 4096},      // path_blocks
       {20480, 40960, 81920}, // reg_waves
       {2560, 5120, 8192},   // fast_waves

@@ -54,7 +54,7 @@ namespace tc {
 
 constexpr int kSBlock = 256;
 constexpr int kSWaves = kSBlock / kWave;
-constexpr int kLiBits = 24;  // local sample index bits of an item code (then 4 motif, 3 delta bits)
+constexpr int kLiBits = 25;  // local sample index bits of an item code (then 4 motif, 3 delta bits)
 static_assert(kLiBits + 4 + 3 <= 32 && kMaxDeltas <= 8, "item code: sample, motif, delta");
 constexpr int kKeyCap = 1024;
 constexpr int kWideCap = 65536;
@@ -115,7 +115,7 @@ struct SampleArgs {
   // per-chunk scratch
   uint32_t* win_lo;   // [nd][kMaxPairs][chunk]
   uint32_t* win_len;  // [nd][kMaxPairs][chunk]
-  uint32_t* item_code;  // local sample | motif << 24 | delta << 28
+  uint32_t* item_code;  // local sample | motif << 25 | delta << 29
   uint32_t* item_count;
   uint32_t* mid_code;
   uint32_t* mid_count;

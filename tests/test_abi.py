@@ -65,7 +65,7 @@ def test_sample_workspace_query(tcb):
     b6 = tcb.sample_workspace_bytes(1000, 6)
     big = tcb.sample_workspace_bytes(10**9, 6)
     assert b6 > b1 > 0
-    assert big == tcb.sample_workspace_bytes(2**24, 6)  # chunked: bounded in k
+    assert big == tcb.sample_workspace_bytes(2**25, 6)  # chunked: bounded in k
     with pytest.raises(tcb.TCError):
         tcb.sample_workspace_bytes(0, 1)
     with pytest.raises(tcb.TCError):

@@ -70,7 +70,7 @@ TUNINGS = [
     dict(chunk_log2=12, path_blocks=0, reg_waves=5120, fast_waves=5120, wide_blocks=1024),
     dict(chunk_log2=16, path_blocks=7, reg_waves=64, fast_waves=64, wide_blocks=64,
          reg_list_cap=128, lds_list_cap=256),
-    dict(chunk_log2=24, path_blocks=1, reg_waves=100, fast_waves=16384, wide_blocks=2048,
+    dict(chunk_log2=25, path_blocks=1, reg_waves=100, fast_waves=16384, wide_blocks=2048,
          reg_list_cap=256, lds_list_cap=512),
     dict(chunk_log2=10, path_blocks=3000, reg_waves=1, fast_waves=1, wide_blocks=1,
          reg_list_cap=1, lds_list_cap=1),
@@ -89,12 +89,13 @@ def test_batch_results_independent_of_tuning(tcb, tiny, tuning):
 
 
 def test_chunk_beyond_2e22_samples(tcb, tiny):
-    """A chunk of 2^23 samples per delta (item codes with sample indices
-    past 2^22) gives the counts, hits and estimates of 2^15-sample chunks."""
+    """One chunk holding all 5*10^6 samples of each delta (item codes with
+    sample indices past 2^22) gives the counts, hits and estimates of
+    2^15-sample chunks."""
     g, G, og, _ = tiny
     Ws = tcb.tc_path_weights_batch(G, [3600, 40000])
     k = 5_000_000
-    big = tcb.tc_batch_estimate(G, Ws, SIX, k, 21, tuning=tcb.make_tuning(chunk_log2=24))
+    big = tcb.tc_batch_estimate(G, Ws, SIX, k, 21, tuning=tcb.make_tuning(chunk_log2=25))
     small = tcb.tc_batch_estimate(G, Ws, SIX, k, 21, tuning=tcb.make_tuning(chunk_log2=16))
     for a, b in zip(big, small):
         assert int(a.status.item()) == int(b.status.item()) == 0
@@ -278,7 +279,7 @@ def test_autotune_returns_usable_tuning(tcb, tiny):
     g, G, og, Ws = tiny
     best, ms = tcb.tc_autotune(G, Ws, SIX, 100000, seed=1)
     t = best.as_dict()
-    assert 10 <= t["chunk_log2"] <= 24 and ms > 0
+    assert 10 <= t["chunk_log2"] <= 25 and ms > 0
     assert t["reg_waves"] >= 1 and t["fast_waves"] >= 1 and t["path_blocks"] >= 0
     ref = tcb.tc_batch_estimate(G, Ws, SIX, 30000, 3, per_sample=True)
     got = tcb.tc_batch_estimate(G, Ws, SIX, 30000, 3, per_sample=True, tuning=best)
