@@ -358,8 +358,10 @@ __device__ __forceinline__ void key_window(const SampleArgs& A, const PathRec& P
   *hi = sg + 1 < A.plan.n_anchor ? P.T[sg + 1] - 1 : P.T[0] + delta;
 }
 
-// Seven wavefronts per SIMD (at most 72 VGPRs): the kernel waits on L2 and
-// HBM round trips, and this occupancy measured fastest (6: -4%, 8: -5%).
+// Five wavefronts per SIMD (at most 102 VGPRs, no spills in the spine form):
+// the kernel waits on L2 and HBM round trips; with chunks of 2^25 samples
+// this measured 1.5% faster than seven (72 VGPRs and spills), with 2^22
+// chunks seven had been fastest.
 // GENERAL = false is the form for the <-,+,<,>> class with the anchor ranks
 // in path order (e1, centre, e3) and random draws, with those choices fixed
 // at compile time (fewer live registers); GENERAL = true reads them from the
@@ -409,7 +411,7 @@ __device__ __forceinline__ uint32_t pick_side(const SampleArgs& A, uint64_t i, c
 }
 
 template <bool GENERAL>
-__global__ __launch_bounds__(kSBlock, 7) void k_paths(SampleArgs A) {
+__global__ __launch_bounds__(kSBlock, 5) void k_paths(SampleArgs A) {
   __shared__ PathRec s_path[kSBlock];
   __shared__ uint32_t s_nvalid;
   __shared__ uint32_t s_mask[kSBlock];     // pairs still needed by each accepted path
