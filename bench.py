@@ -659,8 +659,10 @@ def run_batched(args):
         print(json.dumps({"profile_run": "batched", "build_ms": t_build, "weights_ms": t_w,
                           "sample_ms": t_s, "profile_steps": 1}), flush=True)
         return
-    best, probe_ms = tcb.tc_autotune(G, Ws, motifs, 2**22, seed=7)
-    log(f"[bench] autotuned {best.as_dict()} ({probe_ms:.2f} ms per 2^22-sample probe)")
+    # probes of 2^23 samples per delta, so that the chunk sizes (up to 2^25
+    # samples over the deltas) differ in the probes as in the run
+    best, probe_ms = tcb.tc_autotune(G, Ws, motifs, 2**23, seed=7)
+    log(f"[bench] autotuned {best.as_dict()} ({probe_ms:.2f} ms per 2^23-sample probe)")
     ws = torch.empty(tcb.batch_workspace_bytes(k, nd, nm), dtype=torch.uint8, device=dev)
     ref = tcb.tc_batch_estimate(G, Ws, motifs, k, seed, workspace=ws)
     torch.cuda.synchronize()

@@ -302,7 +302,7 @@ tc_status tc_path_weights_batch(const tc_graph *g, const int64_t *deltas, int32_
 
 /* Workspace size in bytes for tc_sample_estimate with k samples and n_motifs
  * motifs (per-sample pair windows and the closure work queue of one chunk of
- * at most 2^22 samples).  Errors: TC_E_ARG (null, k < 1, n_motifs not in
+ * at most 2^25 samples).  Errors: TC_E_ARG (null, k < 1, n_motifs not in
  * 1..16). */
 tc_status tc_sample_workspace_bytes(uint64_t k, int32_t n_motifs, size_t *bytes);
 
