@@ -86,6 +86,9 @@ def _p(a: np.ndarray):
 # after 0 = window [t - delta, t], 1 = [t, t + delta].  Side 1 is the centre
 # edge's source u, side 3 its destination v.
 SIDE_NONE, SIDE_IN, SIDE_OUT = 0, 1, 2
+# bit 1 of an `after` byte: the side's window leaves out the centre time
+# ([t - delta, t) or (t, t + delta]); every match's anchor still lies in it
+WINDOW_OPEN = 2
 SPINE_CLASS = bytes([SIDE_IN, 0, SIDE_OUT, 1])  # <-,+,<,>
 
 

@@ -70,17 +70,19 @@ def enumerate_class_paths(src, dst, t, delta, cls):
     mode3, after3}: e2 = (u, v, t2) any edge; e1 an edge at u (mode 1: an
     in-edge x -> u, mode 2: an out-edge u -> x; mode 0: none, e1 = -1) with
     t1 in [t2 - delta, t2] (after1 = 0) or [t2, t2 + delta] (after1 = 1); e3
-    likewise at v.  Windows are closed; e1 and e3 may be any edges (even e2)."""
+    likewise at v.  Windows are closed, unless bit 1 of the after byte is set
+    (after1 = 2 or 3): then t1 != t2.  e1 and e3 may be any edges (even e2)."""
     m = len(src)
 
     def side(at, t2, mode, after):
         if mode == 0:
             return [-1]
-        lo, hi = (t2, t2 + delta) if after else (t2 - delta, t2)
+        lo, hi = (t2, t2 + delta) if after & 1 else (t2 - delta, t2)
         out = []
         for e in range(m):
             ends = int(dst[e]) if mode == 1 else int(src[e])
-            if ends == at and lo <= int(t[e]) <= hi:
+            te = int(t[e])
+            if ends == at and lo <= te <= hi and not (after & 2 and te == t2):
                 out.append(e)
         return out
 

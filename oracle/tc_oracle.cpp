@@ -79,20 +79,27 @@ enum { OR_OK = 0, OR_RANGE = 1, OR_OVERFLOW = 2, OR_RNG = 4, OR_ARG = 8 };
 // at its destination v (side 3, edge e3), whether the side has an edge, whether
 // that edge is an in-edge (-) or an out-edge (+) of u (resp. v), and whether
 // it comes before the centre edge (window [t - delta, t]) or after it
-// ([t, t + delta]).  Stored as 4 bytes {mode1, after1, mode3, after3}.
+// ([t, t + delta]).  Stored as 4 bytes {mode1, after1, mode3, after3}; bit 1
+// of an `after` byte (2) opens the window at the centre time: [t - delta, t)
+// or (t, t + delta].  A match's times increase strictly, so the open windows
+// still hold every match's anchor (a variant of the closed windows of Claim
+// "count", with a smaller W).
 enum { SIDE_NONE = 0, SIDE_IN = 1, SIDE_OUT = 2 };
 struct Class {
   int mode[2];   // side 1, side 3
   int after[2];
+  int open[2];   // the window excludes the centre time
 };
-const Class kSpineClass = {{SIDE_IN, SIDE_OUT}, {0, 1}};
+const Class kSpineClass = {{SIDE_IN, SIDE_OUT}, {0, 1}, {0, 0}};
 
 bool parse_class(const uint8_t* c, Class* K) {
   if (!c) { *K = kSpineClass; return true; }
   for (int s = 0; s < 2; ++s) {
     K->mode[s] = c[2 * s];
-    K->after[s] = c[2 * s + 1];
-    if (K->mode[s] > SIDE_OUT || K->after[s] > 1) return false;
+    const int a = c[2 * s + 1];
+    K->after[s] = a & 1;
+    K->open[s] = (a >> 1) & 1;
+    if (K->mode[s] > SIDE_OUT || a > 3) return false;
   }
   return K->mode[0] != SIDE_NONE || K->mode[1] != SIDE_NONE;
 }
@@ -491,8 +498,12 @@ int window_weights(const Graph& G, int64_t delta, const Class& K, uint32_t* lo1,
       const int64_t from = K.after[s] ? t : t - delta;
       const int64_t to = K.after[s] ? t + delta : t;
       auto beg = tt.begin() + off[w], end = tt.begin() + off[w + 1];
-      const int64_t i0 = std::lower_bound(beg, end, from) - tt.begin();
-      const int64_t i1 = std::upper_bound(beg, end, to) - tt.begin();
+      // an open window leaves out the times equal to the centre time
+      const bool open_from = K.open[s] && K.after[s], open_to = K.open[s] && !K.after[s];
+      const int64_t i0 = (open_from ? std::upper_bound(beg, end, from)
+                                    : std::lower_bound(beg, end, from)) - tt.begin();
+      const int64_t i1 = (open_to ? std::lower_bound(beg, end, to)
+                                  : std::upper_bound(beg, end, to)) - tt.begin();
       lo[s] = (uint32_t)i0;
       cnt[s] = (uint32_t)(i1 - i0);
     }

@@ -96,6 +96,73 @@ def _class_motif(cls):
     return mb
 
 
+def _open(cls, side1, side3):
+    c = bytearray(cls)
+    if side1 and c[0]:
+        c[1] |= oracle.WINDOW_OPEN
+    if side3 and c[2]:
+        c[3] |= oracle.WINDOW_OPEN
+    return bytes(c)
+
+
+@pytest.mark.parametrize("cls", CLASSES_3PATH + CLASSES_WEDGE)
+@pytest.mark.parametrize("opens", [(1, 0), (0, 1), (1, 1)])
+def test_open_window_weight_total_equals_path_enumeration(cls, opens):
+    """Windows open at the centre time ([t - delta, t) or (t, t + delta]):
+    sum of w_e = number of class paths whose side times differ from the
+    centre's, on micro graphs full of equal times; never above the closed
+    total."""
+    oc = _open(cls, *opens)
+    for seed in range(3):
+        g = sg.gen_micro(300 + seed, n=5, m=22, t_span=6)
+        og = oracle.OracleGraph.from_graph(g)
+        for delta in (0, 2, 5):
+            w = og.weights(delta, cls=oc)
+            assert w.status == 0
+            assert w.W == len(brute.enumerate_class_paths(g.src, g.dst, g.t, delta, oc))
+            assert w.W <= og.weights(delta, cls=cls).W
+
+
+@pytest.mark.parametrize("cls", CLASSES_3PATH + CLASSES_WEDGE_ANCHORED)
+def test_open_window_enumeration_visits_every_path_once(cls):
+    oc = _open(cls, 1, 1)
+    g = sg.gen_micro(17, n=5, m=18, t_span=6)
+    og = oracle.OracleGraph.from_graph(g)
+    w = og.weights(4, cls=oc)
+    E = og.enumerate(w, [_class_motif(cls)], per_sample=True)
+    got = sorted(zip(E.e1.tolist(), E.e2.tolist(), E.e3.tolist()))
+    assert got == sorted(brute.enumerate_class_paths(g.src, g.dst, g.t, 4, oc))
+
+
+@pytest.mark.parametrize("nv", [3, 4])
+@pytest.mark.parametrize("seed", range(6))
+def test_open_windows_keep_every_match(nv, seed):
+    """A match's times increase strictly, so its anchor's side times differ
+    from the centre's: the windows open at the centre time still give the
+    exact count C over all anchors, with W no larger."""
+    rng = np.random.default_rng(5000 + 100 * nv + seed)
+    M = random_motif(rng, nv)
+    mb = _mb(M, nv)
+    cls = oracle.anchor(mb)[0]
+    oc = _open(cls, 1, 1)
+    g = sg.gen_micro_planted(50 + seed, M, copies=3, n=6, noise=8, t_span=12)
+    og = oracle.OracleGraph.from_graph(g)
+    for delta in (3, 8, 30):
+        C = brute.count_matches(g.src, g.dst, g.t, M, delta)
+        w = og.weights(delta, cls=oc)
+        E = og.enumerate(w, [mb])
+        assert E.status == 0 and E.cnt[0] == C, (M, delta, E.cnt, C)
+        assert w.W <= og.weights(delta, cls=cls).W
+
+
+def test_open_window_bytes_checked():
+    """Only bits 0 and 1 of an `after` byte have a meaning."""
+    g = sg.gen_micro(3, n=5, m=10, t_span=6)
+    og = oracle.OracleGraph.from_graph(g)
+    assert og.weights(3, cls=bytes([1, 4, 2, 1])).status == oracle.OR_ARG
+    assert og.weights(3, cls=bytes([1, 2, 2, 3])).status == 0
+
+
 @pytest.mark.parametrize("nv", [3, 4])
 @pytest.mark.parametrize("seed", range(12))
 def test_sum_checkmotif_over_anchors_equals_match_count(nv, seed):
