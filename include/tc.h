@@ -92,10 +92,18 @@ typedef struct {
  * alpha = -) or TC_SIDE_OUT (an out-edge, alpha = +); after = 0 for an edge
  * before the centre (window [t - delta, t], beta = <), 1 for one after it
  * ([t, t + delta], beta = >).  At least one side has an edge.  The class
- * <-,+,<,>> of the paper's presentation is {IN, 0, OUT, 1}. */
+ * <-,+,<,>> of the paper's presentation is {IN, 0, OUT, 1}.
+ * TC_WINDOW_OPEN added to an `after` value opens that side's window at the
+ * centre time: [t - delta, t) or (t, t + delta].  A match's times increase
+ * strictly, so every match's anchor still lies in the open windows and the
+ * estimate stays unbiased, with a weight total W no larger than the closed
+ * windows' (a variant of Claim "count"; not in the paper).  Motif anchors
+ * (tc_motif_anchor) report closed windows; a weights set of either kind
+ * serves the motifs of its class. */
 #define TC_SIDE_NONE 0
 #define TC_SIDE_IN 1
 #define TC_SIDE_OUT 2
+#define TC_WINDOW_OPEN 2
 typedef struct {
   uint8_t mode1, after1, mode3, after3;
 } tc_class;

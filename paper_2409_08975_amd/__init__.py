@@ -67,12 +67,14 @@ class tc_motif(ctypes.Structure):
 
 
 TC_SIDE_NONE, TC_SIDE_IN, TC_SIDE_OUT = 0, 1, 2
+TC_WINDOW_OPEN = 2  # added to an `after` value: the window leaves out the centre time
 
 
 class tc_class(ctypes.Structure):
     """Anchor class: side 1 (at the centre's source u) and side 3 (at its
     destination v), each with a mode (none / in-edge / out-edge) and whether
-    its edge comes after the centre."""
+    its edge comes after the centre (plus TC_WINDOW_OPEN for a window open at
+    the centre time)."""
     _fields_ = [("mode1", ctypes.c_uint8), ("after1", ctypes.c_uint8),
                 ("mode3", ctypes.c_uint8), ("after3", ctypes.c_uint8)]
 

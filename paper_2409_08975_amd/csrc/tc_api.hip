@@ -10,8 +10,10 @@ const tc_class kSpineClass = {TC_SIDE_IN, 0, TC_SIDE_OUT, 1};
 
 bool same_class(const tc_class& a, const tc_class& b) {
   if (a.mode1 != b.mode1 || a.mode3 != b.mode3) return false;
-  if (a.mode1 != TC_SIDE_NONE && a.after1 != b.after1) return false;
-  if (a.mode3 != TC_SIDE_NONE && a.after3 != b.after3) return false;
+  // the window's direction only: a window open at the centre time serves
+  // the same anchors
+  if (a.mode1 != TC_SIDE_NONE && (a.after1 & 1) != (b.after1 & 1)) return false;
+  if (a.mode3 != TC_SIDE_NONE && (a.after3 & 1) != (b.after3 & 1)) return false;
   return true;
 }
 
@@ -171,8 +173,8 @@ tc_status tc_build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t
 }
 
 static bool class_ok(const tc_class* cls) {
-  return cls->mode1 <= TC_SIDE_OUT && cls->mode3 <= TC_SIDE_OUT && cls->after1 <= 1 &&
-         cls->after3 <= 1 && !(cls->mode1 == TC_SIDE_NONE && cls->mode3 == TC_SIDE_NONE);
+  return cls->mode1 <= TC_SIDE_OUT && cls->mode3 <= TC_SIDE_OUT && cls->after1 <= 3 &&
+         cls->after3 <= 3 && !(cls->mode1 == TC_SIDE_NONE && cls->mode3 == TC_SIDE_NONE);
 }
 
 tc_status tc_weights_workspace_bytes(int64_t m, size_t* bytes) {

@@ -129,9 +129,13 @@ __global__ __launch_bounds__(256) void k_mp_split(SplitJobs J, int64_t nq, int64
 // galloping over the data (probe F -/+ 1, 2, 4, ... until the probe crosses
 // the delta's key, then bisect the last gap), reading the tile's LDS copy
 // where the probe lies inside the tile and the data columns elsewhere.  A
-// window before the centre time (UPPER: F counts "<=") has R = #{data <
-// (w, t - delta)} <= F; one after it (F counts "<") has R = #{data <=
-// (w, t + delta)} >= F.  The pass stores:
+// window before the centre time (BEFORE) has R = #{data < (w, t - delta)} <=
+// F; one after it has R = #{data <= (w, t + delta)} >= F.  F counts the
+// entries up to the centre time: "<=" for a closed window before it, "<" for
+// one after it, and the reverse for a window open at the centre time (FU:
+// F counts "<=").  Either way every entry from F on is not before a
+// backward delta key and every entry below F is before a forward one, which
+// the gallops need.  The pass stores:
 //   RO_SIDE1  side 1's windows, for every delta: lo = F, len = R - F after
 //             the centre time, lo = R, len = F - R before it;
 //   RO_REC    side 3's record of query i's edge, at rec[eid[i] * stride]:
@@ -275,7 +279,7 @@ __device__ __forceinline__ int64_t bracket(const TileKeys& K, int64_t lo, int64_
 // window of the tile's first (or last) query reaches past the tile.
 constexpr int kExt = 1024;
 
-template <bool UPPER, int MODE, int ND = 0>
+template <bool BEFORE, bool FU, int MODE, int ND = 0>
 __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, KeyCols D, int64_t nd,
                                                       const uint32_t* __restrict__ split,
                                                       RankMode M, uint32_t* __restrict__ rec,
@@ -292,7 +296,7 @@ __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, Key
   const int64_t i0 = d0 - q0, i1 = d1 - q1;
   const int nd_t = (int)(i1 - i0);
   // LDS index k holds data entry base + k; the tile starts at toff
-  const int toff = UPPER ? kExt : 0;
+  const int toff = BEFORE ? kExt : 0;
   const int64_t base = i0 - toff;
   for (int k = threadIdx.x; k < nd_t; k += kMPBlock) {
     s_v[toff + k] = D.v[i0 + k];
@@ -302,15 +306,15 @@ __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, Key
     // does the widest window of the outermost query leave the tile?
     bool need = false;
     if (q0 < q1) {
-      const int64_t qi = UPPER ? q0 : q1 - 1;
+      const int64_t qi = BEFORE ? q0 : q1 - 1;
       const int32_t v = Q.v[qi];
-      const int64_t t = Q.t[qi] + Q.shift + (UPPER ? -M.dmax : M.dmax);
-      if (UPPER && i0 > 0)
+      const int64_t t = Q.t[qi] + Q.shift + (BEFORE ? -M.dmax : M.dmax);
+      if (BEFORE && i0 > 0)
         need = !before<false>(D.v[i0 - 1], D.t[i0 - 1] + D.shift, v, t);
-      else if (!UPPER && i1 < nd)
+      else if (!BEFORE && i1 < nd)
         need = before<true>(D.v[i1], D.t[i1] + D.shift, v, t);
     }
-    const int64_t room = UPPER ? i0 : nd - i1;
+    const int64_t room = BEFORE ? i0 : nd - i1;
     s_ext = need ? (int)(room < kExt ? room : kExt) : 0;
   }
   // this thread's queries: `per` consecutive ones (at most kRankPer),
@@ -330,7 +334,7 @@ __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, Key
   __syncthreads();
   const int ext = s_ext;
   if (ext > 0) {
-    const int64_t x0 = UPPER ? i0 - ext : i1;
+    const int64_t x0 = BEFORE ? i0 - ext : i1;
     const int k0 = (int)(x0 - base);
     for (int k = threadIdx.x; k < ext; k += kMPBlock) {
       s_v[k0 + k] = D.v[x0 + k];
@@ -339,7 +343,7 @@ __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, Key
     __syncthreads();
   }
   if (mine == 0) return;
-  const TileKeys K{s_v, s_t, base, UPPER ? i0 - ext : i0, UPPER ? i1 : i1 + ext, D};
+  const TileKeys K{s_v, s_t, base, BEFORE ? i0 - ext : i0, BEFORE ? i1 : i1 + ext, D};
   const int32_t* tv = s_v + toff;
   const int64_t* tt = s_t + toff;
   // delta-free bounds: a bisection of the tile for the first query, then
@@ -358,7 +362,7 @@ __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, Key
       for (int s = 1;; s <<= 1) {
         const int j = lo + s;
         if (j >= nd_t) break;
-        if (!before<UPPER>(tv[j], tt[j], qv[r], qt[r])) {
+        if (!before<FU>(tv[j], tt[j], qv[r], qt[r])) {
           hi = j;
           break;
         }
@@ -367,7 +371,7 @@ __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, Key
     }
     while (hi - lo > 1) {
       const int mid = lo + ((hi - lo) >> 1);
-      if (before<UPPER>(tv[mid], tt[mid], qv[r], qt[r]))
+      if (before<FU>(tv[mid], tt[mid], qv[r], qt[r]))
         lo = mid;
       else
         hi = mid;
@@ -389,16 +393,16 @@ __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, Key
         if (r >= mine) break;
         int64_t R;
         if (r == 0) {
-          R = gallop<UPPER>(K, nd, M.chain ? from0 : F[0], qv[0], qt[0] + dk);
+          R = gallop<BEFORE>(K, nd, M.chain ? from0 : F[0], qv[0], qt[0] + dk);
           from0 = R;
-        } else if (UPPER) {
+        } else if (BEFORE) {
           R = bracket<false>(K, prev - 1, F[r], qv[r], qt[r] + dk);
         } else {
           R = gallop<false>(K, nd, F[r] > prev ? F[r] : prev, qv[r], qt[r] + dk);
         }
         prev = R;
-        M.lo[k][qb + r] = (uint32_t)(UPPER ? R : F[r]);
-        M.len[k][qb + r] = (uint32_t)(UPPER ? F[r] - R : R - F[r]);
+        M.lo[k][qb + r] = (uint32_t)(BEFORE ? R : F[r]);
+        M.len[k][qb + r] = (uint32_t)(BEFORE ? F[r] - R : R - F[r]);
       }
     }
   } else {
@@ -416,9 +420,9 @@ __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, Key
         const int64_t key = qt[r] + M.dsh[k];
         int64_t R;
         if (r == 0)
-          R = gallop<UPPER>(K, nd, M.chain && k > 0 ? prevR[k > 0 ? k - 1 : 0] : F[0], qv[0],
+          R = gallop<BEFORE>(K, nd, M.chain && k > 0 ? prevR[k > 0 ? k - 1 : 0] : F[0], qv[0],
                             key);
-        else if (UPPER)
+        else if (BEFORE)
           R = bracket<false>(K, prevR[k] - 1, F[r], qv[r], key);
         else
           R = gallop<false>(K, nd, F[r] > prevR[k] ? F[r] : prevR[k], qv[r], key);
@@ -438,17 +442,17 @@ __global__ __launch_bounds__(kMPBlock) void k_mp_rank(KeyCols Q, int64_t nq, Key
 }
 
 // the record pass for nd deltas (1..8)
-template <bool UPPER>
-static decltype(&k_mp_rank<UPPER, RO_REC, 1>) rec_kernel(int nd) {
+template <bool BEFORE, bool FU>
+static decltype(&k_mp_rank<BEFORE, FU, RO_REC, 1>) rec_kernel(int nd) {
   switch (nd) {
-    case 1: return k_mp_rank<UPPER, RO_REC, 1>;
-    case 2: return k_mp_rank<UPPER, RO_REC, 2>;
-    case 3: return k_mp_rank<UPPER, RO_REC, 3>;
-    case 4: return k_mp_rank<UPPER, RO_REC, 4>;
-    case 5: return k_mp_rank<UPPER, RO_REC, 5>;
-    case 6: return k_mp_rank<UPPER, RO_REC, 6>;
-    case 7: return k_mp_rank<UPPER, RO_REC, 7>;
-    default: return k_mp_rank<UPPER, RO_REC, 8>;
+    case 1: return k_mp_rank<BEFORE, FU, RO_REC, 1>;
+    case 2: return k_mp_rank<BEFORE, FU, RO_REC, 2>;
+    case 3: return k_mp_rank<BEFORE, FU, RO_REC, 3>;
+    case 4: return k_mp_rank<BEFORE, FU, RO_REC, 4>;
+    case 5: return k_mp_rank<BEFORE, FU, RO_REC, 5>;
+    case 6: return k_mp_rank<BEFORE, FU, RO_REC, 6>;
+    case 7: return k_mp_rank<BEFORE, FU, RO_REC, 7>;
+    default: return k_mp_rank<BEFORE, FU, RO_REC, 8>;
   }
 }
 
@@ -909,8 +913,13 @@ tc_status path_weights_batch(const tc_graph* g, const int64_t* deltas, int nd,
     };
     int j1f = -1, j3f = -1;
     auto dshift = [&](int after, int64_t d) { return after ? d : -d; };
-    if (s1) j1f = job(outk, d1, !cls.after1);
-    if (s3) j3f = job(ink, d3, !cls.after3);
+    // per side: the window's direction (bit 0 of `after`) and whether it is
+    // open at the centre time (bit 1), which decide how F counts ties
+    const bool before1 = (cls.after1 & 1) == 0, before3 = (cls.after3 & 1) == 0;
+    const bool fu1 = before1 != ((cls.after1 & 2) != 0);
+    const bool fu3 = before3 != ((cls.after3 & 2) != 0);
+    if (s1) j1f = job(outk, d1, fu1);
+    if (s3) j3f = job(ink, d3, fu3);
     if (nj > 0) {
       const int64_t ncoarse = (nsplit - 1 + kSplitStride - 1) / kSplitStride + 1;
       hipLaunchKernelGGL(k_mp_split_coarse, dim3((unsigned)((ncoarse + 255) / 256), nj), dim3(256),
@@ -933,11 +942,14 @@ tc_status path_weights_batch(const tc_graph* g, const int64_t* deltas, int nd,
       const SplitJob& S = J.j[j1f];
       RankMode M = rank_mode();
       for (int i = 0; i < nd; ++i) {
-        M.dsh[i] = dshift(cls.after1, deltas[i]);
+        M.dsh[i] = dshift(!before1, deltas[i]);
         M.lo[i] = w[i].lo_in;
         M.len[i] = w[i].a;
       }
-      const auto kern = S.upper ? k_mp_rank<true, RO_SIDE1> : k_mp_rank<false, RO_SIDE1>;
+      const auto kern = before1 ? (fu1 ? k_mp_rank<true, true, RO_SIDE1>
+                                       : k_mp_rank<true, false, RO_SIDE1>)
+                                : (fu1 ? k_mp_rank<false, true, RO_SIDE1>
+                                       : k_mp_rank<false, false, RO_SIDE1>);
       hipLaunchKernelGGL(kern, dim3(rb), dim3(kMPBlock), 0, st, S.Q, m, S.D, m,
                          (const uint32_t*)S.split, M, (uint32_t*)nullptr, (const int32_t*)nullptr,
                          gst);
@@ -946,8 +958,10 @@ tc_status path_weights_batch(const tc_graph* g, const int64_t* deltas, int nd,
       // side 3 in in-CSR order: one record per edge id
       const SplitJob& S = J.j[j3f];
       RankMode M = rank_mode();
-      for (int i = 0; i < nd; ++i) M.dsh[i] = dshift(cls.after3, deltas[i]);
-      const auto kern = S.upper ? rec_kernel<true>(nd) : rec_kernel<false>(nd);
+      for (int i = 0; i < nd; ++i) M.dsh[i] = dshift(!before3, deltas[i]);
+      const auto kern = before3 ? (fu3 ? rec_kernel<true, true>(nd) : rec_kernel<true, false>(nd))
+                                : (fu3 ? rec_kernel<false, true>(nd)
+                                       : rec_kernel<false, false>(nd));
       hipLaunchKernelGGL(kern, dim3(rb), dim3(kMPBlock), 0, st, S.Q, m, S.D, m,
                          (const uint32_t*)S.split, M, rec, (const int32_t*)g->in_eid, gst);
     }
@@ -955,7 +969,7 @@ tc_status path_weights_batch(const tc_graph* g, const int64_t* deltas, int nd,
     C.nd = nd;
     C.side1 = s1 ? 1 : 0;
     C.side3 = s3 ? 1 : 0;
-    C.after3 = cls.after3;
+    C.after3 = before3 ? 0 : 1;
     C.stride = rec_stride(nd);
     for (int i = 0; i < nd; ++i) {
       C.lo_in[i] = w[i].lo_in;

@@ -119,10 +119,15 @@ def test_anchor_and_class_host_checks(tcb):
     g = tcb.tc_graph()
     w = tcb.tc_weights()
     g.m = w.m = 10
-    for bad in ((0, 0, 0, 0), (3, 0, 2, 1), (1, 2, 2, 1)):
+    for bad in ((0, 0, 0, 0), (3, 0, 2, 1), (1, 4, 2, 1), (1, 0, 2, 5)):
         c = tcb.tc_class(*bad)
         assert L.tc_path_weights_class(ctypes.byref(g), 5, ctypes.byref(c), ctypes.c_void_p(1), 0,
                                        None, ctypes.byref(w)) == tcb.TC_E_ARG
+    # windows open at the centre time are a valid class (the workspace is not)
+    for ok in ((1, 2, 2, 1), (1, 0, 2, 3), (2, 3, 0, 0)):
+        c = tcb.tc_class(*ok)
+        assert L.tc_path_weights_class(ctypes.byref(g), 5, ctypes.byref(c), ctypes.c_void_p(1), 0,
+                                       None, ctypes.byref(w)) == tcb.TC_E_WORKSPACE
     fake = ctypes.c_void_p(256).value
     r = tcb.tc_result(fake, fake, fake, fake, None, None, None, None)
     arr = (tcb.tc_motif * 1)(tcb.make_motif([(0, 1), (1, 2), (2, 3), (3, 0)]))

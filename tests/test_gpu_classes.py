@@ -213,3 +213,73 @@ def test_exhaustive_tiny_six_motifs_and_b_statistics(tcb, tiny):
         for j, M in enumerate(six):
             assert E.cnt[j] == og.brute_count(sg.motif_bytes(M), delta)
             assert R.m2[j].item() == pytest.approx(E.m2[j], rel=1e-12)
+
+
+# ---- windows open at the centre time (TC_WINDOW_OPEN) ----------------------
+def _open(cls, side1=True, side3=True):
+    c = list(cls)
+    if side1 and c[0]:
+        c[1] |= 2
+    if side3 and c[2]:
+        c[3] |= 2
+    return tuple(c)
+
+
+@pytest.fixture(scope="module")
+def ties(tcb, torch_mod):
+    """A micro graph full of equal times (300 edges over 21 time values)."""
+    g = sg.gen_micro(400, n=6, m=300, t_span=20)
+    G, og = build_both(tcb, torch_mod, g)
+    return g, G, og
+
+
+@pytest.mark.parametrize("cls", PATH_CLASSES + WEDGE_CLASSES)
+def test_open_window_weights(tcb, tiny, ties, cls):
+    """Every class with one or both windows open at the centre time: windows
+    and S equal the oracle's on the tiny graph and on a graph of ties, and W
+    is never above the closed windows' W."""
+    for opens in ((1, 0), (0, 1), (1, 1)):
+        oc = _open(cls, *opens)
+        for g, G, og in (tiny, ties):
+            for delta in (0, 5, 3600, 40000):
+                Wt = tcb.tc_path_weights(G, delta, cls=oc)
+                _weights_equal(Wt, og.weights(delta, cls=bytes(oc)))
+                assert Wt.total() <= tcb.tc_path_weights(G, delta, cls=cls).total()
+
+
+def test_open_window_batch_hubs_and_sampling(tcb, torch_mod):
+    """Open windows through the batched rank passes on hub windows of
+    thousands of entries (galloping past the tile, bracketing by the previous
+    query), then per-sample sampling parity on them."""
+    from test_gpu_weights_batch import _hub_graph
+    g = _hub_graph()
+    G, og = build_both(tcb, torch_mod, g)
+    oc = (1, 2, 2, 3)
+    deltas = [10, 1000, 20000, 90000]
+    Ws = tcb.tc_path_weights_batch(G, deltas, cls=oc)
+    for W, d in zip(Ws, deltas):
+        _weights_equal(W, og.weights(d, cls=bytes(oc)))
+    M40 = (sg.MOTIFS["M4-0"], 4)
+    _sample_equal(tcb, G, Ws[2], og, og.weights(20000, cls=bytes(oc)), [M40], 20000, 3)
+
+
+@pytest.mark.parametrize("nv", [3, 4])
+@pytest.mark.parametrize("seed", range(3))
+def test_open_windows_exhaustive_equals_count(tcb, torch_mod, nv, seed):
+    """A match's times increase strictly, so the open windows keep every
+    anchor: the exhaustive count over them is the literal match count."""
+    rng = np.random.default_rng(7000 + 100 * nv + seed)
+    while True:
+        ne = int(rng.integers(nv - 1, 7))
+        M = [tuple(int(x) for x in rng.choice(nv, size=2, replace=False)) for _ in range(ne)]
+        if oracle.anchor(sg.motif_bytes(M, nv)) is not None:
+            break
+    oc = _open(tcb.tc_motif_anchor(M, nv)[0])
+    g = sg.gen_micro_planted(60 + seed, M, copies=3, n=6, noise=8, t_span=12)
+    G, og = build_both(tcb, torch_mod, g)
+    for delta in (3, 8, 30):
+        Wt = tcb.tc_path_weights(G, delta, cls=oc)
+        _weights_equal(Wt, og.weights(delta, cls=bytes(oc)))
+        R = tcb.tc_exhaustive_count(G, Wt, [(M, nv)])
+        R.check()
+        assert R.counts()[0] == brute.count_matches(g.src, g.dst, g.t, M, delta)
