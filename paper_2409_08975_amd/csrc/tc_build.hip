@@ -7,13 +7,13 @@
 //
 // Radix sort design (gfx950, wave64): every sort moves 16-byte edge
 // records, tiles of 1536 records per 256-thread block.  A pass is (1)
-// per-tile digit histograms written tile-major (each tile's 256 counts are
-// one contiguous kilobyte), (2) a column scan of that [tiles][256] matrix
-// that turns every count into the tile's global offset for its digit, (3) a
-// scatter that ranks keys stably inside the tile with wavefront ballots
-// (8 ballots give the lanes sharing a digit), stages the tile in LDS in
-// digit order and writes each digit run to its global slot with coalesced
-// stores.
+// per-tile digit histograms written tile-major (each tile's 256 or 512
+// counts are one contiguous row), (2) a column scan of that [tiles][bins]
+// matrix that turns every count into the tile's global offset for its digit,
+// (3) a scatter that ranks keys stably inside the tile with wavefront
+// ballots (one ballot per digit bit gives the lanes sharing a digit), stages
+// the tile in LDS in digit order and writes each digit run to its global
+// slot with coalesced stores.
 //
 // The whole build is one stream-ordered launch sequence: it allocates
 // nothing, never waits on the device, and can be captured in a HIP graph.
@@ -31,6 +31,7 @@ constexpr uint32_t kXcds = 8;  // accelerator complex dies of an MI355X, each wi
 constexpr int kRecItems = 6;  // record-carrying sorts: 1536-entry tiles (LDS holds 16 B/entry)
 constexpr int kRecTile = kSortBlock * kRecItems;
 constexpr int kColChunk = 32;  // tiles per chunk of the histogram column scan
+constexpr int kMaxBins = 512;  // digits of at most 9 bits
 
 static unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -289,14 +290,16 @@ __global__ __launch_bounds__(256) void k_rec_xform(uint4* __restrict__ a, int64_
   }
 }
 
-template <int ITEMS>
+template <int ITEMS, int BINS>
 __global__ __launch_bounds__(kSortBlock) void k_radix_hist(RecPass R, int64_t m,
                                                            uint32_t* __restrict__ hist) {
-  __shared__ uint32_t s_h[256];
+  constexpr int kDig = BINS / kSortBlock;  // digits per thread
+  __shared__ uint32_t s_h[BINS];
   const PassCfg c = resolve(R);
   if (!c.active) return;
   const uint32_t mask = (1u << c.dbits) - 1u;
-  s_h[threadIdx.x] = 0;
+#pragma unroll
+  for (int q = 0; q < kDig; ++q) s_h[q * kSortBlock + threadIdx.x] = 0;
   __syncthreads();
   int64_t start = (int64_t)blockIdx.x * (kSortBlock * ITEMS);
 #pragma unroll
@@ -309,7 +312,10 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(RecPass R, int64_t m,
     }
   }
   __syncthreads();
-  hist[(int64_t)blockIdx.x * 256 + threadIdx.x] = s_h[threadIdx.x];
+#pragma unroll
+  for (int q = 0; q < kDig; ++q)
+    hist[(int64_t)blockIdx.x * BINS + q * kSortBlock + threadIdx.x] =
+        s_h[q * kSortBlock + threadIdx.x];
 }
 
 // Column scan of the tile-major histogram: hist[t][d] becomes the position
@@ -318,8 +324,9 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(RecPass R, int64_t m,
 // per-chunk column sums, an exclusive scan of each digit's chunk sums (which
 // also leaves the digit totals in row `nchunks`), and an in-place walk of
 // every chunk that adds the digit base.  Every access reads or writes whole
-// 1 KB rows except the per-digit chunk scan, which touches nchunks*256 words.
-// `gate` (time sort passes) skips a pass the plan leaves idle.
+// rows (BINS words) except the per-digit chunk scan, which touches
+// nchunks*BINS words.  `gate` (time sort passes) skips a pass the plan
+// leaves idle.
 struct PassGate {
   const BuildPlan* plan;
   int pass;
@@ -328,24 +335,29 @@ __device__ __forceinline__ bool idle(const PassGate& G) {
   return G.plan && (G.plan->bad || !G.plan->active[G.pass]);
 }
 
+template <int BINS>
 __global__ __launch_bounds__(256) void k_col_sum(const uint32_t* __restrict__ hist,
                                                  int64_t ntiles, uint32_t* __restrict__ csum,
                                                  PassGate gate) {
   if (idle(gate)) return;
   const int64_t t0 = (int64_t)blockIdx.x * kColChunk;
-  const int d = threadIdx.x;
-  uint32_t s = 0;
 #pragma unroll
-  for (int j = 0; j < kColChunk; ++j) {
-    // clamped index: every load is issued unconditionally
-    const int64_t t = t0 + j < ntiles ? t0 + j : ntiles - 1;
-    const uint32_t v = hist[t * 256 + d];
-    s += (t0 + j < ntiles) ? v : 0u;
+  for (int q = 0; q < BINS / 256; ++q) {
+    const int d = q * 256 + threadIdx.x;
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kColChunk; ++j) {
+      // clamped index: every load is issued unconditionally
+      const int64_t t = t0 + j < ntiles ? t0 + j : ntiles - 1;
+      const uint32_t v = hist[t * BINS + d];
+      s += (t0 + j < ntiles) ? v : 0u;
+    }
+    csum[(int64_t)blockIdx.x * BINS + d] = s;
   }
-  csum[(int64_t)blockIdx.x * 256 + d] = s;
 }
 
 // one block per digit (blockIdx.x), chunks spread over the block's threads
+template <int BINS>
 __global__ __launch_bounds__(256) void k_col_scan(uint32_t* __restrict__ csum, int64_t nchunks,
                                                   PassGate gate) {
   if (idle(gate)) return;
@@ -354,7 +366,7 @@ __global__ __launch_bounds__(256) void k_col_scan(uint32_t* __restrict__ csum, i
   uint32_t carry = 0;
   for (int64_t base = 0; base < nchunks; base += 256) {
     const int64_t c = base + threadIdx.x;
-    const uint32_t v = c < nchunks ? csum[c * 256 + d] : 0u;
+    const uint32_t v = c < nchunks ? csum[c * BINS + d] : 0u;
     const uint32_t inc = wave_inclusive_scan(v);
     if (lane == 63) s_w[wave] = inc;
     __syncthreads();
@@ -364,65 +376,83 @@ __global__ __launch_bounds__(256) void k_col_scan(uint32_t* __restrict__ csum, i
       off += w < wave ? s_w[w] : 0u;
       tot += s_w[w];
     }
-    if (c < nchunks) csum[c * 256 + d] = carry + off + inc - v;
+    if (c < nchunks) csum[c * BINS + d] = carry + off + inc - v;
     carry += tot;
     __syncthreads();
   }
-  if (threadIdx.x == 0) csum[nchunks * 256 + d] = carry;
+  if (threadIdx.x == 0) csum[nchunks * BINS + d] = carry;
 }
 
-// one block per chunk; thread d walks the chunk's tiles for digit d
+// one block per chunk; thread tid walks the chunk's tiles for digits
+// tid, tid + 256, ...
+template <int BINS>
 __global__ __launch_bounds__(256) void k_col_apply(uint32_t* __restrict__ hist, int64_t ntiles,
                                                    const uint32_t* __restrict__ csum,
                                                    int64_t nchunks, PassGate gate) {
   if (idle(gate)) return;
-  __shared__ uint32_t s_w[256 / kWave];
-  const int d = threadIdx.x, lane = d & 63, wave = d >> 6;
-  // digit base: exclusive scan of the digit totals over d
-  const uint32_t tot = csum[nchunks * 256 + d];
-  const uint32_t inc = wave_inclusive_scan(tot);
-  if (lane == 63) s_w[wave] = inc;
-  __syncthreads();
-  uint32_t run = inc - tot;
-  for (int w = 0; w < wave; ++w) run += s_w[w];
-  run += csum[(int64_t)blockIdx.x * 256 + d];
+  constexpr int kDig = BINS / 256;
+  __shared__ uint32_t s_w[kDig][256 / kWave];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t t0 = (int64_t)blockIdx.x * kColChunk;
-  uint32_t v[kColChunk];
+  uint32_t carry = 0;  // totals of the digits below this group of 256
 #pragma unroll
-  for (int j = 0; j < kColChunk; ++j) {
-    const int64_t t = t0 + j < ntiles ? t0 + j : ntiles - 1;
-    v[j] = hist[t * 256 + d];
-  }
+  for (int q = 0; q < kDig; ++q) {
+    const int d = q * 256 + tid;
+    // digit base: exclusive scan of the digit totals over d
+    const uint32_t tot = csum[nchunks * BINS + d];
+    const uint32_t inc = wave_inclusive_scan(tot);
+    if (lane == 63) s_w[q][wave] = inc;
+    __syncthreads();
+    uint32_t run = carry + inc - tot, group = 0;
 #pragma unroll
-  for (int j = 0; j < kColChunk; ++j) {
-    if (t0 + j < ntiles) hist[(t0 + j) * 256 + d] = run;
-    run += v[j];
+    for (int w = 0; w < 256 / kWave; ++w) {
+      run += w < wave ? s_w[q][w] : 0u;
+      group += s_w[q][w];
+    }
+    carry += group;
+    run += csum[(int64_t)blockIdx.x * BINS + d];
+    uint32_t v[kColChunk];
+#pragma unroll
+    for (int j = 0; j < kColChunk; ++j) {
+      const int64_t t = t0 + j < ntiles ? t0 + j : ntiles - 1;
+      v[j] = hist[t * BINS + d];
+    }
+#pragma unroll
+    for (int j = 0; j < kColChunk; ++j) {
+      if (t0 + j < ntiles) hist[(t0 + j) * BINS + d] = run;
+      run += v[j];
+    }
   }
 }
 
-size_t col_scan_scratch_elems(int64_t ntiles) {
-  return (size_t)256 * ((ntiles + kColChunk - 1) / kColChunk + 1);
+size_t col_scan_scratch_elems(int64_t ntiles, int bins) {
+  return (size_t)bins * ((ntiles + kColChunk - 1) / kColChunk + 1);
 }
 
+template <int BINS>
 void col_scan(uint32_t* hist, int64_t ntiles, uint32_t* csum, PassGate gate, hipStream_t st) {
   const int64_t nchunks = (ntiles + kColChunk - 1) / kColChunk;
-  hipLaunchKernelGGL(k_col_sum, dim3((unsigned)nchunks), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_col_sum<BINS>, dim3((unsigned)nchunks), dim3(256), 0, st,
                      (const uint32_t*)hist, ntiles, csum, gate);
-  hipLaunchKernelGGL(k_col_scan, dim3(256), dim3(256), 0, st, csum, nchunks, gate);
-  hipLaunchKernelGGL(k_col_apply, dim3((unsigned)nchunks), dim3(256), 0, st, hist, ntiles,
+  hipLaunchKernelGGL(k_col_scan<BINS>, dim3(BINS), dim3(256), 0, st, csum, nchunks, gate);
+  hipLaunchKernelGGL(k_col_apply<BINS>, dim3((unsigned)nchunks), dim3(256), 0, st, hist, ntiles,
                      (const uint32_t*)csum, nchunks, gate);
 }
 
-template <int ITEMS>
+template <int ITEMS, int BINS>
 __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(RecPass R, int64_t m,
                                                               const uint32_t* __restrict__ hist) {
   // Each wavefront owns a contiguous quarter of the tile and ranks its keys
   // in order with ballots (no block barrier inside); one block-wide pass then
   // offsets every wavefront's digit counts by those of the wavefronts before
   // it, which keeps the pass stable.
+  static_assert(BINS == 256 || BINS == 512, "8- or 9-bit digits");
   constexpr int kTile = kSortBlock * ITEMS;
   constexpr int kWaves = kSortBlock / kWave;
   constexpr int kSub = kWave * ITEMS;  // entries per wavefront
+  constexpr int kDig = BINS / kSortBlock;
+  constexpr int kBits = BINS == 512 ? 9 : 8;
+  static_assert(2 * kTile < 65536, "16-bit tile positions");
   const PassCfg c = resolve(R);
   if (!c.active) return;
   const int shift = c.shift, dbits = c.dbits;
@@ -436,10 +466,12 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(RecPass R, int64_t
   const uint32_t q = nb / kXcds, rem = nb % kXcds;
   const uint32_t tile = xcd * q + (xcd < rem ? xcd : rem) + slot;
   if ((int64_t)tile * kTile >= m) return;
-  __shared__ uint32_t s_base[256];
-  __shared__ uint32_t s_excl[256];
-  __shared__ uint32_t s_wcnt[kWaves][256];  // per-wavefront running digit counts
-  __shared__ uint32_t s_wsum[kWaves];
+  // s_base[d]: global position of digit d's run minus its start in the tile
+  // s_pos[w][d]: wavefront w's running count of digit d, then the position
+  //              in the tile of w's first key of digit d (16 bits suffice)
+  __shared__ uint32_t s_base[BINS];
+  __shared__ uint16_t s_pos[kWaves][BINS];
+  __shared__ uint32_t s_wsum[kDig][kWaves];
   __shared__ uint4 s_key[kTile];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -447,9 +479,13 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(RecPass R, int64_t
   const int len = (int)((m - start) < kTile ? (m - start) : kTile);
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-  s_base[tid] = hist[(int64_t)tile * 256 + tid];
+  uint32_t gbase[kDig];  // loaded now, used after the ranking
 #pragma unroll
-  for (int w = 0; w < kWaves; ++w) s_wcnt[w][tid] = 0;
+  for (int j = 0; j < kDig; ++j) gbase[j] = hist[(int64_t)tile * BINS + j * kSortBlock + tid];
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w)
+#pragma unroll
+    for (int j = 0; j < kDig; ++j) s_pos[w][j * kSortBlock + tid] = 0;
   __syncthreads();
 
   uint4 key[ITEMS];
@@ -463,36 +499,53 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(RecPass R, int64_t
     uint64_t vb = __ballot(valid);
     uint64_t peers = valid ? vb : ~vb;
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      if (b >= dbits) break;  // uniform: the digit has dbits bits
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bb = __ballot(bit);
-      peers &= bit ? bb : ~bb;
+    for (int b = 0; b < kBits; ++b) {
+      if (b < dbits) {  // uniform: the digit has dbits bits
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        peers &= bit ? bb : ~bb;
+      }
     }
     const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
     // read the running count before the leader of each digit group adds to it
-    const uint32_t run = valid ? s_wcnt[wave][d] : 0u;
+    const uint32_t run = valid ? (uint32_t)s_pos[wave][d] : 0u;
     rank[r] = run + below;
     __builtin_amdgcn_wave_barrier();
-    if (valid && below == 0) s_wcnt[wave][d] = run + (uint32_t)__popcll(peers);
+    if (valid && below == 0) s_pos[wave][d] = (uint16_t)(run + (uint32_t)__popcll(peers));
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  // thread tid owns digit tid: offsets of each wavefront's run of that digit
+  // thread tid owns digits tid, tid + 256, ...: the tile-local start of each
+  // wavefront's run of that digit, digits in increasing order
   {
-    uint32_t tot = 0;
+    uint32_t carry = 0;  // keys of the digit groups below
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-      const uint32_t cw = s_wcnt[w][tid];
-      s_wcnt[w][tid] = tot;  // exclusive prefix over wavefronts
-      tot += cw;
+    for (int j = 0; j < kDig; ++j) {
+      const int d = j * kSortBlock + tid;
+      uint32_t cw[kWaves], tot = 0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) {
+        cw[w] = s_pos[w][d];
+        tot += cw[w];
+      }
+      const uint32_t inc = wave_inclusive_scan(tot);
+      if (lane == 63) s_wsum[j][wave] = inc;
+      __syncthreads();
+      uint32_t off = carry + inc - tot, group = 0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) {
+        off += w < wave ? s_wsum[j][w] : 0u;
+        group += s_wsum[j][w];
+      }
+      carry += group;
+      s_base[d] = gbase[j] - off;  // modulo 2^32; the sum below is exact
+      uint32_t p = off;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) {
+        s_pos[w][d] = (uint16_t)p;
+        p += cw[w];
+      }
     }
-    const uint32_t inc = wave_inclusive_scan(tot);
-    if (lane == 63) s_wsum[wave] = inc;
-    __syncthreads();
-    uint32_t off = inc - tot;
-    for (int w = 0; w < wave; ++w) off += s_wsum[w];
-    s_excl[tid] = off;
   }
   __syncthreads();
 #pragma unroll
@@ -500,25 +553,40 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(RecPass R, int64_t
     const int idx = wave * kSub + r * kWave + lane;
     if (idx < len) {
       const uint32_t d = (key[r].x >> shift) & mask;
-      s_key[s_excl[d] + s_wcnt[wave][d] + rank[r]] = key[r];
+      s_key[(uint32_t)s_pos[wave][d] + rank[r]] = key[r];
     }
   }
   __syncthreads();
   for (int i = tid; i < len; i += kSortBlock) {
     const uint4 k = s_key[i];
     const uint32_t d = (k.x >> shift) & mask;
-    const int64_t gpos = (int64_t)s_base[d] + (i - (int64_t)s_excl[d]);
+    const int64_t gpos = (int64_t)(s_base[d] + (uint32_t)i);
     // the last pass of a sort can re-key the records for the next sort
     c.out[gpos] = rec_xform(k, c.xf1);
     if (c.out2) c.out2[gpos] = rec_xform(k, c.xf2);
   }
 }
 
+// One host-planned pass with BINS-entry digit histograms.
+template <int ITEMS, int BINS>
+void radix_pass(const RecPass& R, int64_t m, int64_t ntiles, uint32_t* hist, uint32_t* part,
+                hipStream_t st) {
+  hipLaunchKernelGGL((k_radix_hist<ITEMS, BINS>), dim3((unsigned)ntiles), dim3(kSortBlock), 0,
+                     st, R, m, hist);
+  col_scan<BINS>(hist, ntiles, part, PassGate{nullptr, 0}, st);
+  TimedLaunch tl("k_radix_scatter", st);
+  hipLaunchKernelGGL((k_radix_scatter<ITEMS, BINS>), dim3((unsigned)ntiles), dim3(kSortBlock), 0,
+                     st, R, m, (const uint32_t*)hist);
+}
+
 // Host-planned stable sort of m records by the low `bits` bits of their
 // first word (a vertex id), ping-ponging between k0 and k1; returns 0 if the
 // result is in k0, 1 if in k1, -1 if the scan scratch is too small (nothing
 // enqueued then).  The result is re-keyed by xf1, and if `extra` is given a
-// second copy re-keyed by xf2 goes there.
+// second copy re-keyed by xf2 goes there.  Digits are at most 8 bits wide,
+// or at most 9 where that saves a pass (9, 17-18 and 25-27 bits: a 26-bit
+// vertex id takes 8 + 9 + 9 instead of 6 + 6 + 7 + 7); a 9-bit pass moves
+// twice the histogram rows, a few percent of the records' bytes.
 template <int ITEMS>
 int radix_sort(uint4* k0, uint4* k1, int64_t m, int bits, uint32_t* hist, uint32_t* part,
                size_t part_elems, hipStream_t st, int xf1 = RX_NONE, uint4* extra = nullptr,
@@ -526,9 +594,11 @@ int radix_sort(uint4* k0, uint4* k1, int64_t m, int bits, uint32_t* hist, uint32
   if (m <= 0) return 0;
   constexpr int kTile = kSortBlock * ITEMS;
   const int64_t ntiles = (m + kTile - 1) / kTile;
-  if (part_elems < col_scan_scratch_elems(ntiles)) return -1;
+  const int n8 = (bits + 7) / 8, n9 = (bits + 8) / 9;
+  const bool nine = n9 < n8;
+  const int npass = nine ? n9 : n8;
+  if (part_elems < col_scan_scratch_elems(ntiles, nine ? 512 : 256)) return -1;
   int cur = 0;
-  const int npass = (bits + 7) / 8;
   if (npass == 0 && (xf1 != RX_NONE || extra))
     hipLaunchKernelGGL(k_rec_xform, dim3(blocks_for(m, 256)), dim3(256), 0, st, k0, m, xf1,
                        extra, xf2);
@@ -542,14 +612,10 @@ int radix_sort(uint4* k0, uint4* k1, int64_t m, int bits, uint32_t* hist, uint32
     R.xf1 = last ? xf1 : (int)RX_NONE;
     R.out2 = last ? extra : nullptr;
     R.xf2 = last ? xf2 : (int)RX_NONE;
-    hipLaunchKernelGGL((k_radix_hist<ITEMS>), dim3((unsigned)ntiles), dim3(kSortBlock), 0, st, R,
-                       m, hist);
-    col_scan(hist, ntiles, part, PassGate{nullptr, 0}, st);
-    {
-      TimedLaunch tl("k_radix_scatter", st);
-      hipLaunchKernelGGL((k_radix_scatter<ITEMS>), dim3((unsigned)ntiles), dim3(kSortBlock), 0,
-                         st, R, m, (const uint32_t*)hist);
-    }
+    if (nine)
+      radix_pass<ITEMS, 512>(R, m, ntiles, hist, part, st);
+    else
+      radix_pass<ITEMS, 256>(R, m, ntiles, hist, part, st);
     cur ^= 1;
   }
   return cur;
@@ -564,7 +630,7 @@ bool time_sort(const BuildPlan* plan, const EdgeCols& ec, uint4* b0, uint4* b1, 
                uint4* out2, int xf2) {
   constexpr int kTile = kSortBlock * ITEMS;
   const int64_t ntiles = (m + kTile - 1) / kTile;
-  if (part_elems < col_scan_scratch_elems(ntiles)) return false;
+  if (part_elems < col_scan_scratch_elems(ntiles, 256)) return false;
   hipLaunchKernelGGL(k_rec_init, dim3(blocks_for(m, 256)), dim3(256), 0, st, ec, m, plan, b0,
                      xf1, out2, xf2);
   for (int p = 0; p < kTimePasses; ++p) {
@@ -577,11 +643,11 @@ bool time_sort(const BuildPlan* plan, const EdgeCols& ec, uint4* b0, uint4* b1, 
     R.out2 = out2;
     R.xf2 = xf2;
     R.ec = ec;
-    hipLaunchKernelGGL((k_radix_hist<ITEMS>), dim3((unsigned)ntiles), dim3(kSortBlock), 0, st, R,
-                       m, hist);
-    col_scan(hist, ntiles, part, PassGate{plan, p}, st);
-    hipLaunchKernelGGL((k_radix_scatter<ITEMS>), dim3((unsigned)ntiles), dim3(kSortBlock), 0, st,
-                       R, m, (const uint32_t*)hist);
+    hipLaunchKernelGGL((k_radix_hist<ITEMS, 256>), dim3((unsigned)ntiles), dim3(kSortBlock), 0,
+                       st, R, m, hist);
+    col_scan<256>(hist, ntiles, part, PassGate{plan, p}, st);
+    hipLaunchKernelGGL((k_radix_scatter<ITEMS, 256>), dim3((unsigned)ntiles), dim3(kSortBlock),
+                       0, st, R, m, (const uint32_t*)hist);
   }
   return true;
 }
@@ -750,9 +816,9 @@ static GraphLayout graph_layout(int32_t n, int64_t m) {
   L.plan = take(sizeof(BuildPlan));
   // sort scratch: four 16-byte-record buffers
   for (int b = 0; b < 4; ++b) L.rr[b] = take((M + 1) * 16);
-  L.hist = take((size_t)256 * ntiles * 4);
+  L.hist = take((size_t)kMaxBins * ntiles * 4);
   // scan scratch of the histogram column scan
-  L.part_elems = col_scan_scratch_elems(ntiles);
+  L.part_elems = col_scan_scratch_elems(ntiles, kMaxBins);
   L.part = take(L.part_elems * 4);
   L.total = o;
   return L;

@@ -212,9 +212,10 @@ def test_counter_high_word_crossed(tcb, tiny):
     check_sample(tcb, G, Wt, og, ow, SIX, 1500, seed=6, stream=0, i0=(1 << 40) + 77)
 
 
-def test_wide_vertex_ids_four_pass_sorts(tcb, torch_mod):
-    """Vertex ids spread over [0, 2^26): 26-bit keys take four radix passes
-    per vertex sort and the offset arrays have 2^26 + 1 entries."""
+def test_wide_vertex_ids_26_bits(tcb, torch_mod):
+    """Vertex ids spread over [0, 2^26): 26-bit keys take three radix passes
+    of 8, 9 and 9 bits per vertex sort and the offset arrays have 2^26 + 1
+    entries."""
     g = sg.relabel_spread(sg.gen_tiny(), 1 << 26, seed=41)
     G, og = build_both(tcb, torch_mod, g)
     check_graph(G, og, g)
@@ -222,6 +223,22 @@ def test_wide_vertex_ids_four_pass_sorts(tcb, torch_mod):
     ow = og.weights(20000)
     check_weights(Wt, ow, g, og)
     check_sample(tcb, G, Wt, og, ow, SIX, 40000, seed=2)
+
+
+@pytest.mark.parametrize("n_new", [512, 1 << 17, 1 << 25])
+def test_nine_bit_digit_sorts(tcb, torch_mod, n_new):
+    """Vertex-id widths at which 9-bit digits save a radix pass (9, 17 and 25
+    bits: one, two and three passes over 512-entry digit histograms), on an
+    edge list of nine tiles with a ragged tail."""
+    g = sg.gen_micro(12289, n=512, m=12289, t_span=6000)
+    if n_new > g.n:
+        g = sg.relabel_spread(g, n_new, seed=n_new % 97)
+    G, og = build_both(tcb, torch_mod, g)
+    check_graph(G, og, g)
+    Wt = tcb.tc_path_weights(G, 600)
+    ow = og.weights(600)
+    check_weights(Wt, ow, g, og)
+    check_sample(tcb, G, Wt, og, ow, SIX, 3000, seed=n_new % 89)
 
 
 # --------------------------------------------------- micro / edge cases ----
