@@ -51,7 +51,7 @@ PMC_FILES = {"bitcoin": os.path.join(ROOT, "profiles", "pmc_traffic_bitcoin.txt"
 STAGE_KERNELS = {
     "build": ["k_init_build", "k_validate", "k_plan", "k_trange", "k_hash_clear", "k_rec_init",
               "k_radix_hist", "k_col_sum", "k_col_scan", "k_col_apply", "k_radix_scatter",
-              "k_rec_xform", "k_emit", "k_hash_insert"],
+              "k_rec_xform", "k_emit", "k_offsets", "k_hash_insert"],
     "weights": ["k_mp_split_coarse", "k_mp_split", "k_mp_rank", "k_combine", "k_scan_tiles",
                 "k_scan_tiles_sets", "k_scan_apply"],
     "sample": ["k_zero_result", "k_store_ptrs", "k_zero_counters", "k_paths", "k_listcount_reg",

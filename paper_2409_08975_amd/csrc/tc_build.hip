@@ -194,6 +194,21 @@ struct EdgeCols {
 // Where a pass reads its records from.
 enum { SRC_BUF = 0, SRC_COLS = 1, SRC_HIGH = 2 };
 
+// The graph columns that the last pass of a vertex sort writes in place of
+// its sorted records: for output position i with record (key, eid, other,
+// t - t_min), key[i], other[i], t[i], eid[i], optionally the 16-byte record
+// {other, eid, t} and, every 16th position, the sampled time levels.
+struct EmitCols {
+  const BuildPlan* plan;  // time base, the wide-range flag and the validation
+  const int64_t* t_in;    // input times, read by edge id for wide ranges
+  int32_t* key;
+  int32_t* other;
+  int64_t* t;
+  int32_t* eid;
+  uint4* rec;      // or null
+  int64_t* skip;   // or null
+};
+
 // One launched radix pass.  With `plan` null the host planned it (the vertex
 // sorts: bit counts follow from n); otherwise it is pass `pass` of the time
 // sort and everything below `plan` is resolved on the device.
@@ -208,6 +223,7 @@ struct RecPass {
   uint4* out2;      // second, re-keyed copy (last pass), or null
   int xf2;
   EdgeCols ec;
+  EmitCols E;       // k_radix_scatter<..., true>: the columns out of the last pass
 };
 
 struct PassCfg {
@@ -439,7 +455,25 @@ void col_scan(uint32_t* hist, int64_t ntiles, uint32_t* csum, PassGate gate, hip
                      (const uint32_t*)csum, nchunks, gate);
 }
 
-template <int ITEMS, int BINS>
+// the columns of one sorted record at output position i (see EmitCols)
+__device__ __forceinline__ void emit_cols(const EmitCols& E, int64_t m, int64_t i,
+                                          const uint4& r) {
+  const BuildPlan& P = *E.plan;
+  const int64_t te = P.wide ? E.t_in[r.y] : P.tmin + (int64_t)r.w;
+  E.key[i] = (int32_t)r.x;
+  E.other[i] = (int32_t)r.z;
+  E.t[i] = te;
+  E.eid[i] = (int32_t)r.y;
+  if (E.rec) E.rec[i] = make_uint4(r.z, r.y, (uint32_t)te, (uint32_t)(te >> 32));
+  if (E.skip && (i & 15) == 0) {
+    const int64_t n1 = skip_level_len(m, 1), n2 = skip_level_len(m, 2);
+    E.skip[i >> 4] = te;
+    if ((i & 255) == 0) E.skip[n1 + (i >> 8)] = te;
+    if ((i & 4095) == 0) E.skip[n1 + n2 + (i >> 12)] = te;
+  }
+}
+
+template <int ITEMS, int BINS, bool EMIT = false>
 __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(RecPass R, int64_t m,
                                                               const uint32_t* __restrict__ hist) {
   // Each wavefront owns a contiguous quarter of the tile and ranks its keys
@@ -557,40 +591,52 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(RecPass R, int64_t
     }
   }
   __syncthreads();
+  const bool cols = EMIT && R.E.plan->bad == 0;
   for (int i = tid; i < len; i += kSortBlock) {
     const uint4 k = s_key[i];
     const uint32_t d = (k.x >> shift) & mask;
     const int64_t gpos = (int64_t)(s_base[d] + (uint32_t)i);
-    // the last pass of a sort can re-key the records for the next sort
-    c.out[gpos] = rec_xform(k, c.xf1);
+    // the last pass of a sort can re-key the records for the next sort, or
+    // write the graph's columns instead of the records
+    if (EMIT) {
+      if (cols) emit_cols(R.E, m, gpos, k);
+    } else {
+      c.out[gpos] = rec_xform(k, c.xf1);
+    }
     if (c.out2) c.out2[gpos] = rec_xform(k, c.xf2);
   }
 }
 
 // One host-planned pass with BINS-entry digit histograms.
 template <int ITEMS, int BINS>
-void radix_pass(const RecPass& R, int64_t m, int64_t ntiles, uint32_t* hist, uint32_t* part,
-                hipStream_t st) {
+void radix_pass(const RecPass& R, bool emit, int64_t m, int64_t ntiles, uint32_t* hist,
+                uint32_t* part, hipStream_t st) {
   hipLaunchKernelGGL((k_radix_hist<ITEMS, BINS>), dim3((unsigned)ntiles), dim3(kSortBlock), 0,
                      st, R, m, hist);
   col_scan<BINS>(hist, ntiles, part, PassGate{nullptr, 0}, st);
   TimedLaunch tl("k_radix_scatter", st);
-  hipLaunchKernelGGL((k_radix_scatter<ITEMS, BINS>), dim3((unsigned)ntiles), dim3(kSortBlock), 0,
-                     st, R, m, (const uint32_t*)hist);
+  if (emit)
+    hipLaunchKernelGGL((k_radix_scatter<ITEMS, BINS, true>), dim3((unsigned)ntiles),
+                       dim3(kSortBlock), 0, st, R, m, (const uint32_t*)hist);
+  else
+    hipLaunchKernelGGL((k_radix_scatter<ITEMS, BINS>), dim3((unsigned)ntiles), dim3(kSortBlock),
+                       0, st, R, m, (const uint32_t*)hist);
 }
 
 // Host-planned stable sort of m records by the low `bits` bits of their
 // first word (a vertex id), ping-ponging between k0 and k1; returns 0 if the
 // result is in k0, 1 if in k1, -1 if the scan scratch is too small (nothing
 // enqueued then).  The result is re-keyed by xf1, and if `extra` is given a
-// second copy re-keyed by xf2 goes there.  Digits are at most 8 bits wide,
+// second copy re-keyed by xf2 goes there.  With `emit` the last pass writes
+// the columns *emit instead of the sorted records (returns 2 then; with no
+// pass at all the caller emits from k0).  Digits are at most 8 bits wide,
 // or at most 9 where that saves a pass (9, 17-18 and 25-27 bits: a 26-bit
 // vertex id takes 8 + 9 + 9 instead of 6 + 6 + 7 + 7); a 9-bit pass moves
 // twice the histogram rows, a few percent of the records' bytes.
 template <int ITEMS>
 int radix_sort(uint4* k0, uint4* k1, int64_t m, int bits, uint32_t* hist, uint32_t* part,
                size_t part_elems, hipStream_t st, int xf1 = RX_NONE, uint4* extra = nullptr,
-               int xf2 = RX_NONE) {
+               int xf2 = RX_NONE, const EmitCols* emit = nullptr) {
   if (m <= 0) return 0;
   constexpr int kTile = kSortBlock * ITEMS;
   const int64_t ntiles = (m + kTile - 1) / kTile;
@@ -602,23 +648,32 @@ int radix_sort(uint4* k0, uint4* k1, int64_t m, int bits, uint32_t* hist, uint32
   if (npass == 0 && (xf1 != RX_NONE || extra))
     hipLaunchKernelGGL(k_rec_xform, dim3(blocks_for(m, 256)), dim3(256), 0, st, k0, m, xf1,
                        extra, xf2);
+  int shift = 0;
   for (int p = 0; p < npass; ++p) {
     const bool last = p + 1 == npass;
     RecPass R{};
     R.plan = nullptr;
     R.in = cur ? k1 : k0;
     R.out = cur ? k0 : k1;
-    digit_plan(bits, npass, p, &R.shift, &R.dbits);
+    // with 9-bit digits the narrow one goes last: the last pass writes the
+    // longest runs, and an 8-bit pass takes 256-entry rows
+    int sh, db;
+    digit_plan(bits, npass, nine ? npass - 1 - p : p, &sh, &db);
+    R.shift = shift;
+    R.dbits = db;
+    shift += db;
     R.xf1 = last ? xf1 : (int)RX_NONE;
     R.out2 = last ? extra : nullptr;
     R.xf2 = last ? xf2 : (int)RX_NONE;
-    if (nine)
-      radix_pass<ITEMS, 512>(R, m, ntiles, hist, part, st);
+    const bool em = last && emit;
+    if (em) R.E = *emit;
+    if (db > 8)
+      radix_pass<ITEMS, 512>(R, em, m, ntiles, hist, part, st);
     else
-      radix_pass<ITEMS, 256>(R, m, ntiles, hist, part, st);
+      radix_pass<ITEMS, 256>(R, em, m, ntiles, hist, part, st);
     cur ^= 1;
   }
-  return cur;
+  return npass > 0 && emit ? 2 : cur;
 }
 
 // The time sort: kTimePasses launched passes planned on the device (see
@@ -765,6 +820,20 @@ __global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ in, int6
   }
 }
 
+// CSR offsets from a sorted key column: off[v] = first position whose key is
+// at least v, for v in [0, n]
+__global__ __launch_bounds__(256) void k_offsets(const int32_t* __restrict__ key, int64_t m,
+                                                 const BuildPlan* __restrict__ plan, int32_t n,
+                                                 uint32_t* __restrict__ off) {
+  if (plan->bad) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= m) {
+    const int64_t prev = (i == 0) ? -1 : (int64_t)key[i - 1];
+    const int64_t cur = (i == m) ? (int64_t)n : (int64_t)key[i];
+    for (int64_t v = prev + 1; v <= cur; ++v) off[v] = (uint32_t)i;
+  }
+}
+
 // the validation word and the time range of the plan, for tc_graph
 __global__ void k_trange(const BuildPlan* __restrict__ plan, int64_t* __restrict__ tr) {
   if (threadIdx.x == 0) {
@@ -897,39 +966,47 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   const EdgeCols ec{src, dst, t};
   if (!time_sort<kRecItems>(plan, ec, rr[0], rr[1], m, hist, part, pe, st, RX_OUT, rr[2], RX_IN))
     return TC_E_WORKSPACE;
-  auto sort_rec = [&](int from, int tmp, int xf1 = RX_NONE, int extra = -1,
-                      int xf2 = RX_NONE) -> int {
-    const int w = radix_sort<kRecItems>(rr[from], rr[tmp], m, vbits, hist, part, pe, st, xf1,
-                                        extra < 0 ? (uint4*)nullptr : rr[extra], xf2);
-    return w < 0 ? -1 : (w ? tmp : from);
+  // A vertex sort of rr[from] (spare rr[tmp]) whose last pass writes the
+  // columns E; with no pass (n = 1) the records are emitted from rr[from].
+  auto sort_emit = [&](int from, int tmp, const EmitCols& E, uint32_t* off, int extra = -1,
+                       int xf2 = RX_NONE) -> bool {
+    const int w = radix_sort<kRecItems>(rr[from], rr[tmp], m, vbits, hist, part, pe, st,
+                                        RX_NONE, extra < 0 ? (uint4*)nullptr : rr[extra], xf2,
+                                        &E);
+    if (w < 0) return false;
+    if (w != 2)
+      hipLaunchKernelGGL(k_emit, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
+                         (const uint4*)rr[w ? tmp : from], m, (const BuildPlan*)plan, t, E.key,
+                         E.other, E.t, E.eid, E.rec, n, off, E.skip);
+    else if (off)
+      hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
+                         (const int32_t*)E.key, m, (const BuildPlan*)plan, n, off);
+    return true;
   };
-  // 2. in-CSR: stable by dst; a second copy of the result, re-keyed, is the
-  //    pair index input (rr[3])
-  const int I = sort_rec(2, 1, RX_NONE, 3, RX_PAIR);
-  if (I < 0) return TC_E_WORKSPACE;
-  const int Ifree = (I == 2) ? 1 : 2;
-  hipLaunchKernelGGL(k_emit, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st, (const uint4*)rr[I],
-                     m, (const BuildPlan*)plan, t, g->in_dst, g->in_src, g->in_t, g->in_eid,
-                     (uint4*)g->in_rec, n, g->in_off, (int64_t*)nullptr);
-  // 3. pair index: the in-order (dst, t, eid) stably by src
-  const int Pr = sort_rec(3, Ifree);
-  if (Pr < 0) return TC_E_WORKSPACE;
-  const int Pfree = (Pr == 3) ? Ifree : 3;
-  // the pair sort's spare buffer holds the pair sources
-  uint32_t* psrc = (uint32_t*)rr[Pfree];
-  hipLaunchKernelGGL(k_emit, dim3(eb), dim3(256), 0, st, (const uint4*)rr[Pr], m,
-                     (const BuildPlan*)plan, t, (int32_t*)psrc, g->pair_dst, g->pair_t,
-                     g->pair_eid, (uint4*)nullptr, n, (uint32_t*)nullptr, g->pair_skip);
+  // 2. in-CSR: stable by dst, written as the in-list columns; a second copy
+  //    of the sorted records, re-keyed, is the pair index input (rr[3])
+  if (!sort_emit(2, 1,
+                 EmitCols{plan, t, g->in_dst, g->in_src, g->in_t, g->in_eid, (uint4*)g->in_rec,
+                          nullptr},
+                 g->in_off, 3, RX_PAIR))
+    return TC_E_WORKSPACE;
+  // 3. pair index: the in-order (dst, t, eid) stably by src; the pair
+  //    sources go to the free buffer rr[2]
+  int32_t* psrc = (int32_t*)rr[2];
+  if (!sort_emit(3, 1,
+                 EmitCols{plan, t, psrc, g->pair_dst, g->pair_t, g->pair_eid, nullptr,
+                          g->pair_skip},
+                 nullptr))
+    return TC_E_WORKSPACE;
   // 4. the run table (its clear was enqueued first)
   hipLaunchKernelGGL(k_hash_insert, dim3(eb), dim3(256), 0, st, (const uint32_t*)psrc,
                      (const int32_t*)g->pair_dst, m, (PairSlot*)g->pair_hash, g->pair_hash_log2);
-  // 5. out-CSR: stable by src, from the time order in rr[0]; the in-CSR
-  //    records' buffer (emitted above) is its spare
-  const int R = sort_rec(0, I);
-  if (R < 0) return TC_E_WORKSPACE;
-  hipLaunchKernelGGL(k_emit, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st, (const uint4*)rr[R],
-                     m, (const BuildPlan*)plan, t, g->out_src, g->out_dst, g->out_t, g->out_eid,
-                     (uint4*)g->out_rec, n, g->out_off, (int64_t*)nullptr);
+  // 5. out-CSR: stable by src, from the time order in rr[0]
+  if (!sort_emit(0, 1,
+                 EmitCols{plan, t, g->out_src, g->out_dst, g->out_t, g->out_eid,
+                          (uint4*)g->out_rec, nullptr},
+                 g->out_off))
+    return TC_E_WORKSPACE;
   if (hipGetLastError() != hipSuccess) return TC_E_HIP;
   return TC_OK;
 }

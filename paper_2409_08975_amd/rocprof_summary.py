@@ -34,6 +34,7 @@ KERNEL_SRC = {
     "k_scan_tiles": "tc_weights.hip", "k_scan_tiles_sets": "tc_weights.hip", "k_scan_apply": "tc_weights.hip",
     "k_radix_scatter": "tc_build.hip",
     "k_radix_hist": "tc_build.hip", "k_hash_insert": "tc_build.hip", "k_emit": "tc_build.hip",
+    "k_offsets": "tc_build.hip",
     "k_rec_xform": "tc_build.hip", "k_mp_split": "tc_weights.hip",
     "k_mp_split_coarse": "tc_weights.hip", "k_rec_init": "tc_build.hip",
     "k_col_sum": "tc_build.hip", "k_col_scan": "tc_build.hip", "k_col_apply": "tc_build.hip",
