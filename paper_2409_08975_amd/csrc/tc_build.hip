@@ -171,12 +171,12 @@ __global__ void k_plan(const uint32_t* __restrict__ status, const uint64_t* __re
 // Re-keying of a 16-byte edge record between the sorts of the build:
 //   RX_NONE  identity
 //   RX_OUT   (t, eid, src, dst) -> (src, eid, dst, t)   out-CSR input
-//   RX_IN    (t, eid, src, dst) -> (dst, eid, src, t)   in-CSR input
-//   RX_PAIR  (dst, eid, src, t) -> (src, eid, dst, t)   pair-index input
-enum { RX_NONE = 0, RX_OUT = 1, RX_IN = 2, RX_PAIR = 3 };
+//   RX_PAIR  (a, eid, b, t) -> (b, eid, a, t): the in-CSR input from the
+//            out-CSR one as it is loaded, and the pair-index input from the
+//            in-CSR order
+enum { RX_NONE = 0, RX_OUT = 1, RX_PAIR = 3 };
 __device__ __forceinline__ uint4 rec_xform(const uint4& r, int xf) {
   if (xf == RX_OUT) return make_uint4(r.z, r.y, r.w, r.x);
-  if (xf == RX_IN) return make_uint4(r.w, r.y, r.z, r.x);
   if (xf == RX_PAIR) return make_uint4(r.z, r.y, r.x, r.w);
   return r;
 }
@@ -219,6 +219,7 @@ struct RecPass {
   uint4* out;       // host-planned output
   uint4* buf[2];    // time sort: the ping-pong buffers (the sort ends in buf[0])
   int shift, dbits;
+  int xfin;         // re-keying of the input as it is loaded (host-planned passes)
   int xf1;          // re-keying of the output (last pass of a sort)
   uint4* out2;      // second, re-keyed copy (last pass), or null
   int xf2;
@@ -228,7 +229,7 @@ struct RecPass {
 
 struct PassCfg {
   bool active;
-  int shift, dbits, src, xf1, xf2;
+  int shift, dbits, src, xfin, xf1, xf2;
   int64_t tmin;
   const uint4* in;
   uint4* out;
@@ -243,6 +244,7 @@ __device__ __forceinline__ PassCfg resolve(const RecPass& R) {
     c.shift = R.shift;
     c.dbits = R.dbits;
     c.src = SRC_BUF;
+    c.xfin = R.xfin;
     c.in = R.in;
     c.out = R.out;
     c.xf1 = R.xf1;
@@ -252,6 +254,7 @@ __device__ __forceinline__ PassCfg resolve(const RecPass& R) {
   }
   const BuildPlan& P = *R.plan;
   const int p = R.pass;
+  c.xfin = RX_NONE;
   c.active = P.active[p] != 0 && P.bad == 0;
   c.shift = P.shift[p];
   c.dbits = P.dbits[p];
@@ -275,7 +278,7 @@ __device__ __forceinline__ uint4 load_rec(const PassCfg& c, const EdgeCols& ec, 
                       (uint32_t)ec.dst[g]);
   uint4 r = c.in[g];
   if (c.src == SRC_HIGH) r.x = (uint32_t)((uint64_t)(ec.t[r.y] - c.tmin) >> 32);
-  return r;
+  return rec_xform(r, c.xfin);
 }
 
 // With no active time pass (every time equal): the records built from the
@@ -290,17 +293,17 @@ __global__ __launch_bounds__(256) void k_rec_init(EdgeCols ec, int64_t m,
     const uint4 r = make_uint4((uint32_t)(uint64_t)(ec.t[i] - plan->tmin), (uint32_t)i,
                                (uint32_t)ec.src[i], (uint32_t)ec.dst[i]);
     out[i] = rec_xform(r, xf1);
-    out2[i] = rec_xform(r, xf2);
+    if (out2) out2[i] = rec_xform(r, xf2);
   }
 }
 
-// the re-keying of a vertex sort with no pass (n = 1), in place: every
-// element is read and written by the same thread
-__global__ __launch_bounds__(256) void k_rec_xform(uint4* __restrict__ a, int64_t m,
+// the re-keying of a vertex sort with no pass (n = 1): a[i] from in[i]
+// (in == a allowed: every element is read and written by the same thread)
+__global__ __launch_bounds__(256) void k_rec_xform(const uint4* in, int xfin, uint4* a, int64_t m,
                                                    int xf1, uint4* __restrict__ out2, int xf2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) {
-    const uint4 r = a[i];
+    const uint4 r = rec_xform(in[i], xfin);
     a[i] = rec_xform(r, xf1);
     if (out2) out2[i] = rec_xform(r, xf2);
   }
@@ -629,14 +632,17 @@ void radix_pass(const RecPass& R, bool emit, int64_t m, int64_t ntiles, uint32_t
 // enqueued then).  The result is re-keyed by xf1, and if `extra` is given a
 // second copy re-keyed by xf2 goes there.  With `emit` the last pass writes
 // the columns *emit instead of the sorted records (returns 2 then; with no
-// pass at all the caller emits from k0).  Digits are at most 8 bits wide,
+// pass at all the caller emits from k0).  With `in0` the first pass reads
+// the records from there, re-keyed by xf_in as it loads them, and in0 is
+// left as it was.  Digits are at most 8 bits wide,
 // or at most 9 where that saves a pass (9, 17-18 and 25-27 bits: a 26-bit
 // vertex id takes 8 + 9 + 9 instead of 6 + 6 + 7 + 7); a 9-bit pass moves
 // twice the histogram rows, a few percent of the records' bytes.
 template <int ITEMS>
 int radix_sort(uint4* k0, uint4* k1, int64_t m, int bits, uint32_t* hist, uint32_t* part,
                size_t part_elems, hipStream_t st, int xf1 = RX_NONE, uint4* extra = nullptr,
-               int xf2 = RX_NONE, const EmitCols* emit = nullptr) {
+               int xf2 = RX_NONE, const EmitCols* emit = nullptr, const uint4* in0 = nullptr,
+               int xf_in = RX_NONE) {
   if (m <= 0) return 0;
   constexpr int kTile = kSortBlock * ITEMS;
   const int64_t ntiles = (m + kTile - 1) / kTile;
@@ -645,15 +651,17 @@ int radix_sort(uint4* k0, uint4* k1, int64_t m, int bits, uint32_t* hist, uint32
   const int npass = nine ? n9 : n8;
   if (part_elems < col_scan_scratch_elems(ntiles, nine ? 512 : 256)) return -1;
   int cur = 0;
-  if (npass == 0 && (xf1 != RX_NONE || extra))
-    hipLaunchKernelGGL(k_rec_xform, dim3(blocks_for(m, 256)), dim3(256), 0, st, k0, m, xf1,
+  if (npass == 0 && (xf1 != RX_NONE || extra || in0))
+    hipLaunchKernelGGL(k_rec_xform, dim3(blocks_for(m, 256)), dim3(256), 0, st,
+                       in0 ? in0 : (const uint4*)k0, in0 ? xf_in : (int)RX_NONE, k0, m, xf1,
                        extra, xf2);
   int shift = 0;
   for (int p = 0; p < npass; ++p) {
     const bool last = p + 1 == npass;
     RecPass R{};
     R.plan = nullptr;
-    R.in = cur ? k1 : k0;
+    R.in = p == 0 && in0 ? in0 : (cur ? k1 : k0);
+    R.xfin = p == 0 && in0 ? xf_in : (int)RX_NONE;
     R.out = cur ? k0 : k1;
     // with 9-bit digits the narrow one goes last: the last pass writes the
     // longest runs, and an 8-bit pass takes 256-entry rows
@@ -961,18 +969,20 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   const unsigned eb = blocks_for(m, 256);
   uint4* rr[4];
   for (int b = 0; b < 4; ++b) rr[b] = (uint4*)(base + L.rr[b]);
-  // 1. time order, ending in rr[0] re-keyed as the out-CSR input and in rr[2]
-  //    re-keyed as the in-CSR input
+  // 1. time order, ending in rr[0] re-keyed as the out-CSR input
   const EdgeCols ec{src, dst, t};
-  if (!time_sort<kRecItems>(plan, ec, rr[0], rr[1], m, hist, part, pe, st, RX_OUT, rr[2], RX_IN))
+  if (!time_sort<kRecItems>(plan, ec, rr[0], rr[1], m, hist, part, pe, st, RX_OUT, nullptr,
+                            RX_NONE))
     return TC_E_WORKSPACE;
   // A vertex sort of rr[from] (spare rr[tmp]) whose last pass writes the
   // columns E; with no pass (n = 1) the records are emitted from rr[from].
+  // With `in0` >= 0 the sort reads rr[in0] (re-keyed by xf_in) and leaves it
+  // as it was, ping-ponging between rr[from] and rr[tmp].
   auto sort_emit = [&](int from, int tmp, const EmitCols& E, uint32_t* off, int extra = -1,
-                       int xf2 = RX_NONE) -> bool {
+                       int xf2 = RX_NONE, int in0 = -1, int xf_in = RX_NONE) -> bool {
     const int w = radix_sort<kRecItems>(rr[from], rr[tmp], m, vbits, hist, part, pe, st,
                                         RX_NONE, extra < 0 ? (uint4*)nullptr : rr[extra], xf2,
-                                        &E);
+                                        &E, in0 < 0 ? (const uint4*)nullptr : rr[in0], xf_in);
     if (w < 0) return false;
     if (w != 2)
       hipLaunchKernelGGL(k_emit, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
@@ -983,12 +993,14 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
                          (const int32_t*)E.key, m, (const BuildPlan*)plan, n, off);
     return true;
   };
-  // 2. in-CSR: stable by dst, written as the in-list columns; a second copy
-  //    of the sorted records, re-keyed, is the pair index input (rr[3])
+  // 2. in-CSR: the time order read from rr[0] with src and dst swapped
+  //    ((src, eid, dst, t) -> (dst, eid, src, t)), stable by dst, written as
+  //    the in-list columns; a second copy of the sorted records, re-keyed,
+  //    is the pair index input (rr[3])
   if (!sort_emit(2, 1,
                  EmitCols{plan, t, g->in_dst, g->in_src, g->in_t, g->in_eid, (uint4*)g->in_rec,
                           nullptr},
-                 g->in_off, 3, RX_PAIR))
+                 g->in_off, 3, RX_PAIR, 0, RX_PAIR))
     return TC_E_WORKSPACE;
   // 3. pair index: the in-order (dst, t, eid) stably by src; the pair
   //    sources go to the free buffer rr[2]

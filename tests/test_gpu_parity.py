@@ -241,6 +241,26 @@ def test_nine_bit_digit_sorts(tcb, torch_mod, n_new):
     check_sample(tcb, G, Wt, og, ow, SIX, 3000, seed=n_new % 89)
 
 
+@pytest.mark.parametrize("tbits", [9, 10, 13, 18, 20, 28, 30, 33, 41, 50])
+def test_time_sort_digit_widths(tcb, torch_mod, tbits):
+    """Time ranges of exactly tbits bits (from negative times up): two to
+    four passes over the low word, with high-word passes past 32 bits, digit
+    widths from 1 to 8 bits; nine tiles with a ragged tail and many ties."""
+    base = sg.gen_micro(12289 + tbits, n=300, m=12289, t_span=4000)
+    t = base.t.astype(np.int64)
+    span = max(1, int(t.max() - t.min()))
+    t = (t - t.min()) * ((1 << tbits) - 1) // span - (1 << (tbits - 1))
+    g = sg.TemporalGraph(base.n, base.src, base.dst, t, name="tbits%d" % tbits)
+    assert int(t.max() - t.min()).bit_length() == tbits
+    G, og = build_both(tcb, torch_mod, g)
+    check_graph(G, og, g)
+    delta = 1 << (tbits - 5)
+    Wt = tcb.tc_path_weights(G, delta)
+    ow = og.weights(delta)
+    check_weights(Wt, ow, g, og)
+    check_sample(tcb, G, Wt, og, ow, SIX, 2000, seed=tbits)
+
+
 # --------------------------------------------------- micro / edge cases ----
 @pytest.mark.parametrize("seed", range(6))
 def test_planted_micro(tcb, torch_mod, seed):
