@@ -829,16 +829,34 @@ __global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ in, int6
 }
 
 // CSR offsets from a sorted key column: off[v] = first position whose key is
-// at least v, for v in [0, n]
+// at least v, for v in [0, n].  Each thread takes kOffItems consecutive
+// positions (two 16-byte loads where the column allows), so the launch has
+// an eighth of the blocks a thread per position would need.
+constexpr int kOffItems = 8;
 __global__ __launch_bounds__(256) void k_offsets(const int32_t* __restrict__ key, int64_t m,
                                                  const BuildPlan* __restrict__ plan, int32_t n,
                                                  uint32_t* __restrict__ off) {
   if (plan->bad) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i <= m) {
-    const int64_t prev = (i == 0) ? -1 : (int64_t)key[i - 1];
-    const int64_t cur = (i == m) ? (int64_t)n : (int64_t)key[i];
-    for (int64_t v = prev + 1; v <= cur; ++v) off[v] = (uint32_t)i;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kOffItems;
+  if (i0 > m) return;
+  int32_t k[kOffItems];
+  if (i0 + kOffItems <= m && ((uintptr_t)key & 15) == 0) {
+    const int4 a = *(const int4*)(key + i0), b = *(const int4*)(key + i0 + 4);
+    k[0] = a.x, k[1] = a.y, k[2] = a.z, k[3] = a.w, k[4] = b.x, k[5] = b.y, k[6] = b.z,
+    k[7] = b.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < kOffItems; ++j) k[j] = i0 + j < m ? key[i0 + j] : n;
+  }
+  int64_t prev = i0 == 0 ? -1 : (int64_t)key[i0 - 1];
+#pragma unroll
+  for (int j = 0; j < kOffItems; ++j) {
+    const int64_t i = i0 + j;
+    if (i <= m) {
+      const int64_t cur = i == m ? (int64_t)n : (int64_t)k[j];
+      for (int64_t v = prev + 1; v <= cur; ++v) off[v] = (uint32_t)i;
+      prev = cur;
+    }
   }
 }
 
@@ -989,8 +1007,9 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
                          (const uint4*)rr[w ? tmp : from], m, (const BuildPlan*)plan, t, E.key,
                          E.other, E.t, E.eid, E.rec, n, off, E.skip);
     else if (off)
-      hipLaunchKernelGGL(k_offsets, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
-                         (const int32_t*)E.key, m, (const BuildPlan*)plan, n, off);
+      hipLaunchKernelGGL(k_offsets, dim3(blocks_for((m + kOffItems) / kOffItems, 256)),
+                         dim3(256), 0, st, (const int32_t*)E.key, m, (const BuildPlan*)plan, n,
+                         off);
     return true;
   };
   // 2. in-CSR: the time order read from rr[0] with src and dst swapped
