@@ -21,7 +21,10 @@
  *     enqueued (tc_autotune alone waits, for its timings).
  *   - The library allocates no device memory and creates no streams.  The
  *     caller provides workspaces of at
- *     least the size reported by the *_workspace_bytes queries; tc_graph and
+ *     least the size reported by the *_workspace_bytes queries, 256-byte
+ *     aligned (as hipMalloc and torch allocations are: the 64-bit atomics
+ *     and 16-byte records inside them need it); a null or misaligned
+ *     workspace gives TC_E_ARG, a short one TC_E_WORKSPACE.  tc_graph and
  *     tc_weights then hold pointers into those workspaces (borrowed: keep the
  *     workspace alive while the struct is used).  There is no free call.
  *   - Host-checkable argument errors are returned synchronously and nothing

@@ -159,6 +159,10 @@ extern "C" {
 
 const char* tc_version(void) { return "tc 0.2 gfx950"; }
 
+// a workspace: present and 256-byte aligned (the 64-bit atomics and 16-byte
+// records inside it are laid out at 256-byte offsets from its start)
+static bool ws_ok(const void* ws) { return ws && ((uintptr_t)ws & 255u) == 0; }
+
 tc_status tc_graph_workspace_bytes(int32_t n, int64_t m, size_t* bytes) {
   if (!bytes || n < 1 || m < 0 || m >= ((int64_t)1 << 31)) return TC_E_ARG;
   *bytes = tc::graph_workspace_bytes(n, m);
@@ -167,7 +171,7 @@ tc_status tc_graph_workspace_bytes(int32_t n, int64_t m, size_t* bytes) {
 
 tc_status tc_build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
                          const int64_t* t, void* ws, size_t ws_bytes, void* stream, tc_graph* g) {
-  if (!g || !ws || n < 1 || m < 0 || m >= ((int64_t)1 << 31)) return TC_E_ARG;
+  if (!g || !ws_ok(ws) || n < 1 || m < 0 || m >= ((int64_t)1 << 31)) return TC_E_ARG;
   if (m > 0 && (!src || !dst || !t)) return TC_E_ARG;
   return tc::build_graph(n, m, src, dst, t, ws, ws_bytes, (hipStream_t)stream, g);
 }
@@ -185,14 +189,14 @@ tc_status tc_weights_workspace_bytes(int64_t m, size_t* bytes) {
 
 tc_status tc_path_weights(const tc_graph* g, int64_t delta, void* ws, size_t ws_bytes,
                           void* stream, tc_weights* w) {
-  if (!g || !w || !ws) return TC_E_ARG;
+  if (!g || !w || !ws_ok(ws)) return TC_E_ARG;
   if (delta < 0 || delta > ((int64_t)1 << 62)) return TC_E_ARG;
   return tc::path_weights(g, delta, tc::kSpineClass, ws, ws_bytes, (hipStream_t)stream, w);
 }
 
 tc_status tc_path_weights_class(const tc_graph* g, int64_t delta, const tc_class* cls, void* ws,
                                 size_t ws_bytes, void* stream, tc_weights* w) {
-  if (!g || !w || !ws || !cls) return TC_E_ARG;
+  if (!g || !w || !ws_ok(ws) || !cls) return TC_E_ARG;
   if (delta < 0 || delta > ((int64_t)1 << 62)) return TC_E_ARG;
   if (!class_ok(cls)) return TC_E_ARG;
   return tc::path_weights(g, delta, *cls, ws, ws_bytes, (hipStream_t)stream, w);
@@ -208,7 +212,7 @@ tc_status tc_weights_batch_workspace_bytes(int64_t m, int32_t n_deltas, size_t* 
 tc_status tc_path_weights_batch(const tc_graph* g, const int64_t* deltas, int32_t n_deltas,
                                 const tc_class* cls, void* ws, size_t ws_bytes, void* stream,
                                 tc_weights* w) {
-  if (!g || !deltas || !w || !ws) return TC_E_ARG;
+  if (!g || !deltas || !w || !ws_ok(ws)) return TC_E_ARG;
   if (n_deltas < 1 || n_deltas > tc::kMaxDeltas) return TC_E_ARG;
   for (int i = 0; i < n_deltas; ++i)
     if (deltas[i] < 0 || deltas[i] > ((int64_t)1 << 62)) return TC_E_ARG;
@@ -266,7 +270,7 @@ tc_status tc_batch_estimate(const tc_graph* g, const tc_weights* const* w, int32
   if (s != TC_OK) return s;
   for (int d = 0; d < n_deltas; ++d)
     if (!tc::same_class(plan.cls, w[d]->cls)) return TC_E_ARG;
-  if (!ws) return TC_E_ARG;
+  if (!ws_ok(ws)) return TC_E_ARG;
   const tc::SampleTuning t = tuning ? *tuning : tc::default_tuning();
   return tc::sample_batch(g, w, n_deltas, plan, k, seed, stream_id, i0, out, t, ws, ws_bytes,
                           (hipStream_t)stream);
@@ -282,7 +286,7 @@ tc_status tc_sample_estimate(const tc_graph* g, const tc_weights* w, const tc_mo
   tc_status s = tc::compile_motifs(motifs, n_motifs, &plan);
   if (s != TC_OK) return s;
   if (!tc::same_class(plan.cls, w->cls)) return TC_E_ARG;
-  if (!ws) return TC_E_ARG;
+  if (!ws_ok(ws)) return TC_E_ARG;
   const tc_weights* wl[1] = {w};
   tc_result* ol[1] = {out};
   return tc::sample_batch(g, wl, 1, plan, k, seed, stream_id, i0, ol, tc::default_tuning(), ws,
@@ -298,7 +302,7 @@ tc_status tc_exhaustive_count(const tc_graph* g, const tc_weights* w, const tc_m
   tc_status s = tc::compile_motifs(motifs, n_motifs, &plan);
   if (s != TC_OK) return s;
   if (!tc::same_class(plan.cls, w->cls)) return TC_E_ARG;
-  if (!ws) return TC_E_ARG;
+  if (!ws_ok(ws)) return TC_E_ARG;
   const tc_weights* wl[1] = {w};
   tc_result* ol[1] = {out};
   return tc::sample_batch(g, wl, 1, plan, count, 0, 0, r0, ol, tc::default_tuning(), ws, ws_bytes,
@@ -383,7 +387,7 @@ tc_status tc_features_workspace_bytes(int64_t m, size_t* bytes) {
 
 tc_status tc_edge_features(const tc_graph* g, const tc_weights* w, uint16_t* feat, void* ws,
                            size_t ws_bytes, void* stream) {
-  if (!g || !w || !feat || !ws || w->m != g->m || !aligned16(feat)) return TC_E_ARG;
+  if (!g || !w || !feat || !ws_ok(ws) || w->m != g->m || !aligned16(feat)) return TC_E_ARG;
   if (!tc::same_class(w->cls, tc::kSpineClass)) return TC_E_UNSUPPORTED;
   return tc::edge_features(g, w, feat, ws, ws_bytes, (hipStream_t)stream);
 }
@@ -403,7 +407,7 @@ tc_status tc_mlp_workspace_bytes(int64_t n, size_t* bytes) {
 tc_status tc_mlp_grad(const float* params, const uint16_t* feat, int64_t n_feat,
                       const uint32_t* rows, const uint64_t* X, int64_t n, float label_cap,
                       float* grad, float* loss, void* ws, size_t ws_bytes, void* stream) {
-  if (!params || !feat || !X || !grad || !loss || !ws || n < 1 || n >= kMaxLabels ||
+  if (!params || !feat || !X || !grad || !loss || !ws_ok(ws) || n < 1 || n >= kMaxLabels ||
       n_feat < 1 || (!rows && n > n_feat) || !aligned16(feat) || !(label_cap >= 0.0f))
     return TC_E_ARG;
   return tc::mlp_grad(params, feat, n_feat, rows, X, n, label_cap, grad, loss, ws, ws_bytes,
@@ -420,7 +424,7 @@ tc_status tc_mlp_train(float* params, float* opt, const uint16_t* feat, int64_t 
                        const uint32_t* rows, const uint64_t* X, int64_t n, float label_cap,
                        int32_t batch, int32_t epochs, float lr, uint64_t seed, int64_t step0,
                        float* loss_per_epoch, void* ws, size_t ws_bytes, void* stream) {
-  if (!params || !opt || !feat || !X || !ws || n < 1 || n >= kMaxLabels || n_feat < 1 ||
+  if (!params || !opt || !feat || !X || !ws_ok(ws) || n < 1 || n >= kMaxLabels || n_feat < 1 ||
       (!rows && n > n_feat) || batch < 32 || batch > (1 << 20) || epochs < 1 || step0 < 0 ||
       !aligned16(feat) || !(label_cap >= 0.0f))
     return TC_E_ARG;
@@ -442,7 +446,8 @@ tc_status tc_proposal_workspace_bytes(int64_t m, size_t* bytes) {
 
 tc_status tc_proposal_weights(const tc_graph* g, const tc_weights* w, const uint32_t* h,
                               void* ws, size_t ws_bytes, tc_weights* wq, void* stream) {
-  if (!g || !w || !h || !ws || !wq || w->m != g->m || w->h || w->ps1 || w->ps3 || !aligned16(h))
+  if (!g || !w || !h || !ws_ok(ws) || !wq || w->m != g->m || w->h || w->ps1 || w->ps3 ||
+      !aligned16(h))
     return TC_E_ARG;
   return tc::proposal_weights(w, h, ws, ws_bytes, (hipStream_t)stream, wq);
 }
@@ -463,7 +468,7 @@ tc_status tc_proposal_window_workspace_bytes(int64_t m, size_t* bytes) {
 tc_status tc_proposal_window(const tc_graph* g, const tc_weights* w, const uint32_t* h,
                              const uint32_t* f_in, const uint32_t* f_out, void* ws,
                              size_t ws_bytes, tc_weights* wq, void* stream) {
-  if (!g || !w || !ws || !wq || w->m != g->m || w->h || w->ps1 || w->ps3) return TC_E_ARG;
+  if (!g || !w || !ws_ok(ws) || !wq || w->m != g->m || w->h || w->ps1 || w->ps3) return TC_E_ARG;
   return tc::proposal_window(g, w, h, f_in, f_out, ws, ws_bytes, (hipStream_t)stream, wq);
 }
 

@@ -126,8 +126,9 @@ def test_anchor_and_class_host_checks(tcb):
     # windows open at the centre time are a valid class (the workspace is not)
     for ok in ((1, 2, 2, 1), (1, 0, 2, 3), (2, 3, 0, 0)):
         c = tcb.tc_class(*ok)
-        assert L.tc_path_weights_class(ctypes.byref(g), 5, ctypes.byref(c), ctypes.c_void_p(1), 0,
-                                       None, ctypes.byref(w)) == tcb.TC_E_WORKSPACE
+        assert L.tc_path_weights_class(ctypes.byref(g), 5, ctypes.byref(c),
+                                       ctypes.c_void_p(256), 0, None,
+                                       ctypes.byref(w)) == tcb.TC_E_WORKSPACE
     fake = ctypes.c_void_p(256).value
     r = tcb.tc_result(fake, fake, fake, fake, None, None, None, None)
     arr = (tcb.tc_motif * 1)(tcb.make_motif([(0, 1), (1, 2), (2, 3), (3, 0)]))
@@ -178,3 +179,30 @@ def test_weights_batch_host_checks(tcb):
     assert L.tc_path_weights_batch(None, arr, 2, None, fake, 1 << 40, None, ws) == tcb.TC_E_ARG
     assert L.tc_path_weights_batch(ctypes.byref(g), arr, 2, None, fake, 16, None,
                                    ws) == tcb.TC_E_WORKSPACE
+
+
+def test_misaligned_workspace_is_an_argument_error(tcb):
+    """A workspace must be 256-byte aligned: a misaligned one is refused on
+    the host (TC_E_ARG) where an aligned one of the same size gets as far as
+    the size check (TC_E_WORKSPACE)."""
+    L = tcb.lib()
+    g = tcb.tc_graph()
+    w = tcb.tc_weights()
+    g.m = w.m = 10
+    w.cls = tcb.tc_class(*tcb.SPINE_CLASS)
+    src = ctypes.c_void_p(4096)
+    for base, want in ((256, tcb.TC_E_WORKSPACE), (256 + 16, tcb.TC_E_ARG),
+                       (256 + 8, tcb.TC_E_ARG), (4096 + 128, tcb.TC_E_ARG)):
+        ws = ctypes.c_void_p(base)
+        assert L.tc_build_graph(5, 1, src, src, src, ws, 0, None, ctypes.byref(g)) == want
+        g.m = 10
+        assert L.tc_path_weights(ctypes.byref(g), 5, ws, 0, None, ctypes.byref(w)) == want
+        arr = (ctypes.c_int64 * 2)(1, 2)
+        wl = (tcb.tc_weights * 2)()
+        assert L.tc_path_weights_batch(ctypes.byref(g), arr, 2, None, ws, 0, None,
+                                       wl) == want
+        fake = ctypes.c_void_p(256).value
+        r = tcb.tc_result(fake, fake, fake, fake, None, None, None, None)
+        arr = (tcb.tc_motif * 1)(tcb.make_motif([(0, 1), (1, 2), (2, 3), (3, 0)]))
+        assert L.tc_sample_estimate(ctypes.byref(g), ctypes.byref(w), arr, 1, 10, 1, 0, 0, ws,
+                                    0, ctypes.byref(r), None) == want
