@@ -192,7 +192,17 @@ struct EdgeCols {
 };
 
 // Where a pass reads its records from.
-enum { SRC_BUF = 0, SRC_COLS = 1, SRC_HIGH = 2 };
+enum { SRC_BUF = 0, SRC_COLS = 1, SRC_HIGH = 2, SRC_INCOLS = 3 };
+
+// The in-list columns as the pair sort's input: the 16-byte in-CSR records
+// {src, eid, t} and the key column dst give the record (src, eid, dst,
+// t - t_min) in in-CSR order, so no re-keyed copy of the in-CSR order is
+// written for it.
+struct InCols {
+  const uint4* rec;
+  const int32_t* key;
+  const BuildPlan* plan;  // t_min
+};
 
 // The graph columns that the last pass of a vertex sort writes in place of
 // its sorted records: for output position i with record (key, eid, other,
@@ -225,6 +235,7 @@ struct RecPass {
   int xf2;
   EdgeCols ec;
   EmitCols E;       // k_radix_scatter<..., true>: the columns out of the last pass
+  InCols ic;        // host-planned input from the in-list columns (ic.rec non-null)
 };
 
 struct PassCfg {
@@ -234,6 +245,7 @@ struct PassCfg {
   const uint4* in;
   uint4* out;
   uint4* out2;
+  InCols ic;
 };
 
 __device__ __forceinline__ PassCfg resolve(const RecPass& R) {
@@ -243,7 +255,9 @@ __device__ __forceinline__ PassCfg resolve(const RecPass& R) {
     c.active = true;
     c.shift = R.shift;
     c.dbits = R.dbits;
-    c.src = SRC_BUF;
+    c.src = R.ic.rec ? SRC_INCOLS : SRC_BUF;
+    c.ic = R.ic;
+    if (R.ic.rec) c.tmin = R.ic.plan->tmin;
     c.xfin = R.xfin;
     c.in = R.in;
     c.out = R.out;
@@ -255,6 +269,7 @@ __device__ __forceinline__ PassCfg resolve(const RecPass& R) {
   const BuildPlan& P = *R.plan;
   const int p = R.pass;
   c.xfin = RX_NONE;
+  c.ic = InCols{nullptr, nullptr, nullptr};
   c.active = P.active[p] != 0 && P.bad == 0;
   c.shift = P.shift[p];
   c.dbits = P.dbits[p];
@@ -276,6 +291,11 @@ __device__ __forceinline__ uint4 load_rec(const PassCfg& c, const EdgeCols& ec, 
   if (c.src == SRC_COLS)
     return make_uint4((uint32_t)(uint64_t)(ec.t[g] - c.tmin), (uint32_t)g, (uint32_t)ec.src[g],
                       (uint32_t)ec.dst[g]);
+  if (c.src == SRC_INCOLS) {
+    const uint4 q = c.ic.rec[g];
+    const int64_t te = (int64_t)(((uint64_t)q.w << 32) | q.z);
+    return make_uint4(q.x, q.y, (uint32_t)c.ic.key[g], (uint32_t)(uint64_t)(te - c.tmin));
+  }
   uint4 r = c.in[g];
   if (c.src == SRC_HIGH) r.x = (uint32_t)((uint64_t)(ec.t[r.y] - c.tmin) >> 32);
   return rec_xform(r, c.xfin);
@@ -634,7 +654,8 @@ void radix_pass(const RecPass& R, bool emit, int64_t m, int64_t ntiles, uint32_t
 // the columns *emit instead of the sorted records (returns 2 then; with no
 // pass at all the caller emits from k0).  With `in0` the first pass reads
 // the records from there, re-keyed by xf_in as it loads them, and in0 is
-// left as it was.  Digits are at most 8 bits wide,
+// left as it was; with `ic` it reads them from the in-list columns (the
+// caller passes ic only when the sort has a pass).  Digits are at most 8 bits wide,
 // or at most 9 where that saves a pass (9, 17-18 and 25-27 bits: a 26-bit
 // vertex id takes 8 + 9 + 9 instead of 6 + 6 + 7 + 7); a 9-bit pass moves
 // twice the histogram rows, a few percent of the records' bytes.
@@ -642,7 +663,7 @@ template <int ITEMS>
 int radix_sort(uint4* k0, uint4* k1, int64_t m, int bits, uint32_t* hist, uint32_t* part,
                size_t part_elems, hipStream_t st, int xf1 = RX_NONE, uint4* extra = nullptr,
                int xf2 = RX_NONE, const EmitCols* emit = nullptr, const uint4* in0 = nullptr,
-               int xf_in = RX_NONE) {
+               int xf_in = RX_NONE, const InCols* ic = nullptr) {
   if (m <= 0) return 0;
   constexpr int kTile = kSortBlock * ITEMS;
   const int64_t ntiles = (m + kTile - 1) / kTile;
@@ -662,6 +683,7 @@ int radix_sort(uint4* k0, uint4* k1, int64_t m, int bits, uint32_t* hist, uint32
     R.plan = nullptr;
     R.in = p == 0 && in0 ? in0 : (cur ? k1 : k0);
     R.xfin = p == 0 && in0 ? xf_in : (int)RX_NONE;
+    if (p == 0 && ic) R.ic = *ic;
     R.out = cur ? k0 : k1;
     // with 9-bit digits the narrow one goes last: the last pass writes the
     // longest runs, and an 8-bit pass takes 256-entry rows
@@ -995,12 +1017,15 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   // A vertex sort of rr[from] (spare rr[tmp]) whose last pass writes the
   // columns E; with no pass (n = 1) the records are emitted from rr[from].
   // With `in0` >= 0 the sort reads rr[in0] (re-keyed by xf_in) and leaves it
-  // as it was, ping-ponging between rr[from] and rr[tmp].
+  // as it was, ping-ponging between rr[from] and rr[tmp]; with `ic` its first
+  // pass reads the in-list columns instead of rr[from].
   auto sort_emit = [&](int from, int tmp, const EmitCols& E, uint32_t* off, int extra = -1,
-                       int xf2 = RX_NONE, int in0 = -1, int xf_in = RX_NONE) -> bool {
+                       int xf2 = RX_NONE, int in0 = -1, int xf_in = RX_NONE,
+                       const InCols* ic = nullptr) -> bool {
     const int w = radix_sort<kRecItems>(rr[from], rr[tmp], m, vbits, hist, part, pe, st,
                                         RX_NONE, extra < 0 ? (uint4*)nullptr : rr[extra], xf2,
-                                        &E, in0 < 0 ? (const uint4*)nullptr : rr[in0], xf_in);
+                                        &E, in0 < 0 ? (const uint4*)nullptr : rr[in0], xf_in,
+                                        ic);
     if (w < 0) return false;
     if (w != 2)
       hipLaunchKernelGGL(k_emit, dim3(blocks_for(m + 1, 256)), dim3(256), 0, st,
@@ -1014,20 +1039,22 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   };
   // 2. in-CSR: the time order read from rr[0] with src and dst swapped
   //    ((src, eid, dst, t) -> (dst, eid, src, t)), stable by dst, written as
-  //    the in-list columns; a second copy of the sorted records, re-keyed,
-  //    is the pair index input (rr[3])
+  //    the in-list columns.  With a single vertex (no pass) a copy of the
+  //    records re-keyed for the pair index goes to rr[3] instead.
+  const bool one = vbits == 0;
   if (!sort_emit(2, 1,
                  EmitCols{plan, t, g->in_dst, g->in_src, g->in_t, g->in_eid, (uint4*)g->in_rec,
                           nullptr},
-                 g->in_off, 3, RX_PAIR, 0, RX_PAIR))
+                 g->in_off, one ? 3 : -1, RX_PAIR, 0, RX_PAIR))
     return TC_E_WORKSPACE;
-  // 3. pair index: the in-order (dst, t, eid) stably by src; the pair
-  //    sources go to the free buffer rr[2]
+  // 3. pair index: the in-order (dst, t, eid), read from the in-list
+  //    columns, stably by src; the pair sources go to the free buffer rr[2]
   int32_t* psrc = (int32_t*)rr[2];
+  const InCols ic{(const uint4*)g->in_rec, g->in_dst, plan};
   if (!sort_emit(3, 1,
                  EmitCols{plan, t, psrc, g->pair_dst, g->pair_t, g->pair_eid, nullptr,
                           g->pair_skip},
-                 nullptr))
+                 nullptr, -1, RX_NONE, -1, RX_NONE, one ? nullptr : &ic))
     return TC_E_WORKSPACE;
   // 4. the run table (its clear was enqueued first)
   hipLaunchKernelGGL(k_hash_insert, dim3(eb), dim3(256), 0, st, (const uint32_t*)psrc,
