@@ -308,8 +308,10 @@ __global__ __launch_bounds__(256) void k_rec_init(EdgeCols ec, int64_t m,
                                                   uint4* __restrict__ out, int xf1,
                                                   uint4* __restrict__ out2, int xf2) {
   if (plan->npass != 0 || plan->bad) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) {
+  // grid-stride: the launch is small, since it is idle for all but inputs
+  // whose times are all equal
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x) {
     const uint4 r = make_uint4((uint32_t)(uint64_t)(ec.t[i] - plan->tmin), (uint32_t)i,
                                (uint32_t)ec.src[i], (uint32_t)ec.dst[i]);
     out[i] = rec_xform(r, xf1);
@@ -337,24 +339,29 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(RecPass R, int64_t m,
   const PassCfg c = resolve(R);
   if (!c.active) return;
   const uint32_t mask = (1u << c.dbits) - 1u;
+  // one tile per block, or several when the grid is smaller than the tile
+  // count (the passes that are usually idle)
+  const int64_t ntiles = (m + kSortBlock * ITEMS - 1) / (kSortBlock * ITEMS);
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
 #pragma unroll
-  for (int q = 0; q < kDig; ++q) s_h[q * kSortBlock + threadIdx.x] = 0;
-  __syncthreads();
-  int64_t start = (int64_t)blockIdx.x * (kSortBlock * ITEMS);
+    for (int q = 0; q < kDig; ++q) s_h[q * kSortBlock + threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t start = tile * (kSortBlock * ITEMS);
 #pragma unroll
-  for (int r = 0; r < ITEMS; ++r) {
-    int64_t i = start + (int64_t)r * kSortBlock + threadIdx.x;
-    if (i < m) {
-      const uint32_t key = c.src == SRC_COLS ? (uint32_t)(uint64_t)(R.ec.t[i] - c.tmin)
-                                             : load_rec(c, R.ec, i).x;
-      atomicAdd(&s_h[(key >> c.shift) & mask], 1u);
+    for (int r = 0; r < ITEMS; ++r) {
+      int64_t i = start + (int64_t)r * kSortBlock + threadIdx.x;
+      if (i < m) {
+        const uint32_t key = c.src == SRC_COLS ? (uint32_t)(uint64_t)(R.ec.t[i] - c.tmin)
+                                               : load_rec(c, R.ec, i).x;
+        atomicAdd(&s_h[(key >> c.shift) & mask], 1u);
+      }
     }
-  }
-  __syncthreads();
+    __syncthreads();
 #pragma unroll
-  for (int q = 0; q < kDig; ++q)
-    hist[(int64_t)blockIdx.x * BINS + q * kSortBlock + threadIdx.x] =
-        s_h[q * kSortBlock + threadIdx.x];
+    for (int q = 0; q < kDig; ++q)
+      hist[tile * BINS + q * kSortBlock + threadIdx.x] = s_h[q * kSortBlock + threadIdx.x];
+    __syncthreads();  // the next tile clears s_h
+  }
 }
 
 // Column scan of the tile-major histogram: hist[t][d] becomes the position
@@ -496,7 +503,7 @@ __device__ __forceinline__ void emit_cols(const EmitCols& E, int64_t m, int64_t 
   }
 }
 
-template <int ITEMS, int BINS, bool EMIT = false>
+template <int ITEMS, int BINS, bool EMIT = false, bool LOOP = false>
 __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(RecPass R, int64_t m,
                                                               const uint32_t* __restrict__ hist) {
   // Each wavefront owns a contiguous quarter of the tile and ranks its keys
@@ -514,15 +521,6 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(RecPass R, int64_t
   if (!c.active) return;
   const int shift = c.shift, dbits = c.dbits;
   const uint32_t mask = (1u << dbits) - 1u;
-  // XCD-aware tile order.  Workgroups are dealt to the XCDs round robin
-  // (block b to XCD b mod 8), and each XCD has its own L2.  Neighbouring
-  // tiles write neighbouring pieces of every digit run, so each XCD takes a
-  // contiguous range of tiles: partial cache lines then meet in one L2
-  // instead of being written back piecewise from several.
-  const uint32_t nb = gridDim.x, xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
-  const uint32_t q = nb / kXcds, rem = nb % kXcds;
-  const uint32_t tile = xcd * q + (xcd < rem ? xcd : rem) + slot;
-  if ((int64_t)tile * kTile >= m) return;
   // s_base[d]: global position of digit d's run minus its start in the tile
   // s_pos[w][d]: wavefront w's running count of digit d, then the position
   //              in the tile of w's first key of digit d (16 bits suffice)
@@ -530,103 +528,117 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(RecPass R, int64_t
   __shared__ uint16_t s_pos[kWaves][BINS];
   __shared__ uint32_t s_wsum[kDig][kWaves];
   __shared__ uint4 s_key[kTile];
-
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t start = (int64_t)tile * kTile;
-  const int len = (int)((m - start) < kTile ? (m - start) : kTile);
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // One tile per block (the grid is the tile count), or with LOOP several
+  // when the grid is smaller (a multiple of 8 blocks then, for the passes
+  // that are usually idle).  XCD-aware tile order: workgroups are dealt to the XCDs round
+  // robin (block b to XCD b mod 8), and each XCD has its own L2.
+  // Neighbouring tiles write neighbouring pieces of every digit run, so each
+  // XCD takes a contiguous range of tiles: partial cache lines then meet in
+  // one L2 instead of being written back piecewise from several.
+  const uint32_t nb = LOOP ? (uint32_t)((m + kTile - 1) / kTile) : gridDim.x;
+  for (uint32_t vt = blockIdx.x; vt < nb; vt += gridDim.x) {
+    const uint32_t xcd = vt % kXcds, slot = vt / kXcds;
+    const uint32_t q = nb / kXcds, rem = nb % kXcds;
+    const uint32_t tile = xcd * q + (xcd < rem ? xcd : rem) + slot;
+    const int64_t start = (int64_t)tile * kTile;
+    const int len = (int)((m - start) < kTile ? (m - start) : kTile);
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-  uint32_t gbase[kDig];  // loaded now, used after the ranking
+    uint32_t gbase[kDig];  // loaded now, used after the ranking
 #pragma unroll
-  for (int j = 0; j < kDig; ++j) gbase[j] = hist[(int64_t)tile * BINS + j * kSortBlock + tid];
+    for (int j = 0; j < kDig; ++j) gbase[j] = hist[(int64_t)tile * BINS + j * kSortBlock + tid];
 #pragma unroll
-  for (int w = 0; w < kWaves; ++w)
+    for (int w = 0; w < kWaves; ++w)
 #pragma unroll
-    for (int j = 0; j < kDig; ++j) s_pos[w][j * kSortBlock + tid] = 0;
-  __syncthreads();
+      for (int j = 0; j < kDig; ++j) s_pos[w][j * kSortBlock + tid] = 0;
+    __syncthreads();
 
-  uint4 key[ITEMS];
-  uint32_t rank[ITEMS];  // rank among the wavefront's keys of the same digit
+    uint4 key[ITEMS];
+    uint32_t rank[ITEMS];  // rank among the wavefront's keys of the same digit
 #pragma unroll
-  for (int r = 0; r < ITEMS; ++r) {
-    const int idx = wave * kSub + r * kWave + lane;
-    const bool valid = idx < len;
-    key[r] = valid ? load_rec(c, R.ec, start + idx) : uint4{};
-    const uint32_t d = (key[r].x >> shift) & mask;
-    uint64_t vb = __ballot(valid);
-    uint64_t peers = valid ? vb : ~vb;
-#pragma unroll
-    for (int b = 0; b < kBits; ++b) {
-      if (b < dbits) {  // uniform: the digit has dbits bits
-        const bool bit = (d >> b) & 1u;
-        const uint64_t bb = __ballot(bit);
-        peers &= bit ? bb : ~bb;
-      }
-    }
-    const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
-    // read the running count before the leader of each digit group adds to it
-    const uint32_t run = valid ? (uint32_t)s_pos[wave][d] : 0u;
-    rank[r] = run + below;
-    __builtin_amdgcn_wave_barrier();
-    if (valid && below == 0) s_pos[wave][d] = (uint16_t)(run + (uint32_t)__popcll(peers));
-    __builtin_amdgcn_wave_barrier();
-  }
-  __syncthreads();
-  // thread tid owns digits tid, tid + 256, ...: the tile-local start of each
-  // wavefront's run of that digit, digits in increasing order
-  {
-    uint32_t carry = 0;  // keys of the digit groups below
-#pragma unroll
-    for (int j = 0; j < kDig; ++j) {
-      const int d = j * kSortBlock + tid;
-      uint32_t cw[kWaves], tot = 0;
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w) {
-        cw[w] = s_pos[w][d];
-        tot += cw[w];
-      }
-      const uint32_t inc = wave_inclusive_scan(tot);
-      if (lane == 63) s_wsum[j][wave] = inc;
-      __syncthreads();
-      uint32_t off = carry + inc - tot, group = 0;
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w) {
-        off += w < wave ? s_wsum[j][w] : 0u;
-        group += s_wsum[j][w];
-      }
-      carry += group;
-      s_base[d] = gbase[j] - off;  // modulo 2^32; the sum below is exact
-      uint32_t p = off;
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w) {
-        s_pos[w][d] = (uint16_t)p;
-        p += cw[w];
-      }
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < ITEMS; ++r) {
-    const int idx = wave * kSub + r * kWave + lane;
-    if (idx < len) {
+    for (int r = 0; r < ITEMS; ++r) {
+      const int idx = wave * kSub + r * kWave + lane;
+      const bool valid = idx < len;
+      key[r] = valid ? load_rec(c, R.ec, start + idx) : uint4{};
       const uint32_t d = (key[r].x >> shift) & mask;
-      s_key[(uint32_t)s_pos[wave][d] + rank[r]] = key[r];
+      uint64_t vb = __ballot(valid);
+      uint64_t peers = valid ? vb : ~vb;
+#pragma unroll
+      for (int b = 0; b < kBits; ++b) {
+        if (b < dbits) {  // uniform: the digit has dbits bits
+          const bool bit = (d >> b) & 1u;
+          const uint64_t bb = __ballot(bit);
+          peers &= bit ? bb : ~bb;
+        }
+      }
+      const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
+      // read the running count before the leader of each digit group adds to it
+      const uint32_t run = valid ? (uint32_t)s_pos[wave][d] : 0u;
+      rank[r] = run + below;
+      __builtin_amdgcn_wave_barrier();
+      if (valid && below == 0) s_pos[wave][d] = (uint16_t)(run + (uint32_t)__popcll(peers));
+      __builtin_amdgcn_wave_barrier();
     }
-  }
-  __syncthreads();
-  const bool cols = EMIT && R.E.plan->bad == 0;
-  for (int i = tid; i < len; i += kSortBlock) {
-    const uint4 k = s_key[i];
-    const uint32_t d = (k.x >> shift) & mask;
-    const int64_t gpos = (int64_t)(s_base[d] + (uint32_t)i);
-    // the last pass of a sort can re-key the records for the next sort, or
-    // write the graph's columns instead of the records
-    if (EMIT) {
-      if (cols) emit_cols(R.E, m, gpos, k);
-    } else {
-      c.out[gpos] = rec_xform(k, c.xf1);
+    __syncthreads();
+    // thread tid owns digits tid, tid + 256, ...: the tile-local start of each
+    // wavefront's run of that digit, digits in increasing order
+    {
+      uint32_t carry = 0;  // keys of the digit groups below
+#pragma unroll
+      for (int j = 0; j < kDig; ++j) {
+        const int d = j * kSortBlock + tid;
+        uint32_t cw[kWaves], tot = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+          cw[w] = s_pos[w][d];
+          tot += cw[w];
+        }
+        const uint32_t inc = wave_inclusive_scan(tot);
+        if (lane == 63) s_wsum[j][wave] = inc;
+        __syncthreads();
+        uint32_t off = carry + inc - tot, group = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+          off += w < wave ? s_wsum[j][w] : 0u;
+          group += s_wsum[j][w];
+        }
+        carry += group;
+        s_base[d] = gbase[j] - off;  // modulo 2^32; the sum below is exact
+        uint32_t p = off;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+          s_pos[w][d] = (uint16_t)p;
+          p += cw[w];
+        }
+      }
     }
-    if (c.out2) c.out2[gpos] = rec_xform(k, c.xf2);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+      const int idx = wave * kSub + r * kWave + lane;
+      if (idx < len) {
+        const uint32_t d = (key[r].x >> shift) & mask;
+        s_key[(uint32_t)s_pos[wave][d] + rank[r]] = key[r];
+      }
+    }
+    __syncthreads();
+    const bool cols = EMIT && R.E.plan->bad == 0;
+    for (int i = tid; i < len; i += kSortBlock) {
+      const uint4 k = s_key[i];
+      const uint32_t d = (k.x >> shift) & mask;
+      const int64_t gpos = (int64_t)(s_base[d] + (uint32_t)i);
+      // the last pass of a sort can re-key the records for the next sort, or
+      // write the graph's columns instead of the records
+      if (EMIT) {
+        if (cols) emit_cols(R.E, m, gpos, k);
+      } else {
+        c.out[gpos] = rec_xform(k, c.xf1);
+      }
+      if (c.out2) c.out2[gpos] = rec_xform(k, c.xf2);
+    }
+    if (!LOOP) break;
+    __syncthreads();  // the next tile reuses the LDS
   }
 }
 
@@ -716,7 +728,8 @@ bool time_sort(const BuildPlan* plan, const EdgeCols& ec, uint4* b0, uint4* b1, 
   constexpr int kTile = kSortBlock * ITEMS;
   const int64_t ntiles = (m + kTile - 1) / kTile;
   if (part_elems < col_scan_scratch_elems(ntiles, 256)) return false;
-  hipLaunchKernelGGL(k_rec_init, dim3(blocks_for(m, 256)), dim3(256), 0, st, ec, m, plan, b0,
+  hipLaunchKernelGGL(k_rec_init, dim3(blocks_for(m, 256) < 2048 ? blocks_for(m, 256) : 2048),
+                     dim3(256), 0, st, ec, m, plan, b0,
                      xf1, out2, xf2);
   for (int p = 0; p < kTimePasses; ++p) {
     RecPass R{};
@@ -728,11 +741,20 @@ bool time_sort(const BuildPlan* plan, const EdgeCols& ec, uint4* b0, uint4* b1, 
     R.out2 = out2;
     R.xf2 = xf2;
     R.ec = ec;
-    hipLaunchKernelGGL((k_radix_hist<ITEMS, 256>), dim3((unsigned)ntiles), dim3(kSortBlock), 0,
-                       st, R, m, hist);
+    // the high-word passes work only for time ranges wider than 32 bits:
+    // their launches take up to eight tiles per block, so that idle ones
+    // cost a few microseconds
+    const int64_t hb = ((ntiles + 63) / 64) * 8;
+    const unsigned grid = (unsigned)(p >= 4 && hb < ntiles ? hb : ntiles);
+    hipLaunchKernelGGL((k_radix_hist<ITEMS, 256>), dim3(grid), dim3(kSortBlock), 0, st, R, m,
+                       hist);
     col_scan<256>(hist, ntiles, part, PassGate{plan, p}, st);
-    hipLaunchKernelGGL((k_radix_scatter<ITEMS, 256>), dim3((unsigned)ntiles), dim3(kSortBlock),
-                       0, st, R, m, (const uint32_t*)hist);
+    if (p >= 4)
+      hipLaunchKernelGGL((k_radix_scatter<ITEMS, 256, false, true>), dim3(grid), dim3(kSortBlock),
+                         0, st, R, m, (const uint32_t*)hist);
+    else
+      hipLaunchKernelGGL((k_radix_scatter<ITEMS, 256>), dim3(grid), dim3(kSortBlock), 0, st, R,
+                         m, (const uint32_t*)hist);
   }
   return true;
 }
