@@ -44,11 +44,18 @@ __global__ void k_init_build(uint32_t* status, uint64_t* tminmax) {
   }
 }
 
+// The validation, which also counts the low byte of every time per sort tile
+// (tile-major rows of 256, as the radix histograms): the first pass of the
+// time sort takes its digit counts from these rows once t_min is known
+// (k_fold_hist), so it needs no histogram read of its own.  Each block walks
+// tiles blockIdx.x, blockIdx.x + gridDim.x, ...
 // t is mapped to an order-preserving unsigned key (flip the sign bit)
-__global__ __launch_bounds__(256) void k_validate(const int32_t* __restrict__ src,
-                                                  const int32_t* __restrict__ dst,
-                                                  const int64_t* __restrict__ t, int64_t m,
-                                                  int32_t n, uint32_t* status, uint64_t* tminmax) {
+__global__ __launch_bounds__(kSortBlock) void k_validate(const int32_t* __restrict__ src,
+                                                         const int32_t* __restrict__ dst,
+                                                         const int64_t* __restrict__ t, int64_t m,
+                                                         int32_t n, uint32_t* status,
+                                                         uint64_t* tminmax,
+                                                         uint32_t* __restrict__ hist) {
   const int64_t lim = (int64_t)1 << 62;
   uint64_t mn = ~0ull, mx = 0;
   uint32_t bad = 0;
@@ -58,22 +65,33 @@ __global__ __launch_bounds__(256) void k_validate(const int32_t* __restrict__ sr
     mn = key < mn ? key : mn;
     mx = key > mx ? key : mx;
   };
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  // four edges per step, their loads issued together (all in bounds)
-  for (; i + 3 * stride < m; i += 4 * stride) {
-    int32_t sv[4], dv[4];
-    int64_t tv[4];
+  __shared__ uint32_t s_h[256];
+  const int64_t ntiles = (m + kRecTile - 1) / kRecTile;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    s_h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t start = tile * kRecTile;
+    int32_t sv[kRecItems], dv[kRecItems];
+    int64_t tv[kRecItems];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      sv[u] = src[i + u * stride];
-      dv[u] = dst[i + u * stride];
-      tv[u] = t[i + u * stride];
+    for (int r = 0; r < kRecItems; ++r) {  // the tile's loads issued together
+      const int64_t i = start + (int64_t)r * kSortBlock + threadIdx.x;
+      const bool in = i < m;
+      sv[r] = in ? src[i] : 0;
+      dv[r] = in ? dst[i] : 0;
+      tv[r] = in ? t[i] : 0;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) check(sv[u], dv[u], tv[u]);
+    for (int r = 0; r < kRecItems; ++r) {
+      if (start + (int64_t)r * kSortBlock + threadIdx.x < m) {
+        check(sv[r], dv[r], tv[r]);
+        atomicAdd(&s_h[(uint32_t)(uint64_t)tv[r] & 255u], 1u);
+      }
+    }
+    __syncthreads();
+    hist[tile * 256 + threadIdx.x] = s_h[threadIdx.x];
+    __syncthreads();  // the next tile clears s_h
   }
-  for (; i < m; i += stride) check(src[i], dst[i], t[i]);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     uint64_t a = __shfl_xor(mn, off, kWave);
@@ -165,6 +183,27 @@ __global__ void k_plan(const uint32_t* __restrict__ status, const uint64_t* __re
     B.wide = hi > 0 ? 1 : 0;
   }
   *P = B;
+}
+
+// The digit counts of the time sort's first pass from the validation's
+// low-byte counts: its digit is the low w <= 8 bits of t - t_min (shift 0),
+// so digit d counts the bytes b with (b - t_min) mod 2^w = d.  In place, one
+// tile row at a time.
+__global__ __launch_bounds__(256) void k_fold_hist(uint32_t* __restrict__ hist, int64_t ntiles,
+                                                   const BuildPlan* __restrict__ plan) {
+  if (plan->bad || !plan->active[0]) return;
+  __shared__ uint32_t s_r[256];
+  const uint32_t W = 1u << plan->dbits[0], tm = (uint32_t)(uint64_t)plan->tmin;
+  const uint32_t d = threadIdx.x;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    s_r[d] = hist[tile * 256 + d];
+    __syncthreads();
+    uint32_t v = 0;
+    if (d < W)
+      for (uint32_t b = (d + tm) & (W - 1); b < 256; b += W) v += s_r[b];
+    hist[tile * 256 + d] = v;
+    __syncthreads();  // the next row overwrites s_r
+  }
 }
 
 // ------------------------------------------------------------ radix pass ---
@@ -746,8 +785,13 @@ bool time_sort(const BuildPlan* plan, const EdgeCols& ec, uint4* b0, uint4* b1, 
     // cost a few microseconds
     const int64_t hb = ((ntiles + 63) / 64) * 8;
     const unsigned grid = (unsigned)(p >= 4 && hb < ntiles ? hb : ntiles);
-    hipLaunchKernelGGL((k_radix_hist<ITEMS, 256>), dim3(grid), dim3(kSortBlock), 0, st, R, m,
-                       hist);
+    // pass 0 takes its counts from the validation's (k_fold_hist)
+    if (p == 0)
+      hipLaunchKernelGGL(k_fold_hist, dim3((unsigned)(ntiles < 2048 ? ntiles : 2048)), dim3(256),
+                         0, st, hist, ntiles, plan);
+    else
+      hipLaunchKernelGGL((k_radix_hist<ITEMS, 256>), dim3(grid), dim3(kSortBlock), 0, st, R, m,
+                         hist);
     col_scan<256>(hist, ntiles, part, PassGate{plan, p}, st);
     if (p >= 4)
       hipLaunchKernelGGL((k_radix_scatter<ITEMS, 256, false, true>), dim3(grid), dim3(kSortBlock),
@@ -1010,10 +1054,9 @@ tc_status build_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   // validation and the sort plan, on the device
   hipLaunchKernelGGL(k_init_build, dim3(1), dim3(64), 0, st, g->status, tminmax);
   if (m > 0) {
-    unsigned vb = blocks_for(m, 256);
-    if (vb > 1024) vb = 1024;
-    hipLaunchKernelGGL(k_validate, dim3(vb), dim3(256), 0, st, src, dst, t, m, n, g->status,
-                       tminmax);
+    const int64_t ntiles = (m + kRecTile - 1) / kRecTile;
+    hipLaunchKernelGGL(k_validate, dim3((unsigned)(ntiles < 1024 ? ntiles : 1024)),
+                       dim3(kSortBlock), 0, st, src, dst, t, m, n, g->status, tminmax, hist);
   }
   hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, st, (const uint32_t*)g->status,
                      (const uint64_t*)tminmax, m, plan);
