@@ -49,8 +49,8 @@ PMC_FILES = {"bitcoin": os.path.join(ROOT, "profiles", "pmc_traffic_bitcoin.txt"
              "medium": os.path.join(ROOT, "profiles", "pmc_traffic_medium.txt")}
 # stages of a step -> kernels whose counter traffic makes up the stage
 STAGE_KERNELS = {
-    "build": ["k_init_build", "k_validate", "k_plan", "k_trange", "k_hash_clear", "k_rec_init",
-              "k_radix_hist", "k_col_sum", "k_col_scan", "k_col_apply", "k_radix_scatter",
+    "build": ["k_init_build", "k_validate", "k_plan", "k_trange", "k_fold_hist", "k_hash_clear",
+              "k_rec_init", "k_radix_hist", "k_col_sum", "k_col_scan", "k_col_apply", "k_radix_scatter",
               "k_rec_xform", "k_emit", "k_offsets", "k_hash_insert"],
     "weights": ["k_mp_split_coarse", "k_mp_split", "k_mp_rank", "k_combine", "k_scan_tiles",
                 "k_scan_tiles_sets", "k_scan_apply"],

@@ -39,6 +39,7 @@ KERNEL_SRC = {
     "k_mp_split_coarse": "tc_weights.hip", "k_rec_init": "tc_build.hip",
     "k_col_sum": "tc_build.hip", "k_col_scan": "tc_build.hip", "k_col_apply": "tc_build.hip",
     "k_hash_clear": "tc_build.hip", "k_validate": "tc_build.hip", "k_plan": "tc_build.hip",
+    "k_fold_hist": "tc_build.hip",
     "k_init_build": "tc_build.hip", "k_trange": "tc_build.hip",
     "k_zero_result": "tc_sample.hip", "k_store_ptrs": "tc_sample.hip",
     "k_zero_counters": "tc_sample.hip", "k_finalize": "tc_sample.hip",
