@@ -6,7 +6,8 @@
 // per-vertex lists; the tie order is this library's convention).
 //
 // Radix sort design (gfx950, wave64): every sort moves 16-byte edge
-// records, tiles of 1536 records per 256-thread block.  A pass is (1)
+// records, tiles of 1536 records per 256-thread block; the last pass of a
+// vertex sort writes the graph's columns instead of records.  A pass is (1)
 // per-tile digit histograms written tile-major (each tile's 256 or 512
 // counts are one contiguous row), (2) a column scan of that [tiles][bins]
 // matrix that turns every count into the tile's global offset for its digit,
@@ -759,7 +760,8 @@ int radix_sort(uint4* k0, uint4* k1, int64_t m, int bits, uint32_t* hist, uint32
 
 // The time sort: kTimePasses launched passes planned on the device (see
 // BuildPlan).  It reads the edge columns and leaves the time-ordered records
-// re-keyed by xf1 in buf[0] and by xf2 in out2.
+// re-keyed by xf1 in buf[0] and, if out2 is given, by xf2 in out2.  Its
+// first pass takes its digit counts from the validation (k_fold_hist).
 template <int ITEMS>
 bool time_sort(const BuildPlan* plan, const EdgeCols& ec, uint4* b0, uint4* b1, int64_t m,
                uint32_t* hist, uint32_t* part, size_t part_elems, hipStream_t st, int xf1,
@@ -873,9 +875,10 @@ int pair_hash_log2(int64_t m) {
   return lg;
 }
 
-// sorted records (key, eid, other, t - t_min) -> columns of one order.  The
-// time is t_min + the record's time word, or, when the range is wider than
-// 32 bits, read back from the input by edge id.
+// sorted records (key, eid, other, t - t_min) -> columns of one order, for a
+// graph of a single vertex (its vertex sorts have no pass whose last one
+// would write the columns).  The time is t_min + the record's time word, or,
+// when the range is wider than 32 bits, read back from the input by edge id.
 // With `off` (n + 1 entries), also the CSR offsets of the sorted keys:
 // off[v] = first position whose key is >= v, written by the thread of the
 // position where the key passes v (grid of m + 1 threads).  With `skip`
